@@ -1,0 +1,376 @@
+"""FP64 CPU oracle for the gamma-EigenGame hot path -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never imports,
+links or calls it, and the two share no code: the oracle is plain C
+(``sgep_oracle.c``, double precision throughout) plus the numpy helpers below,
+each written from the paper (Gemp, Chen, McWilliams, ICLR 2023,
+arXiv 2206.04993):
+
+* ``gep_topk``       exact top-k of A v = lambda B v (Sec. 1 problem; App. A
+                     reduction through a Cholesky factor of B and a cyclic
+                     Jacobi eigensolve of L^{-1} A L^{-T}).
+* ``gamma_step``     one iteration of Alg. 2 with M = 1, per player, with
+                     explicit sums over the minibatch rows.
+* ``alg1_step``      one iteration of Alg. 1 (full batch, exact B y_j).
+* ``utility``        the player utility of Sec. 2 (eq. util_new).
+* ``utility_grad``   its gradient (App. B, gradient lemma).
+* ``subspace_error`` the normalised subspace error of App. A.
+* ``eta``            the step-size schedules.
+
+Arrays of player vectors are numpy (d, k) arrays whose column i is player i.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+KIND_CCA, KIND_GENERAL, KIND_LDA = 0, 1, 2
+OPT_SGD, OPT_ADAM = 0, 1
+SCHED_CONST, SCHED_INV, SCHED_WARMUP_HARMONIC = 0, 1, 2
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(LIB_PATH)
+        D = ctypes.POINTER(ctypes.c_double)
+        I32 = ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_cholesky.argtypes = [ctypes.c_int, D]
+        lib.oracle_cholesky.restype = ctypes.c_int
+        lib.oracle_jacobi_eigh.argtypes = [ctypes.c_int, D, D, D, ctypes.c_double, ctypes.c_int]
+        lib.oracle_jacobi_eigh.restype = ctypes.c_int
+        lib.oracle_gep_topk.argtypes = [ctypes.c_int, D, D, ctypes.c_int, D, D, ctypes.c_int]
+        lib.oracle_gep_topk.restype = ctypes.c_int
+        lib.oracle_eta.argtypes = [ctypes.c_int] + [ctypes.c_double] * 6
+        lib.oracle_eta.restype = ctypes.c_double
+        P = ctypes.POINTER(_Problem)
+        lib.oracle_gamma_step.argtypes = [P, ctypes.c_int64, D, ctypes.c_int64, D, ctypes.c_int64,
+                                          I32, D, D, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, D, D, D, D, D]
+        lib.oracle_gamma_step.restype = ctypes.c_int
+        lib.oracle_gamma_step_dense.argtypes = [P, ctypes.c_int64, D, D, D, D, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_double, D, D, D, D, D]
+        lib.oracle_gamma_step_dense.restype = ctypes.c_int
+        lib.oracle_alg1_step.argtypes = [ctypes.c_int64, ctypes.c_int, D, D, D, ctypes.c_double, D]
+        lib.oracle_alg1_step.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("k", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+        ("optimizer", ctypes.c_int32), ("dx", ctypes.c_int64), ("dy", ctypes.c_int64),
+        ("eps_reg", ctypes.c_double), ("rho", ctypes.c_double), ("adam_b1", ctypes.c_double),
+        ("adam_b2", ctypes.c_double), ("adam_eps", ctypes.c_double),
+        ("class_means", ctypes.POINTER(ctypes.c_double)),
+        ("class_priors", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+def _dp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"], "oracle arrays must be C-contiguous float64"
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# --------------------------------------------------------------------------- #
+# Dense linear algebra                                                        #
+# --------------------------------------------------------------------------- #
+
+def cholesky(B: np.ndarray) -> np.ndarray:
+    """Lower Cholesky factor L of the SPD matrix B (B = L L^T)."""
+    a = np.ascontiguousarray(B, dtype=np.float64).copy()
+    rc = _load().oracle_cholesky(a.shape[0], _dp(a))
+    if rc != 0:
+        raise np.linalg.LinAlgError("matrix is not positive definite")
+    return a
+
+
+def jacobi_eigh(C: np.ndarray, tol: float = 1e-15, max_sweeps: int = 100):
+    """Eigen-decomposition of the symmetric C by cyclic Jacobi.
+
+    Returns (w, Z) unsorted, with C Z[:, c] = w[c] Z[:, c]."""
+    n = C.shape[0]
+    a = np.ascontiguousarray(C, dtype=np.float64).copy()
+    w = np.zeros(n)
+    z = np.zeros((n, n))
+    rc = _load().oracle_jacobi_eigh(n, _dp(a), _dp(w), _dp(z), tol, max_sweeps)
+    if rc < 0:
+        raise RuntimeError("Jacobi did not converge")
+    return w, z
+
+
+def gep_topk(A: np.ndarray, B: np.ndarray, k: int, canon: bool = True):
+    """Top-k generalized eigenpairs of A v = lambda B v (Sec. 1).
+
+    Returns (lam, V): lam descending (k,), V (d, k) B-orthonormal
+    (V^T B V = I, App. A B-orthogonality lemma)."""
+    d = A.shape[0]
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    lam = np.zeros(k)
+    Vc = np.zeros((k, d))  # column-major d x k == row-major k x d
+    rc = _load().oracle_gep_topk(d, _dp(A), _dp(B), k, _dp(lam), _dp(Vc), 1 if canon else 0)
+    if rc == -1:
+        raise np.linalg.LinAlgError("B is not positive definite")
+    if rc != 0:
+        raise RuntimeError(f"oracle_gep_topk failed ({rc})")
+    return lam, Vc.T.copy()
+
+
+def eta(schedule: int, t: float, eta0: float, eta_T: float = 0.0, t0: float = 1.0,
+        t_c: float = 1.0, T: float = 1.0) -> float:
+    """Step size eta_t for iteration t = 1, 2, ... (see sgep_oracle.c)."""
+    return float(_load().oracle_eta(schedule, float(t), eta0, eta_T, t0, t_c, T))
+
+
+# --------------------------------------------------------------------------- #
+# Alg. 2 / Alg. 1                                                              #
+# --------------------------------------------------------------------------- #
+
+@dataclass
+class Problem:
+    """Problem description shared by the step functions.
+
+    kind: KIND_CCA (A, B the block matrices of Sec. 1), KIND_GENERAL
+    (A = E[y y^T], B = E[x x^T] + eps I) or KIND_LDA (A between-class,
+    B within-class covariance + eps I)."""
+    kind: int
+    k: int
+    dx: int
+    dy: int = 0
+    eps_reg: float = 0.0
+    rho: float = 1e-6
+    optimizer: int = OPT_SGD
+    adam_b1: float = 0.9
+    adam_b2: float = 0.999
+    adam_eps: float = 1e-8
+    class_means: Optional[np.ndarray] = None   # (c, d)
+    class_priors: Optional[np.ndarray] = None  # (c,)
+
+    @property
+    def d(self) -> int:
+        return self.dx + self.dy if self.kind == KIND_CCA else self.dx
+
+    def _c(self):
+        self._keep = []
+        means = priors = None
+        nc = 0
+        if self.kind == KIND_LDA:
+            m = np.ascontiguousarray(self.class_means, dtype=np.float64)
+            nc = m.shape[0]
+            p = (np.full(nc, 1.0 / nc) if self.class_priors is None
+                 else np.ascontiguousarray(self.class_priors, dtype=np.float64))
+            self._keep += [m, p]
+            means, priors = _dp(m), _dp(p)
+        return _Problem(self.kind, self.k, nc, self.optimizer, self.dx, self.dy, self.eps_reg,
+                        self.rho, self.adam_b1, self.adam_b2, self.adam_eps, means, priors)
+
+
+@dataclass
+class State:
+    """Iterate of Alg. 2: V (unit columns), the auxiliary G = [Bv], the Adam
+    moments, the iteration counter and the Rayleigh-quotient running means."""
+    V: np.ndarray
+    G: np.ndarray
+    m: Optional[np.ndarray] = None
+    s2: Optional[np.ndarray] = None
+    t: int = 0
+    ema_a: Optional[np.ndarray] = None
+    ema_b: Optional[np.ndarray] = None
+
+    @staticmethod
+    def init(V0: np.ndarray, adam: bool = False) -> "State":
+        """Alg. 2 initialisation: columns of V0 normalised to the unit sphere,
+        [Bv]_i <- v_i."""
+        V = np.asarray(V0, dtype=np.float64)
+        V = V / np.sqrt((V * V).sum(axis=0, keepdims=True))
+        k = V.shape[1]
+        return State(V=V.copy(), G=V.copy(),
+                     m=np.zeros_like(V) if adam else None,
+                     s2=np.zeros_like(V) if adam else None,
+                     t=0, ema_a=np.zeros(k), ema_b=np.zeros(k))
+
+    def eigvals(self) -> np.ndarray:
+        return self.ema_a / self.ema_b
+
+
+def _colmajor(M: np.ndarray) -> np.ndarray:
+    """(d, k) array -> contiguous buffer laid out d x k column-major."""
+    return np.ascontiguousarray(M.T, dtype=np.float64)
+
+
+def gamma_step(pb: Problem, st: State, X: np.ndarray, Y: Optional[np.ndarray], eta_t: float,
+               gamma_t: float, labels: Optional[np.ndarray] = None, return_grad: bool = False):
+    """One iteration of Alg. 2 (M = 1) on the minibatch (X, Y). Updates st in
+    place; returns the number of clipped parents (and the update direction
+    as a (d, k) array when return_grad)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    b = X.shape[0]
+    Yc = np.ascontiguousarray(Y if Y is not None else X, dtype=np.float64)
+    lab = None
+    if labels is not None:
+        lab_arr = np.ascontiguousarray(labels, dtype=np.int32)
+        lab = lab_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    V, G = _colmajor(st.V), _colmajor(st.G)
+    adam = pb.optimizer == OPT_ADAM
+    m = _colmajor(st.m) if adam else None
+    s2 = _colmajor(st.s2) if adam else None
+    ga = np.ascontiguousarray(st.ema_a, dtype=np.float64)
+    gb = np.ascontiguousarray(st.ema_b, dtype=np.float64)
+    grad = np.zeros((pb.k, pb.d)) if return_grad else None
+    st.t += 1
+    cp = pb._c()
+    rc = _load().oracle_gamma_step(ctypes.byref(cp), b, _dp(X), X.shape[1], _dp(Yc), Yc.shape[1],
+                                   lab, _dp(V), _dp(G), eta_t, gamma_t, float(st.t),
+                                   _dp(m), _dp(s2), _dp(ga), _dp(gb), _dp(grad))
+    if rc < 0:
+        raise MemoryError("oracle_gamma_step")
+    st.V, st.G, st.ema_a, st.ema_b = V.T.copy(), G.T.copy(), ga, gb
+    if adam:
+        st.m, st.s2 = m.T.copy(), s2.T.copy()
+    return (rc, grad.T.copy()) if return_grad else rc
+
+
+def gamma_step_dense(pb: Problem, st: State, A: np.ndarray, B: np.ndarray, eta_t: float,
+                     gamma_t: float, return_grad: bool = False):
+    """Alg. 2 iteration with exact A and B (full batch)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    V, G = _colmajor(st.V), _colmajor(st.G)
+    adam = pb.optimizer == OPT_ADAM
+    m = _colmajor(st.m) if adam else None
+    s2 = _colmajor(st.s2) if adam else None
+    ga = np.ascontiguousarray(st.ema_a, dtype=np.float64)
+    gb = np.ascontiguousarray(st.ema_b, dtype=np.float64)
+    grad = np.zeros((pb.k, A.shape[0])) if return_grad else None
+    st.t += 1
+    cp = pb._c()
+    rc = _load().oracle_gamma_step_dense(ctypes.byref(cp), A.shape[0], _dp(A), _dp(B), _dp(V),
+                                         _dp(G), eta_t, gamma_t, float(st.t), _dp(m), _dp(s2),
+                                         _dp(ga), _dp(gb), _dp(grad))
+    if rc < 0:
+        raise MemoryError("oracle_gamma_step_dense")
+    st.V, st.G, st.ema_a, st.ema_b = V.T.copy(), G.T.copy(), ga, gb
+    if adam:
+        st.m, st.s2 = m.T.copy(), s2.T.copy()
+    return (rc, grad.T.copy()) if return_grad else rc
+
+
+def alg1_step(A: np.ndarray, B: np.ndarray, V: np.ndarray, eta_t: float, return_grad: bool = False):
+    """One iteration of Alg. 1; returns the new V (and the direction)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    d, k = V.shape
+    Vc = _colmajor(V)
+    grad = np.zeros((k, d)) if return_grad else None
+    _load().oracle_alg1_step(d, k, _dp(A), _dp(B), _dp(Vc), eta_t, _dp(grad))
+    return (Vc.T.copy(), grad.T.copy()) if return_grad else Vc.T.copy()
+
+
+# --------------------------------------------------------------------------- #
+# Utilities, gradient and metrics (numpy, written from the formulas)         #
+# --------------------------------------------------------------------------- #
+
+def utility(A: np.ndarray, B: np.ndarray, V: np.ndarray, i: int) -> float:
+    """Player i's utility u_i(v_i | v_{j<i}) (Sec. 2, eq. util_new):
+    generalized Rayleigh quotient minus sum_{j<i} <v_j,Av_j> <v_i,Bv_j>^2 /
+    (<v_j,Bv_j>^2 <v_i,Bv_i>)."""
+    vi = V[:, i]
+    vBv = vi @ B @ vi
+    u = (vi @ A @ vi) / vBv
+    for j in range(i):
+        vj = V[:, j]
+        u -= (vj @ A @ vj) * (vi @ B @ vj) ** 2 / ((vj @ B @ vj) ** 2 * vBv)
+    return float(u)
+
+
+def utility_grad(A: np.ndarray, B: np.ndarray, V: np.ndarray, i: int) -> np.ndarray:
+    """Gradient of u_i with respect to v_i (App. B gradient lemma, including
+    the factor 2 and the common 1/<v_i,Bv_i>^2)."""
+    vi = V[:, i]
+    Avi, Bvi = A @ vi, B @ vi
+    vBv, vAv = vi @ Bvi, vi @ Avi
+    g = (vBv * Avi - vAv * Bvi) / vBv ** 2
+    for j in range(i):
+        vj = V[:, j]
+        Bvj = B @ vj
+        lam_j = (vj @ A @ vj) / (vj @ Bvj)
+        g -= lam_j / (vj @ Bvj) * (vi @ Bvj) * (vBv * Bvj - (vi @ Bvj) * Bvi) / vBv ** 2
+    return 2.0 * g
+
+
+def subspace_error(Vhat: np.ndarray, Vstar: np.ndarray, B: np.ndarray) -> float:
+    """Normalised subspace error of App. A in its Gram form.
+
+    With Vstar B-orthonormal (Vstar^T B Vstar = I), W = B^{1/2} Vstar is
+    orthonormal and 1 - tr(U* P)/k = 1 - tr(C^T G^{-1} C)/k where
+    C = Vhat^T B Vstar and G = Vhat^T B Vhat.  The sign and scale of each
+    column of Vhat do not matter."""
+    k = Vstar.shape[1]
+    BVs = B @ Vstar
+    C = Vhat.T @ BVs
+    G = Vhat.T @ (B @ Vhat)
+    return float(1.0 - np.trace(C.T @ np.linalg.solve(G, C)) / k)
+
+
+def subspace_error_definition(Vhat: np.ndarray, Vstar: np.ndarray, B: np.ndarray) -> float:
+    """The same error written as App. A defines it: W holds the top-k
+    eigenvectors of B^{-1/2} A B^{-1/2} (= B^{1/2} Vstar), What = B^{1/2} Vhat,
+    U* = W W^+, P = What What^+, error = 1 - tr(U* P)/k.  Uses the symmetric
+    square root of B from its eigen-decomposition."""
+    w, Q = np.linalg.eigh(B)
+    Bh = (Q * np.sqrt(w)) @ Q.T
+    W = Bh @ Vstar
+    Wh = Bh @ Vhat
+    U = W @ np.linalg.pinv(W)
+    P = Wh @ np.linalg.pinv(Wh)
+    return float(1.0 - np.trace(U @ P) / Vstar.shape[1])
+
+
+def cca_matrices(Sxx: np.ndarray, Syy: np.ndarray, Sxy: np.ndarray):
+    """A and B of CCA (Sec. 1): A = [[0, Sxy], [Sxy^T, 0]], B = diag(Sxx, Syy)."""
+    dx, dy = Sxx.shape[0], Syy.shape[0]
+    A = np.zeros((dx + dy, dx + dy))
+    A[:dx, dx:] = Sxy
+    A[dx:, :dx] = Sxy.T
+    B = np.zeros_like(A)
+    B[:dx, :dx] = Sxx
+    B[dx:, dx:] = Syy
+    return A, B
+
+
+def problem_matrices(pb: Problem, X: np.ndarray, Y: Optional[np.ndarray] = None,
+                     labels: Optional[np.ndarray] = None):
+    """Empirical A and B of a finite dataset (uncentred means, Sec. 1)."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    if pb.kind == KIND_CCA:
+        Y = np.asarray(Y, dtype=np.float64)
+        return cca_matrices(X.T @ X / n, Y.T @ Y / n, X.T @ Y / n)
+    if pb.kind == KIND_GENERAL:
+        Y = np.asarray(Y, dtype=np.float64)
+        return Y.T @ Y / n, X.T @ X / n + pb.eps_reg * np.eye(X.shape[1])
+    means = np.asarray(pb.class_means, dtype=np.float64)
+    c = means.shape[0]
+    pri = np.full(c, 1.0 / c) if pb.class_priors is None else np.asarray(pb.class_priors)
+    E = X - means[np.asarray(labels)]
+    B = E.T @ E / n + pb.eps_reg * np.eye(X.shape[1])
+    Mt = means - pri @ means
+    A = Mt.T @ (pri[:, None] * Mt)
+    return A, B

@@ -1,0 +1,53 @@
+"""Exact targets of the synthetic workloads -- TEST INFRASTRUCTURE.
+
+Population matrices A and B of each generator in ``synth`` (derived from the
+generator's definition), and closed-form top-k solutions where the
+construction plants them.  The generic route is ``oracle.gep_topk``."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import cca_matrices
+
+
+def cca_population(gen):
+    """Population covariances of ``synth.CCAPlanted``:
+    Sxx = Wx Wx^T + sigma^2 I, Syy likewise, Sxy = Wx[:, :r] diag(rho) Wy[:, :r]^T."""
+    r = len(gen.rho)
+    Sxx = gen.Wx @ gen.Wx.T + gen.sigma ** 2 * np.eye(gen.dx)
+    Syy = gen.Wy @ gen.Wy.T + gen.sigma ** 2 * np.eye(gen.dy)
+    Sxy = (gen.Wx[:, :r] * gen.rho[None, :]) @ gen.Wy[:, :r].T
+    return Sxx, Syy, Sxy
+
+
+def cca_population_AB(gen):
+    return cca_matrices(*cca_population(gen))
+
+
+def cca_planted_topk(gen, k: int):
+    """Closed-form top-k of the noiseless square-mixing CCA generator
+    (sigma = 0, Wx and Wy square and invertible): the canonical correlations
+    are the planted rho (descending) with B-orthonormal vectors
+    v_i = [Wx^{-T} e_i ; Wy^{-T} e_i] / sqrt(2)."""
+    assert gen.sigma == 0.0 and gen.Wx.shape[0] == gen.Wx.shape[1]
+    order = np.argsort(-gen.rho)[:k]
+    E = np.eye(gen.dx)[:, order]
+    Vx = np.linalg.solve(gen.Wx.T, E)
+    Vy = np.linalg.solve(gen.Wy.T, E)
+    return gen.rho[order].copy(), np.vstack([Vx, Vy]) / np.sqrt(2.0)
+
+
+def general_population_AB(gen):
+    """A = E[y y^T] = Ymap Ymap^T and B = E[x x^T] + eps I of ``synth.GeneralPlanted``."""
+    A = gen.Y_map @ gen.Y_map.T
+    B = gen.Sx_half @ gen.Sx_half.T + gen.eps * np.eye(gen.d)
+    return A, B
+
+
+def general_planted_topk(gen, k: int):
+    """Planted top-k: with L O = Ymap diag(lam^{-1/2}), v_i = (L O)^{-T} e_i,
+    which is B-orthonormal and satisfies A v_i = lam_i B v_i."""
+    LO = gen.Y_map / np.sqrt(gen.lam)[None, :]
+    order = np.argsort(-gen.lam)[:k]
+    E = np.eye(gen.d)[:, order]
+    return gen.lam[order].copy(), np.linalg.solve(LO.T, E)

@@ -1,0 +1,253 @@
+"""Seeded synthetic workloads for the five benchmark shapes.
+
+This module only DRAWS data: it holds none of the gamma-EigenGame
+arithmetic and is imported by both the tests/oracle side and the benchmark.
+Every array is a deterministic function of (seed, batch index).
+
+Workloads (the paper's datasets are not available; these stand in with the
+shapes of the benchmark configurations):
+
+* ``CCAPlanted``   paired views with planted canonical correlations
+                   (tiny CCA: d = 8 + 8, k = 4; medium CCA: d = 512 + 512,
+                   k = 16, condition number 100 per view).
+* ``CCAActivation`` activation-like paired views: ReLU of a shared Gaussian
+                   latent through dense maps with log-normal feature scales
+                   (d = 8192 + 8192).
+* ``GeneralPlanted`` general SGEP instance with A = E[y y^T],
+                   B = E[x x^T] + eps I and planted generalized eigenvalues.
+* ``LDAClasses``   Gaussian classes with means on a random low-dimensional
+                   subspace and diagonal within-class covariance.
+
+Generator seeds: parameters use ``seed``, the minibatch stream uses
+``(seed + 1, t)`` and the initial players ``seed + 2``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Tuple
+
+import numpy as np
+
+
+def _orth(rng: np.random.Generator, n: int, m: int) -> np.ndarray:
+    """n x m matrix with orthonormal columns (QR of a Gaussian, signs fixed)."""
+    q, r = np.linalg.qr(rng.standard_normal((n, m)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+def initial_players(d: int, k: int, seed: int) -> np.ndarray:
+    """Gaussian draws for the players' starting points, (d, k), NOT normalised
+    (each side normalises them itself)."""
+    return np.random.default_rng(seed + 2).standard_normal((d, k))
+
+
+@dataclass
+class CCAPlanted:
+    """x = Wx [z; e_x] + sigma n_x and y = Wy [z'; e_y] + sigma n_y, where the
+    r latent pairs (z_i, z'_i) are standard normal with correlation rho_i and
+    e, n are independent standard normal.  ``n_free`` extra latent noise
+    dimensions per view; ``spread`` gives the singular values of the mixing
+    maps as geomspace(1, spread, dx) (None: orthonormal columns)."""
+    dx: int
+    dy: int
+    rho: np.ndarray
+    sigma: float = 0.0
+    n_free: int = 0
+    spread: Optional[float] = None
+    seed: int = 0
+    Wx: np.ndarray = field(init=False, repr=False)
+    Wy: np.ndarray = field(init=False, repr=False)
+
+    def __post_init__(self):
+        rng = np.random.default_rng(self.seed)
+        self.rho = np.asarray(self.rho, dtype=np.float64)
+        r = len(self.rho)
+        cols = r + self.n_free
+        assert cols <= min(self.dx, self.dy)
+        self.Wx = _orth(rng, self.dx, cols)
+        self.Wy = _orth(rng, self.dy, cols)
+        if self.spread is not None:
+            assert cols == self.dx == self.dy
+            self.Wx = self.Wx * np.geomspace(1.0, self.spread, cols)[None, :]
+            self.Wy = self.Wy * np.geomspace(1.0, self.spread, cols)[None, :]
+
+    @property
+    def d(self) -> int:
+        return self.dx + self.dy
+
+    def sample(self, n: int, rng: np.random.Generator) -> Tuple[np.ndarray, np.ndarray]:
+        r = len(self.rho)
+        z = rng.standard_normal((n, r))
+        xi = rng.standard_normal((n, r))
+        z2 = z * self.rho + xi * np.sqrt(1.0 - self.rho ** 2)
+        ux = np.concatenate([z, rng.standard_normal((n, self.n_free))], axis=1)
+        uy = np.concatenate([z2, rng.standard_normal((n, self.n_free))], axis=1)
+        x = ux @ self.Wx.T
+        y = uy @ self.Wy.T
+        if self.sigma:
+            x += self.sigma * rng.standard_normal((n, self.dx))
+            y += self.sigma * rng.standard_normal((n, self.dy))
+        return x, y
+
+    def batch(self, t: int, b: int) -> Tuple[np.ndarray, np.ndarray]:
+        """Fresh minibatch number t (float64)."""
+        return self.sample(b, np.random.default_rng([self.seed + 1, t]))
+
+
+def tiny_cca(seed: int = 0) -> CCAPlanted:
+    """Two views of width 8 from 4 latent pairs with correlations
+    0.9, 0.7, 0.5, 0.3, orthonormal mixing and 0.1 isotropic noise."""
+    return CCAPlanted(8, 8, np.array([0.9, 0.7, 0.5, 0.3]), sigma=0.1, seed=seed)
+
+
+def medium_cca(seed: int = 0) -> CCAPlanted:
+    """Two views of width 512; 16 latent pairs with correlations linearly
+    spaced 0.95 -> 0.2, the other 496 latent dimensions independent noise,
+    mixing maps Q diag(geomspace(1, 0.1, 512)) (per-view condition 100)."""
+    return CCAPlanted(512, 512, np.linspace(0.95, 0.2, 16), sigma=0.0, n_free=496, spread=0.1,
+                      seed=seed)
+
+
+@dataclass
+class Pool:
+    """A fixed finite dataset with i.i.d. minibatch indices drawn with
+    replacement (used for the tiny CCA case: n = 10,000 pairs)."""
+    X: np.ndarray
+    Y: Optional[np.ndarray]
+    seed: int
+    labels: Optional[np.ndarray] = None
+
+    def indices(self, t: int, b: int) -> np.ndarray:
+        return np.random.default_rng([self.seed + 1, t]).integers(0, self.X.shape[0], size=b)
+
+    def batch(self, t: int, b: int):
+        idx = self.indices(t, b)
+        Y = None if self.Y is None else self.Y[idx]
+        return self.X[idx], Y
+
+
+def tiny_cca_pool(seed: int = 0, n: int = 10_000) -> Tuple[CCAPlanted, Pool]:
+    gen = tiny_cca(seed)
+    X, Y = gen.sample(n, np.random.default_rng([seed, 7]))
+    return gen, Pool(X, Y, seed)
+
+
+@dataclass
+class CCAActivation:
+    """Activation-like paired views: a shared latent h ~ N(0, I_r), then
+    x = Dx (relu(Wx h + xi) - mu_x), y = Dy (relu(Wy h + xi') - mu_y) with
+    W Gaussian / sqrt(r), xi standard normal noise, D = diag(exp(N(0, 1)))
+    (log-normal feature scales, sigma = 1) and mu the exact mean of the
+    ReLU of a centred Gaussian of standard deviation s (mu = s / sqrt(2 pi)),
+    so the views have mean zero."""
+    dx: int = 8192
+    dy: int = 8192
+    r: int = 64
+    seed: int = 0
+    Wx: np.ndarray = field(init=False, repr=False)
+    Wy: np.ndarray = field(init=False, repr=False)
+    Dx: np.ndarray = field(init=False, repr=False)
+    Dy: np.ndarray = field(init=False, repr=False)
+
+    def __post_init__(self):
+        rng = np.random.default_rng(self.seed)
+        self.Wx = rng.standard_normal((self.dx, self.r)) / np.sqrt(self.r)
+        self.Wy = rng.standard_normal((self.dy, self.r)) / np.sqrt(self.r)
+        self.Dx = np.exp(rng.standard_normal(self.dx))
+        self.Dy = np.exp(rng.standard_normal(self.dy))
+
+    @property
+    def d(self) -> int:
+        return self.dx + self.dy
+
+    def relu_means(self):
+        sx = np.sqrt((self.Wx ** 2).sum(axis=1) + 1.0)
+        sy = np.sqrt((self.Wy ** 2).sum(axis=1) + 1.0)
+        return sx / np.sqrt(2 * np.pi), sy / np.sqrt(2 * np.pi)
+
+    def sample(self, n: int, rng: np.random.Generator, dtype=np.float32):
+        h = rng.standard_normal((n, self.r)).astype(np.float32)
+        mx, my = self.relu_means()
+        ux = h @ self.Wx.T.astype(np.float32) + rng.standard_normal((n, self.dx), dtype=np.float32)
+        uy = h @ self.Wy.T.astype(np.float32) + rng.standard_normal((n, self.dy), dtype=np.float32)
+        x = (np.maximum(ux, 0) - mx.astype(np.float32)) * self.Dx.astype(np.float32)
+        y = (np.maximum(uy, 0) - my.astype(np.float32)) * self.Dy.astype(np.float32)
+        return x.astype(dtype, copy=False), y.astype(dtype, copy=False)
+
+    def batch(self, t: int, b: int, dtype=np.float32):
+        return self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)
+
+
+@dataclass
+class GeneralPlanted:
+    """General SGEP instance of width d: x = Qx diag(sqrt(ax)) g with ax
+    log-uniform in [0.1, 1]; B = E[x x^T] + eps I = L L^T; y = L O diag(sqrt(lam)) g'
+    with O random orthogonal, so that A = E[y y^T] = L O diag(lam) O^T L^T and
+    A v = lam B v holds exactly for v = L^{-T} O e_i.  The top ``k`` planted
+    values are geomspace(10, 0.1, k), the rest uniform in [0.01, 0.05]."""
+    d: int
+    k: int = 8
+    eps: float = 1e-3
+    seed: int = 0
+    Sx_half: np.ndarray = field(init=False, repr=False)
+    Y_map: np.ndarray = field(init=False, repr=False)
+    lam: np.ndarray = field(init=False, repr=False)
+    ax: np.ndarray = field(init=False, repr=False)
+    Qx: np.ndarray = field(init=False, repr=False)
+
+    def __post_init__(self):
+        rng = np.random.default_rng(self.seed)
+        d = self.d
+        self.Qx = _orth(rng, d, d)
+        self.ax = np.exp(rng.uniform(np.log(0.1), np.log(1.0), size=d))
+        self.Sx_half = self.Qx * np.sqrt(self.ax)[None, :]
+        Bfull = (self.Qx * self.ax[None, :]) @ self.Qx.T + self.eps * np.eye(d)
+        L = np.linalg.cholesky(Bfull)
+        O = _orth(rng, d, d)
+        lam = np.empty(d)
+        lam[: self.k] = np.geomspace(10.0, 0.1, self.k)
+        lam[self.k:] = rng.uniform(0.01, 0.05, size=d - self.k)
+        self.lam = lam
+        self.Y_map = (L @ O) * np.sqrt(lam)[None, :]
+
+    def sample(self, n: int, rng: np.random.Generator, dtype=np.float64):
+        x = rng.standard_normal((n, self.d)) @ self.Sx_half.T
+        y = rng.standard_normal((n, self.d)) @ self.Y_map.T
+        return x.astype(dtype, copy=False), y.astype(dtype, copy=False)
+
+    def batch(self, t: int, b: int, dtype=np.float64):
+        return self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)
+
+
+def batched_dims(n: int = 256, lo: int = 64, hi: int = 2048, seed: int = 0) -> np.ndarray:
+    """Instance widths d_i uniform on {lo..hi} for the batched workload."""
+    return np.random.default_rng([seed, 11]).integers(lo, hi + 1, size=n)
+
+
+@dataclass
+class LDAClasses:
+    """c Gaussian classes in R^d with equal priors: means mu_c = U a_c with U
+    (d x r) orthonormal and a_c ~ N(0, 4 I_r); within-class covariance
+    diag(sigma_f^2) with sigma_f log-uniform in [0.3, 3]; labels uniform."""
+    d: int = 65536
+    c: int = 10
+    r: int = 64
+    seed: int = 0
+    means: np.ndarray = field(init=False, repr=False)
+    sigma: np.ndarray = field(init=False, repr=False)
+
+    def __post_init__(self):
+        rng = np.random.default_rng(self.seed)
+        U = _orth(rng, self.d, self.r)
+        a = 2.0 * rng.standard_normal((self.c, self.r))
+        self.means = a @ U.T
+        self.sigma = np.exp(rng.uniform(np.log(0.3), np.log(3.0), size=self.d))
+
+    def sample(self, n: int, rng: np.random.Generator, dtype=np.float32):
+        lab = rng.integers(0, self.c, size=n).astype(np.int32)
+        x = self.means[lab].astype(np.float32) + (
+            rng.standard_normal((n, self.d), dtype=np.float32) * self.sigma.astype(np.float32))
+        return x.astype(dtype, copy=False), lab
+
+    def batch(self, t: int, b: int, dtype=np.float32):
+        return self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)

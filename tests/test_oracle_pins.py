@@ -1,0 +1,427 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these retypes the oracle's own formula: each compares it with a value
+the paper prints, a closed form, an invariant, a library routine the paper
+itself names as ground truth (scipy.linalg.eigh), or brute force."""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle
+from oracle import targets
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_spd(rng, d, shift=1.0):
+    M = rng.standard_normal((d, d))
+    return M @ M.T / d + shift * np.eye(d)
+
+
+def _rand_sym(rng, d):
+    M = rng.standard_normal((d, d))
+    return (M + M.T) / 2
+
+
+def _unit(V):
+    return V / np.linalg.norm(V, axis=0, keepdims=True)
+
+
+# --------------------------------------------------------------------------- #
+# Exact solver                                                                 #
+# --------------------------------------------------------------------------- #
+
+def test_worked_example_2x2_angle_and_utilities():
+    """App. B example matrices; Fig. 1: eigenvectors ~71 deg (109 deg) apart,
+    u_2 = 0 when player 2 copies v_1 and u_2 = lambda_2 at v_2."""
+    g = json.load(open(os.path.join(GOLDEN, "warped_sinusoid_2x2.json")))
+    A, B = np.array(g["A"]), np.array(g["B"])
+    lam, V = oracle.gep_topk(A, B, 2)
+    U = _unit(V)
+    ang = np.degrees(np.arccos(U[:, 0] @ U[:, 1]))
+    folded = min(ang, 180 - ang)
+    assert abs(folded - g["angle_deg"]) < g["angle_tolerance_deg"]
+    assert abs(max(ang, 180 - ang) - g["angle_deg_supplement"]) < g["angle_tolerance_deg"]
+    W = np.stack([U[:, 0], U[:, 0]], axis=1)
+    assert abs(oracle.utility(A, B, W, 1)) < 1e-12
+    W = np.stack([U[:, 0], U[:, 1]], axis=1)
+    assert abs(oracle.utility(A, B, W, 1) - lam[1]) < 1e-10 * lam[0]
+
+
+@pytest.mark.parametrize("d,k", [(2, 1), (7, 3), (16, 4), (40, 8)])
+def test_gep_matches_scipy_and_is_b_orthonormal(d, k):
+    """scipy.linalg.eigh(A, B) is the ground truth the paper uses; V^T B V = I
+    (B-orthogonality lemma) and A v = lambda B v."""
+    rng = np.random.default_rng(d)
+    A, B = _rand_sym(rng, d), _rand_spd(rng, d)
+    lam, V = oracle.gep_topk(A, B, k)
+    ref = sla.eigh(A, B, eigvals_only=True)[::-1][:k]
+    assert np.allclose(lam, ref, rtol=0, atol=1e-12 * abs(ref).max())
+    assert np.abs(V.T @ B @ V - np.eye(k)).max() < 1e-12
+    res = A @ V - (B @ V) * lam[None, :]
+    assert np.abs(res).max() < 1e-12 * np.abs(A).max() * max(1, np.abs(V).max())
+    # vectors agree with scipy's up to sign
+    w, Z = sla.eigh(A, B)
+    Z = Z[:, ::-1][:, :k]
+    for i in range(k):
+        assert min(np.abs(V[:, i] - Z[:, i]).max(), np.abs(V[:, i] + Z[:, i]).max()) < 1e-9
+
+
+def test_cholesky_and_jacobi_against_definitions():
+    rng = np.random.default_rng(3)
+    B = _rand_spd(rng, 12)
+    L = oracle.cholesky(B)
+    assert np.allclose(np.triu(L, 1), 0) and np.all(np.diag(L) > 0)
+    assert np.abs(L @ L.T - B).max() < 1e-13
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.cholesky(-B)
+    C = _rand_sym(rng, 12)
+    w, Z = oracle.jacobi_eigh(C)
+    assert np.abs(Z.T @ Z - np.eye(12)).max() < 1e-13
+    assert np.abs(C @ Z - Z * w[None, :]).max() < 1e-12
+    assert np.allclose(np.sort(w), np.linalg.eigvalsh(C), atol=1e-12)
+
+
+def _count_below(A, B, sigma):
+    """Sylvester inertia: number of eigenvalues of (A, B) below sigma equals
+    the number of negative pivots of symmetric elimination of A - sigma B."""
+    M = (A - sigma * B).copy()
+    n = M.shape[0]
+    neg = 0
+    for p in range(n):
+        piv = M[p, p]
+        if piv < 0:
+            neg += 1
+        for i in range(p + 1, n):
+            f = M[i, p] / piv
+            for j in range(p + 1, n):
+                M[i, j] -= f * M[p, j]
+    return neg
+
+
+def test_brute_force_bisection_d16():
+    """Eigenvalues by bisection on inertia counts and vectors by inverse
+    iteration, on a d = 16 instance (the tiny CCA width)."""
+    rng = np.random.default_rng(16)
+    d, k = 16, 4
+    A, B = _rand_sym(rng, d), _rand_spd(rng, d)
+    lam, V = oracle.gep_topk(A, B, k)
+    R = 1e3
+    for i in range(k):
+        target = d - 1 - i  # index in ascending order
+        lo, hi = -R, R
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            if _count_below(A, B, mid) > target:
+                hi = mid
+            else:
+                lo = mid
+        lam_bf = 0.5 * (lo + hi)
+        assert abs(lam_bf - lam[i]) < 1e-11
+        v = rng.standard_normal(d)
+        for _ in range(3):
+            v = np.linalg.solve(A - (lam_bf + 1e-9) * B, B @ v)
+            v /= np.sqrt(v @ B @ v)
+        assert min(np.abs(v - V[:, i]).max(), np.abs(v + V[:, i]).max()) < 1e-7
+
+
+def test_planted_cca_spectrum_tiny():
+    """Orthonormal mixing with 0.1 noise: canonical correlations rho/(1+0.1^2)."""
+    gen = synth.tiny_cca(0)
+    A, B = targets.cca_population_AB(gen)
+    lam, V = oracle.gep_topk(A, B, 4)
+    assert np.allclose(lam, gen.rho / 1.01, atol=1e-12)
+    # the spectrum of the CCA pencil is symmetric: -rho/1.01 are eigenvalues too
+    lam_all, _ = oracle.gep_topk(A, B, 16)
+    assert np.allclose(np.sort(lam_all)[:4], -gen.rho / 1.01, atol=1e-12)
+
+
+def test_planted_cca_closed_form_matches_exact_solver():
+    """Noiseless square mixing: the planted correlations exactly, with
+    v_i = [Wx^{-T} e_i; Wy^{-T} e_i]/sqrt(2) (per-view invariance of CCA)."""
+    gen = synth.CCAPlanted(32, 32, np.linspace(0.95, 0.2, 4), n_free=28, spread=0.1, seed=5)
+    A, B = targets.cca_population_AB(gen)
+    lam, V = oracle.gep_topk(A, B, 4)
+    lam_c, V_c = targets.cca_planted_topk(gen, 4)
+    assert np.allclose(lam, lam_c, atol=1e-11)
+    assert oracle.subspace_error(V_c, V, B) < 1e-12
+    assert np.abs(V_c.T @ B @ V_c - np.eye(4)).max() < 1e-10
+
+
+def test_general_planted_matches_exact_solver():
+    gen = synth.GeneralPlanted(40, k=8, seed=2)
+    A, B = targets.general_population_AB(gen)
+    lam, V = oracle.gep_topk(A, B, 8)
+    lam_c, V_c = targets.general_planted_topk(gen, 8)
+    assert np.allclose(lam, np.geomspace(10, 0.1, 8), rtol=1e-10)
+    assert np.allclose(lam_c, lam, rtol=1e-10)
+    assert oracle.subspace_error(V_c, V, B) < 1e-12
+
+
+# --------------------------------------------------------------------------- #
+# Metric                                                                       #
+# --------------------------------------------------------------------------- #
+
+def test_subspace_error_gram_form_equals_definition():
+    rng = np.random.default_rng(4)
+    d, k = 12, 3
+    A, B = _rand_sym(rng, d), _rand_spd(rng, d)
+    lam, Vs = oracle.gep_topk(A, B, k)
+    for _ in range(5):
+        Vh = rng.standard_normal((d, k))
+        e1 = oracle.subspace_error(Vh, Vs, B)
+        e2 = oracle.subspace_error_definition(Vh, Vs, B)
+        assert abs(e1 - e2) < 1e-12 and 0 <= e1 <= 1
+    # exact subspace (any scaling / sign / order) -> 0
+    assert abs(oracle.subspace_error(Vs[:, ::-1] * np.array([2.0, -1.0, 0.5]), Vs, B)) < 1e-12
+    # B-orthogonal complement -> 1
+    _, Vall = oracle.gep_topk(A, B, d)
+    assert abs(oracle.subspace_error(Vall[:, k:2 * k], Vs, B) - 1.0) < 1e-12
+
+
+# --------------------------------------------------------------------------- #
+# Update direction and Alg. 2                                                  #
+# --------------------------------------------------------------------------- #
+
+def _cca_data(rng, b=64, dx=5, dy=7):
+    Z = rng.standard_normal((b, 3))
+    X = Z @ rng.standard_normal((3, dx)) + 0.3 * rng.standard_normal((b, dx))
+    Y = Z @ rng.standard_normal((3, dy)) + 0.3 * rng.standard_normal((b, dy))
+    return X, Y
+
+
+@pytest.mark.parametrize("kind", [oracle.KIND_CCA, oracle.KIND_GENERAL, oracle.KIND_LDA])
+def test_minibatch_products_equal_dense_matrices(kind):
+    """The per-row sums of the minibatch step equal the step taken with the
+    minibatch's A and B formed explicitly (Sec. 1 definitions)."""
+    rng = np.random.default_rng(10 + kind)
+    k = 3
+    labels = None
+    if kind == oracle.KIND_CCA:
+        X, Y = _cca_data(rng)
+        pb = oracle.Problem(kind, k, 5, 7, rho=1e-6)
+    elif kind == oracle.KIND_GENERAL:
+        X, Y = rng.standard_normal((50, 9)), rng.standard_normal((50, 9)) * 2
+        pb = oracle.Problem(kind, k, 9, 9, eps_reg=1e-2)
+    else:
+        means = rng.standard_normal((4, 9))
+        labels = rng.integers(0, 4, size=50)
+        X, Y = means[labels] + 0.5 * rng.standard_normal((50, 9)), None
+        pb = oracle.Problem(kind, k, 9, eps_reg=1e-2, class_means=means,
+                            class_priors=np.array([0.1, 0.2, 0.3, 0.4]))
+    A, B = oracle.problem_matrices(pb, X, Y, labels)
+    V0 = rng.standard_normal((pb.d, k))
+    s1 = oracle.State.init(V0)
+    s1.G = s1.G + 0.1 * rng.standard_normal(s1.G.shape)
+    s2 = oracle.State(V=s1.V.copy(), G=s1.G.copy(), ema_a=np.zeros(k), ema_b=np.zeros(k))
+    _, g1 = oracle.gamma_step(pb, s1, X, Y, 0.1, 0.3, labels=labels, return_grad=True)
+    _, g2 = oracle.gamma_step_dense(pb, s2, A, B, 0.1, 0.3, return_grad=True)
+    assert np.abs(g1 - g2).max() < 1e-12 * np.abs(g2).max()
+    assert np.abs(s1.V - s2.V).max() < 1e-13
+    assert np.abs(s1.G - s2.G).max() < 1e-13
+
+
+def test_tangency_of_update_direction():
+    """With one minibatch for every term, v_i^T grad_i = 0 for any V, G."""
+    rng = np.random.default_rng(5)
+    X, Y = _cca_data(rng)
+    pb = oracle.Problem(oracle.KIND_CCA, 4, 5, 7, rho=1e-6)
+    st = oracle.State.init(rng.standard_normal((12, 4)))
+    st.G = rng.standard_normal(st.G.shape)
+    V = st.V.copy()
+    _, g = oracle.gamma_step(pb, st, X, Y, 0.1, 0.5, return_grad=True)
+    for i in range(4):
+        assert abs(V[:, i] @ g[:, i]) <= 1e-13 * np.linalg.norm(g[:, i])
+
+
+def test_fixed_point_at_exact_solution():
+    """Lemma (right fixed point): with exact expectations, unit-norm exact
+    eigenvectors and [Bv] = Bv, the update direction vanishes."""
+    rng = np.random.default_rng(6)
+    d, k = 10, 4
+    A, B = _rand_sym(rng, d) + 3 * np.eye(d), _rand_spd(rng, d)
+    lam, Vs = oracle.gep_topk(A, B, k)
+    pb = oracle.Problem(oracle.KIND_GENERAL, k, d, d, rho=0.0)
+    st = oracle.State.init(Vs)
+    st.G = B @ st.V
+    V0 = st.V.copy()
+    _, g = oracle.gamma_step_dense(pb, st, A, B, 0.5, 1.0, return_grad=True)
+    assert np.abs(g).max() < 1e-13 * np.abs(A).max()
+    assert np.abs(st.V - V0).max() < 1e-13
+
+
+def test_reduces_to_mu_eigengame_when_b_is_identity():
+    """Proposition (equivalence when B = I): with G = V the direction is
+    (I - v_i v_i^T)[A v_i - sum_{j<i} (v_i^T A v_j) v_j]."""
+    rng = np.random.default_rng(7)
+    d, k = 9, 4
+    A = _rand_sym(rng, d)
+    pb = oracle.Problem(oracle.KIND_GENERAL, k, d, d, rho=0.0)
+    st = oracle.State.init(rng.standard_normal((d, k)))
+    V = st.V.copy()
+    _, g = oracle.gamma_step_dense(pb, st, A, np.eye(d), 0.1, 1.0, return_grad=True)
+    for i in range(k):
+        vi = V[:, i]
+        u = A @ vi - sum((vi @ A @ V[:, j]) * V[:, j] for j in range(i))
+        ref = u - vi * (vi @ u)
+        assert np.abs(g[:, i] - ref).max() < 1e-13 * max(1, np.abs(ref).max())
+
+
+def test_utility_gradient_finite_differences_and_steepest_ascent():
+    """Gradient lemma against central differences of the utility; with exact
+    parents and [Bv] = Bv the update direction equals <v_i,Bv_i>^2/2 times
+    the utility gradient (steepest-ascent lemma)."""
+    rng = np.random.default_rng(8)
+    d, k = 8, 3
+    A, B = _rand_sym(rng, d) + 2 * np.eye(d), _rand_spd(rng, d)
+    lam, Vs = oracle.gep_topk(A, B, k)
+    V = _unit(Vs.copy())
+    V[:, k - 1] = _unit(rng.standard_normal((d, 1)))[:, 0]  # last player arbitrary
+    i = k - 1
+    g = oracle.utility_grad(A, B, V, i)
+    h = 1e-6
+    fd = np.zeros(d)
+    for f in range(d):
+        Vp, Vm = V.copy(), V.copy()
+        Vp[f, i] += h
+        Vm[f, i] -= h
+        fd[f] = (oracle.utility(A, B, Vp, i) - oracle.utility(A, B, Vm, i)) / (2 * h)
+    assert np.abs(fd - g).max() < 1e-6 * np.abs(g).max()
+    pb = oracle.Problem(oracle.KIND_GENERAL, k, d, d, rho=0.0)
+    st = oracle.State(V=V.copy(), G=B @ V, ema_a=np.zeros(k), ema_b=np.zeros(k))
+    _, gt = oracle.gamma_step_dense(pb, st, A, B, 0.0, 0.0, return_grad=True)
+    vi = V[:, i]
+    scale = (vi @ B @ vi) ** 2 / 2
+    assert np.abs(gt[:, i] - scale * g).max() < 1e-12 * np.abs(gt[:, i]).max()
+
+
+def test_utility_equals_deflated_rayleigh_quotient():
+    """Deflation proposition: with exact parents u_i equals the Rayleigh
+    quotient of (I - sum_{j<i} B v_j v_j^T / ||v_j||_B^2) A."""
+    rng = np.random.default_rng(9)
+    d, k = 8, 3
+    A, B = _rand_sym(rng, d), _rand_spd(rng, d)
+    lam, Vs = oracle.gep_topk(A, B, k)
+    V = _unit(Vs.copy())
+    for _ in range(3):
+        V[:, k - 1] = rng.standard_normal(d)
+        D = np.eye(d)
+        for j in range(k - 1):
+            vj = Vs[:, j]
+            D -= np.outer(B @ vj, vj) / (vj @ B @ vj)
+        At = D @ A
+        vi = V[:, k - 1]
+        assert abs(oracle.utility(A, B, V, k - 1) - (vi @ At @ vi) / (vi @ B @ vi)) < 1e-12
+
+
+def test_alg2_with_exact_auxiliary_equals_alg1():
+    """With [Bv] reset to the exact B v before each iteration and rho = 0,
+    Alg. 2 on exact matrices takes exactly Alg. 1's step."""
+    rng = np.random.default_rng(11)
+    d, k = 10, 4
+    A, B = _rand_sym(rng, d), _rand_spd(rng, d)
+    pb = oracle.Problem(oracle.KIND_GENERAL, k, d, d, rho=0.0)
+    st = oracle.State.init(rng.standard_normal((d, k)))
+    V1 = st.V.copy()
+    for t in range(1, 6):
+        st.G = B @ st.V
+        oracle.gamma_step_dense(pb, st, A, B, 0.05, 1.0)
+        V1 = oracle.alg1_step(A, B, V1, 0.05)
+        assert np.abs(st.V - V1).max() < 1e-13
+
+
+def _problem_with_gap(rng, d):
+    A = _rand_sym(rng, d)
+    B = _rand_spd(rng, d)
+    return A, B
+
+
+def test_full_batch_convergence_alg1_and_alg2():
+    """Convergence theorem (deterministic case): Alg. 1, and Alg. 2 on exact
+    matrices, reach the exact top-k to 1e-10 subspace error."""
+    rng = np.random.default_rng(12)
+    d, k = 8, 3
+    lam_p = np.array([5.0, 3.0, 2.0, 0.5, 0.3, 0.2, 0.1, 0.05])
+    B = _rand_spd(rng, d)
+    L = np.linalg.cholesky(B)
+    Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    A = L @ Q @ np.diag(lam_p) @ Q.T @ L.T
+    lam, Vs = oracle.gep_topk(A, B, k)
+    assert np.allclose(lam, lam_p[:k])
+    V = _unit(rng.standard_normal((d, k)))
+    for t in range(1, 4001):
+        V = oracle.alg1_step(A, B, V, 0.05)
+    assert oracle.subspace_error(V, Vs, B) < 1e-10
+    pb = oracle.Problem(oracle.KIND_GENERAL, k, d, d, rho=0.0)
+    st = oracle.State.init(rng.standard_normal((d, k)))
+    for t in range(1, 4001):
+        oracle.gamma_step_dense(pb, st, A, B, 0.05, 0.5)
+    assert oracle.subspace_error(st.V, Vs, B) < 1e-10
+    # the Rayleigh-quotient readout converges to the eigenvalues
+    assert np.allclose(st.eigvals(), lam, rtol=1e-8)
+
+
+def test_stochastic_tiny_cca_reaches_1e3():
+    """Alg. 2 on the tiny CCA pool (n = 10,000, b = 128, 2000 steps) reaches
+    1e-3 subspace error against the pool's exact solution."""
+    gen, pool = synth.tiny_cca_pool(0)
+    pb = oracle.Problem(oracle.KIND_CCA, 4, 8, 8, rho=1e-6)
+    A, B = oracle.problem_matrices(pb, pool.X, pool.Y)
+    lam, Vs = oracle.gep_topk(A, B, 4)
+    # empirical correlations close to the population ones rho/1.01
+    assert np.abs(lam - gen.rho / 1.01).max() < 0.03
+    st = oracle.State.init(synth.initial_players(16, 4, 0))
+    for t in range(1, 2001):
+        X, Y = pool.batch(t, 128)
+        oracle.gamma_step(pb, st, X, Y, oracle.eta(oracle.SCHED_INV, t, 1.0, t0=200.0), 1.0)
+    assert oracle.subspace_error(st.V, Vs, B) < 1e-3
+
+
+def test_clip_counts_and_guards():
+    """<v_j, [Bv]_j> below rho is clipped (Alg. 2): with G = -V every player
+    is clipped and the step stays finite."""
+    rng = np.random.default_rng(13)
+    X, Y = _cca_data(rng)
+    pb = oracle.Problem(oracle.KIND_CCA, 3, 5, 7, rho=1e-3)
+    st = oracle.State.init(rng.standard_normal((12, 3)))
+    st.G = -st.V
+    n = oracle.gamma_step(pb, st, X, Y, 0.1, 0.5)
+    assert n == 3
+    assert np.all(np.isfinite(st.V))
+    assert np.allclose(np.linalg.norm(st.V, axis=0), 1.0)
+
+
+def test_adam_first_step_closed_form():
+    """First Adam step: bias-corrected moments are g and g^2, so the step is
+    eta * g / (|g| + eps) before the retraction."""
+    rng = np.random.default_rng(14)
+    X, Y = _cca_data(rng)
+    pb = oracle.Problem(oracle.KIND_CCA, 3, 5, 7, rho=1e-6, optimizer=oracle.OPT_ADAM)
+    st = oracle.State.init(rng.standard_normal((12, 3)), adam=True)
+    V = st.V.copy()
+    pb_sgd = oracle.Problem(oracle.KIND_CCA, 3, 5, 7, rho=1e-6)
+    st2 = oracle.State.init(V)
+    _, g = oracle.gamma_step(pb_sgd, st2, X, Y, 0.0, 0.5, return_grad=True)
+    oracle.gamma_step(pb, st, X, Y, 0.01, 0.5)
+    ref = _unit(V + 0.01 * g / (np.abs(g) + 1e-8))
+    assert np.abs(st.V - ref).max() < 1e-12
+
+
+def test_schedules_closed_forms():
+    e = oracle.eta
+    assert e(oracle.SCHED_CONST, 17, 0.3) == 0.3
+    assert abs(e(oracle.SCHED_INV, 200, 1.0, t0=200) - 0.5) < 1e-15
+    # warmup + harmonic decay with the neural-CCA table's values: Delta = 0
+    kw = dict(eta0=1e-4, eta_T=1e-6, t_c=1e5, T=1e7)
+    assert abs(e(oracle.SCHED_WARMUP_HARMONIC, 5e4, **kw) - 0.5e-4) < 1e-18
+    assert abs(e(oracle.SCHED_WARMUP_HARMONIC, 1e5, **kw) - 1e-4) < 1e-18
+    assert abs(e(oracle.SCHED_WARMUP_HARMONIC, 1e7, **kw) - 1e-6) < 1e-18
+    assert abs(e(oracle.SCHED_WARMUP_HARMONIC, 2e5, **kw) - 0.5e-4) < 1e-18
+    # a case with nonzero Delta still hits both ends
+    kw = dict(eta0=1e-2, eta_T=1e-3, t_c=100, T=1000)
+    assert abs(e(oracle.SCHED_WARMUP_HARMONIC, 100, **kw) - 1e-2) < 1e-15
+    assert abs(e(oracle.SCHED_WARMUP_HARMONIC, 1000, **kw) - 1e-3) < 1e-15
