@@ -1,0 +1,187 @@
+/*
+ * sgep.h -- C ABI of the MI355X streaming symmetric generalized eigensolver
+ * (stochastic gamma-EigenGame, Gemp, Chen, McWilliams, ICLR 2023,
+ * arXiv 2206.04993).
+ *
+ * The library finds the top-k generalized eigenvectors of A v = lambda B v
+ * (A symmetric, B symmetric positive definite; Sec. 1) from a stream of
+ * minibatches, by the k-player update of Alg. 2 (M = 1 machine per player:
+ * one GPU sees the whole minibatch).  A and B are never formed: each step only
+ * needs products of the minibatch with the players' vectors (Sec. 1, App. I).
+ *
+ * Problem kinds (Sec. 1):
+ *   SGEP_KIND_CCA      paired views x (dx) and y (dy), d = dx + dy,
+ *                      A = [[0, E xy^T], [E yx^T, 0]], B = diag(E xx^T, E yy^T)
+ *   SGEP_KIND_GENERAL  two streams of width d: A = E[y y^T], B = E[x x^T] + eps I
+ *   SGEP_KIND_LDA      (reserved; returns SGEP_EUNSUPPORTED in this version)
+ * Expectations are estimated by minibatch means (1/b) sum over the rows; the
+ * data are taken as zero-mean (Sec. 1); no centring is applied.
+ *
+ * Conventions
+ *   - Every call returns an sgep_status; 0 is success.
+ *   - Argument and shape errors are returned synchronously and leave the
+ *     handle unchanged.
+ *   - Device faults detected inside a step (non-finite Gram terms or norms)
+ *     are latched in a device status word and reported by the next call that
+ *     synchronises (sgep_eigvals, sgep_vectors, sgep_auxiliary,
+ *     sgep_get_state, sgep_sync).  The handle is then POISONED: every later
+ *     call except sgep_set_state and sgep_destroy returns SGEP_EPOISONED.
+ *   - Host arrays of player vectors are d x k COLUMN-major doubles: column i
+ *     (elements i*d .. i*d+d-1) is player i.
+ *   - Minibatch views are device arrays, ROW-major (one sample per row) with a
+ *     leading dimension in elements; they are borrowed, never copied or
+ *     retained beyond the work the call enqueues on the handle's stream.
+ *   - sgep_step never synchronises the host, allocates memory or copies to
+ *     pageable memory, so a sequence of steps can be captured in a hipGraph;
+ *     the step counter t and the step sizes live on the device.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - The library runs on gfx950 only and has no CPU fallback.
+ */
+#ifndef SGEP_H
+#define SGEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sgep_status;
+#define SGEP_OK 0
+#define SGEP_EINVAL (-1)       /* bad argument value or NULL pointer */
+#define SGEP_ESHAPE (-2)       /* inconsistent sizes / leading dimensions / alignment */
+#define SGEP_ENOMEM (-3)       /* device allocation failed (init only) */
+#define SGEP_EDEVICE (-4)      /* HIP runtime error */
+#define SGEP_ENONFINITE (-5)   /* a step produced a non-finite or zero norm / Gram term */
+#define SGEP_EUNSUPPORTED (-6) /* valid request this build does not implement */
+#define SGEP_EPOISONED (-7)    /* an earlier fault poisoned the handle */
+
+/* problem kinds */
+#define SGEP_KIND_CCA 0
+#define SGEP_KIND_GENERAL 1
+#define SGEP_KIND_LDA 2
+
+/* element type of the minibatch views (and of the arithmetic) */
+#define SGEP_F64 0     /* FP64 data, FP64 MFMA, FP64 state */
+#define SGEP_F32 1     /* FP32 data, FP32 MFMA, FP32 state */
+#define SGEP_BF16 2    /* reserved */
+#define SGEP_FP8_E4M3 3 /* reserved */
+
+/* optimiser applied to the update direction (Alg. 2 uses plain ascent;
+ * App. H uses Adam with b1 = 0.9, b2 = 0.999, eps = 1e-8) */
+#define SGEP_SGD 0
+#define SGEP_ADAM 1
+
+/* step-size schedules for eta_t, t = 1, 2, ...
+ *   CONST            eta0
+ *   INV              eta0 / (1 + t / t0): square-summable, not summable
+ *                    (condition of the convergence theorem, Sec. 3)
+ *   WARMUP_HARMONIC  eta0 * t / t_c for t < t_c, then eta0 (t_c + D) / (t + D)
+ *                    with D chosen so that eta_T is reached at t = T (App. H) */
+#define SGEP_SCHED_CONST 0
+#define SGEP_SCHED_INV 1
+#define SGEP_SCHED_WARMUP_HARMONIC 2
+
+typedef struct sgep_config {
+    int32_t kind;      /* SGEP_KIND_* */
+    int32_t dtype;     /* SGEP_F64 or SGEP_F32 */
+    int32_t k;         /* number of players, 1 <= k <= 64 (F64: k <= 32) */
+    int32_t optimizer; /* SGEP_SGD or SGEP_ADAM */
+    int32_t schedule;  /* SGEP_SCHED_* */
+    int32_t n_classes; /* LDA only; 0 otherwise */
+    int64_t dx;        /* CCA: width of view x. GENERAL: d */
+    int64_t dy;        /* CCA: width of view y. GENERAL: must equal dx */
+    int64_t b_max;     /* largest minibatch that sgep_step will receive */
+    double eta0, eta_T, t0, t_c, T; /* schedule parameters (see above) */
+    double gamma;      /* rate gamma_t (constant) of the auxiliary [Bv] update
+                        * and of the Rayleigh-quotient running means, 0 < gamma <= 1 */
+    double rho;        /* clip: <v_j, [Bv]_j> is replaced by max(., rho), rho >= 0 */
+    double eps_reg;    /* GENERAL: ridge, B = E[x x^T] + eps_reg I; CCA: must be 0 */
+    double adam_b1, adam_b2, adam_eps;
+    uint64_t seed;     /* reserved (initial players are always supplied) */
+} sgep_config;
+
+typedef struct sgep_handle_s sgep_handle;
+
+/* Create a solver (Alg. 2 initialisation).
+ *   out        : receives the handle
+ *   cfg        : copied; validated synchronously
+ *   V0         : host, d x k column-major, the players' starting points; each
+ *                column is normalised to the unit sphere on the device and the
+ *                auxiliary variable starts at [Bv]_i = v_i.  Must be non-NULL
+ *                with non-zero columns.
+ *   hip_stream : hipStream_t on which all device work of this handle runs
+ *                (NULL = the null stream); must belong to the current device
+ * Device memory owned by the handle: V, [Bv] (d x k each), the Adam moments
+ * (2 d x k, Adam only), the projections of one minibatch (2 b_max x k),
+ * k x k coefficient blocks and reduction workspaces.  Errors: SGEP_EINVAL,
+ * SGEP_ESHAPE, SGEP_EUNSUPPORTED, SGEP_ENOMEM, SGEP_EDEVICE. */
+sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V0,
+                      void *hip_stream);
+
+/* Enqueue one iteration of Alg. 2 on the minibatch (X, Y) of b rows.
+ *   X   : device, b x dx row-major (element type cfg.dtype), leading dim ldx
+ *   Y   : device, b x dy row-major, leading dim ldy
+ *   1 <= b <= b_max.  X and Y must be 16-byte aligned and ldx, ldy multiples
+ *   of 16 bytes / element size (2 for F64, 4 for F32), ldx >= dx, ldy >= dy.
+ * Per iteration, with v_i the current unit players, [Bv]_i the auxiliary
+ * variable, A_t and B_t the minibatch estimates:
+ *   s_j  = max(<v_j, [Bv]_j>, rho)                                 (Alg. 2)
+ *   grad_i = (v_i'B_t v_i) A_t v_i - (v_i'A_t v_i) B_t v_i
+ *          - sum_{j<i} (v_i'A_t v_j / s_j) [ (v_i'B_t v_i)[Bv]_j - (v_i'[Bv]_j) B_t v_i ]
+ *   v_i  <- (v_i + eta_t grad_i) / ||.||  (or Adam on grad_i, then normalise)
+ *   [Bv]_i <- [Bv]_i + gamma (B_t v_i - [Bv]_i)
+ * Returns synchronously only argument errors; SGEP_EPOISONED if poisoned. */
+sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y, int64_t ldy,
+                      int64_t b);
+
+/* sgep_step with timing marks for measurement: records the caller's
+ * hipEvent_t events[0] before the forward-product kernel, events[1] between
+ * it and the backward-product/update kernel, and events[2] after it, all on
+ * the handle's stream (create them with timing enabled).  Same semantics and
+ * errors as sgep_step, plus SGEP_EINVAL if an event is NULL. */
+sgep_status sgep_step_profiled(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
+                               int64_t ldy, int64_t b, void *const *events);
+
+/* Wait for the handle's stream and report any latched device fault. */
+sgep_status sgep_sync(sgep_handle *h);
+
+/* Eigenvalue estimates lambda_i = abar_i / bbar_i, the ratio of running means
+ * (rate gamma) of v_i'A_t v_i and v_i'B_t v_i (Rayleigh quotient, Sec. 2).
+ * out: host, k doubles.  Synchronises. */
+sgep_status sgep_eigvals(sgep_handle *h, double *out);
+
+/* Current players.  b_normalized = 0: the unit vectors v_i (Alg. 2 output);
+ * 1: v_i / sqrt(s_i), the estimate of the B-normalised eigenvector.
+ * out: host, d x k column-major doubles.  Synchronises. */
+sgep_status sgep_vectors(sgep_handle *h, int32_t b_normalized, double *out);
+
+/* The auxiliary variable [Bv] (host, d x k column-major).  Synchronises. */
+sgep_status sgep_auxiliary(sgep_handle *h, double *out);
+
+/* Number of completed iterations.  Synchronises. */
+sgep_status sgep_step_count(sgep_handle *h, int64_t *t);
+
+/* Checkpoint / resume: size in bytes of the opaque state blob, copy it out
+ * (synchronises), and restore it (clears a poisoned status).  The blob holds
+ * the iterate, the auxiliary variable, the Adam moments, the running means,
+ * the step counter and a hash of the configuration, which must match. */
+sgep_status sgep_state_size(const sgep_handle *h, size_t *bytes);
+sgep_status sgep_get_state(sgep_handle *h, void *host_buf, size_t bytes);
+sgep_status sgep_set_state(sgep_handle *h, const void *host_buf, size_t bytes);
+
+/* Release every resource of the handle (synchronises its stream first). */
+sgep_status sgep_destroy(sgep_handle *h);
+
+/* Static description of a status code. */
+const char *sgep_status_string(sgep_status s);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int32_t sgep_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SGEP_H */

@@ -66,6 +66,8 @@ def _load():
         lib.oracle_gamma_step_dense.restype = ctypes.c_int
         lib.oracle_alg1_step.argtypes = [ctypes.c_int64, ctypes.c_int, D, D, D, ctypes.c_double, D]
         lib.oracle_alg1_step.restype = ctypes.c_int
+        lib.oracle_threads.argtypes = []
+        lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -131,6 +133,11 @@ def gep_topk(A: np.ndarray, B: np.ndarray, k: int, canon: bool = True):
     if rc != 0:
         raise RuntimeError(f"oracle_gep_topk failed ({rc})")
     return lam, Vc.T.copy()
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel regions use."""
+    return int(_load().oracle_threads())
 
 
 def eta(schedule: int, t: float, eta0: float, eta_T: float = 0.0, t0: float = 1.0,

@@ -620,3 +620,16 @@ int oracle_alg1_step(int64_t d, int k, const double *A, const double *B, double 
 
 /* Library self-description for the Python loader. */
 int oracle_abi_version(void) { return 1; }
+
+/* Threads an OpenMP region of this library uses (for the CPU baseline). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,274 @@
+"""Python binding of the MI355X streaming SGEP library (libsgep.so).
+
+Argument marshalling only: every function forwards to the C ABI of
+``include/sgep.h`` with the same name; all arithmetic of an iteration runs in
+the library's HIP kernels.  Device arrays are passed as ``torch`` tensors (or
+raw integer device addresses); host arrays of player vectors are numpy
+``(d, k)`` arrays whose column i is player i.
+
+The library must have been built (``python -m paper_2206_04993_amd.build``);
+importing the binding without it raises ``ImportError`` -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsgep.so")
+
+SGEP_OK = 0
+SGEP_EINVAL = -1
+SGEP_ESHAPE = -2
+SGEP_ENOMEM = -3
+SGEP_EDEVICE = -4
+SGEP_ENONFINITE = -5
+SGEP_EUNSUPPORTED = -6
+SGEP_EPOISONED = -7
+
+SGEP_KIND_CCA, SGEP_KIND_GENERAL, SGEP_KIND_LDA = 0, 1, 2
+SGEP_F64, SGEP_F32, SGEP_BF16, SGEP_FP8_E4M3 = 0, 1, 2, 3
+SGEP_SGD, SGEP_ADAM = 0, 1
+SGEP_SCHED_CONST, SGEP_SCHED_INV, SGEP_SCHED_WARMUP_HARMONIC = 0, 1, 2
+
+# every symbol include/sgep.h declares
+EXPORTS = (
+    "sgep_init", "sgep_step", "sgep_step_profiled", "sgep_sync", "sgep_eigvals", "sgep_vectors", "sgep_auxiliary",
+    "sgep_step_count", "sgep_state_size", "sgep_get_state", "sgep_set_state", "sgep_destroy",
+    "sgep_status_string", "sgep_version",
+)
+
+
+class sgep_config(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("k", ctypes.c_int32),
+        ("optimizer", ctypes.c_int32), ("schedule", ctypes.c_int32),
+        ("n_classes", ctypes.c_int32),
+        ("dx", ctypes.c_int64), ("dy", ctypes.c_int64), ("b_max", ctypes.c_int64),
+        ("eta0", ctypes.c_double), ("eta_T", ctypes.c_double), ("t0", ctypes.c_double),
+        ("t_c", ctypes.c_double), ("T", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("rho", ctypes.c_double), ("eps_reg", ctypes.c_double),
+        ("adam_b1", ctypes.c_double), ("adam_b2", ctypes.c_double),
+        ("adam_eps", ctypes.c_double), ("seed", ctypes.c_uint64),
+    ]
+
+
+def make_config(kind: int, dtype: int, k: int, dx: int, dy: int, b_max: int, *,
+                optimizer: int = SGEP_SGD, schedule: int = SGEP_SCHED_CONST,
+                eta0: float = 0.1, eta_T: float = 0.0, t0: float = 1.0, t_c: float = 1.0,
+                T: float = 1.0, gamma: float = 1.0, rho: float = 1e-6, eps_reg: float = 0.0,
+                adam_b1: float = 0.9, adam_b2: float = 0.999, adam_eps: float = 1e-8,
+                n_classes: int = 0, seed: int = 0) -> sgep_config:
+    return sgep_config(kind, dtype, k, optimizer, schedule, n_classes, dx, dy, b_max, eta0,
+                       eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps, seed)
+
+
+class SgepError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {sgep_status_string(status)} ({status})")
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libsgep.so (raises ImportError when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2206_04993_amd.build`")
+    # torch ships its own HIP runtime under the same soname as ROCm's
+    # (libamdhip64.so.7); loading torch first makes the library bind to that
+    # one runtime, so torch's streams, events and allocations are valid here.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    lib.sgep_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(sgep_config), dp, vp]
+    lib.sgep_step.argtypes = [vp, vp, i64, vp, i64, i64]
+    lib.sgep_step_profiled.argtypes = [vp, vp, i64, vp, i64, i64, ctypes.POINTER(vp)]
+    lib.sgep_sync.argtypes = [vp]
+    lib.sgep_eigvals.argtypes = [vp, dp]
+    lib.sgep_vectors.argtypes = [vp, i32, dp]
+    lib.sgep_auxiliary.argtypes = [vp, dp]
+    lib.sgep_step_count.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.sgep_state_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.sgep_get_state.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.sgep_set_state.argtypes = [vp, vp, ctypes.c_size_t]
+    lib.sgep_destroy.argtypes = [vp]
+    lib.sgep_status_string.argtypes = [i32]
+    lib.sgep_status_string.restype = ctypes.c_char_p
+    lib.sgep_version.argtypes = []
+    for name in EXPORTS:
+        fn = getattr(lib, name)
+        if name not in ("sgep_status_string",):
+            fn.restype = i32
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != SGEP_OK:
+        raise SgepError(rc, where)
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return 0
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def sgep_status_string(status: int) -> str:
+    try:
+        return load().sgep_status_string(status).decode()
+    except ImportError:
+        return f"status {status}"
+
+
+def sgep_version() -> int:
+    return int(load().sgep_version())
+
+
+def sgep_init(cfg: sgep_config, V0: np.ndarray, stream=None) -> ctypes.c_void_p:
+    """Create a solver.  V0: (d, k) host array of starting points."""
+    lib = load()
+    V0c = np.ascontiguousarray(np.asarray(V0, dtype=np.float64).T)  # column-major d x k
+    h = ctypes.c_void_p()
+    rc = lib.sgep_init(ctypes.byref(h), ctypes.byref(cfg),
+                       V0c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _stream(stream))
+    _check(rc, "sgep_init")
+    return h
+
+
+def sgep_step(h, X, ldx: int, Y, ldy: int, b: int) -> None:
+    """Enqueue one iteration on the minibatch views X (b x dx) and Y (b x dy)."""
+    _check(load().sgep_step(h, _ptr(X), ldx, _ptr(Y), ldy, b), "sgep_step")
+
+
+def sgep_step_profiled(h, X, ldx: int, Y, ldy: int, b: int, events) -> None:
+    """sgep_step recording three caller-owned hipEvent_t handles (ints):
+    before the forward kernel, between the kernels, after the update kernel."""
+    ev = (ctypes.c_void_p * 3)(*[int(e) for e in events])
+    _check(load().sgep_step_profiled(h, _ptr(X), ldx, _ptr(Y), ldy, b, ev), "sgep_step_profiled")
+
+
+def sgep_sync(h) -> None:
+    _check(load().sgep_sync(h), "sgep_sync")
+
+
+def sgep_eigvals(h, k: int) -> np.ndarray:
+    out = np.zeros(k)
+    _check(load().sgep_eigvals(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "sgep_eigvals")
+    return out
+
+
+def sgep_vectors(h, d: int, k: int, b_normalized: int = 0) -> np.ndarray:
+    out = np.zeros((k, d))
+    _check(load().sgep_vectors(h, int(b_normalized),
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "sgep_vectors")
+    return out.T.copy()
+
+
+def sgep_auxiliary(h, d: int, k: int) -> np.ndarray:
+    out = np.zeros((k, d))
+    _check(load().sgep_auxiliary(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "sgep_auxiliary")
+    return out.T.copy()
+
+
+def sgep_step_count(h) -> int:
+    t = ctypes.c_int64()
+    _check(load().sgep_step_count(h, ctypes.byref(t)), "sgep_step_count")
+    return int(t.value)
+
+
+def sgep_state_size(h) -> int:
+    n = ctypes.c_size_t()
+    _check(load().sgep_state_size(h, ctypes.byref(n)), "sgep_state_size")
+    return int(n.value)
+
+
+def sgep_get_state(h) -> bytes:
+    n = sgep_state_size(h)
+    buf = ctypes.create_string_buffer(n)
+    _check(load().sgep_get_state(h, buf, n), "sgep_get_state")
+    return buf.raw
+
+
+def sgep_set_state(h, blob: bytes) -> None:
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(load().sgep_set_state(h, buf, len(blob)), "sgep_set_state")
+
+
+def sgep_destroy(h) -> None:
+    _check(load().sgep_destroy(h), "sgep_destroy")
+
+
+class Solver:
+    """Owning convenience wrapper around one handle (same calls, fewer args)."""
+
+    def __init__(self, cfg: sgep_config, V0: np.ndarray, stream=None):
+        self.cfg = cfg
+        self.d = cfg.dx + cfg.dy if cfg.kind == SGEP_KIND_CCA else cfg.dx
+        self.k = cfg.k
+        self.h = sgep_init(cfg, V0, stream)
+
+    def step(self, X, Y, b: Optional[int] = None, ldx: Optional[int] = None,
+             ldy: Optional[int] = None):
+        b = X.shape[0] if b is None else b
+        ldx = X.stride(0) if ldx is None else ldx
+        ldy = Y.stride(0) if ldy is None else ldy
+        sgep_step(self.h, X, ldx, Y, ldy, b)
+
+    def sync(self):
+        sgep_sync(self.h)
+
+    def eigvals(self):
+        return sgep_eigvals(self.h, self.k)
+
+    def vectors(self, b_normalized: int = 0):
+        return sgep_vectors(self.h, self.d, self.k, b_normalized)
+
+    def auxiliary(self):
+        return sgep_auxiliary(self.h, self.d, self.k)
+
+    def step_count(self):
+        return sgep_step_count(self.h)
+
+    def get_state(self):
+        return sgep_get_state(self.h)
+
+    def set_state(self, blob):
+        sgep_set_state(self.h, blob)
+
+    def close(self):
+        if self.h is not None:
+            sgep_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,107 @@
+"""CPU checks of the C-ABI boundary: the library loads, exports every symbol
+include/sgep.h declares, the header compiles as C and C++, the ctypes config
+mirrors the C struct layout, and argument validation answers synchronously
+without touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sgep.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(sgep_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2206_04993_amd as sg
+    lib = sg.load()
+    names = _declared()
+    assert "sgep_init" in names and "sgep_step" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sg.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", sg.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sgep_[a-z_]+)\b", out))
+    assert set(names) <= exported
+
+
+def test_header_compiles_as_c_and_cpp_and_layout_matches(tmp_path):
+    import paper_2206_04993_amd as sg
+    prog = tmp_path / "lay.c"
+    fields = [f[0] for f in sg.sgep_config._fields_]
+    body = "\n".join(f'printf("%zu\\n", offsetof(sgep_config, {f}));' for f in fields)
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "sgep.h"\n'
+                    'int main(void){' + body + 'printf("%zu\\n", sizeof(sgep_config));return 0;}\n')
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER),
+                    str(prog), "-o", str(exe)], check=True)
+    vals = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    offs = [getattr(sg.sgep_config, f).offset for f in fields]
+    assert vals[:-1] == offs
+    assert vals[-1] == ctypes.sizeof(sg.sgep_config)
+    cpp = tmp_path / "h.cpp"
+    cpp.write_text('#include "sgep.h"\nint main(){ sgep_config c{}; (void)c; return 0; }\n')
+    subprocess.run(["g++", "-std=c++11", "-Wall", "-Werror", "-I", os.path.dirname(HEADER),
+                    "-c", str(cpp), "-o", str(tmp_path / "h.o")], check=True)
+
+
+def _init_status(cfg, V0=None):
+    import paper_2206_04993_amd as sg
+    lib = sg.load()
+    d = cfg.dx + cfg.dy if cfg.kind == sg.SGEP_KIND_CCA else cfg.dx
+    if V0 is None:
+        V0 = np.ones((cfg.k, max(d, 1)))
+    V0 = np.ascontiguousarray(V0, dtype=np.float64)
+    h = ctypes.c_void_p()
+    return lib.sgep_init(ctypes.byref(h), ctypes.byref(cfg),
+                         V0.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None)
+
+
+def test_config_validation_is_synchronous():
+    import paper_2206_04993_amd as sg
+    mk = sg.make_config
+    C, G = sg.SGEP_KIND_CCA, sg.SGEP_KIND_GENERAL
+    cases = [
+        (mk(C, sg.SGEP_F32, 0, 8, 8, 16), sg.SGEP_EINVAL),          # k = 0
+        (mk(C, sg.SGEP_F32, 65, 64, 64, 16), sg.SGEP_EUNSUPPORTED),  # k > 64
+        (mk(C, sg.SGEP_F64, 33, 64, 64, 16), sg.SGEP_EUNSUPPORTED),  # F64 k > 32
+        (mk(C, sg.SGEP_F32, 4, 0, 8, 16), sg.SGEP_ESHAPE),           # empty view
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 0), sg.SGEP_ESHAPE),            # b_max = 0
+        (mk(C, sg.SGEP_F32, 20, 8, 8, 16), sg.SGEP_ESHAPE),          # k > d
+        (mk(G, sg.SGEP_F32, 4, 8, 9, 16), sg.SGEP_ESHAPE),           # general needs dx == dy
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, gamma=0.0), sg.SGEP_EINVAL),
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, gamma=1.5), sg.SGEP_EINVAL),
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, rho=-1.0), sg.SGEP_EINVAL),
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, eps_reg=1e-3), sg.SGEP_EINVAL),  # ridge is GENERAL only
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, schedule=sg.SGEP_SCHED_INV, t0=0.0), sg.SGEP_EINVAL),
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, schedule=7), sg.SGEP_EINVAL),
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, optimizer=sg.SGEP_ADAM, adam_b1=1.0), sg.SGEP_EINVAL),
+        (mk(C, sg.SGEP_BF16, 4, 8, 8, 16), sg.SGEP_EUNSUPPORTED),
+        (mk(sg.SGEP_KIND_LDA, sg.SGEP_F32, 4, 8, 8, 16), sg.SGEP_EUNSUPPORTED),
+        (mk(9, sg.SGEP_F32, 4, 8, 8, 16), sg.SGEP_EINVAL),
+    ]
+    for cfg, want in cases:
+        assert _init_status(cfg) == want, (cfg.kind, cfg.dtype, cfg.k, want)
+
+
+def test_null_arguments_rejected():
+    import paper_2206_04993_amd as sg
+    lib = sg.load()
+    assert lib.sgep_init(None, None, None, None) == sg.SGEP_EINVAL
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 4, 8, 8, 16)
+    h = ctypes.c_void_p()
+    assert lib.sgep_init(ctypes.byref(h), ctypes.byref(cfg), None, None) == sg.SGEP_EINVAL
+    for fn in ("sgep_sync", "sgep_destroy"):
+        assert getattr(lib, fn)(None) == sg.SGEP_EINVAL
+    assert lib.sgep_step(None, None, 0, None, 0, 1) == sg.SGEP_EINVAL
+    assert sg.sgep_status_string(sg.SGEP_EPOISONED).startswith("handle poisoned")
+    assert sg.sgep_version() >= 100

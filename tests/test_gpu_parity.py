@@ -1,0 +1,353 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Both sides consume the same seeded minibatches (already rounded to the GPU's
+element type) and the same starting points.  Tolerances (see the design doc,
+"Parity tolerances"): FP64 runs agree to 1e-11 on unit players after 100
+iterations; FP32 runs agree to TOL32_1 after one iteration and TOL32_N after
+N iterations, which is the FP32 rounding of length-d and length-b dot
+products (unit round-off 6e-8 times sqrt-length growth, times the step-size
+amplification of the retraction) with a 10x margin."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32_1 = 2e-5
+TOL32_N = 3e-4
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _sg():
+    import paper_2206_04993_amd as sg
+    sg.load()
+    return sg
+
+
+def _dev(a, dtype):
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to(device="cuda", dtype=dtype).contiguous()
+
+
+def _round(a, np_dtype):
+    return np.asarray(a, dtype=np_dtype).astype(np.float64)
+
+
+def _hyper_to_oracle(cfg):
+    return dict(schedule=cfg.schedule, eta0=cfg.eta0, eta_T=cfg.eta_T, t0=cfg.t0, t_c=cfg.t_c,
+                T=cfg.T)
+
+
+def run_both(cfg, batches, V0, checkpoints, labels=None):
+    """Run the GPU solver and the oracle side by side; return lists of
+    (t, Vgpu, Voracle, Ggpu, Goracle, lam_gpu, lam_oracle)."""
+    torch = _torch()
+    sg = _sg()
+    tdt = torch.float64 if cfg.dtype == sg.SGEP_F64 else torch.float32
+    ndt = np.float64 if cfg.dtype == sg.SGEP_F64 else np.float32
+    kind = oracle.KIND_CCA if cfg.kind == sg.SGEP_KIND_CCA else oracle.KIND_GENERAL
+    pb = oracle.Problem(kind, cfg.k, cfg.dx, cfg.dy, eps_reg=cfg.eps_reg, rho=cfg.rho,
+                        optimizer=cfg.optimizer, adam_b1=cfg.adam_b1, adam_b2=cfg.adam_b2,
+                        adam_eps=cfg.adam_eps)
+    st = oracle.State.init(V0, adam=cfg.optimizer == sg.SGEP_ADAM)
+    solver = sg.Solver(cfg, V0)
+    out = []
+    sched = _hyper_to_oracle(cfg)
+    for t, (X, Y) in enumerate(batches, start=1):
+        Xr, Yr = _round(X, ndt), _round(Y, ndt)
+        Xd, Yd = _dev(Xr, tdt), _dev(Yr, tdt)
+        solver.step(Xd, Yd)
+        eta_t = oracle.eta(sched["schedule"], t, sched["eta0"], sched["eta_T"], sched["t0"],
+                           sched["t_c"], sched["T"])
+        oracle.gamma_step(pb, st, Xr, Yr, eta_t, cfg.gamma)
+        if t in checkpoints:
+            out.append((t, solver.vectors(), st.V.copy(), solver.auxiliary(), st.G.copy(),
+                        solver.eigvals(), st.eigvals()))
+    assert solver.step_count() == len(batches)
+    solver.close()
+    return out
+
+
+def _maxdiff(a, b):
+    return float(np.abs(a - b).max())
+
+
+def _cca_batches(gen, n, b):
+    return [gen.batch(t, b) for t in range(1, n + 1)]
+
+
+# --------------------------------------------------------------------------- #
+# FP64 (tiny CCA workload: d = 8 + 8, k = 4, b = 128, inverse-time schedule)   #
+# --------------------------------------------------------------------------- #
+
+def test_f64_tiny_cca_trajectory():
+    sg = _sg()
+    gen, pool = synth.tiny_cca_pool(0)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F64, 4, 8, 8, 128,
+                         schedule=sg.SGEP_SCHED_INV, eta0=1.0, t0=200.0, gamma=1.0, rho=1e-6)
+    batches = [pool.batch(t, 128) for t in range(1, 101)]
+    V0 = synth.initial_players(16, 4, 0)
+    res = run_both(cfg, batches, V0, {1, 10, 100})
+    for t, vg, vo, gg, go, lg, lo in res:
+        print(f"f64 t={t} dV={_maxdiff(vg, vo):.2e} dG={_maxdiff(gg, go):.2e} "
+              f"dlam={_maxdiff(lg, lo):.2e}")
+        assert _maxdiff(vg, vo) < TOL64
+        assert _maxdiff(gg, go) < TOL64 * max(1.0, np.abs(go).max())
+        assert _maxdiff(lg, lo) < 1e-9
+
+
+def test_f64_tiny_cca_reaches_target():
+    """2000 iterations on the GPU reach 1e-3 subspace error (the pool's exact
+    FP64 solution), as the oracle does."""
+    torch = _torch()
+    sg = _sg()
+    gen, pool = synth.tiny_cca_pool(0)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F64, 4, 8, 8, 128,
+                         schedule=sg.SGEP_SCHED_INV, eta0=1.0, t0=200.0, gamma=1.0, rho=1e-6)
+    pb = oracle.Problem(oracle.KIND_CCA, 4, 8, 8)
+    A, B = oracle.problem_matrices(pb, pool.X, pool.Y)
+    lam, Vs = oracle.gep_topk(A, B, 4)
+    Xp = _dev(pool.X, torch.float64)
+    Yp = _dev(pool.Y, torch.float64)
+    solver = sg.Solver(cfg, synth.initial_players(16, 4, 0))
+    for t in range(1, 2001):
+        idx = torch.from_numpy(pool.indices(t, 128)).cuda()
+        solver.step(Xp.index_select(0, idx).contiguous(), Yp.index_select(0, idx).contiguous())
+    err = oracle.subspace_error(solver.vectors(), Vs, B)
+    print("f64 tiny CCA err after 2000 steps", err)
+    assert err < 1e-3
+    solver.close()
+
+
+# --------------------------------------------------------------------------- #
+# FP32 CCA with ragged shapes (several tiles, tails in every dimension)       #
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("dx,dy,k,b", [
+    (100, 150, 16, 300),   # ragged features, full KP block, 3 row-splits
+    (37, 21, 13, 45),      # tails smaller than one tile, padded players
+    (64, 64, 20, 1000),    # KP = 32
+    (200, 120, 40, 256),   # KP = 64
+    (3, 5, 1, 1),          # single player, single row, views narrower than a vector
+])
+def test_f32_cca_parity(dx, dy, k, b):
+    sg = _sg()
+    rng = np.random.default_rng(dx * 1000 + dy)
+    gen = synth.CCAPlanted(dx, dy, np.linspace(0.9, 0.3, min(4, dx, dy)), sigma=0.3,
+                           seed=dx + dy)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, k, dx, dy, b,
+                         schedule=sg.SGEP_SCHED_INV, eta0=0.5, t0=50.0, gamma=0.5, rho=1e-6)
+    batches = _cca_batches(gen, 20, b)
+    V0 = rng.standard_normal((dx + dy, k))
+    res = run_both(cfg, batches, V0, {1, 20})
+    for t, vg, vo, gg, go, lg, lo in res:
+        dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
+        print(f"f32 cca {dx},{dy},k={k},b={b} t={t} dV={dv:.2e} dG={dg:.2e}")
+        tol = TOL32_1 if t == 1 else TOL32_N
+        assert dv < tol and dg < tol
+
+
+def test_f32_cca_adam_parity():
+    sg = _sg()
+    gen = synth.medium_cca(0)
+    gen_small = synth.CCAPlanted(96, 80, np.linspace(0.95, 0.2, 8), sigma=0.2, seed=3)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 8, 96, 80, 512,
+                         optimizer=sg.SGEP_ADAM, schedule=sg.SGEP_SCHED_WARMUP_HARMONIC,
+                         eta0=2e-3, eta_T=1e-4, t_c=5, T=100, gamma=0.3, rho=1e-6)
+    batches = _cca_batches(gen_small, 20, 512)
+    V0 = synth.initial_players(176, 8, 4)
+    res = run_both(cfg, batches, V0, {1, 20})
+    for t, vg, vo, gg, go, lg, lo in res:
+        dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
+        print(f"f32 cca adam t={t} dV={dv:.2e} dG={dg:.2e}")
+        # Adam divides by sqrt(second moment): near-zero moments amplify rounding
+        tol = 5 * (TOL32_1 if t == 1 else TOL32_N)
+        assert dv < tol and dg < tol
+    del gen
+
+
+@pytest.mark.parametrize("d,k,b", [(100, 8, 200), (64, 16, 64)])
+def test_f32_general_parity(d, k, b):
+    sg = _sg()
+    gen = synth.GeneralPlanted(d, k=min(k, 8), seed=d)
+    cfg = sg.make_config(sg.SGEP_KIND_GENERAL, sg.SGEP_F32, k, d, d, b,
+                         schedule=sg.SGEP_SCHED_INV, eta0=0.05, t0=50.0, gamma=0.5, rho=1e-4,
+                         eps_reg=1e-3)
+    batches = [gen.batch(t, b) for t in range(1, 21)]
+    V0 = synth.initial_players(d, k, 7)
+    res = run_both(cfg, batches, V0, {1, 20})
+    for t, vg, vo, gg, go, lg, lo in res:
+        dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
+        print(f"f32 general d={d} k={k} t={t} dV={dv:.2e} dG={dg:.2e}")
+        tol = TOL32_1 if t == 1 else TOL32_N
+        assert dv < tol and dg < tol
+
+
+def test_f64_general_kp32_parity():
+    sg = _sg()
+    gen = synth.GeneralPlanted(80, k=8, seed=1)
+    cfg = sg.make_config(sg.SGEP_KIND_GENERAL, sg.SGEP_F64, 24, 80, 80, 100,
+                         schedule=sg.SGEP_SCHED_CONST, eta0=0.02, gamma=0.3, rho=1e-4,
+                         eps_reg=1e-3)
+    batches = [gen.batch(t, 100) for t in range(1, 31)]
+    res = run_both(cfg, batches, synth.initial_players(80, 24, 2), {30})
+    for t, vg, vo, gg, go, lg, lo in res:
+        print(f"f64 general kp32 t={t} dV={_maxdiff(vg, vo):.2e}")
+        assert _maxdiff(vg, vo) < TOL64
+        assert _maxdiff(gg, go) < TOL64 * max(1.0, np.abs(go).max())
+
+
+# --------------------------------------------------------------------------- #
+# Full-size medium CCA (d = 512 + 512, k = 16, b = 1024) in the benchmark's   #
+# launch configuration                                                          #
+# --------------------------------------------------------------------------- #
+
+def test_f32_medium_cca_full_size():
+    sg = _sg()
+    gen = synth.medium_cca(0)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 16, 512, 512, 1024,
+                         optimizer=sg.SGEP_ADAM, schedule=sg.SGEP_SCHED_INV, eta0=2e-3,
+                         t0=3000.0, gamma=0.3, rho=1e-6)
+    batches = _cca_batches(gen, 5, 1024)
+    res = run_both(cfg, batches, synth.initial_players(1024, 16, 0), {1, 5})
+    for t, vg, vo, gg, go, lg, lo in res:
+        dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
+        print(f"f32 medium cca t={t} dV={dv:.2e} dG={dg:.2e} dlam={_maxdiff(lg, lo):.2e}")
+        tol = 5 * (TOL32_1 if t == 1 else TOL32_N)
+        assert dv < tol and dg < tol
+
+
+# --------------------------------------------------------------------------- #
+# Properties: determinism, checkpoint/resume, hipGraph replay, errors          #
+# --------------------------------------------------------------------------- #
+
+def _solver_run(cfg, batches, V0, solver=None):
+    torch = _torch()
+    sg = _sg()
+    s = solver or sg.Solver(cfg, V0)
+    for X, Y in batches:
+        s.step(_dev(X, torch.float32), _dev(Y, torch.float32))
+    return s
+
+
+def test_bitwise_determinism_and_resume():
+    sg = _sg()
+    gen = synth.CCAPlanted(130, 70, np.linspace(0.9, 0.3, 4), sigma=0.3, seed=9)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 16, 130, 70, 500,
+                         optimizer=sg.SGEP_ADAM, eta0=1e-3, gamma=0.3)
+    batches = _cca_batches(gen, 12, 500)
+    V0 = synth.initial_players(200, 16, 1)
+    a = _solver_run(cfg, batches, V0)
+    b = _solver_run(cfg, batches, V0)
+    assert np.array_equal(a.vectors(), b.vectors())
+    assert np.array_equal(a.auxiliary(), b.auxiliary())
+    # checkpoint after 6, resume in a fresh handle
+    c = _solver_run(cfg, batches[:6], V0)
+    blob = c.get_state()
+    d = sg.Solver(cfg, synth.initial_players(200, 16, 5))
+    d.set_state(blob)
+    assert d.step_count() == 6
+    _solver_run(cfg, batches[6:], V0, solver=d)
+    assert np.array_equal(a.vectors(), d.vectors())
+    assert np.array_equal(a.eigvals(), d.eigvals())
+    # a blob from another configuration is refused
+    cfg2 = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 16, 130, 70, 500,
+                          optimizer=sg.SGEP_ADAM, eta0=2e-3, gamma=0.3)
+    e = sg.Solver(cfg2, V0)
+    with pytest.raises(sg.SgepError):
+        e.set_state(blob)
+    for s in (a, b, c, d, e):
+        s.close()
+
+
+def test_hipgraph_replay_matches_eager():
+    torch = _torch()
+    sg = _sg()
+    gen = synth.CCAPlanted(96, 64, np.linspace(0.9, 0.3, 4), sigma=0.3, seed=4)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 8, 96, 64, 256, eta0=0.2, gamma=0.5)
+    R = 4
+    batches = _cca_batches(gen, R, 256)
+    V0 = synth.initial_players(160, 8, 3)
+    Xs = [_dev(X, torch.float32) for X, _ in batches]
+    Ys = [_dev(Y, torch.float32) for _, Y in batches]
+    eager = sg.Solver(cfg, V0)
+    stream = torch.cuda.Stream()
+    graphed = sg.Solver(cfg, V0, stream=stream)
+    g = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=stream):
+        for X, Y in zip(Xs, Ys):
+            graphed.step(X, Y)
+    for rep in range(3):
+        for X, Y in zip(Xs, Ys):
+            eager.step(X, Y)
+        eager.sync()
+        g.replay()
+        torch.cuda.synchronize()
+        assert graphed.step_count() == R * (rep + 1)
+        assert np.array_equal(eager.vectors(), graphed.vectors()), rep
+        assert np.array_equal(eager.auxiliary(), graphed.auxiliary()), rep
+    eager.close()
+    graphed.close()
+
+
+def test_step_argument_errors():
+    torch = _torch()
+    sg = _sg()
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 4, 10, 12, 64)
+    s = sg.Solver(cfg, np.ones((22, 4)) + np.eye(22, 4))
+    X = torch.zeros((64, 16), device="cuda")
+    Y = torch.zeros((64, 12), device="cuda")
+    with pytest.raises(sg.SgepError) as e:
+        sg.sgep_step(s.h, X, 16, Y, 12, 0)        # empty minibatch
+    assert e.value.status == sg.SGEP_ESHAPE
+    with pytest.raises(sg.SgepError) as e:
+        sg.sgep_step(s.h, X, 16, Y, 12, 65)       # above b_max
+    assert e.value.status == sg.SGEP_ESHAPE
+    with pytest.raises(sg.SgepError) as e:
+        sg.sgep_step(s.h, X, 10, Y, 13, 8)        # row pitch not 16-byte aligned
+    assert e.value.status == sg.SGEP_ESHAPE
+    with pytest.raises(sg.SgepError) as e:
+        sg.sgep_step(s.h, X, 8, Y, 12, 8)         # ldx < dx
+    assert e.value.status == sg.SGEP_ESHAPE
+    with pytest.raises(sg.SgepError) as e:
+        sg.sgep_step(s.h, int(X.data_ptr()) + 4, 16, Y, 12, 8)  # misaligned base
+    assert e.value.status == sg.SGEP_ESHAPE
+    assert s.step_count() == 0
+    s.close()
+    # a zero starting column is rejected at init
+    with pytest.raises(sg.SgepError) as e:
+        sg.Solver(cfg, np.zeros((22, 4)))
+    assert e.value.status == sg.SGEP_EINVAL
+
+
+def test_nonfinite_input_poisons_until_restore():
+    torch = _torch()
+    sg = _sg()
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 4, 32, 32, 64, eta0=0.1, gamma=0.5)
+    gen = synth.CCAPlanted(32, 32, np.linspace(0.9, 0.3, 4), sigma=0.3, seed=2)
+    s = _solver_run(cfg, _cca_batches(gen, 3, 64), synth.initial_players(64, 4, 0))
+    blob = s.get_state()
+    X, Y = gen.batch(99, 64)
+    X[5, 7] = np.nan
+    s.step(_dev(X, torch.float32), _dev(Y, torch.float32))
+    with pytest.raises(sg.SgepError) as e:
+        s.eigvals()
+    assert e.value.status == sg.SGEP_ENONFINITE
+    with pytest.raises(sg.SgepError) as e:
+        s.step(_dev(X, torch.float32), _dev(Y, torch.float32))
+    assert e.value.status == sg.SGEP_EPOISONED
+    s.set_state(blob)
+    assert s.step_count() == 3
+    assert np.all(np.isfinite(s.vectors()))
+    s.close()
