@@ -43,12 +43,12 @@ struct sgep_handle_s {
     hipStream_t stream = nullptr;
     int device = 0;
     void *V = nullptr, *G = nullptr, *Am = nullptr, *As = nullptr;
-    void *P = nullptr, *Q = nullptr, *ws = nullptr;
-    double *gram_part = nullptr, *stat_part = nullptr, *readout = nullptr;
+    void *P = nullptr, *Q = nullptr;
+    double *gram_part = nullptr, *stat_part = nullptr, *stat_tot = nullptr, *readout = nullptr;
     Coef *coef = nullptr;
-    unsigned *cnt = nullptr;
-    int n_tx = 0, n_ty = 0, n_tiles = 0, max_splits = 1;
-    int64_t rows_per_split = 0;
+    int n_tx = 0, n_ty = 0, n_tiles = 0;
+    int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
+    int64_t W = 0;          // partial width: KP (KP + 1) / 2 + KP
     int64_t fwd_blocks_max = 0;
     bool poisoned = false;
 };
@@ -79,12 +79,16 @@ uint64_t config_hash(const sgep_config &c)
     return h;
 }
 
-template <typename T> constexpr int mb_for(int kp) { return (kp * (int)sizeof(T) <= 128) ? 4 : 2; }
+// feature-tile height of the backward pass: 16 features (MB = 1) keeps the
+// tile count up for small d; wide problems use MB = 4 (2 when the LDS tiles of
+// KP * sizeof(T) > 128 bytes per row would not fit) to cut the re-reads of P, Q
+template <typename T> constexpr int mb_wide(int kp) { return (kp * (int)sizeof(T) <= 128) ? 4 : 2; }
+constexpr int64_t kWideD = 8192;
 
 void free_all(sgep_handle *h)
 {
-    void *ptrs[] = {h->V, h->G, h->Am, h->As, h->P, h->Q, h->ws, h->gram_part, h->stat_part,
-                    h->readout, h->coef, h->cnt};
+    void *ptrs[] = {h->V, h->G, h->Am, h->As, h->P, h->Q, h->gram_part, h->stat_part,
+                    h->stat_tot, h->readout, h->coef};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -115,6 +119,9 @@ sgep_status check_cfg(const sgep_config *c)
     const int64_t d = c->kind == SGEP_KIND_CCA ? c->dx + c->dy : c->dx;
     if (c->k > d)
         return SGEP_ESHAPE;
+    // partial reductions are sized for at most 2^19 rows / features
+    if (c->b_max > (int64_t)1 << 19 || d > (int64_t)1 << 19)
+        return SGEP_EUNSUPPORTED;
     if (!(c->eta0 >= 0.0) || !(c->gamma > 0.0 && c->gamma <= 1.0) || !(c->rho >= 0.0))
         return SGEP_EINVAL;
     if (c->kind == SGEP_KIND_CCA && c->eps_reg != 0.0)
@@ -143,26 +150,17 @@ template <typename T, int KP>
 sgep_status launch_init(sgep_handle *h)
 {
     hipLaunchKernelGGL((sgep::k_init<T, KP>), dim3(1), dim3(sgep::kNT), 0, h->stream, (T *)h->V,
-                       (T *)h->G, h->d, h->cfg.k, h->cfg.rho, h->coef);
+                       (T *)h->G, h->d, h->cfg.k, h->stat_part, h->lds, h->coef);
     HIPCHK(hipGetLastError());
     return SGEP_OK;
 }
 
-template <typename T, int KP>
-sgep_status launch_step(sgep_handle *h, const StepArgs &a, int fwd_blocks, void *const *events)
+template <typename T, int KP, int MB>
+sgep_status launch_bwd(sgep_handle *h, const StepArgs &a)
 {
-    constexpr int MB = mb_for<T>(KP);
-    const dim3 gf(fwd_blocks), gb(h->n_tiles, a.splits), blk(sgep::kNT);
+    const dim3 gb(h->n_tiles), blk(sgep::kNT);
     const bool cca = h->cfg.kind == SGEP_KIND_CCA;
     const bool adam = h->cfg.optimizer == SGEP_ADAM;
-    if (events)
-        HIPCHK(hipEventRecord((hipEvent_t)events[0], h->stream));
-    if (cca)
-        hipLaunchKernelGGL((sgep::k_fwd<T, KP, sgep::kKindCCA>), gf, blk, 0, h->stream, a);
-    else
-        hipLaunchKernelGGL((sgep::k_fwd<T, KP, sgep::kKindGeneral>), gf, blk, 0, h->stream, a);
-    if (events)
-        HIPCHK(hipEventRecord((hipEvent_t)events[1], h->stream));
     if (cca && !adam)
         hipLaunchKernelGGL((sgep::k_bwd<T, KP, MB, sgep::kKindCCA, sgep::kOptSGD>), gb, blk, 0,
                            h->stream, a);
@@ -175,6 +173,25 @@ sgep_status launch_step(sgep_handle *h, const StepArgs &a, int fwd_blocks, void 
     else
         hipLaunchKernelGGL((sgep::k_bwd<T, KP, MB, sgep::kKindGeneral, sgep::kOptAdam>), gb, blk,
                            0, h->stream, a);
+    return SGEP_OK;
+}
+
+template <typename T, int KP>
+sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
+{
+    const dim3 gf(a.n_fwd + 1), blk(sgep::kNT); // + the norm-totals workgroup
+    if (events)
+        HIPCHK(hipEventRecord((hipEvent_t)events[0], h->stream));
+    if (h->cfg.kind == SGEP_KIND_CCA)
+        hipLaunchKernelGGL((sgep::k_fwd<T, KP, sgep::kKindCCA>), gf, blk, 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((sgep::k_fwd<T, KP, sgep::kKindGeneral>), gf, blk, 0, h->stream, a);
+    if (events)
+        HIPCHK(hipEventRecord((hipEvent_t)events[1], h->stream));
+    if (h->mb == 1)
+        launch_bwd<T, KP, 1>(h, a);
+    else
+        launch_bwd<T, KP, mb_wide<T>(KP)>(h, a);
     HIPCHK(hipGetLastError());
     if (events)
         HIPCHK(hipEventRecord((hipEvent_t)events[2], h->stream));
@@ -184,12 +201,9 @@ sgep_status launch_step(sgep_handle *h, const StepArgs &a, int fwd_blocks, void 
 template <typename T, int KP>
 sgep_status launch_readout(sgep_handle *h, const void *S, int mode)
 {
-    const int64_t n = h->d * h->cfg.k;
-    int blocks = (int)((n + sgep::kNT - 1) / sgep::kNT);
-    if (blocks > 1024)
-        blocks = 1024;
-    hipLaunchKernelGGL((sgep::k_readout<T, KP>), dim3(blocks), dim3(sgep::kNT), 0, h->stream,
-                       (const T *)S, h->d, h->cfg.k, h->coef, mode, h->readout);
+    hipLaunchKernelGGL((sgep::k_readout<T, KP>), dim3(1), dim3(sgep::kNT), 0, h->stream,
+                       (const T *)S, h->d, h->cfg.k, h->stat_part, h->n_tiles, h->lds, h->cfg.rho,
+                       h->coef, mode, h->readout);
     HIPCHK(hipGetLastError());
     return SGEP_OK;
 }
@@ -257,9 +271,10 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
     h->cfg = *cfg;
     h->stream = (hipStream_t)hip_stream;
     h->d = cfg->kind == SGEP_KIND_CCA ? cfg->dx + cfg->dy : cfg->dx;
-    h->kp = ((cfg->k + 15) / 16) * 16;
+    h->kp = cfg->k <= 16 ? 16 : (cfg->k <= 32 ? 32 : 64);
     h->esz = cfg->dtype == SGEP_F64 ? sizeof(double) : sizeof(float);
-    h->mb = cfg->dtype == SGEP_F64 ? mb_for<double>(h->kp) : mb_for<float>(h->kp);
+    const bool wide = h->d >= kWideD;
+    h->mb = !wide ? 1 : (cfg->dtype == SGEP_F64 ? mb_wide<double>(h->kp) : mb_wide<float>(h->kp));
     h->ft = 16 * h->mb;
     if (cfg->kind == SGEP_KIND_CCA) {
         h->n_tx = (int)((cfg->dx + h->ft - 1) / h->ft);
@@ -269,25 +284,16 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
         h->n_ty = 0;
     }
     h->n_tiles = h->n_tx + h->n_ty;
-    // rows per workgroup of the backward pass: aim at ~512 workgroups in
-    // total while keeping at least 64 rows per workgroup
-    const int64_t want = (512 + h->n_tiles - 1) / h->n_tiles;
-    const int64_t cap = (cfg->b_max + 63) / 64;
-    int64_t splits = want < cap ? want : cap;
-    if (splits < 1)
-        splits = 1;
-    int64_t rps = (cfg->b_max + splits - 1) / splits;
-    rps = ((rps + 15) / 16) * 16;
-    h->rows_per_split = rps;
-    h->max_splits = (int)((cfg->b_max + rps - 1) / rps);
     h->fwd_blocks_max = (cfg->b_max + 15) / 16;
+    h->ldg = (int)((h->fwd_blocks_max + 1) / 2 * 2);
+    h->lds = (h->n_tiles + 1) / 2 * 2;
+    h->W = (int64_t)h->kp * (h->kp + 1) / 2 + h->kp;
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return SGEP_EDEVICE;
     }
 
     const int64_t kp = h->kp, d = h->d;
-    const int64_t tri = kp * (kp + 1) / 2;
     const size_t st_bytes = (size_t)d * kp * h->esz;
     bool ok = true;
     auto alloc = [&](void **p, size_t n) {
@@ -304,13 +310,11 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
     }
     alloc(&h->P, (size_t)cfg->b_max * kp * h->esz);
     alloc(&h->Q, (size_t)cfg->b_max * kp * h->esz);
-    if (h->max_splits > 1)
-        alloc(&h->ws, (size_t)h->n_tiles * h->max_splits * 2 * h->ft * kp * h->esz);
-    alloc((void **)&h->gram_part, (size_t)h->fwd_blocks_max * (tri + kp) * sizeof(double));
-    alloc((void **)&h->stat_part, (size_t)h->n_tiles * (tri + kp) * sizeof(double));
+    alloc((void **)&h->gram_part, (size_t)h->W * h->ldg * sizeof(double));
+    alloc((void **)&h->stat_part, (size_t)h->W * h->lds * sizeof(double));
+    alloc((void **)&h->stat_tot, (size_t)h->W * sizeof(double));
     alloc((void **)&h->readout, (size_t)d * cfg->k * sizeof(double));
     alloc((void **)&h->coef, sizeof(Coef));
-    alloc((void **)&h->cnt, (size_t)(2 + h->n_tiles) * sizeof(unsigned));
     if (!ok) {
         free_all(h);
         delete h;
@@ -318,8 +322,10 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
     }
     // zero state, then upload the raw starting points (padding columns zero)
     bool hok = hipMemsetAsync(h->coef, 0, sizeof(Coef), h->stream) == hipSuccess &&
-               hipMemsetAsync(h->cnt, 0, (2 + h->n_tiles) * sizeof(unsigned), h->stream) ==
-                   hipSuccess;
+               hipMemsetAsync(h->stat_part, 0, (size_t)h->W * h->lds * sizeof(double),
+                              h->stream) == hipSuccess &&
+               hipMemsetAsync(h->gram_part, 0, (size_t)h->W * h->ldg * sizeof(double),
+                              h->stream) == hipSuccess;
     if (h->Am)
         hok = hok && hipMemsetAsync(h->Am, 0, st_bytes, h->stream) == hipSuccess &&
               hipMemsetAsync(h->As, 0, st_bytes, h->stream) == hipSuccess;
@@ -362,10 +368,14 @@ static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const v
         return SGEP_EINVAL;
     if (b < 1 || b > h->cfg.b_max)
         return SGEP_ESHAPE;
-    const int64_t vec = 16 / (int64_t)h->esz;
-    if (ldx < h->cfg.dx || ldy < h->cfg.dy || ldx % vec || ldy % vec ||
-        ((uintptr_t)X & 15u) || ((uintptr_t)Y & 15u))
+    if (ldx < h->cfg.dx || ldy < h->cfg.dy)
         return SGEP_ESHAPE;
+    const int64_t vec = 16 / (int64_t)h->esz;
+    const bool vec_ok = ldx % vec == 0 && ldy % vec == 0 && ((uintptr_t)X & 15u) == 0 &&
+                        ((uintptr_t)Y & 15u) == 0 && ((uintptr_t)X % h->esz) == 0 &&
+                        ((uintptr_t)Y % h->esz) == 0;
+    if (((uintptr_t)X % h->esz) != 0 || ((uintptr_t)Y % h->esz) != 0)
+        return SGEP_ESHAPE; // not even element-aligned
     StepArgs a;
     memset(&a, 0, sizeof(a));
     a.X = X;
@@ -378,19 +388,20 @@ static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const v
     a.k = h->cfg.k;
     a.n_tx = h->n_tx;
     a.n_ty = h->n_ty;
-    a.rows_per_split = h->rows_per_split;
-    a.splits = (int32_t)((b + h->rows_per_split - 1) / h->rows_per_split);
+    a.vec_ok = vec_ok ? 1 : 0;
+    a.n_fwd = (int32_t)((b + 15) / 16);
+    a.ldg = h->ldg;
+    a.lds = h->lds;
     a.V = h->V;
     a.G = h->G;
     a.Am = h->Am;
     a.As = h->As;
     a.P = h->P;
     a.Q = h->Q;
-    a.ws = h->ws;
     a.gram_part = h->gram_part;
     a.stat_part = h->stat_part;
+    a.stat_tot = h->stat_tot;
     a.coef = h->coef;
-    a.cnt = h->cnt;
     a.schedule = h->cfg.schedule;
     a.eta0 = h->cfg.eta0;
     a.eta_T = h->cfg.eta_T;
@@ -403,8 +414,7 @@ static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const v
     a.adam_b1 = h->cfg.adam_b1;
     a.adam_b2 = h->cfg.adam_b2;
     a.adam_eps = h->cfg.adam_eps;
-    const int fwd_blocks = (int)((b + 15) / 16);
-    return SGEP_DISPATCH(h, launch_step, h, a, fwd_blocks, events);
+    return SGEP_DISPATCH(h, launch_step, h, a, events);
 }
 
 sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y, int64_t ldy,
@@ -497,7 +507,8 @@ sgep_status sgep_state_size(const sgep_handle *h, size_t *bytes)
     if (!h || !bytes)
         return SGEP_EINVAL;
     const size_t st = (size_t)h->d * h->kp * h->esz;
-    *bytes = sizeof(StateHeader) + sizeof(Coef) + st * (h->Am ? 4 : 2);
+    *bytes = sizeof(StateHeader) + sizeof(Coef) + st * (h->Am ? 4 : 2) +
+             (size_t)h->W * h->lds * sizeof(double);
     return SGEP_OK;
 }
 
@@ -529,6 +540,8 @@ sgep_status sgep_get_state(sgep_handle *h, void *host_buf, size_t bytes)
         HIPCHK(hipMemcpyAsync(p, a, st, hipMemcpyDeviceToHost, h->stream));
         p += st;
     }
+    HIPCHK(hipMemcpyAsync(p, h->stat_part, (size_t)h->W * h->lds * sizeof(double),
+                          hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return SGEP_OK;
 }
@@ -560,7 +573,8 @@ sgep_status sgep_set_state(sgep_handle *h, const void *host_buf, size_t bytes)
         HIPCHK(hipMemcpyAsync(a, p, st, hipMemcpyHostToDevice, h->stream));
         p += st;
     }
-    HIPCHK(hipMemsetAsync(h->cnt, 0, (2 + h->n_tiles) * sizeof(unsigned), h->stream));
+    HIPCHK(hipMemcpyAsync(h->stat_part, p, (size_t)h->W * h->lds * sizeof(double),
+                          hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     int st_word = 0;
     memcpy(&st_word, (const unsigned char *)host_buf + sizeof(hd) + offsetof(Coef, status),

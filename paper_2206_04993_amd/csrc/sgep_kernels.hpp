@@ -1,34 +1,35 @@
 // sgep_kernels.hpp -- CDNA4 (gfx950) kernels of the stochastic gamma-EigenGame
 // step (Alg. 2 of Gemp, Chen, McWilliams, ICLR 2023, with M = 1).
 //
-// One iteration is two launches:
-//   k_fwd  P = X V, Q = Y V (tall-skinny products on MFMA), then per-workgroup
-//          partial k x k Grams; the last workgroup to finish reduces them in a
-//          fixed order and forms every k x k coefficient of the update
-//          (the Rayleigh terms of the rewards and the triangular penalty
-//          weights), the step sizes and the running means.
-//   k_bwd  A_t V and B_t V for a tile of features (X^T [Q|P] on MFMA, X tiles
-//          streamed straight from HBM, rows split over waves and optionally
-//          over workgroups), then a fused epilogue: the update direction in
-//          matrix form, the retraction step (SGD or Adam), the auxiliary
-//          update, and per-tile partials of ||v_i||^2 and v_i^T [Bv]_j; the
-//          last tile reduces those (fixed order) into the normalisation and
-//          the parent terms the next iteration needs.
+// One iteration is two launches and no cross-workgroup synchronisation inside
+// either of them (the kernel boundary is the only barrier):
+//   k_fwd  P = X V and Q = Y V for a 16-row tile (tall-skinny products on
+//          MFMA, features split over the four waves), stored unnormalised,
+//          plus the tile's partial k x k Gram terms (column-major partials).
+//          One extra workgroup reduces the previous iteration's norm /
+//          parent-term partials to totals and advances the step counter.
+//   k_bwd  for a tile of features: A_t V and B_t V (X^T [Q|P] on MFMA over
+//          all minibatch rows), then every workgroup reduces -- in the same
+//          fixed order, so all obtain identical bits -- the Gram partials,
+//          forms the k x k coefficients, and runs the fused epilogue:
+//          update direction, retraction step (SGD or Adam), auxiliary update,
+//          and this tile's partials of ||v_i||^2 and v_i^T [Bv]_j.
 //
-// Matrix form of the update direction used here.  With the unit players v_i,
-// the auxiliary G_j = [Bv]_j, the minibatch Gram M_A = V^T A_t V and
-// m_B,i = v_i^T B_t v_i, s_j = max(v_j^T G_j, rho), C_ij = v_i^T G_j,
-// T_ij = (M_A)_ij / s_j for j < i and c_i = sum_{j<i} T_ij C_ij, the
-// rewards-minus-penalties direction of Alg. 2 for all players at once is
+// Matrix form of the update direction.  With unit players v_i, auxiliary
+// G_j = [Bv]_j, minibatch Gram M_A = V^T A_t V, m_B,i = v_i^T B_t v_i,
+// s_j = max(v_j^T G_j, rho), C_ij = v_i^T G_j, T_ij = (M_A)_ij / s_j (j < i)
+// and c_i = sum_{j<i} T_ij C_ij, the rewards-minus-penalties direction of
+// Alg. 2 for all players at once is
 //     grad = (A_t V - G T^T) diag(m_B) - B_t V diag(m_A - c),
 // because v_i^T A_t y_j = (M_A)_ij / sqrt(s_j), [By]_j = G_j / sqrt(s_j) and
-// <v_i, [By]_j> = C_ij / sqrt(s_j).  The paper's per-player loop costs
-// O(b d k^2); sharing A_t V and B_t V across players makes it O(b d k + d k^2).
+// <v_i, [By]_j> = C_ij / sqrt(s_j).  Sharing A_t V and B_t V across players
+// turns the per-player O(b d k^2) of the paper's loop into O(b d k + d k^2).
 //
-// Storage: V, G and the Adam moments are d x KP row-major (KP = k rounded up
-// to a multiple of 16, padding columns held at zero) so that one MFMA B
-// operand row and one accumulator column are contiguous.  The stored V is the
-// iterate before normalisation; inv_nrm (in the coefficient block) rescales it.
+// Normalisation is lazy: the stored V is the iterate before it is projected
+// back to the sphere, and 1/||V_i|| (from the norm partials) scales every use.
+// Storage: V, G and the Adam moments are d x KP row-major (KP = 16, 32 or 64,
+// padding columns held at zero), so one MFMA B-operand row and one
+// accumulator column are contiguous.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,13 +40,13 @@ namespace sgep {
 
 constexpr int kNT = 256;     // threads per workgroup: four wave64
 constexpr int kKPMax = 64;   // largest padded player count
+constexpr int kScr = 1024;   // LDS scratch (doubles) of the partial reductions
 
 constexpr int kKindCCA = 0;
 constexpr int kKindGeneral = 1;
 constexpr int kOptSGD = 0;
 constexpr int kOptAdam = 1;
 
-// status bits latched on the device
 constexpr int kStatusNonFinite = 1;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -53,10 +54,14 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-// 16x16x4 MFMA for one element type.  Operand layout (wave64):
+// 16x16x4 MFMA for one element type.  Operand layout (wave64), identical for
+// FP32 and FP64:
 //   A (16 x 4):  lane l holds A[l % 16][l / 16]
 //   B (4 x 16):  lane l holds B[l / 16][l % 16]
-//   D (16 x 16): lane l holds D[4 (l / 16) + r][l % 16], r = 0..3
+// The result layout differs (measured on gfx950):
+//   FP32 D (16 x 16): lane l, register r holds D[4 (l / 16) + r][l % 16]
+//   FP64 D (16 x 16): lane l, register r holds D[(l / 16) + 4 r][l % 16]
+// drow(l / 16, r) gives the row of D held in register r.
 template <typename T> struct Mfma;
 template <> struct Mfma<float> {
     typedef f32x4 acc;
@@ -64,6 +69,7 @@ template <> struct Mfma<float> {
     {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int drow(int kk, int r) { return 4 * kk + r; }
 };
 template <> struct Mfma<double> {
     typedef f64x4 acc;
@@ -71,26 +77,22 @@ template <> struct Mfma<double> {
     {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int drow(int kk, int r) { return kk + 4 * r; }
 };
 
-// Coefficient block shared by the two kernels (device memory, FP64).
-// Matrices use row stride KP of the handle.
+// Public per-handle block (device memory, FP64): step counter, the
+// coefficients of the latest iteration, running means and the status word.
 struct Coef {
-    double mA[kKPMax];      // v_i^T A_t v_i (this iteration)
-    double mB[kKPMax];      // v_i^T B_t v_i
-    double c[kKPMax];       // sum_{j<i} T_ij C_ij
-    double T[kKPMax * kKPMax];  // (M_A)_ij / s_j, j < i
-    double C[kKPMax * kKPMax];  // v_i^T G_j, j <= i (for the next iteration)
-    double s[kKPMax];       // max(C_jj, rho)
-    double inv_nrm[kKPMax]; // 1 / ||stored V_i||
-    double ema_a[kKPMax];   // running mean of mA (rate gamma)
-    double ema_b[kKPMax];   // running mean of mB
-    double t;               // completed iterations
-    double eta, gamma;      // step sizes of the current iteration
-    double adam_c1, adam_c2; // 1 - b1^t, 1 - b2^t
-    int status;             // kStatus* bits
-    int clip_count;         // parents clipped at rho, cumulative
-    int pad[2];
+    double t;                // completed iterations (incremented by k_fwd)
+    double eta, gamma;       // step sizes of the latest iteration
+    double mA[kKPMax];       // v_i^T A_t v_i (latest iteration)
+    double mB[kKPMax];       // v_i^T B_t v_i
+    double c[kKPMax];        // sum_{j<i} T_ij C_ij
+    double s[kKPMax];        // max(v_j^T G_j, rho) used by the latest iteration
+    double ema_a[kKPMax];    // running mean of mA (rate gamma)
+    double ema_b[kKPMax];    // running mean of mB
+    int status;              // kStatus* bits
+    int clip_count;          // parents clipped at rho, cumulative
 };
 
 struct StepArgs {
@@ -98,15 +100,15 @@ struct StepArgs {
     int64_t ldx, ldy, b;
     int64_t dx, dy;          // CCA: view widths; GENERAL: dx = dy = d
     int32_t k, n_tx, n_ty;   // feature tiles over view x and view y (GENERAL: n_ty = 0)
-    int32_t splits;          // workgroups per feature tile along the rows
-    int64_t rows_per_split;
+    int32_t vec_ok;          // rows of X and Y 16-byte aligned: vector loads allowed
+    int32_t n_fwd;           // forward workgroups of this iteration
+    int32_t ldg, lds;        // leading dimensions of the Gram / stats partials
     void *V, *G, *Am, *As;   // d x KP state
-    void *P, *Q;             // b x KP projections (normalised players)
-    void *ws;                // split partials: tiles x splits x 2 x FT x KP
-    double *gram_part;       // fwd workgroups x (KP(KP+1)/2 + KP)
-    double *stat_part;       // tiles x (KP(KP+1)/2 + KP)
+    void *P, *Q;             // b x KP raw projections X V, Y V
+    double *gram_part;       // [W][ldg]: column blk = forward workgroup blk
+    double *stat_part;       // [W][lds]: column tile = backward workgroup tile
+    double *stat_tot;        // [W]: reduced stat_part of the state entering this iteration
     Coef *coef;
-    unsigned *cnt;           // [0] fwd arrivals, [1] tile arrivals, [2 + tile] split arrivals
     int32_t schedule;
     double eta0, eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps;
 };
@@ -138,25 +140,58 @@ __device__ inline double eta_at(const StepArgs &a, double t)
     return a.eta0 * (a.t_c + D) / (t + D);
 }
 
-// Arrival counter for "last workgroup finishes the reduction".  Every thread
-// releases its global writes at agent scope before the barrier; the last
-// arrival acquires before reading the other workgroups' partials.
-__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total, int *flag)
+// out[c] = sum_{r < n} part[c * ld + r] for c < W, by all threads of the
+// workgroup in a fixed order (rows in chunks of 32, chunks in order).
+// ld is even and part 16-byte aligned.  scr: kScr doubles of LDS.
+__device__ inline void colsum(const double *__restrict__ part, int n, int ld, int W,
+                              double *__restrict__ out, double *__restrict__ scr)
 {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = atomicAdd(counter, 1u);
-        *flag = (prev == total - 1u) ? 1 : 0;
+    constexpr int CH = 32;
+    const int nch = (n + CH - 1) / CH;
+    int per_pass = kScr / nch;
+    if (per_pass < 1)
+        per_pass = 1;
+    for (int c0 = 0; c0 < W; c0 += per_pass) {
+        const int cols = (W - c0 < per_pass) ? W - c0 : per_pass;
+        for (int p = threadIdx.x; p < cols * nch; p += kNT) {
+            const int cl = p / nch, q = p - cl * nch;
+            const double *src = part + (int64_t)(c0 + cl) * ld + q * CH;
+            const int m = (n - q * CH < CH) ? n - q * CH : CH;
+            double s = 0.0;
+            if (m == CH) {
+                f64x2 v[CH / 2];
+#pragma unroll
+                for (int u = 0; u < CH / 2; ++u)
+                    v[u] = *reinterpret_cast<const f64x2 *>(src + 2 * u);
+#pragma unroll
+                for (int u = 0; u < CH / 2; ++u) {
+                    s += v[u][0];
+                    s += v[u][1];
+                }
+            } else {
+                for (int r = 0; r < m; ++r)
+                    s += src[r];
+            }
+            scr[p] = s;
+        }
+        __syncthreads();
+        for (int cl = threadIdx.x; cl < cols; cl += kNT) {
+            double s = 0.0;
+            for (int q = 0; q < nch; ++q)
+                s += scr[cl * nch + q];
+            out[c0 + cl] = s;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    const bool last = *flag != 0;
-    if (last)
-        __threadfence();
-    return last;
 }
 
 template <typename T, int N> struct VecLoad;
+template <> struct VecLoad<float, 1> {
+    static __device__ __forceinline__ void run(const float *p, float *o) { o[0] = p[0]; }
+};
+template <> struct VecLoad<double, 1> {
+    static __device__ __forceinline__ void run(const double *p, double *o) { o[0] = p[0]; }
+};
 template <> struct VecLoad<float, 4> {
     static __device__ __forceinline__ void run(const float *p, float *o)
     {
@@ -187,14 +222,14 @@ template <> struct VecLoad<double, 4> {
     }
 };
 
-// N consecutive elements of row `row` starting at feature fs (masked beyond
-// nf and for invalid rows).  The vector path needs fs % N == 0 and a leading
-// dimension that keeps rows 16-byte aligned (checked by the host).
+// N consecutive elements of row `row` starting at feature fs, masked beyond
+// nf and for invalid rows.  The vector path needs vec_ok (16-byte aligned rows)
+// and fs % N == 0.
 template <typename T, int N>
 __device__ __forceinline__ void load_run(const T *__restrict__ X, int64_t ld, int64_t row, bool rv,
-                                         int64_t fs, int64_t nf, T *o)
+                                         int64_t fs, int64_t nf, bool vec_ok, T *o)
 {
-    if (rv && fs + N <= nf) {
+    if (rv && vec_ok && fs + N <= nf) {
         VecLoad<T, N>::run(X + row * ld + fs, o);
     } else {
 #pragma unroll
@@ -204,38 +239,50 @@ __device__ __forceinline__ void load_run(const T *__restrict__ X, int64_t ld, in
 }
 
 // ---------------------------------------------------------------------------
-// Forward products: partial P-tile (16 rows x KP) of one view for this wave.
-// The view's features are split in four contiguous ranges, one per wave.
-// Each lane loads VEC consecutive features of its row; MFMA j of a group
-// consumes element j, i.e. the k-index l/16 of the MFMA maps to feature
-// fb = chunk*4*VEC + VEC*(l/16) + j.  The same feature indexes the B operand
-// (row of V), so the sum over k is unchanged.
+// Forward products.  One wave accumulates the 16 x KP tile of one view over a
+// contiguous quarter of the features.  Each lane loads VEC consecutive
+// features of its row; MFMA j of a group consumes element j, i.e. the MFMA
+// k-index l/16 stands for feature c*4*VEC + VEC*(l/16) + j, and the B operand
+// (row of V) is taken at the same feature, so the sum is unchanged.  U groups
+// are loaded before their MFMAs are issued.
 // ---------------------------------------------------------------------------
 template <typename T, int KP>
 __device__ __forceinline__ void fwd_view(const T *__restrict__ X, int64_t ldx, int64_t nf, int64_t row,
-                                         bool rv, const T *__restrict__ V, int lane, int w,
-                                         typename Mfma<T>::acc *acc)
+                                         bool rv, bool vec_ok, const T *__restrict__ V, int lane,
+                                         int w, typename Mfma<T>::acc *acc)
 {
     constexpr int VEC = 16 / (int)sizeof(T);
     constexpr int CH = 4 * VEC;
     constexpr int NB = KP / 16;
+    constexpr int U = 8 / NB > 1 ? 8 / NB : 2;
     const int kk = lane >> 4, n = lane & 15;
     const int64_t nch = (nf + CH - 1) / CH;
     const int64_t c0 = (nch * w) >> 2, c1 = (nch * (w + 1)) >> 2;
-    for (int64_t c = c0; c < c1; ++c) {
-        const int64_t fb = c * CH + (int64_t)VEC * kk;
-        T xv[VEC];
-        load_run<T, VEC>(X, ldx, row, rv, fb, nf, xv);
+    for (int64_t cb = c0; cb < c1; cb += U) {
+        T xv[U][VEC];
+        T bv[U][VEC][NB];
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const int64_t fe = fb + j;
-            const bool fv = fe < nf;
+        for (int u = 0; u < U; ++u) {
+            const int64_t c = cb + u;
+            const bool cv = c < c1;
+            const int64_t fb = c * CH + (int64_t)VEC * kk;
+            load_run<T, VEC>(X, ldx, row, rv && cv, fb, nf, vec_ok, xv[u]);
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const T bv = fv ? V[fe * KP + nb * 16 + n] : T(0);
-                acc[nb] = Mfma<T>::fma(xv[j], bv, acc[nb]);
+            for (int j = 0; j < VEC; ++j) {
+                const int64_t fe = fb + j;
+                const bool fv = cv && fe < nf;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    bv[u][j][nb] = fv ? V[fe * KP + nb * 16 + n] : T(0);
             }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < VEC; ++j)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[nb] = Mfma<T>::fma(xv[u][j], bv[u][j][nb], acc[nb]);
     }
 }
 
@@ -248,16 +295,27 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
     constexpr int GW = TRI + KP;
     __shared__ T red[4][16][KP];
     __shared__ T pt[16][KP], qt[16][KP];
-    __shared__ int s_flag;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int kk = lane >> 4, n = lane & 15;
+    if ((int)blockIdx.x == a.n_fwd) {
+        // norm / parent-term totals of the current state (sum over the
+        // previous backward pass's tiles, fixed order); advance t
+        __shared__ double scr[kScr];
+        __shared__ double tot[GW];
+        colsum(a.stat_part, a.n_tx + a.n_ty, a.lds, GW, tot, scr);
+        for (int e = tid; e < GW; e += kNT)
+            a.stat_tot[e] = tot[e];
+        if (tid == 0)
+            a.coef->t += 1.0; // read by k_bwd only, after this kernel has finished
+        return;
+    }
     const int64_t r0 = (int64_t)blockIdx.x * 16;
     const int64_t row = r0 + n;
     const bool rv = row < a.b;
+    const bool vec_ok = a.vec_ok != 0;
     const T *X = (const T *)a.X, *Y = (const T *)a.Y, *V = (const T *)a.V;
     T *P = (T *)a.P, *Q = (T *)a.Q;
-    const Coef *cf = a.coef;
 
     Acc accP[NB], accQ[NB];
 #pragma unroll
@@ -265,23 +323,22 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
         accP[nb] = Acc{0, 0, 0, 0};
         accQ[nb] = Acc{0, 0, 0, 0};
     }
-    fwd_view<T, KP>(X, a.ldx, a.dx, row, rv, V, lane, w, accP);
+    fwd_view<T, KP>(X, a.ldx, a.dx, row, rv, vec_ok, V, lane, w, accP);
     if (KIND == kKindCCA)
-        fwd_view<T, KP>(Y, a.ldy, a.dy, row, rv, V + a.dx * KP, lane, w, accQ);
+        fwd_view<T, KP>(Y, a.ldy, a.dy, row, rv, vec_ok, V + a.dx * KP, lane, w, accQ);
     else
-        fwd_view<T, KP>(Y, a.ldy, a.dx, row, rv, V, lane, w, accQ);
+        fwd_view<T, KP>(Y, a.ldy, a.dx, row, rv, vec_ok, V, lane, w, accQ);
 
-    // sum the four waves' partial tiles (fixed order), normalise the columns
+    // sum the four waves' partial tiles in a fixed order
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            red[w][4 * kk + r][nb * 16 + n] = accP[nb][r];
+            red[w][Mfma<T>::drow(kk, r)][nb * 16 + n] = accP[nb][r];
     __syncthreads();
     for (int e = tid; e < 16 * KP; e += kNT) {
         const int r = e / KP, c = e % KP;
-        T s = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
-        s *= (T)cf->inv_nrm[c];
+        const T s = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
         pt[r][c] = s;
         if (r0 + r < a.b)
             P[(r0 + r) * KP + c] = s;
@@ -291,20 +348,19 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            red[w][4 * kk + r][nb * 16 + n] = accQ[nb][r];
+            red[w][Mfma<T>::drow(kk, r)][nb * 16 + n] = accQ[nb][r];
     __syncthreads();
     for (int e = tid; e < 16 * KP; e += kNT) {
         const int r = e / KP, c = e % KP;
-        T s = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
-        s *= (T)cf->inv_nrm[c];
+        const T s = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
         qt[r][c] = s;
         if (r0 + r < a.b)
             Q[(r0 + r) * KP + c] = s;
     }
     __syncthreads();
 
-    // partial Grams over these 16 rows: lower triangle of V^T A_t V (times b)
-    // and the diagonal of V^T B_t V (times b), accumulated in FP64
+    // partial Grams over these 16 rows (raw players, FP64): lower triangle of
+    // b V^T A_t V and the diagonal of b V^T B_t V (without the ridge)
     for (int e = tid; e < GW; e += kNT) {
         double s = 0.0;
         if (e < TRI) {
@@ -325,59 +381,7 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
                     s += (double)pt[r][i] * (double)pt[r][i];
             }
         }
-        a.gram_part[(int64_t)blockIdx.x * GW + e] = s;
-    }
-
-    if (!arrive_last(&a.cnt[0], gridDim.x, &s_flag))
-        return;
-
-    // ---- last workgroup: reduce the Grams and form the coefficients ----
-    __shared__ double gs[GW];
-    __shared__ double Ts[KP][KP];
-    for (int e = tid; e < GW; e += kNT) {
-        double s = 0.0;
-        for (unsigned blk = 0; blk < gridDim.x; ++blk)
-            s += a.gram_part[(int64_t)blk * GW + e];
-        gs[e] = s;
-    }
-    __syncthreads();
-    Coef *cw = a.coef;
-    const double ib = 1.0 / (double)a.b;
-    const double t = cw->t + 1.0;
-    for (int e = tid; e < KP * KP; e += kNT) {
-        const int i = e / KP, j = e % KP;
-        double v = 0.0;
-        if (i < a.k && j < i)
-            v = gs[tri_idx(i, j)] * ib / cw->s[j];
-        Ts[i][j] = v;
-        cw->T[e] = v;
-    }
-    __syncthreads();
-    if (tid < KP) {
-        const int i = tid;
-        double mA = 0.0, mB = 0.0, c = 0.0;
-        if (i < a.k) {
-            mA = gs[tri_idx(i, i)] * ib;
-            mB = gs[TRI + i] * ib + (KIND == kKindCCA ? 0.0 : a.eps_reg);
-            for (int j = 0; j < i; ++j)
-                c += Ts[i][j] * cw->C[i * KP + j];
-            cw->ema_a[i] += a.gamma * (mA - cw->ema_a[i]);
-            cw->ema_b[i] += a.gamma * (mB - cw->ema_b[i]);
-            if (!isfinite(mA) || !isfinite(mB) || !isfinite(c))
-                atomicOr(&cw->status, kStatusNonFinite);
-        }
-        cw->mA[i] = mA;
-        cw->mB[i] = mB;
-        cw->c[i] = c;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        cw->t = t;
-        cw->eta = eta_at(a, t);
-        cw->gamma = a.gamma;
-        cw->adam_c1 = 1.0 - pow(a.adam_b1, t);
-        cw->adam_c2 = 1.0 - pow(a.adam_b2, t);
-        atomicExch(&a.cnt[0], 0u);
+        a.gram_part[(int64_t)e * a.ldg + blockIdx.x] = s;
     }
 }
 
@@ -385,7 +389,8 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 // Backward products + fused update for a tile of FT = 16*MB features.
 // A operand = X^T: lane l loads MB consecutive features f0 + MB*(l%16) + j of
 // row r + l/16; element j feeds M-block j, so M-block j, M-row m holds feature
-// f0 + MB*m + j.  B operands: rows of Q and P (KP wide).
+// f0 + MB*m + j.  B operands: rows of Q and P (KP wide).  The four waves take
+// interleaved 4-row groups; U groups are loaded before their MFMAs.
 // ---------------------------------------------------------------------------
 template <typename T, int KP, int MB, int KIND, int OPT>
 __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
@@ -394,22 +399,26 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
     constexpr int NB = KP / 16;
     constexpr int FT = 16 * MB;
     constexpr int TRI = KP * (KP + 1) / 2;
-    constexpr int SW = TRI + KP;
+    constexpr int W = TRI + KP; // width of both partial kinds
+    constexpr int U = 16 / (MB * NB) > 2 ? 16 / (MB * NB) : 2;
+    constexpr int EPT = FT * KP / kNT; // epilogue elements per thread
+    static_assert(EPT * kNT == FT * KP, "tile must be a multiple of the workgroup");
     __shared__ T red[4][FT * KP];
-    __shared__ T avt[FT * KP], bvt[FT * KP], gt[FT * KP], vt[FT * KP];
+    __shared__ T avt[FT * KP], bvt[FT * KP], gt[FT * KP];
     __shared__ T Tl[KP * KP];
     __shared__ T cMB[KP], cMAc[KP], cInv[KP];
-    __shared__ int s_flag;
+    __shared__ double gs[W], ss[W], scr[kScr];
+    __shared__ double dInv[KP], dS[KP];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int kk = lane >> 4, m = lane & 15;
-    const int tile = blockIdx.x, split = blockIdx.y;
+    const int tile = blockIdx.x;
+    const bool vec_ok = a.vec_ok != 0;
     const T *X = (const T *)a.X, *Y = (const T *)a.Y;
     const T *P = (const T *)a.P, *Q = (const T *)a.Q;
 
-    // geometry of this tile
-    const T *Xa;      // view whose transpose multiplies the A-side operand
-    const T *Xb;      // view whose transpose multiplies the B-side operand
+    const T *Xa;      // view multiplying the A-side operand
+    const T *Xb;      // view multiplying the B-side operand
     int64_t lda, ldb, nf, fbase, f0;
     const T *opA, *opB;
     if (KIND == kKindCCA) {
@@ -427,6 +436,7 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
         opA = Q; opB = P;
     }
 
+    // ---- main loop: raw X^T Q and X^T P over all rows ----
     Acc accA[MB][NB], accB[MB][NB];
 #pragma unroll
     for (int j = 0; j < MB; ++j)
@@ -435,34 +445,32 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
             accA[j][nb] = Acc{0, 0, 0, 0};
             accB[j][nb] = Acc{0, 0, 0, 0};
         }
-    const int64_t rb = (int64_t)split * a.rows_per_split;
-    const int64_t re = (rb + a.rows_per_split < a.b) ? rb + a.rows_per_split : a.b;
     const int64_t fs = f0 + (int64_t)MB * m;
-    for (int64_t r = rb + 4 * w; r < re; r += 16) {
-        const int64_t row = r + kk;
-        const bool rv = row < re;
-        T xa[MB], xb[MB];
-        load_run<T, MB>(Xa, lda, row, rv, fs, nf, xa);
-        if (KIND == kKindCCA) {
+    for (int64_t rb = 4 * w; rb < a.b; rb += 16 * U) {
+        T xa[U][MB], xb[U][MB], ba[U][NB], bb[U][NB];
 #pragma unroll
-            for (int j = 0; j < MB; ++j)
-                xb[j] = xa[j];
-        } else {
-            load_run<T, MB>(Xb, ldb, row, rv, fs, nf, xb);
-        }
-        T ba[NB], bb[NB];
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            ba[nb] = rv ? opA[row * KP + nb * 16 + m] : T(0);
-            bb[nb] = rv ? opB[row * KP + nb * 16 + m] : T(0);
-        }
-#pragma unroll
-        for (int j = 0; j < MB; ++j)
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = rb + 16 * u + kk;
+            const bool rv = row < a.b;
+            load_run<T, MB>(Xa, lda, row, rv, fs, nf, vec_ok, xa[u]);
+            if (KIND != kKindCCA)
+                load_run<T, MB>(Xb, ldb, row, rv, fs, nf, vec_ok, xb[u]);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                accA[j][nb] = Mfma<T>::fma(xa[j], ba[nb], accA[j][nb]);
-                accB[j][nb] = Mfma<T>::fma(xb[j], bb[nb], accB[j][nb]);
+                ba[u][nb] = rv ? opA[row * KP + nb * 16 + m] : T(0);
+                bb[u][nb] = rv ? opB[row * KP + nb * 16 + m] : T(0);
             }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < MB; ++j)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    accA[j][nb] = Mfma<T>::fma(xa[u][j], ba[u][nb], accA[j][nb]);
+                    accB[j][nb] = Mfma<T>::fma(KIND == kKindCCA ? xa[u][j] : xb[u][j], bb[u][nb],
+                                               accB[j][nb]);
+                }
     }
 
     // cross-wave reduction (fixed order) into natural feature order
@@ -472,7 +480,7 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                red[w][(MB * (4 * kk + r) + j) * KP + nb * 16 + m] = accA[j][nb][r];
+                red[w][(MB * Mfma<T>::drow(kk, r) + j) * KP + nb * 16 + m] = accA[j][nb][r];
     __syncthreads();
     for (int e = tid; e < FT * KP; e += kNT)
         avt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
@@ -483,66 +491,110 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                red[w][(MB * (4 * kk + r) + j) * KP + nb * 16 + m] = accB[j][nb][r];
+                red[w][(MB * Mfma<T>::drow(kk, r) + j) * KP + nb * 16 + m] = accB[j][nb][r];
     __syncthreads();
     for (int e = tid; e < FT * KP; e += kNT)
         bvt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
-    __syncthreads();
 
-    if (a.splits > 1) {
-        T *ws = (T *)a.ws + ((int64_t)tile * a.splits + split) * (2 * FT * KP);
-        for (int e = tid; e < FT * KP; e += kNT) {
-            ws[e] = avt[e];
-            ws[FT * KP + e] = bvt[e];
-        }
-        if (!arrive_last(&a.cnt[2 + tile], (unsigned)a.splits, &s_flag))
-            return;
-        const T *base = (const T *)a.ws + (int64_t)tile * a.splits * (2 * FT * KP);
-        for (int e = tid; e < FT * KP; e += kNT) {
-            T sa = 0, sb = 0;
-            for (int s = 0; s < a.splits; ++s) {
-                sa += base[(int64_t)s * 2 * FT * KP + e];
-                sb += base[(int64_t)s * 2 * FT * KP + FT * KP + e];
-            }
-            avt[e] = sa;
-            bvt[e] = sb;
-        }
-        if (tid == 0)
-            atomicExch(&a.cnt[2 + tile], 0u);
-    }
-
-    // ---- fused epilogue ----
-    const Coef *cf = a.coef;
-    for (int e = tid; e < KP * KP; e += kNT)
-        Tl[e] = (T)cf->T[e];
-    if (tid < KP) {
-        cMB[tid] = (T)cf->mB[tid];
-        cMAc[tid] = (T)(cf->mA[tid] - cf->c[tid]);
-        cInv[tid] = (T)cf->inv_nrm[tid];
-    }
+    // ---- prefetch the epilogue operands of this thread's elements ----
     T *V = (T *)a.V, *G = (T *)a.G, *Am = (T *)a.Am, *As = (T *)a.As;
-    for (int e = tid; e < FT * KP; e += kNT) {
+    T pv[EPT], pm[EPT], ps[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * kNT;
         const int fl = e / KP, i = e % KP;
         const int64_t f = f0 + fl;
-        const bool valid = f < nf;
-        const int64_t gi = (fbase + f) * KP + i;
-        gt[e] = valid ? G[gi] : T(0);
-        vt[e] = valid ? V[gi] : T(0);
+        const bool ok = f < nf;
+        const int64_t gi = (fbase + (ok ? f : 0)) * KP + i;
+        gt[e] = ok ? G[gi] : T(0);
+        pv[q] = ok ? V[gi] : T(0);
+        if (OPT == kOptAdam) {
+            pm[q] = ok ? Am[gi] : T(0);
+            ps[q] = ok ? As[gi] : T(0);
+        }
+    }
+
+    // ---- k x k coefficients (identical in every workgroup) ----
+    Coef *cw = a.coef;
+    const double t = cw->t; // this iteration's number, set by k_fwd
+    for (int e = tid; e < W; e += kNT)
+        ss[e] = a.stat_tot[e];
+    colsum(a.gram_part, a.n_fwd, a.ldg, W, gs, scr);
+    const double ib = 1.0 / (double)a.b;
+    if (tid < KP) {
+        const int i = tid;
+        double inv = 0.0, s = 1.0;
+        if (i < a.k) {
+            inv = 1.0 / sqrt(ss[TRI + i]);
+            s = ss[tri_idx(i, i)] * inv; // v_i^T G_i with the unit v_i
+            if (!(s >= a.rho))
+                s = a.rho;
+        }
+        dInv[i] = inv;
+        dS[i] = s;
     }
     __syncthreads();
-    const T eta = (T)cf->eta, gam = (T)cf->gamma, ib = (T)(1.0 / (double)a.b);
+    // T_ij = (M_A)_ij / s_j with (M_A)_ij = b^{-1} inv_i inv_j (raw Gram)_ij
+    for (int e = tid; e < KP * KP; e += kNT) {
+        const int i = e / KP, j = e % KP;
+        double v = 0.0;
+        if (i < a.k && j < i)
+            v = gs[tri_idx(i, j)] * dInv[i] * dInv[j] * ib / dS[j];
+        Tl[e] = (T)v;
+    }
+    if (tid < KP) {
+        const int i = tid;
+        double mA = 0.0, mB = 0.0, c = 0.0;
+        if (i < a.k) {
+            const double ii2 = dInv[i] * dInv[i];
+            mA = gs[tri_idx(i, i)] * ii2 * ib;
+            mB = gs[TRI + i] * ii2 * ib + (KIND == kKindCCA ? 0.0 : a.eps_reg);
+            for (int j = 0; j < i; ++j) {
+                const double Tij = gs[tri_idx(i, j)] * dInv[i] * dInv[j] * ib / dS[j];
+                c += Tij * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
+            }
+        }
+        cMB[i] = (T)mB;
+        cMAc[i] = (T)(mA - c);
+        cInv[i] = (T)dInv[i];
+        if (blockIdx.x == 0) {
+            if (i < a.k) {
+                cw->ema_a[i] += a.gamma * (mA - cw->ema_a[i]);
+                cw->ema_b[i] += a.gamma * (mB - cw->ema_b[i]);
+                const double craw = ss[tri_idx(i, i)] * dInv[i];
+                if (!(craw >= a.rho))
+                    atomicAdd(&cw->clip_count, 1);
+                if (!isfinite(mA) || !isfinite(mB) || !isfinite(c) || !isfinite(dInv[i]) ||
+                    !(dInv[i] > 0.0) || !isfinite(craw))
+                    atomicOr(&cw->status, kStatusNonFinite);
+            }
+            cw->mA[i] = mA;
+            cw->mB[i] = mB;
+            cw->c[i] = c;
+            cw->s[i] = dS[i];
+            if (i == 0) {
+                cw->eta = eta_at(a, t);
+                cw->gamma = a.gamma;
+            }
+        }
+    }
+    // ---- fused epilogue ----
+    __syncthreads();
+    const T eta = (T)eta_at(a, t), gam = (T)a.gamma, ibT = (T)ib;
     const T eps = (T)a.eps_reg;
     const T b1 = (T)a.adam_b1, b2 = (T)a.adam_b2, aeps = (T)a.adam_eps;
-    const T c1 = (T)cf->adam_c1, c2 = (T)cf->adam_c2;
-    for (int e = tid; e < FT * KP; e += kNT) {
+    const T c1 = (T)(1.0 - pow(a.adam_b1, t)), c2 = (T)(1.0 - pow(a.adam_b2, t));
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * kNT;
         const int fl = e / KP, i = e % KP;
         const int64_t f = f0 + fl;
         T vn = 0, gn = 0;
         if (f < nf && i < a.k) {
             const int64_t gi = (fbase + f) * KP + i;
-            const T vh = vt[e] * cInv[i];
-            const T av = avt[e] * ib;
-            T bv = bvt[e] * ib;
+            const T vh = pv[q] * cInv[i];
+            const T av = avt[e] * cInv[i] * ibT;
+            T bv = bvt[e] * cInv[i] * ibT;
             if (KIND != kKindCCA)
                 bv += eps * vh;
             T pen = 0;
@@ -552,24 +604,24 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
             if (OPT == kOptSGD) {
                 vn = vh + eta * grad;
             } else {
-                const T mm = b1 * Am[gi] + (T(1) - b1) * grad;
-                const T ss = b2 * As[gi] + (T(1) - b2) * grad * grad;
+                const T mm = b1 * pm[q] + (T(1) - b1) * grad;
+                const T sq = b2 * ps[q] + (T(1) - b2) * grad * grad;
                 Am[gi] = mm;
-                As[gi] = ss;
-                vn = vh + eta * (mm / c1) / (sqrt(ss / c2) + aeps);
+                As[gi] = sq;
+                vn = vh + eta * (mm / c1) / (sqrt(sq / c2) + aeps);
             }
             const T g0 = gt[e];
             gn = g0 + gam * (bv - g0);
             V[gi] = vn;
             G[gi] = gn;
         }
-        avt[e] = vn; // own slot only: reused for the stats below
+        avt[e] = vn; // own slot: reused for the partials below
         bvt[e] = gn;
     }
     __syncthreads();
-
-    // per-tile partials of v_i^T G_j (j <= i) and ||v_i||^2 of the new state
-    for (int e = tid; e < SW; e += kNT) {
+    // this tile's partials of v_i^T G_j (j <= i) and ||v_i||^2 of the new state
+    double *sout = a.stat_part;
+    for (int e = tid; e < W; e += kNT) {
         double s = 0.0;
         if (e < TRI) {
             int i, j;
@@ -581,75 +633,24 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
             for (int fl = 0; fl < FT; ++fl)
                 s += (double)avt[fl * KP + i] * (double)avt[fl * KP + i];
         }
-        a.stat_part[(int64_t)tile * SW + e] = s;
+        sout[(int64_t)e * a.lds + tile] = s;
     }
-    const unsigned n_tiles = (unsigned)(a.n_tx + a.n_ty);
-    if (!arrive_last(&a.cnt[1], n_tiles, &s_flag))
-        return;
-
-    // ---- last tile: normalisation and parent terms for the next iteration ----
-    __shared__ double ssum[SW];
-    __shared__ double sinv[KP];
-    for (int e = tid; e < SW; e += kNT) {
-        double s = 0.0;
-        for (unsigned tl = 0; tl < n_tiles; ++tl)
-            s += a.stat_part[(int64_t)tl * SW + e];
-        ssum[e] = s;
-    }
-    __syncthreads();
-    Coef *cw = a.coef;
-    if (tid < KP) {
-        const int i = tid;
-        double inv = 0.0;
-        if (i < a.k) {
-            const double n2 = ssum[TRI + i];
-            inv = 1.0 / sqrt(n2);
-            if (!(n2 > 0.0) || !isfinite(inv))
-                atomicOr(&cw->status, kStatusNonFinite);
-        }
-        sinv[i] = inv;
-        cw->inv_nrm[i] = inv;
-    }
-    __syncthreads();
-    for (int e = tid; e < KP * KP; e += kNT) {
-        const int i = e / KP, j = e % KP;
-        double c = 0.0;
-        if (i < a.k && j <= i)
-            c = ssum[tri_idx(i, j)] * sinv[i];
-        cw->C[e] = c;
-    }
-    if (tid < KP) {
-        const int j = tid;
-        double s = 1.0;
-        if (j < a.k) {
-            const double cjj = ssum[tri_idx(j, j)] * sinv[j];
-            s = cjj;
-            if (!(cjj >= a.rho)) {
-                s = a.rho;
-                atomicAdd(&cw->clip_count, 1);
-            }
-            if (!isfinite(cjj))
-                atomicOr(&cw->status, kStatusNonFinite);
-        }
-        cw->s[j] = s;
-    }
-    if (tid == 0)
-        atomicExch(&a.cnt[1], 0u);
 }
 
 // ---------------------------------------------------------------------------
 // Initialisation (one workgroup; not on the hot path): normalise the supplied
-// players to the unit sphere, set [Bv]_i = v_i (Alg. 2), and form the
-// normalisation and parent terms of the first iteration.
+// players to the unit sphere, set [Bv]_i = v_i (Alg. 2), and write the norm /
+// parent-term sums of this state as column 0 of stats buffer 0 (the other
+// columns are zero).
 // ---------------------------------------------------------------------------
 template <typename T, int KP>
-__global__ void __launch_bounds__(kNT) k_init(T *V, T *G, int64_t d, int k, double rho, Coef *cw)
+__global__ void __launch_bounds__(kNT) k_init(T *V, T *G, int64_t d, int k, double *stat0, int lds,
+                                              Coef *cw)
 {
     constexpr int TRI = KP * (KP + 1) / 2;
     __shared__ double part[kNT];
     __shared__ double nrm[KP];
     const int tid = threadIdx.x;
-    // column norms of the raw players
     for (int i = 0; i < KP; ++i) {
         double s = 0.0;
         for (int64_t f = tid; f < d; f += kNT)
@@ -671,62 +672,59 @@ __global__ void __launch_bounds__(kNT) k_init(T *V, T *G, int64_t d, int k, doub
         G[e] = v;
     }
     __syncthreads();
-    // C = V^T G (= V^T V) lower triangle and the norms of the normalised V
-    for (int e = tid; e < TRI; e += kNT) {
+    for (int e = tid; e < TRI + KP; e += kNT) {
         int i, j;
-        tri_ij(e, i, j);
+        if (e < TRI)
+            tri_ij(e, i, j);
+        else
+            i = j = e - TRI;
         double s = 0.0;
         for (int64_t f = 0; f < d; ++f)
-            s += (double)V[f * KP + i] * (double)G[f * KP + j];
-        cw->C[i * KP + j] = s; // scaled by inv_nrm below
-    }
-    __syncthreads();
-    if (tid < KP) {
-        const int i = tid;
-        double inv = 0.0;
-        if (i < k) {
-            const double n2 = cw->C[i * KP + i];
-            inv = 1.0 / sqrt(n2);
-            if (!(n2 > 0.0) || !isfinite(inv))
-                atomicOr(&cw->status, kStatusNonFinite);
-        }
-        cw->inv_nrm[i] = inv;
-    }
-    __syncthreads();
-    for (int e = tid; e < KP * KP; e += kNT) {
-        const int i = e / KP, j = e % KP;
-        cw->C[e] = (i < k && j <= i) ? cw->C[e] * cw->inv_nrm[i] : 0.0;
-    }
-    __syncthreads();
-    if (tid < KP) {
-        const int j = tid;
-        double s = 1.0;
-        if (j < k) {
-            s = cw->C[j * KP + j];
-            if (!(s >= rho))
-                s = rho;
-        }
-        cw->s[j] = s;
+            s += (double)V[f * KP + i] * (double)G[f * KP + j]; // G = V
+        stat0[(int64_t)e * lds] = s;
+        if (e >= TRI && i < k && !(s > 0.0))
+            atomicOr(&cw->status, kStatusNonFinite);
     }
 }
 
-// Read-out: out[i*d + f] = scale_i * S[f*KP + i] (column-major FP64), with
-// scale_i = inv_nrm_i (players) times 1/sqrt(s_i) when B-normalising, or 1
-// (auxiliary variable).
+// Read-out (one workgroup): reduce the latest norm / parent partials, then
+// out[i*d + f] = scale_i * S[f*KP + i] (column-major FP64) with scale_i =
+// 1/||V_i|| for the players (mode 1), additionally 1/sqrt(s_i) (mode 2:
+// B-normalised), or 1 (mode 0: the auxiliary variable).
 template <typename T, int KP>
-__global__ void __launch_bounds__(kNT) k_readout(const T *S, int64_t d, int k, const Coef *cf, int mode,
+__global__ void __launch_bounds__(kNT) k_readout(const T *S, int64_t d, int k, const double *stat_part,
+                                                 int n_tiles, int lds, double rho, Coef *cw, int mode,
                                                  double *out)
 {
+    constexpr int TRI = KP * (KP + 1) / 2;
+    constexpr int W = TRI + KP;
+    __shared__ double ss[W], scr[kScr];
+    __shared__ double scale[KP];
+    colsum(stat_part, n_tiles, lds, W, ss, scr);
+    if (threadIdx.x < KP) {
+        const int i = threadIdx.x;
+        double sc = 1.0;
+        if (i < k) {
+            const double inv = 1.0 / sqrt(ss[TRI + i]);
+            if (!isfinite(inv) || !(ss[TRI + i] > 0.0))
+                atomicOr(&cw->status, kStatusNonFinite);
+            if (mode >= 1)
+                sc = inv;
+            if (mode == 2) {
+                double s = ss[tri_idx(i, i)] * inv;
+                if (!(s >= rho))
+                    s = rho;
+                sc /= sqrt(s);
+            }
+        }
+        scale[i] = sc;
+    }
+    __syncthreads();
     const int64_t n = d * (int64_t)k;
-    for (int64_t e = (int64_t)blockIdx.x * kNT + threadIdx.x; e < n; e += (int64_t)gridDim.x * kNT) {
+    for (int64_t e = threadIdx.x; e < n; e += kNT) {
         const int i = (int)(e / d);
         const int64_t f = e % d;
-        double sc = 1.0;
-        if (mode >= 1)
-            sc = cf->inv_nrm[i];
-        if (mode == 2)
-            sc /= sqrt(cf->s[i]);
-        out[e] = sc * (double)S[f * KP + i];
+        out[e] = scale[i] * (double)S[f * KP + i];
     }
 }
 
