@@ -49,6 +49,9 @@ struct sgep_handle_s {
     int n_tx = 0, n_ty = 0, n_tiles = 0;
     int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
     int64_t W = 0;          // partial width: KP (KP + 1) / 2 + KP
+    int64_t ldv = 0;        // player row length of V, G, Adam moments (padded views)
+    int64_t dxp = 0;        // storage offset of view y in a player row (CCA)
+    int64_t ldp = 0;        // player row length of P^T, Q^T
     int64_t fwd_blocks_max = 0;
     bool poisoned = false;
 };
@@ -150,7 +153,7 @@ template <typename T, int KP>
 sgep_status launch_init(sgep_handle *h)
 {
     hipLaunchKernelGGL((sgep::k_init<T, KP>), dim3(1), dim3(sgep::kNT), 0, h->stream, (T *)h->V,
-                       (T *)h->G, h->d, h->cfg.k, h->stat_part, h->lds, h->coef);
+                       (T *)h->G, h->ldv, h->cfg.k, h->stat_part, h->lds, h->coef);
     HIPCHK(hipGetLastError());
     return SGEP_OK;
 }
@@ -201,9 +204,10 @@ sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
 template <typename T, int KP>
 sgep_status launch_readout(sgep_handle *h, const void *S, int mode)
 {
+    const int64_t dx = h->cfg.kind == SGEP_KIND_CCA ? h->cfg.dx : h->d;
     hipLaunchKernelGGL((sgep::k_readout<T, KP>), dim3(1), dim3(sgep::kNT), 0, h->stream,
-                       (const T *)S, h->d, h->cfg.k, h->stat_part, h->n_tiles, h->lds, h->cfg.rho,
-                       h->coef, mode, h->readout);
+                       (const T *)S, h->d, dx, h->dxp, h->ldv, h->cfg.k, h->stat_part, h->n_tiles,
+                       h->lds, h->cfg.rho, h->coef, mode, h->readout);
     HIPCHK(hipGetLastError());
     return SGEP_OK;
 }
@@ -288,13 +292,22 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
     h->ldg = (int)((h->fwd_blocks_max + 1) / 2 * 2);
     h->lds = (h->n_tiles + 1) / 2 * 2;
     h->W = (int64_t)h->kp * (h->kp + 1) / 2 + h->kp;
+    auto r4 = [](int64_t x) { return (x + 3) / 4 * 4; };
+    if (cfg->kind == SGEP_KIND_CCA) {
+        h->dxp = r4(cfg->dx);
+        h->ldv = h->dxp + r4(cfg->dy);
+    } else {
+        h->dxp = 0;
+        h->ldv = r4(h->d);
+    }
+    h->ldp = r4(cfg->b_max);
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
         return SGEP_EDEVICE;
     }
 
     const int64_t kp = h->kp, d = h->d;
-    const size_t st_bytes = (size_t)d * kp * h->esz;
+    const size_t st_bytes = (size_t)h->ldv * kp * h->esz;
     bool ok = true;
     auto alloc = [&](void **p, size_t n) {
         if (ok && hipMalloc(p, n < 256 ? 256 : n) != hipSuccess) {
@@ -308,8 +321,8 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
         alloc(&h->Am, st_bytes);
         alloc(&h->As, st_bytes);
     }
-    alloc(&h->P, (size_t)cfg->b_max * kp * h->esz);
-    alloc(&h->Q, (size_t)cfg->b_max * kp * h->esz);
+    alloc(&h->P, (size_t)h->ldp * kp * h->esz);
+    alloc(&h->Q, (size_t)h->ldp * kp * h->esz);
     alloc((void **)&h->gram_part, (size_t)h->W * h->ldg * sizeof(double));
     alloc((void **)&h->stat_part, (size_t)h->W * h->lds * sizeof(double));
     alloc((void **)&h->stat_tot, (size_t)h->W * sizeof(double));
@@ -329,14 +342,19 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
     if (h->Am)
         hok = hok && hipMemsetAsync(h->Am, 0, st_bytes, h->stream) == hipSuccess &&
               hipMemsetAsync(h->As, 0, st_bytes, h->stream) == hipSuccess;
+    // quad-interleaved with padded views: (feature f, player i) at
+    // (sf / 4) 4 KP + 4 i + sf % 4, sf = storage position of f
     std::vector<unsigned char> host(st_bytes, 0);
-    for (int64_t f = 0; f < d; ++f)
-        for (int i = 0; i < cfg->k; ++i) {
+    const int64_t dxv = cfg->kind == SGEP_KIND_CCA ? cfg->dx : d;
+    for (int i = 0; i < cfg->k; ++i)
+        for (int64_t f = 0; f < d; ++f) {
             const double v = V0[(size_t)i * d + f];
+            const int64_t sf = f < dxv ? f : h->dxp + (f - dxv);
+            const int64_t at = (sf >> 2) * 4 * kp + 4 * i + (sf & 3);
             if (h->esz == sizeof(double))
-                ((double *)host.data())[f * kp + i] = v;
+                ((double *)host.data())[at] = v;
             else
-                ((float *)host.data())[f * kp + i] = (float)v;
+                ((float *)host.data())[at] = (float)v;
         }
     hok = hok && hipMemcpyAsync(h->V, host.data(), st_bytes, hipMemcpyHostToDevice, h->stream) ==
                      hipSuccess;
@@ -385,6 +403,9 @@ static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const v
     a.b = b;
     a.dx = h->cfg.dx;
     a.dy = h->cfg.dy;
+    a.dxp = h->dxp;
+    a.ldv = h->ldv;
+    a.ldp = h->ldp;
     a.k = h->cfg.k;
     a.n_tx = h->n_tx;
     a.n_ty = h->n_ty;
@@ -506,7 +527,7 @@ sgep_status sgep_state_size(const sgep_handle *h, size_t *bytes)
 {
     if (!h || !bytes)
         return SGEP_EINVAL;
-    const size_t st = (size_t)h->d * h->kp * h->esz;
+    const size_t st = (size_t)h->ldv * h->kp * h->esz;
     *bytes = sizeof(StateHeader) + sizeof(Coef) + st * (h->Am ? 4 : 2) +
              (size_t)h->W * h->lds * sizeof(double);
     return SGEP_OK;
@@ -530,7 +551,7 @@ sgep_status sgep_get_state(sgep_handle *h, void *host_buf, size_t bytes)
     unsigned char *p = (unsigned char *)host_buf;
     memcpy(p, &hd, sizeof(hd));
     p += sizeof(hd);
-    const size_t st = (size_t)h->d * h->kp * h->esz;
+    const size_t st = (size_t)h->ldv * h->kp * h->esz;
     HIPCHK(hipMemcpyAsync(p, h->coef, sizeof(Coef), hipMemcpyDeviceToHost, h->stream));
     p += sizeof(Coef);
     void *arrs[] = {h->V, h->G, h->Am, h->As};
@@ -561,7 +582,7 @@ sgep_status sgep_set_state(sgep_handle *h, const void *host_buf, size_t bytes)
         hd.elem != (int64_t)h->esz || hd.adam != (h->Am ? 1 : 0))
         return SGEP_EINVAL;
     const unsigned char *p = (const unsigned char *)host_buf + sizeof(hd);
-    const size_t st = (size_t)h->d * h->kp * h->esz;
+    const size_t st = (size_t)h->ldv * h->kp * h->esz;
     // drain any queued work before overwriting the state it uses
     HIPCHK(hipStreamSynchronize(h->stream));
     HIPCHK(hipMemcpyAsync(h->coef, p, sizeof(Coef), hipMemcpyHostToDevice, h->stream));

@@ -27,9 +27,13 @@
 //
 // Normalisation is lazy: the stored V is the iterate before it is projected
 // back to the sphere, and 1/||V_i|| (from the norm partials) scales every use.
-// Storage: V, G and the Adam moments are d x KP row-major (KP = 16, 32 or 64,
-// padding columns held at zero), so one MFMA B-operand row and one
-// accumulator column are contiguous.
+// Storage is quad-interleaved: element (f, i) of V, G and the Adam moments
+// (feature f, player i; KP = 16, 32 or 64 players, those beyond k zero) sits
+// at qidx(f, i) = (f / 4) 4 KP + 4 i + f % 4, each view padded to a multiple
+// of 4 features; the projections P = X V and Q = Y V use the same layout with
+// the minibatch row in place of f.  A lane fetches the MFMA B operand of four
+// consecutive k-indices (features or rows) of one player in one 16-byte load,
+// and the 64 lanes of a wave read one contiguous 1 KB block.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -99,12 +103,15 @@ struct StepArgs {
     const void *X, *Y;
     int64_t ldx, ldy, b;
     int64_t dx, dy;          // CCA: view widths; GENERAL: dx = dy = d
+    int64_t dxp;             // storage offset of view y in a player row (CCA), 0 otherwise
+    int64_t ldv;             // padded feature count of V, G and the Adam moments
+    int64_t ldp;             // padded row count of P and Q (multiple of 4)
     int32_t k, n_tx, n_ty;   // feature tiles over view x and view y (GENERAL: n_ty = 0)
     int32_t vec_ok;          // rows of X and Y 16-byte aligned: vector loads allowed
-    int32_t n_fwd;           // forward workgroups of this iteration
+    int32_t n_fwd;           // forward workgroups (16-row tiles) of this iteration
     int32_t ldg, lds;        // leading dimensions of the Gram / stats partials
-    void *V, *G, *Am, *As;   // d x KP state
-    void *P, *Q;             // b x KP raw projections X V, Y V
+    void *V, *G, *Am, *As;   // ldv x KP, quad-interleaved
+    void *P, *Q;             // ldp x KP, quad-interleaved raw projections X V, Y V
     double *gram_part;       // [W][ldg]: column blk = forward workgroup blk
     double *stat_part;       // [W][lds]: column tile = backward workgroup tile
     double *stat_tot;        // [W]: reduced stat_part of the state entering this iteration
@@ -114,6 +121,13 @@ struct StepArgs {
 };
 
 __device__ __forceinline__ int tri_idx(int i, int j) { return i * (i + 1) / 2 + j; } // j <= i
+
+// quad-interleaved position of (feature or row f, player i) for KP players
+template <int KP>
+__device__ __forceinline__ int64_t qidx(int64_t f, int i)
+{
+    return (f >> 2) * (4 * KP) + 4 * i + (f & 3);
+}
 
 __device__ __forceinline__ void tri_ij(int e, int &i, int &j)
 {
@@ -222,70 +236,85 @@ template <> struct VecLoad<double, 4> {
     }
 };
 
-// N consecutive elements of row `row` starting at feature fs, masked beyond
-// nf and for invalid rows.  The vector path needs vec_ok (16-byte aligned rows)
-// and fs % N == 0.
-template <typename T, int N>
-__device__ __forceinline__ void load_run(const T *__restrict__ X, int64_t ld, int64_t row, bool rv,
-                                         int64_t fs, int64_t nf, bool vec_ok, T *o)
-{
-    if (rv && vec_ok && fs + N <= nf) {
-        VecLoad<T, N>::run(X + row * ld + fs, o);
-    } else {
-#pragma unroll
-        for (int j = 0; j < N; ++j)
-            o[j] = (rv && fs + j < nf) ? X[row * ld + fs + j] : T(0);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Forward products.  One wave accumulates the 16 x KP tile of one view over a
-// contiguous quarter of the features.  Each lane loads VEC consecutive
-// features of its row; MFMA j of a group consumes element j, i.e. the MFMA
-// k-index l/16 stands for feature c*4*VEC + VEC*(l/16) + j, and the B operand
-// (row of V) is taken at the same feature, so the sum is unchanged.  U groups
-// are loaded before their MFMAs are issued.
+// contiguous quarter of the feature chunks (CH = 4 VEC features).  Lane l
+// loads VEC consecutive features fb = c CH + VEC (l/16) .. + VEC - 1 of its
+// row, and for B the same VEC features of player row (l % 16) of V^T: MFMA j
+// of the chunk consumes element j of both, so its k-index l/16 stands for
+// feature fb + j and the sum over features is unchanged.  Batches of U chunks
+// issue all loads before any MFMA; chunks past the wave's full range are
+// loaded from a valid chunk and zeroed; the ragged last chunk runs masked.
+// `row` is a valid row index; rows past the minibatch are zeroed through rv.
 // ---------------------------------------------------------------------------
 template <typename T, int KP>
 __device__ __forceinline__ void fwd_view(const T *__restrict__ X, int64_t ldx, int64_t nf, int64_t row,
-                                         bool rv, bool vec_ok, const T *__restrict__ V, int lane,
-                                         int w, typename Mfma<T>::acc *acc)
+                                         bool rv, bool vec_ok, const T *__restrict__ VQ,
+                                         int lane, int w, typename Mfma<T>::acc (*acc)[KP / 16])
 {
     constexpr int VEC = 16 / (int)sizeof(T);
     constexpr int CH = 4 * VEC;
     constexpr int NB = KP / 16;
-    constexpr int U = 8 / NB > 1 ? 8 / NB : 2;
+    constexpr int U = 8 / NB;
     const int kk = lane >> 4, n = lane & 15;
     const int64_t nch = (nf + CH - 1) / CH;
+    const int64_t nfull = nf / CH; // chunks whose features are all valid
     const int64_t c0 = (nch * w) >> 2, c1 = (nch * (w + 1)) >> 2;
-    for (int64_t cb = c0; cb < c1; cb += U) {
+    const int64_t cf = c1 < nfull ? c1 : nfull;
+    const T *xr = X + row * ldx;
+    for (int64_t c = c0; c < cf; c += U) {
         T xv[U][VEC];
-        T bv[U][VEC][NB];
+        T bv[U][NB][VEC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t c = cb + u;
-            const bool cv = c < c1;
-            const int64_t fb = c * CH + (int64_t)VEC * kk;
-            load_run<T, VEC>(X, ldx, row, rv && cv, fb, nf, vec_ok, xv[u]);
+            const int64_t cu = (c + u < cf) ? c + u : c;
+            const int64_t fb = cu * CH + (int64_t)VEC * kk;
+            if (vec_ok) {
+                VecLoad<T, VEC>::run(xr + fb, xv[u]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j)
+                    xv[u][j] = xr[fb + j];
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                VecLoad<T, VEC>::run(VQ + qidx<KP>(fb, nb * 16 + n), bv[u][nb]);
+        }
+        // keep the batch's loads ahead of its MFMAs (no interleaving by the
+        // scheduler, which would serialise the memory latency)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = rv && (c + u < cf);
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
-                const int64_t fe = fb + j;
-                const bool fv = cv && fe < nf;
+                const T xs = ok ? xv[u][j] : T(0);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    bv[u][j][nb] = fv ? V[fe * KP + nb * 16 + n] : T(0);
+                    acc[j & 1][nb] = Mfma<T>::fma(xs, bv[u][nb][j], acc[j & 1][nb]);
             }
         }
+    }
+    if (nfull < c1 && nfull >= c0) { // the ragged last chunk, features masked
+        const int64_t fb = nfull * CH + (int64_t)VEC * kk;
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int j = 0; j < VEC; ++j) {
+            const int64_t fe = fb + j;
+            const bool fv = fe < nf;
+            const int64_t fc = fv ? fe : nf - 1;
+            const T xs = (rv && fv) ? xr[fc] : T(0);
 #pragma unroll
-            for (int j = 0; j < VEC; ++j)
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[nb] = Mfma<T>::fma(xv[u][j], bv[u][j][nb], acc[nb]);
+            for (int nb = 0; nb < NB; ++nb) {
+                const T bvv = fv ? VQ[qidx<KP>(fc, nb * 16 + n)] : T(0);
+                acc[0][nb] = Mfma<T>::fma(xs, bvv, acc[0][nb]);
+            }
+        }
     }
 }
 
+// Forward kernel: workgroup rt takes rows 16 rt .. 16 rt + 15; the four waves
+// split the features.  The extra last workgroup reduces the norm / parent
+// partials of the current state and advances the step counter.
 template <typename T, int KP, int KIND>
 __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 {
@@ -293,7 +322,7 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
     constexpr int NB = KP / 16;
     constexpr int TRI = KP * (KP + 1) / 2;
     constexpr int GW = TRI + KP;
-    __shared__ T red[4][16][KP];
+    __shared__ T red[4][16 * KP];
     __shared__ T pt[16][KP], qt[16][KP];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -311,53 +340,57 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
         return;
     }
     const int64_t r0 = (int64_t)blockIdx.x * 16;
-    const int64_t row = r0 + n;
-    const bool rv = row < a.b;
+    const bool rv = r0 + n < a.b;
+    const int64_t row = rv ? r0 + n : a.b - 1; // valid address; zeroed through rv
     const bool vec_ok = a.vec_ok != 0;
-    const T *X = (const T *)a.X, *Y = (const T *)a.Y, *V = (const T *)a.V;
-    T *P = (T *)a.P, *Q = (T *)a.Q;
+    const T *X = (const T *)a.X, *Y = (const T *)a.Y, *VQ = (const T *)a.V;
+    T *PQ = (T *)a.P, *QQ = (T *)a.Q;
 
-    Acc accP[NB], accQ[NB];
+    Acc aP[2][NB], aQ[2][NB];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            aP[h][nb] = Acc{0, 0, 0, 0};
+            aQ[h][nb] = Acc{0, 0, 0, 0};
+        }
+    fwd_view<T, KP>(X, a.ldx, a.dx, row, rv, vec_ok, VQ, lane, w, aP);
+    if (KIND == kKindCCA) // view y starts at feature dxp (a multiple of 4)
+        fwd_view<T, KP>(Y, a.ldy, a.dy, row, rv, vec_ok, VQ + a.dxp * KP, lane, w, aQ);
+    else
+        fwd_view<T, KP>(Y, a.ldy, a.dx, row, rv, vec_ok, VQ, lane, w, aQ);
+
+    // sum the accumulator sets and the four waves' tiles in a fixed order
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-        accP[nb] = Acc{0, 0, 0, 0};
-        accQ[nb] = Acc{0, 0, 0, 0};
-    }
-    fwd_view<T, KP>(X, a.ldx, a.dx, row, rv, vec_ok, V, lane, w, accP);
-    if (KIND == kKindCCA)
-        fwd_view<T, KP>(Y, a.ldy, a.dy, row, rv, vec_ok, V + a.dx * KP, lane, w, accQ);
-    else
-        fwd_view<T, KP>(Y, a.ldy, a.dx, row, rv, vec_ok, V, lane, w, accQ);
-
-    // sum the four waves' partial tiles in a fixed order
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+        const Acc s = aP[0][nb] + aP[1][nb];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            red[w][Mfma<T>::drow(kk, r)][nb * 16 + n] = accP[nb][r];
-    __syncthreads();
-    for (int e = tid; e < 16 * KP; e += kNT) {
-        const int r = e / KP, c = e % KP;
-        const T s = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
-        pt[r][c] = s;
-        if (r0 + r < a.b)
-            P[(r0 + r) * KP + c] = s;
+            red[w][Mfma<T>::drow(kk, r) * KP + nb * 16 + n] = s[r];
     }
     __syncthreads();
+    for (int e = tid; e < 16 * KP; e += kNT)
+        (&pt[0][0])[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    __syncthreads();
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+    for (int nb = 0; nb < NB; ++nb) {
+        const Acc s = aQ[0][nb] + aQ[1][nb];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            red[w][Mfma<T>::drow(kk, r)][nb * 16 + n] = accQ[nb][r];
-    __syncthreads();
-    for (int e = tid; e < 16 * KP; e += kNT) {
-        const int r = e / KP, c = e % KP;
-        const T s = red[0][r][c] + red[1][r][c] + red[2][r][c] + red[3][r][c];
-        qt[r][c] = s;
-        if (r0 + r < a.b)
-            Q[(r0 + r) * KP + c] = s;
+            red[w][Mfma<T>::drow(kk, r) * KP + nb * 16 + n] = s[r];
     }
     __syncthreads();
+    for (int e = tid; e < 16 * KP; e += kNT)
+        (&qt[0][0])[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    __syncthreads();
+    // P, Q of these 16 rows: one contiguous quad-interleaved block
+    for (int e = tid; e < 16 * KP; e += kNT) {
+        const int rq = e / (4 * KP), c = (e / 4) % KP, r = 4 * rq + (e & 3);
+        if (r0 + r < a.b) {
+            PQ[r0 * KP + e] = pt[r][c];
+            QQ[r0 * KP + e] = qt[r][c];
+        }
+    }
 
     // partial Grams over these 16 rows (raw players, FP64): lower triangle of
     // b V^T A_t V and the diagonal of b V^T B_t V (without the ridge)
@@ -386,11 +419,14 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Backward products + fused update for a tile of FT = 16*MB features.
-// A operand = X^T: lane l loads MB consecutive features f0 + MB*(l%16) + j of
-// row r + l/16; element j feeds M-block j, so M-block j, M-row m holds feature
-// f0 + MB*m + j.  B operands: rows of Q and P (KP wide).  The four waves take
-// interleaved 4-row groups; U groups are loaded before their MFMAs.
+// Backward products + fused update for a tile of FT = 16 MB features.
+// Rows go in groups of 16; wave w takes groups w, w + 4, ...  Within a group
+// the four MFMAs j = 0..3 cover rows 16 g + 4 (l/16) + j: lane l supplies
+// A = X[that row][f0 + MB (l%16) + jm] for M-block jm (MB consecutive features
+// in one load) and B = element j of the 4 consecutive rows 16 g + 4 (l/16) ..
+// of P^T / Q^T for player l % 16 (one 16-byte load), so M-block jm, M-row m
+// holds feature f0 + MB m + jm.  Batches of UB groups issue all loads before
+// any MFMA; the ragged last group runs masked.
 // ---------------------------------------------------------------------------
 template <typename T, int KP, int MB, int KIND, int OPT>
 __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
@@ -400,7 +436,9 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
     constexpr int FT = 16 * MB;
     constexpr int TRI = KP * (KP + 1) / 2;
     constexpr int W = TRI + KP; // width of both partial kinds
-    constexpr int U = 16 / (MB * NB) > 2 ? 16 / (MB * NB) : 2;
+    constexpr int XPG = (KIND == kKindCCA ? 4 : 8) * MB; // X registers per group
+    constexpr int UB0 = 512 / ((XPG + 8 * NB) * (int)sizeof(T)); // ~128 VGPRs in flight
+    constexpr int UB = UB0 < 1 ? 1 : (UB0 > 16 ? 16 : UB0);
     constexpr int EPT = FT * KP / kNT; // epilogue elements per thread
     static_assert(EPT * kNT == FT * KP, "tile must be a multiple of the workgroup");
     __shared__ T red[4][FT * KP];
@@ -415,7 +453,7 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
     const int tile = blockIdx.x;
     const bool vec_ok = a.vec_ok != 0;
     const T *X = (const T *)a.X, *Y = (const T *)a.Y;
-    const T *P = (const T *)a.P, *Q = (const T *)a.Q;
+    const T *PQ = (const T *)a.P, *QQ = (const T *)a.Q;
 
     const T *Xa;      // view multiplying the A-side operand
     const T *Xb;      // view multiplying the B-side operand
@@ -424,94 +462,165 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
     if (KIND == kKindCCA) {
         if (tile < a.n_tx) { // x features: A_t V = X^T Q / b, B_t V = X^T P / b
             Xa = X; lda = a.ldx; nf = a.dx; fbase = 0; f0 = (int64_t)tile * FT;
-            opA = Q; opB = P;
+            opA = QQ; opB = PQ;
         } else {             // y features: A_t V = Y^T P / b, B_t V = Y^T Q / b
-            Xa = Y; lda = a.ldy; nf = a.dy; fbase = a.dx; f0 = (int64_t)(tile - a.n_tx) * FT;
-            opA = P; opB = Q;
+            Xa = Y; lda = a.ldy; nf = a.dy; fbase = a.dxp; f0 = (int64_t)(tile - a.n_tx) * FT;
+            opA = PQ; opB = QQ;
         }
         Xb = Xa; ldb = lda;
     } else {                 // GENERAL: A_t V = Y^T Q / b, B_t V = X^T P / b + eps V
         Xa = Y; lda = a.ldy; Xb = X; ldb = a.ldx;
         nf = a.dx; fbase = 0; f0 = (int64_t)tile * FT;
-        opA = Q; opB = P;
+        opA = QQ; opB = PQ;
+    }
+
+    // epilogue operands of this thread's elements: element e of the tile's
+    // contiguous quad-interleaved block, i.e. feature f0 + 4 (e / 4KP) + e % 4
+    // of player (e / 4) % KP
+    T *VQ = (T *)a.V, *GQ = (T *)a.G, *Am = (T *)a.Am, *As = (T *)a.As;
+    const int64_t tbase = (fbase + f0) * KP; // first element of this tile's block
+    T pv[EPT], pg[EPT], pm[EPT], ps[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * kNT;
+        const int fl = 4 * (e / (4 * KP)) + (e & 3);
+        const bool ok = f0 + fl < nf;
+        const int64_t si = tbase + e;
+        pg[q] = ok ? GQ[si] : T(0);
+        pv[q] = ok ? VQ[si] : T(0);
+        if (OPT == kOptAdam) {
+            pm[q] = ok ? Am[si] : T(0);
+            ps[q] = ok ? As[si] : T(0);
+        }
     }
 
     // ---- main loop: raw X^T Q and X^T P over all rows ----
-    Acc accA[MB][NB], accB[MB][NB];
+    Acc aA[2][MB][NB], aB[2][MB][NB];
 #pragma unroll
-    for (int j = 0; j < MB; ++j)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            accA[j][nb] = Acc{0, 0, 0, 0};
-            accB[j][nb] = Acc{0, 0, 0, 0};
-        }
-    const int64_t fs = f0 + (int64_t)MB * m;
-    for (int64_t rb = 4 * w; rb < a.b; rb += 16 * U) {
-        T xa[U][MB], xb[U][MB], ba[U][NB], bb[U][NB];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t row = rb + 16 * u + kk;
-            const bool rv = row < a.b;
-            load_run<T, MB>(Xa, lda, row, rv, fs, nf, vec_ok, xa[u]);
-            if (KIND != kKindCCA)
-                load_run<T, MB>(Xb, ldb, row, rv, fs, nf, vec_ok, xb[u]);
+        for (int j = 0; j < MB; ++j)
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                ba[u][nb] = rv ? opA[row * KP + nb * 16 + m] : T(0);
-                bb[u][nb] = rv ? opB[row * KP + nb * 16 + m] : T(0);
+                aA[h][j][nb] = Acc{0, 0, 0, 0};
+                aB[h][j][nb] = Acc{0, 0, 0, 0};
+            }
+    const int64_t fs = f0 + (int64_t)MB * m;
+    bool fok[MB];
+    int64_t fcl[MB];
+#pragma unroll
+    for (int jm = 0; jm < MB; ++jm) {
+        fok[jm] = fs + jm < nf;
+        fcl[jm] = fok[jm] ? fs + jm : nf - 1;
+    }
+    const bool vrun = vec_ok && fs + MB <= nf;
+    const T *pa[NB], *pb[NB]; // player (nb*16 + m): rows r..r+3 at p[r * KP]
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        pa[nb] = opA + 4 * (nb * 16 + m);
+        pb[nb] = opB + 4 * (nb * 16 + m);
+    }
+    const int64_t ngf = a.b / 16; // full 16-row groups
+    for (int64_t g0 = w; g0 < ngf; g0 += 4 * UB) {
+        T xa[UB][4][MB], xb[UB][4][MB], ba[UB][NB][4], bb[UB][NB][4];
+#pragma unroll
+        for (int u = 0; u < UB; ++u) {
+            const int64_t g = (g0 + 4 * u < ngf) ? g0 + 4 * u : g0;
+            const int64_t r4 = 16 * g + 4 * kk;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t row = r4 + j;
+                if (vrun) {
+                    VecLoad<T, MB>::run(Xa + row * lda + fs, xa[u][j]);
+                    if (KIND != kKindCCA)
+                        VecLoad<T, MB>::run(Xb + row * ldb + fs, xb[u][j]);
+                } else {
+#pragma unroll
+                    for (int jm = 0; jm < MB; ++jm) {
+                        xa[u][j][jm] = Xa[row * lda + fcl[jm]];
+                        if (KIND != kKindCCA)
+                            xb[u][j][jm] = Xb[row * ldb + fcl[jm]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                VecLoad<T, 4>::run(pa[nb] + r4 * KP, ba[u][nb]);
+                VecLoad<T, 4>::run(pb[nb] + r4 * KP, bb[u][nb]);
             }
         }
+        __builtin_amdgcn_sched_barrier(0); // all of the batch's loads first
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < UB; ++u) {
+            const bool gv = g0 + 4 * u < ngf;
 #pragma unroll
-            for (int j = 0; j < MB; ++j)
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int jm = 0; jm < MB; ++jm) {
+                    const bool ok = gv && fok[jm];
+                    const T va = ok ? xa[u][j][jm] : T(0);
+                    const T vb = ok ? (KIND == kKindCCA ? xa[u][j][jm] : xb[u][j][jm]) : T(0);
+#pragma unroll
+                    for (int nb = 0; nb < NB; ++nb) {
+                        aA[j & 1][jm][nb] = Mfma<T>::fma(va, ba[u][nb][j], aA[j & 1][jm][nb]);
+                        aB[j & 1][jm][nb] = Mfma<T>::fma(vb, bb[u][nb][j], aB[j & 1][jm][nb]);
+                    }
+                }
+        }
+    }
+    if (ngf * 16 < a.b && w == (int)(ngf & 3)) { // the ragged last group, masked
+        const int64_t r4 = 16 * ngf + 4 * kk;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t r = r4 + j;
+            const bool rv = r < a.b;
+            const int64_t row = rv ? r : a.b - 1;
+#pragma unroll
+            for (int jm = 0; jm < MB; ++jm) {
+                const bool ok = rv && fok[jm];
+                const T va = ok ? Xa[row * lda + fcl[jm]] : T(0);
+                const T vb = ok ? (KIND == kKindCCA ? va : Xb[row * ldb + fcl[jm]]) : T(0);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
-                    accA[j][nb] = Mfma<T>::fma(xa[u][j], ba[u][nb], accA[j][nb]);
-                    accB[j][nb] = Mfma<T>::fma(KIND == kKindCCA ? xa[u][j] : xb[u][j], bb[u][nb],
-                                               accB[j][nb]);
+                    const T qa = rv ? opA[qidx<KP>(row, nb * 16 + m)] : T(0);
+                    const T qb = rv ? opB[qidx<KP>(row, nb * 16 + m)] : T(0);
+                    aA[0][jm][nb] = Mfma<T>::fma(va, qa, aA[0][jm][nb]);
+                    aB[0][jm][nb] = Mfma<T>::fma(vb, qb, aB[0][jm][nb]);
                 }
+            }
+        }
     }
 
-    // cross-wave reduction (fixed order) into natural feature order
+    // cross-wave reduction (fixed order) into natural feature order [fl][i]
 #pragma unroll
-    for (int j = 0; j < MB; ++j)
+    for (int jm = 0; jm < MB; ++jm)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
+        for (int nb = 0; nb < NB; ++nb) {
+            const Acc s = aA[0][jm][nb] + aA[1][jm][nb];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                red[w][(MB * Mfma<T>::drow(kk, r) + j) * KP + nb * 16 + m] = accA[j][nb][r];
+                red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
+        }
     __syncthreads();
     for (int e = tid; e < FT * KP; e += kNT)
         avt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < MB; ++j)
+    for (int jm = 0; jm < MB; ++jm)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
+        for (int nb = 0; nb < NB; ++nb) {
+            const Acc s = aB[0][jm][nb] + aB[1][jm][nb];
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                red[w][(MB * Mfma<T>::drow(kk, r) + j) * KP + nb * 16 + m] = accB[j][nb][r];
+                red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
+        }
     __syncthreads();
     for (int e = tid; e < FT * KP; e += kNT)
         bvt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
-
-    // ---- prefetch the epilogue operands of this thread's elements ----
-    T *V = (T *)a.V, *G = (T *)a.G, *Am = (T *)a.Am, *As = (T *)a.As;
-    T pv[EPT], pm[EPT], ps[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         const int e = tid + q * kNT;
-        const int fl = e / KP, i = e % KP;
-        const int64_t f = f0 + fl;
-        const bool ok = f < nf;
-        const int64_t gi = (fbase + (ok ? f : 0)) * KP + i;
-        gt[e] = ok ? G[gi] : T(0);
-        pv[q] = ok ? V[gi] : T(0);
-        if (OPT == kOptAdam) {
-            pm[q] = ok ? Am[gi] : T(0);
-            ps[q] = ok ? As[gi] : T(0);
-        }
+        gt[(4 * (e / (4 * KP)) + (e & 3)) * KP + (e / 4) % KP] = pg[q];
     }
 
     // ---- k x k coefficients (identical in every workgroup) ----
@@ -584,17 +693,19 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
     const T eps = (T)a.eps_reg;
     const T b1 = (T)a.adam_b1, b2 = (T)a.adam_b2, aeps = (T)a.adam_eps;
     const T c1 = (T)(1.0 - pow(a.adam_b1, t)), c2 = (T)(1.0 - pow(a.adam_b2, t));
+    T vnq[EPT], gnq[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         const int e = tid + q * kNT;
-        const int fl = e / KP, i = e % KP;
+        const int i = (e / 4) % KP, fl = 4 * (e / (4 * KP)) + (e & 3);
         const int64_t f = f0 + fl;
         T vn = 0, gn = 0;
         if (f < nf && i < a.k) {
-            const int64_t gi = (fbase + f) * KP + i;
+            const int64_t si = tbase + e;
+            const int ti = fl * KP + i;
             const T vh = pv[q] * cInv[i];
-            const T av = avt[e] * cInv[i] * ibT;
-            T bv = bvt[e] * cInv[i] * ibT;
+            const T av = avt[ti] * cInv[i] * ibT;
+            T bv = bvt[ti] * cInv[i] * ibT;
             if (KIND != kKindCCA)
                 bv += eps * vh;
             T pen = 0;
@@ -606,17 +717,25 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
             } else {
                 const T mm = b1 * pm[q] + (T(1) - b1) * grad;
                 const T sq = b2 * ps[q] + (T(1) - b2) * grad * grad;
-                Am[gi] = mm;
-                As[gi] = sq;
+                Am[si] = mm;
+                As[si] = sq;
                 vn = vh + eta * (mm / c1) / (sqrt(sq / c2) + aeps);
             }
-            const T g0 = gt[e];
+            const T g0 = pg[q];
             gn = g0 + gam * (bv - g0);
-            V[gi] = vn;
-            G[gi] = gn;
+            VQ[si] = vn;
+            GQ[si] = gn;
         }
-        avt[e] = vn; // own slot: reused for the partials below
-        bvt[e] = gn;
+        vnq[q] = vn;
+        gnq[q] = gn;
+    }
+    __syncthreads(); // every read of avt / bvt is done
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+        const int e = tid + q * kNT;
+        const int ti = (4 * (e / (4 * KP)) + (e & 3)) * KP + (e / 4) % KP;
+        avt[ti] = vnq[q];
+        bvt[ti] = gnq[q];
     }
     __syncthreads();
     // this tile's partials of v_i^T G_j (j <= i) and ||v_i||^2 of the new state
@@ -639,13 +758,13 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
 
 // ---------------------------------------------------------------------------
 // Initialisation (one workgroup; not on the hot path): normalise the supplied
-// players to the unit sphere, set [Bv]_i = v_i (Alg. 2), and write the norm /
-// parent-term sums of this state as column 0 of stats buffer 0 (the other
-// columns are zero).
+// players (player-major rows of length ldv, padding zero) to the unit sphere,
+// set [Bv]_i = v_i (Alg. 2), and write the norm / parent-term sums of this
+// state as column 0 of the stats partials (the other columns are zero).
 // ---------------------------------------------------------------------------
 template <typename T, int KP>
-__global__ void __launch_bounds__(kNT) k_init(T *V, T *G, int64_t d, int k, double *stat0, int lds,
-                                              Coef *cw)
+__global__ void __launch_bounds__(kNT) k_init(T *VQ, T *GQ, int64_t ldv, int k, double *stat0,
+                                              int lds, Coef *cw)
 {
     constexpr int TRI = KP * (KP + 1) / 2;
     __shared__ double part[kNT];
@@ -653,8 +772,10 @@ __global__ void __launch_bounds__(kNT) k_init(T *V, T *G, int64_t d, int k, doub
     const int tid = threadIdx.x;
     for (int i = 0; i < KP; ++i) {
         double s = 0.0;
-        for (int64_t f = tid; f < d; f += kNT)
-            s += (double)V[f * KP + i] * (double)V[f * KP + i];
+        for (int64_t f = tid; f < ldv; f += kNT) {
+            const double v = (double)VQ[qidx<KP>(f, i)];
+            s += v * v;
+        }
         part[tid] = s;
         __syncthreads();
         if (tid == 0) {
@@ -665,11 +786,11 @@ __global__ void __launch_bounds__(kNT) k_init(T *V, T *G, int64_t d, int k, doub
         }
         __syncthreads();
     }
-    for (int64_t e = tid; e < d * KP; e += kNT) {
-        const int i = (int)(e % KP);
-        const T v = (i < k) ? (T)((double)V[e] / sqrt(nrm[i])) : T(0);
-        V[e] = v;
-        G[e] = v;
+    for (int64_t e = tid; e < KP * ldv; e += kNT) {
+        const int i = (int)((e / 4) % KP);
+        const T v = (i < k) ? (T)((double)VQ[e] / sqrt(nrm[i])) : T(0);
+        VQ[e] = v;
+        GQ[e] = v;
     }
     __syncthreads();
     for (int e = tid; e < TRI + KP; e += kNT) {
@@ -679,8 +800,8 @@ __global__ void __launch_bounds__(kNT) k_init(T *V, T *G, int64_t d, int k, doub
         else
             i = j = e - TRI;
         double s = 0.0;
-        for (int64_t f = 0; f < d; ++f)
-            s += (double)V[f * KP + i] * (double)G[f * KP + j]; // G = V
+        for (int64_t f = 0; f < ldv; ++f)
+            s += (double)VQ[qidx<KP>(f, i)] * (double)GQ[qidx<KP>(f, j)]; // G = V
         stat0[(int64_t)e * lds] = s;
         if (e >= TRI && i < k && !(s > 0.0))
             atomicOr(&cw->status, kStatusNonFinite);
@@ -688,11 +809,13 @@ __global__ void __launch_bounds__(kNT) k_init(T *V, T *G, int64_t d, int k, doub
 }
 
 // Read-out (one workgroup): reduce the latest norm / parent partials, then
-// out[i*d + f] = scale_i * S[f*KP + i] (column-major FP64) with scale_i =
-// 1/||V_i|| for the players (mode 1), additionally 1/sqrt(s_i) (mode 2:
-// B-normalised), or 1 (mode 0: the auxiliary variable).
+// out[i*d + f] = scale_i * S[qidx(storage(f), i)] (column-major FP64) with
+// scale_i = 1/||V_i|| for the players (mode 1), additionally 1/sqrt(s_i)
+// (mode 2: B-normalised), or 1 (mode 0: the auxiliary variable).  storage(f)
+// maps feature f of the concatenated views to its padded position.
 template <typename T, int KP>
-__global__ void __launch_bounds__(kNT) k_readout(const T *S, int64_t d, int k, const double *stat_part,
+__global__ void __launch_bounds__(kNT) k_readout(const T *S, int64_t d, int64_t dx, int64_t dxp,
+                                                 int64_t ldv, int k, const double *stat_part,
                                                  int n_tiles, int lds, double rho, Coef *cw, int mode,
                                                  double *out)
 {
@@ -724,7 +847,8 @@ __global__ void __launch_bounds__(kNT) k_readout(const T *S, int64_t d, int k, c
     for (int64_t e = threadIdx.x; e < n; e += kNT) {
         const int i = (int)(e / d);
         const int64_t f = e % d;
-        out[e] = scale[i] * (double)S[f * KP + i];
+        const int64_t sf = f < dx ? f : dxp + (f - dx);
+        out[e] = scale[i] * (double)S[qidx<KP>(sf, i)];
     }
 }
 
