@@ -84,6 +84,32 @@ def config_for(sg, w):
         eta0=w["eta0"], t0=w.get("t0", 1.0), gamma=w["gamma"], rho=w["rho"])
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2206_04993_amd/csrc/sgep_kernels.hpp", "paper_2206_04993_amd/csrc/sgep.hip"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (calibrated against a plain copy), or
+    None when no summary exists or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("json: "):
+            rec = json.loads(line[6:])
+    if rec.get("source_hash") != kernel_source_hash() or kernel not in rec.get("kernels", {}):
+        return None
+    k = rec["kernels"][kernel]
+    return {"read_bytes": k["read_bytes"], "write_bytes": k["write_bytes"],
+            "total_bytes": k["read_bytes"] + k["write_bytes"], "source": os.path.basename(path)}
+
+
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle (Alg. 2 per player, OpenMP over players) on a bounded
     sample of the same workload: consecutive minibatches until budget_s of
@@ -126,6 +152,8 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -166,6 +194,16 @@ def main():
             step(t)
     torch.cuda.synchronize()
     n_rep, rem = divmod(K, chunk)
+
+    if args.calibrate_copy_mb:
+        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this kernel
+        # calibrate the per-dispatch counters of the step kernels
+        src = torch.ones(args.calibrate_copy_mb << 18, device="cuda", dtype=torch.float32)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- timed region: exactly K steps ----
     torch.cuda.synchronize()
@@ -214,7 +252,8 @@ def main():
     peak = PEAK_FP32_MFMA_TFLOPS if w["dtype"] == "f32" else PEAK_FP64_MFMA_TFLOPS
     achieved = flops[dom] / (dom_us * 1e-6) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 5), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
+                "traffic": measured_traffic(args.workload, dom),
                 "kernel": dom, "kernel_avg_us": round(dom_us, 3),
                 "k_fwd_avg_us": round(fwd_avg, 3), "k_bwd_avg_us": round(bwd_avg, 3),
                 "algorithmic_flops_per_launch": flops[dom],

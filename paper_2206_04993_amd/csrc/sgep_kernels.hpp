@@ -122,6 +122,17 @@ struct StepArgs {
 
 __device__ __forceinline__ int tri_idx(int i, int j) { return i * (i + 1) / 2 + j; } // j <= i
 
+// Workgroup index -> tile index such that consecutive tiles run on the same
+// XCD (workgroups are dealt to the 8 XCDs round-robin): neighbouring feature
+// tiles share the 128-byte lines of a minibatch row, so they should share an
+// L2.  Identity when the count is not a multiple of 8.
+__device__ __forceinline__ int xcd_tile(int b, int nblk)
+{
+    if (nblk % 8 != 0)
+        return b;
+    return (b % 8) * (nblk / 8) + b / 8;
+}
+
 // quad-interleaved position of (feature or row f, player i) for KP players
 template <int KP>
 __device__ __forceinline__ int64_t qidx(int64_t f, int i)
@@ -450,7 +461,7 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int kk = lane >> 4, m = lane & 15;
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const bool vec_ok = a.vec_ok != 0;
     const T *X = (const T *)a.X, *Y = (const T *)a.Y;
     const T *PQ = (const T *)a.P, *QQ = (const T *)a.Q;
@@ -666,7 +677,7 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
         cMB[i] = (T)mB;
         cMAc[i] = (T)(mA - c);
         cInv[i] = (T)dInv[i];
-        if (blockIdx.x == 0) {
+        if (tile == 0) {
             if (i < a.k) {
                 cw->ema_a[i] += a.gamma * (mA - cw->ema_a[i]);
                 cw->ema_b[i] += a.gamma * (mB - cw->ema_b[i]);

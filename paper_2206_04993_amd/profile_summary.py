@@ -1,0 +1,99 @@
+"""Summarise rocprofv3 output of one bench.py workload into profiles/.
+
+Reads the kernel-trace stats and the FETCH_SIZE / WRITE_SIZE counter passes
+produced by
+
+    rocprofv3 --kernel-trace --stats --output-format csv -d DIR -o ks -- CMD
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o fetch -- CMD
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR -o write -- CMD
+
+with CMD = python3 bench.py --workload W --steps 256 --warmup 16
+--no-cpu-baseline --calibrate-copy-mb 256, and writes
+profiles/kernels_<W>.txt (kernel durations) and profiles/traffic_<W>.txt
+(HBM bytes per launch).  Counter values are KiB per dispatch; the plain
+256 MiB copy in the same run calibrates them (bytes per counter-KiB).
+"""
+from __future__ import annotations
+
+import csv
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _rows(path):
+    return list(csv.DictReader(open(path)))
+
+
+def _short(name: str) -> str:
+    if "k_fwd" in name:
+        return "k_fwd"
+    if "k_bwd" in name:
+        return "k_bwd"
+    if "copybuffer" in name.lower():
+        return "copy"
+    return name[:60]
+
+
+def main(prof_dir: str, workload: str, copy_mib: int = 256):
+    sys.path.insert(0, ROOT)
+    import bench  # noqa: the source hash of the kernels
+
+    cmd = (f"python3 bench.py --workload {workload} --steps 256 --warmup 16 --no-cpu-baseline "
+           f"--calibrate-copy-mb {copy_mib}")
+    ks = _rows(os.path.join(prof_dir, "ks_kernel_stats.csv"))
+    out = [f"# rocprofv3 kernel statistics, workload {workload} (MI355X)",
+           f"# command: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o ks -- {cmd}",
+           "kernel | calls | avg_us | min_us | max_us | share_%"]
+    for r in ks:
+        out.append(f"{r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs'])/1e3:.3f} | "
+                   f"{float(r['MinNs'])/1e3:.3f} | {float(r['MaxNs'])/1e3:.3f} | "
+                   f"{float(r['Percentage']):.2f}")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    open(os.path.join(ROOT, "profiles", f"kernels_{workload}.txt"), "w").write("\n".join(out) + "\n")
+
+    vals = {}
+    for tag, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
+        for r in _rows(os.path.join(prof_dir, f"{tag}_counter_collection.csv")):
+            if r["Counter_Name"] != ctr:
+                continue
+            vals.setdefault((_short(r["Kernel_Name"]), tag), []).append(
+                (int(r["Grid_Size"]), float(r["Counter_Value"])))
+    # the calibration copy: the largest-grid copy dispatches
+    def copy_kib(tag):
+        c = vals.get(("copy", tag), [])
+        big = max(g for g, _ in c)
+        return statistics.median(v for g, v in c if g == big)
+    scale_r = copy_mib * 2 ** 20 / copy_kib("fetch")   # bytes per counter-KiB, reads
+    scale_w = copy_mib * 2 ** 20 / copy_kib("write")   # bytes per counter-KiB, writes
+    rec = {"workload": workload, "source_hash": bench.kernel_source_hash(),
+           "copy_calibration": {"mib": copy_mib, "fetch_kib": copy_kib("fetch"),
+                                "write_kib": copy_kib("write"), "read_scale": scale_r,
+                                "write_scale": scale_w},
+           "kernels": {}}
+    lines = [f"# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE, workload {workload}",
+             f"# commands: rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- {cmd}",
+             f"#           rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o write -- {cmd}",
+             f"# calibration: plain copy of {copy_mib} MiB reads {copy_kib('fetch'):.0f} KiB and writes "
+             f"{copy_kib('write'):.0f} KiB by these counters",
+             "kernel | dispatches | fetch_KiB(median) | write_KiB(median) | read_bytes | write_bytes"]
+    for k in ("k_fwd", "k_bwd"):
+        f = [v for _, v in vals.get((k, "fetch"), [])]
+        w = [v for _, v in vals.get((k, "write"), [])]
+        if not f:
+            continue
+        fr, wr = statistics.median(f), statistics.median(w)
+        rb, wb = fr * scale_r, wr * scale_w
+        rec["kernels"][k] = {"read_bytes": round(rb), "write_bytes": round(wb),
+                             "fetch_kib": fr, "write_kib": wr, "dispatches": len(f)}
+        lines.append(f"{k} | {len(f)} | {fr:.1f} | {wr:.1f} | {rb:.0f} | {wb:.0f}")
+    lines.append("json: " + json.dumps(rec))
+    open(os.path.join(ROOT, "profiles", f"traffic_{workload}.txt"), "w").write("\n".join(lines) + "\n")
+    print("\n".join(out + lines))
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], sys.argv[2])
