@@ -84,11 +84,12 @@ def config_for(sg, w):
         eta0=w["eta0"], t0=w.get("t0", 1.0), gamma=w["gamma"], rho=w["rho"])
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(header: str = "sgep_kernels.hpp") -> str:
+    """Hash of the device code of one kernel family (its header under csrc/);
+    the launch grids the counters were taken with are in the same summary."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("paper_2206_04993_amd/csrc/sgep_kernels.hpp", "paper_2206_04993_amd/csrc/sgep.hip"):
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2206_04993_amd", "csrc", header), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -218,10 +219,10 @@ def main():
     ms_per_step = (t1 - t0) * 1e3 / K
     value = b / (ms_per_step * 1e-3)
 
-    # ---- per-kernel durations: the same K steps again, with HIP events
-    # recorded on the solver's stream between the two kernels ----
+    # ---- per-kernel durations: the same K steps again, each kernel launched
+    # with a start/stop HIP event pair stamped by its own dispatch ----
     hip = hip_runtime()
-    nev = 3 * K
+    nev = 4 * K
     evs = [ctypes.c_void_p() for _ in range(nev)]
     for e in evs:
         assert hip.hipEventCreate(ctypes.byref(e)) == 0
@@ -229,14 +230,14 @@ def main():
     for t in range(K):
         s = t % R
         sg.sgep_step_profiled(solver.h, X[s], X[s].stride(0), Y[s], Y[s].stride(0), b,
-                              [evs[3 * t].value, evs[3 * t + 1].value, evs[3 * t + 2].value])
+                              [evs[4 * t + i].value for i in range(4)])
     torch.cuda.synchronize()
     ms = ctypes.c_float()
     fwd_us, bwd_us = [], []
     for t in range(K):
-        hip.hipEventElapsedTime(ctypes.byref(ms), evs[3 * t], evs[3 * t + 1])
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), evs[4 * t], evs[4 * t + 1]) == 0
         fwd_us.append(ms.value * 1e3)
-        hip.hipEventElapsedTime(ctypes.byref(ms), evs[3 * t + 1], evs[3 * t + 2])
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), evs[4 * t + 2], evs[4 * t + 3]) == 0
         bwd_us.append(ms.value * 1e3)
     for e in evs:
         hip.hipEventDestroy(e)

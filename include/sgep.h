@@ -136,11 +136,13 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
 sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y, int64_t ldy,
                       int64_t b);
 
-/* sgep_step with timing marks for measurement: records the caller's
- * hipEvent_t events[0] before the forward-product kernel, events[1] between
- * it and the backward-product/update kernel, and events[2] after it, all on
- * the handle's stream (create them with timing enabled).  Same semantics and
- * errors as sgep_step, plus SGEP_EINVAL if an event is NULL. */
+/* sgep_step with per-kernel timing: events[0] and events[1] receive the start
+ * and end of the forward-product kernel's execution, events[2] and events[3]
+ * those of the backward-product/update kernel (timestamps of the kernels'
+ * own dispatches, without launch gaps; the caller's hipEvent_t objects, created
+ * with timing enabled, read with hipEventElapsedTime).  Same semantics and
+ * errors as sgep_step, plus SGEP_EINVAL if an event is NULL.  Not for stream
+ * capture. */
 sgep_status sgep_step_profiled(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
                                int64_t ldy, int64_t b, void *const *events);
 

@@ -165,9 +165,9 @@ def sgep_step(h, X, ldx: int, Y, ldy: int, b: int) -> None:
 
 
 def sgep_step_profiled(h, X, ldx: int, Y, ldy: int, b: int, events) -> None:
-    """sgep_step recording three caller-owned hipEvent_t handles (ints):
-    before the forward kernel, between the kernels, after the update kernel."""
-    ev = (ctypes.c_void_p * 3)(*[int(e) for e in events])
+    """sgep_step with four caller-owned hipEvent_t handles (ints) stamped with
+    the start and end of the forward kernel, then of the backward/update kernel."""
+    ev = (ctypes.c_void_p * 4)(*[int(e) for e in events])
     _check(load().sgep_step_profiled(h, _ptr(X), ldx, _ptr(Y), ldy, b, ev), "sgep_step_profiled")
 
 

@@ -5,6 +5,7 @@
 // iteration (sgep_kernels.hpp) on the handle's stream.  sgep_step performs
 // no allocation, no synchronisation and no host copy, so it can be captured
 // in a hipGraph.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
@@ -158,46 +159,55 @@ sgep_status launch_init(sgep_handle *h)
     return SGEP_OK;
 }
 
-template <typename T, int KP, int MB>
-sgep_status launch_bwd(sgep_handle *h, const StepArgs &a)
+// One launch of a step kernel.  With timing events the launch goes through
+// hipExtLaunchKernelGGL, which stamps e0 / e1 with the start and end of the
+// kernel's own dispatch (no launch gaps), the same interval a kernel trace
+// reports.
+template <typename K>
+void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                  const StepArgs &a)
 {
-    const dim3 gb(h->n_tiles), blk(sgep::kNT);
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, grid, dim3(sgep::kNT), 0, s, e0, e1, 0, a);
+    else
+        hipLaunchKernelGGL(kernel, grid, dim3(sgep::kNT), 0, s, a);
+}
+
+template <typename T, int KP, int MB>
+void launch_bwd(sgep_handle *h, const StepArgs &a, hipEvent_t e0, hipEvent_t e1)
+{
+    const dim3 gb(h->n_tiles);
     const bool cca = h->cfg.kind == SGEP_KIND_CCA;
     const bool adam = h->cfg.optimizer == SGEP_ADAM;
     if (cca && !adam)
-        hipLaunchKernelGGL((sgep::k_bwd<T, KP, MB, sgep::kKindCCA, sgep::kOptSGD>), gb, blk, 0,
-                           h->stream, a);
+        launch_timed(sgep::k_bwd<T, KP, MB, sgep::kKindCCA, sgep::kOptSGD>, gb, h->stream, e0, e1, a);
     else if (cca && adam)
-        hipLaunchKernelGGL((sgep::k_bwd<T, KP, MB, sgep::kKindCCA, sgep::kOptAdam>), gb, blk, 0,
-                           h->stream, a);
+        launch_timed(sgep::k_bwd<T, KP, MB, sgep::kKindCCA, sgep::kOptAdam>, gb, h->stream, e0, e1, a);
     else if (!adam)
-        hipLaunchKernelGGL((sgep::k_bwd<T, KP, MB, sgep::kKindGeneral, sgep::kOptSGD>), gb, blk,
-                           0, h->stream, a);
+        launch_timed(sgep::k_bwd<T, KP, MB, sgep::kKindGeneral, sgep::kOptSGD>, gb, h->stream, e0, e1,
+                     a);
     else
-        hipLaunchKernelGGL((sgep::k_bwd<T, KP, MB, sgep::kKindGeneral, sgep::kOptAdam>), gb, blk,
-                           0, h->stream, a);
-    return SGEP_OK;
+        launch_timed(sgep::k_bwd<T, KP, MB, sgep::kKindGeneral, sgep::kOptAdam>, gb, h->stream, e0,
+                     e1, a);
 }
 
 template <typename T, int KP>
 sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
 {
-    const dim3 gf(a.n_fwd + 1), blk(sgep::kNT); // + the norm-totals workgroup
+    const dim3 gf(a.n_fwd + 1); // + the norm-totals workgroup
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     if (events)
-        HIPCHK(hipEventRecord((hipEvent_t)events[0], h->stream));
+        for (int i = 0; i < 4; ++i)
+            ev[i] = (hipEvent_t)events[i];
     if (h->cfg.kind == SGEP_KIND_CCA)
-        hipLaunchKernelGGL((sgep::k_fwd<T, KP, sgep::kKindCCA>), gf, blk, 0, h->stream, a);
+        launch_timed(sgep::k_fwd<T, KP, sgep::kKindCCA>, gf, h->stream, ev[0], ev[1], a);
     else
-        hipLaunchKernelGGL((sgep::k_fwd<T, KP, sgep::kKindGeneral>), gf, blk, 0, h->stream, a);
-    if (events)
-        HIPCHK(hipEventRecord((hipEvent_t)events[1], h->stream));
+        launch_timed(sgep::k_fwd<T, KP, sgep::kKindGeneral>, gf, h->stream, ev[0], ev[1], a);
     if (h->mb == 1)
-        launch_bwd<T, KP, 1>(h, a);
+        launch_bwd<T, KP, 1>(h, a, ev[2], ev[3]);
     else
-        launch_bwd<T, KP, mb_wide<T>(KP)>(h, a);
+        launch_bwd<T, KP, mb_wide<T>(KP)>(h, a, ev[2], ev[3]);
     HIPCHK(hipGetLastError());
-    if (events)
-        HIPCHK(hipEventRecord((hipEvent_t)events[2], h->stream));
     return SGEP_OK;
 }
 
@@ -447,7 +457,7 @@ sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
 sgep_status sgep_step_profiled(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
                                int64_t ldy, int64_t b, void *const *events)
 {
-    if (!events || !events[0] || !events[1] || !events[2])
+    if (!events || !events[0] || !events[1] || !events[2] || !events[3])
         return SGEP_EINVAL;
     return step_impl(h, X, ldx, Y, ldy, b, events);
 }

@@ -301,6 +301,42 @@ def test_hipgraph_replay_matches_eager():
     graphed.close()
 
 
+def test_profiled_step_matches_plain_and_times_kernels():
+    torch = _torch()
+    sg = _sg()
+    import bench
+    gen = synth.CCAPlanted(96, 64, np.linspace(0.9, 0.3, 4), sigma=0.3, seed=6)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 8, 96, 64, 256, eta0=0.2, gamma=0.5)
+    batches = [(_dev(X, torch.float32), _dev(Y, torch.float32))
+               for X, Y in _cca_batches(gen, 3, 256)]
+    V0 = synth.initial_players(160, 8, 2)
+    plain = sg.Solver(cfg, V0)
+    timed = sg.Solver(cfg, V0)
+    hip = bench.hip_runtime()
+    evs = [ctypes.c_void_p() for _ in range(4)]
+    for e in evs:
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+    for X, Y in batches:
+        plain.step(X, Y)
+        sg.sgep_step_profiled(timed.h, X, X.stride(0), Y, Y.stride(0), 256,
+                              [e.value for e in evs])
+    timed.sync()
+    assert np.array_equal(plain.vectors(), timed.vectors())
+    assert np.array_equal(plain.auxiliary(), timed.auxiliary())
+    ms = ctypes.c_float()
+    for a, b in ((0, 1), (2, 3)):
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), evs[a], evs[b]) == 0
+        assert 0.0 < ms.value < 100.0, ms.value
+    X, Y = batches[0]
+    with pytest.raises(sg.SgepError):
+        sg.sgep_step_profiled(timed.h, X, X.stride(0), Y, Y.stride(0), 256,
+                              [evs[0].value, evs[1].value, evs[2].value, 0])
+    for e in evs:
+        hip.hipEventDestroy(e)
+    plain.close()
+    timed.close()
+
+
 def test_step_argument_errors():
     torch = _torch()
     sg = _sg()
