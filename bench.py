@@ -229,7 +229,7 @@ def main():
     torch.cuda.synchronize()
     for t in range(K):
         s = t % R
-        sg.sgep_step_profiled(solver.h, X[s], X[s].stride(0), Y[s], Y[s].stride(0), b,
+        sg.sgep_step_profiled(solver.h, X[s], X[s].stride(0), Y[s], Y[s].stride(0), None, b,
                               [evs[4 * t + i].value for i in range(4)])
     torch.cuda.synchronize()
     ms = ctypes.c_float()

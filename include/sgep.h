@@ -13,7 +13,11 @@
  *   SGEP_KIND_CCA      paired views x (dx) and y (dy), d = dx + dy,
  *                      A = [[0, E xy^T], [E yx^T, 0]], B = diag(E xx^T, E yy^T)
  *   SGEP_KIND_GENERAL  two streams of width d: A = E[y y^T], B = E[x x^T] + eps I
- *   SGEP_KIND_LDA      (reserved; returns SGEP_EUNSUPPORTED in this version)
+ *   SGEP_KIND_LDA      labelled samples x (width d) of n_classes classes with
+ *                      given class means mu_c and priors pi_c:
+ *                      A = sum_c pi_c (mu_c - mu)(mu_c - mu)^T, mu = sum_c pi_c mu_c
+ *                      (between-class), B = E[(x - mu_l)(x - mu_l)^T] + eps I
+ *                      (within-class, l the sample's label)
  * Expectations are estimated by minibatch means (1/b) sum over the rows; the
  * data are taken as zero-mean (Sec. 1); no centring is applied.
  *
@@ -65,8 +69,9 @@ typedef int32_t sgep_status;
 /* element type of the minibatch views (and of the arithmetic) */
 #define SGEP_F64 0     /* FP64 data, FP64 MFMA, FP64 state */
 #define SGEP_F32 1     /* FP32 data, FP32 MFMA, FP32 state */
-#define SGEP_BF16 2    /* reserved */
-#define SGEP_FP8_E4M3 3 /* reserved */
+#define SGEP_BF16 2    /* BF16 data, BF16 MFMA with FP32 accumulation, FP32 state */
+#define SGEP_FP8_E4M3 3 /* OCP FP8 e4m3 codes with per-column FP32 scales (value =
+                         * code * scale), decoded exactly to BF16; as SGEP_BF16 */
 
 /* optimiser applied to the update direction (Alg. 2 uses plain ascent;
  * App. H uses Adam with b1 = 0.9, b2 = 0.999, eps = 1e-8) */
@@ -85,19 +90,22 @@ typedef int32_t sgep_status;
 
 typedef struct sgep_config {
     int32_t kind;      /* SGEP_KIND_* */
-    int32_t dtype;     /* SGEP_F64 or SGEP_F32 */
-    int32_t k;         /* number of players, 1 <= k <= 64 (F64: k <= 32) */
+    int32_t dtype;     /* SGEP_F64, SGEP_F32 (CCA, GENERAL); SGEP_BF16 (CCA, LDA);
+                        * SGEP_FP8_E4M3 (CCA) */
+    int32_t k;         /* number of players, 1 <= k <= 64 (F64, and CCA in BF16 or
+                        * FP8: k <= 32) */
     int32_t optimizer; /* SGEP_SGD or SGEP_ADAM */
     int32_t schedule;  /* SGEP_SCHED_* */
-    int32_t n_classes; /* LDA only; 0 otherwise */
-    int64_t dx;        /* CCA: width of view x. GENERAL: d */
-    int64_t dy;        /* CCA: width of view y. GENERAL: must equal dx */
+    int32_t n_classes; /* LDA: 2 .. 16 classes; 0 otherwise */
+    int64_t dx;        /* CCA: width of view x. GENERAL, LDA: d */
+    int64_t dy;        /* CCA: width of view y. GENERAL: must equal dx. LDA: 0.
+                        * BF16 and FP8: dx and dy multiples of 8 */
     int64_t b_max;     /* largest minibatch that sgep_step will receive */
     double eta0, eta_T, t0, t_c, T; /* schedule parameters (see above) */
     double gamma;      /* rate gamma_t (constant) of the auxiliary [Bv] update
                         * and of the Rayleigh-quotient running means, 0 < gamma <= 1 */
     double rho;        /* clip: <v_j, [Bv]_j> is replaced by max(., rho), rho >= 0 */
-    double eps_reg;    /* GENERAL: ridge, B = E[x x^T] + eps_reg I; CCA: must be 0 */
+    double eps_reg;    /* GENERAL, LDA: ridge, B = ... + eps_reg I; CCA: must be 0 */
     double adam_b1, adam_b2, adam_eps;
     uint64_t seed;     /* reserved (initial players are always supplied) */
 } sgep_config;
@@ -120,6 +128,25 @@ typedef struct sgep_handle_s sgep_handle;
 sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V0,
                       void *hip_stream);
 
+/* Problem data that some configurations need at initialisation; all host
+ * pointers, copied into handle-owned device memory (the caller keeps
+ * ownership).  Members a configuration does not use must be NULL. */
+typedef struct sgep_init_aux {
+    const float *x_col_scale;   /* FP8: dx positive finite scales of view x */
+    const float *y_col_scale;   /* FP8: dy positive finite scales of view y */
+    const double *class_means;  /* LDA: n_classes x d, row-major (row c = mu_c) */
+    const double *class_priors; /* LDA: n_classes positive weights pi_c */
+} sgep_init_aux;
+
+/* sgep_init for every configuration: aux may be NULL unless dtype is
+ * SGEP_FP8_E4M3 (column scales) or kind is SGEP_KIND_LDA (class means and
+ * priors).  The FP8 scales are fixed for the life of the handle, because the
+ * next iteration's product operand is prepared at the end of each step.
+ * Errors as sgep_init, plus SGEP_EINVAL for missing, extra or non-finite
+ * auxiliary data. */
+sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double *V0,
+                         const sgep_init_aux *aux, void *hip_stream);
+
 /* Enqueue one iteration of Alg. 2 on the minibatch (X, Y) of b rows.
  *   X   : device, b x dx row-major (element type cfg.dtype), leading dim ldx
  *   Y   : device, b x dy row-major, leading dim ldy
@@ -136,15 +163,30 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
 sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y, int64_t ldy,
                       int64_t b);
 
-/* sgep_step with per-kernel timing: events[0] and events[1] receive the start
- * and end of the forward-product kernel's execution, events[2] and events[3]
- * those of the backward-product/update kernel (timestamps of the kernels'
- * own dispatches, without launch gaps; the caller's hipEvent_t objects, created
- * with timing enabled, read with hipEventElapsedTime).  Same semantics and
- * errors as sgep_step, plus SGEP_EINVAL if an event is NULL.  Not for stream
- * capture. */
+/* LDA iteration: X is b x d row-major as in sgep_step, labels a device array
+ * of b int32 class indices in [0, n_classes).  A label outside that range
+ * poisons the handle (reported by the next synchronising call).  BF16 and
+ * FP8 views: 16-byte aligned, ldx a multiple of 8 elements. */
+sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int32_t *labels,
+                          int64_t b);
+
+/* Number of kernels one iteration launches: 2 for F64 / F32 (forward
+ * products; backward products and update), 3 for BF16 / FP8 (forward
+ * products; operand preparation and reductions; backward products and
+ * update). */
+sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n);
+
+/* One iteration (sgep_step, or sgep_step_lda when labels is non-NULL) with
+ * per-kernel timing: events[2 i] and events[2 i + 1] receive the start and end
+ * of the execution of kernel i of the iteration, in launch order (timestamps
+ * of the kernel's own dispatch, without launch gaps); n_events must be twice
+ * sgep_kernels_per_step.  The events are the caller's hipEvent_t objects,
+ * created with timing enabled and read with hipEventElapsedTime.  Errors as
+ * the plain step, plus SGEP_EINVAL for a NULL event or a wrong n_events.
+ * Not for stream capture. */
 sgep_status sgep_step_profiled(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
-                               int64_t ldy, int64_t b, void *const *events);
+                               int64_t ldy, const int32_t *labels, int64_t b,
+                               void *const *events, int32_t n_events);
 
 /* Wait for the handle's stream and report any latched device fault. */
 sgep_status sgep_sync(sgep_handle *h);

@@ -37,7 +37,8 @@ SGEP_SCHED_CONST, SGEP_SCHED_INV, SGEP_SCHED_WARMUP_HARMONIC = 0, 1, 2
 
 # every symbol include/sgep.h declares
 EXPORTS = (
-    "sgep_init", "sgep_step", "sgep_step_profiled", "sgep_sync", "sgep_eigvals", "sgep_vectors", "sgep_auxiliary",
+    "sgep_init", "sgep_init_ex", "sgep_step", "sgep_step_lda", "sgep_kernels_per_step",
+    "sgep_step_profiled", "sgep_sync", "sgep_eigvals", "sgep_vectors", "sgep_auxiliary",
     "sgep_step_count", "sgep_state_size", "sgep_get_state", "sgep_set_state", "sgep_destroy",
     "sgep_status_string", "sgep_version",
 )
@@ -67,6 +68,15 @@ def make_config(kind: int, dtype: int, k: int, dx: int, dy: int, b_max: int, *,
                        eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps, seed)
 
 
+class sgep_init_aux(ctypes.Structure):
+    _fields_ = [
+        ("x_col_scale", ctypes.POINTER(ctypes.c_float)),
+        ("y_col_scale", ctypes.POINTER(ctypes.c_float)),
+        ("class_means", ctypes.POINTER(ctypes.c_double)),
+        ("class_priors", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
 class SgepError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -94,8 +104,12 @@ def load() -> ctypes.CDLL:
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
     lib.sgep_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(sgep_config), dp, vp]
+    lib.sgep_init_ex.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(sgep_config), dp,
+                                 ctypes.POINTER(sgep_init_aux), vp]
     lib.sgep_step.argtypes = [vp, vp, i64, vp, i64, i64]
-    lib.sgep_step_profiled.argtypes = [vp, vp, i64, vp, i64, i64, ctypes.POINTER(vp)]
+    lib.sgep_step_lda.argtypes = [vp, vp, i64, vp, i64]
+    lib.sgep_kernels_per_step.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.sgep_step_profiled.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.POINTER(vp), i32]
     lib.sgep_sync.argtypes = [vp]
     lib.sgep_eigvals.argtypes = [vp, dp]
     lib.sgep_vectors.argtypes = [vp, i32, dp]
@@ -159,16 +173,60 @@ def sgep_init(cfg: sgep_config, V0: np.ndarray, stream=None) -> ctypes.c_void_p:
     return h
 
 
+def sgep_init_ex(cfg: sgep_config, V0: np.ndarray, stream=None, *, x_col_scale=None,
+                 y_col_scale=None, class_means=None, class_priors=None) -> ctypes.c_void_p:
+    """Create a solver with the problem data FP8 (column scales) or LDA (class
+    means, n_classes x d, and priors) configurations need; host numpy arrays."""
+    lib = load()
+    V0c = np.ascontiguousarray(np.asarray(V0, dtype=np.float64).T)
+    keep = []
+
+    def f32p(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+    def f64p(a):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    aux = sgep_init_aux(f32p(x_col_scale), f32p(y_col_scale), f64p(class_means),
+                        f64p(class_priors))
+    h = ctypes.c_void_p()
+    rc = lib.sgep_init_ex(ctypes.byref(h), ctypes.byref(cfg),
+                          V0c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                          ctypes.byref(aux), _stream(stream))
+    _check(rc, "sgep_init_ex")
+    return h
+
+
 def sgep_step(h, X, ldx: int, Y, ldy: int, b: int) -> None:
     """Enqueue one iteration on the minibatch views X (b x dx) and Y (b x dy)."""
     _check(load().sgep_step(h, _ptr(X), ldx, _ptr(Y), ldy, b), "sgep_step")
 
 
-def sgep_step_profiled(h, X, ldx: int, Y, ldy: int, b: int, events) -> None:
-    """sgep_step with four caller-owned hipEvent_t handles (ints) stamped with
-    the start and end of the forward kernel, then of the backward/update kernel."""
-    ev = (ctypes.c_void_p * 4)(*[int(e) for e in events])
-    _check(load().sgep_step_profiled(h, _ptr(X), ldx, _ptr(Y), ldy, b, ev), "sgep_step_profiled")
+def sgep_step_lda(h, X, ldx: int, labels, b: int) -> None:
+    """Enqueue one LDA iteration on X (b x d) with int32 device labels (b)."""
+    _check(load().sgep_step_lda(h, _ptr(X), ldx, _ptr(labels), b), "sgep_step_lda")
+
+
+def sgep_kernels_per_step(h) -> int:
+    n = ctypes.c_int32()
+    _check(load().sgep_kernels_per_step(h, ctypes.byref(n)), "sgep_kernels_per_step")
+    return int(n.value)
+
+
+def sgep_step_profiled(h, X, ldx: int, Y, ldy: int, labels, b: int, events) -> None:
+    """One iteration with caller-owned hipEvent_t handles (ints), a start/end
+    pair per kernel in launch order (2 * sgep_kernels_per_step of them)."""
+    ev = (ctypes.c_void_p * len(events))(*[int(e) for e in events])
+    _check(load().sgep_step_profiled(h, _ptr(X), ldx, _ptr(Y), ldy, _ptr(labels), b, ev,
+                                     len(events)), "sgep_step_profiled")
 
 
 def sgep_sync(h) -> None:
@@ -228,18 +286,25 @@ def sgep_destroy(h) -> None:
 class Solver:
     """Owning convenience wrapper around one handle (same calls, fewer args)."""
 
-    def __init__(self, cfg: sgep_config, V0: np.ndarray, stream=None):
+    def __init__(self, cfg: sgep_config, V0: np.ndarray, stream=None, **aux):
         self.cfg = cfg
         self.d = cfg.dx + cfg.dy if cfg.kind == SGEP_KIND_CCA else cfg.dx
         self.k = cfg.k
-        self.h = sgep_init(cfg, V0, stream)
+        self.h = sgep_init_ex(cfg, V0, stream, **aux) if aux else sgep_init(cfg, V0, stream)
 
     def step(self, X, Y, b: Optional[int] = None, ldx: Optional[int] = None,
              ldy: Optional[int] = None):
+        """One iteration; for LDA, Y is the int32 label vector."""
         b = X.shape[0] if b is None else b
         ldx = X.stride(0) if ldx is None else ldx
+        if self.cfg.kind == SGEP_KIND_LDA:
+            sgep_step_lda(self.h, X, ldx, Y, b)
+            return
         ldy = Y.stride(0) if ldy is None else ldy
         sgep_step(self.h, X, ldx, Y, ldy, b)
+
+    def kernels_per_step(self):
+        return sgep_kernels_per_step(self.h)
 
     def sync(self):
         sgep_sync(self.h)

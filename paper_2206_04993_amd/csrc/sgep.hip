@@ -12,14 +12,17 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
 #include <new>
 #include <vector>
 
 #include "../../include/sgep.h"
 #include "sgep_kernels.hpp"
+#include "sgep_wide.hpp"
 
 using sgep::Coef;
 using sgep::StepArgs;
+using sgep::wide::WideArgs;
 
 namespace {
 
@@ -55,6 +58,12 @@ struct sgep_handle_s {
     int64_t ldp = 0;        // player row length of P^T, Q^T
     int64_t fwd_blocks_max = 0;
     bool poisoned = false;
+    // BF16 / FP8 path (sgep_wide.hpp): argument block with every field that
+    // does not change between iterations, and its extra buffers
+    bool wide = false;
+    WideArgs wa;
+    void *Vh = nullptr, *Vl = nullptr, *colscale = nullptr, *Ppart = nullptr;
+    void *Wh = nullptr, *Wl = nullptr, *Mcls = nullptr, *Mbar = nullptr, *prior = nullptr;
 };
 
 namespace {
@@ -91,8 +100,9 @@ constexpr int64_t kWideD = 8192;
 
 void free_all(sgep_handle *h)
 {
-    void *ptrs[] = {h->V, h->G, h->Am, h->As, h->P, h->Q, h->gram_part, h->stat_part,
-                    h->stat_tot, h->readout, h->coef};
+    void *ptrs[] = {h->V,  h->G,        h->Am,      h->As,    h->P,  h->Q,    h->gram_part,
+                    h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
+                    h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -102,23 +112,34 @@ sgep_status check_cfg(const sgep_config *c)
 {
     if (!c)
         return SGEP_EINVAL;
-    if (c->kind == SGEP_KIND_LDA)
-        return SGEP_EUNSUPPORTED;
-    if (c->kind != SGEP_KIND_CCA && c->kind != SGEP_KIND_GENERAL)
+    if (c->kind != SGEP_KIND_CCA && c->kind != SGEP_KIND_GENERAL && c->kind != SGEP_KIND_LDA)
         return SGEP_EINVAL;
-    if (c->dtype == SGEP_BF16 || c->dtype == SGEP_FP8_E4M3)
-        return SGEP_EUNSUPPORTED;
-    if (c->dtype != SGEP_F64 && c->dtype != SGEP_F32)
+    if (c->dtype < SGEP_F64 || c->dtype > SGEP_FP8_E4M3)
         return SGEP_EINVAL;
-    if (c->k < 1 || c->k > 64 || (c->dtype == SGEP_F64 && c->k > 32))
-        return c->k < 1 ? SGEP_EINVAL : SGEP_EUNSUPPORTED;
+    const bool narrow = c->dtype == SGEP_BF16 || c->dtype == SGEP_FP8_E4M3;
+    const bool lda = c->kind == SGEP_KIND_LDA;
+    // LDA runs on the BF16 path only; GENERAL on the F64 / F32 path only
+    if ((lda && c->dtype != SGEP_BF16) || (narrow && c->kind == SGEP_KIND_GENERAL))
+        return SGEP_EUNSUPPORTED;
+    if (c->k < 1)
+        return SGEP_EINVAL;
+    if (c->k > 64 || ((c->dtype == SGEP_F64 || (narrow && !lda)) && c->k > 32))
+        return SGEP_EUNSUPPORTED;
     if (c->optimizer != SGEP_SGD && c->optimizer != SGEP_ADAM)
         return SGEP_EINVAL;
     if (c->schedule < SGEP_SCHED_CONST || c->schedule > SGEP_SCHED_WARMUP_HARMONIC)
         return SGEP_EINVAL;
-    if (c->dx < 1 || c->dy < 1 || c->b_max < 1)
+    if (lda) {
+        if (c->n_classes < 2 || c->n_classes > sgep::wide::kMaxCls)
+            return SGEP_EINVAL;
+        if (c->dx < 1 || c->dy != 0 || c->b_max < 1)
+            return SGEP_ESHAPE;
+    } else if (c->dx < 1 || c->dy < 1 || c->b_max < 1) {
         return SGEP_ESHAPE;
+    }
     if (c->kind == SGEP_KIND_GENERAL && c->dx != c->dy)
+        return SGEP_ESHAPE;
+    if (narrow && (c->dx % 8 != 0 || c->dy % 8 != 0))
         return SGEP_ESHAPE;
     const int64_t d = c->kind == SGEP_KIND_CCA ? c->dx + c->dy : c->dx;
     if (c->k > d)
@@ -222,6 +243,86 @@ sgep_status launch_readout(sgep_handle *h, const void *S, int mode)
     return SGEP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// BF16 / FP8 path
+// ---------------------------------------------------------------------------
+template <typename K, typename... Args>
+void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+              Args... args)
+{
+    if (e0)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
+int wide_stat_blocks(const WideArgs &a)
+{
+    return (a.Ws + sgep::wide::kStatCols - 1) / sgep::wide::kStatCols;
+}
+
+template <int KP, int IN, int KIND>
+sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
+{
+    using namespace sgep::wide;
+    const dim3 blk(kWT);
+    const bool adam = h->cfg.optimizer == SGEP_ADAM;
+    launch_k(k_wfwd<KP, IN>, dim3(a.n_rb * a.nview * a.n_split), blk, h->stream, ev[0], ev[1], a);
+    launch_k(k_wmid<KP, KIND>, dim3(a.nA + wide_stat_blocks(a)), blk, h->stream, ev[2], ev[3], a, 0);
+    if (adam)
+        launch_k(k_wbwd<KP, IN, KIND, sgep::kOptAdam>, dim3(a.nwg), blk, h->stream, ev[4], ev[5], a);
+    else
+        launch_k(k_wbwd<KP, IN, KIND, sgep::kOptSGD>, dim3(a.nwg), blk, h->stream, ev[4], ev[5], a);
+    HIPCHK(hipGetLastError());
+    return SGEP_OK;
+}
+
+template <int KP, int IN, int KIND>
+sgep_status wide_init_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *)
+{
+    hipLaunchKernelGGL((sgep::wide::k_winit<KP, IN, KIND>), dim3(a.nwg), dim3(sgep::wide::kWT), 0,
+                       h->stream, a);
+    HIPCHK(hipGetLastError());
+    return SGEP_OK;
+}
+
+// reduce the latest statistics, then scale the state rows into h->readout
+template <int KP, int IN, int KIND>
+sgep_status wide_readout_t(sgep_handle *h, const WideArgs &a, const void *S, int mode)
+{
+    using namespace sgep::wide;
+    hipLaunchKernelGGL((k_wmid<KP, KIND>), dim3(wide_stat_blocks(a)), dim3(kWT), 0, h->stream, a,
+                       1);
+    const int64_t n = h->d * (int64_t)h->cfg.k;
+    int64_t nb = (n + 255) / 256;
+    if (nb > 1024)
+        nb = 1024;
+    const int64_t dx = h->cfg.kind == SGEP_KIND_CCA ? h->cfg.dx : h->d;
+    hipLaunchKernelGGL((k_wreadout<KP>), dim3((unsigned)nb), dim3(256), 0, h->stream,
+                       (const float *)S, (const double *)a.stot, h->d, dx, a.off[1], h->cfg.k,
+                       h->cfg.rho, h->coef, mode, h->readout);
+    HIPCHK(hipGetLastError());
+    return SGEP_OK;
+}
+
+// dispatch on (input format, kind, KP) for the BF16 / FP8 path
+#define WIDE_DISPATCH(h, FN, ...)                                                          \
+    ([&]() -> sgep_status {                                                                \
+        using namespace sgep::wide;                                                        \
+        if ((h)->cfg.kind == SGEP_KIND_LDA) {                                              \
+            if ((h)->kp == 16) return FN<16, kInBF16, kKindLDA>(__VA_ARGS__);              \
+            if ((h)->kp == 32) return FN<32, kInBF16, kKindLDA>(__VA_ARGS__);              \
+            if ((h)->kp == 64) return FN<64, kInBF16, kKindLDA>(__VA_ARGS__);              \
+        } else if ((h)->cfg.dtype == SGEP_FP8_E4M3) {                                      \
+            if ((h)->kp == 16) return FN<16, kInFP8, sgep::kKindCCA>(__VA_ARGS__);         \
+            if ((h)->kp == 32) return FN<32, kInFP8, sgep::kKindCCA>(__VA_ARGS__);         \
+        } else {                                                                           \
+            if ((h)->kp == 16) return FN<16, kInBF16, sgep::kKindCCA>(__VA_ARGS__);        \
+            if ((h)->kp == 32) return FN<32, kInBF16, sgep::kKindCCA>(__VA_ARGS__);        \
+        }                                                                                  \
+        return SGEP_EUNSUPPORTED;                                                          \
+    }())
+
 // dispatch on (dtype, KP)
 #define SGEP_DISPATCH(h, FN, ...)                                                          \
     ([&]() -> sgep_status {                                                                \
@@ -248,11 +349,283 @@ sgep_status latch_status(sgep_handle *h)
     return SGEP_OK;
 }
 
+sgep_status check_aux(const sgep_config *c, const sgep_init_aux *aux)
+{
+    const bool fp8 = c->dtype == SGEP_FP8_E4M3, lda = c->kind == SGEP_KIND_LDA;
+    const bool has_scale = aux && (aux->x_col_scale || aux->y_col_scale);
+    const bool has_cls = aux && (aux->class_means || aux->class_priors);
+    if (has_scale != fp8 || has_cls != lda)
+        return SGEP_EINVAL;
+    if (fp8) {
+        if (!aux->x_col_scale || !aux->y_col_scale)
+            return SGEP_EINVAL;
+        for (int64_t f = 0; f < c->dx; ++f)
+            if (!(aux->x_col_scale[f] > 0.f) || !std::isfinite(aux->x_col_scale[f]))
+                return SGEP_EINVAL;
+        for (int64_t f = 0; f < c->dy; ++f)
+            if (!(aux->y_col_scale[f] > 0.f) || !std::isfinite(aux->y_col_scale[f]))
+                return SGEP_EINVAL;
+    }
+    if (lda) {
+        if (!aux->class_means || !aux->class_priors)
+            return SGEP_EINVAL;
+        for (int cc = 0; cc < c->n_classes; ++cc)
+            if (!(aux->class_priors[cc] > 0.0) || !std::isfinite(aux->class_priors[cc]))
+                return SGEP_EINVAL;
+        for (int64_t e = 0; e < (int64_t)c->n_classes * c->dx; ++e)
+            if (!std::isfinite(aux->class_means[e]))
+                return SGEP_EINVAL;
+    }
+    return SGEP_OK;
+}
+
+// Set up the BF16 / FP8 path: launch geometry, buffers, starting state (unit
+// columns of V0, normalised here in FP64; [Bv] = V, the BF16 operand and the
+// first statistics are written by k_winit).
+sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux)
+{
+    using namespace sgep::wide;
+    const sgep_config &c = h->cfg;
+    const bool lda = c.kind == SGEP_KIND_LDA, fp8 = c.dtype == SGEP_FP8_E4M3;
+    const int64_t KP = h->kp, d = h->d;
+    auto r64 = [](int64_t x) { return (x + 63) / 64 * 64; };
+    WideArgs &a = h->wa;
+    memset(&a, 0, sizeof(a));
+    h->esz = fp8 ? 1 : 2; // element size of the minibatch (checkpoint header)
+    a.nview = lda ? 1 : 2;
+    a.dv[0] = c.dx;
+    a.dv[1] = lda ? 0 : c.dy;
+    a.off[0] = 0;
+    a.off[1] = r64(c.dx);
+    a.dtot = lda ? r64(c.dx) : r64(c.dx) + r64(c.dy);
+    a.k = c.k;
+    a.ncls = lda ? c.n_classes : 0;
+    a.ldr = r64(c.b_max);
+    // forward: aim at >= 512 workgroups at b_max, each wave >= one 64-feature step
+    const int64_t nrb = a.ldr / kRB;
+    const int64_t dvmax = a.dv[0] > a.dv[1] ? a.dv[0] : a.dv[1];
+    const int64_t nf64 = (dvmax + 63) / 64;
+    int64_t ns = (512 + nrb * a.nview - 1) / (nrb * a.nview);
+    const int64_t ns_max = (nf64 + kNW - 1) / kNW;
+    if (ns > ns_max)
+        ns = ns_max;
+    if (ns < 1)
+        ns = 1;
+    a.fw = 64 * ((nf64 + kNW * ns - 1) / (kNW * ns));
+    a.fs = kNW * a.fw;
+    a.n_split = (int32_t)((dvmax + a.fs - 1) / a.fs);
+    // backward: 64-feature subtiles, about 256 workgroups
+    a.nsubv[0] = (int32_t)((a.dv[0] + kFT - 1) / kFT);
+    a.nsubv[1] = (int32_t)((a.dv[1] + kFT - 1) / kFT);
+    const int nsubt = a.nsubv[0] + a.nsubv[1];
+    a.nsub = nsubt / 256 > 1 ? nsubt / 256 : 1;
+    a.nwg0 = (a.nsubv[0] + a.nsub - 1) / a.nsub;
+    a.nwg = a.nwg0 + (a.nsubv[1] + a.nsub - 1) / a.nsub;
+    a.lds = (a.nwg + 1) / 2 * 2;
+    a.Ws = (int32_t)(KP * (KP + 1) / 2 + KP + (lda ? a.ncls * KP : 0));
+    const int64_t MW = lda ? KP + 16 : 2 * KP;
+
+    bool ok = true;
+    auto alloc = [&](void **p, size_t n) {
+        if (ok && hipMalloc(p, n < 256 ? 256 : n) != hipSuccess) {
+            *p = nullptr;
+            ok = false;
+        }
+    };
+    const size_t st = (size_t)a.dtot * KP * sizeof(float);
+    const size_t op = (size_t)KP * a.dtot * sizeof(uint16_t);
+    const size_t wbytes = (size_t)MW * a.ldr * sizeof(uint16_t);
+    const size_t spb = (size_t)a.Ws * a.lds * sizeof(double);
+    alloc(&h->V, st);
+    alloc(&h->G, st);
+    if (c.optimizer == SGEP_ADAM) {
+        alloc(&h->Am, st);
+        alloc(&h->As, st);
+    }
+    alloc(&h->Vh, op);
+    alloc(&h->Vl, op);
+    if (fp8)
+        alloc(&h->colscale, (size_t)a.dtot * sizeof(float));
+    alloc(&h->Ppart, (size_t)a.n_split * a.nview * a.ldr * KP * sizeof(float));
+    alloc(&h->Wh, wbytes);
+    alloc(&h->Wl, wbytes);
+    if (lda) {
+        alloc(&h->Mcls, (size_t)a.ncls * a.dtot * sizeof(float));
+        alloc(&h->Mbar, (size_t)a.dtot * sizeof(float));
+        alloc(&h->prior, (size_t)a.ncls * sizeof(double));
+    }
+    alloc((void **)&h->stat_part, spb);
+    alloc((void **)&h->stat_tot, (size_t)a.Ws * sizeof(double));
+    alloc((void **)&h->readout, (size_t)d * c.k * sizeof(double));
+    alloc((void **)&h->coef, sizeof(Coef));
+    if (!ok)
+        return SGEP_ENOMEM;
+    a.V = (float *)h->V;
+    a.G = (float *)h->G;
+    a.Am = (float *)h->Am;
+    a.As = (float *)h->As;
+    a.Vh = (uint16_t *)h->Vh;
+    a.Vl = (uint16_t *)h->Vl;
+    a.colscale = (const float *)h->colscale;
+    a.Ppart = (float *)h->Ppart;
+    a.Wh = (uint16_t *)h->Wh;
+    a.Wl = (uint16_t *)h->Wl;
+    a.M = (const float *)h->Mcls;
+    a.Mbar = (const float *)h->Mbar;
+    a.prior = (const double *)h->prior;
+    a.spart = h->stat_part;
+    a.stot = h->stat_tot;
+    a.coef = h->coef;
+    a.schedule = c.schedule;
+    a.eta0 = c.eta0;
+    a.eta_T = c.eta_T;
+    a.t0 = c.t0;
+    a.t_c = c.t_c;
+    a.T = c.T;
+    a.gamma = c.gamma;
+    a.rho = c.rho;
+    a.eps_reg = c.eps_reg;
+    a.adam_b1 = c.adam_b1;
+    a.adam_b2 = c.adam_b2;
+    a.adam_eps = c.adam_eps;
+
+    // starting players: unit columns (FP64 norms), FP32, state rows of the views
+    auto row_of = [&](int64_t f) { return f < c.dx ? f : a.off[1] + (f - c.dx); };
+    std::vector<float> hv((size_t)a.dtot * KP, 0.f);
+    for (int i = 0; i < c.k; ++i) {
+        double n2 = 0.0;
+        for (int64_t f = 0; f < d; ++f)
+            n2 += V0[(size_t)i * d + f] * V0[(size_t)i * d + f];
+        if (!(n2 > 0.0) || !std::isfinite(n2))
+            return SGEP_EINVAL; // zero or non-finite starting column
+        const double inv = 1.0 / sqrt(n2);
+        for (int64_t f = 0; f < d; ++f)
+            hv[(size_t)row_of(f) * KP + i] = (float)(V0[(size_t)i * d + f] * inv);
+    }
+    std::vector<float> hs, hm, hmb;
+    std::vector<double> hp;
+    bool hok = hipMemsetAsync(h->coef, 0, sizeof(Coef), h->stream) == hipSuccess &&
+               hipMemsetAsync(h->stat_part, 0, spb, h->stream) == hipSuccess &&
+               hipMemsetAsync(h->Vh, 0, op, h->stream) == hipSuccess &&
+               hipMemsetAsync(h->Vl, 0, op, h->stream) == hipSuccess &&
+               hipMemsetAsync(h->Wh, 0, wbytes, h->stream) == hipSuccess &&
+               hipMemsetAsync(h->Wl, 0, wbytes, h->stream) == hipSuccess &&
+               hipMemcpyAsync(h->V, hv.data(), st, hipMemcpyHostToDevice, h->stream) == hipSuccess;
+    if (h->Am)
+        hok = hok && hipMemsetAsync(h->Am, 0, st, h->stream) == hipSuccess &&
+              hipMemsetAsync(h->As, 0, st, h->stream) == hipSuccess;
+    if (fp8) {
+        hs.assign((size_t)a.dtot, 0.f);
+        for (int64_t f = 0; f < d; ++f)
+            hs[(size_t)row_of(f)] = f < c.dx ? aux->x_col_scale[f] : aux->y_col_scale[f - c.dx];
+        hok = hok && hipMemcpyAsync(h->colscale, hs.data(), hs.size() * sizeof(float),
+                                    hipMemcpyHostToDevice, h->stream) == hipSuccess;
+    }
+    if (lda) {
+        hm.assign((size_t)a.ncls * a.dtot, 0.f);
+        hmb.assign((size_t)a.dtot, 0.f);
+        hp.assign(aux->class_priors, aux->class_priors + a.ncls);
+        for (int64_t f = 0; f < d; ++f) {
+            double mb = 0.0;
+            for (int cc = 0; cc < a.ncls; ++cc) {
+                const double m = aux->class_means[(size_t)cc * d + f];
+                hm[(size_t)cc * a.dtot + f] = (float)m;
+                mb += hp[cc] * m;
+            }
+            hmb[(size_t)f] = (float)mb;
+        }
+        hok = hok &&
+              hipMemcpyAsync(h->Mcls, hm.data(), hm.size() * sizeof(float), hipMemcpyHostToDevice,
+                             h->stream) == hipSuccess &&
+              hipMemcpyAsync(h->Mbar, hmb.data(), hmb.size() * sizeof(float),
+                             hipMemcpyHostToDevice, h->stream) == hipSuccess &&
+              hipMemcpyAsync(h->prior, hp.data(), hp.size() * sizeof(double), hipMemcpyHostToDevice,
+                             h->stream) == hipSuccess;
+    }
+    if (!hok)
+        return SGEP_EDEVICE;
+    sgep_status rc = WIDE_DISPATCH(h, wide_init_t, h, a, nullptr);
+    if (rc != SGEP_OK)
+        return rc;
+    // waits for the uploads from the host vectors above
+    if (hipStreamSynchronize(h->stream) != hipSuccess)
+        return SGEP_EDEVICE;
+    return SGEP_OK;
+}
+
+sgep_status step_wide(sgep_handle *h, const void *X, int64_t ldx, const void *Y, int64_t ldy,
+                      const int32_t *labels, int64_t b, void *const *events)
+{
+    const sgep_config &c = h->cfg;
+    const bool lda = c.kind == SGEP_KIND_LDA;
+    if (!X || (lda ? !labels : (!Y || labels != nullptr)))
+        return SGEP_EINVAL;
+    if (b < 1 || b > c.b_max)
+        return SGEP_ESHAPE;
+    if (ldx < c.dx || ldx % 8 != 0 || ((uintptr_t)X & 15u) != 0)
+        return SGEP_ESHAPE;
+    if (!lda && (ldy < c.dy || ldy % 8 != 0 || ((uintptr_t)Y & 15u) != 0))
+        return SGEP_ESHAPE;
+    WideArgs a = h->wa;
+    a.X = X;
+    a.Y = lda ? nullptr : Y;
+    a.labels = labels;
+    a.ldx = ldx;
+    a.ldy = lda ? 0 : ldy;
+    a.b = b;
+    a.n_rb = (int32_t)((b + sgep::wide::kRB - 1) / sgep::wide::kRB);
+    a.nA = 4 * a.n_rb;
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (events)
+        for (int i = 0; i < 6; ++i)
+            ev[i] = (hipEvent_t)events[i];
+    return WIDE_DISPATCH(h, wide_step_t, h, a, ev);
+}
+
+// device arrays of a checkpoint after the header and the coefficient block
+struct StateLayout {
+    int n = 0;
+    void *ptr[8];
+    size_t bytes[8];
+    void add(void *p, size_t b)
+    {
+        if (p) {
+            ptr[n] = p;
+            bytes[n] = b;
+            ++n;
+        }
+    }
+};
+
+StateLayout state_layout(const sgep_handle *h)
+{
+    StateLayout L;
+    if (h->wide) {
+        const size_t st = (size_t)h->wa.dtot * h->kp * sizeof(float);
+        const size_t op = (size_t)h->kp * h->wa.dtot * sizeof(uint16_t);
+        L.add(h->V, st);
+        L.add(h->G, st);
+        L.add(h->Am, st);
+        L.add(h->As, st);
+        L.add(h->Vh, op);
+        L.add(h->Vl, op);
+        L.add(h->stat_part, (size_t)h->wa.Ws * h->wa.lds * sizeof(double));
+    } else {
+        const size_t st = (size_t)h->ldv * h->kp * h->esz;
+        L.add(h->V, st);
+        L.add(h->G, st);
+        L.add(h->Am, st);
+        L.add(h->As, st);
+        L.add(h->stat_part, (size_t)h->W * h->lds * sizeof(double));
+    }
+    return L;
+}
+
 } // namespace
 
 extern "C" {
 
-int32_t sgep_version(void) { return 100; }
+int32_t sgep_version(void) { return 110; }
 
 const char *sgep_status_string(sgep_status s)
 {
@@ -271,6 +644,12 @@ const char *sgep_status_string(sgep_status s)
 
 sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V0, void *hip_stream)
 {
+    return sgep_init_ex(out, cfg, V0, nullptr, hip_stream);
+}
+
+sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double *V0,
+                         const sgep_init_aux *aux, void *hip_stream)
+{
     if (!out)
         return SGEP_EINVAL;
     *out = nullptr;
@@ -279,6 +658,9 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
         return rc;
     if (!V0)
         return SGEP_EINVAL;
+    rc = check_aux(cfg, aux);
+    if (rc != SGEP_OK)
+        return rc;
     sgep_handle *h = new (std::nothrow) sgep_handle_s();
     if (!h)
         return SGEP_ENOMEM;
@@ -286,6 +668,21 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
     h->stream = (hipStream_t)hip_stream;
     h->d = cfg->kind == SGEP_KIND_CCA ? cfg->dx + cfg->dy : cfg->dx;
     h->kp = cfg->k <= 16 ? 16 : (cfg->k <= 32 ? 32 : 64);
+    if (cfg->dtype == SGEP_BF16 || cfg->dtype == SGEP_FP8_E4M3) {
+        h->wide = true;
+        if (hipGetDevice(&h->device) != hipSuccess) {
+            delete h;
+            return SGEP_EDEVICE;
+        }
+        rc = init_wide(h, V0, aux);
+        if (rc != SGEP_OK) {
+            free_all(h);
+            delete h;
+            return rc;
+        }
+        *out = h;
+        return SGEP_OK;
+    }
     h->esz = cfg->dtype == SGEP_F64 ? sizeof(double) : sizeof(float);
     const bool wide = h->d >= kWideD;
     h->mb = !wide ? 1 : (cfg->dtype == SGEP_F64 ? mb_wide<double>(h->kp) : mb_wide<float>(h->kp));
@@ -386,13 +783,15 @@ sgep_status sgep_init(sgep_handle **out, const sgep_config *cfg, const double *V
 }
 
 static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
-                             int64_t ldy, int64_t b, void *const *events)
+                             int64_t ldy, const int32_t *labels, int64_t b, void *const *events)
 {
     if (!h)
         return SGEP_EINVAL;
     if (h->poisoned)
         return SGEP_EPOISONED;
-    if (!X || !Y)
+    if (h->wide)
+        return step_wide(h, X, ldx, Y, ldy, labels, b, events);
+    if (!X || !Y || labels)
         return SGEP_EINVAL;
     if (b < 1 || b > h->cfg.b_max)
         return SGEP_ESHAPE;
@@ -451,15 +850,42 @@ static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const v
 sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y, int64_t ldy,
                       int64_t b)
 {
-    return step_impl(h, X, ldx, Y, ldy, b, nullptr);
+    if (h && h->cfg.kind == SGEP_KIND_LDA)
+        return SGEP_EINVAL; // labelled data: sgep_step_lda
+    return step_impl(h, X, ldx, Y, ldy, nullptr, b, nullptr);
+}
+
+sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int32_t *labels,
+                          int64_t b)
+{
+    if (!h || h->cfg.kind != SGEP_KIND_LDA)
+        return SGEP_EINVAL;
+    return step_impl(h, X, ldx, nullptr, 0, labels, b, nullptr);
+}
+
+sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n)
+{
+    if (!h || !n)
+        return SGEP_EINVAL;
+    *n = h->wide ? 3 : 2;
+    return SGEP_OK;
 }
 
 sgep_status sgep_step_profiled(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
-                               int64_t ldy, int64_t b, void *const *events)
+                               int64_t ldy, const int32_t *labels, int64_t b,
+                               void *const *events, int32_t n_events)
 {
-    if (!events || !events[0] || !events[1] || !events[2] || !events[3])
+    if (!h || !events)
         return SGEP_EINVAL;
-    return step_impl(h, X, ldx, Y, ldy, b, events);
+    const int32_t need = h->wide ? 6 : 4;
+    if (n_events != need)
+        return SGEP_EINVAL;
+    for (int i = 0; i < need; ++i)
+        if (!events[i])
+            return SGEP_EINVAL;
+    if ((h->cfg.kind == SGEP_KIND_LDA) != (labels != nullptr))
+        return SGEP_EINVAL;
+    return step_impl(h, X, ldx, Y, ldy, labels, b, events);
 }
 
 sgep_status sgep_sync(sgep_handle *h)
@@ -497,7 +923,10 @@ static sgep_status readout(sgep_handle *h, const void *S, int mode, double *out)
     sgep_status rc = latch_status(h);
     if (rc != SGEP_OK)
         return rc;
-    rc = SGEP_DISPATCH(h, launch_readout, h, S, mode);
+    if (h->wide)
+        rc = WIDE_DISPATCH(h, wide_readout_t, h, h->wa, S, mode);
+    else
+        rc = SGEP_DISPATCH(h, launch_readout, h, S, mode);
     if (rc != SGEP_OK)
         return rc;
     HIPCHK(hipMemcpyAsync(out, h->readout, (size_t)h->d * h->cfg.k * sizeof(double),
@@ -537,6 +966,13 @@ sgep_status sgep_state_size(const sgep_handle *h, size_t *bytes)
 {
     if (!h || !bytes)
         return SGEP_EINVAL;
+    if (h->wide) {
+        const size_t st = (size_t)h->wa.dtot * h->kp * sizeof(float);
+        const size_t op = (size_t)h->kp * h->wa.dtot * sizeof(uint16_t);
+        *bytes = sizeof(StateHeader) + sizeof(Coef) + st * (h->Am ? 4 : 2) + 2 * op +
+                 (size_t)h->wa.Ws * h->wa.lds * sizeof(double);
+        return SGEP_OK;
+    }
     const size_t st = (size_t)h->ldv * h->kp * h->esz;
     *bytes = sizeof(StateHeader) + sizeof(Coef) + st * (h->Am ? 4 : 2) +
              (size_t)h->W * h->lds * sizeof(double);
@@ -561,18 +997,13 @@ sgep_status sgep_get_state(sgep_handle *h, void *host_buf, size_t bytes)
     unsigned char *p = (unsigned char *)host_buf;
     memcpy(p, &hd, sizeof(hd));
     p += sizeof(hd);
-    const size_t st = (size_t)h->ldv * h->kp * h->esz;
     HIPCHK(hipMemcpyAsync(p, h->coef, sizeof(Coef), hipMemcpyDeviceToHost, h->stream));
     p += sizeof(Coef);
-    void *arrs[] = {h->V, h->G, h->Am, h->As};
-    for (void *a : arrs) {
-        if (!a)
-            continue;
-        HIPCHK(hipMemcpyAsync(p, a, st, hipMemcpyDeviceToHost, h->stream));
-        p += st;
+    StateLayout L = state_layout(h);
+    for (int i = 0; i < L.n; ++i) {
+        HIPCHK(hipMemcpyAsync(p, L.ptr[i], L.bytes[i], hipMemcpyDeviceToHost, h->stream));
+        p += L.bytes[i];
     }
-    HIPCHK(hipMemcpyAsync(p, h->stat_part, (size_t)h->W * h->lds * sizeof(double),
-                          hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return SGEP_OK;
 }
@@ -592,20 +1023,15 @@ sgep_status sgep_set_state(sgep_handle *h, const void *host_buf, size_t bytes)
         hd.elem != (int64_t)h->esz || hd.adam != (h->Am ? 1 : 0))
         return SGEP_EINVAL;
     const unsigned char *p = (const unsigned char *)host_buf + sizeof(hd);
-    const size_t st = (size_t)h->ldv * h->kp * h->esz;
     // drain any queued work before overwriting the state it uses
     HIPCHK(hipStreamSynchronize(h->stream));
     HIPCHK(hipMemcpyAsync(h->coef, p, sizeof(Coef), hipMemcpyHostToDevice, h->stream));
     p += sizeof(Coef);
-    void *arrs[] = {h->V, h->G, h->Am, h->As};
-    for (void *a : arrs) {
-        if (!a)
-            continue;
-        HIPCHK(hipMemcpyAsync(a, p, st, hipMemcpyHostToDevice, h->stream));
-        p += st;
+    StateLayout L = state_layout(h);
+    for (int i = 0; i < L.n; ++i) {
+        HIPCHK(hipMemcpyAsync(L.ptr[i], p, L.bytes[i], hipMemcpyHostToDevice, h->stream));
+        p += L.bytes[i];
     }
-    HIPCHK(hipMemcpyAsync(h->stat_part, p, (size_t)h->W * h->lds * sizeof(double),
-                          hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     int st_word = 0;
     memcpy(&st_word, (const unsigned char *)host_buf + sizeof(hd) + offsetof(Coef, status),

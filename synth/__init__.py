@@ -251,3 +251,75 @@ class LDAClasses:
 
     def batch(self, t: int, b: int, dtype=np.float32):
         return self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)
+
+
+# ---------------------------------------------------------------------------
+# Narrow storage formats of the minibatch (input preparation, shared by the
+# tests, the oracle's inputs and the benchmark; no method arithmetic).
+# ---------------------------------------------------------------------------
+
+def bf16_bits(x: np.ndarray) -> np.ndarray:
+    """BF16 encoding (round to nearest, ties to even) of float32 values, as
+    uint16 bit patterns.  Inputs are finite."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def bf16_value(bits: np.ndarray) -> np.ndarray:
+    """Exact float64 value of BF16 bit patterns."""
+    u = (np.asarray(bits, dtype=np.uint16).astype(np.uint32) << 16)
+    return u.view(np.float32).astype(np.float64)
+
+
+def _e4m3_table() -> np.ndarray:
+    """Values of the OCP FP8 e4m3 codes 0x00 .. 0x7E (sign bit clear): 4-bit
+    exponent with bias 7, 3-bit mantissa, subnormals at exponent 0; 0x7F is
+    NaN and there is no infinity."""
+    codes = np.arange(0x7F)
+    e, m = codes >> 3, codes & 7
+    return np.where(e == 0, m / 8.0 * 2.0 ** -6, (1.0 + m / 8.0) * 2.0 ** (e - 7.0))
+
+
+E4M3_VALUES = _e4m3_table()
+E4M3_MAX = float(E4M3_VALUES[-1])  # 448
+
+
+def e4m3_encode(y: np.ndarray) -> np.ndarray:
+    """OCP e4m3 codes of y: round to nearest (ties to the even code),
+    saturating at +-448."""
+    y = np.asarray(y, dtype=np.float64)
+    a = np.minimum(np.abs(y), E4M3_MAX)
+    hi = np.clip(np.searchsorted(E4M3_VALUES, a), 1, len(E4M3_VALUES) - 1)
+    lo = hi - 1
+    dlo, dhi = a - E4M3_VALUES[lo], E4M3_VALUES[hi] - a
+    pick_hi = (dhi < dlo) | ((dhi == dlo) & (hi % 2 == 0))
+    code = np.where(pick_hi, hi, lo).astype(np.uint8)
+    return np.where(y < 0, code | 0x80, code).astype(np.uint8)
+
+
+def e4m3_value(codes: np.ndarray) -> np.ndarray:
+    """Exact float64 value of e4m3 codes (0x7F / 0xFF are NaN)."""
+    c = np.asarray(codes, dtype=np.uint8)
+    mag = c & 0x7F
+    v = np.where(mag == 0x7F, np.nan, E4M3_VALUES[np.minimum(mag, 0x7E)])
+    return np.where(c & 0x80, -v, v)
+
+
+def fp8_column_scales(X: np.ndarray) -> np.ndarray:
+    """Per-column scales s_c = max_r |X[r, c]| / 448 (float32) from a
+    calibration prefix, so X / s maps onto the full e4m3 range; an all-zero
+    column gets scale 1."""
+    amax = np.abs(np.asarray(X, dtype=np.float64)).max(axis=0)
+    s = np.where(amax > 0, amax / E4M3_MAX, 1.0).astype(np.float32)
+    return s
+
+
+def fp8_quantize(X: np.ndarray, scales: np.ndarray) -> np.ndarray:
+    """e4m3 codes of X / scales (column-wise), saturating."""
+    return e4m3_encode(np.asarray(X, dtype=np.float64) / scales.astype(np.float64)[None, :])
+
+
+def fp8_dequantize(codes: np.ndarray, scales: np.ndarray) -> np.ndarray:
+    """Exact float64 values code * scale (products of a 4-bit and a 24-bit
+    significand are exact in float64)."""
+    return e4m3_value(codes) * scales.astype(np.float64)[None, :]

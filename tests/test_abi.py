@@ -69,7 +69,7 @@ def _init_status(cfg, V0=None):
 def test_config_validation_is_synchronous():
     import paper_2206_04993_amd as sg
     mk = sg.make_config
-    C, G = sg.SGEP_KIND_CCA, sg.SGEP_KIND_GENERAL
+    C, G, L = sg.SGEP_KIND_CCA, sg.SGEP_KIND_GENERAL, sg.SGEP_KIND_LDA
     cases = [
         (mk(C, sg.SGEP_F32, 0, 8, 8, 16), sg.SGEP_EINVAL),          # k = 0
         (mk(C, sg.SGEP_F32, 65, 64, 64, 16), sg.SGEP_EUNSUPPORTED),  # k > 64
@@ -85,12 +85,48 @@ def test_config_validation_is_synchronous():
         (mk(C, sg.SGEP_F32, 4, 8, 8, 16, schedule=sg.SGEP_SCHED_INV, t0=0.0), sg.SGEP_EINVAL),
         (mk(C, sg.SGEP_F32, 4, 8, 8, 16, schedule=7), sg.SGEP_EINVAL),
         (mk(C, sg.SGEP_F32, 4, 8, 8, 16, optimizer=sg.SGEP_ADAM, adam_b1=1.0), sg.SGEP_EINVAL),
-        (mk(C, sg.SGEP_BF16, 4, 8, 8, 16), sg.SGEP_EUNSUPPORTED),
-        (mk(sg.SGEP_KIND_LDA, sg.SGEP_F32, 4, 8, 8, 16), sg.SGEP_EUNSUPPORTED),
+        (mk(G, sg.SGEP_BF16, 4, 8, 8, 16), sg.SGEP_EUNSUPPORTED),    # BF16: CCA and LDA only
+        (mk(C, sg.SGEP_BF16, 40, 64, 64, 16), sg.SGEP_EUNSUPPORTED),  # BF16 CCA: k <= 32
+        (mk(C, sg.SGEP_BF16, 4, 12, 8, 16), sg.SGEP_ESHAPE),         # BF16 widths: multiples of 8
+        (mk(C, sg.SGEP_FP8_E4M3, 4, 8, 8, 16), sg.SGEP_EINVAL),      # FP8 needs column scales
+        (mk(C, 4, 4, 8, 8, 16), sg.SGEP_EINVAL),                     # unknown dtype
+        (mk(L, sg.SGEP_F32, 4, 8, 0, 16, n_classes=3), sg.SGEP_EUNSUPPORTED),  # LDA: BF16 only
+        (mk(L, sg.SGEP_FP8_E4M3, 4, 8, 0, 16, n_classes=3), sg.SGEP_EUNSUPPORTED),
+        (mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=1), sg.SGEP_EINVAL),   # >= 2 classes
+        (mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=17), sg.SGEP_EINVAL),  # <= 16 classes
+        (mk(L, sg.SGEP_BF16, 4, 8, 8, 16, n_classes=3), sg.SGEP_ESHAPE),   # LDA: dy = 0
+        (mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=3), sg.SGEP_EINVAL),   # no class means
         (mk(9, sg.SGEP_F32, 4, 8, 8, 16), sg.SGEP_EINVAL),
     ]
     for cfg, want in cases:
         assert _init_status(cfg) == want, (cfg.kind, cfg.dtype, cfg.k, want)
+
+
+def test_auxiliary_data_validation_is_synchronous():
+    """Missing, extra or non-finite FP8 scales / LDA class data are refused
+    before any device work."""
+    import paper_2206_04993_amd as sg
+    mk = sg.make_config
+    C, L = sg.SGEP_KIND_CCA, sg.SGEP_KIND_LDA
+    fp8 = mk(C, sg.SGEP_FP8_E4M3, 4, 8, 8, 16)
+    bf16 = mk(C, sg.SGEP_BF16, 4, 8, 8, 16)
+    lda = mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=3)
+    ones8 = np.ones(8)
+    means, priors = np.zeros((3, 8)), np.full(3, 1.0 / 3)
+    cases = [
+        (fp8, dict(x_col_scale=ones8), sg.SGEP_EINVAL),                       # y scales missing
+        (fp8, dict(x_col_scale=ones8, y_col_scale=-ones8), sg.SGEP_EINVAL),    # non-positive
+        (fp8, dict(x_col_scale=np.r_[ones8[:7], np.inf], y_col_scale=ones8), sg.SGEP_EINVAL),
+        (bf16, dict(x_col_scale=ones8, y_col_scale=ones8), sg.SGEP_EINVAL),    # BF16 has no scales
+        (lda, dict(class_means=means), sg.SGEP_EINVAL),                        # priors missing
+        (lda, dict(class_means=means, class_priors=np.array([0.5, 0.5, 0.0])), sg.SGEP_EINVAL),
+        (lda, dict(class_means=means * np.nan, class_priors=priors), sg.SGEP_EINVAL),
+        (bf16, dict(class_means=means, class_priors=priors), sg.SGEP_EINVAL),  # CCA has no classes
+    ]
+    for cfg, aux, want in cases:
+        with pytest.raises(sg.SgepError) as ei:
+            sg.sgep_init_ex(cfg, np.ones((8 if cfg.kind == L else 16, 4)), **aux)
+        assert ei.value.status == want, (cfg.kind, cfg.dtype, sorted(aux))
 
 
 def test_null_arguments_rejected():
@@ -103,5 +139,9 @@ def test_null_arguments_rejected():
     for fn in ("sgep_sync", "sgep_destroy"):
         assert getattr(lib, fn)(None) == sg.SGEP_EINVAL
     assert lib.sgep_step(None, None, 0, None, 0, 1) == sg.SGEP_EINVAL
+    assert lib.sgep_step_lda(None, None, 0, None, 1) == sg.SGEP_EINVAL
+    assert lib.sgep_kernels_per_step(None, None) == sg.SGEP_EINVAL
+    assert lib.sgep_step_profiled(None, None, 0, None, 0, None, 1, None, 0) == sg.SGEP_EINVAL
+    assert lib.sgep_init_ex(None, None, None, None, None) == sg.SGEP_EINVAL
     assert sg.sgep_status_string(sg.SGEP_EPOISONED).startswith("handle poisoned")
     assert sg.sgep_version() >= 100

@@ -318,7 +318,7 @@ def test_profiled_step_matches_plain_and_times_kernels():
         assert hip.hipEventCreate(ctypes.byref(e)) == 0
     for X, Y in batches:
         plain.step(X, Y)
-        sg.sgep_step_profiled(timed.h, X, X.stride(0), Y, Y.stride(0), 256,
+        sg.sgep_step_profiled(timed.h, X, X.stride(0), Y, Y.stride(0), None, 256,
                               [e.value for e in evs])
     timed.sync()
     assert np.array_equal(plain.vectors(), timed.vectors())
@@ -329,7 +329,7 @@ def test_profiled_step_matches_plain_and_times_kernels():
         assert 0.0 < ms.value < 100.0, ms.value
     X, Y = batches[0]
     with pytest.raises(sg.SgepError):
-        sg.sgep_step_profiled(timed.h, X, X.stride(0), Y, Y.stride(0), 256,
+        sg.sgep_step_profiled(timed.h, X, X.stride(0), Y, Y.stride(0), None, 256,
                               [evs[0].value, evs[1].value, evs[2].value, 0])
     for e in evs:
         hip.hipEventDestroy(e)

@@ -1,0 +1,289 @@
+"""GPU parity of the BF16 / FP8 path (CCA and LDA) against the FP64 oracle,
+through the C ABI.
+
+The oracle is fed the exact values the GPU receives: BF16 inputs decoded to
+float64, FP8 codes times their column scales (exact in float64).  The
+difference that remains is the GPU's own arithmetic: the FP32 right-hand
+operands (players V, projections P and Q) are split into BF16 hi + lo (16
+significand bits, relative error <= 2^-17 per element), products accumulate
+in FP32, the state is FP32.  That is the FP32 path's error budget with the
+operand rounding 2^-24 replaced by about 2^-17 on one factor, so the bounds
+are those of the FP32 tests (2e-5 after one iteration, 3e-4 after N) times a
+factor of 4 (TOLW_1, TOLW_N).  Sizes span several 64-feature subtiles,
+several forward splits and ragged row blocks."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOLW_1 = 8e-5
+TOLW_N = 1.2e-3
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _sg():
+    import paper_2206_04993_amd as sg
+    sg.load()
+    return sg
+
+
+def _bf16_dev(bits):
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(bits).view(np.int16))
+    return t.to("cuda").view(torch.bfloat16).contiguous()
+
+
+def _u8_dev(codes):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(codes, dtype=np.uint8)).to("cuda").contiguous()
+
+
+def _i32_dev(lab):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(lab, dtype=np.int32)).to("cuda").contiguous()
+
+
+def _maxdiff(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max())
+
+
+def _cca_inputs(gen, n, b, fmt, scales=None):
+    """Minibatches as (device X, device Y, float64 X, float64 Y) in the given
+    storage format."""
+    out = []
+    for t in range(1, n + 1):
+        X, Y = gen.batch(t, b)
+        if fmt == "bf16":
+            bx, by = synth.bf16_bits(X), synth.bf16_bits(Y)
+            out.append((_bf16_dev(bx), _bf16_dev(by), synth.bf16_value(bx), synth.bf16_value(by)))
+        else:
+            sx, sy = scales
+            cx, cy = synth.fp8_quantize(X, sx), synth.fp8_quantize(Y, sy)
+            out.append((_u8_dev(cx), _u8_dev(cy), synth.fp8_dequantize(cx, sx),
+                        synth.fp8_dequantize(cy, sy)))
+    return out
+
+
+def _eta(cfg, t):
+    return oracle.eta(cfg.schedule, t, cfg.eta0, eta_T=cfg.eta_T, t0=cfg.t0, t_c=cfg.t_c, T=cfg.T)
+
+
+def _run_cca(cfg, batches, V0, checkpoints, aux=None):
+    sg = _sg()
+    s = sg.Solver(cfg, V0, **(aux or {}))
+    pb = oracle.Problem(oracle.KIND_CCA, cfg.k, cfg.dx, cfg.dy, rho=cfg.rho,
+                        optimizer=cfg.optimizer, adam_b1=cfg.adam_b1, adam_b2=cfg.adam_b2,
+                        adam_eps=cfg.adam_eps)
+    st = oracle.State.init(V0, adam=cfg.optimizer == sg.SGEP_ADAM)
+    res = []
+    for t, (Xd, Yd, X, Y) in enumerate(batches, start=1):
+        s.step(Xd, Yd)
+        oracle.gamma_step(pb, st, X, Y, _eta(cfg, t), cfg.gamma)
+        if t in checkpoints:
+            res.append((t, s.vectors(), st.V.copy(), s.auxiliary(), st.G.copy(), s.eigvals(),
+                        st.eigvals()))
+    s.close()
+    return res
+
+
+@pytest.mark.parametrize("fmt,dx,dy,k,b,opt", [
+    ("bf16", 200, 136, 13, 100, "sgd"),     # ragged rows, 4 + 3 subtiles, KP 16
+    ("bf16", 520, 264, 32, 130, "adam"),    # KP 32, several forward splits
+    ("bf16", 64, 64, 1, 1, "sgd"),          # one player, one row
+    ("fp8", 200, 136, 13, 100, "sgd"),
+    ("fp8", 520, 264, 32, 130, "adam"),
+])
+def test_wide_cca_parity(fmt, dx, dy, k, b, opt):
+    sg = _sg()
+    print(f"wide CCA {fmt} dx={dx} dy={dy} k={k} b={b} {opt}", flush=True)
+    gen = synth.CCAPlanted(dx, dy, np.linspace(0.9, 0.3, min(k, 6)), sigma=0.5, seed=3)
+    dtype = sg.SGEP_BF16 if fmt == "bf16" else sg.SGEP_FP8_E4M3
+    adam = opt == "adam"
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, dtype, k, dx, dy, b,
+                         optimizer=sg.SGEP_ADAM if adam else sg.SGEP_SGD,
+                         schedule=sg.SGEP_SCHED_INV, eta0=2e-3 if adam else 0.05, t0=100.0,
+                         gamma=0.5, rho=1e-6)
+    aux, scales = None, None
+    if fmt == "fp8":
+        Xc, Yc = gen.sample(4096, np.random.default_rng([3, 99]))
+        scales = (synth.fp8_column_scales(Xc), synth.fp8_column_scales(Yc))
+        aux = dict(x_col_scale=scales[0], y_col_scale=scales[1])
+    N = 40
+    batches = _cca_inputs(gen, N, b, fmt, scales)
+    V0 = synth.initial_players(dx + dy, k, 4)
+    res = _run_cca(cfg, batches, V0, {1, N}, aux)
+    for t, Vg, Vo, Gg, Go, lg, lo in res:
+        tol = TOLW_1 if t == 1 else TOLW_N
+        dv, dg = _maxdiff(Vg, Vo), _maxdiff(Gg, Go)
+        print(f"  t={t}: max|dV|={dv:.2e} max|dG|={dg:.2e}", flush=True)
+        assert dv < tol, (t, dv)
+        assert dg < tol, (t, dg)
+        assert np.allclose(lg, lo, rtol=10 * tol, atol=10 * tol), (t, lg, lo)
+        # unit players (Alg. 2 output)
+        assert np.allclose((Vg * Vg).sum(axis=0), 1.0, atol=1e-5)
+
+
+def _lda_problem(d, c, k, seed=5):
+    gen = synth.LDAClasses(d=d, c=c, r=min(16, d), seed=seed)
+    priors = np.full(c, 1.0 / c)
+    return gen, priors
+
+
+@pytest.mark.parametrize("d,c,k,b,opt", [
+    (200, 10, 9, 300, "sgd"),     # KP 16, 4 subtiles, ragged rows
+    (520, 6, 20, 130, "adam"),    # KP 32
+    (136, 10, 64, 77, "sgd"),     # KP 64, k > classes (zero eigenvalues beyond c - 1)
+])
+def test_wide_lda_parity(d, c, k, b, opt):
+    sg = _sg()
+    print(f"wide LDA bf16 d={d} c={c} k={k} b={b} {opt}", flush=True)
+    gen, priors = _lda_problem(d, c, k)
+    adam = opt == "adam"
+    eps = 1e-3
+    cfg = sg.make_config(sg.SGEP_KIND_LDA, sg.SGEP_BF16, k, d, 0, b,
+                         optimizer=sg.SGEP_ADAM if adam else sg.SGEP_SGD,
+                         schedule=sg.SGEP_SCHED_INV, eta0=1e-3 if adam else 0.01, t0=100.0,
+                         gamma=0.5, rho=1e-6, eps_reg=eps, n_classes=c)
+    V0 = synth.initial_players(d, k, 6)
+    s = sg.Solver(cfg, V0, class_means=gen.means, class_priors=priors)
+    pb = oracle.Problem(oracle.KIND_LDA, k, d, 0, eps_reg=eps, rho=1e-6, optimizer=cfg.optimizer,
+                        class_means=gen.means, class_priors=priors)
+    st = oracle.State.init(V0, adam=adam)
+    N = 30
+    for t in range(1, N + 1):
+        X, lab = gen.batch(t, b)
+        bits = synth.bf16_bits(X)
+        s.step(_bf16_dev(bits), _i32_dev(lab))
+        oracle.gamma_step(pb, st, synth.bf16_value(bits), None, _eta(cfg, t), cfg.gamma,
+                          labels=lab)
+        if t in (1, N):
+            tol = TOLW_1 if t == 1 else TOLW_N
+            Vg, Gg = s.vectors(), s.auxiliary()
+            dv, dg = _maxdiff(Vg, st.V), _maxdiff(Gg, st.G)
+            print(f"  t={t}: max|dV|={dv:.2e} max|dG|={dg:.2e}", flush=True)
+            assert dv < tol, (t, dv)
+            assert dg < tol * max(1.0, float(np.abs(st.G).max())), (t, dg)
+            lg, lo = s.eigvals(), st.eigvals()
+            assert np.allclose(lg, lo, rtol=10 * tol, atol=10 * tol), (t, lg, lo)
+    s.close()
+
+
+def test_wide_determinism_resume_and_graph():
+    """Bitwise-identical reruns, checkpoint / resume in a fresh handle, and
+    hipGraph replay equal to eager steps (BF16 CCA with Adam)."""
+    torch = _torch()
+    sg = _sg()
+    gen = synth.CCAPlanted(136, 72, np.linspace(0.9, 0.3, 4), sigma=0.5, seed=8)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_BF16, 8, 136, 72, 96,
+                         optimizer=sg.SGEP_ADAM, eta0=1e-3, gamma=0.3)
+    batches = _cca_inputs(gen, 8, 96, "bf16")
+    V0 = synth.initial_players(208, 8, 1)
+
+    def run(bs, solver=None):
+        s = solver or sg.Solver(cfg, V0)
+        for Xd, Yd, _, _ in bs:
+            s.step(Xd, Yd)
+        return s
+
+    a, b = run(batches), run(batches)
+    assert np.array_equal(a.vectors(), b.vectors())
+    assert np.array_equal(a.auxiliary(), b.auxiliary())
+    c = run(batches[:4])
+    blob = c.get_state()
+    d = sg.Solver(cfg, synth.initial_players(208, 8, 7))
+    d.set_state(blob)
+    assert d.step_count() == 4
+    run(batches[4:], solver=d)
+    assert np.array_equal(a.vectors(), d.vectors())
+    assert np.array_equal(a.eigvals(), d.eigvals())
+    # graph: the same 8 steps captured once, replayed twice, against eager
+    stream = torch.cuda.Stream()
+    g_s = sg.Solver(cfg, V0, stream=stream)
+    e_s = sg.Solver(cfg, V0)
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=stream):
+        for Xd, Yd, _, _ in batches:
+            g_s.step(Xd, Yd)
+    for rep in range(2):
+        run(batches, solver=e_s)
+        e_s.sync()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert g_s.step_count() == 8 * (rep + 1)
+        assert np.array_equal(e_s.vectors(), g_s.vectors()), rep
+    for s in (a, b, c, d, e_s, g_s):
+        s.close()
+
+
+def test_wide_step_errors_and_bad_label():
+    torch = _torch()
+    sg = _sg()
+    gen, priors = _lda_problem(64, 4, 4)
+    cfg = sg.make_config(sg.SGEP_KIND_LDA, sg.SGEP_BF16, 4, 64, 0, 32, eta0=0.01,
+                         eps_reg=1e-3, n_classes=4)
+    s = sg.Solver(cfg, synth.initial_players(64, 4, 0), class_means=gen.means,
+                  class_priors=priors)
+    X, lab = gen.batch(1, 32)
+    Xd = _bf16_dev(synth.bf16_bits(X))
+    with pytest.raises(sg.SgepError) as e:           # LDA needs labels
+        sg.sgep_step(s.h, Xd, 64, Xd, 64, 32)
+    assert e.value.status == sg.SGEP_EINVAL
+    with pytest.raises(sg.SgepError) as e:           # b > b_max
+        sg.sgep_step_lda(s.h, Xd, 64, _i32_dev(lab), 33)
+    assert e.value.status == sg.SGEP_ESHAPE
+    with pytest.raises(sg.SgepError) as e:           # ldx not a multiple of 8
+        sg.sgep_step_lda(s.h, Xd, 66, _i32_dev(lab), 16)
+    assert e.value.status == sg.SGEP_ESHAPE
+    assert s.kernels_per_step() == 3
+    s.step(Xd, _i32_dev(lab))
+    s.sync()
+    bad = lab.copy()
+    bad[5] = 4                                        # class index out of range
+    s.step(Xd, _i32_dev(bad))
+    with pytest.raises(sg.SgepError) as e:
+        s.sync()
+    assert e.value.status == sg.SGEP_ENONFINITE
+    with pytest.raises(sg.SgepError) as e:
+        s.step(Xd, _i32_dev(lab))
+    assert e.value.status == sg.SGEP_EPOISONED
+    s.close()
+
+
+def test_wide_profiled_step_matches_plain():
+    sg = _sg()
+    import bench
+    gen = synth.CCAPlanted(136, 72, np.linspace(0.9, 0.3, 4), sigma=0.5, seed=2)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_BF16, 8, 136, 72, 96, eta0=0.05, gamma=0.5)
+    batches = _cca_inputs(gen, 3, 96, "bf16")
+    V0 = synth.initial_players(208, 8, 3)
+    plain, timed = sg.Solver(cfg, V0), sg.Solver(cfg, V0)
+    hip = bench.hip_runtime()
+    evs = [ctypes.c_void_p() for _ in range(6)]
+    for e in evs:
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+    for Xd, Yd, _, _ in batches:
+        plain.step(Xd, Yd)
+        sg.sgep_step_profiled(timed.h, Xd, 136, Yd, 72, None, 96, [e.value for e in evs])
+    timed.sync()
+    assert np.array_equal(plain.vectors(), timed.vectors())
+    ms = ctypes.c_float()
+    for i in range(3):
+        assert hip.hipEventElapsedTime(ctypes.byref(ms), evs[2 * i], evs[2 * i + 1]) == 0
+        assert 0.0 < ms.value < 100.0
+    Xd, Yd, _, _ = batches[0]
+    with pytest.raises(sg.SgepError):                 # four events for three kernels
+        sg.sgep_step_profiled(timed.h, Xd, 136, Yd, 72, None, 96, [e.value for e in evs[:4]])
+    for e in evs:
+        hip.hipEventDestroy(e)
+    plain.close()
+    timed.close()
