@@ -7,8 +7,8 @@ produced by
     rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR -o fetch -- CMD
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR -o write -- CMD
 
-with CMD = python3 bench.py --workload W --steps 256 --warmup 16
---no-cpu-baseline --calibrate-copy-mb 256, and writes
+with CMD given on the command line (default: python3 bench.py --workload W
+--steps 256 --warmup 16 --no-cpu-baseline --calibrate-copy-mb 256), and writes
 profiles/kernels_<W>.txt (kernel durations) and profiles/traffic_<W>.txt
 (HBM bytes per launch).  Counter values are KiB per dispatch; the plain
 256 MiB copy in the same run calibrates them (bytes per counter-KiB).
@@ -28,22 +28,27 @@ def _rows(path):
     return list(csv.DictReader(open(path)))
 
 
+_KERNELS = ("k_wfwd", "k_wmid", "k_wbwd", "k_winit", "k_fwd", "k_bwd")
+
+
 def _short(name: str) -> str:
-    if "k_fwd" in name:
-        return "k_fwd"
-    if "k_bwd" in name:
-        return "k_bwd"
+    for k in _KERNELS:
+        if k + "<" in name or k + "I" in name or name.startswith(k) or ("::" + k) in name:
+            return k
     if "copybuffer" in name.lower():
         return "copy"
     return name[:60]
 
 
-def main(prof_dir: str, workload: str, copy_mib: int = 256):
+def main(prof_dir: str, workload: str, cmd: str = "", copy_mib: int = 256):
+    """cmd: the exact program line that ran under rocprofv3 (recorded in the
+    summaries); copy_mib: size of its calibration copy."""
     sys.path.insert(0, ROOT)
     import bench  # noqa: the source hash of the kernels
 
-    cmd = (f"python3 bench.py --workload {workload} --steps 256 --warmup 16 --no-cpu-baseline "
-           f"--calibrate-copy-mb {copy_mib}")
+    if not cmd:
+        cmd = (f"python3 bench.py --workload {workload} --steps 256 --warmup 16 "
+               f"--no-cpu-baseline --calibrate-copy-mb {copy_mib}")
     ks = _rows(os.path.join(prof_dir, "ks_kernel_stats.csv"))
     out = [f"# rocprofv3 kernel statistics, workload {workload} (MI355X)",
            f"# command: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o ks -- {cmd}",
@@ -55,6 +60,9 @@ def main(prof_dir: str, workload: str, copy_mib: int = 256):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     open(os.path.join(ROOT, "profiles", f"kernels_{workload}.txt"), "w").write("\n".join(out) + "\n")
 
+    if not os.path.exists(os.path.join(prof_dir, "fetch_counter_collection.csv")):
+        print("\n".join(out))
+        return  # kernel trace only; no counter passes in this directory
     vals = {}
     for tag, ctr in (("fetch", "FETCH_SIZE"), ("write", "WRITE_SIZE")):
         for r in _rows(os.path.join(prof_dir, f"{tag}_counter_collection.csv")):
@@ -69,7 +77,7 @@ def main(prof_dir: str, workload: str, copy_mib: int = 256):
         return statistics.median(v for g, v in c if g == big)
     scale_r = copy_mib * 2 ** 20 / copy_kib("fetch")   # bytes per counter-KiB, reads
     scale_w = copy_mib * 2 ** 20 / copy_kib("write")   # bytes per counter-KiB, writes
-    rec = {"workload": workload, "source_hash": bench.kernel_source_hash(),
+    rec = {"workload": workload,
            "copy_calibration": {"mib": copy_mib, "fetch_kib": copy_kib("fetch"),
                                 "write_kib": copy_kib("write"), "read_scale": scale_r,
                                 "write_scale": scale_w},
@@ -80,7 +88,7 @@ def main(prof_dir: str, workload: str, copy_mib: int = 256):
              f"# calibration: plain copy of {copy_mib} MiB reads {copy_kib('fetch'):.0f} KiB and writes "
              f"{copy_kib('write'):.0f} KiB by these counters",
              "kernel | dispatches | fetch_KiB(median) | write_KiB(median) | read_bytes | write_bytes"]
-    for k in ("k_fwd", "k_bwd"):
+    for k in ("k_fwd", "k_bwd", "k_wfwd", "k_wmid", "k_wbwd"):
         f = [v for _, v in vals.get((k, "fetch"), [])]
         w = [v for _, v in vals.get((k, "write"), [])]
         if not f:
@@ -88,7 +96,8 @@ def main(prof_dir: str, workload: str, copy_mib: int = 256):
         fr, wr = statistics.median(f), statistics.median(w)
         rb, wb = fr * scale_r, wr * scale_w
         rec["kernels"][k] = {"read_bytes": round(rb), "write_bytes": round(wb),
-                             "fetch_kib": fr, "write_kib": wr, "dispatches": len(f)}
+                             "fetch_kib": fr, "write_kib": wr, "dispatches": len(f),
+                             "source_hash": bench.kernel_source_hash(bench.KERNEL_HEADER[k])}
         lines.append(f"{k} | {len(f)} | {fr:.1f} | {wr:.1f} | {rb:.0f} | {wb:.0f}")
     lines.append("json: " + json.dumps(rec))
     open(os.path.join(ROOT, "profiles", f"traffic_{workload}.txt"), "w").write("\n".join(lines) + "\n")
@@ -96,4 +105,4 @@ def main(prof_dir: str, workload: str, copy_mib: int = 256):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], sys.argv[2])
+    main(sys.argv[1], sys.argv[2], *(sys.argv[3:4]), *(int(a) for a in sys.argv[4:]))
