@@ -267,12 +267,15 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
     using namespace sgep::wide;
     const dim3 blk(kWT);
     const bool adam = h->cfg.optimizer == SGEP_ADAM;
-    launch_k(k_wfwd<KP, IN>, dim3(a.n_rb * a.nview * a.n_split), blk, h->stream, ev[0], ev[1], a);
-    launch_k(k_wmid<KP, KIND>, dim3(a.nA + wide_stat_blocks(a)), blk, h->stream, ev[2], ev[3], a, 0);
+    // forward workgroups, then the statistics reductions
+    launch_k(k_wfwd<KP, IN>, dim3(a.n_rb * a.nview * a.n_split + wide_stat_blocks(a)), blk,
+             h->stream, ev[0], ev[1], a);
+    launch_k(k_wmid<KP, KIND>, dim3(a.nA), blk, h->stream, ev[2], ev[3], a);
+    const dim3 bblk(kBT);
     if (adam)
-        launch_k(k_wbwd<KP, IN, KIND, sgep::kOptAdam>, dim3(a.nwg), blk, h->stream, ev[4], ev[5], a);
+        launch_k(k_wbwd<KP, IN, KIND, sgep::kOptAdam>, dim3(a.nwg), bblk, h->stream, ev[4], ev[5], a);
     else
-        launch_k(k_wbwd<KP, IN, KIND, sgep::kOptSGD>, dim3(a.nwg), blk, h->stream, ev[4], ev[5], a);
+        launch_k(k_wbwd<KP, IN, KIND, sgep::kOptSGD>, dim3(a.nwg), bblk, h->stream, ev[4], ev[5], a);
     HIPCHK(hipGetLastError());
     return SGEP_OK;
 }
@@ -280,7 +283,7 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
 template <int KP, int IN, int KIND>
 sgep_status wide_init_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *)
 {
-    hipLaunchKernelGGL((sgep::wide::k_winit<KP, IN, KIND>), dim3(a.nwg), dim3(sgep::wide::kWT), 0,
+    hipLaunchKernelGGL((sgep::wide::k_winit<KP, IN, KIND>), dim3(a.nwg), dim3(sgep::wide::kBT), 0,
                        h->stream, a);
     HIPCHK(hipGetLastError());
     return SGEP_OK;
@@ -291,8 +294,7 @@ template <int KP, int IN, int KIND>
 sgep_status wide_readout_t(sgep_handle *h, const WideArgs &a, const void *S, int mode)
 {
     using namespace sgep::wide;
-    hipLaunchKernelGGL((k_wmid<KP, KIND>), dim3(wide_stat_blocks(a)), dim3(kWT), 0, h->stream, a,
-                       1);
+    hipLaunchKernelGGL(k_wstats, dim3(wide_stat_blocks(a)), dim3(kWT), 0, h->stream, a);
     const int64_t n = h->d * (int64_t)h->cfg.k;
     int64_t nb = (n + 255) / 256;
     if (nb > 1024)

@@ -16,20 +16,26 @@
 //   k_wfwd  raw P = X V (CCA also Q = Y V) for a 64-row block over one slice of
 //           the features (split-K, the minibatch width d >> b), eight waves
 //           each over a contiguous feature range, FP32 partials per slice.
-//   k_wmid  sums the slices (fixed order), writes the products transposed as
-//           BF16 hi/lo operand rows W (CCA: P then Q; LDA: P then the one-hot
-//           class indicator of the labels), advances the step counter, and
-//           reduces the previous iteration's per-workgroup state statistics
-//           (v_i^T [Bv]_j, ||v_i||^2, LDA: class means times v_i) to totals.
+//           Extra workgroups reduce the previous iteration's per-workgroup
+//           state statistics (v_i^T [Bv]_j, ||v_i||^2, LDA: class means times
+//           v_i) to totals.
+//   k_wmid  sums the slices (fixed order) and writes the backward operand W,
+//           transposed, as BF16 hi/lo rows: CCA [P | Q]; LDA the within-class
+//           residual R = X V - (M V)[labels] and the one-hot class indicator L;
+//           advances the step counter.
 //   k_wbwd  for one view and a run of 64-feature subtiles: X^T W over all rows
 //           (X transposed in registers), the k x k Gram terms of the minibatch
 //           recomputed from the W fragments already in registers (identical in
 //           every workgroup, so no extra reduction pass), the coefficients,
-//           and the fused epilogue: update direction, retraction step (SGD or
-//           Adam), auxiliary update, the BF16 hi/lo V operand of the next
-//           iteration, and this workgroup's FP64 partial statistics.
+//           and the fused epilogue on MFMA tiles: parent penalty (and the LDA
+//           class terms) as small products, update direction, retraction step
+//           (SGD or Adam), auxiliary update, the BF16 hi/lo V operand of the
+//           next iteration, and this workgroup's FP64 partial statistics.
 // The stored V is lazily normalised as in sgep_kernels.hpp: P and W are raw
 // products with the stored V, and the norm totals scale every use.
+//
+// Both streaming loops are software-pipelined: the loads of the next chunk are
+// issued before the MFMAs of the current one.
 #pragma once
 
 #include "sgep_kernels.hpp"
@@ -46,10 +52,11 @@ constexpr int kInBF16 = 0;
 constexpr int kInFP8 = 1;
 constexpr int kKindLDA = 2;
 constexpr int kStatusBadLabel = 2;
-constexpr int kStatCols = 16;  // statistics columns per reduction workgroup of k_wmid
+constexpr int kStatCols = 16;  // statistics columns per reduction workgroup
+constexpr int kBT = 256;       // threads per backward workgroup: four wave64, one per SIMD
+constexpr int kBW = kBT / 64;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
@@ -63,7 +70,7 @@ struct WideArgs {
     int32_t nview, k, ncls;
     // forward decomposition: block = (split, view, 64-row block), row blocks fastest
     int32_t n_rb, n_split;
-    int32_t nA;                 // k_wmid row workgroups: 16 rows each, 4 n_rb
+    int32_t nA;                 // k_wmid workgroups: 16 rows each, 4 n_rb
     int64_t fs, fw;             // features per split and per wave (multiples of 64)
     int64_t ldr;                // padded rows (multiple of kRB) of the partials and of W
     // backward decomposition: workgroups [0, nwg0) cover view 0, the rest view 1;
@@ -74,7 +81,7 @@ struct WideArgs {
     uint16_t *Vh, *Vl;          // KP x dtot, player-major BF16 hi / lo of s_f V
     const float *colscale;      // dtot (FP8 only): s_f, 0 on padding
     float *Ppart;               // [n_split][nview][ldr][KP]
-    uint16_t *Wh, *Wl;          // [MW][ldr]
+    uint16_t *Wh, *Wl;          // [rows of W][ldr]
     const float *M;             // LDA: ncls x dtot class means
     const float *Mbar;          // LDA: dtot, prior-weighted mean of the class means
     const double *prior;        // LDA: ncls
@@ -125,34 +132,68 @@ __device__ __forceinline__ void fp8x4_to_bf16(uint32_t w, uint32_t &d0, uint32_t
 }
 
 template <int KP, int KIND> struct Shape {
-    static constexpr int NT = KP / 16;                               // 16-player tiles
-    static constexpr int MW = (KIND == kKindLDA) ? KP + 16 : 2 * KP; // rows of W
-    static constexpr int NU = MW / 16;
-    static constexpr int MWP = MW + 4;                               // LDS row of the products
+    static constexpr bool LDA = KIND == kKindLDA;
+    static constexpr int NT = KP / 16;                 // 16-player tiles
+    static constexpr int MWA = LDA ? KP : 2 * KP;      // rows of W in the products X^T W
+    static constexpr int NU = MWA / 16;
+    static constexpr int MWP = MWA + 4;                // LDS row of the products
     static constexpr int TRI = KP * (KP + 1) / 2;
-    static constexpr int SLOT = kFT * MWP;                           // floats per reduction slot
-    // Gram terms per wave and in total (CCA: P^T Q, then sum P^2, sum Q^2 per
-    // lane group; LDA: L^T P, sum P^2 per lane group, class counts per group)
-    static constexpr int GW = (KIND == kKindLDA) ? 16 * KP + 4 * KP + 4 * 16 : KP * KP + 8 * KP;
-    static constexpr int GT = (KIND == kKindLDA) ? 16 * KP + KP + 16 : KP * KP + 2 * KP;
+    static constexpr int SLOT = kFT * MWP;             // floats per reduction slot
+    static constexpr int GLD = KP + 4;                 // LDS row of the old auxiliary tile
+    static constexpr int VLD = KP + 1;                 // LDS row of the new V, G tiles
+    // Gram terms per wave (CCA: P^T Q, then sum P^2 and sum Q^2 per lane
+    // group; LDA: L^T R, then sum R^2 per lane group) and in total
+    static constexpr int GW = LDA ? 16 * KP + 4 * KP : KP * KP + 8 * KP;
+    static constexpr int GT = LDA ? 16 * KP + KP : KP * KP + 2 * KP;
+    static constexpr int NG = LDA ? NT : NT * NT;      // Gram MFMA tiles per wave
     // statistics tiles: lower 16x16 tiles of V^T G, then (LDA) M V tiles
-    static constexpr int NST = NT * (NT + 1) / 2 + ((KIND == kKindLDA) ? NT : 0);
+    static constexpr int NST = NT * (NT + 1) / 2 + (LDA ? NT : 0);
 };
 
 // ---------------------------------------------------------------------------
+// Statistics totals: kStatCols columns of the per-workgroup partials of the
+// latest backward pass (or of k_winit), summed over the workgroups in a fixed
+// order (each lane over a fixed strided subset, then a fixed butterfly).
+// ---------------------------------------------------------------------------
+__device__ inline void reduce_stats(const WideArgs &a, int qb)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
+    for (int cc = w; cc < kStatCols; cc += kNW) {
+        const int e = qb * kStatCols + cc;
+        if (e >= a.Ws)
+            break;
+        double s = 0.0;
+        for (int j = lane; j < a.nwg; j += 64)
+            s += a.spart[(int64_t)e * a.lds + j];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            s += __shfl_xor(s, off);
+        if (lane == 0)
+            a.stot[e] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kWT) k_wstats(WideArgs a) { reduce_stats(a, blockIdx.x); }
+
+// ---------------------------------------------------------------------------
 // Forward products.  Lane l (row r = l % 16 of a 16-row tile, group g = l / 16)
-// holds features f0 + 16 g + 8 m + j (j < 8) of MFMA chunk m in {0, 1} of a
-// 64-feature step, and the V operand holds the same features of player
-// l % 16 of a 16-player tile, so every 16-byte load is one contiguous piece
-// of a row of X or of the player-major V operand; the pairing of k-indices to
-// features is the same in both operands, so the sum is unchanged.
+// holds features f0 + 8 g .. f0 + 8 g + 7 of a 32-feature MFMA chunk, the V
+// operand the same features of player l % 16 of a 16-player tile: one 16-byte
+// (BF16) or 8-byte (FP8) load per row tile, one per player tile and half.
 // ---------------------------------------------------------------------------
 template <int KP, int IN>
 __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
 {
     constexpr int NT = KP / 16;
     __shared__ float red[4][kRB * KP];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nfwd = a.n_rb * a.nview * a.n_split;
+    if ((int)blockIdx.x >= nfwd) {
+        reduce_stats(a, (int)blockIdx.x - nfwd);
+        return;
+    }
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
     const int r16 = lane & 15, g = lane >> 4;
     int blk = blockIdx.x;
     const int rb = blk % a.n_rb;
@@ -162,11 +203,25 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
     const int64_t dv = a.dv[v];
     const int64_t ld = v ? a.ldy : a.ldx;
     const uint8_t *Xb = (const uint8_t *)(v ? a.Y : a.X);
+    constexpr int ES = IN == kInBF16 ? 2 : 1;
     const int64_t row0 = (int64_t)rb * kRB;
     const int64_t fbeg = (int64_t)s * a.fs + (int64_t)w * a.fw;
     const int64_t fend = (fbeg + a.fw < dv) ? fbeg + a.fw : dv;
-    const uint16_t *Vh = a.Vh + a.off[v] + (int64_t)r16 * a.dtot;
-    const uint16_t *Vl = a.Vl + a.off[v] + (int64_t)r16 * a.dtot;
+    const int nst = fend > fbeg ? (int)((fend - fbeg + 31) / 32) : 0;
+    const uint16_t *Vh = a.Vh + a.off[v] + (int64_t)r16 * a.dtot + 8 * g;
+    const uint16_t *Vl = a.Vl + a.off[v] + (int64_t)r16 * a.dtot + 8 * g;
+    // Loads are unconditional, from clamped in-bounds addresses (a row past the
+    // minibatch reads the last row, a feature unit past the view the last
+    // unit); the data are zeroed where they are consumed.  Branch-free loads
+    // let the next chunk stay in flight while the current one is multiplied.
+    const uint8_t *xr[4];
+    bool rok[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t row = row0 + 16 * t + r16;
+        rok[t] = row < a.b;
+        xr[t] = Xb + (rok[t] ? row : a.b - 1) * ld * ES;
+    }
 
     f32x4 acc[4][NT];
 #pragma unroll
@@ -175,47 +230,59 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
         for (int u = 0; u < NT; ++u)
             acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int64_t f0 = fbeg; f0 < fend; f0 += 64) {
-        u32x4 xa[4][2], vh[NT][2], vl[NT][2];
+    // one 32-feature chunk: raw X (BF16: 4 dwords; FP8: 2 dwords) and V hi/lo
+    auto load = [&](int st, u32x4(&xa)[4], u32x4(&vh)[NT], u32x4(&vl)[NT]) {
+        const int64_t f0 = fbeg + 32 * (int64_t)(st < nst ? st : nst - 1);
+        const int64_t fx = f0 + 8 * g < dv ? f0 + 8 * g : dv - 8;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const int64_t row = row0 + 16 * t + r16;
-            const bool rok = row < a.b;
-#pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                const int64_t fu = f0 + 16 * g + 8 * m;
-                const bool ok = rok && fu < dv;
-                if (IN == kInBF16) {
-                    xa[t][m] = ok ? *reinterpret_cast<const u32x4 *>(Xb + 2 * (row * ld + fu))
-                                  : u32x4{0u, 0u, 0u, 0u};
-                } else {
-                    const u32x2 q = ok ? *reinterpret_cast<const u32x2 *>(Xb + row * ld + fu)
-                                       : u32x2{0u, 0u};
-                    uint32_t e0, e1, e2, e3;
-                    fp8x4_to_bf16(q[0], e0, e1);
-                    fp8x4_to_bf16(q[1], e2, e3);
-                    xa[t][m] = u32x4{e0, e1, e2, e3};
-                }
+            if (IN == kInBF16) {
+                xa[t] = *reinterpret_cast<const u32x4 *>(xr[t] + 2 * fx);
+            } else {
+                const u32x2 q = *reinterpret_cast<const u32x2 *>(xr[t] + fx);
+                xa[t] = u32x4{q[0], q[1], 0u, 0u};
             }
         }
 #pragma unroll
-        for (int u = 0; u < NT; ++u)
+        for (int u = 0; u < NT; ++u) {
+            const int64_t vo = (int64_t)16 * u * a.dtot + f0;
+            vh[u] = *reinterpret_cast<const u32x4 *>(Vh + vo);
+            vl[u] = *reinterpret_cast<const u32x4 *>(Vl + vo);
+        }
+    };
+    auto mma = [&](int st, const u32x4(&xa)[4], const u32x4(&vh)[NT], const u32x4(&vl)[NT]) {
+        if (st >= nst)
+            return; // wave-uniform
+        const bool fok = fbeg + 32 * (int64_t)st + 8 * g < dv;
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                const int64_t vo = (int64_t)16 * u * a.dtot + f0 + 16 * g + 8 * m;
-                vh[u][m] = *reinterpret_cast<const u32x4 *>(Vh + vo);
-                vl[u][m] = *reinterpret_cast<const u32x4 *>(Vl + vo);
+        for (int t = 0; t < 4; ++t) {
+            u32x4 x = xa[t];
+            if (IN == kInFP8) {
+                uint32_t e0, e1, e2, e3;
+                fp8x4_to_bf16(xa[t][0], e0, e1);
+                fp8x4_to_bf16(xa[t][1], e2, e3);
+                x = u32x4{e0, e1, e2, e3};
             }
-        __builtin_amdgcn_sched_barrier(0);
+            if (!(fok && rok[t]))
+                x = u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
-#pragma unroll
-            for (int t = 0; t < 4; ++t)
-#pragma unroll
-                for (int u = 0; u < NT; ++u) {
-                    acc[t][u] = mfma_bf16(xa[t][m], vh[u][m], acc[t][u]);
-                    acc[t][u] = mfma_bf16(xa[t][m], vl[u][m], acc[t][u]);
-                }
+            for (int u = 0; u < NT; ++u) {
+                acc[t][u] = mfma_bf16(x, vh[u], acc[t][u]);
+                acc[t][u] = mfma_bf16(x, vl[u], acc[t][u]);
+            }
+        }
+    };
+    u32x4 xa0[4], vh0[NT], vl0[NT], xa1[4], vh1[NT], vl1[NT];
+    if (nst > 0) {
+        load(0, xa0, vh0, vl0);
+        for (int st = 0; st < nst; st += 2) {
+            load(st + 1, xa1, vh1, vl1);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(st, xa0, vh0, vl0);
+            load(st + 2, xa0, vh0, vl0);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(st + 1, xa1, vh1, vl1);
+        }
     }
 
     // eight waves -> one 64 x KP partial: waves 4..7 park, 0..3 add, four-slot sum
@@ -248,97 +315,86 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Middle pass.  Blocks [0, ldr / 16): 16 rows each -- sum the forward slices,
-// write W (BF16 hi/lo, row m of W holds column m of [P | Q] or of [P | L]
-// over the minibatch rows), advance the step counter (block 0).  The other
-// blocks (all of them when stats_only): kStatCols statistics columns each,
-// summed over the backward workgroups in a fixed order.
+// Middle pass, 16 rows per workgroup: sum the forward slices in a fixed order
+// and write row m of W (BF16 hi/lo over the minibatch rows) = column m of
+// [P | Q] (CCA) or of R = P - (M V)[labels] followed by the one-hot L (LDA,
+// M V from the statistics totals of this iteration); block 0 advances t.
 // ---------------------------------------------------------------------------
 template <int KP, int KIND>
-__global__ void __launch_bounds__(kWT) k_wmid(WideArgs a, int stats_only)
+__global__ void __launch_bounds__(kWT) k_wmid(WideArgs a)
 {
-    constexpr int NV = (KIND == kKindLDA) ? 1 : 2;
+    constexpr bool LDA = KIND == kKindLDA;
+    constexpr int NV = LDA ? 1 : 2;
+    constexpr int TRI = KP * (KP + 1) / 2;
     __shared__ float tile[16 * NV * KP];
-    __shared__ double wsum[kNW][64];
+    __shared__ int lab[16];
     const int tid = threadIdx.x;
-    const int nA = stats_only ? 0 : a.nA;
-    if ((int)blockIdx.x < nA) {
-        const int q = blockIdx.x;
-        const int64_t r0 = (int64_t)q * 16;
-        for (int e = tid; e < 16 * NV * KP; e += kWT) {
-            const int rl = e / (NV * KP), rem = e % (NV * KP);
-            const int vv = rem / KP, c = rem % KP;
-            float s = 0.f;
-            for (int sp = 0; sp < a.n_split; ++sp)
-                s += a.Ppart[(((int64_t)sp * a.nview + vv) * a.ldr + r0 + rl) * KP + c];
-            tile[e] = s;
-        }
-        __syncthreads();
-        for (int e = tid; e < NV * KP * 16; e += kWT) {
-            const int m = e / 16, rl = e % 16;
-            uint32_t hi, lo;
-            split_bf16(tile[rl * NV * KP + m], hi, lo);
-            a.Wh[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)hi;
-            a.Wl[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)lo;
-        }
-        if (KIND == kKindLDA) {
-            for (int e = tid; e < 16 * 16; e += kWT) {
-                const int c = e / 16, rl = e % 16;
-                const int64_t row = r0 + rl;
-                uint16_t one = 0;
-                if (row < a.b) {
-                    const int lab = a.labels[row];
-                    if (lab < 0 || lab >= a.ncls) {
-                        if (c == 0)
-                            atomicOr(&a.coef->status, kStatusBadLabel);
-                    } else if (lab == c) {
-                        one = 0x3F80; // 1.0
-                    }
-                }
-                a.Wh[(int64_t)(KP + c) * a.ldr + row] = one;
+    const int q = blockIdx.x;
+    const int64_t r0 = (int64_t)q * 16;
+    if (LDA && tid < 16) {
+        const int64_t row = r0 + tid;
+        int l = -1;
+        if (row < a.b) {
+            l = a.labels[row];
+            if (l < 0 || l >= a.ncls) {
+                atomicOr(&a.coef->status, kStatusBadLabel);
+                l = -1;
             }
         }
-        if (q == 0 && tid == 0)
-            a.coef->t += 1.0;
-        return;
+        lab[tid] = l;
     }
-    // statistics columns: one wave per column, lanes over workgroups, fixed order
-    const int qb = blockIdx.x - nA;
-    const int lane = tid & 63, w = tid >> 6;
-    for (int cc = w; cc < kStatCols; cc += kNW) {
-        const int e = qb * kStatCols + cc;
-        double s = 0.0;
-        if (e < a.Ws)
-            for (int j = lane; j < a.nwg; j += 64)
-                s += a.spart[(int64_t)e * a.lds + j];
-        wsum[w][lane] = s;
-        __syncthreads();
-        if (lane == 0 && e < a.Ws) {
-            double tot = 0.0;
-            for (int j = 0; j < 64; ++j)
-                tot += wsum[w][j];
-            a.stot[e] = tot;
+    __syncthreads();
+    for (int e = tid; e < 16 * NV * KP; e += kWT) {
+        const int rl = e / (NV * KP), rem = e % (NV * KP);
+        const int vv = rem / KP, c = rem % KP;
+        float s = 0.f;
+        for (int sp = 0; sp < a.n_split; ++sp)
+            s += a.Ppart[(((int64_t)sp * a.nview + vv) * a.ldr + r0 + rl) * KP + c];
+        if (LDA && lab[rl] >= 0)
+            s = (float)((double)s - a.stot[TRI + KP + lab[rl] * KP + c]);
+        tile[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < NV * KP * 16; e += kWT) {
+        const int m = e / 16, rl = e % 16;
+        uint32_t hi, lo;
+        split_bf16(tile[rl * NV * KP + m], hi, lo);
+        a.Wh[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)hi;
+        a.Wl[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)lo;
+    }
+    if (LDA) {
+        for (int e = tid; e < 16 * 16; e += kWT) {
+            const int c = e / 16, rl = e % 16;
+            a.Wh[(int64_t)(KP + c) * a.ldr + r0 + rl] = lab[rl] == c ? (uint16_t)0x3F80 : (uint16_t)0;
         }
-        __syncthreads();
     }
+    if (q == 0 && tid == 0)
+        a.coef->t += 1.0;
 }
 
 // ---------------------------------------------------------------------------
 // Statistics of a finished 64-feature tile (new players Vn, new auxiliary Gn,
-// LDS, feature-major, KP per row; LDA: class means Mt, 16 x 64): FP64 MFMA
-// (16x16x4) over the tile's features, accumulated in sacc over the subtiles
-// of a workgroup.  Wave w owns statistics tiles w and w + 8.
+// LDS, feature-major with row stride VLD; LDA: class means Mt, 16 x 64): FP64
+// MFMA (16x16x4) over the tile's features, accumulated in sacc over the
+// subtiles of a workgroup (kBW waves).  Wave w owns statistics tiles w,
+// w + kBW, w + 2 kBW, ...
 // ---------------------------------------------------------------------------
+template <int KP, int KIND> struct StatTiles {
+    static constexpr int H = (Shape<KP, KIND>::NST + kBW - 1) / kBW; // tiles per wave
+};
+
 template <int KP, int KIND>
 __device__ __forceinline__ void tile_stats(const float *Vn, const float *Gn, const float *Mt,
-                                           f64x4 (&sacc)[2])
+                                           f64x4 (&sacc)[StatTiles<KP, KIND>::H])
 {
     typedef Shape<KP, KIND> S;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int VLD = S::VLD;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l16 = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int st = w + kNW * h;
+    for (int h = 0; h < StatTiles<KP, KIND>::H; ++h) {
+        const int st = w + kBW * h;
         if (st >= S::NST)
             continue;
         int u, u2;
@@ -358,8 +414,8 @@ __device__ __forceinline__ void tile_stats(const float *Vn, const float *Gn, con
 #pragma unroll 4
         for (int k4 = 0; k4 < kFT; k4 += 4) {
             const int fl = k4 + g;
-            const double av = mv ? (double)Mt[l16 * kFT + fl] : (double)Vn[fl * KP + 16 * u + l16];
-            const double bv = mv ? (double)Vn[fl * KP + 16 * u2 + l16] : (double)Gn[fl * KP + 16 * u2 + l16];
+            const double av = mv ? (double)Mt[l16 * kFT + fl] : (double)Vn[fl * VLD + 16 * u + l16];
+            const double bv = mv ? (double)Vn[fl * VLD + 16 * u2 + l16] : (double)Gn[fl * VLD + 16 * u2 + l16];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
         sacc[h] = acc;
@@ -367,15 +423,16 @@ __device__ __forceinline__ void tile_stats(const float *Vn, const float *Gn, con
 }
 
 template <int KP, int KIND>
-__device__ __forceinline__ void write_stats(const WideArgs &a, int wg, const f64x4 (&sacc)[2],
-                                            double nrm)
+__device__ __forceinline__ void write_stats(const WideArgs &a, int wg,
+                                            const f64x4 (&sacc)[StatTiles<KP, KIND>::H], double nrm)
 {
     typedef Shape<KP, KIND> S;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
     const int l16 = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int st = w + kNW * h;
+    for (int h = 0; h < StatTiles<KP, KIND>::H; ++h) {
+        const int st = w + kBW * h;
         if (st >= S::NST)
             continue;
         if (st < S::NT * (S::NT + 1) / 2) {
@@ -405,12 +462,13 @@ __device__ __forceinline__ void write_stats(const WideArgs &a, int wg, const f64
 
 // Player-major BF16 hi/lo operand of s_f Vn for the 64 features of a tile
 // (two features per thread per pass, one 128-byte run per player).
-template <int KP, int IN>
+template <int KP, int KIND, int IN>
 __device__ __forceinline__ void write_vop(const WideArgs &a, const float *Vn, int64_t frow)
 {
-    for (int e = threadIdx.x; e < KP * (kFT / 2); e += kWT) {
+    constexpr int VLD = Shape<KP, KIND>::VLD;
+    for (int e = threadIdx.x; e < KP * (kFT / 2); e += kBT) {
         const int i = e / (kFT / 2), fl = 2 * (e % (kFT / 2));
-        float x0 = Vn[fl * KP + i], x1 = Vn[(fl + 1) * KP + i];
+        float x0 = Vn[fl * VLD + i], x1 = Vn[(fl + 1) * VLD + i];
         if (IN == kInFP8) {
             x0 *= a.colscale[frow + fl];
             x1 *= a.colscale[frow + fl + 1];
@@ -422,6 +480,16 @@ __device__ __forceinline__ void write_vop(const WideArgs &a, const float *Vn, in
         *reinterpret_cast<uint32_t *>(a.Vh + o) = h0 | (h1 << 16);
         *reinterpret_cast<uint32_t *>(a.Vl + o) = l0 | (l1 << 16);
     }
+}
+
+// |Vn_i|^2 over the tile (threads i < KP), FP64
+template <int KP, int KIND>
+__device__ __forceinline__ void tile_norms(const float *Vn, double &nrm)
+{
+    constexpr int VLD = Shape<KP, KIND>::VLD;
+    if ((int)threadIdx.x < KP)
+        for (int fl = 0; fl < kFT; ++fl)
+            nrm += (double)Vn[fl * VLD + threadIdx.x] * (double)Vn[fl * VLD + threadIdx.x];
 }
 
 __device__ __forceinline__ void wg_range(const WideArgs &a, int wg, int &v, int &sub0, int &sub1)
@@ -436,6 +504,14 @@ __device__ __forceinline__ void wg_range(const WideArgs &a, int wg, int &v, int 
     sub1 = sub0 + a.nsub < a.nsubv[v] ? sub0 + a.nsub : a.nsubv[v];
 }
 
+// One 32-row chunk of the backward stream held in registers: X (8 rows x 4
+// features per lane, raw), the W tiles (hi, lo), and the one-hot tile (LDA).
+template <int NU> struct BwdChunk {
+    u32x2 x[8];
+    u32x4 wh[NU], wl[NU];
+    u32x4 lh;
+};
+
 // ---------------------------------------------------------------------------
 // Backward products, coefficients and fused epilogue.
 // Main loop over 32-row chunks (wave w takes chunks w, w + 8, ...): lane l
@@ -446,22 +522,24 @@ __device__ __forceinline__ void wg_range(const WideArgs &a, int wg, int &v, int 
 // 8 g + 7] in one 16-byte load.  D[m][n] is then (X^T W^T)[4 n + c][m].
 // ---------------------------------------------------------------------------
 template <int KP, int IN, int KIND, int OPT>
-__global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
+__global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
 {
     typedef Shape<KP, KIND> S;
     constexpr int NT = S::NT, NU = S::NU, MWP = S::MWP, SLOT = S::SLOT, TRI = S::TRI;
-    constexpr bool LDA = KIND == kKindLDA;
+    constexpr int GLD = S::GLD, VLD = S::VLD, NG = S::NG;
+    constexpr bool LDA = S::LDA;
     constexpr int NC = LDA ? kMaxCls : 1;
     __shared__ __attribute__((aligned(16))) float red[4 * SLOT];
-    __shared__ float Tl[KP * KP];
+    __shared__ float Tt[KP * KP];   // Tt[j * KP + i] = T_ij (j < i), else 0
     __shared__ double gd[S::GT];
-    __shared__ float cInv[KP], cMB[KP], cMAc[KP];
+    __shared__ float cInv[KP], cMB[KP], cMAc[KP], cUc[KP];
     __shared__ double dInv[KP], dS[KP];
-    __shared__ float cMV[NC * KP], cSp[NC * KP], cU[NC * KP];
+    __shared__ float cSp[NC * KP], cU[NC * KP];
     __shared__ double dMc[NC * KP];
     __shared__ float Mt[NC * kFT], Mb[LDA ? kFT : 1];
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
     const int l16 = lane & 15, g = lane >> 4;
     const int wg = xcd_tile(blockIdx.x, gridDim.x);
     int v, sub0, sub1;
@@ -469,11 +547,17 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
     const int64_t dv = a.dv[v];
     const int64_t ld = v ? a.ldy : a.ldx;
     const uint8_t *Xb = (const uint8_t *)(v ? a.Y : a.X);
+    constexpr int ES = IN == kInBF16 ? 2 : 1;
     const int nch = (int)((a.b + 31) / 32);
     const double t = a.coef->t; // this iteration's number, set by k_wmid
     const double ib = 1.0 / (double)a.b;
+    const uint16_t *Wh = a.Wh + (int64_t)l16 * a.ldr + 8 * g;
+    const uint16_t *Wl = a.Wl + (int64_t)l16 * a.ldr + 8 * g;
 
-    f64x4 sacc[2] = {f64x4{0, 0, 0, 0}, f64x4{0, 0, 0, 0}};
+    f64x4 sacc[StatTiles<KP, KIND>::H];
+#pragma unroll
+    for (int h = 0; h < StatTiles<KP, KIND>::H; ++h)
+        sacc[h] = f64x4{0, 0, 0, 0};
     double nrm = 0.0;
 
     for (int sub = sub0; sub < sub1; ++sub) {
@@ -485,45 +569,59 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
 #pragma unroll
             for (int u = 0; u < NU; ++u)
                 acc[c][u] = f32x4{0.f, 0.f, 0.f, 0.f};
-        f32x4 gacc[LDA ? NT : NT * NT];
+        f32x4 gacc[NG];
 #pragma unroll
-        for (int u = 0; u < (LDA ? NT : NT * NT); ++u)
+        for (int u = 0; u < NG; ++u)
             gacc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-        float dP[NT], dQ[NT], ncnt = 0.f;
+        float dP[NT], dQ[NT];
 #pragma unroll
         for (int u = 0; u < NT; ++u)
             dP[u] = dQ[u] = 0.f;
 
+        // Loads are unconditional, from clamped in-bounds addresses (a chunk past
+        // the minibatch reads the last chunk, a row past it the last row, a
+        // feature unit past the view the last unit); invalid X is zeroed where
+        // it is consumed and an invalid chunk is skipped (wave-uniform), so the
+        // ring of chunks stays in flight.
         const int64_t fu = fv0 + 4 * l16;
         const bool fok = fu < dv;
-        for (int ch = w; ch < nch; ch += kNW) {
+        const uint8_t *xc = Xb + (fok ? fu : dv - 4) * ES;
+
+        auto loadc = [&](int ch, BwdChunk<NU> &B) {
+            const int64_t r0 = (int64_t)(ch < nch ? ch : nch - 1) * 32;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t row = r0 + 8 * g + j < a.b ? r0 + 8 * g + j : a.b - 1;
+                if (IN == kInBF16)
+                    B.x[j] = *reinterpret_cast<const u32x2 *>(xc + row * ld * 2);
+                else
+                    B.x[j] = u32x2{*reinterpret_cast<const uint32_t *>(xc + row * ld), 0u};
+            }
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int64_t wo = (int64_t)16 * u * a.ldr + r0;
+                B.wh[u] = *reinterpret_cast<const u32x4 *>(Wh + wo);
+                B.wl[u] = *reinterpret_cast<const u32x4 *>(Wl + wo);
+            }
+            if (LDA)
+                B.lh = *reinterpret_cast<const u32x4 *>(Wh + (int64_t)KP * a.ldr + r0);
+        };
+        auto compute = [&](int ch, const BwdChunk<NU> &B) {
+            if (ch >= nch)
+                return; // wave-uniform
             const int64_t r0 = (int64_t)ch * 32;
             uint32_t d0[8], d1[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                const int64_t row = r0 + 8 * g + j;
-                const bool ok = fok && row < a.b;
                 if (IN == kInBF16) {
-                    const u32x2 q = ok ? *reinterpret_cast<const u32x2 *>(Xb + 2 * (row * ld + fu))
-                                       : u32x2{0u, 0u};
-                    d0[j] = q[0];
-                    d1[j] = q[1];
+                    d0[j] = B.x[j][0];
+                    d1[j] = B.x[j][1];
                 } else {
-                    const uint32_t q = ok ? *reinterpret_cast<const uint32_t *>(Xb + row * ld + fu) : 0u;
-                    fp8x4_to_bf16(q, d0[j], d1[j]);
+                    fp8x4_to_bf16(B.x[j][0], d0[j], d1[j]);
                 }
+                if (!(fok && r0 + 8 * g + j < a.b))
+                    d0[j] = d1[j] = 0u;
             }
-            u32x4 wh[NU], wl[NU];
-#pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                const int64_t wo = (int64_t)(16 * u + l16) * a.ldr + r0 + 8 * g;
-                wh[u] = *reinterpret_cast<const u32x4 *>(a.Wh + wo);
-                if (!(LDA && u == NT))
-                    wl[u] = *reinterpret_cast<const u32x4 *>(a.Wl + wo);
-                else
-                    wl[u] = u32x4{0u, 0u, 0u, 0u};
-            }
-            __builtin_amdgcn_sched_barrier(0);
             u32x4 bx[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -538,9 +636,8 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
             for (int c = 0; c < 4; ++c)
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
-                    acc[c][u] = mfma_bf16(wh[u], bx[c], acc[c][u]);
-                    if (!(LDA && u == NT))
-                        acc[c][u] = mfma_bf16(wl[u], bx[c], acc[c][u]);
+                    acc[c][u] = mfma_bf16(B.wh[u], bx[c], acc[c][u]);
+                    acc[c][u] = mfma_bf16(B.wl[u], bx[c], acc[c][u]);
                 }
             if (first) {
                 // Gram terms from the W fragments: lane (m, g) holds rows 8g..8g+7 of
@@ -552,65 +649,65 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
 #pragma unroll
                         for (int uq = 0; uq < NT; ++uq) {
                             f32x4 &ga = gacc[up * NT + uq];
-                            ga = mfma_bf16(wh[up], wh[NT + uq], ga);
-                            ga = mfma_bf16(wh[up], wl[NT + uq], ga);
-                            ga = mfma_bf16(wl[up], wh[NT + uq], ga);
+                            ga = mfma_bf16(B.wh[up], B.wh[NT + uq], ga);
+                            ga = mfma_bf16(B.wh[up], B.wl[NT + uq], ga);
+                            ga = mfma_bf16(B.wl[up], B.wh[NT + uq], ga);
                         }
                 } else {
 #pragma unroll
                     for (int u = 0; u < NT; ++u) {
-                        gacc[u] = mfma_bf16(wh[NT], wh[u], gacc[u]);
-                        gacc[u] = mfma_bf16(wh[NT], wl[u], gacc[u]);
+                        gacc[u] = mfma_bf16(B.lh, B.wh[u], gacc[u]);
+                        gacc[u] = mfma_bf16(B.lh, B.wl[u], gacc[u]);
                     }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        ncnt += bf16_val(wh[NT][q] & 0xFFFFu) + bf16_val(wh[NT][q] >> 16);
                 }
 #pragma unroll
                 for (int u = 0; u < NT; ++u)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const float p0 = bf16_val(wh[u][q] & 0xFFFFu) + bf16_val(wl[u][q] & 0xFFFFu);
-                        const float p1 = bf16_val(wh[u][q] >> 16) + bf16_val(wl[u][q] >> 16);
+                        const float p0 = bf16_val(B.wh[u][q] & 0xFFFFu) + bf16_val(B.wl[u][q] & 0xFFFFu);
+                        const float p1 = bf16_val(B.wh[u][q] >> 16) + bf16_val(B.wl[u][q] >> 16);
                         dP[u] += p0 * p0 + p1 * p1;
                         if (!LDA) {
-                            const float q0 = bf16_val(wh[NT + u][q] & 0xFFFFu) + bf16_val(wl[NT + u][q] & 0xFFFFu);
-                            const float q1 = bf16_val(wh[NT + u][q] >> 16) + bf16_val(wl[NT + u][q] >> 16);
+                            const float q0 = bf16_val(B.wh[NT + u][q] & 0xFFFFu) +
+                                             bf16_val(B.wl[NT + u][q] & 0xFFFFu);
+                            const float q1 = bf16_val(B.wh[NT + u][q] >> 16) + bf16_val(B.wl[NT + u][q] >> 16);
                             dQ[u] += q0 * q0 + q1 * q1;
                         }
                     }
             }
+        };
+        // ring of NB chunks in flight: the loads of chunk i + NB - 1 are issued
+        // before the MFMAs of chunk i (wave w takes chunks w, w + kBW, ...)
+        constexpr int NB = 3;
+        BwdChunk<NU> cb[NB];
+#pragma unroll
+        for (int p = 0; p < NB - 1; ++p)
+            loadc(w + kBW * p, cb[p]);
+        for (int ch = w; ch < nch; ch += NB * kBW) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                loadc(ch + kBW * (q + NB - 1), cb[(q + NB - 1) % NB]);
+                __builtin_amdgcn_sched_barrier(0);
+                compute(ch + kBW * q, cb[q]);
+            }
         }
 
-        // ---- products: eight waves -> prod = slot 0, element (feature, m) ----
-        if (w >= 4) {
+        // ---- products: four waves -> prod = slot 0, element (feature, m) ----
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int u = 0; u < NU; ++u)
-                    *reinterpret_cast<f32x4 *>(&red[(w - 4) * SLOT + (4 * l16 + c) * MWP + 16 * u + 4 * g]) =
-                        acc[c][u];
-        }
+            for (int u = 0; u < NU; ++u)
+                *reinterpret_cast<f32x4 *>(&red[w * SLOT + (4 * l16 + c) * MWP + 16 * u + 4 * g]) = acc[c][u];
         __syncthreads();
-        if (w < 4) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    f32x4 *p = reinterpret_cast<f32x4 *>(&red[w * SLOT + (4 * l16 + c) * MWP + 16 * u + 4 * g]);
-                    *p = acc[c][u] + *p;
-                }
-        }
-        __syncthreads();
-        for (int e = tid; e < kFT * S::MW; e += kWT) {
-            const int idx = (e / S::MW) * MWP + e % S::MW;
+        for (int e = tid; e < kFT * S::MWA; e += kBT) {
+            const int idx = (e / S::MWA) * MWP + e % S::MWA;
             red[idx] = ((red[idx] + red[SLOT + idx]) + red[2 * SLOT + idx]) + red[3 * SLOT + idx];
         }
         __syncthreads();
         float *ext = red + SLOT; // three free slots from here on
 
         if (first) {
-            // ---- Gram terms: eight waves x lane groups, fixed-order sum ----
+            // ---- Gram terms: four waves x lane groups, fixed-order sum ----
             float *gw = ext + w * S::GW;
             if (!LDA) {
 #pragma unroll
@@ -634,36 +731,19 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
 #pragma unroll
                 for (int u = 0; u < NT; ++u)
                     gw[16 * KP + g * KP + 16 * u + l16] = dP[u];
-                gw[20 * KP + g * 16 + l16] = ncnt;
             }
             __syncthreads();
-            for (int e = tid; e < S::GT; e += kWT) {
+            for (int e = tid; e < S::GT; e += kBT) {
                 double s = 0.0;
-                if (!LDA) {
-                    if (e < KP * KP) {
-                        for (int ww = 0; ww < kNW; ++ww)
-                            s += (double)ext[ww * S::GW + e];
-                    } else {
-                        const int which = (e - KP * KP) / KP, col = (e - KP * KP) % KP;
-                        for (int ww = 0; ww < kNW; ++ww)
-                            for (int gg = 0; gg < 4; ++gg)
-                                s += (double)ext[ww * S::GW + KP * KP + which * 4 * KP + gg * KP + col];
-                    }
+                const int base = LDA ? 16 * KP : KP * KP;
+                if (e < base) {
+                    for (int ww = 0; ww < kBW; ++ww)
+                        s += (double)ext[ww * S::GW + e];
                 } else {
-                    if (e < 16 * KP) {
-                        for (int ww = 0; ww < kNW; ++ww)
-                            s += (double)ext[ww * S::GW + e];
-                    } else if (e < 17 * KP) {
-                        const int col = e - 16 * KP;
-                        for (int ww = 0; ww < kNW; ++ww)
-                            for (int gg = 0; gg < 4; ++gg)
-                                s += (double)ext[ww * S::GW + 16 * KP + gg * KP + col];
-                    } else {
-                        const int c = e - 17 * KP;
-                        for (int ww = 0; ww < kNW; ++ww)
-                            for (int gg = 0; gg < 4; ++gg)
-                                s += (double)ext[ww * S::GW + 20 * KP + gg * 16 + c];
-                    }
+                    const int which = (e - base) / KP, col = (e - base) % KP;
+                    for (int ww = 0; ww < kBW; ++ww)
+                        for (int gg = 0; gg < 4; ++gg)
+                            s += (double)ext[ww * S::GW + base + which * 4 * KP + gg * KP + col];
                 }
                 gd[e] = s;
             }
@@ -671,7 +751,7 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
 
             // ---- k x k coefficients (identical in every workgroup) ----
             double *ss = reinterpret_cast<double *>(ext);
-            for (int e = tid; e < a.Ws; e += kWT)
+            for (int e = tid; e < a.Ws; e += kBT)
                 ss[e] = a.stot[e];
             __syncthreads();
             if (tid < KP) {
@@ -688,22 +768,15 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
             }
             __syncthreads();
             if (LDA) {
-                // raw M V, the class-sum terms, and the centred normalised class-mean
-                // projections Mc_ci = (mu_c - mubar)^T v_i (FP64) with cU = pi_c Mc_ci
-                for (int e = tid; e < kMaxCls * KP; e += kWT) {
+                // class sums S = L^T R (raw) and the centred normalised class-mean
+                // projections Mc_ci = (mu_c - mubar)^T v_i (FP64), cU = pi_c Mc_ci
+                for (int e = tid; e < kMaxCls * KP; e += kBT) {
                     const int c = e / KP, i = e % KP;
-                    float mv = 0.f, sp = 0.f;
-                    if (c < a.ncls && i < a.k) {
-                        const double mvr = ss[TRI + KP + c * KP + i];
-                        mv = (float)mvr;
-                        sp = (float)(gd[c * KP + i] - gd[17 * KP + c] * mvr);
-                    }
-                    cMV[e] = mv;
-                    cSp[e] = sp;
+                    cSp[e] = (c < a.ncls && i < a.k) ? (float)gd[e] : 0.f;
                 }
                 if (tid < KP) {
                     const int i = tid;
-                    double mbar = 0.0;
+                    double mbar = 0.0, usum = 0.0;
                     if (i < a.k)
                         for (int c = 0; c < a.ncls; ++c)
                             mbar += a.prior[c] * ss[TRI + KP + c * KP + i] * dInv[i];
@@ -712,8 +785,11 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
                         if (c < a.ncls && i < a.k)
                             mc = ss[TRI + KP + c * KP + i] * dInv[i] - mbar;
                         dMc[c * KP + i] = mc;
-                        cU[c * KP + i] = (float)((c < a.ncls ? a.prior[c] : 0.0) * mc);
+                        const float u = (float)((c < a.ncls ? a.prior[c] : 0.0) * mc);
+                        cU[c * KP + i] = u;
+                        usum += (double)u;
                     }
+                    cUc[i] = (float)usum;
                 }
             }
             __syncthreads();
@@ -726,12 +802,12 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
                     s += a.prior[c] * dMc[c * KP + i] * dMc[c * KP + j];
                 return s;
             };
-            for (int e = tid; e < KP * KP; e += kWT) {
-                const int i = e / KP, j = e % KP;
+            for (int e = tid; e < KP * KP; e += kBT) {
+                const int j = e / KP, i = e % KP;
                 double val = 0.0;
                 if (i < a.k && j < i)
                     val = MA(i, j) / dS[j];
-                Tl[e] = (float)val;
+                Tt[e] = (float)val;
             }
             Coef *cw = a.coef;
             if (tid < KP) {
@@ -740,16 +816,10 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
                 if (i < a.k) {
                     const double ii2 = dInv[i] * dInv[i];
                     mA = MA(i, i);
-                    if (!LDA) {
+                    if (!LDA)
                         mB = (gd[KP * KP + i] + gd[KP * KP + KP + i]) * ii2 * ib;
-                    } else {
-                        double q = gd[16 * KP + i];
-                        for (int cc = 0; cc < a.ncls; ++cc) {
-                            const double mvr = ss[TRI + KP + cc * KP + i];
-                            q += -2.0 * mvr * gd[cc * KP + i] + gd[17 * KP + cc] * mvr * mvr;
-                        }
-                        mB = q * ii2 * ib + a.eps_reg;
-                    }
+                    else
+                        mB = gd[16 * KP + i] * ii2 * ib + a.eps_reg;
                     for (int j = 0; j < i; ++j)
                         c += MA(i, j) / dS[j] * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
                 }
@@ -780,17 +850,17 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
             __syncthreads();
         }
 
-        // ---- fused epilogue over the subtile's 64 features x KP players ----
+        // ---- fused epilogue on 16 x 16 tiles (feature block fb, player block pb) ----
         const int64_t frow = a.off[v] + fv0; // state row of the subtile's first feature
-        float *Gold = ext, *Vn = ext + kFT * KP, *Gn = ext + 2 * kFT * KP;
-        for (int e = tid; e < kFT * KP; e += kWT)
-            Gold[e] = a.G[frow * KP + e];
+        float *Gold = ext, *Vn = ext + kFT * GLD, *Gn = Vn + kFT * VLD;
+        for (int e = tid; e < kFT * KP; e += kBT)
+            Gold[(e / KP) * GLD + e % KP] = a.G[frow * KP + e];
         if (LDA) {
-            for (int e = tid; e < kMaxCls * kFT; e += kWT) {
+            for (int e = tid; e < kMaxCls * kFT; e += kBT) {
                 const int c = e / kFT, fl = e % kFT;
                 Mt[e] = c < a.ncls ? a.M[(int64_t)c * a.dtot + frow + fl] : 0.f;
             }
-            for (int e = tid; e < kFT; e += kWT)
+            for (int e = tid; e < kFT; e += kBT)
                 Mb[e] = a.Mbar[frow + e];
         }
         __syncthreads();
@@ -798,57 +868,67 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
         const float eps = (float)a.eps_reg;
         const float b1 = (float)a.adam_b1, b2 = (float)a.adam_b2, aeps = (float)a.adam_eps;
         const float c1 = (float)(1.0 - pow(a.adam_b1, t)), c2 = (float)(1.0 - pow(a.adam_b2, t));
-        for (int e = tid; e < kFT * KP; e += kWT) {
-            const int fl = e / KP, i = e % KP;
-            const int64_t si = frow * KP + e;
-            float vn = 0.f, gn = 0.f;
-            if (fv0 + fl < dv && i < a.k) {
-                const float inv = cInv[i];
-                const float vh = a.V[si] * inv;
-                const float *pr = red + fl * MWP;
-                float av, bv;
-                if (!LDA) {
-                    const float sf = IN == kInFP8 ? a.colscale[frow + fl] : 1.f;
-                    const float rawA = v == 0 ? pr[KP + i] : pr[i];
-                    const float rawB = v == 0 ? pr[i] : pr[KP + i];
-                    av = rawA * sf * inv * ibf;
-                    bv = rawB * sf * inv * ibf;
-                } else {
-                    float corr = 0.f, ma = 0.f;
-                    for (int c = 0; c < a.ncls; ++c) {
-                        corr += pr[KP + c] * cMV[c * KP + i] + Mt[c * kFT + fl] * cSp[c * KP + i];
-                        ma += (Mt[c * kFT + fl] - Mb[fl]) * cU[c * KP + i];
-                    }
-                    bv = (pr[i] - corr) * inv * ibf + eps * vh;
-                    av = ma;
+        for (int tt = w; tt < 4 * NT; tt += kBW) {
+            const int fb = tt / NT, pb = tt % NT;
+            // parent penalty sum_j G_old[fl][j] T_ij, and (LDA) the class terms
+            // sum_c M[c][fl] S_ci and sum_c M[c][fl] U_ci: FP32 MFMA 16x16x4
+            f32x4 pen = {0.f, 0.f, 0.f, 0.f}, e2 = pen, e3 = pen;
+#pragma unroll 4
+            for (int j0 = 0; j0 < KP; j0 += 4)
+                pen = __builtin_amdgcn_mfma_f32_16x16x4f32(Gold[(16 * fb + l16) * GLD + j0 + g],
+                                                          Tt[(j0 + g) * KP + 16 * pb + l16], pen, 0, 0, 0);
+            if (LDA) {
+#pragma unroll
+                for (int c0 = 0; c0 < kMaxCls; c0 += 4) {
+                    const float mA_ = Mt[(c0 + g) * kFT + 16 * fb + l16];
+                    e2 = __builtin_amdgcn_mfma_f32_16x16x4f32(mA_, cSp[(c0 + g) * KP + 16 * pb + l16], e2, 0, 0, 0);
+                    e3 = __builtin_amdgcn_mfma_f32_16x16x4f32(mA_, cU[(c0 + g) * KP + 16 * pb + l16], e3, 0, 0, 0);
                 }
-                float pen = 0.f;
-                for (int j = 0; j < i; ++j)
-                    pen += Tl[i * KP + j] * Gold[fl * KP + j];
-                const float grad = (av - pen) * cMB[i] - bv * cMAc[i];
-                if (OPT == kOptSGD) {
-                    vn = vh + eta * grad;
-                } else {
-                    const float mm = b1 * a.Am[si] + (1.f - b1) * grad;
-                    const float sq = b2 * a.As[si] + (1.f - b2) * grad * grad;
-                    a.Am[si] = mm;
-                    a.As[si] = sq;
-                    vn = vh + eta * (mm / c1) / (sqrtf(sq / c2) + aeps);
-                }
-                const float g0 = Gold[e];
-                gn = g0 + gam * (bv - g0);
-                a.V[si] = vn;
-                a.G[si] = gn;
             }
-            Vn[e] = vn;
-            Gn[e] = gn;
+            const int i = 16 * pb + l16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int fl = 16 * fb + 4 * g + r; // FP32 D row 4 (l/16) + r
+                const int64_t si = (frow + fl) * KP + i;
+                float vn = 0.f, gn = 0.f;
+                if (fv0 + fl < dv && i < a.k) {
+                    const float inv = cInv[i];
+                    const float vh = a.V[si] * inv;
+                    const float *pr = red + fl * MWP;
+                    float av, bv;
+                    if (!LDA) {
+                        const float sf = IN == kInFP8 ? a.colscale[frow + fl] : 1.f;
+                        const float rawA = v == 0 ? pr[KP + i] : pr[i];
+                        const float rawB = v == 0 ? pr[i] : pr[KP + i];
+                        av = rawA * sf * inv * ibf;
+                        bv = rawB * sf * inv * ibf;
+                    } else {
+                        bv = (pr[i] - e2[r]) * inv * ibf + eps * vh;
+                        av = e3[r] - Mb[fl] * cUc[i];
+                    }
+                    const float grad = (av - pen[r]) * cMB[i] - bv * cMAc[i];
+                    if (OPT == kOptSGD) {
+                        vn = vh + eta * grad;
+                    } else {
+                        const float mm = b1 * a.Am[si] + (1.f - b1) * grad;
+                        const float sq = b2 * a.As[si] + (1.f - b2) * grad * grad;
+                        a.Am[si] = mm;
+                        a.As[si] = sq;
+                        vn = vh + eta * (mm / c1) / (sqrtf(sq / c2) + aeps);
+                    }
+                    const float g0 = Gold[fl * GLD + i];
+                    gn = g0 + gam * (bv - g0);
+                    a.V[si] = vn;
+                    a.G[si] = gn;
+                }
+                Vn[fl * VLD + i] = vn;
+                Gn[fl * VLD + i] = gn;
+            }
         }
         __syncthreads();
-        write_vop<KP, IN>(a, Vn, frow);
+        write_vop<KP, KIND, IN>(a, Vn, frow);
         tile_stats<KP, KIND>(Vn, Gn, Mt, sacc);
-        if (tid < KP)
-            for (int fl = 0; fl < kFT; ++fl)
-                nrm += (double)Vn[fl * KP + tid] * (double)Vn[fl * KP + tid];
+        tile_norms<KP, KIND>(Vn, nrm);
         __syncthreads();
     }
     write_stats<KP, KIND>(a, wg, sacc, nrm);
@@ -860,40 +940,42 @@ __global__ void __launch_bounds__(kWT) k_wbwd(WideArgs a)
 // first statistics.
 // ---------------------------------------------------------------------------
 template <int KP, int IN, int KIND>
-__global__ void __launch_bounds__(kWT) k_winit(WideArgs a)
+__global__ void __launch_bounds__(kBT) k_winit(WideArgs a)
 {
-    __shared__ float Vn[kFT * KP];
+    constexpr int VLD = Shape<KP, KIND>::VLD;
+    __shared__ float Vn[kFT * VLD];
     __shared__ float Mt[(KIND == kKindLDA ? kMaxCls : 1) * kFT];
     const int tid = threadIdx.x;
     const int wg = blockIdx.x;
     int v, sub0, sub1;
     wg_range(a, wg, v, sub0, sub1);
-    f64x4 sacc[2] = {f64x4{0, 0, 0, 0}, f64x4{0, 0, 0, 0}};
+    f64x4 sacc[StatTiles<KP, KIND>::H];
+#pragma unroll
+    for (int h = 0; h < StatTiles<KP, KIND>::H; ++h)
+        sacc[h] = f64x4{0, 0, 0, 0};
     double nrm = 0.0;
     for (int sub = sub0; sub < sub1; ++sub) {
         const int64_t frow = a.off[v] + (int64_t)sub * kFT;
-        for (int e = tid; e < kFT * KP; e += kWT) {
+        for (int e = tid; e < kFT * KP; e += kBT) {
             const float x = a.V[frow * KP + e];
-            Vn[e] = x;
+            Vn[(e / KP) * VLD + e % KP] = x;
             a.G[frow * KP + e] = x;
         }
         if (KIND == kKindLDA)
-            for (int e = tid; e < kMaxCls * kFT; e += kWT) {
+            for (int e = tid; e < kMaxCls * kFT; e += kBT) {
                 const int c = e / kFT, fl = e % kFT;
                 Mt[e] = c < a.ncls ? a.M[(int64_t)c * a.dtot + frow + fl] : 0.f;
             }
         __syncthreads();
-        write_vop<KP, IN>(a, Vn, frow);
+        write_vop<KP, KIND, IN>(a, Vn, frow);
         tile_stats<KP, KIND>(Vn, Vn, Mt, sacc);
-        if (tid < KP)
-            for (int fl = 0; fl < kFT; ++fl)
-                nrm += (double)Vn[fl * KP + tid] * (double)Vn[fl * KP + tid];
+        tile_norms<KP, KIND>(Vn, nrm);
         __syncthreads();
     }
     write_stats<KP, KIND>(a, wg, sacc, nrm);
 }
 
-// Read-out after k_wmid(stats_only): out[i * d + f] (column-major FP64) =
+// Read-out after k_wstats: out[i * d + f] (column-major FP64) =
 // scale_i * S[row(f) * KP + i], scale as in k_readout (mode 0: 1, 1: 1/||V_i||,
 // 2: additionally 1/sqrt(s_i)); row(f) maps feature f of the concatenated
 // views to its state row.
