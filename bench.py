@@ -10,7 +10,9 @@ hipGraph that holds one pass over the ring.
 
 Other workloads (``--workload``): the FP64 tiny CCA, the large CCA
 (8192 + 8192 activation-like views, k = 32, b = 4096) in BF16, FP8-e4m3 and
-FP32, and the large LDA (d = 65536, 10 classes, k = 64, b = 2048) in BF16.
+FP32, the large LDA (d = 65536, 10 classes, k = 64, b = 2048) in BF16, and
+256 independent general instances (d uniform in [64, 2048], k = 8, b = 512)
+advanced together in FP32.
 
 Prints ONE JSON line.  Usage:
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
@@ -73,12 +75,26 @@ WORKLOADS = {
         describe="LDA BF16: d=65536, 10 Gaussian classes with means on a random 64-dim "
                  "subspace, within-class B + 1e-4 I, k=64, minibatch 2048"),
 }
+# many independent GENERAL instances advanced together (widths uniform in
+# [64, 2048], planted generalized eigenvalues geomspace(10, 0.1, 8), B ridge
+# 1e-3); minibatches drawn on the device
+BATCH_WORKLOADS = {
+    "batch256_general_d64-2048_k8_b512_fp32": dict(
+        kind="batch", dtype="f32", n=256, lo=64, hi=2048, k=8, b=512, ring=2,
+        optimizer="adam", schedule="inv", eta0=1e-3, t0=3000.0, gamma=0.3, rho=1e-6,
+        eps_reg=1e-3,
+        describe="256 independent general SGEP instances (A = E[yy^T], B = E[xx^T] + 1e-3 I), "
+                 "d uniform in [64, 2048], k=8, minibatch 512, FP32, one batched iteration "
+                 "per step in the autotuned launch plan"),
+}
 DEFAULT = "cca_d1024_k16_b1024_fp32"
 
 # kernels of one iteration, in launch order, and the header holding their code
 KERNELS = {False: ("k_fwd", "k_bwd"), True: ("k_wfwd", "k_wmid", "k_wbwd")}
 KERNEL_HEADER = {"k_fwd": "sgep_kernels.hpp", "k_bwd": "sgep_kernels.hpp",
-                 "k_wfwd": "sgep_wide.hpp", "k_wmid": "sgep_wide.hpp", "k_wbwd": "sgep_wide.hpp"}
+                 "k_wfwd": "sgep_wide.hpp", "k_wmid": "sgep_wide.hpp", "k_wbwd": "sgep_wide.hpp",
+                 "k_bfwd": ("sgep_kernels.hpp", "sgep_batch.hpp"),
+                 "k_bbwd": ("sgep_kernels.hpp", "sgep_batch.hpp")}
 
 
 def hip_runtime():
@@ -92,12 +108,14 @@ def hip_runtime():
     return lib
 
 
-def kernel_source_hash(header: str = "sgep_kernels.hpp") -> str:
-    """Hash of the device code of one kernel family (its header under csrc/);
-    the launch grids the counters were taken with are in the same summary."""
+def kernel_source_hash(header="sgep_kernels.hpp") -> str:
+    """Hash of the device code of one kernel family (its header, or headers,
+    under csrc/); the launch grids the counters were taken with are in the
+    same summary."""
     import hashlib
     h = hashlib.sha256()
-    h.update(open(os.path.join(ROOT, "paper_2206_04993_amd", "csrc", header), "rb").read())
+    for name in ((header,) if isinstance(header, str) else header):
+        h.update(open(os.path.join(ROOT, "paper_2206_04993_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -240,12 +258,182 @@ def cpu_baseline(w, budget_s: float, host):
                       f"on the values the GPU receives, FP64 oracle, {el:.1f} s wall"}
 
 
+def run_batch(args, w):
+    """The many-instance workload: value = instance-samples/s (n b per step)."""
+    import torch
+    import paper_2206_04993_amd as sg
+    import synth
+
+    sg.load()
+    n, k, b, R = w["n"], w["k"], w["b"], w["ring"]
+    K = args.steps if args.steps is not None else 128
+    W = args.warmup if args.warmup is not None else 8
+    gens = synth.batched_general(n, w["lo"], w["hi"], k, w["eps_reg"], seed=0)
+    dims = [g.d for g in gens]
+    print(f"bench: drawing {R} minibatches of {n} instances on the device", file=sys.stderr,
+          flush=True)
+    ring = []
+    for t in range(1, R + 1):
+        xs, ys = [], []
+        for g in gens:
+            x, y = g.sample_torch(b, t, "cuda", torch.float32)
+            xs.append(x.contiguous())
+            ys.append(y.contiguous())
+        ring.append((xs, ys, sg.BatchSolver.pointers(xs, "cuda"),
+                     sg.BatchSolver.pointers(ys, "cuda")))
+    torch.cuda.synchronize()
+    cfg = sg.make_config(sg.SGEP_KIND_GENERAL, sg.SGEP_F32, k, 0, 0, b,
+                         optimizer=sg.SGEP_ADAM if w["optimizer"] == "adam" else sg.SGEP_SGD,
+                         schedule=sg.SGEP_SCHED_INV, eta0=w["eta0"], t0=w["t0"],
+                         gamma=w["gamma"], rho=w["rho"], eps_reg=w["eps_reg"])
+    stream = torch.cuda.Stream()
+    V0s = [synth.initial_players(d, k, 1000 + i) for i, d in enumerate(dims)]
+    bat = sg.BatchSolver(dims, cfg, V0s, stream=stream)
+    tune_us = bat.tune(ring[0][2], ring[0][3], b, reps=3)
+    groups, mb = bat.plan()
+    print(f"bench: tuned plan groups={groups} tile heights={mb} ({tune_us:.1f} us)",
+          file=sys.stderr, flush=True)
+
+    def step(t):
+        bat.step(ring[t % R][2], ring[t % R][3], b)
+
+    with torch.cuda.stream(stream):
+        for t in range(W):
+            step(t)
+    torch.cuda.synchronize()
+    chunk = min(K, R)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for t in range(chunk):
+            step(t)
+    torch.cuda.synchronize()
+    n_rep, rem = divmod(K, chunk)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_rep):
+        g.replay()
+    with torch.cuda.stream(stream):
+        for t in range(rem):
+            step(t)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / K
+    value = n * b / (ms_per_step * 1e-3)
+
+    # per-launch durations (events stamped by each kernel's dispatch)
+    kinds = bat.launches()
+    hip = hip_runtime()
+    Kp = min(K, 64)
+    ne = 2 * len(kinds)
+    evs = [ctypes.c_void_p() for _ in range(ne * Kp)]
+    for e in evs:
+        assert hip.hipEventCreate(ctypes.byref(e)) == 0
+    torch.cuda.synchronize()
+    for t in range(Kp):
+        sg.sgep_batch_step_profiled(bat.bt, ring[t % R][2], ring[t % R][3], b,
+                                    [evs[ne * t + i].value for i in range(ne)])
+    torch.cuda.synchronize()
+    ms = ctypes.c_float()
+    fwd_us, bwd_us = [], []
+    for t in range(Kp):
+        f = bb = 0.0
+        for i, kd in enumerate(kinds):
+            assert hip.hipEventElapsedTime(ctypes.byref(ms), evs[ne * t + 2 * i],
+                                           evs[ne * t + 2 * i + 1]) == 0
+            if kd == 0:
+                f += ms.value * 1e3
+            else:
+                bb += ms.value * 1e3
+        fwd_us.append(f)
+        bwd_us.append(bb)
+    for e in evs:
+        hip.hipEventDestroy(e)
+    bat.sync()
+    # algorithmic HBM bytes: one read of both minibatch views of every
+    # instance, plus the FP32 state each kernel must touch
+    D = float(sum(dims))
+    adam = w["optimizer"] == "adam"
+    data = 2.0 * b * D * 4
+    fwd_bytes = data + 4 * D * 16 + 2 * 4 * b * 16 * n          # X, Y; V (KP = 16); P, Q out
+    bwd_bytes = data + (4 + (4 if adam else 0)) * 4 * D * 16 + 2 * 4 * b * 16 * n
+    step_bytes = data + (4 + (4 if adam else 0)) * 4 * D * k
+    avg_f, avg_b = float(np.mean(fwd_us)), float(np.mean(bwd_us))
+    dom, dom_us, dom_bytes = ("k_bbwd", avg_b, bwd_bytes) if avg_b >= avg_f else (
+        "k_bfwd", avg_f, fwd_bytes)
+    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 5),
+                "traffic": measured_traffic(args.workload, dom),
+                "kernel": dom, "kernel_avg_us": round(dom_us, 3),
+                "kernel_note": "sum over the step's launches of this kernel",
+                "kernels_avg_us": {"k_bfwd": round(avg_f, 3), "k_bbwd": round(avg_b, 3)},
+                "algorithmic_hbm_bytes_per_launch": dom_bytes,
+                "step_algorithmic_hbm_bytes": step_bytes,
+                "step_hbm_frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)}
+    out = {
+        "metric": "samples/s per gamma-EigenGame step",
+        "value": round(value, 1),
+        "unit": "instance-samples/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": f"synthetic: ring of {R} minibatches per instance drawn on the device",
+        "config": {"workload": args.workload, "description": w["describe"], "instances": n,
+                   "sum_d": int(D), "k": k, "minibatch": b, "optimizer": w["optimizer"],
+                   "plan": {"groups": groups, "tile_heights": mb, "launches": len(kinds)},
+                   "graph_steps": chunk, "parallelism": "single GPU"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(w, gens, dims, V0s, ring, args.cpu_budget)
+    bat.close()
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline_batch(w, gens, dims, V0s, ring, budget_s):
+    """The FP64 oracle on the many-instance workload: whole iterations over
+    every instance (the values the GPU received) until budget_s is spent."""
+    import oracle
+    pbs = {}
+    states = [oracle.State.init(V0, adam=w["optimizer"] == "adam") for V0 in V0s]
+    host = [[(x.double().cpu().numpy(), y.double().cpu().numpy()) for x, y in zip(r[0], r[1])]
+            for r in ring]
+    n_it = 0
+    t0 = time.perf_counter()
+    while True:
+        eta = oracle.eta(oracle.SCHED_INV, n_it + 1, w["eta0"], t0=w["t0"])
+        for i, d in enumerate(dims):
+            pb = pbs.get(d)
+            if pb is None:
+                pb = pbs[d] = oracle.Problem(
+                    oracle.KIND_GENERAL, w["k"], d, d, rho=w["rho"], eps_reg=w["eps_reg"],
+                    optimizer=oracle.OPT_ADAM if w["optimizer"] == "adam" else oracle.OPT_SGD)
+            X, Y = host[n_it % len(host)][i]
+            oracle.gamma_step(pb, states[i], X, Y, eta, w["gamma"])
+        n_it += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    n = len(dims)
+    return {"value": n_it * n * w["b"] / el, "unit": "instance-samples/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{n_it} whole iteration(s) of all {n} instances ({n_it * n * w['b']} "
+                      f"instance-samples) on the values the GPU received, FP64 oracle, "
+                      f"{el:.1f} s wall"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default per workload)")
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) +
+                    sorted(BATCH_WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
@@ -262,6 +450,9 @@ def main():
 
     sg.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload in BATCH_WORKLOADS:
+        run_batch(args, BATCH_WORKLOADS[args.workload])
+        return
     w = WORKLOADS[args.workload]
     big = w["b"] * (w["dx"] + w["dy"]) > 1 << 24
     K = args.steps if args.steps is not None else (256 if big else 2048)

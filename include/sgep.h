@@ -218,6 +218,93 @@ sgep_status sgep_set_state(sgep_handle *h, const void *host_buf, size_t bytes);
 /* Release every resource of the handle (synchronises its stream first). */
 sgep_status sgep_destroy(sgep_handle *h);
 
+/* ------------------------------------------------------------------------
+ * Batched instances.  Many independent problems of kind GENERAL that share
+ * the configuration (k, dtype, optimiser, schedule, hyperparameters, b_max)
+ * but not the width d are advanced together: one iteration of Alg. 2 for
+ * every instance per sgep_batch_step, enqueued as a short fixed sequence of
+ * launches on one stream (capturable in a hipGraph).  Each instance computes
+ * exactly what a single handle of width d_i computes; an instance advanced by
+ * the batch holds the same bits as the same instance advanced alone with the
+ * same feature-tile height.  Not part of the paper, whose parallelism is over
+ * players and machines (Sec. 3, App. F): a throughput form for many small
+ * problems on one GPU.
+ * ------------------------------------------------------------------------ */
+typedef struct sgep_batch_s sgep_batch;
+
+/* Create n >= 1 instances (n <= 65535).
+ *   d       : host, n widths d_i >= common->k
+ *   ld      : host, n leading dimensions ld_i >= d_i (elements) of the rows of
+ *             instance i's views; a multiple of 16 bytes / element size
+ *             enables 16-byte loads (with 16-byte aligned views)
+ *   common  : kind SGEP_KIND_GENERAL, dtype SGEP_F32 or SGEP_F64; dx and dy are
+ *             ignored (each instance uses dx = dy = d_i); validated as by
+ *             sgep_init for every instance
+ *   V0      : host, n pointers to d_i x k column-major starting points
+ *   hip_stream : the stream of every instance
+ * The initial launch plan is one group with 16-feature backward tiles.
+ * Errors: as sgep_init; SGEP_EUNSUPPORTED for another kind or dtype. */
+sgep_status sgep_batch_init(sgep_batch **out, int32_t n, const int64_t *d, const int64_t *ld,
+                            const sgep_config *common, const double *const *V0,
+                            void *hip_stream);
+
+/* Borrowed handle of instance i (0 <= i < n) for the read-out and checkpoint
+ * calls (sgep_eigvals, sgep_vectors, sgep_auxiliary, sgep_step_count,
+ * sgep_get_state / sgep_set_state, sgep_sync) and for stepping the instance
+ * alone with sgep_step.  Never pass it to sgep_destroy. */
+sgep_status sgep_batch_instance(sgep_batch *bt, int32_t i, sgep_handle **h);
+
+/* Enqueue one iteration for every instance.
+ *   X, Y : DEVICE arrays of n device pointers; instance i reads the b x d_i
+ *          row-major views X[i], Y[i] with leading dimension ld_i
+ *   1 <= b <= b_max (common to all instances)
+ * Returns synchronously only argument errors, and SGEP_EPOISONED when any
+ * instance is poisoned.  No allocation, synchronisation or host copy. */
+sgep_status sgep_batch_step(sgep_batch *bt, const void *const *X, const void *const *Y,
+                            int64_t b);
+
+/* Launches of one batched iteration: *n receives their number; kinds (cap
+ * entries, nullable) receives 0 for a forward launch and the backward
+ * feature-tile height in units of 16 features (1, 2 or 4) otherwise. */
+sgep_status sgep_batch_launches(const sgep_batch *bt, int32_t *n, int32_t *kinds, int32_t cap);
+
+/* sgep_batch_step with a start / end event pair per launch, in launch order
+ * (n_events = 2 * the count of sgep_batch_launches), stamped by each kernel's
+ * own dispatch.  Not for stream capture. */
+sgep_status sgep_batch_step_profiled(sgep_batch *bt, const void *const *X, const void *const *Y,
+                                     int64_t b, void *const *events, int32_t n_events);
+
+/* The launch plan: *groups, the number of instance groups run one after the
+ * other (each a forward launch and its backward launches, so that a group's
+ * minibatches are re-read from cache), and mb_bucket[3], the backward
+ * feature-tile height (units of 16 features) for instances with d <= 256,
+ * 256 < d <= 1024 and d > 1024. */
+sgep_status sgep_batch_plan(const sgep_batch *bt, int32_t *groups, int32_t *mb_bucket);
+
+/* Set the launch plan (mb_bucket entries 1 or the larger height this dtype
+ * and k allow, as reported by sgep_batch_plan after sgep_batch_tune; groups
+ * >= 1, clipped to n).  Only before the first iteration (SGEP_EINVAL
+ * otherwise), because the norm partials of a running state are laid out by
+ * tile.  Synchronises. */
+sgep_status sgep_batch_set_plan(sgep_batch *bt, int32_t groups, const int32_t *mb_bucket);
+
+/* Autotune the launch plan on a caller's minibatch before the first
+ * iteration: every candidate (groups 1, 2, 4, 8; per width bucket the tile
+ * height 16 or the larger one) runs 1 + reps iterations from the initial
+ * state on (X, Y, b) and is timed with HIP events; the fastest plan is kept
+ * and the initial state restored, so the instances are as after
+ * sgep_batch_init.  best_us (nullable) receives the chosen plan's time per
+ * iteration in microseconds.  Allocates a temporary copy of the state.
+ * Errors: SGEP_EINVAL after the first iteration; as sgep_batch_step. */
+sgep_status sgep_batch_tune(sgep_batch *bt, const void *const *X, const void *const *Y, int64_t b,
+                            int32_t reps, double *best_us);
+
+/* sgep_sync of every instance; returns the first error. */
+sgep_status sgep_batch_sync(sgep_batch *bt);
+
+/* Release every instance and the batch (synchronises the stream first). */
+sgep_status sgep_batch_destroy(sgep_batch *bt);
+
 /* Static description of a status code. */
 const char *sgep_status_string(sgep_status s);
 

@@ -41,6 +41,9 @@ EXPORTS = (
     "sgep_step_profiled", "sgep_sync", "sgep_eigvals", "sgep_vectors", "sgep_auxiliary",
     "sgep_step_count", "sgep_state_size", "sgep_get_state", "sgep_set_state", "sgep_destroy",
     "sgep_status_string", "sgep_version",
+    "sgep_batch_init", "sgep_batch_instance", "sgep_batch_step", "sgep_batch_launches",
+    "sgep_batch_step_profiled", "sgep_batch_plan", "sgep_batch_set_plan", "sgep_batch_tune",
+    "sgep_batch_sync", "sgep_batch_destroy",
 )
 
 
@@ -122,6 +125,18 @@ def load() -> ctypes.CDLL:
     lib.sgep_status_string.argtypes = [i32]
     lib.sgep_status_string.restype = ctypes.c_char_p
     lib.sgep_version.argtypes = []
+    pi32, pi64 = ctypes.POINTER(i32), ctypes.POINTER(i64)
+    lib.sgep_batch_init.argtypes = [ctypes.POINTER(vp), i32, pi64, pi64, ctypes.POINTER(sgep_config),
+                                    ctypes.POINTER(dp), vp]
+    lib.sgep_batch_instance.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.sgep_batch_step.argtypes = [vp, vp, vp, i64]
+    lib.sgep_batch_launches.argtypes = [vp, pi32, pi32, i32]
+    lib.sgep_batch_step_profiled.argtypes = [vp, vp, vp, i64, ctypes.POINTER(vp), i32]
+    lib.sgep_batch_plan.argtypes = [vp, pi32, pi32]
+    lib.sgep_batch_set_plan.argtypes = [vp, i32, pi32]
+    lib.sgep_batch_tune.argtypes = [vp, vp, vp, i64, i32, dp]
+    lib.sgep_batch_sync.argtypes = [vp]
+    lib.sgep_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         fn = getattr(lib, name)
         if name not in ("sgep_status_string",):
@@ -283,6 +298,75 @@ def sgep_destroy(h) -> None:
     _check(load().sgep_destroy(h), "sgep_destroy")
 
 
+def sgep_batch_init(d, ld, cfg: sgep_config, V0s, stream=None) -> ctypes.c_void_p:
+    """Create n instances of widths d (host ints) with row leading dimensions
+    ld; V0s: n host arrays (d_i, k) of starting points."""
+    lib = load()
+    n = len(d)
+    d64 = (ctypes.c_int64 * n)(*[int(x) for x in d])
+    ld64 = (ctypes.c_int64 * n)(*[int(x) for x in ld])
+    cols = [np.ascontiguousarray(np.asarray(v, dtype=np.float64).T) for v in V0s]
+    ptrs = (ctypes.POINTER(ctypes.c_double) * n)(
+        *[c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for c in cols])
+    bt = ctypes.c_void_p()
+    _check(lib.sgep_batch_init(ctypes.byref(bt), n, d64, ld64, ctypes.byref(cfg), ptrs,
+                               _stream(stream)), "sgep_batch_init")
+    return bt
+
+
+def sgep_batch_instance(bt, i: int) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(load().sgep_batch_instance(bt, int(i), ctypes.byref(h)), "sgep_batch_instance")
+    return h
+
+
+def sgep_batch_step(bt, X_ptrs, Y_ptrs, b: int) -> None:
+    """X_ptrs, Y_ptrs: int64 device tensors holding the n device pointers."""
+    _check(load().sgep_batch_step(bt, _ptr(X_ptrs), _ptr(Y_ptrs), b), "sgep_batch_step")
+
+
+def sgep_batch_launches(bt) -> list:
+    lib = load()
+    n = ctypes.c_int32()
+    _check(lib.sgep_batch_launches(bt, ctypes.byref(n), None, 0), "sgep_batch_launches")
+    kinds = (ctypes.c_int32 * max(1, n.value))()
+    _check(lib.sgep_batch_launches(bt, ctypes.byref(n), kinds, n.value), "sgep_batch_launches")
+    return [int(kinds[i]) for i in range(n.value)]
+
+
+def sgep_batch_step_profiled(bt, X_ptrs, Y_ptrs, b: int, events) -> None:
+    ev = (ctypes.c_void_p * len(events))(*[int(e) for e in events])
+    _check(load().sgep_batch_step_profiled(bt, _ptr(X_ptrs), _ptr(Y_ptrs), b, ev, len(events)),
+           "sgep_batch_step_profiled")
+
+
+def sgep_batch_plan(bt):
+    g = ctypes.c_int32()
+    mb = (ctypes.c_int32 * 3)()
+    _check(load().sgep_batch_plan(bt, ctypes.byref(g), mb), "sgep_batch_plan")
+    return int(g.value), [int(mb[i]) for i in range(3)]
+
+
+def sgep_batch_set_plan(bt, groups: int, mb_bucket) -> None:
+    mb = (ctypes.c_int32 * 3)(*[int(x) for x in mb_bucket])
+    _check(load().sgep_batch_set_plan(bt, int(groups), mb), "sgep_batch_set_plan")
+
+
+def sgep_batch_tune(bt, X_ptrs, Y_ptrs, b: int, reps: int = 3) -> float:
+    us = ctypes.c_double()
+    _check(load().sgep_batch_tune(bt, _ptr(X_ptrs), _ptr(Y_ptrs), b, int(reps),
+                                  ctypes.byref(us)), "sgep_batch_tune")
+    return float(us.value)
+
+
+def sgep_batch_sync(bt) -> None:
+    _check(load().sgep_batch_sync(bt), "sgep_batch_sync")
+
+
+def sgep_batch_destroy(bt) -> None:
+    _check(load().sgep_batch_destroy(bt), "sgep_batch_destroy")
+
+
 class Solver:
     """Owning convenience wrapper around one handle (same calls, fewer args)."""
 
@@ -331,6 +415,69 @@ class Solver:
         if self.h is not None:
             sgep_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """Owning wrapper around a batch of GENERAL instances.  Minibatches are
+    given as lists of device tensors (or one int64 device tensor of
+    pointers per view)."""
+
+    def __init__(self, d, cfg: sgep_config, V0s, ld=None, stream=None):
+        self.d = [int(x) for x in d]
+        self.ld = list(self.d) if ld is None else [int(x) for x in ld]
+        self.k = cfg.k
+        self.cfg = cfg
+        self.bt = sgep_batch_init(self.d, self.ld, cfg, V0s, stream)
+
+    @staticmethod
+    def pointers(tensors, device):
+        """int64 device tensor of the data pointers of `tensors`."""
+        import torch
+        return torch.tensor([t.data_ptr() for t in tensors], dtype=torch.int64, device=device)
+
+    def step(self, Xp, Yp, b: int):
+        sgep_batch_step(self.bt, Xp, Yp, b)
+
+    def launches(self):
+        return sgep_batch_launches(self.bt)
+
+    def plan(self):
+        return sgep_batch_plan(self.bt)
+
+    def set_plan(self, groups, mb_bucket):
+        sgep_batch_set_plan(self.bt, groups, mb_bucket)
+
+    def tune(self, Xp, Yp, b: int, reps: int = 3):
+        return sgep_batch_tune(self.bt, Xp, Yp, b, reps)
+
+    def sync(self):
+        sgep_batch_sync(self.bt)
+
+    def instance(self, i):
+        return sgep_batch_instance(self.bt, i)
+
+    def vectors(self, i, b_normalized: int = 0):
+        return sgep_vectors(self.instance(i), self.d[i], self.k, b_normalized)
+
+    def auxiliary(self, i):
+        return sgep_auxiliary(self.instance(i), self.d[i], self.k)
+
+    def eigvals(self, i):
+        return sgep_eigvals(self.instance(i), self.k)
+
+    def step_count(self, i):
+        return sgep_step_count(self.instance(i))
+
+    def close(self):
+        if self.bt is not None:
+            sgep_batch_destroy(self.bt)
+            self.bt = None
 
     def __del__(self):
         try:

@@ -12,7 +12,8 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "sgep.hip")
-HDRS = [os.path.join(PKG, "csrc", "sgep_kernels.hpp"), os.path.join(ROOT, "include", "sgep.h")]
+HDRS = [os.path.join(PKG, "csrc", h) for h in ("sgep_kernels.hpp", "sgep_wide.hpp", "sgep_batch.hpp")] + [
+    os.path.join(ROOT, "include", "sgep.h")]
 OUT = os.path.join(PKG, "libsgep.so")
 ARCH = "gfx950"
 

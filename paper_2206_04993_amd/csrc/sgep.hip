@@ -12,11 +12,13 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <new>
 #include <vector>
 
 #include "../../include/sgep.h"
+#include "sgep_batch.hpp"
 #include "sgep_kernels.hpp"
 #include "sgep_wide.hpp"
 
@@ -784,34 +786,14 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     return SGEP_OK;
 }
 
-static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
-                             int64_t ldy, const int32_t *labels, int64_t b, void *const *events)
+// Arguments of one iteration of the narrow path that do not depend on the
+// minibatch itself (X, Y, b and n_fwd are left zero).
+static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool vec_ok)
 {
-    if (!h)
-        return SGEP_EINVAL;
-    if (h->poisoned)
-        return SGEP_EPOISONED;
-    if (h->wide)
-        return step_wide(h, X, ldx, Y, ldy, labels, b, events);
-    if (!X || !Y || labels)
-        return SGEP_EINVAL;
-    if (b < 1 || b > h->cfg.b_max)
-        return SGEP_ESHAPE;
-    if (ldx < h->cfg.dx || ldy < h->cfg.dy)
-        return SGEP_ESHAPE;
-    const int64_t vec = 16 / (int64_t)h->esz;
-    const bool vec_ok = ldx % vec == 0 && ldy % vec == 0 && ((uintptr_t)X & 15u) == 0 &&
-                        ((uintptr_t)Y & 15u) == 0 && ((uintptr_t)X % h->esz) == 0 &&
-                        ((uintptr_t)Y % h->esz) == 0;
-    if (((uintptr_t)X % h->esz) != 0 || ((uintptr_t)Y % h->esz) != 0)
-        return SGEP_ESHAPE; // not even element-aligned
     StepArgs a;
     memset(&a, 0, sizeof(a));
-    a.X = X;
-    a.Y = Y;
     a.ldx = ldx;
     a.ldy = ldy;
-    a.b = b;
     a.dx = h->cfg.dx;
     a.dy = h->cfg.dy;
     a.dxp = h->dxp;
@@ -821,7 +803,6 @@ static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const v
     a.n_tx = h->n_tx;
     a.n_ty = h->n_ty;
     a.vec_ok = vec_ok ? 1 : 0;
-    a.n_fwd = (int32_t)((b + 15) / 16);
     a.ldg = h->ldg;
     a.lds = h->lds;
     a.V = h->V;
@@ -846,6 +827,35 @@ static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const v
     a.adam_b1 = h->cfg.adam_b1;
     a.adam_b2 = h->cfg.adam_b2;
     a.adam_eps = h->cfg.adam_eps;
+    return a;
+}
+
+static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
+                             int64_t ldy, const int32_t *labels, int64_t b, void *const *events)
+{
+    if (!h)
+        return SGEP_EINVAL;
+    if (h->poisoned)
+        return SGEP_EPOISONED;
+    if (h->wide)
+        return step_wide(h, X, ldx, Y, ldy, labels, b, events);
+    if (!X || !Y || labels)
+        return SGEP_EINVAL;
+    if (b < 1 || b > h->cfg.b_max)
+        return SGEP_ESHAPE;
+    if (ldx < h->cfg.dx || ldy < h->cfg.dy)
+        return SGEP_ESHAPE;
+    const int64_t vec = 16 / (int64_t)h->esz;
+    const bool vec_ok = ldx % vec == 0 && ldy % vec == 0 && ((uintptr_t)X & 15u) == 0 &&
+                        ((uintptr_t)Y & 15u) == 0 && ((uintptr_t)X % h->esz) == 0 &&
+                        ((uintptr_t)Y % h->esz) == 0;
+    if (((uintptr_t)X % h->esz) != 0 || ((uintptr_t)Y % h->esz) != 0)
+        return SGEP_ESHAPE; // not even element-aligned
+    StepArgs a = make_args(h, ldx, ldy, vec_ok);
+    a.X = X;
+    a.Y = Y;
+    a.b = b;
+    a.n_fwd = (int32_t)((b + 15) / 16);
     return SGEP_DISPATCH(h, launch_step, h, a, events);
 }
 
@@ -1049,6 +1059,519 @@ sgep_status sgep_destroy(sgep_handle *h)
     (void)hipStreamSynchronize(h->stream);
     free_all(h);
     delete h;
+    return SGEP_OK;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched instances (sgep_batch.hpp): n narrow handles of kind GENERAL that
+// share one stream, advanced together by a fixed sequence of launches.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kBuckets = 3; // d <= 256, d <= 1024, larger
+
+int bucket_of(int64_t d) { return d <= 256 ? 0 : (d <= 1024 ? 1 : 2); }
+
+struct BatchLaunchRec {
+    int mb;         // 0: forward launch; otherwise the backward feature-tile height
+    size_t map_off; // first entry of its map in the device map array
+    int per_xcd;    // map entries per XCD
+};
+
+} // namespace
+
+struct sgep_batch_s {
+    sgep_config cfg;
+    int n = 0;
+    hipStream_t stream = nullptr;
+    std::vector<sgep_handle *> inst;
+    std::vector<int64_t> d, ld;
+    std::vector<int> mb_min; // smallest tile height each instance's partials allow
+    int mb_wide = 4;         // the larger candidate tile height for (dtype, KP)
+    int groups = 1;
+    int mb_bucket[kBuckets] = {1, 1, 1};
+    std::vector<BatchLaunchRec> launches;
+    StepArgs *d_args = nullptr;
+    uint32_t *d_map = nullptr;
+};
+
+namespace {
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Build and upload the argument table and the launch maps for a plan:
+// `groups` contiguous instance ranges of about equal total width, and the
+// backward feature-tile height mb_bucket[bucket(d)] per instance.  Within a
+// group every instance goes to one XCD, largest first, each to the XCD with
+// the least total width so far.  Synchronous (init and tuning only).
+sgep_status apply_plan(sgep_batch *bt, int groups, const int *mb_bucket)
+{
+    const int n = bt->n;
+    if (groups < 1)
+        groups = 1;
+    if (groups > n)
+        groups = n;
+    std::vector<StepArgs> args(n);
+    for (int i = 0; i < n; ++i) {
+        sgep_handle *h = bt->inst[i];
+        int mb = mb_bucket[bucket_of(bt->d[i])];
+        if (mb < bt->mb_min[i])
+            mb = bt->mb_min[i];
+        h->mb = mb;
+        h->ft = 16 * mb;
+        h->n_tx = (int)ceil_div(bt->d[i], h->ft);
+        h->n_ty = 0;
+        h->n_tiles = h->n_tx;
+        const int64_t vec = 16 / (int64_t)h->esz;
+        args[i] = make_args(h, bt->ld[i], bt->ld[i], bt->ld[i] % vec == 0);
+    }
+    // contiguous groups of about equal total width
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i)
+        total += bt->d[i];
+    std::vector<int> gstart(1, 0);
+    int64_t acc = 0;
+    for (int i = 0; i < n && (int)gstart.size() < groups; ++i) {
+        acc += bt->d[i];
+        if (acc * groups >= total * (int64_t)gstart.size() && i + 1 < n)
+            gstart.push_back(i + 1);
+    }
+    gstart.push_back(n);
+    std::vector<uint32_t> map;
+    std::vector<BatchLaunchRec> recs;
+    for (size_t g = 0; g + 1 < gstart.size(); ++g) {
+        std::vector<int> ids;
+        for (int i = gstart[g]; i < gstart[g + 1]; ++i)
+            ids.push_back(i);
+        std::stable_sort(ids.begin(), ids.end(),
+                         [&](int a, int b) { return bt->d[a] > bt->d[b]; });
+        std::vector<int> xcd_of(n, 0);
+        std::vector<std::vector<int>> lists(8);
+        int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int i : ids) {
+            int x = 0;
+            for (int c = 1; c < 8; ++c)
+                if (load[c] < load[x])
+                    x = c;
+            load[x] += bt->d[i];
+            lists[x].push_back(i);
+        }
+        // forward: one entry per instance
+        size_t per = 0;
+        for (auto &l : lists)
+            per = l.size() > per ? l.size() : per;
+        BatchLaunchRec fr = {0, map.size(), (int)per};
+        for (int x = 0; x < 8; ++x)
+            for (size_t j = 0; j < per; ++j)
+                map.push_back(j < lists[x].size() ? (uint32_t)lists[x][j] : sgep::batch::kNoTile);
+        recs.push_back(fr);
+        // backward: one launch per tile height in use, entries (instance, tile)
+        const int heights[2] = {1, bt->mb_wide};
+        for (int hh = 0; hh < 2; ++hh) {
+            const int mb = heights[hh];
+            if (hh == 1 && mb == heights[0])
+                break;
+            std::vector<std::vector<uint32_t>> tl(8);
+            size_t tper = 0;
+            for (int x = 0; x < 8; ++x) {
+                for (int i : lists[x])
+                    if (bt->inst[i]->mb == mb)
+                        for (int t = 0; t < bt->inst[i]->n_tiles; ++t)
+                            tl[x].push_back(((uint32_t)i << 16) | (uint32_t)t);
+                tper = tl[x].size() > tper ? tl[x].size() : tper;
+            }
+            if (tper == 0)
+                continue;
+            BatchLaunchRec br = {mb, map.size(), (int)tper};
+            for (int x = 0; x < 8; ++x)
+                for (size_t j = 0; j < tper; ++j)
+                    map.push_back(j < tl[x].size() ? tl[x][j] : sgep::batch::kNoTile);
+            recs.push_back(br);
+        }
+    }
+    // upload (drain the stream first: the old tables may still be in use)
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    if (bt->d_map)
+        HIPCHK(hipFree(bt->d_map));
+    bt->d_map = nullptr;
+    HIPCHK(hipMalloc((void **)&bt->d_map, map.size() * sizeof(uint32_t)));
+    HIPCHK(hipMemcpy(bt->d_map, map.data(), map.size() * sizeof(uint32_t),
+                     hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(bt->d_args, args.data(), n * sizeof(StepArgs), hipMemcpyHostToDevice));
+    bt->launches = recs;
+    bt->groups = (int)gstart.size() - 1;
+    for (int c = 0; c < kBuckets; ++c)
+        bt->mb_bucket[c] = mb_bucket[c];
+    return SGEP_OK;
+}
+
+template <typename T, int KP>
+sgep_status batch_launch_t(sgep_batch *bt, const sgep::batch::Launch &base, void *const *events)
+{
+    using namespace sgep::batch;
+    const bool adam = bt->cfg.optimizer == SGEP_ADAM;
+    const int64_t nf = ceil_div(base.b, 16);
+    int ie = 0;
+    for (const BatchLaunchRec &r : bt->launches) {
+        Launch L = base;
+        L.map = bt->d_map + r.map_off;
+        L.per_xcd = r.per_xcd;
+        hipEvent_t e0 = events ? (hipEvent_t)events[ie] : nullptr;
+        hipEvent_t e1 = events ? (hipEvent_t)events[ie + 1] : nullptr;
+        ie += 2;
+        const dim3 blk(sgep::kNT);
+        constexpr int MBW = mb_wide<T>(KP);
+        constexpr int GEN = sgep::kKindGeneral;
+        if (r.mb == 0) {
+            launch_k(k_bfwd<T, KP, GEN>, dim3((unsigned)(8 * r.per_xcd * (nf + 1))), blk,
+                     bt->stream, e0, e1, L);
+        } else {
+            const dim3 grid((unsigned)(8 * r.per_xcd));
+            if (r.mb == 1 && !adam)
+                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptSGD>, grid, blk, bt->stream, e0, e1, L);
+            else if (r.mb == 1)
+                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptAdam>, grid, blk, bt->stream, e0, e1, L);
+            else if (!adam)
+                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptSGD>, grid, blk, bt->stream, e0, e1, L);
+            else
+                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptAdam>, grid, blk, bt->stream, e0, e1, L);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return SGEP_OK;
+}
+
+sgep_status batch_step_impl(sgep_batch *bt, const void *const *X, const void *const *Y, int64_t b,
+                            void *const *events)
+{
+    if (!bt || !X || !Y)
+        return SGEP_EINVAL;
+    if (b < 1 || b > bt->cfg.b_max)
+        return SGEP_ESHAPE;
+    for (sgep_handle *h : bt->inst)
+        if (h->poisoned)
+            return SGEP_EPOISONED;
+    sgep::batch::Launch L;
+    memset(&L, 0, sizeof(L));
+    L.args = bt->d_args;
+    L.X = X;
+    L.Y = Y;
+    L.b = b;
+    sgep_handle *h0 = bt->inst[0];
+    return SGEP_DISPATCH(h0, batch_launch_t, bt, L, events);
+}
+
+void batch_free(sgep_batch *bt)
+{
+    for (sgep_handle *h : bt->inst)
+        if (h) {
+            free_all(h);
+            delete h;
+        }
+    if (bt->d_args)
+        (void)hipFree(bt->d_args);
+    if (bt->d_map)
+        (void)hipFree(bt->d_map);
+    delete bt;
+}
+
+// device state of every instance that an iteration changes (the players, the
+// auxiliary variable, the Adam moments, the norm / parent partials and the
+// coefficient block), for the tuner's trial iterations
+struct BatchSnapshot {
+    void *buf = nullptr;
+    std::vector<std::pair<void *, size_t>> parts;
+    size_t total = 0;
+};
+
+sgep_status batch_snapshot(sgep_batch *bt, BatchSnapshot &s)
+{
+    for (sgep_handle *h : bt->inst) {
+        StateLayout L = state_layout(h);
+        for (int i = 0; i < L.n; ++i)
+            s.parts.push_back({L.ptr[i], L.bytes[i]});
+        s.parts.push_back({h->coef, sizeof(Coef)});
+    }
+    for (auto &p : s.parts)
+        s.total += (p.second + 255) / 256 * 256;
+    HIPCHK(hipMalloc(&s.buf, s.total));
+    size_t off = 0;
+    for (auto &p : s.parts) {
+        HIPCHK(hipMemcpyAsync((char *)s.buf + off, p.first, p.second, hipMemcpyDeviceToDevice,
+                              bt->stream));
+        off += (p.second + 255) / 256 * 256;
+    }
+    return SGEP_OK;
+}
+
+sgep_status batch_restore(sgep_batch *bt, const BatchSnapshot &s)
+{
+    size_t off = 0;
+    for (auto &p : s.parts) {
+        HIPCHK(hipMemcpyAsync(p.first, (char *)s.buf + off, p.second, hipMemcpyDeviceToDevice,
+                              bt->stream));
+        off += (p.second + 255) / 256 * 256;
+    }
+    return SGEP_OK;
+}
+
+// every instance still at its initial state (no iteration run yet)
+sgep_status batch_at_start(sgep_batch *bt, bool *yes)
+{
+    *yes = true;
+    for (sgep_handle *h : bt->inst) {
+        double t = 0.0;
+        HIPCHK(hipMemcpyAsync(&t, &h->coef->t, sizeof(double), hipMemcpyDeviceToHost,
+                              bt->stream));
+        HIPCHK(hipStreamSynchronize(bt->stream));
+        if (t != 0.0)
+            *yes = false;
+    }
+    return SGEP_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+sgep_status sgep_batch_init(sgep_batch **out, int32_t n, const int64_t *d, const int64_t *ld,
+                            const sgep_config *common, const double *const *V0, void *hip_stream)
+{
+    if (!out)
+        return SGEP_EINVAL;
+    *out = nullptr;
+    if (!d || !ld || !common || !V0 || n < 1)
+        return SGEP_EINVAL;
+    if (n > 65535)
+        return SGEP_EUNSUPPORTED;
+    if (common->kind != SGEP_KIND_GENERAL)
+        return SGEP_EUNSUPPORTED;
+    if (common->dtype != SGEP_F32 && common->dtype != SGEP_F64)
+        return SGEP_EUNSUPPORTED;
+    for (int i = 0; i < n; ++i) {
+        if (!V0[i])
+            return SGEP_EINVAL;
+        if (d[i] < 1 || ld[i] < d[i])
+            return SGEP_ESHAPE;
+    }
+    sgep_batch *bt = new (std::nothrow) sgep_batch_s();
+    if (!bt)
+        return SGEP_ENOMEM;
+    bt->cfg = *common;
+    bt->n = n;
+    bt->stream = (hipStream_t)hip_stream;
+    bt->d.assign(d, d + n);
+    bt->ld.assign(ld, ld + n);
+    bt->inst.assign(n, nullptr);
+    bt->mb_min.assign(n, 1);
+    for (int i = 0; i < n; ++i) {
+        sgep_config c = *common;
+        c.dx = c.dy = d[i];
+        sgep_status rc = sgep_init(&bt->inst[i], &c, V0[i], hip_stream);
+        if (rc != SGEP_OK) {
+            bt->inst[i] = nullptr;
+            batch_free(bt);
+            return rc;
+        }
+        bt->mb_min[i] = bt->inst[i]->mb; // partials sized for this height or larger
+    }
+    const sgep_handle *h0 = bt->inst[0];
+    bt->mb_wide = h0->esz == sizeof(double) ? (h0->kp * 8 <= 128 ? 4 : 2)
+                                            : (h0->kp * 4 <= 128 ? 4 : 2);
+    if (hipMalloc((void **)&bt->d_args, (size_t)n * sizeof(StepArgs)) != hipSuccess) {
+        bt->d_args = nullptr;
+        batch_free(bt);
+        return SGEP_ENOMEM;
+    }
+    const int mb1[kBuckets] = {1, 1, 1};
+    sgep_status rc = apply_plan(bt, 1, mb1);
+    if (rc != SGEP_OK) {
+        batch_free(bt);
+        return rc;
+    }
+    *out = bt;
+    return SGEP_OK;
+}
+
+sgep_status sgep_batch_instance(sgep_batch *bt, int32_t i, sgep_handle **h)
+{
+    if (!bt || !h || i < 0 || i >= bt->n)
+        return SGEP_EINVAL;
+    *h = bt->inst[i];
+    return SGEP_OK;
+}
+
+sgep_status sgep_batch_step(sgep_batch *bt, const void *const *X, const void *const *Y, int64_t b)
+{
+    return batch_step_impl(bt, X, Y, b, nullptr);
+}
+
+sgep_status sgep_batch_launches(const sgep_batch *bt, int32_t *n, int32_t *kinds, int32_t cap)
+{
+    if (!bt || !n)
+        return SGEP_EINVAL;
+    *n = (int32_t)bt->launches.size();
+    if (kinds) {
+        if (cap < *n)
+            return SGEP_ESHAPE;
+        for (int32_t i = 0; i < *n; ++i)
+            kinds[i] = bt->launches[i].mb;
+    }
+    return SGEP_OK;
+}
+
+sgep_status sgep_batch_step_profiled(sgep_batch *bt, const void *const *X, const void *const *Y,
+                                     int64_t b, void *const *events, int32_t n_events)
+{
+    if (!bt || !events || n_events != 2 * (int32_t)bt->launches.size())
+        return SGEP_EINVAL;
+    for (int32_t i = 0; i < n_events; ++i)
+        if (!events[i])
+            return SGEP_EINVAL;
+    return batch_step_impl(bt, X, Y, b, events);
+}
+
+sgep_status sgep_batch_plan(const sgep_batch *bt, int32_t *groups, int32_t *mb_bucket)
+{
+    if (!bt || !groups || !mb_bucket)
+        return SGEP_EINVAL;
+    *groups = bt->groups;
+    for (int c = 0; c < kBuckets; ++c)
+        mb_bucket[c] = bt->mb_bucket[c];
+    return SGEP_OK;
+}
+
+sgep_status sgep_batch_set_plan(sgep_batch *bt, int32_t groups, const int32_t *mb_bucket)
+{
+    if (!bt || !mb_bucket || groups < 1)
+        return SGEP_EINVAL;
+    int mb[kBuckets];
+    for (int c = 0; c < kBuckets; ++c) {
+        if (mb_bucket[c] != 1 && mb_bucket[c] != bt->mb_wide)
+            return SGEP_EINVAL;
+        mb[c] = mb_bucket[c];
+    }
+    bool start = false;
+    sgep_status rc = batch_at_start(bt, &start);
+    if (rc != SGEP_OK)
+        return rc;
+    if (!start)
+        return SGEP_EINVAL; // the partials of a running state fix the tile heights
+    return apply_plan(bt, groups, mb);
+}
+
+sgep_status sgep_batch_tune(sgep_batch *bt, const void *const *X, const void *const *Y, int64_t b,
+                            int32_t reps, double *best_us)
+{
+    if (!bt || !X || !Y || reps < 1)
+        return SGEP_EINVAL;
+    if (b < 1 || b > bt->cfg.b_max)
+        return SGEP_ESHAPE;
+    for (sgep_handle *h : bt->inst)
+        if (h->poisoned)
+            return SGEP_EPOISONED;
+    bool start = false;
+    sgep_status rc = batch_at_start(bt, &start);
+    if (rc != SGEP_OK)
+        return rc;
+    if (!start)
+        return SGEP_EINVAL;
+    bool used[kBuckets] = {false, false, false};
+    for (int i = 0; i < bt->n; ++i)
+        used[bucket_of(bt->d[i])] = true;
+    BatchSnapshot snap;
+    rc = batch_snapshot(bt, snap);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == SGEP_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = SGEP_EDEVICE;
+    double best = 1e300;
+    int best_g = 1, best_mb[kBuckets] = {1, 1, 1};
+    const int gcand[4] = {1, 2, 4, 8};
+    for (int gi = 0; gi < 4 && rc == SGEP_OK; ++gi) {
+        if (gcand[gi] > bt->n)
+            break;
+        for (int mask = 0; mask < (1 << kBuckets) && rc == SGEP_OK; ++mask) {
+            int mb[kBuckets];
+            bool dup = false;
+            for (int c = 0; c < kBuckets; ++c) {
+                const bool wide = (mask >> c) & 1;
+                if (wide && (!used[c] || bt->mb_wide == 1))
+                    dup = true; // same plan as with this bit clear
+                mb[c] = wide ? bt->mb_wide : 1;
+            }
+            if (dup)
+                continue;
+            rc = apply_plan(bt, gcand[gi], mb);
+            if (rc == SGEP_OK)
+                rc = batch_restore(bt, snap);
+            if (rc == SGEP_OK)
+                rc = batch_step_impl(bt, X, Y, b, nullptr); // warm-up
+            if (rc != SGEP_OK)
+                break;
+            if (hipEventRecord(e0, bt->stream) != hipSuccess) {
+                rc = SGEP_EDEVICE;
+                break;
+            }
+            for (int r = 0; r < reps && rc == SGEP_OK; ++r)
+                rc = batch_step_impl(bt, X, Y, b, nullptr);
+            float ms = 0.f;
+            if (rc != SGEP_OK || hipEventRecord(e1, bt->stream) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = rc != SGEP_OK ? rc : SGEP_EDEVICE;
+                break;
+            }
+            const double us = 1e3 * ms / reps;
+            if (us < best) {
+                best = us;
+                best_g = gcand[gi];
+                for (int c = 0; c < kBuckets; ++c)
+                    best_mb[c] = mb[c];
+            }
+        }
+    }
+    if (rc == SGEP_OK)
+        rc = apply_plan(bt, best_g, best_mb);
+    if (rc == SGEP_OK && snap.buf)
+        rc = batch_restore(bt, snap);
+    if (hipStreamSynchronize(bt->stream) != hipSuccess && rc == SGEP_OK)
+        rc = SGEP_EDEVICE;
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    if (snap.buf)
+        (void)hipFree(snap.buf);
+    // trial iterations may have latched a fault in a status word: the
+    // restored coefficient blocks clear it
+    for (sgep_handle *h : bt->inst)
+        h->poisoned = false;
+    if (rc == SGEP_OK && best_us)
+        *best_us = best;
+    return rc;
+}
+
+sgep_status sgep_batch_sync(sgep_batch *bt)
+{
+    if (!bt)
+        return SGEP_EINVAL;
+    sgep_status first = SGEP_OK;
+    for (sgep_handle *h : bt->inst) {
+        const sgep_status rc = sgep_sync(h);
+        if (rc != SGEP_OK && first == SGEP_OK)
+            first = rc;
+    }
+    return first;
+}
+
+sgep_status sgep_batch_destroy(sgep_batch *bt)
+{
+    if (!bt)
+        return SGEP_EINVAL;
+    (void)hipStreamSynchronize(bt->stream);
+    batch_free(bt);
     return SGEP_OK;
 }
 

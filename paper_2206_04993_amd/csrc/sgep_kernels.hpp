@@ -323,11 +323,11 @@ __device__ __forceinline__ void fwd_view(const T *__restrict__ X, int64_t ldx, i
     }
 }
 
-// Forward kernel: workgroup rt takes rows 16 rt .. 16 rt + 15; the four waves
-// split the features.  The extra last workgroup reduces the norm / parent
+// Forward body: workgroup blk takes rows 16 blk .. 16 blk + 15; the four waves
+// split the features.  Workgroup blk == n_fwd reduces the norm / parent
 // partials of the current state and advances the step counter.
 template <typename T, int KP, int KIND>
-__global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
+__device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
 {
     typedef typename Mfma<T>::acc Acc;
     constexpr int NB = KP / 16;
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int kk = lane >> 4, n = lane & 15;
-    if ((int)blockIdx.x == a.n_fwd) {
+    if (blk == a.n_fwd) {
         // norm / parent-term totals of the current state (sum over the
         // previous backward pass's tiles, fixed order); advance t
         __shared__ double scr[kScr];
@@ -350,7 +350,7 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
             a.coef->t += 1.0; // read by k_bwd only, after this kernel has finished
         return;
     }
-    const int64_t r0 = (int64_t)blockIdx.x * 16;
+    const int64_t r0 = (int64_t)blk * 16;
     const bool rv = r0 + n < a.b;
     const int64_t row = rv ? r0 + n : a.b - 1; // valid address; zeroed through rv
     const bool vec_ok = a.vec_ok != 0;
@@ -425,8 +425,14 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
                     s += (double)pt[r][i] * (double)pt[r][i];
             }
         }
-        a.gram_part[(int64_t)e * a.ldg + blockIdx.x] = s;
+        a.gram_part[(int64_t)e * a.ldg + blk] = s;
     }
+}
+
+template <typename T, int KP, int KIND>
+__global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
+{
+    fwd_body<T, KP, KIND>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -440,7 +446,7 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 // any MFMA; the ragged last group runs masked.
 // ---------------------------------------------------------------------------
 template <typename T, int KP, int MB, int KIND, int OPT>
-__global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
+__device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
 {
     typedef typename Mfma<T>::acc Acc;
     constexpr int NB = KP / 16;
@@ -461,7 +467,6 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int kk = lane >> 4, m = lane & 15;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const bool vec_ok = a.vec_ok != 0;
     const T *X = (const T *)a.X, *Y = (const T *)a.Y;
     const T *PQ = (const T *)a.P, *QQ = (const T *)a.Q;
@@ -765,6 +770,12 @@ __global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
         }
         sout[(int64_t)e * a.lds + tile] = s;
     }
+}
+
+template <typename T, int KP, int MB, int KIND, int OPT>
+__global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
+{
+    bwd_body<T, KP, MB, KIND, OPT>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------

@@ -28,7 +28,7 @@ def _rows(path):
     return list(csv.DictReader(open(path)))
 
 
-_KERNELS = ("k_wfwd", "k_wmid", "k_wbwd", "k_winit", "k_fwd", "k_bwd")
+_KERNELS = ("k_bfwd", "k_bbwd", "k_wfwd", "k_wmid", "k_wbwd", "k_winit", "k_fwd", "k_bwd")
 
 
 def _short(name: str) -> str:

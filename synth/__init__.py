@@ -178,19 +178,68 @@ class CCAActivation:
         return self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)
 
 
+class _FastOrth:
+    """Dense random orthogonal d x d matrix Q = H2 H1 C Pi: Pi a signed random
+    permutation (Pi[perm[j], j] = sign[j]), C the orthonormal DCT-II matrix
+    C[i, j] = c_i cos(pi i (2 j + 1) / (2 d)) with c_0 = sqrt(1/d) and
+    c_i = sqrt(2/d) otherwise, and H = I - 2 u u^T two random Householder
+    reflections.  Every factor is orthogonal, so Q is; building it costs
+    O(d^2) instead of the O(d^3) of a QR."""
+
+    def __init__(self, rng: np.random.Generator, d: int):
+        self.d = d
+        self.perm = rng.permutation(d)
+        self.sign = rng.choice([-1.0, 1.0], size=d)
+        self.u = []
+        for _ in range(2):
+            u = rng.standard_normal(d)
+            self.u.append(u / np.linalg.norm(u))
+
+    def dense(self) -> np.ndarray:
+        d = self.d
+        i = np.arange(d)[:, None]
+        j = self.perm[None, :]                    # column j of C Pi is C[:, perm[j]] sign[j]
+        M = np.cos(np.pi * i * (2 * j + 1) / (2 * d)) * self.sign[None, :]
+        M *= np.where(np.arange(d) == 0, np.sqrt(1.0 / d), np.sqrt(2.0 / d))[:, None]
+        for u in self.u:
+            M -= 2.0 * np.outer(u, u @ M)
+        return M
+
+    def dense_torch(self, device, dtype):
+        """The same matrix built with torch on `device` (rounded to dtype)."""
+        import torch
+        d = self.d
+        i = torch.arange(d, device=device, dtype=torch.float64)[:, None]
+        j = torch.from_numpy(self.perm).to(device=device, dtype=torch.float64)[None, :]
+        M = torch.cos(np.pi * i * (2 * j + 1) / (2 * d))
+        M *= torch.from_numpy(self.sign).to(device)[None, :]
+        c = torch.full((d, 1), np.sqrt(2.0 / d), dtype=torch.float64, device=device)
+        c[0, 0] = np.sqrt(1.0 / d)
+        M *= c
+        for u in self.u:
+            ut = torch.from_numpy(u).to(device)
+            M -= 2.0 * torch.outer(ut, ut @ M)
+        return M.to(dtype)
+
+
 @dataclass
 class GeneralPlanted:
     """General SGEP instance of width d: x = Qx diag(sqrt(ax)) g with ax
     log-uniform in [0.1, 1]; B = E[x x^T] + eps I = L L^T; y = L O diag(sqrt(lam)) g'
     with O random orthogonal, so that A = E[y y^T] = L O diag(lam) O^T L^T and
     A v = lam B v holds exactly for v = L^{-T} O e_i.  The top ``k`` planted
-    values are geomspace(10, 0.1, k), the rest uniform in [0.01, 0.05]."""
+    values are geomspace(10, 0.1, k), the rest uniform in [0.01, 0.05].
+
+    ``mixing="haar"``: Qx and O Haar-distributed (QR of Gaussians), L the
+    Cholesky factor of B (O(d^3)).  ``mixing="fast"``: Qx and O from
+    ``_fast_orth`` and L = Qx diag(sqrt(ax + eps)), another square root of
+    the same B (O(d^2 log d); used for the many-instance workload)."""
     d: int
     k: int = 8
     eps: float = 1e-3
     seed: int = 0
+    mixing: str = "haar"
     Sx_half: np.ndarray = field(init=False, repr=False)
-    Y_map: np.ndarray = field(init=False, repr=False)
     lam: np.ndarray = field(init=False, repr=False)
     ax: np.ndarray = field(init=False, repr=False)
     Qx: np.ndarray = field(init=False, repr=False)
@@ -198,22 +247,70 @@ class GeneralPlanted:
     def __post_init__(self):
         rng = np.random.default_rng(self.seed)
         d = self.d
-        self.Qx = _orth(rng, d, d)
+        self._fx = self._fo = None
+        if self.mixing == "fast":
+            self._fx = _FastOrth(rng, d)
+        else:
+            self.Qx = _orth(rng, d, d)
         self.ax = np.exp(rng.uniform(np.log(0.1), np.log(1.0), size=d))
-        self.Sx_half = self.Qx * np.sqrt(self.ax)[None, :]
-        Bfull = (self.Qx * self.ax[None, :]) @ self.Qx.T + self.eps * np.eye(d)
-        L = np.linalg.cholesky(Bfull)
-        O = _orth(rng, d, d)
+        if self.mixing == "fast":
+            self._fo = _FastOrth(rng, d)
+            self._Y_map = None
+        else:
+            self.Sx_half = self.Qx * np.sqrt(self.ax)[None, :]
+            Bfull = (self.Qx * self.ax[None, :]) @ self.Qx.T + self.eps * np.eye(d)
+            L = np.linalg.cholesky(Bfull)
+            O = _orth(rng, d, d)
         lam = np.empty(d)
         lam[: self.k] = np.geomspace(10.0, 0.1, self.k)
         lam[self.k:] = rng.uniform(0.01, 0.05, size=d - self.k)
         self.lam = lam
-        self.Y_map = (L @ O) * np.sqrt(lam)[None, :]
+        if self.mixing != "fast":
+            self._Y_map = (L @ O) * np.sqrt(lam)[None, :]
+
+    def __getattr__(self, name):
+        # dense factors of the fast construction, formed on first use
+        if name in ("Qx", "Sx_half") and self.__dict__.get("_fx") is not None:
+            Q = self._fx.dense()
+            self.__dict__["Qx"] = Q
+            self.__dict__["Sx_half"] = Q * np.sqrt(self.ax)[None, :]
+            return self.__dict__[name]
+        raise AttributeError(name)
+
+    @property
+    def Y_map(self) -> np.ndarray:
+        """L O diag(sqrt(lam)); for fast mixing L = Qx diag(sqrt(ax + eps)),
+        formed on first use."""
+        if self._Y_map is None:
+            L = self.Qx * np.sqrt(self.ax + self.eps)[None, :]
+            self._Y_map = (L @ self._fo.dense()) * np.sqrt(self.lam)[None, :]
+        return self._Y_map
 
     def sample(self, n: int, rng: np.random.Generator, dtype=np.float64):
         x = rng.standard_normal((n, self.d)) @ self.Sx_half.T
         y = rng.standard_normal((n, self.d)) @ self.Y_map.T
         return x.astype(dtype, copy=False), y.astype(dtype, copy=False)
+
+    def sample_torch(self, n: int, t: int, device, dtype):
+        """n fresh rows of x and y drawn on `device` (fast mixing only), from
+        a torch generator seeded by (seed, t): x = Qx diag(sqrt(ax)) g and
+        y = Qx diag(sqrt(ax + eps)) O diag(sqrt(lam)) g' with the dense
+        factors built in FP32 on the device.  Values differ from ``sample``,
+        which uses numpy's generator."""
+        import torch
+        assert self._fx is not None, "sample_torch needs mixing='fast'"
+        g = torch.Generator(device=device)
+        g.manual_seed((int(self.seed) * 1_000_003 + int(t)) & ((1 << 63) - 1))
+        f32 = torch.float32
+        Q = self._fx.dense_torch(device, f32)
+        O = self._fo.dense_torch(device, f32)
+        ax = torch.from_numpy(self.ax).to(device=device, dtype=f32)
+        lam = torch.from_numpy(self.lam).to(device=device, dtype=f32)
+        gx = torch.randn((n, self.d), generator=g, device=device, dtype=f32)
+        gy = torch.randn((n, self.d), generator=g, device=device, dtype=f32)
+        x = (gx * ax.sqrt()) @ Q.T
+        y = (((gy * lam.sqrt()) @ O.T) * (ax + self.eps).sqrt()) @ Q.T
+        return x.to(dtype), y.to(dtype)
 
     def batch(self, t: int, b: int, dtype=np.float64):
         return self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)
@@ -222,6 +319,16 @@ class GeneralPlanted:
 def batched_dims(n: int = 256, lo: int = 64, hi: int = 2048, seed: int = 0) -> np.ndarray:
     """Instance widths d_i uniform on {lo..hi} for the batched workload."""
     return np.random.default_rng([seed, 11]).integers(lo, hi + 1, size=n)
+
+
+def batched_general(n: int = 256, lo: int = 64, hi: int = 2048, k: int = 8, eps: float = 1e-3,
+                    seed: int = 0, dims=None):
+    """The many-instance workload: n ``GeneralPlanted`` instances with widths
+    ``batched_dims`` (or ``dims``), fast mixing, instance i seeded
+    (seed, 100 + i)."""
+    dims = batched_dims(n, lo, hi, seed) if dims is None else np.asarray(dims)
+    return [GeneralPlanted(int(di), k=k, eps=eps, seed=(seed << 16) + 100 + 2 * i, mixing="fast")
+            for i, di in enumerate(dims)]
 
 
 @dataclass

@@ -145,3 +145,40 @@ def test_null_arguments_rejected():
     assert lib.sgep_init_ex(None, None, None, None, None) == sg.SGEP_EINVAL
     assert sg.sgep_status_string(sg.SGEP_EPOISONED).startswith("handle poisoned")
     assert sg.sgep_version() >= 100
+
+
+def test_batch_validation_is_synchronous():
+    """Batch creation refuses bad arguments before any device work."""
+    import paper_2206_04993_amd as sg
+    lib = sg.load()
+    mk = sg.make_config
+
+    def status(n, d, ld, cfg, V0s):
+        bt = ctypes.c_void_p()
+        d64 = (ctypes.c_int64 * max(1, n))(*d)
+        ld64 = (ctypes.c_int64 * max(1, n))(*ld)
+        cols = [np.ascontiguousarray(v, dtype=np.float64) for v in V0s]
+        ptrs = (ctypes.POINTER(ctypes.c_double) * max(1, n))(
+            *[c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if c.size else None
+              for c in cols])
+        return lib.sgep_batch_init(ctypes.byref(bt), n, d64, ld64, ctypes.byref(cfg), ptrs,
+                                   None)
+
+    G = sg.SGEP_KIND_GENERAL
+    ok = mk(G, sg.SGEP_F32, 4, 0, 0, 16)
+    V = [np.ones((4, 32)), np.ones((4, 40))]
+    assert status(0, [32], [32], ok, V[:1]) == sg.SGEP_EINVAL                  # n = 0
+    assert status(2, [32, 40], [32, 39], ok, V) == sg.SGEP_ESHAPE              # ld < d
+    assert status(2, [32, 0], [32, 40], ok, V) == sg.SGEP_ESHAPE               # d = 0
+    assert status(2, [32, 40], [32, 40], ok, [V[0], np.zeros(0)]) == sg.SGEP_EINVAL  # V0 NULL
+    assert status(1, [32], [32], mk(sg.SGEP_KIND_CCA, sg.SGEP_F32, 4, 16, 16, 16),
+                  V[:1]) == sg.SGEP_EUNSUPPORTED                                # GENERAL only
+    assert status(1, [32], [32], mk(G, sg.SGEP_BF16, 4, 0, 0, 16),
+                  V[:1]) == sg.SGEP_EUNSUPPORTED                                # F32 / F64 only
+    assert lib.sgep_batch_init(None, 1, None, None, None, None, None) == sg.SGEP_EINVAL
+    for fn in ("sgep_batch_sync", "sgep_batch_destroy"):
+        assert getattr(lib, fn)(None) == sg.SGEP_EINVAL
+    assert lib.sgep_batch_step(None, None, None, 1) == sg.SGEP_EINVAL
+    assert lib.sgep_batch_tune(None, None, None, 1, 1, None) == sg.SGEP_EINVAL
+    assert lib.sgep_batch_plan(None, None, None) == sg.SGEP_EINVAL
+    assert lib.sgep_batch_launches(None, None, None, 0) == sg.SGEP_EINVAL

@@ -55,3 +55,35 @@ def test_e4m3_rounding_and_saturation():
     big = np.abs(x) > 2.0 ** -6 * s[None, :]
     assert np.all(np.abs(q - x)[big] <= 2.0 ** -4 * np.abs(x)[big] + 1e-300)
     assert np.allclose(np.abs(x).max(axis=0), np.abs(q).max(axis=0))
+
+
+def test_fast_orthogonal_mixing_is_orthogonal_and_planted():
+    """The O(d^2) orthogonal factor equals its definition (scipy's orthonormal
+    DCT-II of a signed permutation, then two reflections), is orthogonal, and
+    the fast general instance keeps A v = lam B v exactly for the planted
+    top-k (checked against the exact solver)."""
+    from scipy.fft import dct
+
+    import oracle
+    from oracle import targets
+    f = synth._FastOrth(np.random.default_rng(4), 29)
+    P = np.zeros((29, 29))
+    P[f.perm, np.arange(29)] = f.sign
+    M = dct(P, type=2, norm="ortho", axis=0)
+    for u in f.u:
+        M -= 2.0 * np.outer(u, u @ M)
+    Q = f.dense()
+    assert np.abs(M - Q).max() < 1e-13
+    assert np.abs(Q.T @ Q - np.eye(29)).max() < 1e-13
+    g = synth.GeneralPlanted(48, k=8, seed=5, mixing="fast")
+    A, B = targets.general_population_AB(g)
+    lam, V = targets.general_planted_topk(g, 8)
+    assert np.allclose(lam, np.geomspace(10.0, 0.1, 8))
+    assert np.abs(A @ V - (B @ V) * lam[None, :]).max() < 1e-12
+    lam2, V2 = oracle.gep_topk(A, B, 8)
+    assert np.abs(lam2 - lam).max() < 1e-11
+    assert oracle.subspace_error(V, V2, B) < 1e-12
+    # the sample covariances approach A and B
+    X, Y = g.sample(100000, np.random.default_rng(1))
+    assert np.abs(X.T @ X / 1e5 + 1e-3 * np.eye(48) - B).max() < 0.05 * np.abs(B).max()
+    assert np.abs(Y.T @ Y / 1e5 - A).max() < 0.05 * np.abs(A).max()
