@@ -6,7 +6,9 @@ backward products, update, auxiliary update) on one minibatch that is already
 resident in HBM.  Default workload: CCA in FP32 with two views of width 512
 (d = 1024), k = 16 players, minibatch 1024, Adam with the inverse-time
 schedule.  A ring of pre-generated synthetic minibatches is replayed through a
-hipGraph that holds one pass over the ring.
+hipGraph that holds one pass over the ring.  For the CCA workloads with a
+closed-form or small exact target the line also carries the time to 1e-3
+subspace error (``time_to_accuracy``), measured on a separate solver.
 
 Other workloads (``--workload``): the FP64 tiny CCA, the large CCA
 (8192 + 8192 activation-like views, k = 32, b = 4096) in BF16, FP8-e4m3 and
@@ -48,14 +50,14 @@ _C5 = dict(kind="lda", dx=65536, dy=0, k=64, b=2048, ring=4, optimizer="adam",
 WORKLOADS = {
     "cca_d1024_k16_b1024_fp32": dict(
         kind="cca", dtype="f32", dx=512, dy=512, k=16, b=1024, ring=128,
-        optimizer="adam", schedule="inv", eta0=2e-3, t0=3000.0, gamma=0.3, rho=1e-6,
-        generator="medium_cca",
+        optimizer="adam", schedule="inv", eta0=4e-3, t0=100.0, gamma=0.3, rho=1e-6,
+        generator="medium_cca", tta=dict(target=1e-3, max_steps=100_000, every=1000),
         describe="CCA FP32: views 512+512 (d=1024), k=16, minibatch 1024; planted "
                  "correlations linspace(0.95,0.2,16), per-view condition 100"),
     "cca_d16_k4_b128_fp64": dict(
         kind="cca", dtype="f64", dx=8, dy=8, k=4, b=128, ring=128,
         optimizer="sgd", schedule="inv", eta0=1.0, t0=200.0, gamma=1.0, rho=1e-6,
-        generator="tiny_cca",
+        generator="tiny_cca", tta=dict(target=1e-3, max_steps=6000, every=100),
         describe="CCA FP64: views 8+8 (d=16), k=4, minibatch 128; planted "
                  "correlations 0.9,0.7,0.5,0.3"),
     "cca_d16384_k32_b4096_bf16": dict(
@@ -90,10 +92,13 @@ BATCH_WORKLOADS = {
 DEFAULT = "cca_d1024_k16_b1024_fp32"
 
 # kernels of one iteration, in launch order, and the header holding their code
-KERNELS = {False: ("k_fwd", "k_bwd"), True: ("k_wfwd", "k_wmid", "k_wbwd")}
+KERNELS = {"narrow2": ("k_fwd", "k_bwd"), "narrow3": ("k_fwd", "k_coef", "k_bwd"),
+           "wide": ("k_wfwd", "k_wmid", "k_wbwd")}
 KERNEL_HEADER = {"k_fwd": "sgep_kernels.hpp", "k_bwd": "sgep_kernels.hpp",
+                 "k_coef": "sgep_kernels.hpp",
                  "k_wfwd": "sgep_wide.hpp", "k_wmid": "sgep_wide.hpp", "k_wbwd": "sgep_wide.hpp",
                  "k_bfwd": ("sgep_kernels.hpp", "sgep_batch.hpp"),
+                 "k_bcoef": ("sgep_kernels.hpp", "sgep_batch.hpp"),
                  "k_bbwd": ("sgep_kernels.hpp", "sgep_batch.hpp")}
 
 
@@ -210,6 +215,9 @@ def algorithmic_work(w, kernel):
     state = (4 + (4 if adam else 0)) * se * d * k               # V, G (+ moments) read + written
     if kernel == "k_fwd":
         return 2.0 * b * d * k, float(data + se * d * k + se * 2 * b * k)
+    if kernel == "k_coef":  # the Gram partials of the forward row tiles, once
+        kp = 16 if k <= 16 else (32 if k <= 32 else 64)
+        return 0.0, float(8 * (kp * (kp + 1) // 2 + kp) * ((b + 15) // 16))
     if kernel == "k_bwd":
         return 4.0 * b * d * k, float(data + se * 2 * b * k + state)
     mw = k + c if lda else 2 * k                                # rows of the backward operand W
@@ -256,6 +264,93 @@ def cpu_baseline(w, budget_s: float, host):
             "kind": "oracle",
             "sample": f"{n} consecutive iterations ({n * w['b']} samples) of the same workload "
                       f"on the values the GPU receives, FP64 oracle, {el:.1f} s wall"}
+
+
+def time_to_accuracy(w, target: float, max_steps: int, every: int, hyper=None, log=None):
+    """Time to `target` subspace error (normalised, Gram form of App. A) for a
+    single-handle workload, by the rule: summed step time (HIP events around
+    hipGraph replays of `every` steps) up to the first evaluation at or below
+    target whose next evaluation also is.  Minibatches are refilled and the
+    error evaluated outside the timed region.
+      medium CCA: fresh pairs drawn on the device from the same generator
+                  each chunk; target the population solution (planted
+                  correlations, closed form)
+      tiny CCA:   i.i.d. minibatches of the fixed 10,000-pair pool; target
+                  the pool's exact FP64 solution (oracle)"""
+    import torch
+    import oracle
+    import paper_2206_04993_amd as sg
+    import synth
+    from oracle import targets
+
+    w = dict(w, **(hyper or {}))
+    d, k, b, E = w["dx"] + w["dy"], w["k"], w["b"], every
+    dt = torch.float64 if w["dtype"] == "f64" else torch.float32
+    if w["generator"] == "medium_cca":
+        gen = synth.medium_cca(0)
+        _, Vs = targets.cca_planted_topk(gen, k)
+        _, B = targets.cca_population_AB(gen)
+        ref = "population solution of the generator (planted correlations, closed form)"
+
+        def fill(c, Xb, Yb):
+            x, y = gen.sample_torch(E * b, 1_000_000 + c, "cuda", dt)
+            Xb.copy_(x.view(E, b, -1))
+            Yb.copy_(y.view(E, b, -1))
+    else:
+        gen, pool = synth.tiny_cca_pool(0)
+        pb = oracle.Problem(oracle.KIND_CCA, k, w["dx"], w["dy"])
+        A, B = oracle.problem_matrices(pb, pool.X, pool.Y)
+        _, Vs = oracle.gep_topk(A, B, k)
+        ref = "exact FP64 solution of the 10,000-pair pool (oracle)"
+        PX = torch.from_numpy(pool.X).to("cuda", dt)
+        PY = torch.from_numpy(pool.Y).to("cuda", dt)
+
+        def fill(c, Xb, Yb):
+            idx = np.concatenate([pool.indices(c * E + j + 1, b) for j in range(E)])
+            it = torch.from_numpy(idx).cuda()
+            Xb.copy_(PX.index_select(0, it).view(E, b, -1))
+            Yb.copy_(PY.index_select(0, it).view(E, b, -1))
+    Xb = torch.empty((E, b, w["dx"]), device="cuda", dtype=dt)
+    Yb = torch.empty((E, b, w["dy"]), device="cuda", dtype=dt)
+    stream = torch.cuda.Stream()
+    solver = sg.Solver(config_for(sg, w), synth.initial_players(d, k, 0), stream=stream)
+    fill(0, Xb, Yb)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        for j in range(E):
+            solver.step(Xb[j], Yb[j])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_gpu, steps, hist, hit = 0.0, 0, [], None
+    c = 0
+    while steps < max_steps:
+        if c > 0:
+            fill(c, Xb, Yb)
+            torch.cuda.synchronize()
+        with torch.cuda.stream(stream):  # a graph replays on the current stream
+            e0.record(stream)
+            g.replay()
+            e1.record(stream)
+        e1.synchronize()
+        t_gpu += e0.elapsed_time(e1) * 1e-3
+        steps += E
+        c += 1
+        err = oracle.subspace_error(solver.vectors(), Vs, B)
+        hist.append((steps, t_gpu, err))
+        if log:
+            log(f"tta {w['dtype']} steps {steps} gpu {t_gpu:.3f}s err {err:.3e}")
+        if hit is None and len(hist) >= 2 and hist[-2][2] <= target and err <= target:
+            hit = hist[-2]
+            break
+    solver.close()
+    out = {"target": target, "reached": hit is not None, "eval_every_steps": E,
+           "reference": ref, "stream": ("fresh device-drawn pairs" if w["generator"] ==
+                                         "medium_cca" else "i.i.d. minibatches of the pool"),
+           "final_error": hist[-1][2], "steps_run": steps}
+    if hit is not None:
+        out.update({"seconds": round(hit[1], 4), "steps": hit[0], "samples": hit[0] * b})
+    return out
 
 
 def run_batch(args, w):
@@ -334,17 +429,20 @@ def run_batch(args, w):
                                     [evs[ne * t + i].value for i in range(ne)])
     torch.cuda.synchronize()
     ms = ctypes.c_float()
-    fwd_us, bwd_us = [], []
+    fwd_us, coef_us, bwd_us = [], [], []
     for t in range(Kp):
-        f = bb = 0.0
+        f = cc = bb = 0.0
         for i, kd in enumerate(kinds):
             assert hip.hipEventElapsedTime(ctypes.byref(ms), evs[ne * t + 2 * i],
                                            evs[ne * t + 2 * i + 1]) == 0
             if kd == 0:
                 f += ms.value * 1e3
+            elif kd < 0:
+                cc += ms.value * 1e3
             else:
                 bb += ms.value * 1e3
         fwd_us.append(f)
+        coef_us.append(cc)
         bwd_us.append(bb)
     for e in evs:
         hip.hipEventDestroy(e)
@@ -366,7 +464,9 @@ def run_batch(args, w):
                 "traffic": measured_traffic(args.workload, dom),
                 "kernel": dom, "kernel_avg_us": round(dom_us, 3),
                 "kernel_note": "sum over the step's launches of this kernel",
-                "kernels_avg_us": {"k_bfwd": round(avg_f, 3), "k_bbwd": round(avg_b, 3)},
+                "kernels_avg_us": {"k_bfwd": round(avg_f, 3),
+                                   "k_bcoef": round(float(np.mean(coef_us)), 3),
+                                   "k_bbwd": round(avg_b, 3)},
                 "algorithmic_hbm_bytes_per_launch": dom_bytes,
                 "step_algorithmic_hbm_bytes": step_bytes,
                 "step_hbm_frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 5)}
@@ -435,6 +535,7 @@ def main():
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS) +
                     sorted(BATCH_WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy run")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -493,7 +594,9 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
     solver = sg.Solver(config_for(sg, w), synth.initial_players(d, k, 0), stream=stream, **aux)
-    wide = solver.kernels_per_step() == 3
+    nk = solver.kernels_per_step()
+    wide = w["dtype"] in ("bf16", "fp8")
+    family = "wide" if wide else ("narrow3" if nk == 3 else "narrow2")
 
     def step(t):
         s = t % R
@@ -537,8 +640,8 @@ def main():
 
     # ---- per-kernel durations: the same steps again, each kernel launched
     # with a start/stop HIP event pair stamped by its own dispatch ----
-    names = KERNELS[wide]
-    nk = len(names)
+    names = KERNELS[family]
+    assert len(names) == nk
     hip = hip_runtime()
     Kp = min(K, 512)
     evs = [ctypes.c_void_p() for _ in range(2 * nk * Kp)]
@@ -602,9 +705,19 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
     }
+    solver.close()
+    if "tta" in w and not args.no_tta:
+        tt = w["tta"]
+        print(f"bench: time to {tt['target']:g} subspace error", file=sys.stderr, flush=True)
+        out["time_to_accuracy"] = time_to_accuracy(w, tt["target"], tt["max_steps"], tt["every"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget, host)
-    solver.close()
+        tta = out.get("time_to_accuracy")
+        if tta and tta.get("reached"):
+            # the oracle follows the same iteration: its time per step times
+            # the GPU's step count (an extrapolation, not a run to target)
+            sps = out["cpu_baseline"]["value"] / b
+            out["cpu_baseline"]["time_to_accuracy_extrapolated_s"] = round(tta["steps"] / sps, 3)
     print(json.dumps(out), flush=True)
 
 

@@ -170,10 +170,12 @@ sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
 sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int32_t *labels,
                           int64_t b);
 
-/* Number of kernels one iteration launches: 2 for F64 / F32 (forward
- * products; backward products and update), 3 for BF16 / FP8 (forward
- * products; operand preparation and reductions; backward products and
- * update). */
+/* Number of kernels one iteration launches: for F64 / F32, 2 (forward
+ * products; backward products, k x k coefficients and update) when the
+ * backward tile is one 16-feature block and k * element size <= 128 bytes
+ * after padding, else 3 (forward products; k x k coefficients; backward
+ * products and update); for BF16 / FP8, 3 (forward products; operand
+ * preparation and reductions; backward products and update). */
 sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n);
 
 /* One iteration (sgep_step, or sgep_step_lda when labels is non-NULL) with
@@ -264,8 +266,10 @@ sgep_status sgep_batch_step(sgep_batch *bt, const void *const *X, const void *co
                             int64_t b);
 
 /* Launches of one batched iteration: *n receives their number; kinds (cap
- * entries, nullable) receives 0 for a forward launch and the backward
- * feature-tile height in units of 16 features (1, 2 or 4) otherwise. */
+ * entries, nullable) receives 0 for a forward launch, -1 for a coefficient
+ * launch (the k x k terms of each instance, once per iteration) and the
+ * backward feature-tile height in units of 16 features (1, 2 or 4) for a
+ * backward launch. */
 sgep_status sgep_batch_launches(const sgep_batch *bt, int32_t *n, int32_t *kinds, int32_t cap);
 
 /* sgep_batch_step with a start / end event pair per launch, in launch order

@@ -52,6 +52,7 @@ struct sgep_handle_s {
     void *P = nullptr, *Q = nullptr;
     double *gram_part = nullptr, *stat_part = nullptr, *stat_tot = nullptr, *readout = nullptr;
     Coef *coef = nullptr;
+    void *cpre = nullptr; // coefficient block of the iteration (k_coef)
     int n_tx = 0, n_ty = 0, n_tiles = 0;
     int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
     int64_t W = 0;          // partial width: KP (KP + 1) / 2 + KP
@@ -104,7 +105,7 @@ void free_all(sgep_handle *h)
 {
     void *ptrs[] = {h->V,  h->G,        h->Am,      h->As,    h->P,  h->Q,    h->gram_part,
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
-                    h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior};
+                    h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -188,50 +189,78 @@ sgep_status launch_init(sgep_handle *h)
 // reports.
 template <typename K>
 void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                  const StepArgs &a)
+                  const StepArgs &a, int threads = sgep::kNT)
 {
     if (e0)
-        hipExtLaunchKernelGGL(kernel, grid, dim3(sgep::kNT), 0, s, e0, e1, 0, a);
+        hipExtLaunchKernelGGL(kernel, grid, dim3(threads), 0, s, e0, e1, 0, a);
     else
-        hipLaunchKernelGGL(kernel, grid, dim3(sgep::kNT), 0, s, a);
+        hipLaunchKernelGGL(kernel, grid, dim3(threads), 0, s, a);
 }
 
-template <typename T, int KP, int MB>
+// The backward mode of a single handle: four helper waves compute the
+// coefficients during the main loop when the tile is one 16-feature block
+// and the player tile small enough for eight waves' registers; otherwise
+// k_coef computes them once per iteration.
+template <typename T> bool spec_mode(int kp, int mb) { return mb == 1 && kp * (int)sizeof(T) <= 128; }
+
+template <typename T, int KP, int MB, int MODE>
 void launch_bwd(sgep_handle *h, const StepArgs &a, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 gb(h->n_tiles);
     const bool cca = h->cfg.kind == SGEP_KIND_CCA;
     const bool adam = h->cfg.optimizer == SGEP_ADAM;
+    const int nt = MODE == sgep::kModeSpec ? 2 * sgep::kNT : sgep::kNT;
+    using namespace sgep;
     if (cca && !adam)
-        launch_timed(sgep::k_bwd<T, KP, MB, sgep::kKindCCA, sgep::kOptSGD>, gb, h->stream, e0, e1, a);
+        launch_timed(k_bwd<T, KP, MB, kKindCCA, kOptSGD, MODE>, gb, h->stream, e0, e1, a, nt);
     else if (cca && adam)
-        launch_timed(sgep::k_bwd<T, KP, MB, sgep::kKindCCA, sgep::kOptAdam>, gb, h->stream, e0, e1, a);
+        launch_timed(k_bwd<T, KP, MB, kKindCCA, kOptAdam, MODE>, gb, h->stream, e0, e1, a, nt);
     else if (!adam)
-        launch_timed(sgep::k_bwd<T, KP, MB, sgep::kKindGeneral, sgep::kOptSGD>, gb, h->stream, e0, e1,
-                     a);
+        launch_timed(k_bwd<T, KP, MB, kKindGeneral, kOptSGD, MODE>, gb, h->stream, e0, e1, a, nt);
     else
-        launch_timed(sgep::k_bwd<T, KP, MB, sgep::kKindGeneral, sgep::kOptAdam>, gb, h->stream, e0,
-                     e1, a);
+        launch_timed(k_bwd<T, KP, MB, kKindGeneral, kOptAdam, MODE>, gb, h->stream, e0, e1, a, nt);
 }
 
 template <typename T, int KP>
 sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
 {
     const dim3 gf(a.n_fwd + 1); // + the norm-totals workgroup
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    const bool spec = spec_mode<T>(KP, h->mb);
     if (events)
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < (spec ? 4 : 6); ++i)
             ev[i] = (hipEvent_t)events[i];
-    if (h->cfg.kind == SGEP_KIND_CCA)
+    const bool cca = h->cfg.kind == SGEP_KIND_CCA;
+    if (cca)
         launch_timed(sgep::k_fwd<T, KP, sgep::kKindCCA>, gf, h->stream, ev[0], ev[1], a);
     else
         launch_timed(sgep::k_fwd<T, KP, sgep::kKindGeneral>, gf, h->stream, ev[0], ev[1], a);
-    if (h->mb == 1)
-        launch_bwd<T, KP, 1>(h, a, ev[2], ev[3]);
-    else
-        launch_bwd<T, KP, mb_wide<T>(KP)>(h, a, ev[2], ev[3]);
+    constexpr int MBW = mb_wide<T>(KP);
+    constexpr bool can_spec = KP * (int)sizeof(T) <= 128; // spec_mode's player-tile bound
+    if (spec) {
+        if constexpr (can_spec)
+            launch_bwd<T, KP, 1, sgep::kModeSpec>(h, a, ev[2], ev[3]);
+    } else {
+        if (cca)
+            launch_timed(sgep::k_coef<T, KP, sgep::kKindCCA>, dim3(1), h->stream, ev[2], ev[3], a);
+        else
+            launch_timed(sgep::k_coef<T, KP, sgep::kKindGeneral>, dim3(1), h->stream, ev[2], ev[3],
+                         a);
+        if (h->mb == 1)
+            launch_bwd<T, KP, 1, sgep::kModePre>(h, a, ev[4], ev[5]);
+        else
+            launch_bwd<T, KP, MBW, sgep::kModePre>(h, a, ev[4], ev[5]);
+    }
     HIPCHK(hipGetLastError());
     return SGEP_OK;
+}
+
+// kernels of one iteration of a narrow handle
+int narrow_kernels(const sgep_handle *h)
+{
+    const bool spec = h->esz == sizeof(double) ? spec_mode<double>(h->kp, h->mb)
+                                               : spec_mode<float>(h->kp, h->mb);
+    return spec ? 2 : 3;
 }
 
 template <typename T, int KP>
@@ -739,6 +768,7 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     alloc((void **)&h->stat_tot, (size_t)h->W * sizeof(double));
     alloc((void **)&h->readout, (size_t)d * cfg->k * sizeof(double));
     alloc((void **)&h->coef, sizeof(Coef));
+    alloc(&h->cpre, (size_t)(kp * kp + 3 * kp + 4) * h->esz);
     if (!ok) {
         free_all(h);
         delete h;
@@ -815,6 +845,7 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.stat_part = h->stat_part;
     a.stat_tot = h->stat_tot;
     a.coef = h->coef;
+    a.cpre = h->cpre;
     a.schedule = h->cfg.schedule;
     a.eta0 = h->cfg.eta0;
     a.eta_T = h->cfg.eta_T;
@@ -879,7 +910,7 @@ sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n)
 {
     if (!h || !n)
         return SGEP_EINVAL;
-    *n = h->wide ? 3 : 2;
+    *n = h->wide ? 3 : narrow_kernels(h);
     return SGEP_OK;
 }
 
@@ -889,7 +920,7 @@ sgep_status sgep_step_profiled(sgep_handle *h, const void *X, int64_t ldx, const
 {
     if (!h || !events)
         return SGEP_EINVAL;
-    const int32_t need = h->wide ? 6 : 4;
+    const int32_t need = 2 * (h->wide ? 3 : narrow_kernels(h));
     if (n_events != need)
         return SGEP_EINVAL;
     for (int i = 0; i < need; ++i)
@@ -1167,6 +1198,8 @@ sgep_status apply_plan(sgep_batch *bt, int groups, const int *mb_bucket)
             for (size_t j = 0; j < per; ++j)
                 map.push_back(j < lists[x].size() ? (uint32_t)lists[x][j] : sgep::batch::kNoTile);
         recs.push_back(fr);
+        // coefficients: one workgroup per instance, same map as the forward
+        recs.push_back(BatchLaunchRec{-1, fr.map_off, fr.per_xcd});
         // backward: one launch per tile height in use, entries (instance, tile)
         const int heights[2] = {1, bt->mb_wide};
         for (int hh = 0; hh < 2; ++hh) {
@@ -1226,17 +1259,24 @@ sgep_status batch_launch_t(sgep_batch *bt, const sgep::batch::Launch &base, void
         constexpr int GEN = sgep::kKindGeneral;
         if (r.mb == 0) {
             launch_k(k_bfwd<T, KP, GEN>, dim3((unsigned)(8 * r.per_xcd * (nf + 1))), blk,
-                     bt->stream, e0, e1, L);
+                     bt->stream, e0, e1, L, L.args, L.X, L.Y);
+        } else if (r.mb < 0) {
+            launch_k(k_bcoef<T, KP, GEN>, dim3((unsigned)(8 * r.per_xcd)), blk, bt->stream, e0, e1,
+                     L, L.args, L.X, L.Y);
         } else {
             const dim3 grid((unsigned)(8 * r.per_xcd));
             if (r.mb == 1 && !adam)
-                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptSGD>, grid, blk, bt->stream, e0, e1, L);
+                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptSGD>, grid, blk, bt->stream, e0, e1, L,
+                         L.args, L.X, L.Y);
             else if (r.mb == 1)
-                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptAdam>, grid, blk, bt->stream, e0, e1, L);
+                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptAdam>, grid, blk, bt->stream, e0, e1, L,
+                         L.args, L.X, L.Y);
             else if (!adam)
-                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptSGD>, grid, blk, bt->stream, e0, e1, L);
+                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptSGD>, grid, blk, bt->stream, e0, e1, L,
+                         L.args, L.X, L.Y);
             else
-                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptAdam>, grid, blk, bt->stream, e0, e1, L);
+                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptAdam>, grid, blk, bt->stream, e0, e1, L,
+                         L.args, L.X, L.Y);
         }
     }
     HIPCHK(hipGetLastError());

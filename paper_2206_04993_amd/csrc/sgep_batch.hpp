@@ -5,8 +5,9 @@
 // One iteration of the whole batch is a short, fixed sequence of launches
 // (capturable in one hipGraph).  The instances are split into groups; per
 // group there is one forward launch (sgep_kernels.hpp fwd_body for every row
-// tile of every instance of the group) and one backward launch per feature-
-// tile height in use (bwd_body for every feature tile).  Running the groups
+// tile of every instance of the group), one coefficient launch (coef_body,
+// one workgroup per instance) and one backward launch per feature-tile height
+// in use (bwd_body for every feature tile).  Running the groups
 // one after the other keeps each group's minibatches small enough to still
 // sit in the last-level cache when the backward launch reads them again.
 //
@@ -41,11 +42,15 @@ struct Launch {
 
 // the per-instance arguments of this iteration; vector loads also need
 // 16-byte aligned views (the table's vec_ok covers the leading dimensions)
-__device__ __forceinline__ StepArgs instance_args(const Launch &L, uint32_t inst)
+__device__ __forceinline__ StepArgs instance_args(const Launch &L,
+                                                  const StepArgs *__restrict__ args,
+                                                  const void *const *__restrict__ Xs,
+                                                  const void *const *__restrict__ Ys,
+                                                  uint32_t inst)
 {
-    StepArgs a = L.args[inst];
-    a.X = L.X[inst];
-    a.Y = L.Y[inst];
+    StepArgs a = args[inst];
+    a.X = Xs[inst];
+    a.Y = Ys[inst];
     a.b = L.b;
     a.n_fwd = (int32_t)((L.b + 15) / 16);
     if (((uintptr_t)a.X & 15u) != 0 || ((uintptr_t)a.Y & 15u) != 0)
@@ -57,7 +62,9 @@ __device__ __forceinline__ StepArgs instance_args(const Launch &L, uint32_t inst
 // takes instance map[x * per_xcd + s / (n_fwd + 1)], row tile s % (n_fwd + 1)
 // (the last one of each instance reduces its norm / parent partials).
 template <typename T, int KP, int KIND>
-__global__ void __launch_bounds__(kNT) k_bfwd(Launch L)
+__global__ void __launch_bounds__(kNT) k_bfwd(Launch L, const StepArgs *__restrict__ args,
+                                        const void *const *__restrict__ Xs,
+                                        const void *const *__restrict__ Ys)
 {
     const int nf = (int)((L.b + 15) / 16);
     const int x = blockIdx.x & 7, s = blockIdx.x >> 3;
@@ -67,21 +74,38 @@ __global__ void __launch_bounds__(kNT) k_bfwd(Launch L)
     const uint32_t inst = L.map[x * L.per_xcd + q];
     if (inst == kNoTile)
         return;
-    const StepArgs a = instance_args(L, inst);
+    const StepArgs a = instance_args(L, args, Xs, Ys, inst);
     fwd_body<T, KP, KIND>(a, s - q * (nf + 1));
 }
 
+// Coefficient launch: 8 * per_xcd workgroups over the forward map (one
+// instance per entry); each computes its instance's coefficient block.
+template <typename T, int KP, int KIND>
+__global__ void __launch_bounds__(kNT) k_bcoef(Launch L, const StepArgs *__restrict__ args,
+                                        const void *const *__restrict__ Xs,
+                                        const void *const *__restrict__ Ys)
+{
+    const int x = blockIdx.x & 7, s = blockIdx.x >> 3;
+    const uint32_t inst = L.map[x * L.per_xcd + s];
+    if (inst == kNoTile)
+        return;
+    const StepArgs a = instance_args(L, args, Xs, Ys, inst);
+    coef_body<T, KP, KIND>(a);
+}
+
 // Backward launch: 8 * per_xcd workgroups; slot s of XCD x takes the feature
-// tile map[x * per_xcd + s] (kNoTile: nothing).
+// tile map[x * per_xcd + s] (kNoTile: nothing); coefficients from k_bcoef.
 template <typename T, int KP, int MB, int KIND, int OPT>
-__global__ void __launch_bounds__(kNT) k_bbwd(Launch L)
+__global__ void __launch_bounds__(kNT) k_bbwd(Launch L, const StepArgs *__restrict__ args,
+                                        const void *const *__restrict__ Xs,
+                                        const void *const *__restrict__ Ys)
 {
     const int x = blockIdx.x & 7, s = blockIdx.x >> 3;
     const uint32_t e = L.map[x * L.per_xcd + s];
     if (e == kNoTile)
         return;
-    const StepArgs a = instance_args(L, e >> 16);
-    bwd_body<T, KP, MB, KIND, OPT>(a, (int)(e & 0xffffu));
+    const StepArgs a = instance_args(L, args, Xs, Ys, e >> 16);
+    bwd_body<T, KP, MB, KIND, OPT, kModePre>(a, (int)(e & 0xffffu));
 }
 
 } // namespace batch

@@ -42,9 +42,13 @@
 
 namespace sgep {
 
+// Global-memory pointer type.  Pointers that reach a kernel through memory
+// (the batched argument table) are otherwise generic, and generic (flat)
+// accesses also count against the LDS / scalar wait counter.
+#define SGEP_G __attribute__((address_space(1)))
+
 constexpr int kNT = 256;     // threads per workgroup: four wave64
 constexpr int kKPMax = 64;   // largest padded player count
-constexpr int kScr = 1024;   // LDS scratch (doubles) of the partial reductions
 
 constexpr int kKindCCA = 0;
 constexpr int kKindGeneral = 1;
@@ -116,6 +120,7 @@ struct StepArgs {
     double *stat_part;       // [W][lds]: column tile = backward workgroup tile
     double *stat_tot;        // [W]: reduced stat_part of the state entering this iteration
     Coef *coef;
+    void *cpre;              // coefficient block of the iteration (kModePre)
     int32_t schedule;
     double eta0, eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps;
 };
@@ -165,84 +170,68 @@ __device__ inline double eta_at(const StepArgs &a, double t)
     return a.eta0 * (a.t_c + D) / (t + D);
 }
 
-// out[c] = sum_{r < n} part[c * ld + r] for c < W, by all threads of the
-// workgroup in a fixed order (rows in chunks of 32, chunks in order).
-// ld is even and part 16-byte aligned.  scr: kScr doubles of LDS.
-__device__ inline void colsum(const double *__restrict__ part, int n, int ld, int W,
-                              double *__restrict__ out, double *__restrict__ scr)
+// out[c] = sum_{r < n} part[c * ld + r], rows in ascending order, for c < W:
+// thread q of nthr sums columns q, q + nthr, ...  No synchronisation inside
+// (the caller orders the writes to out).  ld is even and part 16-byte
+// aligned.  Every caller uses this one order, so all obtain the same bits.
+__device__ inline void colsum(const SGEP_G double *__restrict__ part, int n, int ld, int W,
+                              double *__restrict__ out, int q, int nthr)
 {
     constexpr int CH = 32;
-    const int nch = (n + CH - 1) / CH;
-    int per_pass = kScr / nch;
-    if (per_pass < 1)
-        per_pass = 1;
-    for (int c0 = 0; c0 < W; c0 += per_pass) {
-        const int cols = (W - c0 < per_pass) ? W - c0 : per_pass;
-        for (int p = threadIdx.x; p < cols * nch; p += kNT) {
-            const int cl = p / nch, q = p - cl * nch;
-            const double *src = part + (int64_t)(c0 + cl) * ld + q * CH;
-            const int m = (n - q * CH < CH) ? n - q * CH : CH;
-            double s = 0.0;
-            if (m == CH) {
-                f64x2 v[CH / 2];
+    for (int c = q; c < W; c += nthr) {
+        const SGEP_G double *src = part + (int64_t)c * ld;
+        double s = 0.0;
+        int r = 0;
+        for (; r + CH <= n; r += CH) {
+            f64x2 v[CH / 2];
 #pragma unroll
-                for (int u = 0; u < CH / 2; ++u)
-                    v[u] = *reinterpret_cast<const f64x2 *>(src + 2 * u);
+            for (int u = 0; u < CH / 2; ++u)
+                v[u] = *reinterpret_cast<const SGEP_G f64x2 *>(src + r + 2 * u);
 #pragma unroll
-                for (int u = 0; u < CH / 2; ++u) {
-                    s += v[u][0];
-                    s += v[u][1];
-                }
-            } else {
-                for (int r = 0; r < m; ++r)
-                    s += src[r];
+            for (int u = 0; u < CH / 2; ++u) {
+                s += v[u][0];
+                s += v[u][1];
             }
-            scr[p] = s;
         }
-        __syncthreads();
-        for (int cl = threadIdx.x; cl < cols; cl += kNT) {
-            double s = 0.0;
-            for (int q = 0; q < nch; ++q)
-                s += scr[cl * nch + q];
-            out[c0 + cl] = s;
-        }
-        __syncthreads();
+        for (; r < n; ++r)
+            s += src[r];
+        out[c] = s;
     }
 }
 
 template <typename T, int N> struct VecLoad;
 template <> struct VecLoad<float, 1> {
-    static __device__ __forceinline__ void run(const float *p, float *o) { o[0] = p[0]; }
+    static __device__ __forceinline__ void run(const SGEP_G float *p, float *o) { o[0] = p[0]; }
 };
 template <> struct VecLoad<double, 1> {
-    static __device__ __forceinline__ void run(const double *p, double *o) { o[0] = p[0]; }
+    static __device__ __forceinline__ void run(const SGEP_G double *p, double *o) { o[0] = p[0]; }
 };
 template <> struct VecLoad<float, 4> {
-    static __device__ __forceinline__ void run(const float *p, float *o)
+    static __device__ __forceinline__ void run(const SGEP_G float *p, float *o)
     {
-        f32x4 v = *reinterpret_cast<const f32x4 *>(p);
+        f32x4 v = *reinterpret_cast<const SGEP_G f32x4 *>(p);
         o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
     }
 };
 template <> struct VecLoad<float, 2> {
-    static __device__ __forceinline__ void run(const float *p, float *o)
+    static __device__ __forceinline__ void run(const SGEP_G float *p, float *o)
     {
-        f32x2 v = *reinterpret_cast<const f32x2 *>(p);
+        f32x2 v = *reinterpret_cast<const SGEP_G f32x2 *>(p);
         o[0] = v[0]; o[1] = v[1];
     }
 };
 template <> struct VecLoad<double, 2> {
-    static __device__ __forceinline__ void run(const double *p, double *o)
+    static __device__ __forceinline__ void run(const SGEP_G double *p, double *o)
     {
-        f64x2 v = *reinterpret_cast<const f64x2 *>(p);
+        f64x2 v = *reinterpret_cast<const SGEP_G f64x2 *>(p);
         o[0] = v[0]; o[1] = v[1];
     }
 };
 template <> struct VecLoad<double, 4> {
-    static __device__ __forceinline__ void run(const double *p, double *o)
+    static __device__ __forceinline__ void run(const SGEP_G double *p, double *o)
     {
-        f64x2 v0 = *reinterpret_cast<const f64x2 *>(p);
-        f64x2 v1 = *reinterpret_cast<const f64x2 *>(p + 2);
+        f64x2 v0 = *reinterpret_cast<const SGEP_G f64x2 *>(p);
+        f64x2 v1 = *reinterpret_cast<const SGEP_G f64x2 *>(p + 2);
         o[0] = v0[0]; o[1] = v0[1]; o[2] = v1[0]; o[3] = v1[1];
     }
 };
@@ -259,8 +248,9 @@ template <> struct VecLoad<double, 4> {
 // `row` is a valid row index; rows past the minibatch are zeroed through rv.
 // ---------------------------------------------------------------------------
 template <typename T, int KP>
-__device__ __forceinline__ void fwd_view(const T *__restrict__ X, int64_t ldx, int64_t nf, int64_t row,
-                                         bool rv, bool vec_ok, const T *__restrict__ VQ,
+__device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t ldx, int64_t nf,
+                                         int64_t row, bool rv, bool vec_ok,
+                                         const SGEP_G T *__restrict__ VQ,
                                          int lane, int w, typename Mfma<T>::acc (*acc)[KP / 16])
 {
     constexpr int VEC = 16 / (int)sizeof(T);
@@ -272,7 +262,7 @@ __device__ __forceinline__ void fwd_view(const T *__restrict__ X, int64_t ldx, i
     const int64_t nfull = nf / CH; // chunks whose features are all valid
     const int64_t c0 = (nch * w) >> 2, c1 = (nch * (w + 1)) >> 2;
     const int64_t cf = c1 < nfull ? c1 : nfull;
-    const T *xr = X + row * ldx;
+    const SGEP_G T *xr = X + row * ldx;
     for (int64_t c = c0; c < cf; c += U) {
         T xv[U][VEC];
         T bv[U][NB][VEC];
@@ -323,6 +313,93 @@ __device__ __forceinline__ void fwd_view(const T *__restrict__ X, int64_t ldx, i
     }
 }
 
+// Both views of the same width in one pass: the loads of a batch cover the
+// chunks of both, so the memory latency is paid once per batch instead of
+// once per view.  Same arithmetic (per view, chunk order and accumulator
+// assignment) as two calls of fwd_view.  SAMEV (GENERAL: one V for both
+// products) loads the V operand once; a compile-time choice, because a
+// run-time one makes the compiler drain all loads in flight around it.
+template <typename T, int KP, bool SAMEV>
+__device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_t ldx,
+                                          const SGEP_G T *__restrict__ Y, int64_t ldy, int64_t nf,
+                                          int64_t row, bool rv, bool vec_ok,
+                                          const SGEP_G T *__restrict__ VQx,
+                                          const SGEP_G T *__restrict__ VQy,
+                                          int lane, int w, typename Mfma<T>::acc (*accx)[KP / 16],
+                                          typename Mfma<T>::acc (*accy)[KP / 16])
+{
+    constexpr int VEC = 16 / (int)sizeof(T);
+    constexpr int CH = 4 * VEC;
+    constexpr int NB = KP / 16;
+    constexpr int U = 8 / NB;
+    const int kk = lane >> 4, n = lane & 15;
+    const int64_t nch = (nf + CH - 1) / CH;
+    const int64_t nfull = nf / CH;
+    const int64_t c0 = (nch * w) >> 2, c1 = (nch * (w + 1)) >> 2;
+    const int64_t cf = c1 < nfull ? c1 : nfull;
+    const SGEP_G T *xr = X + row * ldx;
+    const SGEP_G T *yr = Y + row * ldy;
+    for (int64_t c = c0; c < cf; c += U) {
+        T xv[U][VEC], yv[U][VEC];
+        T bx[U][NB][VEC], by[U][NB][VEC];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t cu = (c + u < cf) ? c + u : c;
+            const int64_t fb = cu * CH + (int64_t)VEC * kk;
+            if (vec_ok) {
+                VecLoad<T, VEC>::run(xr + fb, xv[u]);
+                VecLoad<T, VEC>::run(yr + fb, yv[u]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    xv[u][j] = xr[fb + j];
+                    yv[u][j] = yr[fb + j];
+                }
+            }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                VecLoad<T, VEC>::run(VQx + qidx<KP>(fb, nb * 16 + n), bx[u][nb]);
+                if (!SAMEV)
+                    VecLoad<T, VEC>::run(VQy + qidx<KP>(fb, nb * 16 + n), by[u][nb]);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0); // the whole batch's loads first
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = rv && (c + u < cf);
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                const T xs = ok ? xv[u][j] : T(0);
+                const T ys = ok ? yv[u][j] : T(0);
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    accx[j & 1][nb] = Mfma<T>::fma(xs, bx[u][nb][j], accx[j & 1][nb]);
+                    accy[j & 1][nb] =
+                        Mfma<T>::fma(ys, SAMEV ? bx[u][nb][j] : by[u][nb][j], accy[j & 1][nb]);
+                }
+            }
+        }
+    }
+    if (nfull < c1 && nfull >= c0) { // the ragged last chunk, features masked
+        const int64_t fb = nfull * CH + (int64_t)VEC * kk;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const int64_t fe = fb + j;
+            const bool fv = fe < nf;
+            const int64_t fc = fv ? fe : nf - 1;
+            const T xs = (rv && fv) ? xr[fc] : T(0);
+            const T ys = (rv && fv) ? yr[fc] : T(0);
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const T bxv = fv ? VQx[qidx<KP>(fc, nb * 16 + n)] : T(0);
+                const T byv = fv ? VQy[qidx<KP>(fc, nb * 16 + n)] : T(0);
+                accx[0][nb] = Mfma<T>::fma(xs, bxv, accx[0][nb]);
+                accy[0][nb] = Mfma<T>::fma(ys, byv, accy[0][nb]);
+            }
+        }
+    }
+}
+
 // Forward body: workgroup blk takes rows 16 blk .. 16 blk + 15; the four waves
 // split the features.  Workgroup blk == n_fwd reduces the norm / parent
 // partials of the current state and advances the step counter.
@@ -341,21 +418,19 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     if (blk == a.n_fwd) {
         // norm / parent-term totals of the current state (sum over the
         // previous backward pass's tiles, fixed order); advance t
-        __shared__ double scr[kScr];
-        __shared__ double tot[GW];
-        colsum(a.stat_part, a.n_tx + a.n_ty, a.lds, GW, tot, scr);
-        for (int e = tid; e < GW; e += kNT)
-            a.stat_tot[e] = tot[e];
+        colsum((const SGEP_G double *)a.stat_part, a.n_tx + a.n_ty, a.lds, GW, a.stat_tot, tid,
+               kNT);
         if (tid == 0)
-            a.coef->t += 1.0; // read by k_bwd only, after this kernel has finished
+            ((SGEP_G Coef *)a.coef)->t += 1.0; // read by k_bwd only, after this kernel has finished
         return;
     }
     const int64_t r0 = (int64_t)blk * 16;
     const bool rv = r0 + n < a.b;
     const int64_t row = rv ? r0 + n : a.b - 1; // valid address; zeroed through rv
     const bool vec_ok = a.vec_ok != 0;
-    const T *X = (const T *)a.X, *Y = (const T *)a.Y, *VQ = (const T *)a.V;
-    T *PQ = (T *)a.P, *QQ = (T *)a.Q;
+    const SGEP_G T *X = (const SGEP_G T *)a.X, *Y = (const SGEP_G T *)a.Y;
+    const SGEP_G T *VQ = (const SGEP_G T *)a.V;
+    SGEP_G T *PQ = (SGEP_G T *)a.P, *QQ = (SGEP_G T *)a.Q;
 
     Acc aP[2][NB], aQ[2][NB];
 #pragma unroll
@@ -365,11 +440,16 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
             aP[h][nb] = Acc{0, 0, 0, 0};
             aQ[h][nb] = Acc{0, 0, 0, 0};
         }
-    fwd_view<T, KP>(X, a.ldx, a.dx, row, rv, vec_ok, VQ, lane, w, aP);
-    if (KIND == kKindCCA) // view y starts at feature dxp (a multiple of 4)
-        fwd_view<T, KP>(Y, a.ldy, a.dy, row, rv, vec_ok, VQ + a.dxp * KP, lane, w, aQ);
-    else
-        fwd_view<T, KP>(Y, a.ldy, a.dx, row, rv, vec_ok, VQ, lane, w, aQ);
+    // view y's players start at feature dxp (a multiple of 4) for CCA
+    const SGEP_G T *VQy = KIND == kKindCCA ? VQ + a.dxp * KP : VQ;
+    const int64_t nfy = KIND == kKindCCA ? a.dy : a.dx;
+    if (nfy == a.dx) {
+        fwd_view2<T, KP, KIND != kKindCCA>(X, a.ldx, Y, a.ldy, a.dx, row, rv, vec_ok, VQ, VQy,
+                                           lane, w, aP, aQ);
+    } else {
+        fwd_view<T, KP>(X, a.ldx, a.dx, row, rv, vec_ok, VQ, lane, w, aP);
+        fwd_view<T, KP>(Y, a.ldy, nfy, row, rv, vec_ok, VQy, lane, w, aQ);
+    }
 
     // sum the accumulator sets and the four waves' tiles in a fixed order
 #pragma unroll
@@ -425,7 +505,7 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
                     s += (double)pt[r][i] * (double)pt[r][i];
             }
         }
-        a.gram_part[(int64_t)e * a.ldg + blk] = s;
+        ((SGEP_G double *)a.gram_part)[(int64_t)e * a.ldg + blk] = s;
     }
 }
 
@@ -433,6 +513,165 @@ template <typename T, int KP, int KIND>
 __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 {
     fwd_body<T, KP, KIND>(a, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Coefficients of one iteration, as the backward epilogue uses them: with the
+// totals ss of the state entering the iteration (||V_i||^2, V_i^T G_j) and
+// the minibatch Gram totals gs (lower b V^T A_t V, diagonal of b V^T B_t V,
+// raw players), inv_i = 1/||V_i||, s_j = max(v_j^T G_j, rho), the penalty
+// weights T_ij = (M_A)_ij / s_j (j < i), m_B,i, m_A,i - c_i with
+// c_i = sum_{j<i} T_ij C_ij, the step size and the Adam bias corrections.
+// Computed either by four extra waves of the backward workgroup while the
+// main waves stream the minibatch (few workgroups), or once per iteration by
+// k_coef (many workgroups); both run the functions below, so both give the
+// same bits.
+// ---------------------------------------------------------------------------
+constexpr int kModePre = 0;  // backward reads the block k_coef wrote
+constexpr int kModeSpec = 1; // backward computes it on four extra waves
+
+template <typename T, int KP> struct CoefTile {
+    T Tl[KP * KP];            // T_ij, row i
+    T mB[KP], mAc[KP], inv[KP];
+    T eta, c1, c2, pad;       // eta_t, 1 - b1^t, 1 - b2^t
+};
+
+// inv_i and s_i (thread q < KP)
+template <int KP>
+__device__ __forceinline__ void coef_norms(const StepArgs &a, const double *ss, double *dInv,
+                                           double *dS, int q)
+{
+    constexpr int TRI = KP * (KP + 1) / 2;
+    if (q < KP) {
+        const int i = q;
+        double inv = 0.0, s = 1.0;
+        if (i < a.k) {
+            inv = 1.0 / sqrt(ss[TRI + i]);
+            s = ss[tri_idx(i, i)] * inv; // v_i^T G_i with the unit v_i
+            if (!(s >= a.rho))
+                s = a.rho;
+        }
+        dInv[i] = inv;
+        dS[i] = s;
+    }
+}
+
+// T_ij = (M_A)_ij / s_j with (M_A)_ij = b^{-1} inv_i inv_j (raw Gram)_ij, in
+// the element type (Tl) and in FP64 (Td)
+template <typename T, int KP>
+__device__ __forceinline__ void coef_T(const StepArgs &a, const double *gs, const double *dInv,
+                                       const double *dS, T *Tl, double *Td, int q, int nthr)
+{
+    const double ib = 1.0 / (double)a.b;
+    for (int e = q; e < KP * KP; e += nthr) {
+        const int i = e / KP, j = e % KP;
+        double v = 0.0;
+        if (i < a.k && j < i)
+            v = gs[tri_idx(i, j)] * dInv[i] * dInv[j] * ib / dS[j];
+        Tl[e] = (T)v;
+        Td[e] = v;
+    }
+}
+
+// Terms of the iteration that depend only on its number t: eta_t and the Adam
+// bias corrections (thread q == 0), and the running means the writer updates
+// (thread q < KP, into ema[2 KP]); read before the Gram totals are known
+template <typename T, int KP>
+__device__ __forceinline__ void coef_early(const StepArgs &a, double t, CoefTile<T, KP> &C,
+                                           double *ema, bool writer, int q)
+{
+    if (q == 0) {
+        C.eta = (T)eta_at(a, t);
+        C.c1 = (T)(1.0 - pow(a.adam_b1, t));
+        C.c2 = (T)(1.0 - pow(a.adam_b2, t));
+        C.pad = T(0);
+    }
+    if (writer && q < KP) {
+        const SGEP_G Coef *cg = (const SGEP_G Coef *)a.coef;
+        ema[q] = cg->ema_a[q];
+        ema[KP + q] = cg->ema_b[q];
+    }
+}
+
+// m_A, m_B, c per player (thread q < KP), the uniform terms (q == 0), and --
+// by the one writer of the iteration -- the running means, clip count,
+// status word and the public coefficient fields
+template <typename T, int KP, int KIND>
+__device__ __forceinline__ void coef_rows(const StepArgs &a, const double *gs, const double *ss,
+                                          const double *dInv, const double *dS, const double *Td,
+                                          const double *ema, double t, CoefTile<T, KP> &C,
+                                          bool writer, int q)
+{
+    constexpr int TRI = KP * (KP + 1) / 2;
+    const double ib = 1.0 / (double)a.b;
+    SGEP_G Coef *cw = (SGEP_G Coef *)a.coef;
+    if (q < KP) {
+        const int i = q;
+        double mA = 0.0, mB = 0.0, c = 0.0;
+        if (i < a.k) {
+            const double ii2 = dInv[i] * dInv[i];
+            mA = gs[tri_idx(i, i)] * ii2 * ib;
+            mB = gs[TRI + i] * ii2 * ib + (KIND == kKindCCA ? 0.0 : a.eps_reg);
+            for (int j = 0; j < i; ++j)
+                c += Td[i * KP + j] * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
+        }
+        C.mB[i] = (T)mB;
+        C.mAc[i] = (T)(mA - c);
+        C.inv[i] = (T)dInv[i];
+        if (writer) {
+            if (i < a.k) {
+                cw->ema_a[i] = ema[i] + a.gamma * (mA - ema[i]);
+                cw->ema_b[i] = ema[KP + i] + a.gamma * (mB - ema[KP + i]);
+                const double craw = ss[tri_idx(i, i)] * dInv[i];
+                if (!(craw >= a.rho))
+                    atomicAdd((int *)&cw->clip_count, 1);
+                if (!isfinite(mA) || !isfinite(mB) || !isfinite(c) || !isfinite(dInv[i]) ||
+                    !(dInv[i] > 0.0) || !isfinite(craw))
+                    atomicOr((int *)&cw->status, kStatusNonFinite);
+            }
+            cw->mA[i] = mA;
+            cw->mB[i] = mB;
+            cw->c[i] = c;
+            cw->s[i] = dS[i];
+            if (i == 0) {
+                cw->eta = eta_at(a, t);
+                cw->gamma = a.gamma;
+            }
+        }
+    }
+}
+
+// k_coef: one workgroup computes the iteration's coefficient block into
+// a.cpre (used with the backward mode kModePre)
+template <typename T, int KP, int KIND>
+__device__ __forceinline__ void coef_body(const StepArgs &a)
+{
+    constexpr int W = KP * (KP + 1) / 2 + KP;
+    constexpr int NC = (int)(sizeof(CoefTile<T, KP>) / sizeof(T));
+    __shared__ double gs[W], ss[W], dInv[KP], dS[KP], Td[KP * KP], ema[2 * KP];
+    __shared__ CoefTile<T, KP> C;
+    const int tid = threadIdx.x;
+    const double t = ((const SGEP_G Coef *)a.coef)->t; // this iteration's number (k_fwd)
+    coef_early<T, KP>(a, t, C, ema, true, tid);
+    for (int e = tid; e < W; e += kNT)
+        ss[e] = ((const SGEP_G double *)a.stat_tot)[e];
+    colsum((const SGEP_G double *)a.gram_part, a.n_fwd, a.ldg, W, gs, tid, kNT);
+    __syncthreads();
+    coef_norms<KP>(a, ss, dInv, dS, tid);
+    __syncthreads();
+    coef_T<T, KP>(a, gs, dInv, dS, C.Tl, Td, tid, kNT);
+    __syncthreads();
+    coef_rows<T, KP, KIND>(a, gs, ss, dInv, dS, Td, ema, t, C, true, tid);
+    __syncthreads();
+    SGEP_G T *out = (SGEP_G T *)a.cpre;
+    for (int e = tid; e < NC; e += kNT)
+        out[e] = (&C.Tl[0])[e];
+}
+
+template <typename T, int KP, int KIND>
+__global__ void __launch_bounds__(kNT) k_coef(StepArgs a)
+{
+    coef_body<T, KP, KIND>(a);
 }
 
 // ---------------------------------------------------------------------------
@@ -444,8 +683,12 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 // of P^T / Q^T for player l % 16 (one 16-byte load), so M-block jm, M-row m
 // holds feature f0 + MB m + jm.  Batches of UB groups issue all loads before
 // any MFMA; the ragged last group runs masked.
+//
+// MODE kModeSpec: the workgroup has eight waves; waves 4..7 reduce the Gram
+// partials and compute the coefficients while waves 0..3 run the main loop.
+// MODE kModePre: four waves; the coefficient block comes from k_coef.
 // ---------------------------------------------------------------------------
-template <typename T, int KP, int MB, int KIND, int OPT>
+template <typename T, int KP, int MB, int KIND, int OPT, int MODE>
 __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
 {
     typedef typename Mfma<T>::acc Acc;
@@ -454,27 +697,36 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
     constexpr int TRI = KP * (KP + 1) / 2;
     constexpr int W = TRI + KP; // width of both partial kinds
     constexpr int XPG = (KIND == kKindCCA ? 4 : 8) * MB; // X registers per group
-    constexpr int UB0 = 512 / ((XPG + 8 * NB) * (int)sizeof(T)); // ~128 VGPRs in flight
+    // loads in flight per batch: ~128 VGPRs, or ~192 for the smallest player
+    // tile with eight waves (kModeSpec; one workgroup per CU, fewer round
+    // trips, still within 256 VGPRs)
+    constexpr bool BIG = MODE == 1 && KP * (int)sizeof(T) <= 64;
+    constexpr int UB0 = (BIG ? 768 : 512) / ((XPG + 8 * NB) * (int)sizeof(T));
     constexpr int UB = UB0 < 1 ? 1 : (UB0 > 16 ? 16 : UB0);
     constexpr int EPT = FT * KP / kNT; // epilogue elements per thread
     static_assert(EPT * kNT == FT * KP, "tile must be a multiple of the workgroup");
+    constexpr bool SPEC = MODE == kModeSpec;
+    constexpr int NTH = SPEC ? 2 * kNT : kNT; // threads of the workgroup
+    constexpr int NC = (int)(sizeof(CoefTile<T, KP>) / sizeof(T));
+    constexpr int CPT = SPEC ? 1 : (NC + kNT - 1) / kNT;
     __shared__ T red[4][FT * KP];
     __shared__ T avt[FT * KP], bvt[FT * KP], gt[FT * KP];
-    __shared__ T Tl[KP * KP];
-    __shared__ T cMB[KP], cMAc[KP], cInv[KP];
-    __shared__ double gs[W], ss[W], scr[kScr];
-    __shared__ double dInv[KP], dS[KP];
+    __shared__ CoefTile<T, KP> C;
+    __shared__ double gs[SPEC ? W : 1], ss[SPEC ? W : 1], Td[SPEC ? KP * KP : 1];
+    __shared__ double dInv[KP], dS[KP], ema[2 * KP];
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
+    const bool main_w = !SPEC || w < 4;
     const int kk = lane >> 4, m = lane & 15;
     const bool vec_ok = a.vec_ok != 0;
-    const T *X = (const T *)a.X, *Y = (const T *)a.Y;
-    const T *PQ = (const T *)a.P, *QQ = (const T *)a.Q;
+    const SGEP_G T *X = (const SGEP_G T *)a.X, *Y = (const SGEP_G T *)a.Y;
+    const SGEP_G T *PQ = (const SGEP_G T *)a.P, *QQ = (const SGEP_G T *)a.Q;
 
-    const T *Xa;      // view multiplying the A-side operand
-    const T *Xb;      // view multiplying the B-side operand
+    const SGEP_G T *Xa;      // view multiplying the A-side operand
+    const SGEP_G T *Xb;      // view multiplying the B-side operand
     int64_t lda, ldb, nf, fbase, f0;
-    const T *opA, *opB;
+    const SGEP_G T *opA, *opB;
     if (KIND == kKindCCA) {
         if (tile < a.n_tx) { // x features: A_t V = X^T Q / b, B_t V = X^T P / b
             Xa = X; lda = a.ldx; nf = a.dx; fbase = 0; f0 = (int64_t)tile * FT;
@@ -493,9 +745,31 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
     // epilogue operands of this thread's elements: element e of the tile's
     // contiguous quad-interleaved block, i.e. feature f0 + 4 (e / 4KP) + e % 4
     // of player (e / 4) % KP
-    T *VQ = (T *)a.V, *GQ = (T *)a.G, *Am = (T *)a.Am, *As = (T *)a.As;
+    SGEP_G T *VQ = (SGEP_G T *)a.V, *GQ = (SGEP_G T *)a.G;
+    SGEP_G T *Am = (SGEP_G T *)a.Am, *As = (SGEP_G T *)a.As;
     const int64_t tbase = (fbase + f0) * KP; // first element of this tile's block
     T pv[EPT], pg[EPT], pm[EPT], ps[EPT];
+    T cpr[CPT]; // kModePre: this thread's elements of the coefficient block
+    typedef typename Mfma<T>::acc Acc2;
+    Acc2 aA[2][MB][NB], aB[2][MB][NB];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < MB; ++j)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                aA[h][j][nb] = Acc2{0, 0, 0, 0};
+                aB[h][j][nb] = Acc2{0, 0, 0, 0};
+            }
+    double t_it = 0.0; // helper waves: this iteration's number (set by k_fwd)
+    if (main_w) {
+    if (!SPEC) {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int e = tid + q * kNT;
+            cpr[q] = e < NC ? ((const SGEP_G T *)a.cpre)[e] : T(0);
+        }
+    }
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
         const int e = tid + q * kNT;
@@ -511,16 +785,6 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
     }
 
     // ---- main loop: raw X^T Q and X^T P over all rows ----
-    Acc aA[2][MB][NB], aB[2][MB][NB];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int j = 0; j < MB; ++j)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                aA[h][j][nb] = Acc{0, 0, 0, 0};
-                aB[h][j][nb] = Acc{0, 0, 0, 0};
-            }
     const int64_t fs = f0 + (int64_t)MB * m;
     bool fok[MB];
     int64_t fcl[MB];
@@ -530,7 +794,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
         fcl[jm] = fok[jm] ? fs + jm : nf - 1;
     }
     const bool vrun = vec_ok && fs + MB <= nf;
-    const T *pa[NB], *pb[NB]; // player (nb*16 + m): rows r..r+3 at p[r * KP]
+    const SGEP_G T *pa[NB], *pb[NB]; // player (nb*16 + m): rows r..r+3 at p[r * KP]
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         pa[nb] = opA + 4 * (nb * 16 + m);
@@ -606,112 +870,86 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
             }
         }
     }
-
-    // cross-wave reduction (fixed order) into natural feature order [fl][i]
-#pragma unroll
-    for (int jm = 0; jm < MB; ++jm)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const Acc s = aA[0][jm][nb] + aA[1][jm][nb];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
-        }
-    __syncthreads();
-    for (int e = tid; e < FT * KP; e += kNT)
-        avt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
-    __syncthreads();
-#pragma unroll
-    for (int jm = 0; jm < MB; ++jm)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const Acc s = aB[0][jm][nb] + aB[1][jm][nb];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
-        }
-    __syncthreads();
-    for (int e = tid; e < FT * KP; e += kNT)
-        bvt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-        const int e = tid + q * kNT;
-        gt[(4 * (e / (4 * KP)) + (e & 3)) * KP + (e / 4) % KP] = pg[q];
+    } else {
+        // helper waves (kModeSpec): t-dependent terms, state totals and
+        // Gram totals
+        const int q = tid - kNT;
+        t_it = ((const SGEP_G Coef *)a.coef)->t;
+        coef_early<T, KP>(a, t_it, C, ema, tile == 0, q);
+        for (int e = q; e < W; e += kNT)
+            ss[e] = ((const SGEP_G double *)a.stat_tot)[e];
+        colsum((const SGEP_G double *)a.gram_part, a.n_fwd, a.ldg, W, gs, q, kNT);
     }
 
-    // ---- k x k coefficients (identical in every workgroup) ----
-    Coef *cw = a.coef;
-    const double t = cw->t; // this iteration's number, set by k_fwd
-    for (int e = tid; e < W; e += kNT)
-        ss[e] = a.stat_tot[e];
-    colsum(a.gram_part, a.n_fwd, a.ldg, W, gs, scr);
-    const double ib = 1.0 / (double)a.b;
-    if (tid < KP) {
-        const int i = tid;
-        double inv = 0.0, s = 1.0;
-        if (i < a.k) {
-            inv = 1.0 / sqrt(ss[TRI + i]);
-            s = ss[tri_idx(i, i)] * inv; // v_i^T G_i with the unit v_i
-            if (!(s >= a.rho))
-                s = a.rho;
+    // cross-wave reduction (fixed order) into natural feature order [fl][i],
+    // interleaved with the helper waves' coefficient phases (the barriers are
+    // common to all waves)
+    __syncthreads();
+    if (main_w) {
+#pragma unroll
+        for (int jm = 0; jm < MB; ++jm)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const Acc s = aA[0][jm][nb] + aA[1][jm][nb];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
+            }
+        if (!SPEC) {
+#pragma unroll
+            for (int q = 0; q < CPT; ++q) {
+                const int e = tid + q * kNT;
+                if (e < NC)
+                    (&C.Tl[0])[e] = cpr[q];
+            }
         }
-        dInv[i] = inv;
-        dS[i] = s;
+    } else {
+        coef_norms<KP>(a, ss, dInv, dS, tid - kNT);
     }
     __syncthreads();
-    // T_ij = (M_A)_ij / s_j with (M_A)_ij = b^{-1} inv_i inv_j (raw Gram)_ij
-    for (int e = tid; e < KP * KP; e += kNT) {
-        const int i = e / KP, j = e % KP;
-        double v = 0.0;
-        if (i < a.k && j < i)
-            v = gs[tri_idx(i, j)] * dInv[i] * dInv[j] * ib / dS[j];
-        Tl[e] = (T)v;
+    if (main_w) {
+        for (int e = tid; e < FT * KP; e += kNT)
+            avt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    } else {
+        coef_T<T, KP>(a, gs, dInv, dS, C.Tl, Td, tid - kNT, kNT);
     }
-    if (tid < KP) {
-        const int i = tid;
-        double mA = 0.0, mB = 0.0, c = 0.0;
-        if (i < a.k) {
-            const double ii2 = dInv[i] * dInv[i];
-            mA = gs[tri_idx(i, i)] * ii2 * ib;
-            mB = gs[TRI + i] * ii2 * ib + (KIND == kKindCCA ? 0.0 : a.eps_reg);
-            for (int j = 0; j < i; ++j) {
-                const double Tij = gs[tri_idx(i, j)] * dInv[i] * dInv[j] * ib / dS[j];
-                c += Tij * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
-            }
-        }
-        cMB[i] = (T)mB;
-        cMAc[i] = (T)(mA - c);
-        cInv[i] = (T)dInv[i];
-        if (tile == 0) {
-            if (i < a.k) {
-                cw->ema_a[i] += a.gamma * (mA - cw->ema_a[i]);
-                cw->ema_b[i] += a.gamma * (mB - cw->ema_b[i]);
-                const double craw = ss[tri_idx(i, i)] * dInv[i];
-                if (!(craw >= a.rho))
-                    atomicAdd(&cw->clip_count, 1);
-                if (!isfinite(mA) || !isfinite(mB) || !isfinite(c) || !isfinite(dInv[i]) ||
-                    !(dInv[i] > 0.0) || !isfinite(craw))
-                    atomicOr(&cw->status, kStatusNonFinite);
-            }
-            cw->mA[i] = mA;
-            cw->mB[i] = mB;
-            cw->c[i] = c;
-            cw->s[i] = dS[i];
-            if (i == 0) {
-                cw->eta = eta_at(a, t);
-                cw->gamma = a.gamma;
-            }
-        }
-    }
-    // ---- fused epilogue ----
     __syncthreads();
-    const T eta = (T)eta_at(a, t), gam = (T)a.gamma, ibT = (T)ib;
+    if (main_w) {
+#pragma unroll
+        for (int jm = 0; jm < MB; ++jm)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const Acc s = aB[0][jm][nb] + aB[1][jm][nb];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
+            }
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = tid + q * kNT;
+            gt[(4 * (e / (4 * KP)) + (e & 3)) * KP + (e / 4) % KP] = pg[q];
+        }
+    } else {
+        // this iteration's number t was set by k_fwd
+        coef_rows<T, KP, KIND>(a, gs, ss, dInv, dS, Td, ema, t_it, C, tile == 0, tid - kNT);
+    }
+    __syncthreads();
+    if (main_w) {
+        for (int e = tid; e < FT * KP; e += kNT)
+            bvt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    }
+
+    // ---- fused epilogue (main waves) ----
+    __syncthreads();
+    const T gam = (T)a.gamma, ibT = (T)(1.0 / (double)a.b);
     const T eps = (T)a.eps_reg;
     const T b1 = (T)a.adam_b1, b2 = (T)a.adam_b2, aeps = (T)a.adam_eps;
-    const T c1 = (T)(1.0 - pow(a.adam_b1, t)), c2 = (T)(1.0 - pow(a.adam_b2, t));
+    const T eta = C.eta, c1 = C.c1, c2 = C.c2;
     T vnq[EPT], gnq[EPT];
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
+        if (!main_w)
+            break;
         const int e = tid + q * kNT;
         const int i = (e / 4) % KP, fl = 4 * (e / (4 * KP)) + (e & 3);
         const int64_t f = f0 + fl;
@@ -719,15 +957,15 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
         if (f < nf && i < a.k) {
             const int64_t si = tbase + e;
             const int ti = fl * KP + i;
-            const T vh = pv[q] * cInv[i];
-            const T av = avt[ti] * cInv[i] * ibT;
-            T bv = bvt[ti] * cInv[i] * ibT;
+            const T vh = pv[q] * C.inv[i];
+            const T av = avt[ti] * C.inv[i] * ibT;
+            T bv = bvt[ti] * C.inv[i] * ibT;
             if (KIND != kKindCCA)
                 bv += eps * vh;
             T pen = 0;
             for (int j = 0; j < i; ++j)
-                pen += Tl[i * KP + j] * gt[fl * KP + j];
-            const T grad = (av - pen) * cMB[i] - bv * cMAc[i];
+                pen += C.Tl[i * KP + j] * gt[fl * KP + j];
+            const T grad = (av - pen) * C.mB[i] - bv * C.mAc[i];
             if (OPT == kOptSGD) {
                 vn = vh + eta * grad;
             } else {
@@ -748,6 +986,8 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
     __syncthreads(); // every read of avt / bvt is done
 #pragma unroll
     for (int q = 0; q < EPT; ++q) {
+        if (!main_w)
+            break;
         const int e = tid + q * kNT;
         const int ti = (4 * (e / (4 * KP)) + (e & 3)) * KP + (e / 4) % KP;
         avt[ti] = vnq[q];
@@ -755,8 +995,8 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
     }
     __syncthreads();
     // this tile's partials of v_i^T G_j (j <= i) and ||v_i||^2 of the new state
-    double *sout = a.stat_part;
-    for (int e = tid; e < W; e += kNT) {
+    SGEP_G double *sout = (SGEP_G double *)a.stat_part;
+    for (int e = tid; e < W; e += NTH) {
         double s = 0.0;
         if (e < TRI) {
             int i, j;
@@ -772,10 +1012,10 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
     }
 }
 
-template <typename T, int KP, int MB, int KIND, int OPT>
-__global__ void __launch_bounds__(kNT) k_bwd(StepArgs a)
+template <typename T, int KP, int MB, int KIND, int OPT, int MODE>
+__global__ void __launch_bounds__(MODE == kModeSpec ? 2 * kNT : kNT) k_bwd(StepArgs a)
 {
-    bwd_body<T, KP, MB, KIND, OPT>(a, xcd_tile(blockIdx.x, gridDim.x));
+    bwd_body<T, KP, MB, KIND, OPT, MODE>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // ---------------------------------------------------------------------------
@@ -843,9 +1083,10 @@ __global__ void __launch_bounds__(kNT) k_readout(const T *S, int64_t d, int64_t 
 {
     constexpr int TRI = KP * (KP + 1) / 2;
     constexpr int W = TRI + KP;
-    __shared__ double ss[W], scr[kScr];
+    __shared__ double ss[W];
     __shared__ double scale[KP];
-    colsum(stat_part, n_tiles, lds, W, ss, scr);
+    colsum((const SGEP_G double *)stat_part, n_tiles, lds, W, ss, threadIdx.x, kNT);
+    __syncthreads();
     if (threadIdx.x < KP) {
         const int i = threadIdx.x;
         double sc = 1.0;

@@ -93,6 +93,28 @@ class CCAPlanted:
         """Fresh minibatch number t (float64)."""
         return self.sample(b, np.random.default_rng([self.seed + 1, t]))
 
+    def sample_torch(self, n: int, t: int, device, dtype):
+        """n fresh pairs drawn on `device` from a torch generator seeded by
+        (seed, t), with the mixing maps in FP32 (same distribution as
+        ``sample``, different values)."""
+        import torch
+        g = torch.Generator(device=device)
+        g.manual_seed((int(self.seed) * 1_000_003 + 7919 * int(t) + 1) & ((1 << 63) - 1))
+        f32 = torch.float32
+        r = len(self.rho)
+        rho = torch.from_numpy(self.rho).to(device=device, dtype=f32)
+        z = torch.randn((n, r), generator=g, device=device, dtype=f32)
+        xi = torch.randn((n, r), generator=g, device=device, dtype=f32)
+        z2 = z * rho + xi * torch.sqrt(1.0 - rho * rho)
+        ux = torch.cat([z, torch.randn((n, self.n_free), generator=g, device=device, dtype=f32)], 1)
+        uy = torch.cat([z2, torch.randn((n, self.n_free), generator=g, device=device, dtype=f32)], 1)
+        x = ux @ torch.from_numpy(self.Wx.T).to(device=device, dtype=f32)
+        y = uy @ torch.from_numpy(self.Wy.T).to(device=device, dtype=f32)
+        if self.sigma:
+            x += self.sigma * torch.randn((n, self.dx), generator=g, device=device, dtype=f32)
+            y += self.sigma * torch.randn((n, self.dy), generator=g, device=device, dtype=f32)
+        return x.to(dtype), y.to(dtype)
+
 
 def tiny_cca(seed: int = 0) -> CCAPlanted:
     """Two views of width 8 from 4 latent pairs with correlations

@@ -110,7 +110,7 @@ def test_batch_matches_single_handles_and_oracle(dtype, adam):
         ref.set_plan(groups, mb)
         kinds = bat.launches()
         print(f"{dtype} adam={adam} plan={bat.plan()} launches={kinds}")
-        assert kinds.count(0) == bat.plan()[0]
+        assert kinds.count(0) == bat.plan()[0] and kinds.count(-1) == bat.plan()[0]
         for t in range(T):
             bat.step(*data.ptrs[t], b)
             xs, ys = data.dev[t]
