@@ -51,15 +51,27 @@ WORKLOADS = {
     "cca_d1024_k16_b1024_fp32": dict(
         kind="cca", dtype="f32", dx=512, dy=512, k=16, b=1024, ring=128,
         optimizer="adam", schedule="inv", eta0=4e-3, t0=100.0, gamma=0.3, rho=1e-6,
-        generator="medium_cca", tta=dict(target=1e-3, max_steps=100_000, every=1000),
+        generator="medium_cca", tta=dict(targets=(5e-3, 1e-3), max_steps=100_000, every=1000),
         describe="CCA FP32: views 512+512 (d=1024), k=16, minibatch 1024; planted "
                  "correlations linspace(0.95,0.2,16), per-view condition 100"),
     "cca_d16_k4_b128_fp64": dict(
         kind="cca", dtype="f64", dx=8, dy=8, k=4, b=128, ring=128,
         optimizer="sgd", schedule="inv", eta0=1.0, t0=200.0, gamma=1.0, rho=1e-6,
-        generator="tiny_cca", tta=dict(target=1e-3, max_steps=6000, every=100),
+        generator="tiny_cca", tta=dict(targets=(1e-3,), max_steps=6000, every=100),
         describe="CCA FP64: views 8+8 (d=16), k=4, minibatch 128; planted "
                  "correlations 0.9,0.7,0.5,0.3"),
+    "cca_d1024_k16_b1024_bf16": dict(
+        kind="cca", dtype="bf16", dx=512, dy=512, k=16, b=1024, ring=128,
+        optimizer="adam", schedule="inv", eta0=4e-3, t0=100.0, gamma=0.3, rho=1e-6,
+        generator="medium_cca", tta=dict(targets=(5e-3, 1e-3), max_steps=100_000, every=1000),
+        describe="CCA BF16 ingest of the medium problem: views 512+512 (d=1024), k=16, "
+                 "minibatch 1024 (same generator and target as the FP32 workload)"),
+    "cca_d1024_k16_b1024_fp8": dict(
+        kind="cca", dtype="fp8", dx=512, dy=512, k=16, b=1024, ring=128,
+        optimizer="adam", schedule="inv", eta0=4e-3, t0=100.0, gamma=0.3, rho=1e-6,
+        generator="medium_cca", tta=dict(targets=(5e-3, 1e-3), max_steps=100_000, every=1000),
+        describe="CCA FP8-e4m3 ingest (per-column scales) of the medium problem: views 512+512 "
+                 "(d=1024), k=16, minibatch 1024"),
     "cca_d16384_k32_b4096_bf16": dict(
         _C3, dtype="bf16",
         describe="CCA BF16: activation-like views 8192+8192 (d=16384), k=32, minibatch 4096; "
@@ -266,14 +278,29 @@ def cpu_baseline(w, budget_s: float, host):
                       f"on the values the GPU receives, FP64 oracle, {el:.1f} s wall"}
 
 
-def time_to_accuracy(w, target: float, max_steps: int, every: int, hyper=None, log=None):
-    """Time to `target` subspace error (normalised, Gram form of App. A) for a
-    single-handle workload, by the rule: summed step time (HIP events around
-    hipGraph replays of `every` steps) up to the first evaluation at or below
-    target whose next evaluation also is.  Minibatches are refilled and the
-    error evaluated outside the timed region.
+def calibration_copy(mib: int):
+    """A plain device copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+    calibrate the per-dispatch counters of the step kernels."""
+    import torch
+    src = torch.ones(mib << 18, device="cuda", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
+def time_to_accuracy(w, targets, max_steps: int, every: int, hyper=None, log=None):
+    """Time to each subspace error in `targets` (normalised, Gram form of
+    App. A) for a single-handle workload, by the rule: summed step time (HIP
+    events around hipGraph replays of `every` steps) up to the first
+    evaluation at or below the target whose next evaluation also is.
+    Minibatches are refilled and the error evaluated outside the timed region;
+    the run stops when the smallest target is met or after max_steps.
       medium CCA: fresh pairs drawn on the device from the same generator
-                  each chunk; target the population solution (planted
+                  each chunk (stored in the workload's format: FP32, BF16, or
+                  FP8-e4m3 with per-column scales fixed from a 65,536-pair
+                  prefix); target the population solution (planted
                   correlations, closed form)
       tiny CCA:   i.i.d. minibatches of the fixed 10,000-pair pool; target
                   the pool's exact FP64 solution (oracle)"""
@@ -281,39 +308,56 @@ def time_to_accuracy(w, target: float, max_steps: int, every: int, hyper=None, l
     import oracle
     import paper_2206_04993_amd as sg
     import synth
-    from oracle import targets
+    from oracle import targets as otargets
 
     w = dict(w, **(hyper or {}))
+    targets = sorted(targets, reverse=True)
     d, k, b, E = w["dx"] + w["dy"], w["k"], w["b"], every
-    dt = torch.float64 if w["dtype"] == "f64" else torch.float32
+    fmt = w["dtype"]
+    store = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+             "fp8": torch.uint8}[fmt]
+    aux = {}
     if w["generator"] == "medium_cca":
         gen = synth.medium_cca(0)
-        _, Vs = targets.cca_planted_topk(gen, k)
-        _, B = targets.cca_population_AB(gen)
+        _, Vs = otargets.cca_planted_topk(gen, k)
+        _, B = otargets.cca_population_AB(gen)
         ref = "population solution of the generator (planted correlations, closed form)"
+        scales = None
+        if fmt == "fp8":
+            px, py = gen.sample_torch(65536, 999_999, "cuda", torch.float32)
+            scales = (synth.fp8_column_scales(px.cpu().numpy()),
+                      synth.fp8_column_scales(py.cpu().numpy()))
+            aux = dict(x_col_scale=scales[0], y_col_scale=scales[1])
+            sx = torch.from_numpy(scales[0]).cuda()
+            sy = torch.from_numpy(scales[1]).cuda()
+
+        def conv(v, sc):
+            if fmt == "fp8":  # e4m3 codes of v / s, saturating, nearest even
+                return torch.clamp(v / sc, -448.0, 448.0).to(torch.float8_e4m3fn).view(torch.uint8)
+            return v.to(store)
 
         def fill(c, Xb, Yb):
-            x, y = gen.sample_torch(E * b, 1_000_000 + c, "cuda", dt)
-            Xb.copy_(x.view(E, b, -1))
-            Yb.copy_(y.view(E, b, -1))
+            x, y = gen.sample_torch(E * b, 1_000_000 + c, "cuda", torch.float32)
+            Xb.copy_(conv(x, sx if fmt == "fp8" else None).view(E, b, -1))
+            Yb.copy_(conv(y, sy if fmt == "fp8" else None).view(E, b, -1))
     else:
         gen, pool = synth.tiny_cca_pool(0)
         pb = oracle.Problem(oracle.KIND_CCA, k, w["dx"], w["dy"])
         A, B = oracle.problem_matrices(pb, pool.X, pool.Y)
         _, Vs = oracle.gep_topk(A, B, k)
         ref = "exact FP64 solution of the 10,000-pair pool (oracle)"
-        PX = torch.from_numpy(pool.X).to("cuda", dt)
-        PY = torch.from_numpy(pool.Y).to("cuda", dt)
+        PX = torch.from_numpy(pool.X).to("cuda", store)
+        PY = torch.from_numpy(pool.Y).to("cuda", store)
 
         def fill(c, Xb, Yb):
             idx = np.concatenate([pool.indices(c * E + j + 1, b) for j in range(E)])
             it = torch.from_numpy(idx).cuda()
             Xb.copy_(PX.index_select(0, it).view(E, b, -1))
             Yb.copy_(PY.index_select(0, it).view(E, b, -1))
-    Xb = torch.empty((E, b, w["dx"]), device="cuda", dtype=dt)
-    Yb = torch.empty((E, b, w["dy"]), device="cuda", dtype=dt)
+    Xb = torch.empty((E, b, w["dx"]), device="cuda", dtype=store)
+    Yb = torch.empty((E, b, w["dy"]), device="cuda", dtype=store)
     stream = torch.cuda.Stream()
-    solver = sg.Solver(config_for(sg, w), synth.initial_players(d, k, 0), stream=stream)
+    solver = sg.Solver(config_for(sg, w), synth.initial_players(d, k, 0), stream=stream, **aux)
     fill(0, Xb, Yb)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -322,7 +366,7 @@ def time_to_accuracy(w, target: float, max_steps: int, every: int, hyper=None, l
             solver.step(Xb[j], Yb[j])
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_gpu, steps, hist, hit = 0.0, 0, [], None
+    t_gpu, steps, hist, hits = 0.0, 0, [], {}
     c = 0
     while steps < max_steps:
         if c > 0:
@@ -339,17 +383,21 @@ def time_to_accuracy(w, target: float, max_steps: int, every: int, hyper=None, l
         err = oracle.subspace_error(solver.vectors(), Vs, B)
         hist.append((steps, t_gpu, err))
         if log:
-            log(f"tta {w['dtype']} steps {steps} gpu {t_gpu:.3f}s err {err:.3e}")
-        if hit is None and len(hist) >= 2 and hist[-2][2] <= target and err <= target:
-            hit = hist[-2]
+            log(f"tta {fmt} steps {steps} gpu {t_gpu:.3f}s err {err:.3e}")
+        for tg in targets:
+            if tg not in hits and len(hist) >= 2 and hist[-2][2] <= tg and err <= tg:
+                hits[tg] = hist[-2]
+        if targets[-1] in hits:
             break
     solver.close()
-    out = {"target": target, "reached": hit is not None, "eval_every_steps": E,
-           "reference": ref, "stream": ("fresh device-drawn pairs" if w["generator"] ==
-                                         "medium_cca" else "i.i.d. minibatches of the pool"),
-           "final_error": hist[-1][2], "steps_run": steps}
-    if hit is not None:
-        out.update({"seconds": round(hit[1], 4), "steps": hit[0], "samples": hit[0] * b})
+    out = {"targets": {}, "eval_every_steps": E, "reference": ref,
+           "stream": ("fresh device-drawn pairs" if w["generator"] == "medium_cca" else
+                      "i.i.d. minibatches of the pool") + f", stored as {fmt}",
+           "final_error": hist[-1][2], "steps_run": steps, "gpu_seconds_run": round(t_gpu, 4)}
+    for tg in targets:
+        h = hits.get(tg)
+        out["targets"][f"{tg:g}"] = ({"reached": True, "seconds": round(h[1], 4), "steps": h[0],
+                                      "samples": h[0] * b} if h else {"reached": False})
     return out
 
 
@@ -384,10 +432,15 @@ def run_batch(args, w):
     stream = torch.cuda.Stream()
     V0s = [synth.initial_players(d, k, 1000 + i) for i, d in enumerate(dims)]
     bat = sg.BatchSolver(dims, cfg, V0s, stream=stream)
-    tune_us = bat.tune(ring[0][2], ring[0][3], b, reps=3)
+    if args.batch_plan:
+        g_, *mb_ = [int(x) for x in args.batch_plan.split(",")]
+        bat.set_plan(g_, mb_)
+        plan_src = "set"
+    else:
+        tune_us = bat.tune(ring[0][2], ring[0][3], b, reps=3)
+        plan_src = f"autotuned ({tune_us:.1f} us per iteration)"
     groups, mb = bat.plan()
-    print(f"bench: tuned plan groups={groups} tile heights={mb} ({tune_us:.1f} us)",
-          file=sys.stderr, flush=True)
+    print(f"bench: plan groups={groups} tile heights={mb}, {plan_src}", file=sys.stderr, flush=True)
 
     def step(t):
         bat.step(ring[t % R][2], ring[t % R][3], b)
@@ -403,6 +456,8 @@ def run_batch(args, w):
             step(t)
     torch.cuda.synchronize()
     n_rep, rem = divmod(K, chunk)
+    if args.calibrate_copy_mb:
+        calibration_copy(args.calibrate_copy_mb)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(n_rep):
@@ -485,7 +540,8 @@ def run_batch(args, w):
         "data": f"synthetic: ring of {R} minibatches per instance drawn on the device",
         "config": {"workload": args.workload, "description": w["describe"], "instances": n,
                    "sum_d": int(D), "k": k, "minibatch": b, "optimizer": w["optimizer"],
-                   "plan": {"groups": groups, "tile_heights": mb, "launches": len(kinds)},
+                   "plan": {"groups": groups, "tile_heights": mb, "launches": len(kinds),
+                            "source": plan_src},
                    "graph_steps": chunk, "parallelism": "single GPU"},
         "roofline": roofline,
     }
@@ -536,6 +592,8 @@ def main():
                     sorted(BATCH_WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy run")
+    ap.add_argument("--batch-plan", default="",
+                    help="batched workloads: 'groups,mb0,mb1,mb2' instead of autotuning")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration)")
@@ -616,14 +674,7 @@ def main():
     n_rep, rem = divmod(K, chunk)
 
     if args.calibrate_copy_mb:
-        # a plain copy of known size: FETCH_SIZE / WRITE_SIZE of this kernel
-        # calibrate the per-dispatch counters of the step kernels
-        src = torch.ones(args.calibrate_copy_mb << 18, device="cuda", dtype=torch.float32)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        calibration_copy(args.calibrate_copy_mb)
 
     # ---- timed region: exactly K steps ----
     torch.cuda.synchronize()
@@ -708,16 +759,17 @@ def main():
     solver.close()
     if "tta" in w and not args.no_tta:
         tt = w["tta"]
-        print(f"bench: time to {tt['target']:g} subspace error", file=sys.stderr, flush=True)
-        out["time_to_accuracy"] = time_to_accuracy(w, tt["target"], tt["max_steps"], tt["every"])
+        print(f"bench: time to subspace error {tt['targets']}", file=sys.stderr, flush=True)
+        out["time_to_accuracy"] = time_to_accuracy(w, tt["targets"], tt["max_steps"], tt["every"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget, host)
         tta = out.get("time_to_accuracy")
-        if tta and tta.get("reached"):
+        if tta:
             # the oracle follows the same iteration: its time per step times
             # the GPU's step count (an extrapolation, not a run to target)
             sps = out["cpu_baseline"]["value"] / b
-            out["cpu_baseline"]["time_to_accuracy_extrapolated_s"] = round(tta["steps"] / sps, 3)
+            out["cpu_baseline"]["time_to_accuracy_extrapolated_s"] = {
+                tg: round(h["steps"] / sps, 3) for tg, h in tta["targets"].items() if h["reached"]}
     print(json.dumps(out), flush=True)
 
 

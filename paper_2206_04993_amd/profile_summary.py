@@ -8,7 +8,7 @@ produced by
     rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR -o write -- CMD
 
 with CMD given on the command line (default: python3 bench.py --workload W
---steps 256 --warmup 16 --no-cpu-baseline --calibrate-copy-mb 256), and writes
+--steps 256 --warmup 16 --no-cpu-baseline --no-tta --calibrate-copy-mb 256), and writes
 profiles/kernels_<W>.txt (kernel durations) and profiles/traffic_<W>.txt
 (HBM bytes per launch).  Counter values are KiB per dispatch; the plain
 256 MiB copy in the same run calibrates them (bytes per counter-KiB).
@@ -28,7 +28,8 @@ def _rows(path):
     return list(csv.DictReader(open(path)))
 
 
-_KERNELS = ("k_bfwd", "k_bbwd", "k_wfwd", "k_wmid", "k_wbwd", "k_winit", "k_fwd", "k_bwd")
+_KERNELS = ("k_bfwd", "k_bcoef", "k_bbwd", "k_wfwd", "k_wmid", "k_wbwd", "k_winit", "k_fwd",
+            "k_coef", "k_bwd")
 
 
 def _short(name: str) -> str:
@@ -48,7 +49,7 @@ def main(prof_dir: str, workload: str, cmd: str = "", copy_mib: int = 256):
 
     if not cmd:
         cmd = (f"python3 bench.py --workload {workload} --steps 256 --warmup 16 "
-               f"--no-cpu-baseline --calibrate-copy-mb {copy_mib}")
+               f"--no-cpu-baseline --no-tta --calibrate-copy-mb {copy_mib}")
     ks = _rows(os.path.join(prof_dir, "ks_kernel_stats.csv"))
     out = [f"# rocprofv3 kernel statistics, workload {workload} (MI355X)",
            f"# command: rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o ks -- {cmd}",
@@ -88,7 +89,8 @@ def main(prof_dir: str, workload: str, cmd: str = "", copy_mib: int = 256):
              f"# calibration: plain copy of {copy_mib} MiB reads {copy_kib('fetch'):.0f} KiB and writes "
              f"{copy_kib('write'):.0f} KiB by these counters",
              "kernel | dispatches | fetch_KiB(median) | write_KiB(median) | read_bytes | write_bytes"]
-    for k in ("k_fwd", "k_bwd", "k_wfwd", "k_wmid", "k_wbwd"):
+    for k in ("k_fwd", "k_coef", "k_bwd", "k_wfwd", "k_wmid", "k_wbwd", "k_bfwd", "k_bcoef",
+              "k_bbwd"):
         f = [v for _, v in vals.get((k, "fetch"), [])]
         w = [v for _, v in vals.get((k, "write"), [])]
         if not f:

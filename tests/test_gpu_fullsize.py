@@ -1,0 +1,76 @@
+"""Full-size parity of the large workloads, in the launch configuration the
+benchmark times (bench.py's workload definitions, encodings and solver
+configuration), against the FP64 oracle fed the exact values the GPU
+receives.  Two iterations; every output compared.
+
+* activation-like CCA, d = 8192 + 8192, k = 32, b = 4096: BF16, FP8-e4m3 with
+  per-column scales (BF16 / FP8 path), FP32 (narrow path, 64-feature tiles,
+  coefficients in k_coef)
+* LDA, d = 65536, 10 classes, k = 64, b = 2048, BF16
+
+Bars: the N-iteration bars of the small-size tests (BF16 / FP8: 1.2e-3;
+FP32 with Adam: 3e-4 x 5) on unit players and relative on [Bv]."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"bf16": 1.2e-3, "fp8": 1.2e-3, "f32": 1.5e-3}
+
+
+@pytest.mark.parametrize("wname", ["cca_d16384_k32_b4096_bf16", "cca_d16384_k32_b4096_fp8",
+                                   "cca_d16384_k32_b4096_fp32", "lda_d65536_k64_b2048_bf16"])
+def test_full_size_against_oracle(wname):
+    import torch
+
+    import bench
+    import paper_2206_04993_amd as sg
+    sg.load()
+    w = bench.WORKLOADS[wname]
+    lda = w["kind"] == "lda"
+    d, k, b = w["dx"] + w["dy"], w["k"], w["b"]
+    T = 2
+    print(f"full size {wname}: generating {T} minibatches", flush=True)
+    raw = bench.host_batches(w, T)
+    aux, scales, extra = {}, None, {}
+    if w["dtype"] == "fp8":
+        scales = (synth.fp8_column_scales(np.concatenate([r[0] for r in raw])),
+                  synth.fp8_column_scales(np.concatenate([r[1] for r in raw])))
+        aux = dict(x_col_scale=scales[0], y_col_scale=scales[1])
+    if lda:
+        gen = bench._generator(w)
+        priors = np.full(w["n_classes"], 1.0 / w["n_classes"])
+        aux = dict(class_means=gen.means, class_priors=priors)
+        extra = dict(class_means=gen.means, class_priors=priors)
+    V0 = synth.initial_players(d, k, 0)
+    solver = sg.Solver(bench.config_for(sg, w), V0, **aux)
+    pb = oracle.Problem(oracle.KIND_LDA if lda else oracle.KIND_CCA, k, w["dx"], w["dy"],
+                        rho=w["rho"], eps_reg=w.get("eps_reg", 0.0),
+                        optimizer=oracle.OPT_ADAM if w["optimizer"] == "adam" else oracle.OPT_SGD,
+                        **extra)
+    st = oracle.State.init(V0, adam=w["optimizer"] == "adam")
+    for t, (Xr, Yr) in enumerate(raw, start=1):
+        tx, vx = bench.encode(w, Xr, scales[0] if scales else None)
+        if lda:
+            ty = torch.from_numpy(np.ascontiguousarray(Yr, dtype=np.int32))
+            vy = None
+        else:
+            ty, vy = bench.encode(w, Yr, scales[1] if scales else None)
+        solver.step(tx.cuda(), ty.cuda())
+        eta = oracle.eta(oracle.SCHED_INV, t, w["eta0"], t0=w["t0"])
+        if lda:
+            oracle.gamma_step(pb, st, vx, None, eta, w["gamma"], labels=Yr.astype(np.int32))
+        else:
+            oracle.gamma_step(pb, st, vx, vy, eta, w["gamma"])
+    V, G, lam = solver.vectors(), solver.auxiliary(), solver.eigvals()
+    solver.close()
+    dv = float(np.abs(V - st.V).max())
+    dg = float(np.abs(G - st.G).max()) / max(1.0, float(np.abs(st.G).max()))
+    dl = float(np.abs(lam - st.eigvals()).max()) / max(1.0, float(np.abs(st.eigvals()).max()))
+    print(f"  {wname}: max|dV| = {dv:.2e}  rel|dG| = {dg:.2e}  rel|dlam| = {dl:.2e}", flush=True)
+    tol = TOL[w["dtype"]]
+    assert dv < tol and dg < tol and dl < tol, (dv, dg, dl)
+    assert np.allclose(np.linalg.norm(V, axis=0), 1.0, atol=1e-5)
