@@ -9,7 +9,14 @@ receives.  Two iterations; every output compared.
 * LDA, d = 65536, 10 classes, k = 64, b = 2048, BF16
 
 Bars: the N-iteration bars of the small-size tests (BF16 / FP8: 1.2e-3;
-FP32 with Adam: 3e-4 x 5) on unit players and relative on [Bv]."""
+FP32: 3e-4) on unit players and relative on [Bv] and the eigenvalue
+estimates.  With Adam an element's step is about eta_t sign(g) while its
+second moment is g^2 (the first iterations), so an element whose gradient g
+is at the rounding level may step either way: such elements can differ by up
+to 2 sum_t eta_t, and only they may exceed the plain bar -- checked as a
+bound on every element plus at most 1e-4 of the elements above the plain bar
+and a relative Frobenius difference below it.  The same workloads with plain
+ascent (SGD) meet the plain bar on every element."""
 import numpy as np
 import pytest
 
@@ -18,18 +25,21 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"bf16": 1.2e-3, "fp8": 1.2e-3, "f32": 1.5e-3}
+TOL = {"bf16": 1.2e-3, "fp8": 1.2e-3, "f32": 3e-4}
+
+WORKLOADS = ["cca_d16384_k32_b4096_bf16", "cca_d16384_k32_b4096_fp8",
+             "cca_d16384_k32_b4096_fp32", "lda_d65536_k64_b2048_bf16"]
 
 
-@pytest.mark.parametrize("wname", ["cca_d16384_k32_b4096_bf16", "cca_d16384_k32_b4096_fp8",
-                                   "cca_d16384_k32_b4096_fp32", "lda_d65536_k64_b2048_bf16"])
-def test_full_size_against_oracle(wname):
+@pytest.mark.parametrize("opt", ["adam", "sgd"])
+@pytest.mark.parametrize("wname", WORKLOADS)
+def test_full_size_against_oracle(wname, opt):
     import torch
 
     import bench
     import paper_2206_04993_amd as sg
     sg.load()
-    w = bench.WORKLOADS[wname]
+    w = dict(bench.WORKLOADS[wname], optimizer=opt)
     lda = w["kind"] == "lda"
     d, k, b = w["dx"] + w["dy"], w["k"], w["b"]
     T = 2
@@ -67,10 +77,21 @@ def test_full_size_against_oracle(wname):
             oracle.gamma_step(pb, st, vx, vy, eta, w["gamma"])
     V, G, lam = solver.vectors(), solver.auxiliary(), solver.eigvals()
     solver.close()
-    dv = float(np.abs(V - st.V).max())
+    dV = np.abs(V - st.V)
+    dv = float(dV.max())
     dg = float(np.abs(G - st.G).max()) / max(1.0, float(np.abs(st.G).max()))
     dl = float(np.abs(lam - st.eigvals()).max()) / max(1.0, float(np.abs(st.eigvals()).max()))
-    print(f"  {wname}: max|dV| = {dv:.2e}  rel|dG| = {dg:.2e}  rel|dlam| = {dl:.2e}", flush=True)
     tol = TOL[w["dtype"]]
-    assert dv < tol and dg < tol and dl < tol, (dv, dg, dl)
+    over = int((dV > tol).sum())
+    fro = float(np.linalg.norm(V - st.V) / np.linalg.norm(st.V))
+    print(f"  {wname} {opt}: max|dV| = {dv:.2e} ({over} of {dV.size} above {tol:g}), "
+          f"rel F |dV| = {fro:.2e}, rel|dG| = {dg:.2e}, rel|dlam| = {dl:.2e}", flush=True)
+    assert dg < tol and dl < tol, (dg, dl)
+    if opt == "sgd":
+        assert dv < tol, dv
+    else:
+        flip = 2.0 * sum(oracle.eta(oracle.SCHED_INV, t, w["eta0"], t0=w["t0"])
+                         for t in range(1, T + 1))
+        assert dv < flip + tol, (dv, flip)
+        assert over <= 1e-4 * dV.size and fro < tol, (over, fro)
     assert np.allclose(np.linalg.norm(V, axis=0), 1.0, atol=1e-5)
