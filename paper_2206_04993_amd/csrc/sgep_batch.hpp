@@ -20,7 +20,9 @@
 //
 // The arithmetic is exactly that of a single handle: an instance advanced by
 // the batch holds the same bits as the same instance advanced alone with the
-// same feature-tile height.
+// same feature-tile height.  The batch kernels keep fewer loads in flight per
+// wave (LOWREG) so that more workgroups share a CU; that changes when values
+// arrive, not the order in which they are summed.
 #pragma once
 
 #include "sgep_kernels.hpp"
@@ -75,7 +77,7 @@ __global__ void __launch_bounds__(kNT) k_bfwd(Launch L, const StepArgs *__restri
     if (inst == kNoTile)
         return;
     const StepArgs a = instance_args(L, args, Xs, Ys, inst);
-    fwd_body<T, KP, KIND>(a, s - q * (nf + 1));
+    fwd_body<T, KP, KIND, true>(a, s - q * (nf + 1));
 }
 
 // Coefficient launch: 8 * per_xcd workgroups over the forward map (one
@@ -105,7 +107,7 @@ __global__ void __launch_bounds__(kNT) k_bbwd(Launch L, const StepArgs *__restri
     if (e == kNoTile)
         return;
     const StepArgs a = instance_args(L, args, Xs, Ys, e >> 16);
-    bwd_body<T, KP, MB, KIND, OPT, kModePre>(a, (int)(e & 0xffffu));
+    bwd_body<T, KP, MB, KIND, OPT, kModePre, true>(a, (int)(e & 0xffffu));
 }
 
 } // namespace batch

@@ -319,7 +319,9 @@ __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t
 // assignment) as two calls of fwd_view.  SAMEV (GENERAL: one V for both
 // products) loads the V operand once; a compile-time choice, because a
 // run-time one makes the compiler drain all loads in flight around it.
-template <typename T, int KP, bool SAMEV>
+// LOWREG halves the chunks per batch (fewer registers, more workgroups per
+// CU, for launches with many workgroups); the accumulation order is the same.
+template <typename T, int KP, bool SAMEV, bool LOWREG>
 __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_t ldx,
                                           const SGEP_G T *__restrict__ Y, int64_t ldy, int64_t nf,
                                           int64_t row, bool rv, bool vec_ok,
@@ -331,7 +333,7 @@ __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_
     constexpr int VEC = 16 / (int)sizeof(T);
     constexpr int CH = 4 * VEC;
     constexpr int NB = KP / 16;
-    constexpr int U = 8 / NB;
+    constexpr int U = (LOWREG ? 4 : 8) / NB;
     const int kk = lane >> 4, n = lane & 15;
     const int64_t nch = (nf + CH - 1) / CH;
     const int64_t nfull = nf / CH;
@@ -403,7 +405,7 @@ __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_
 // Forward body: workgroup blk takes rows 16 blk .. 16 blk + 15; the four waves
 // split the features.  Workgroup blk == n_fwd reduces the norm / parent
 // partials of the current state and advances the step counter.
-template <typename T, int KP, int KIND>
+template <typename T, int KP, int KIND, bool LOWREG = false>
 __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
 {
     typedef typename Mfma<T>::acc Acc;
@@ -444,8 +446,8 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     const SGEP_G T *VQy = KIND == kKindCCA ? VQ + a.dxp * KP : VQ;
     const int64_t nfy = KIND == kKindCCA ? a.dy : a.dx;
     if (nfy == a.dx) {
-        fwd_view2<T, KP, KIND != kKindCCA>(X, a.ldx, Y, a.ldy, a.dx, row, rv, vec_ok, VQ, VQy,
-                                           lane, w, aP, aQ);
+        fwd_view2<T, KP, KIND != kKindCCA, LOWREG>(X, a.ldx, Y, a.ldy, a.dx, row, rv, vec_ok, VQ,
+                                                   VQy, lane, w, aP, aQ);
     } else {
         fwd_view<T, KP>(X, a.ldx, a.dx, row, rv, vec_ok, VQ, lane, w, aP);
         fwd_view<T, KP>(Y, a.ldy, nfy, row, rv, vec_ok, VQy, lane, w, aQ);
@@ -688,7 +690,7 @@ __global__ void __launch_bounds__(kNT) k_coef(StepArgs a)
 // partials and compute the coefficients while waves 0..3 run the main loop.
 // MODE kModePre: four waves; the coefficient block comes from k_coef.
 // ---------------------------------------------------------------------------
-template <typename T, int KP, int MB, int KIND, int OPT, int MODE>
+template <typename T, int KP, int MB, int KIND, int OPT, int MODE, bool LOWREG = false>
 __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
 {
     typedef typename Mfma<T>::acc Acc;
@@ -697,11 +699,12 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
     constexpr int TRI = KP * (KP + 1) / 2;
     constexpr int W = TRI + KP; // width of both partial kinds
     constexpr int XPG = (KIND == kKindCCA ? 4 : 8) * MB; // X registers per group
-    // loads in flight per batch: ~128 VGPRs, or ~192 for the smallest player
+    // loads in flight per batch: ~128 VGPRs; ~192 for the smallest player
     // tile with eight waves (kModeSpec; one workgroup per CU, fewer round
-    // trips, still within 256 VGPRs)
+    // trips, still within 256 VGPRs); ~64 with LOWREG (more workgroups per
+    // CU).  The order of the row groups, hence the sums, is the same.
     constexpr bool BIG = MODE == 1 && KP * (int)sizeof(T) <= 64;
-    constexpr int UB0 = (BIG ? 768 : 512) / ((XPG + 8 * NB) * (int)sizeof(T));
+    constexpr int UB0 = (LOWREG ? 256 : (BIG ? 768 : 512)) / ((XPG + 8 * NB) * (int)sizeof(T));
     constexpr int UB = UB0 < 1 ? 1 : (UB0 > 16 ? 16 : UB0);
     constexpr int EPT = FT * KP / kNT; // epilogue elements per thread
     static_assert(EPT * kNT == FT * KP, "tile must be a multiple of the workgroup");

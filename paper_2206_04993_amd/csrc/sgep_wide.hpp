@@ -531,7 +531,9 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
     constexpr int NC = LDA ? kMaxCls : 1;
     __shared__ __attribute__((aligned(16))) float red[4 * SLOT];
     __shared__ float Tt[KP * KP];   // Tt[j * KP + i] = T_ij (j < i), else 0
+    __shared__ double Td[KP * KP];  // the same T_ij in FP64, row i: Td[i * KP + j]
     __shared__ double gd[S::GT];
+    __shared__ double sprior[NC];   // LDA class priors
     __shared__ float cInv[KP], cMB[KP], cMAc[KP], cUc[KP];
     __shared__ double dInv[KP], dS[KP];
     __shared__ float cSp[NC * KP], cU[NC * KP];
@@ -551,6 +553,13 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
     const int nch = (int)((a.b + 31) / 32);
     const double t = a.coef->t; // this iteration's number, set by k_wmid
     const double ib = 1.0 / (double)a.b;
+    // terms that depend only on t, once per workgroup
+    const float eta = (float)eta_sched(a, t), gam = (float)a.gamma, ibf = (float)ib;
+    const float eps = (float)a.eps_reg;
+    const float b1 = (float)a.adam_b1, b2 = (float)a.adam_b2, aeps = (float)a.adam_eps;
+    const float c1 = (float)(1.0 - pow(a.adam_b1, t)), c2 = (float)(1.0 - pow(a.adam_b2, t));
+    if (LDA && tid < NC)
+        sprior[tid] = tid < a.ncls ? a.prior[tid] : 0.0; // read after the loop's barriers
     const uint16_t *Wh = a.Wh + (int64_t)l16 * a.ldr + 8 * g;
     const uint16_t *Wl = a.Wl + (int64_t)l16 * a.ldr + 8 * g;
 
@@ -692,6 +701,14 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
             }
         }
 
+        // the old auxiliary tile of this subtile, into registers now (written
+        // to LDS once the products and Gram terms no longer need the space)
+        const int64_t frow = a.off[v] + fv0; // state row of the subtile's first feature
+        constexpr int GPT = kFT * KP / kBT;
+        float gpre[GPT];
+#pragma unroll
+        for (int q = 0; q < GPT; ++q)
+            gpre[q] = a.G[frow * KP + tid + q * kBT];
         // ---- products: four waves -> prod = slot 0, element (feature, m) ----
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -779,13 +796,13 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                     double mbar = 0.0, usum = 0.0;
                     if (i < a.k)
                         for (int c = 0; c < a.ncls; ++c)
-                            mbar += a.prior[c] * ss[TRI + KP + c * KP + i] * dInv[i];
+                            mbar += sprior[c] * ss[TRI + KP + c * KP + i] * dInv[i];
                     for (int c = 0; c < kMaxCls; ++c) {
                         double mc = 0.0;
                         if (c < a.ncls && i < a.k)
                             mc = ss[TRI + KP + c * KP + i] * dInv[i] - mbar;
                         dMc[c * KP + i] = mc;
-                        const float u = (float)((c < a.ncls ? a.prior[c] : 0.0) * mc);
+                        const float u = (float)((c < a.ncls ? sprior[c] : 0.0) * mc);
                         cU[c * KP + i] = u;
                         usum += (double)u;
                     }
@@ -799,7 +816,7 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                     return (gd[i * KP + j] + gd[j * KP + i]) * dInv[i] * dInv[j] * ib;
                 double s = 0.0;
                 for (int c = 0; c < a.ncls; ++c)
-                    s += a.prior[c] * dMc[c * KP + i] * dMc[c * KP + j];
+                    s += sprior[c] * dMc[c * KP + i] * dMc[c * KP + j];
                 return s;
             };
             for (int e = tid; e < KP * KP; e += kBT) {
@@ -808,7 +825,9 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                 if (i < a.k && j < i)
                     val = MA(i, j) / dS[j];
                 Tt[e] = (float)val;
+                Td[i * KP + j] = val;
             }
+            __syncthreads();
             Coef *cw = a.coef;
             if (tid < KP) {
                 const int i = tid;
@@ -821,7 +840,7 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                     else
                         mB = gd[16 * KP + i] * ii2 * ib + a.eps_reg;
                     for (int j = 0; j < i; ++j)
-                        c += MA(i, j) / dS[j] * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
+                        c += Td[i * KP + j] * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
                 }
                 cMB[i] = (float)mB;
                 cMAc[i] = (float)(mA - c);
@@ -851,10 +870,12 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
         }
 
         // ---- fused epilogue on 16 x 16 tiles (feature block fb, player block pb) ----
-        const int64_t frow = a.off[v] + fv0; // state row of the subtile's first feature
         float *Gold = ext, *Vn = ext + kFT * GLD, *Gn = Vn + kFT * VLD;
-        for (int e = tid; e < kFT * KP; e += kBT)
-            Gold[(e / KP) * GLD + e % KP] = a.G[frow * KP + e];
+#pragma unroll
+        for (int q = 0; q < GPT; ++q) {
+            const int e = tid + q * kBT;
+            Gold[(e / KP) * GLD + e % KP] = gpre[q];
+        }
         if (LDA) {
             for (int e = tid; e < kMaxCls * kFT; e += kBT) {
                 const int c = e / kFT, fl = e % kFT;
@@ -864,10 +885,6 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                 Mb[e] = a.Mbar[frow + e];
         }
         __syncthreads();
-        const float eta = (float)eta_sched(a, t), gam = (float)a.gamma, ibf = (float)ib;
-        const float eps = (float)a.eps_reg;
-        const float b1 = (float)a.adam_b1, b2 = (float)a.adam_b2, aeps = (float)a.adam_eps;
-        const float c1 = (float)(1.0 - pow(a.adam_b1, t)), c2 = (float)(1.0 - pow(a.adam_b2, t));
         for (int tt = w; tt < 4 * NT; tt += kBW) {
             const int fb = tt / NT, pb = tt % NT;
             // parent penalty sum_j G_old[fl][j] T_ij, and (LDA) the class terms
@@ -886,6 +903,17 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                 }
             }
             const int i = 16 * pb + l16;
+            // the state of this tile's four rows, loaded together
+            float vold[4], mold[4], sold[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t si = (frow + 16 * fb + 4 * g + r) * KP + i;
+                vold[r] = a.V[si];
+                if (OPT != kOptSGD) {
+                    mold[r] = a.Am[si];
+                    sold[r] = a.As[si];
+                }
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int fl = 16 * fb + 4 * g + r; // FP32 D row 4 (l/16) + r
@@ -893,7 +921,7 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                 float vn = 0.f, gn = 0.f;
                 if (fv0 + fl < dv && i < a.k) {
                     const float inv = cInv[i];
-                    const float vh = a.V[si] * inv;
+                    const float vh = vold[r] * inv;
                     const float *pr = red + fl * MWP;
                     float av, bv;
                     if (!LDA) {
@@ -910,8 +938,8 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                     if (OPT == kOptSGD) {
                         vn = vh + eta * grad;
                     } else {
-                        const float mm = b1 * a.Am[si] + (1.f - b1) * grad;
-                        const float sq = b2 * a.As[si] + (1.f - b2) * grad * grad;
+                        const float mm = b1 * mold[r] + (1.f - b1) * grad;
+                        const float sq = b2 * sold[r] + (1.f - b2) * grad * grad;
                         a.Am[si] = mm;
                         a.As[si] = sq;
                         vn = vh + eta * (mm / c1) / (sqrtf(sq / c2) + aeps);
