@@ -299,8 +299,15 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
     const dim3 blk(kWT);
     const bool adam = h->cfg.optimizer == SGEP_ADAM;
     // forward workgroups, then the statistics reductions
-    launch_k(k_wfwd<KP, IN>, dim3(a.n_rb * a.nview * a.n_split + wide_stat_blocks(a)), blk,
-             h->stream, ev[0], ev[1], a);
+    const dim3 gf(a.n_rb * a.nview * a.n_split + wide_stat_blocks(a));
+    if constexpr (KP <= 32) {
+        if (a.rbf == 128)
+            launch_k(k_wfwd<KP, IN, 128>, gf, blk, h->stream, ev[0], ev[1], a);
+        else
+            launch_k(k_wfwd<KP, IN, 64>, gf, blk, h->stream, ev[0], ev[1], a);
+    } else {
+        launch_k(k_wfwd<KP, IN, 64>, gf, blk, h->stream, ev[0], ev[1], a);
+    }
     launch_k(k_wmid<KP, KIND>, dim3(a.nA), blk, h->stream, ev[2], ev[3], a);
     const dim3 bblk(kBT);
     if (adam)
@@ -433,12 +440,18 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.dtot = lda ? r64(c.dx) : r64(c.dx) + r64(c.dy);
     a.k = c.k;
     a.ncls = lda ? c.n_classes : 0;
-    a.ldr = r64(c.b_max);
-    // forward: aim at >= 512 workgroups at b_max, each wave >= one 64-feature step
-    const int64_t nrb = a.ldr / kRB;
+    a.ldr = (c.b_max + kRowPad - 1) / kRowPad * kRowPad;
+    // forward: aim at >= 512 workgroups of 64 rows at b_max (the same number of
+    // rows in flight with 128-row blocks), each wave >= one 64-feature step;
+    // 128-row blocks when they still give >= 256 workgroups
     const int64_t dvmax = a.dv[0] > a.dv[1] ? a.dv[0] : a.dv[1];
     const int64_t nf64 = (dvmax + 63) / 64;
-    int64_t ns = (512 + nrb * a.nview - 1) / (nrb * a.nview);
+    const int64_t ns_cap = (nf64 + kNW - 1) / kNW;
+    a.rbf = (KP <= 32 && (a.ldr / 128) * a.nview * ns_cap >= 256) ? 128 : 64;
+    const int64_t rbf = a.rbf;
+    const int64_t nrb = a.ldr / rbf;
+    const int64_t target = 512 * kRB / rbf;
+    int64_t ns = (target + nrb * a.nview - 1) / (nrb * a.nview);
     const int64_t ns_max = (nf64 + kNW - 1) / kNW;
     if (ns > ns_max)
         ns = ns_max;
@@ -606,8 +619,8 @@ sgep_status step_wide(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
     a.ldx = ldx;
     a.ldy = lda ? 0 : ldy;
     a.b = b;
-    a.n_rb = (int32_t)((b + sgep::wide::kRB - 1) / sgep::wide::kRB);
-    a.nA = 4 * a.n_rb;
+    a.n_rb = (int32_t)((b + a.rbf - 1) / a.rbf);
+    a.nA = 4 * (int32_t)((b + sgep::wide::kRB - 1) / sgep::wide::kRB);
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (events)
         for (int i = 0; i < 6; ++i)

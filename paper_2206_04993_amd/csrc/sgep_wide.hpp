@@ -46,7 +46,12 @@ namespace wide {
 constexpr int kWT = 512;       // threads per workgroup: eight wave64
 constexpr int kNW = kWT / 64;  // waves per workgroup
 constexpr int kFT = 64;        // features per backward subtile
-constexpr int kRB = 64;        // minibatch rows per forward workgroup
+constexpr int kRB = 64;        // row granularity of the forward partials and the middle pass
+constexpr int kRowPad = 128;   // padding of the row dimension (a multiple of every block)
+// minibatch rows per forward workgroup: 64, or 128 (eight 16-row tiles per
+// wave, so each V operand load serves twice the rows) where the accumulators
+// and the reduction buffer fit (KP <= 32) and the minibatch is large enough to
+// keep >= 256 workgroups busy (chosen at init)
 constexpr int kMaxCls = 16;    // LDA classes
 constexpr int kInBF16 = 0;
 constexpr int kInFP8 = 1;
@@ -70,9 +75,10 @@ struct WideArgs {
     int32_t nview, k, ncls;
     // forward decomposition: block = (split, view, 64-row block), row blocks fastest
     int32_t n_rb, n_split;
-    int32_t nA;                 // k_wmid workgroups: 16 rows each, 4 n_rb
+    int32_t rbf;                // rows per forward workgroup: 64 or 128
+    int32_t nA;                 // k_wmid workgroups: 16 rows each, 4 per 64-row block
     int64_t fs, fw;             // features per split and per wave (multiples of 64)
-    int64_t ldr;                // padded rows (multiple of kRB) of the partials and of W
+    int64_t ldr;                // padded rows (multiple of kRowPad) of the partials and of W
     // backward decomposition: workgroups [0, nwg0) cover view 0, the rest view 1;
     // each covers nsub consecutive subtiles of its view (nsubv[v] subtiles in all)
     int32_t nwg0, nwg, nsub;
@@ -182,11 +188,13 @@ __global__ void __launch_bounds__(kWT) k_wstats(WideArgs a) { reduce_stats(a, bl
 // operand the same features of player l % 16 of a 16-player tile: one 16-byte
 // (BF16) or 8-byte (FP8) load per row tile, one per player tile and half.
 // ---------------------------------------------------------------------------
-template <int KP, int IN>
+template <int KP, int IN, int RBF>
 __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
 {
     constexpr int NT = KP / 16;
-    __shared__ float red[4][kRB * KP];
+    static_assert(RBF == 64 || (RBF == 128 && KP <= 32), "forward row block");
+    constexpr int TR = RBF / 16;       // 16-row MFMA tiles
+    __shared__ float red[4][RBF * KP];
     const int nfwd = a.n_rb * a.nview * a.n_split;
     if ((int)blockIdx.x >= nfwd) {
         reduce_stats(a, (int)blockIdx.x - nfwd);
@@ -204,7 +212,7 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
     const int64_t ld = v ? a.ldy : a.ldx;
     const uint8_t *Xb = (const uint8_t *)(v ? a.Y : a.X);
     constexpr int ES = IN == kInBF16 ? 2 : 1;
-    const int64_t row0 = (int64_t)rb * kRB;
+    const int64_t row0 = (int64_t)rb * RBF;
     const int64_t fbeg = (int64_t)s * a.fs + (int64_t)w * a.fw;
     const int64_t fend = (fbeg + a.fw < dv) ? fbeg + a.fw : dv;
     const int nst = fend > fbeg ? (int)((fend - fbeg + 31) / 32) : 0;
@@ -214,28 +222,28 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
     // minibatch reads the last row, a feature unit past the view the last
     // unit); the data are zeroed where they are consumed.  Branch-free loads
     // let the next chunk stay in flight while the current one is multiplied.
-    const uint8_t *xr[4];
-    bool rok[4];
+    const uint8_t *xr[TR];
+    bool rok[TR];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < TR; ++t) {
         const int64_t row = row0 + 16 * t + r16;
         rok[t] = row < a.b;
         xr[t] = Xb + (rok[t] ? row : a.b - 1) * ld * ES;
     }
 
-    f32x4 acc[4][NT];
+    f32x4 acc[TR][NT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < TR; ++t)
 #pragma unroll
         for (int u = 0; u < NT; ++u)
             acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // one 32-feature chunk: raw X (BF16: 4 dwords; FP8: 2 dwords) and V hi/lo
-    auto load = [&](int st, u32x4(&xa)[4], u32x4(&vh)[NT], u32x4(&vl)[NT]) {
+    auto load = [&](int st, u32x4(&xa)[TR], u32x4(&vh)[NT], u32x4(&vl)[NT]) {
         const int64_t f0 = fbeg + 32 * (int64_t)(st < nst ? st : nst - 1);
         const int64_t fx = f0 + 8 * g < dv ? f0 + 8 * g : dv - 8;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < TR; ++t) {
             if (IN == kInBF16) {
                 xa[t] = *reinterpret_cast<const u32x4 *>(xr[t] + 2 * fx);
             } else {
@@ -250,12 +258,12 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
             vl[u] = *reinterpret_cast<const u32x4 *>(Vl + vo);
         }
     };
-    auto mma = [&](int st, const u32x4(&xa)[4], const u32x4(&vh)[NT], const u32x4(&vl)[NT]) {
+    auto mma = [&](int st, const u32x4(&xa)[TR], const u32x4(&vh)[NT], const u32x4(&vl)[NT]) {
         if (st >= nst)
             return; // wave-uniform
         const bool fok = fbeg + 32 * (int64_t)st + 8 * g < dv;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < TR; ++t) {
             u32x4 x = xa[t];
             if (IN == kInFP8) {
                 uint32_t e0, e1, e2, e3;
@@ -272,7 +280,7 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
             }
         }
     };
-    u32x4 xa0[4], vh0[NT], vl0[NT], xa1[4], vh1[NT], vl1[NT];
+    u32x4 xa0[TR], vh0[NT], vl0[NT], xa1[TR], vh1[NT], vl1[NT];
     if (nst > 0) {
         load(0, xa0, vh0, vl0);
         for (int st = 0; st < nst; st += 2) {
@@ -285,11 +293,11 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
         }
     }
 
-    // eight waves -> one 64 x KP partial: waves 4..7 park, 0..3 add, four-slot sum
-    // D layout: lane l, register q holds row 4 (l/16) + q, column l % 16
+    // eight waves -> one RBF x KP partial: waves 4..7 park, 0..3 add, four-slot
+    // sum.  D layout: lane l, register q holds row 4 (l/16) + q, column l % 16
     if (w >= 4) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < TR; ++t)
 #pragma unroll
             for (int u = 0; u < NT; ++u)
 #pragma unroll
@@ -299,7 +307,7 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
     __syncthreads();
     if (w < 4) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < TR; ++t)
 #pragma unroll
             for (int u = 0; u < NT; ++u)
 #pragma unroll
@@ -310,7 +318,7 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
     }
     __syncthreads();
     float *out = a.Ppart + (((int64_t)s * a.nview + v) * a.ldr + row0) * KP;
-    for (int e = tid; e < kRB * KP; e += kWT)
+    for (int e = tid; e < RBF * KP; e += kWT)
         out[e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
