@@ -103,11 +103,9 @@ BATCH_WORKLOADS = {
 }
 DEFAULT = "cca_d1024_k16_b1024_fp32"
 
-# kernels of one iteration, in launch order, and the header holding their code
-KERNELS = {"narrow2": ("k_fwd", "k_bwd"), "narrow3": ("k_fwd", "k_coef", "k_bwd"),
-           "wide": ("k_wfwd", "k_wmid", "k_wbwd")}
+# the header holding each kernel's code
 KERNEL_HEADER = {"k_fwd": "sgep_kernels.hpp", "k_bwd": "sgep_kernels.hpp",
-                 "k_coef": "sgep_kernels.hpp",
+                 "k_coef": "sgep_kernels.hpp", "k_bwdp": "sgep_kernels.hpp",
                  "k_wfwd": "sgep_wide.hpp", "k_wmid": "sgep_wide.hpp", "k_wbwd": "sgep_wide.hpp",
                  "k_bfwd": ("sgep_kernels.hpp", "sgep_batch.hpp"),
                  "k_bcoef": ("sgep_kernels.hpp", "sgep_batch.hpp"),
@@ -213,9 +211,11 @@ def config_for(sg, w):
         eps_reg=w.get("eps_reg", 0.0), n_classes=w.get("n_classes", 0))
 
 
-def algorithmic_work(w, kernel):
+def algorithmic_work(w, kernel, names=()):
     """(FLOPs, HBM bytes) one launch of `kernel` must do at minimum: one read
-    of the minibatch, its products once, the O(d k) state it touches."""
+    of the minibatch, its products once, the O(d k) state it touches.  names:
+    the kernels of the iteration (with k_bwdp, k_bwd is the finishing pass:
+    the update alone)."""
     b, k = w["b"], w["k"]
     d = w["dx"] + w["dy"]
     e = {"f64": 8, "f32": 4, "bf16": 2, "fp8": 1}[w["dtype"]]
@@ -230,6 +230,10 @@ def algorithmic_work(w, kernel):
     if kernel == "k_coef":  # the Gram partials of the forward row tiles, once
         kp = 16 if k <= 16 else (32 if k <= 32 else 64)
         return 0.0, float(8 * (kp * (kp + 1) // 2 + kp) * ((b + 15) // 16))
+    if kernel == "k_bwdp":
+        return 4.0 * b * d * k, float(data + se * 2 * b * k)
+    if kernel == "k_bwd" and "k_bwdp" in names:
+        return 0.0, float(state)
     if kernel == "k_bwd":
         return 4.0 * b * d * k, float(data + se * 2 * b * k + state)
     mw = k + c if lda else 2 * k                                # rows of the backward operand W
@@ -653,8 +657,7 @@ def main():
     stream = torch.cuda.Stream()
     solver = sg.Solver(config_for(sg, w), synth.initial_players(d, k, 0), stream=stream, **aux)
     nk = solver.kernels_per_step()
-    wide = w["dtype"] in ("bf16", "fp8")
-    family = "wide" if wide else ("narrow3" if nk == 3 else "narrow2")
+    names = solver.kernel_names()
 
     def step(t):
         s = t % R
@@ -691,8 +694,6 @@ def main():
 
     # ---- per-kernel durations: the same steps again, each kernel launched
     # with a start/stop HIP event pair stamped by its own dispatch ----
-    names = KERNELS[family]
-    assert len(names) == nk
     hip = hip_runtime()
     Kp = min(K, 512)
     evs = [ctypes.c_void_p() for _ in range(2 * nk * Kp)]
@@ -720,8 +721,8 @@ def main():
     solver.sync()
     avg = {n: float(np.mean(v)) for n, v in dur.items()}
     dom = max(avg, key=avg.get)
-    flops, nbytes = algorithmic_work(w, dom)
-    if w["dtype"] in ("bf16", "fp8"):
+    flops, nbytes = algorithmic_work(w, dom, names)
+    if w["dtype"] in ("bf16", "fp8") or flops == 0.0:
         achieved = nbytes / (avg[dom] * 1e-6) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 5)}

@@ -170,13 +170,22 @@ sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
 sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int32_t *labels,
                           int64_t b);
 
-/* Number of kernels one iteration launches: for F64 / F32, 2 (forward
- * products; backward products, k x k coefficients and update) when the
- * backward tile is one 16-feature block and k * element size <= 128 bytes
- * after padding, else 3 (forward products; k x k coefficients; backward
- * products and update); for BF16 / FP8, 3 (forward products; operand
- * preparation and reductions; backward products and update). */
+/* Number of kernels one iteration launches.  F64 / F32: 3 for a CCA handle
+ * with b_max >= 512 and at most 128 backward tiles (forward products; two
+ * row slices of the backward products per tile plus the k x k coefficients;
+ * sum of the slices and update); else 2 (forward products; backward products,
+ * k x k coefficients and update) when the backward tile is one 16-feature
+ * block and k * element size <= 128 bytes after padding; else 3 (forward
+ * products; k x k coefficients; backward products and update).  BF16 / FP8:
+ * 3 (forward products; operand preparation and reductions; backward products
+ * and update). */
 sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n);
+
+/* Short name of kernel i (0 <= i < sgep_kernels_per_step) of one iteration,
+ * in launch order: "k_fwd", "k_coef", "k_bwdp", "k_bwd", "k_wfwd", "k_wmid"
+ * or "k_wbwd" -- a static string, not to be freed; NULL for a NULL handle or
+ * an index out of range. */
+const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i);
 
 /* One iteration (sgep_step, or sgep_step_lda when labels is non-NULL) with
  * per-kernel timing: events[2 i] and events[2 i + 1] receive the start and end

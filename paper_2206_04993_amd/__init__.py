@@ -38,6 +38,7 @@ SGEP_SCHED_CONST, SGEP_SCHED_INV, SGEP_SCHED_WARMUP_HARMONIC = 0, 1, 2
 # every symbol include/sgep.h declares
 EXPORTS = (
     "sgep_init", "sgep_init_ex", "sgep_step", "sgep_step_lda", "sgep_kernels_per_step",
+    "sgep_step_kernel_name",
     "sgep_step_profiled", "sgep_sync", "sgep_eigvals", "sgep_vectors", "sgep_auxiliary",
     "sgep_step_count", "sgep_state_size", "sgep_get_state", "sgep_set_state", "sgep_destroy",
     "sgep_status_string", "sgep_version",
@@ -112,6 +113,8 @@ def load() -> ctypes.CDLL:
     lib.sgep_step.argtypes = [vp, vp, i64, vp, i64, i64]
     lib.sgep_step_lda.argtypes = [vp, vp, i64, vp, i64]
     lib.sgep_kernels_per_step.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.sgep_step_kernel_name.argtypes = [vp, i32]
+    lib.sgep_step_kernel_name.restype = ctypes.c_char_p
     lib.sgep_step_profiled.argtypes = [vp, vp, i64, vp, i64, vp, i64, ctypes.POINTER(vp), i32]
     lib.sgep_sync.argtypes = [vp]
     lib.sgep_eigvals.argtypes = [vp, dp]
@@ -139,7 +142,7 @@ def load() -> ctypes.CDLL:
     lib.sgep_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
         fn = getattr(lib, name)
-        if name not in ("sgep_status_string",):
+        if name not in ("sgep_status_string", "sgep_step_kernel_name"):
             fn.restype = i32
     _lib = lib
     return lib
@@ -234,6 +237,14 @@ def sgep_kernels_per_step(h) -> int:
     n = ctypes.c_int32()
     _check(load().sgep_kernels_per_step(h, ctypes.byref(n)), "sgep_kernels_per_step")
     return int(n.value)
+
+
+def sgep_step_kernel_name(h, i: int) -> str:
+    """Short name of kernel i of one iteration, in launch order."""
+    n = load().sgep_step_kernel_name(h, i)
+    if n is None:
+        raise ValueError(f"sgep_step_kernel_name: no kernel {i}")
+    return n.decode()
 
 
 def sgep_step_profiled(h, X, ldx: int, Y, ldy: int, labels, b: int, events) -> None:
@@ -389,6 +400,10 @@ class Solver:
 
     def kernels_per_step(self):
         return sgep_kernels_per_step(self.h)
+
+    def kernel_names(self):
+        """Short names of the kernels of one iteration, in launch order."""
+        return tuple(sgep_step_kernel_name(self.h, i) for i in range(self.kernels_per_step()))
 
     def sync(self):
         sgep_sync(self.h)

@@ -53,6 +53,8 @@ struct sgep_handle_s {
     double *gram_part = nullptr, *stat_part = nullptr, *stat_tot = nullptr, *readout = nullptr;
     Coef *coef = nullptr;
     void *cpre = nullptr; // coefficient block of the iteration (k_coef)
+    int nsplit = 1;        // row slices of the backward products (1: one pass)
+    void *bpart = nullptr; // the slices' partial products (nsplit > 1)
     int n_tx = 0, n_ty = 0, n_tiles = 0;
     int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
     int64_t W = 0;          // partial width: KP (KP + 1) / 2 + KP
@@ -105,7 +107,7 @@ void free_all(sgep_handle *h)
 {
     void *ptrs[] = {h->V,  h->G,        h->Am,      h->As,    h->P,  h->Q,    h->gram_part,
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
-                    h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre};
+                    h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -203,6 +205,21 @@ void launch_timed(K kernel, dim3 grid, hipStream_t s, hipEvent_t e0, hipEvent_t 
 // k_coef computes them once per iteration.
 template <typename T> bool spec_mode(int kp, int mb) { return mb == 1 && kp * (int)sizeof(T) <= 128; }
 
+// Row-split backward (CCA, one 16-feature tile per workgroup): with few tiles
+// and long minibatches one workgroup per tile leaves most CUs idle; two row
+// slices per tile (k_bwdp, with the coefficient block on one more
+// workgroup), then a finishing pass per tile.  Measured at d = 512 + 512,
+// k = 16, b = 1024 (64 tiles): 2 slices ~1 us per step faster than the
+// single pass with helper waves; 4 and 8 slices slower (the extra launch
+// and the partials' round trip outweigh the shorter main loop).  GENERAL
+// handles keep one pass, so that an instance of a batch matches its single
+// handle bit for bit.
+constexpr int kSplit = 2;
+bool split_mode(const sgep_config &c, int mb, int n_tiles)
+{
+    return c.kind == SGEP_KIND_CCA && mb == 1 && n_tiles <= 128 && c.b_max >= 512;
+}
+
 template <typename T, int KP, int MB, int MODE>
 void launch_bwd(sgep_handle *h, const StepArgs &a, hipEvent_t e0, hipEvent_t e1)
 {
@@ -226,7 +243,8 @@ sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
 {
     const dim3 gf(a.n_fwd + 1); // + the norm-totals workgroup
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-    const bool spec = spec_mode<T>(KP, h->mb);
+    const bool split = h->nsplit > 1;
+    const bool spec = !split && spec_mode<T>(KP, h->mb);
     if (events)
         for (int i = 0; i < (spec ? 4 : 6); ++i)
             ev[i] = (hipEvent_t)events[i];
@@ -237,7 +255,14 @@ sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
         launch_timed(sgep::k_fwd<T, KP, sgep::kKindGeneral>, gf, h->stream, ev[0], ev[1], a);
     constexpr int MBW = mb_wide<T>(KP);
     constexpr bool can_spec = KP * (int)sizeof(T) <= 128; // spec_mode's player-tile bound
-    if (spec) {
+    if (split) {
+        const dim3 gp(h->n_tiles * h->nsplit + 1); // + the coefficient workgroup
+        if (cca)
+            launch_timed(sgep::k_bwdp<T, KP, sgep::kKindCCA>, gp, h->stream, ev[2], ev[3], a);
+        else
+            launch_timed(sgep::k_bwdp<T, KP, sgep::kKindGeneral>, gp, h->stream, ev[2], ev[3], a);
+        launch_bwd<T, KP, 1, sgep::kModeFin>(h, a, ev[4], ev[5]);
+    } else if (spec) {
         if constexpr (can_spec)
             launch_bwd<T, KP, 1, sgep::kModeSpec>(h, a, ev[2], ev[3]);
     } else {
@@ -260,7 +285,7 @@ int narrow_kernels(const sgep_handle *h)
 {
     const bool spec = h->esz == sizeof(double) ? spec_mode<double>(h->kp, h->mb)
                                                : spec_mode<float>(h->kp, h->mb);
-    return spec ? 2 : 3;
+    return (spec && h->nsplit == 1) ? 2 : 3;
 }
 
 template <typename T, int KP>
@@ -782,6 +807,10 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     alloc((void **)&h->readout, (size_t)d * cfg->k * sizeof(double));
     alloc((void **)&h->coef, sizeof(Coef));
     alloc(&h->cpre, (size_t)(kp * kp + 3 * kp + 4) * h->esz);
+    if (split_mode(*cfg, h->mb, h->n_tiles)) {
+        h->nsplit = kSplit;
+        alloc(&h->bpart, (size_t)h->n_tiles * kSplit * 2 * h->ft * kp * h->esz);
+    }
     if (!ok) {
         free_all(h);
         delete h;
@@ -859,6 +888,8 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.stat_tot = h->stat_tot;
     a.coef = h->coef;
     a.cpre = h->cpre;
+    a.bpart = h->bpart;
+    a.nsplit = h->nsplit;
     a.schedule = h->cfg.schedule;
     a.eta0 = h->cfg.eta0;
     a.eta_T = h->cfg.eta_T;
@@ -925,6 +956,22 @@ sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n)
         return SGEP_EINVAL;
     *n = h->wide ? 3 : narrow_kernels(h);
     return SGEP_OK;
+}
+
+const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i)
+{
+    if (!h || i < 0)
+        return nullptr;
+    static const char *wide[] = {"k_wfwd", "k_wmid", "k_wbwd"};
+    static const char *spec[] = {"k_fwd", "k_bwd"};
+    static const char *pre[] = {"k_fwd", "k_coef", "k_bwd"};
+    static const char *split[] = {"k_fwd", "k_bwdp", "k_bwd"};
+    if (h->wide)
+        return i < 3 ? wide[i] : nullptr;
+    const int n = narrow_kernels(h);
+    if (i >= n)
+        return nullptr;
+    return n == 2 ? spec[i] : (h->nsplit > 1 ? split[i] : pre[i]);
 }
 
 sgep_status sgep_step_profiled(sgep_handle *h, const void *X, int64_t ldx, const void *Y,

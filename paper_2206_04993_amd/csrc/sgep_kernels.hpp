@@ -113,14 +113,16 @@ struct StepArgs {
     int32_t k, n_tx, n_ty;   // feature tiles over view x and view y (GENERAL: n_ty = 0)
     int32_t vec_ok;          // rows of X and Y 16-byte aligned: vector loads allowed
     int32_t n_fwd;           // forward workgroups (16-row tiles) of this iteration
-    int32_t ldg, lds;        // leading dimensions of the Gram / stats partials
+    int32_t ldg, lds;        // rows allocated for the Gram / stats partials
     void *V, *G, *Am, *As;   // ldv x KP, quad-interleaved
     void *P, *Q;             // ldp x KP, quad-interleaved raw projections X V, Y V
-    double *gram_part;       // [W][ldg]: column blk = forward workgroup blk
-    double *stat_part;       // [W][lds]: column tile = backward workgroup tile
+    double *gram_part;       // [ldg][W]: row blk = forward workgroup blk
+    double *stat_part;       // [lds][W]: row tile = backward workgroup tile
     double *stat_tot;        // [W]: reduced stat_part of the state entering this iteration
     Coef *coef;
-    void *cpre;              // coefficient block of the iteration (kModePre)
+    void *cpre;              // coefficient block of the iteration (kModePre, kModeFin)
+    void *bpart;             // [tile][split][2][FT * KP] partial products (kModePart)
+    int32_t nsplit;          // row slices of the backward products (kModePart)
     int32_t schedule;
     double eta0, eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps;
 };
@@ -170,31 +172,28 @@ __device__ inline double eta_at(const StepArgs &a, double t)
     return a.eta0 * (a.t_c + D) / (t + D);
 }
 
-// out[c] = sum_{r < n} part[c * ld + r], rows in ascending order, for c < W:
-// thread q of nthr sums columns q, q + nthr, ...  No synchronisation inside
-// (the caller orders the writes to out).  ld is even and part 16-byte
-// aligned.  Every caller uses this one order, so all obtain the same bits.
+// Column sums out[c] = sum_{r < n} part[r * ld + c], rows in ascending
+// order, for c < W: thread q of nthr takes columns q, q + nthr, ...  Rows
+// are the partials of one workgroup each (W contiguous values), so the
+// threads of a wave read consecutive addresses; R rows per thread are in
+// flight together.  No synchronisation inside (the caller orders the writes
+// to out).  Every caller uses this one order, so all obtain the same bits.
 __device__ inline void colsum(const SGEP_G double *__restrict__ part, int n, int ld, int W,
                               double *__restrict__ out, int q, int nthr)
 {
-    constexpr int CH = 32;
+    constexpr int R = 32;
     for (int c = q; c < W; c += nthr) {
-        const SGEP_G double *src = part + (int64_t)c * ld;
         double s = 0.0;
-        int r = 0;
-        for (; r + CH <= n; r += CH) {
-            f64x2 v[CH / 2];
+        for (int r0 = 0; r0 < n; r0 += R) {
+            double v[R];
 #pragma unroll
-            for (int u = 0; u < CH / 2; ++u)
-                v[u] = *reinterpret_cast<const SGEP_G f64x2 *>(src + r + 2 * u);
+            for (int u = 0; u < R; ++u)
+                v[u] = r0 + u < n ? part[(uint32_t)((r0 + u) * ld + c)] : 0.0;
 #pragma unroll
-            for (int u = 0; u < CH / 2; ++u) {
-                s += v[u][0];
-                s += v[u][1];
-            }
+            for (int u = 0; u < R; ++u)
+                if (r0 + u < n)
+                    s += v[u];
         }
-        for (; r < n; ++r)
-            s += src[r];
         out[c] = s;
     }
 }
@@ -420,8 +419,7 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     if (blk == a.n_fwd) {
         // norm / parent-term totals of the current state (sum over the
         // previous backward pass's tiles, fixed order); advance t
-        colsum((const SGEP_G double *)a.stat_part, a.n_tx + a.n_ty, a.lds, GW, a.stat_tot, tid,
-               kNT);
+        colsum((const SGEP_G double *)a.stat_part, a.n_tx + a.n_ty, GW, GW, a.stat_tot, tid, kNT);
         if (tid == 0)
             ((SGEP_G Coef *)a.coef)->t += 1.0; // read by k_bwd only, after this kernel has finished
         return;
@@ -507,7 +505,7 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
                     s += (double)pt[r][i] * (double)pt[r][i];
             }
         }
-        ((SGEP_G double *)a.gram_part)[(int64_t)e * a.ldg + blk] = s;
+        ((SGEP_G double *)a.gram_part)[(int64_t)blk * GW + e] = s;
     }
 }
 
@@ -531,6 +529,8 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 // ---------------------------------------------------------------------------
 constexpr int kModePre = 0;  // backward reads the block k_coef wrote
 constexpr int kModeSpec = 1; // backward computes it on four extra waves
+constexpr int kModePart = 2; // one row slice of the products -> partial tiles
+constexpr int kModeFin = 3;  // sum of the partial tiles, block from k_coef, epilogue
 
 template <typename T, int KP> struct CoefTile {
     T Tl[KP * KP];            // T_ij, row i
@@ -657,7 +657,7 @@ __device__ __forceinline__ void coef_body(const StepArgs &a)
     coef_early<T, KP>(a, t, C, ema, true, tid);
     for (int e = tid; e < W; e += kNT)
         ss[e] = ((const SGEP_G double *)a.stat_tot)[e];
-    colsum((const SGEP_G double *)a.gram_part, a.n_fwd, a.ldg, W, gs, tid, kNT);
+    colsum((const SGEP_G double *)a.gram_part, a.n_fwd, W, W, gs, tid, kNT);
     __syncthreads();
     coef_norms<KP>(a, ss, dInv, dS, tid);
     __syncthreads();
@@ -689,9 +689,13 @@ __global__ void __launch_bounds__(kNT) k_coef(StepArgs a)
 // MODE kModeSpec: the workgroup has eight waves; waves 4..7 reduce the Gram
 // partials and compute the coefficients while waves 0..3 run the main loop.
 // MODE kModePre: four waves; the coefficient block comes from k_coef.
+// MODE kModePart: four waves over row slice `split` of nsplit (16-row groups
+// in contiguous ranges); the reduced products go to the partial buffer.
+// MODE kModeFin: four waves; the products are the fixed-order sum of the
+// slices' partials, the coefficient block comes from k_coef.
 // ---------------------------------------------------------------------------
 template <typename T, int KP, int MB, int KIND, int OPT, int MODE, bool LOWREG = false>
-__device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
+__device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split = 0)
 {
     typedef typename Mfma<T>::acc Acc;
     constexpr int NB = KP / 16;
@@ -711,7 +715,8 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
     constexpr bool SPEC = MODE == kModeSpec;
     constexpr int NTH = SPEC ? 2 * kNT : kNT; // threads of the workgroup
     constexpr int NC = (int)(sizeof(CoefTile<T, KP>) / sizeof(T));
-    constexpr int CPT = SPEC ? 1 : (NC + kNT - 1) / kNT;
+    constexpr bool PART = MODE == kModePart, FIN = MODE == kModeFin;
+    constexpr int CPT = (SPEC || PART) ? 1 : (NC + kNT - 1) / kNT;
     __shared__ T red[4][FT * KP];
     __shared__ T avt[FT * KP], bvt[FT * KP], gt[FT * KP];
     __shared__ CoefTile<T, KP> C;
@@ -766,7 +771,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
             }
     double t_it = 0.0; // helper waves: this iteration's number (set by k_fwd)
     if (main_w) {
-    if (!SPEC) {
+    if (!SPEC && !PART) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
             const int e = tid + q * kNT;
@@ -774,7 +779,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
         }
     }
 #pragma unroll
-    for (int q = 0; q < EPT; ++q) {
+    for (int q = 0; q < (PART ? 0 : EPT); ++q) {
         const int e = tid + q * kNT;
         const int fl = 4 * (e / (4 * KP)) + (e & 3);
         const bool ok = f0 + fl < nf;
@@ -804,11 +809,21 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
         pb[nb] = opB + 4 * (nb * 16 + m);
     }
     const int64_t ngf = a.b / 16; // full 16-row groups
-    for (int64_t g0 = w; g0 < ngf; g0 += 4 * UB) {
+    // this workgroup's groups [gb, ge) (all, or slice `split`) and whether it
+    // owns the ragged last group; kModeFin runs no main loop
+    int64_t gb = 0, ge = FIN ? 0 : ngf;
+    bool ragged = !FIN && ngf * 16 < a.b;
+    if (PART) {
+        const int64_t gps = (ngf + a.nsplit - 1) / a.nsplit;
+        gb = split * gps < ngf ? split * gps : ngf;
+        ge = gb + gps < ngf ? gb + gps : ngf;
+        ragged = ragged && split == a.nsplit - 1;
+    }
+    for (int64_t g0 = gb + w; g0 < ge; g0 += 4 * UB) {
         T xa[UB][4][MB], xb[UB][4][MB], ba[UB][NB][4], bb[UB][NB][4];
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
-            const int64_t g = (g0 + 4 * u < ngf) ? g0 + 4 * u : g0;
+            const int64_t g = (g0 + 4 * u < ge) ? g0 + 4 * u : g0;
             const int64_t r4 = 16 * g + 4 * kk;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -835,7 +850,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
         __builtin_amdgcn_sched_barrier(0); // all of the batch's loads first
 #pragma unroll
         for (int u = 0; u < UB; ++u) {
-            const bool gv = g0 + 4 * u < ngf;
+            const bool gv = g0 + 4 * u < ge;
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -851,7 +866,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
                 }
         }
     }
-    if (ngf * 16 < a.b && w == (int)(ngf & 3)) { // the ragged last group, masked
+    if (ragged && w == (int)((ngf - gb) & 3)) { // the ragged last group, masked
         const int64_t r4 = 16 * ngf + 4 * kk;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -881,14 +896,14 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
         coef_early<T, KP>(a, t_it, C, ema, tile == 0, q);
         for (int e = q; e < W; e += kNT)
             ss[e] = ((const SGEP_G double *)a.stat_tot)[e];
-        colsum((const SGEP_G double *)a.gram_part, a.n_fwd, a.ldg, W, gs, q, kNT);
+        colsum((const SGEP_G double *)a.gram_part, a.n_fwd, W, W, gs, q, kNT);
     }
 
     // cross-wave reduction (fixed order) into natural feature order [fl][i],
     // interleaved with the helper waves' coefficient phases (the barriers are
     // common to all waves)
     __syncthreads();
-    if (main_w) {
+    if (main_w && !FIN) {
 #pragma unroll
         for (int jm = 0; jm < MB; ++jm)
 #pragma unroll
@@ -898,7 +913,9 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
                 for (int r = 0; r < 4; ++r)
                     red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
             }
-        if (!SPEC) {
+    }
+    if (main_w) {
+        if (!SPEC && !PART) {
 #pragma unroll
             for (int q = 0; q < CPT; ++q) {
                 const int e = tid + q * kNT;
@@ -910,14 +927,26 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
         coef_norms<KP>(a, ss, dInv, dS, tid - kNT);
     }
     __syncthreads();
-    if (main_w) {
+    if (main_w && !FIN) {
         for (int e = tid; e < FT * KP; e += kNT)
             avt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    } else if (FIN) {
+        // products = fixed-order sum of the row slices' partials
+        const SGEP_G T *bp = (const SGEP_G T *)a.bpart + (int64_t)tile * a.nsplit * 2 * FT * KP;
+        for (int e = tid; e < FT * KP; e += kNT) {
+            T sa = bp[e], sb = bp[FT * KP + e];
+            for (int sp = 1; sp < a.nsplit; ++sp) {
+                sa += bp[(int64_t)sp * 2 * FT * KP + e];
+                sb += bp[(int64_t)sp * 2 * FT * KP + FT * KP + e];
+            }
+            avt[e] = sa;
+            bvt[e] = sb;
+        }
     } else {
         coef_T<T, KP>(a, gs, dInv, dS, C.Tl, Td, tid - kNT, kNT);
     }
     __syncthreads();
-    if (main_w) {
+    if (main_w && !FIN) {
 #pragma unroll
         for (int jm = 0; jm < MB; ++jm)
 #pragma unroll
@@ -927,19 +956,31 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
                 for (int r = 0; r < 4; ++r)
                     red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
             }
+    }
+    if (main_w && !PART) {
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
             const int e = tid + q * kNT;
             gt[(4 * (e / (4 * KP)) + (e & 3)) * KP + (e / 4) % KP] = pg[q];
         }
-    } else {
+    } else if (!main_w) {
         // this iteration's number t was set by k_fwd
         coef_rows<T, KP, KIND>(a, gs, ss, dInv, dS, Td, ema, t_it, C, tile == 0, tid - kNT);
     }
     __syncthreads();
-    if (main_w) {
+    if (main_w && !FIN) {
         for (int e = tid; e < FT * KP; e += kNT)
             bvt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    }
+    if (PART) {
+        // this slice's products for the finishing pass
+        __syncthreads();
+        SGEP_G T *bp = (SGEP_G T *)a.bpart + ((int64_t)tile * a.nsplit + split) * 2 * FT * KP;
+        for (int e = tid; e < FT * KP; e += kNT) {
+            bp[e] = avt[e];
+            bp[FT * KP + e] = bvt[e];
+        }
+        return;
     }
 
     // ---- fused epilogue (main waves) ----
@@ -1011,7 +1052,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile)
             for (int fl = 0; fl < FT; ++fl)
                 s += (double)avt[fl * KP + i] * (double)avt[fl * KP + i];
         }
-        sout[(int64_t)e * a.lds + tile] = s;
+        sout[(int64_t)tile * W + e] = s;
     }
 }
 
@@ -1021,11 +1062,27 @@ __global__ void __launch_bounds__(MODE == kModeSpec ? 2 * kNT : kNT) k_bwd(StepA
     bwd_body<T, KP, MB, KIND, OPT, MODE>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
+// Row-split backward, first pass: workgroup 0 computes the iteration's
+// coefficient block (coef_body; first, as the longest), and n_tiles * nsplit
+// more compute one row slice of one 16-feature tile each (block b >= 1:
+// tile (b - 1) / nsplit, slice (b - 1) % nsplit).  The second pass is k_bwd
+// with kModeFin.
+template <typename T, int KP, int KIND>
+__global__ void __launch_bounds__(kNT) k_bwdp(StepArgs a)
+{
+    if (blockIdx.x == 0) {
+        coef_body<T, KP, KIND>(a);
+        return;
+    }
+    const int b = blockIdx.x - 1;
+    bwd_body<T, KP, 1, KIND, kOptSGD, kModePart>(a, b / a.nsplit, b % a.nsplit);
+}
+
 // ---------------------------------------------------------------------------
 // Initialisation (one workgroup; not on the hot path): normalise the supplied
 // players (player-major rows of length ldv, padding zero) to the unit sphere,
 // set [Bv]_i = v_i (Alg. 2), and write the norm / parent-term sums of this
-// state as column 0 of the stats partials (the other columns are zero).
+// state as row 0 of the stats partials (the other rows are zero).
 // ---------------------------------------------------------------------------
 template <typename T, int KP>
 __global__ void __launch_bounds__(kNT) k_init(T *VQ, T *GQ, int64_t ldv, int k, double *stat0,
@@ -1067,7 +1124,7 @@ __global__ void __launch_bounds__(kNT) k_init(T *VQ, T *GQ, int64_t ldv, int k, 
         double s = 0.0;
         for (int64_t f = 0; f < ldv; ++f)
             s += (double)VQ[qidx<KP>(f, i)] * (double)GQ[qidx<KP>(f, j)]; // G = V
-        stat0[(int64_t)e * lds] = s;
+        stat0[e] = s;
         if (e >= TRI && i < k && !(s > 0.0))
             atomicOr(&cw->status, kStatusNonFinite);
     }
@@ -1088,7 +1145,7 @@ __global__ void __launch_bounds__(kNT) k_readout(const T *S, int64_t d, int64_t 
     constexpr int W = TRI + KP;
     __shared__ double ss[W];
     __shared__ double scale[KP];
-    colsum((const SGEP_G double *)stat_part, n_tiles, lds, W, ss, threadIdx.x, kNT);
+    colsum((const SGEP_G double *)stat_part, n_tiles, W, W, ss, threadIdx.x, kNT);
     __syncthreads();
     if (threadIdx.x < KP) {
         const int i = threadIdx.x;

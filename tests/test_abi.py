@@ -141,6 +141,7 @@ def test_null_arguments_rejected():
     assert lib.sgep_step(None, None, 0, None, 0, 1) == sg.SGEP_EINVAL
     assert lib.sgep_step_lda(None, None, 0, None, 1) == sg.SGEP_EINVAL
     assert lib.sgep_kernels_per_step(None, None) == sg.SGEP_EINVAL
+    assert lib.sgep_step_kernel_name(None, 0) is None
     assert lib.sgep_step_profiled(None, None, 0, None, 0, None, 1, None, 0) == sg.SGEP_EINVAL
     assert lib.sgep_init_ex(None, None, None, None, None) == sg.SGEP_EINVAL
     assert sg.sgep_status_string(sg.SGEP_EPOISONED).startswith("handle poisoned")

@@ -208,6 +208,32 @@ def test_f64_general_kp32_parity():
 
 
 # --------------------------------------------------------------------------- #
+# Row-split backward (CCA, b_max >= 512): two row slices per feature tile,     #
+# minibatches of varying length (ragged last group, empty slices)              #
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("dtype,k", [("f64", 4), ("f64", 20), ("f32", 16), ("f32", 50)])
+def test_cca_row_split_parity(dtype, k):
+    sg = _sg()
+    dx, dy = 40, 57
+    gen = synth.CCAPlanted(dx, dy, np.linspace(0.9, 0.3, 4), sigma=0.3, seed=k)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F64 if dtype == "f64" else sg.SGEP_F32, k,
+                         dx, dy, 1024, schedule=sg.SGEP_SCHED_INV, eta0=0.3, t0=20.0, gamma=0.5,
+                         rho=1e-6)
+    probe = sg.Solver(cfg, synth.initial_players(dx + dy, k, 0))
+    assert probe.kernel_names() == ("k_fwd", "k_bwdp", "k_bwd")
+    probe.close()
+    sizes = [1024, 1000, 17, 600, 513, 1, 777, 1024]
+    batches = [gen.batch(t, n) for t, n in enumerate(sizes, start=1)]
+    res = run_both(cfg, batches, synth.initial_players(dx + dy, k, 3), {1, len(sizes)})
+    for t, vg, vo, gg, go, lg, lo in res:
+        dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
+        print(f"{dtype} cca row split k={k} t={t} dV={dv:.2e} dG={dg:.2e}")
+        tol = TOL64 if dtype == "f64" else (TOL32_1 if t == 1 else TOL32_N)
+        assert dv < tol and dg < tol
+
+
+# --------------------------------------------------------------------------- #
 # Full-size medium CCA (d = 512 + 512, k = 16, b = 1024) in the benchmark's   #
 # launch configuration                                                          #
 # --------------------------------------------------------------------------- #
@@ -270,13 +296,14 @@ def test_bitwise_determinism_and_resume():
         s.close()
 
 
-def test_hipgraph_replay_matches_eager():
+@pytest.mark.parametrize("b", [256, 640])  # one backward pass; row-split backward
+def test_hipgraph_replay_matches_eager(b):
     torch = _torch()
     sg = _sg()
     gen = synth.CCAPlanted(96, 64, np.linspace(0.9, 0.3, 4), sigma=0.3, seed=4)
-    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 8, 96, 64, 256, eta0=0.2, gamma=0.5)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 8, 96, 64, b, eta0=0.2, gamma=0.5)
     R = 4
-    batches = _cca_batches(gen, R, 256)
+    batches = _cca_batches(gen, R, b)
     V0 = synth.initial_players(160, 8, 3)
     Xs = [_dev(X, torch.float32) for X, _ in batches]
     Ys = [_dev(Y, torch.float32) for _, Y in batches]
