@@ -11,7 +11,8 @@ arXiv 2206.04993):
                      reduction through a Cholesky factor of B and a cyclic
                      Jacobi eigensolve of L^{-1} A L^{-T}).
 * ``gamma_step``     one iteration of Alg. 2 with M = 1, per player, with
-                     explicit sums over the minibatch rows.
+                     explicit sums over the minibatch rows; Alg. 3 (smooth
+                     estimate of <v_j, B v_j>, App. G) with Problem.smooth.
 * ``alg1_step``      one iteration of Alg. 1 (full batch, exact B y_j).
 * ``utility``        the player utility of Sec. 2 (eq. util_new).
 * ``utility_grad``   its gradient (App. B, gradient lemma).
@@ -59,10 +60,11 @@ def _load():
         P = ctypes.POINTER(_Problem)
         lib.oracle_gamma_step.argtypes = [P, ctypes.c_int64, D, ctypes.c_int64, D, ctypes.c_int64,
                                           I32, D, D, ctypes.c_double, ctypes.c_double,
-                                          ctypes.c_double, D, D, D, D, D]
+                                          ctypes.c_double, D, D, D, D, D, D]
         lib.oracle_gamma_step.restype = ctypes.c_int
         lib.oracle_gamma_step_dense.argtypes = [P, ctypes.c_int64, D, D, D, D, ctypes.c_double,
-                                                ctypes.c_double, ctypes.c_double, D, D, D, D, D]
+                                                ctypes.c_double, ctypes.c_double, D, D, D, D, D,
+                                                D]
         lib.oracle_gamma_step_dense.restype = ctypes.c_int
         lib.oracle_alg1_step.argtypes = [ctypes.c_int64, ctypes.c_int, D, D, D, ctypes.c_double, D]
         lib.oracle_alg1_step.restype = ctypes.c_int
@@ -80,6 +82,7 @@ class _Problem(ctypes.Structure):
         ("adam_b2", ctypes.c_double), ("adam_eps", ctypes.c_double),
         ("class_means", ctypes.POINTER(ctypes.c_double)),
         ("class_priors", ctypes.POINTER(ctypes.c_double)),
+        ("smooth", ctypes.c_int32), ("pad", ctypes.c_int32), ("nu", ctypes.c_double),
     ]
 
 
@@ -156,7 +159,10 @@ class Problem:
 
     kind: KIND_CCA (A, B the block matrices of Sec. 1), KIND_GENERAL
     (A = E[y y^T], B = E[x x^T] + eps I) or KIND_LDA (A between-class,
-    B within-class covariance + eps I)."""
+    B within-class covariance + eps I).  smooth: Alg. 3 instead of Alg. 2
+    (the denominator <v_j, [Bv]_j> clipped at rho is replaced by
+    exp(log rho + (log nu - log rho) sigmoid(z_j)), z_j updated at rate
+    gamma toward <v_j, [Bv]_j>); nu bounds lambda_max(B) from above."""
     kind: int
     k: int
     dx: int
@@ -169,6 +175,8 @@ class Problem:
     adam_eps: float = 1e-8
     class_means: Optional[np.ndarray] = None   # (c, d)
     class_priors: Optional[np.ndarray] = None  # (c,)
+    smooth: bool = False
+    nu: float = 0.0
 
     @property
     def d(self) -> int:
@@ -186,13 +194,15 @@ class Problem:
             self._keep += [m, p]
             means, priors = _dp(m), _dp(p)
         return _Problem(self.kind, self.k, nc, self.optimizer, self.dx, self.dy, self.eps_reg,
-                        self.rho, self.adam_b1, self.adam_b2, self.adam_eps, means, priors)
+                        self.rho, self.adam_b1, self.adam_b2, self.adam_eps, means, priors,
+                        1 if self.smooth else 0, 0, self.nu)
 
 
 @dataclass
 class State:
     """Iterate of Alg. 2: V (unit columns), the auxiliary G = [Bv], the Adam
-    moments, the iteration counter and the Rayleigh-quotient running means."""
+    moments, the iteration counter, the Rayleigh-quotient running means and
+    the log-space variables z of Alg. 3 (zero at the start)."""
     V: np.ndarray
     G: np.ndarray
     m: Optional[np.ndarray] = None
@@ -200,6 +210,7 @@ class State:
     t: int = 0
     ema_a: Optional[np.ndarray] = None
     ema_b: Optional[np.ndarray] = None
+    z: Optional[np.ndarray] = None
 
     @staticmethod
     def init(V0: np.ndarray, adam: bool = False) -> "State":
@@ -211,7 +222,7 @@ class State:
         return State(V=V.copy(), G=V.copy(),
                      m=np.zeros_like(V) if adam else None,
                      s2=np.zeros_like(V) if adam else None,
-                     t=0, ema_a=np.zeros(k), ema_b=np.zeros(k))
+                     t=0, ema_a=np.zeros(k), ema_b=np.zeros(k), z=np.zeros(k))
 
     def eigvals(self) -> np.ndarray:
         return self.ema_a / self.ema_b
@@ -220,6 +231,22 @@ class State:
 def _colmajor(M: np.ndarray) -> np.ndarray:
     """(d, k) array -> contiguous buffer laid out d x k column-major."""
     return np.ascontiguousarray(M.T, dtype=np.float64)
+
+
+def _z(pb: Problem, st: State) -> Optional[np.ndarray]:
+    """The Alg. 3 variables, updated in place by the C step (None for Alg. 2)."""
+    if not pb.smooth:
+        return None
+    if st.z is None:
+        st.z = np.zeros(pb.k)
+    st.z = np.ascontiguousarray(st.z, dtype=np.float64)
+    return st.z
+
+
+def smooth_estimate(pb: Problem, z: np.ndarray) -> np.ndarray:
+    """Alg. 3's estimate of <v_j, B v_j>: exp(log rho + (log nu - log rho) sigmoid(z_j))."""
+    sg = 1.0 / (1.0 + np.exp(-np.asarray(z, dtype=np.float64)))
+    return np.exp(np.log(pb.rho) + (np.log(pb.nu) - np.log(pb.rho)) * sg)
 
 
 def gamma_step(pb: Problem, st: State, X: np.ndarray, Y: Optional[np.ndarray], eta_t: float,
@@ -241,11 +268,12 @@ def gamma_step(pb: Problem, st: State, X: np.ndarray, Y: Optional[np.ndarray], e
     ga = np.ascontiguousarray(st.ema_a, dtype=np.float64)
     gb = np.ascontiguousarray(st.ema_b, dtype=np.float64)
     grad = np.zeros((pb.k, pb.d)) if return_grad else None
+    z = _z(pb, st)
     st.t += 1
     cp = pb._c()
     rc = _load().oracle_gamma_step(ctypes.byref(cp), b, _dp(X), X.shape[1], _dp(Yc), Yc.shape[1],
                                    lab, _dp(V), _dp(G), eta_t, gamma_t, float(st.t),
-                                   _dp(m), _dp(s2), _dp(ga), _dp(gb), _dp(grad))
+                                   _dp(m), _dp(s2), _dp(ga), _dp(gb), _dp(grad), _dp(z))
     if rc < 0:
         raise MemoryError("oracle_gamma_step")
     st.V, st.G, st.ema_a, st.ema_b = V.T.copy(), G.T.copy(), ga, gb
@@ -266,11 +294,12 @@ def gamma_step_dense(pb: Problem, st: State, A: np.ndarray, B: np.ndarray, eta_t
     ga = np.ascontiguousarray(st.ema_a, dtype=np.float64)
     gb = np.ascontiguousarray(st.ema_b, dtype=np.float64)
     grad = np.zeros((pb.k, A.shape[0])) if return_grad else None
+    z = _z(pb, st)
     st.t += 1
     cp = pb._c()
     rc = _load().oracle_gamma_step_dense(ctypes.byref(cp), A.shape[0], _dp(A), _dp(B), _dp(V),
                                          _dp(G), eta_t, gamma_t, float(st.t), _dp(m), _dp(s2),
-                                         _dp(ga), _dp(gb), _dp(grad))
+                                         _dp(ga), _dp(gb), _dp(grad), _dp(z))
     if rc < 0:
         raise MemoryError("oracle_gamma_step_dense")
     st.V, st.G, st.ema_a, st.ema_b = V.T.copy(), G.T.copy(), ga, gb

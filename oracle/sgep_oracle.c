@@ -22,7 +22,9 @@
  *                          App. H neural-CCA table: warmup + harmonic decay)
  *   oracle_gamma_step      one iteration of Alg. 2 (stochastic gamma-EigenGame)
  *                          with M = 1, written per player with explicit sums
- *                          over the minibatch rows
+ *                          over the minibatch rows; with pb->smooth, Alg. 3
+ *                          (App. G: the clipped denominator replaced by a
+ *                          smooth log-space estimate with its own variable)
  *   oracle_gamma_step_dense  the same Alg. 2 iteration with exact A and B
  *                          (full batch; used by the fixed-point pins)
  *   oracle_alg1_step       one iteration of Alg. 1 (deterministic, exact B y_j)
@@ -322,6 +324,9 @@ typedef struct {
     double adam_b1, adam_b2, adam_eps;
     const double *class_means;  /* LDA: n_classes x d, row-major */
     const double *class_priors; /* LDA: n_classes */
+    int32_t smooth;    /* 0: Alg. 2 (clip at rho); 1: Alg. 3 (smooth estimate) */
+    int32_t pad;
+    double nu;         /* Alg. 3: upper bound of lambda_max(B), nu > rho > 0 */
 } oracle_problem;
 
 static int64_t problem_dim(const oracle_problem *pb)
@@ -425,23 +430,35 @@ static void minibatch_products(const oracle_problem *pb, int64_t b,
  *   ema_a, ema_b : running means of v_i^T A_t v_i and v_i^T B_t v_i at rate
  *           gamma (eigenvalue readout lambda_i = ema_a / ema_b), may be NULL
  *   grad_out : optional d x k copy of the update direction (tests)
- * Returns the number of parents whose <v_j, [Bv]_j> was clipped at rho. */
+ *   z     : Alg. 3 only (pb->smooth): the k log-space variables z_j, in/out
+ * Returns the number of parents whose <v_j, [Bv]_j> was clipped at rho
+ * (Alg. 2; always 0 for Alg. 3). */
 static int alg2_body(const oracle_problem *pb, int64_t d, double *V, double *G,
                      const double *AV, const double *BV, double eta, double gamma, double t,
-                     double *m, double *s2, double *ema_a, double *ema_b, double *grad_out)
+                     double *m, double *s2, double *ema_a, double *ema_b, double *grad_out,
+                     double *z)
 {
     int k = pb->k;
     double *s = (double *)malloc((size_t)k * sizeof(double));
+    double *vgs = (double *)malloc((size_t)k * sizeof(double));
     double *Vn = (double *)malloc((size_t)d * k * sizeof(double));
     int clipped = 0;
-    /* s_j = max(<v_j, [Bv]_j>, rho): the clipped estimate of ||v_j||_B^2 */
+    const double lrho = log(pb->rho), lspan = log(pb->nu) - log(pb->rho);
     for (int j = 0; j < k; ++j) {
         double vg = dot(d, V + (size_t)j * d, G + (size_t)j * d);
-        if (vg < pb->rho) {
-            vg = pb->rho;
-            ++clipped;
+        vgs[j] = vg;
+        if (pb->smooth) {
+            /* Alg. 3: [<v, B v>]_j = exp(log rho + (log nu - log rho) sigmoid(z_j)) */
+            double sg = 1.0 / (1.0 + exp(-z[j]));
+            s[j] = exp(lrho + lspan * sg);
+        } else {
+            /* Alg. 2: s_j = max(<v_j, [Bv]_j>, rho), the clipped estimate of ||v_j||_B^2 */
+            if (vg < pb->rho) {
+                vg = pb->rho;
+                ++clipped;
+            }
+            s[j] = vg;
         }
-        s[j] = vg;
     }
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < k; ++i) {
@@ -501,8 +518,17 @@ static int alg2_body(const oracle_problem *pb, int64_t d, double *V, double *G,
         for (int64_t f = 0; f < d; ++f)
             gi[f] += gamma * (Bvi[f] - gi[f]);
     }
+    /* Alg. 3: z_i <- z_i + gamma grad_z, grad_z = (<v_i, [Bv]_i> - s_i) s_i
+     * (log nu - log rho) sigmoid(z_i) (1 - sigmoid(z_i)), with v_i, [Bv]_i and
+     * s_i of this iteration (before the updates above) */
+    if (pb->smooth)
+        for (int i = 0; i < k; ++i) {
+            double sg = 1.0 / (1.0 + exp(-z[i]));
+            z[i] += gamma * (vgs[i] - s[i]) * s[i] * lspan * sg * (1.0 - sg);
+        }
     memcpy(V, Vn, (size_t)d * k * sizeof(double));
     free(s);
+    free(vgs);
     free(Vn);
     return clipped;
 }
@@ -514,7 +540,7 @@ int oracle_gamma_step(const oracle_problem *pb, int64_t b,
                       const double *X, int64_t ldx, const double *Y, int64_t ldy,
                       const int32_t *labels, double *V, double *G, double eta, double gamma,
                       double t, double *m, double *s2, double *ema_a, double *ema_b,
-                      double *grad_out)
+                      double *grad_out, double *z)
 {
     int64_t d = problem_dim(pb);
     int k = pb->k;
@@ -534,7 +560,7 @@ int oracle_gamma_step(const oracle_problem *pb, int64_t b,
                                AV + (size_t)i * d, BV + (size_t)i * d, tmp);
         free(tmp);
     }
-    int rc = alg2_body(pb, d, V, G, AV, BV, eta, gamma, t, m, s2, ema_a, ema_b, grad_out);
+    int rc = alg2_body(pb, d, V, G, AV, BV, eta, gamma, t, m, s2, ema_a, ema_b, grad_out, z);
     free(AV);
     free(BV);
     return rc;
@@ -544,7 +570,8 @@ int oracle_gamma_step(const oracle_problem *pb, int64_t b,
  * A_t = A, B_t = B.  Used for the fixed-point and consistency pins. */
 int oracle_gamma_step_dense(const oracle_problem *pb, int64_t d, const double *A, const double *B,
                             double *V, double *G, double eta, double gamma, double t,
-                            double *m, double *s2, double *ema_a, double *ema_b, double *grad_out)
+                            double *m, double *s2, double *ema_a, double *ema_b, double *grad_out,
+                            double *z)
 {
     int k = pb->k;
     double *AV = (double *)malloc((size_t)d * k * sizeof(double));
@@ -559,7 +586,7 @@ int oracle_gamma_step_dense(const oracle_problem *pb, int64_t d, const double *A
             AV[(size_t)i * d + r] = dot(d, A + (size_t)r * d, V + (size_t)i * d);
             BV[(size_t)i * d + r] = dot(d, B + (size_t)r * d, V + (size_t)i * d);
         }
-    int rc = alg2_body(pb, d, V, G, AV, BV, eta, gamma, t, m, s2, ema_a, ema_b, grad_out);
+    int rc = alg2_body(pb, d, V, G, AV, BV, eta, gamma, t, m, s2, ema_a, ema_b, grad_out, z);
     free(AV);
     free(BV);
     return rc;

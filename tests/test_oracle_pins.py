@@ -425,3 +425,135 @@ def test_schedules_closed_forms():
     kw = dict(eta0=1e-2, eta_T=1e-3, t_c=100, T=1000)
     assert abs(e(oracle.SCHED_WARMUP_HARMONIC, 100, **kw) - 1e-2) < 1e-15
     assert abs(e(oracle.SCHED_WARMUP_HARMONIC, 1000, **kw) - 1e-3) < 1e-15
+
+
+# --------------------------------------------------------------------------- #
+# Alg. 3 (smooth stochastic gamma-EigenGame, App. G)                          #
+# --------------------------------------------------------------------------- #
+
+def _z_for(pb, s):
+    """z with exp(log rho + (log nu - log rho) sigmoid(z)) = s, rho < s < nu."""
+    f = (np.log(s) - np.log(pb.rho)) / (np.log(pb.nu) - np.log(pb.rho))
+    return np.log(f / (1.0 - f))
+
+
+def test_smooth_estimate_closed_forms():
+    """The log-space estimate lies strictly between rho and nu, equals their
+    geometric mean at z = 0 (the initial value), tends to rho and nu at the
+    ends, and its logarithm is affine in sigmoid(z)."""
+    pb = oracle.Problem(oracle.KIND_CCA, 3, 5, 7, rho=1e-4, nu=25.0, smooth=True)
+    assert np.isclose(oracle.smooth_estimate(pb, [0.0])[0], np.sqrt(1e-4 * 25.0), rtol=1e-14)
+    z = np.linspace(-30, 30, 61)
+    s = oracle.smooth_estimate(pb, z)
+    assert np.all(s > pb.rho * (1 - 1e-12)) and np.all(s < pb.nu * (1 + 1e-12))
+    assert np.all(np.diff(s) > 0)
+    assert np.isclose(s[0], pb.rho, rtol=1e-9) and np.isclose(s[-1], pb.nu, rtol=1e-9)
+    sg = 1 / (1 + np.exp(-z))
+    assert np.allclose(np.log(s), np.log(1e-4) + np.log(25.0 / 1e-4) * sg, atol=1e-12)
+    # the inverse used by the tests below
+    assert np.allclose(oracle.smooth_estimate(pb, _z_for(pb, np.array([0.01, 0.3, 7.0]))),
+                       [0.01, 0.3, 7.0], rtol=1e-12)
+
+
+def test_smooth_z_step_is_descent_on_squared_mismatch():
+    """One Alg. 3 iteration with eta = 0 moves z_i by gamma times minus the
+    derivative of (c_i - s(z_i))^2 / 2, c_i = <v_i, [Bv]_i> of the iteration:
+    checked against central finite differences of that loss (which also
+    fixes the sign: the estimate moves toward c_i)."""
+    rng = np.random.default_rng(21)
+    d, k = 9, 4
+    A, B = _rand_sym(rng, d), _rand_spd(rng, d)
+    pb = oracle.Problem(oracle.KIND_GENERAL, k, d, d, rho=1e-3, nu=50.0, smooth=True)
+    st = oracle.State.init(rng.standard_normal((d, k)))
+    st.G = B @ st.V + 0.1 * rng.standard_normal((d, k))
+    st.z = rng.uniform(-2, 2, k)
+    c = np.einsum("fi,fi->i", st.V, st.G)
+    z0 = st.z.copy()
+    gamma = 0.3
+    oracle.gamma_step_dense(pb, st, A, B, 0.0, gamma)
+    h = 1e-6
+
+    def loss(z):
+        return 0.5 * (c - oracle.smooth_estimate(pb, z)) ** 2
+
+    fd = (loss(z0 + h) - loss(z0 - h)) / (2 * h)
+    assert np.allclose(st.z - z0, -gamma * fd, rtol=1e-6, atol=1e-12)
+    assert np.all(np.sign(st.z - z0) == np.sign(c - oracle.smooth_estimate(pb, z0)))
+
+
+def test_smooth_reduces_to_clip_when_estimate_matches():
+    """When z_j gives s_j = <v_j, [Bv]_j> (inside (rho, nu)), Alg. 3 takes
+    exactly Alg. 2's step and z stays put (its gradient vanishes)."""
+    rng = np.random.default_rng(22)
+    X, Y = _cca_data(rng, b=96)
+    p2 = oracle.Problem(oracle.KIND_CCA, 4, 5, 7, rho=1e-6)
+    p3 = oracle.Problem(oracle.KIND_CCA, 4, 5, 7, rho=1e-6, nu=100.0, smooth=True)
+    V0 = rng.standard_normal((12, 4))
+    s2, s3 = oracle.State.init(V0), oracle.State.init(V0)
+    G = s2.V * rng.uniform(0.5, 2.0, 4) + 0.05 * rng.standard_normal((12, 4))
+    s2.G, s3.G = G.copy(), G.copy()
+    c = np.einsum("fi,fi->i", s3.V, s3.G)
+    assert np.all(c > 1e-6)
+    s3.z = _z_for(p3, c)
+    z0 = s3.z.copy()
+    _, g2 = oracle.gamma_step(p2, s2, X, Y, 0.2, 0.5, return_grad=True)
+    _, g3 = oracle.gamma_step(p3, s3, X, Y, 0.2, 0.5, return_grad=True)
+    assert np.abs(g2 - g3).max() < 1e-12 * np.abs(g2).max()
+    assert np.abs(s2.V - s3.V).max() < 1e-13 and np.abs(s2.G - s3.G).max() < 1e-13
+    assert np.abs(s3.z - z0).max() < 1e-12
+
+
+def test_smooth_tangency_and_fixed_point():
+    """The smooth estimate changes only the parents' scaling: v_i^T grad_i = 0
+    for any z, and at the exact solution with [Bv] = Bv and s_j = v_j^T B v_j
+    the direction and the z step vanish."""
+    rng = np.random.default_rng(23)
+    X, Y = _cca_data(rng)
+    pb = oracle.Problem(oracle.KIND_CCA, 4, 5, 7, rho=1e-6, nu=10.0, smooth=True)
+    st = oracle.State.init(rng.standard_normal((12, 4)))
+    st.G = rng.standard_normal(st.G.shape)
+    st.z = rng.uniform(-3, 3, 4)
+    V = st.V.copy()
+    _, g = oracle.gamma_step(pb, st, X, Y, 0.1, 0.5, return_grad=True)
+    for i in range(4):
+        assert abs(V[:, i] @ g[:, i]) <= 1e-13 * np.linalg.norm(g[:, i])
+    d, k = 10, 4
+    A, B = _rand_sym(rng, d) + 3 * np.eye(d), _rand_spd(rng, d)
+    lam, Vs = oracle.gep_topk(A, B, k)
+    pb = oracle.Problem(oracle.KIND_GENERAL, k, d, d, rho=1e-6, nu=1e3, smooth=True)
+    st = oracle.State.init(Vs)
+    st.G = B @ st.V
+    st.z = _z_for(pb, np.einsum("fi,fi->i", st.V, st.G))
+    z0, V0 = st.z.copy(), st.V.copy()
+    _, g = oracle.gamma_step_dense(pb, st, A, B, 0.5, 1.0, return_grad=True)
+    assert np.abs(g).max() < 1e-13 * np.abs(A).max()
+    assert np.abs(st.V - V0).max() < 1e-13 and np.abs(st.z - z0).max() < 1e-10
+
+
+def test_smooth_estimate_tracks_b_norm_and_alg3_converges():
+    """With eta = 0 on exact matrices, [Bv] -> B v and the estimate s_j ->
+    v_j^T B v_j (the stationary point of the z dynamics); with a decaying
+    eta, Alg. 3 on exact matrices reaches the exact top-k (the convergence
+    the paper conjectures) to 1e-9 subspace error.  The z step is gradient
+    descent on (c - s(z))^2 / 2 at rate gamma, stable only while
+    gamma s'(z)^2 < 2 near the target; (rho, nu) = (0.1, 10) with gamma = 0.1
+    keeps it there (gamma = 0.5 with (1e-3, 1e2) overshoots into the flat
+    tail at rho)."""
+    rng = np.random.default_rng(24)
+    d, k = 8, 3
+    lam_p = np.array([5.0, 3.0, 2.0, 0.5, 0.3, 0.2, 0.1, 0.05])
+    B = _rand_spd(rng, d)
+    L = np.linalg.cholesky(B)
+    Q, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    A = L @ Q @ np.diag(lam_p) @ Q.T @ L.T
+    lam, Vs = oracle.gep_topk(A, B, k)
+    pb = oracle.Problem(oracle.KIND_GENERAL, k, d, d, rho=0.1, nu=10.0, smooth=True)
+    st = oracle.State.init(rng.standard_normal((d, k)))
+    for t in range(1, 3001):
+        oracle.gamma_step_dense(pb, st, A, B, 0.0, 0.1)
+    bnorm = np.einsum("fi,fg,gi->i", st.V, B, st.V)
+    assert np.allclose(oracle.smooth_estimate(pb, st.z), bnorm, rtol=1e-9)
+    st = oracle.State.init(rng.standard_normal((d, k)))
+    for t in range(1, 6001):
+        oracle.gamma_step_dense(pb, st, A, B, 0.05, 0.1)
+    assert oracle.subspace_error(st.V, Vs, B) < 1e-9
