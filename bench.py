@@ -54,6 +54,13 @@ WORKLOADS = {
         generator="medium_cca", tta=dict(targets=(5e-3, 1e-3), max_steps=100_000, every=1000),
         describe="CCA FP32: views 512+512 (d=1024), k=16, minibatch 1024; planted "
                  "correlations linspace(0.95,0.2,16), per-view condition 100"),
+    "cca_d1024_k16_b1024_fp32_alg3": dict(
+        kind="cca", dtype="f32", dx=512, dy=512, k=16, b=1024, ring=128,
+        optimizer="adam", schedule="inv", eta0=4e-3, t0=100.0, gamma=0.3, rho=1e-3,
+        smooth=1, nu=4.0,
+        generator="medium_cca", tta=dict(targets=(5e-3, 1e-3), max_steps=100_000, every=1000),
+        describe="the medium FP32 CCA (views 512+512, k=16, minibatch 1024) with Alg. 3: "
+                 "parents' B-norms estimated in log space between rho=1e-3 and nu=4"),
     "cca_d16_k4_b128_fp64": dict(
         kind="cca", dtype="f64", dx=8, dy=8, k=4, b=128, ring=128,
         optimizer="sgd", schedule="inv", eta0=1.0, t0=200.0, gamma=1.0, rho=1e-6,
@@ -208,7 +215,8 @@ def config_for(sg, w):
         optimizer=sg.SGEP_ADAM if w["optimizer"] == "adam" else sg.SGEP_SGD,
         schedule={"const": sg.SGEP_SCHED_CONST, "inv": sg.SGEP_SCHED_INV}[w["schedule"]],
         eta0=w["eta0"], t0=w.get("t0", 1.0), gamma=w["gamma"], rho=w["rho"],
-        eps_reg=w.get("eps_reg", 0.0), n_classes=w.get("n_classes", 0))
+        eps_reg=w.get("eps_reg", 0.0), n_classes=w.get("n_classes", 0),
+        smooth=w.get("smooth", 0), nu=w.get("nu", 0.0))
 
 
 def algorithmic_work(w, kernel, names=()):
@@ -260,7 +268,7 @@ def cpu_baseline(w, budget_s: float, host):
     pb = oracle.Problem(oracle.KIND_LDA if lda else oracle.KIND_CCA, w["k"], w["dx"], w["dy"],
                         rho=w["rho"], eps_reg=w.get("eps_reg", 0.0),
                         optimizer=oracle.OPT_ADAM if w["optimizer"] == "adam" else oracle.OPT_SGD,
-                        **extra)
+                        smooth=bool(w.get("smooth", 0)), nu=w.get("nu", 0.0), **extra)
     st = oracle.State.init(synth.initial_players(w["dx"] + w["dy"], w["k"], 0),
                            adam=w["optimizer"] == "adam")
     n = 0

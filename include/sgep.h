@@ -104,10 +104,21 @@ typedef struct sgep_config {
     double eta0, eta_T, t0, t_c, T; /* schedule parameters (see above) */
     double gamma;      /* rate gamma_t (constant) of the auxiliary [Bv] update
                         * and of the Rayleigh-quotient running means, 0 < gamma <= 1 */
-    double rho;        /* clip: <v_j, [Bv]_j> is replaced by max(., rho), rho >= 0 */
+    double rho;        /* Alg. 2 clip: <v_j, [Bv]_j> is replaced by max(., rho),
+                        * rho >= 0; Alg. 3: the lower end of the estimate, > 0 */
     double eps_reg;    /* GENERAL, LDA: ridge, B = ... + eps_reg I; CCA: must be 0 */
     double adam_b1, adam_b2, adam_eps;
     uint64_t seed;     /* reserved (initial players are always supplied) */
+    int32_t smooth;    /* 0: Alg. 2 (parents' <v_j, B v_j> estimated by
+                        * max(<v_j, [Bv]_j>, rho)); 1: Alg. 3 (smooth stochastic
+                        * variant, App. G: estimated by
+                        * exp(log rho + (log nu - log rho) sigmoid(z_j)), with z_j
+                        * starting at 0 and moved at rate gamma by
+                        * (<v_j, [Bv]_j> - s_j) s_j (log nu - log rho)
+                        * sigmoid(z_j) (1 - sigmoid(z_j)) each iteration) */
+    int32_t reserved;  /* must be 0 */
+    double nu;         /* Alg. 3: upper bound of lambda_max(B), nu > rho; unused
+                        * (any value) with smooth = 0 */
 } sgep_config;
 
 typedef struct sgep_handle_s sgep_handle;

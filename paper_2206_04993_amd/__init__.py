@@ -59,6 +59,7 @@ class sgep_config(ctypes.Structure):
         ("rho", ctypes.c_double), ("eps_reg", ctypes.c_double),
         ("adam_b1", ctypes.c_double), ("adam_b2", ctypes.c_double),
         ("adam_eps", ctypes.c_double), ("seed", ctypes.c_uint64),
+        ("smooth", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nu", ctypes.c_double),
     ]
 
 
@@ -67,9 +68,12 @@ def make_config(kind: int, dtype: int, k: int, dx: int, dy: int, b_max: int, *,
                 eta0: float = 0.1, eta_T: float = 0.0, t0: float = 1.0, t_c: float = 1.0,
                 T: float = 1.0, gamma: float = 1.0, rho: float = 1e-6, eps_reg: float = 0.0,
                 adam_b1: float = 0.9, adam_b2: float = 0.999, adam_eps: float = 1e-8,
-                n_classes: int = 0, seed: int = 0) -> sgep_config:
+                n_classes: int = 0, seed: int = 0, smooth: int = 0,
+                nu: float = 0.0) -> sgep_config:
+    """smooth = 1 selects Alg. 3 (smooth estimate between rho and nu)."""
     return sgep_config(kind, dtype, k, optimizer, schedule, n_classes, dx, dy, b_max, eta0,
-                       eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps, seed)
+                       eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps, seed,
+                       smooth, 0, nu)
 
 
 class sgep_init_aux(ctypes.Structure):

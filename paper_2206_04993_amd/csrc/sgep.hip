@@ -29,7 +29,7 @@ using sgep::wide::WideArgs;
 namespace {
 
 constexpr uint32_t kStateMagic = 0x53474550u; // "SGEP"
-constexpr uint32_t kStateVersion = 1u;
+constexpr uint32_t kStateVersion = 2u;
 
 struct StateHeader {
     uint32_t magic, version;
@@ -87,10 +87,10 @@ uint64_t config_hash(const sgep_config &c)
 {
     // hash every field explicitly (no struct padding in the digest)
     uint64_t h = 1469598103934665603ull;
-    const int32_t ints[] = {c.kind, c.dtype, c.k, c.optimizer, c.schedule, c.n_classes};
+    const int32_t ints[] = {c.kind, c.dtype, c.k, c.optimizer, c.schedule, c.n_classes, c.smooth};
     const int64_t dims[] = {c.dx, c.dy, c.b_max};
     const double reals[] = {c.eta0, c.eta_T, c.t0, c.t_c, c.T, c.gamma, c.rho, c.eps_reg,
-                            c.adam_b1, c.adam_b2, c.adam_eps};
+                            c.adam_b1, c.adam_b2, c.adam_eps, c.smooth ? c.nu : 0.0};
     h = fnv1a(ints, sizeof(ints), h);
     h = fnv1a(dims, sizeof(dims), h);
     h = fnv1a(reals, sizeof(reals), h);
@@ -153,6 +153,10 @@ sgep_status check_cfg(const sgep_config *c)
     if (c->b_max > (int64_t)1 << 19 || d > (int64_t)1 << 19)
         return SGEP_EUNSUPPORTED;
     if (!(c->eta0 >= 0.0) || !(c->gamma > 0.0 && c->gamma <= 1.0) || !(c->rho >= 0.0))
+        return SGEP_EINVAL;
+    if ((c->smooth != 0 && c->smooth != 1) || c->reserved != 0)
+        return SGEP_EINVAL;
+    if (c->smooth && !(c->rho > 0.0 && c->nu > c->rho && std::isfinite(c->nu)))
         return SGEP_EINVAL;
     if (c->kind == SGEP_KIND_CCA && c->eps_reg != 0.0)
         return SGEP_EINVAL;
@@ -555,6 +559,9 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.T = c.T;
     a.gamma = c.gamma;
     a.rho = c.rho;
+    a.smooth = c.smooth;
+    a.lrho = c.smooth ? log(c.rho) : 0.0;
+    a.lspan = c.smooth ? log(c.nu) - log(c.rho) : 0.0;
     a.eps_reg = c.eps_reg;
     a.adam_b1 = c.adam_b1;
     a.adam_b2 = c.adam_b2;
@@ -898,6 +905,9 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.T = h->cfg.T;
     a.gamma = h->cfg.gamma;
     a.rho = h->cfg.rho;
+    a.smooth = h->cfg.smooth;
+    a.lrho = h->cfg.smooth ? log(h->cfg.rho) : 0.0;
+    a.lspan = h->cfg.smooth ? log(h->cfg.nu) - log(h->cfg.rho) : 0.0;
     a.eps_reg = h->cfg.eps_reg;
     a.adam_b1 = h->cfg.adam_b1;
     a.adam_b2 = h->cfg.adam_b2;

@@ -96,9 +96,12 @@ struct Coef {
     double mA[kKPMax];       // v_i^T A_t v_i (latest iteration)
     double mB[kKPMax];       // v_i^T B_t v_i
     double c[kKPMax];        // sum_{j<i} T_ij C_ij
-    double s[kKPMax];        // max(v_j^T G_j, rho) used by the latest iteration
+    double s[kKPMax];        // estimate of v_j^T B v_j used by the latest iteration
     double ema_a[kKPMax];    // running mean of mA (rate gamma)
     double ema_b[kKPMax];    // running mean of mB
+    double z[2][kKPMax];     // Alg. 3 variables: iteration t reads z[t & 1] and
+                             // writes z[(t + 1) & 1] (other workgroups may still
+                             // read z[t & 1] while the writer stores)
     int status;              // kStatus* bits
     int clip_count;          // parents clipped at rho, cumulative
 };
@@ -124,7 +127,9 @@ struct StepArgs {
     void *bpart;             // [tile][split][2][FT * KP] partial products (kModePart)
     int32_t nsplit;          // row slices of the backward products (kModePart)
     int32_t schedule;
+    int32_t smooth;          // Alg. 3 estimate of v_j^T B v_j instead of the clip
     double eta0, eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps;
+    double lrho, lspan;      // Alg. 3: log rho, log nu - log rho
 };
 
 __device__ __forceinline__ int tri_idx(int i, int j) { return i * (i + 1) / 2 + j; } // j <= i
@@ -538,10 +543,17 @@ template <typename T, int KP> struct CoefTile {
     T eta, c1, c2, pad;       // eta_t, 1 - b1^t, 1 - b2^t
 };
 
-// inv_i and s_i (thread q < KP)
+// Alg. 3 estimate of v_j^T B v_j from its log-space variable z
+__device__ __forceinline__ double smooth_s(double lrho, double lspan, double z)
+{
+    return exp(lrho + lspan / (1.0 + exp(-z)));
+}
+
+// inv_i and s_i (thread q < KP) of iteration t: s_i = max(v_i^T G_i, rho)
+// (Alg. 2) or the smooth estimate from z_i (Alg. 3)
 template <int KP>
 __device__ __forceinline__ void coef_norms(const StepArgs &a, const double *ss, double *dInv,
-                                           double *dS, int q)
+                                           double *dS, double t, int q)
 {
     constexpr int TRI = KP * (KP + 1) / 2;
     if (q < KP) {
@@ -549,9 +561,14 @@ __device__ __forceinline__ void coef_norms(const StepArgs &a, const double *ss, 
         double inv = 0.0, s = 1.0;
         if (i < a.k) {
             inv = 1.0 / sqrt(ss[TRI + i]);
-            s = ss[tri_idx(i, i)] * inv; // v_i^T G_i with the unit v_i
-            if (!(s >= a.rho))
-                s = a.rho;
+            if (a.smooth) {
+                const SGEP_G Coef *cg = (const SGEP_G Coef *)a.coef;
+                s = smooth_s(a.lrho, a.lspan, cg->z[(int64_t)t & 1][i]);
+            } else {
+                s = ss[tri_idx(i, i)] * inv; // v_i^T G_i with the unit v_i
+                if (!(s >= a.rho))
+                    s = a.rho;
+            }
         }
         dInv[i] = inv;
         dS[i] = s;
@@ -625,8 +642,18 @@ __device__ __forceinline__ void coef_rows(const StepArgs &a, const double *gs, c
                 cw->ema_a[i] = ema[i] + a.gamma * (mA - ema[i]);
                 cw->ema_b[i] = ema[KP + i] + a.gamma * (mB - ema[KP + i]);
                 const double craw = ss[tri_idx(i, i)] * dInv[i];
-                if (!(craw >= a.rho))
+                if (a.smooth) {
+                    // Alg. 3: z_i += gamma (c_i - s_i) s_i (log nu - log rho) sig (1 - sig)
+                    const double z = cw->z[(int64_t)t & 1][i];
+                    const double sg = 1.0 / (1.0 + exp(-z));
+                    const double zn =
+                        z + a.gamma * (craw - dS[i]) * dS[i] * a.lspan * sg * (1.0 - sg);
+                    cw->z[((int64_t)t + 1) & 1][i] = zn;
+                    if (!isfinite(zn))
+                        atomicOr((int *)&cw->status, kStatusNonFinite);
+                } else if (!(craw >= a.rho)) {
                     atomicAdd((int *)&cw->clip_count, 1);
+                }
                 if (!isfinite(mA) || !isfinite(mB) || !isfinite(c) || !isfinite(dInv[i]) ||
                     !(dInv[i] > 0.0) || !isfinite(craw))
                     atomicOr((int *)&cw->status, kStatusNonFinite);
@@ -659,7 +686,7 @@ __device__ __forceinline__ void coef_body(const StepArgs &a)
         ss[e] = ((const SGEP_G double *)a.stat_tot)[e];
     colsum((const SGEP_G double *)a.gram_part, a.n_fwd, W, W, gs, tid, kNT);
     __syncthreads();
-    coef_norms<KP>(a, ss, dInv, dS, tid);
+    coef_norms<KP>(a, ss, dInv, dS, t, tid);
     __syncthreads();
     coef_T<T, KP>(a, gs, dInv, dS, C.Tl, Td, tid, kNT);
     __syncthreads();
@@ -924,7 +951,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
             }
         }
     } else {
-        coef_norms<KP>(a, ss, dInv, dS, tid - kNT);
+        coef_norms<KP>(a, ss, dInv, dS, t_it, tid - kNT);
     }
     __syncthreads();
     if (main_w && !FIN) {

@@ -97,6 +97,8 @@ struct WideArgs {
     Coef *coef;
     int32_t schedule;
     double eta0, eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps;
+    int32_t smooth;          // Alg. 3 estimate of v_j^T B v_j instead of the clip
+    double lrho, lspan;      // Alg. 3: log rho, log nu - log rho
 };
 
 __device__ inline double eta_sched(const WideArgs &a, double t)
@@ -784,9 +786,14 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                 double inv = 0.0, s = 1.0;
                 if (i < a.k) {
                     inv = 1.0 / sqrt(ss[TRI + i]);
-                    s = ss[tri_idx(i, i)] * inv;
-                    if (!(s >= a.rho))
-                        s = a.rho;
+                    if (a.smooth) { // Alg. 3: exp(log rho + (log nu - log rho) sigmoid(z_i))
+                        const double z = a.coef->z[(int64_t)t & 1][i];
+                        s = exp(a.lrho + a.lspan / (1.0 + exp(-z)));
+                    } else {        // Alg. 2: max(v_i^T G_i, rho)
+                        s = ss[tri_idx(i, i)] * inv;
+                        if (!(s >= a.rho))
+                            s = a.rho;
+                    }
                 }
                 dInv[i] = inv;
                 dS[i] = s;
@@ -858,8 +865,18 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                         cw->ema_a[i] += a.gamma * (mA - cw->ema_a[i]);
                         cw->ema_b[i] += a.gamma * (mB - cw->ema_b[i]);
                         const double craw = ss[tri_idx(i, i)] * dInv[i];
-                        if (!(craw >= a.rho))
+                        if (a.smooth) {
+                            // Alg. 3 z step at rate gamma, into the other buffer
+                            const double z = cw->z[(int64_t)t & 1][i];
+                            const double sg = 1.0 / (1.0 + exp(-z));
+                            const double zn = z + a.gamma * (craw - dS[i]) * dS[i] * a.lspan *
+                                                      sg * (1.0 - sg);
+                            cw->z[((int64_t)t + 1) & 1][i] = zn;
+                            if (!isfinite(zn))
+                                atomicOr(&cw->status, kStatusNonFinite);
+                        } else if (!(craw >= a.rho)) {
                             atomicAdd(&cw->clip_count, 1);
+                        }
                         if (!isfinite(mA) || !isfinite(mB) || !isfinite(c) || !isfinite(dInv[i]) ||
                             !(dInv[i] > 0.0) || !isfinite(craw))
                             atomicOr(&cw->status, kStatusNonFinite);

@@ -97,6 +97,10 @@ def test_config_validation_is_synchronous():
         (mk(L, sg.SGEP_BF16, 4, 8, 8, 16, n_classes=3), sg.SGEP_ESHAPE),   # LDA: dy = 0
         (mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=3), sg.SGEP_EINVAL),   # no class means
         (mk(9, sg.SGEP_F32, 4, 8, 8, 16), sg.SGEP_EINVAL),
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=2, nu=10.0), sg.SGEP_EINVAL),    # Alg. 2 or 3
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=1, rho=0.0, nu=10.0), sg.SGEP_EINVAL),  # rho > 0
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=1, rho=1e-2, nu=1e-2), sg.SGEP_EINVAL),  # nu > rho
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=1, rho=1e-2, nu=float("inf")), sg.SGEP_EINVAL),
     ]
     for cfg, want in cases:
         assert _init_status(cfg) == want, (cfg.kind, cfg.dtype, cfg.k, want)

@@ -1,0 +1,235 @@
+"""GPU parity of Alg. 3 (smooth stochastic gamma-EigenGame, App. G) against
+the FP64 oracle, through the C ABI, in every backward mode: helper waves
+(tiny FP64 CCA), the coefficient kernel (FP64 GENERAL with 32 players), the
+row-split backward (FP32 CCA, minibatches of varying length), the BF16 path
+(CCA and LDA) and the batched path (bit-equal to single handles).  The
+estimates s_j = exp(log rho + (log nu - log rho) sigmoid(z_j)) and the z
+steps are FP64 on both sides, so the bars are those of Alg. 2 at the same
+precision.  (rho, nu, gamma) keep the z step in its stable range
+(gamma s'(z)^2 < 2 at the data's B-norms)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32_1, TOL32_N = 2e-5, 3e-4
+TOLW_1, TOLW_N = 8e-5, 1.2e-3
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _sg():
+    import paper_2206_04993_amd as sg
+    sg.load()
+    return sg
+
+
+def _dev(a, dtype):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype).contiguous()
+
+
+def _eta(cfg, t):
+    return oracle.eta(cfg.schedule, t, cfg.eta0, cfg.eta_T, cfg.t0, cfg.t_c, cfg.T)
+
+
+def _pb(cfg, kind, **kw):
+    return oracle.Problem(kind, cfg.k, cfg.dx, cfg.dy, eps_reg=cfg.eps_reg, rho=cfg.rho,
+                          optimizer=cfg.optimizer, adam_b1=cfg.adam_b1, adam_b2=cfg.adam_b2,
+                          adam_eps=cfg.adam_eps, smooth=True, nu=cfg.nu, **kw)
+
+
+def _run_narrow(cfg, kind, batches, V0, checkpoints, f64):
+    torch = _torch()
+    sg = _sg()
+    tdt, ndt = (torch.float64, np.float64) if f64 else (torch.float32, np.float32)
+    s = sg.Solver(cfg, V0)
+    pb = _pb(cfg, kind)
+    st = oracle.State.init(V0, adam=cfg.optimizer == sg.SGEP_ADAM)
+    out = []
+    for t, (X, Y) in enumerate(batches, start=1):
+        Xr, Yr = X.astype(ndt).astype(np.float64), Y.astype(ndt).astype(np.float64)
+        s.step(_dev(Xr, tdt), _dev(Yr, tdt))
+        oracle.gamma_step(pb, st, Xr, Yr, _eta(cfg, t), cfg.gamma)
+        if t in checkpoints:
+            out.append((t, s.vectors(), st.V.copy(), s.auxiliary(), st.G.copy(), s.eigvals(),
+                        st.eigvals()))
+    names = s.kernel_names()
+    s.close()
+    return out, names
+
+
+def _check(res, tol1, tolN, label):
+    for t, vg, vo, gg, go, lg, lo in res:
+        dv = float(np.abs(vg - vo).max())
+        dg = float(np.abs(gg - go).max()) / max(1.0, float(np.abs(go).max()))
+        print(f"{label} t={t} dV={dv:.2e} dG={dg:.2e}", flush=True)
+        tol = tol1 if t == 1 else tolN
+        assert dv < tol and dg < tol, (t, dv, dg)
+        assert np.allclose(lg, lo, rtol=10 * tol, atol=10 * tol), (t, lg, lo)
+
+
+def test_smooth_f64_tiny_cca_helper_waves():
+    sg = _sg()
+    gen, pool = synth.tiny_cca_pool(0)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F64, 4, 8, 8, 128,
+                         schedule=sg.SGEP_SCHED_INV, eta0=1.0, t0=200.0, gamma=0.5,
+                         rho=1e-2, nu=10.0, smooth=1)
+    batches = [pool.batch(t, 128) for t in range(1, 101)]
+    res, names = _run_narrow(cfg, oracle.KIND_CCA, batches, synth.initial_players(16, 4, 0),
+                             {1, 10, 100}, True)
+    assert names == ("k_fwd", "k_bwd")
+    _check(res, TOL64, TOL64, "f64 tiny cca smooth")
+
+
+def test_smooth_f64_general_coefficient_kernel():
+    sg = _sg()
+    gen = synth.GeneralPlanted(80, k=8, seed=1)
+    cfg = sg.make_config(sg.SGEP_KIND_GENERAL, sg.SGEP_F64, 24, 80, 80, 100,
+                         schedule=sg.SGEP_SCHED_CONST, eta0=0.02, gamma=0.3, rho=1e-3, nu=30.0,
+                         eps_reg=1e-3, smooth=1)
+    batches = [gen.batch(t, 100) for t in range(1, 31)]
+    res, names = _run_narrow(cfg, oracle.KIND_GENERAL, batches, synth.initial_players(80, 24, 2),
+                             {1, 30}, True)
+    assert names == ("k_fwd", "k_coef", "k_bwd")
+    _check(res, TOL64, TOL64, "f64 general kp32 smooth")
+
+
+@pytest.mark.parametrize("k,adam,b_max", [(16, False, 1024), (20, True, 256)])
+def test_smooth_f32_cca(k, adam, b_max):
+    sg = _sg()
+    dx, dy = 70, 57
+    gen = synth.CCAPlanted(dx, dy, np.linspace(0.9, 0.3, 4), sigma=0.3, seed=k)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, k, dx, dy, b_max,
+                         optimizer=sg.SGEP_ADAM if adam else sg.SGEP_SGD,
+                         schedule=sg.SGEP_SCHED_INV, eta0=2e-3 if adam else 0.3, t0=20.0,
+                         gamma=0.5, rho=1e-2, nu=10.0, smooth=1)
+    sizes = [b_max, b_max - 24, 17, b_max // 2 + 1, 1, b_max] * 3
+    batches = [gen.batch(t, n) for t, n in enumerate(sizes, start=1)]
+    res, names = _run_narrow(cfg, oracle.KIND_CCA, batches, synth.initial_players(dx + dy, k, 3),
+                             {1, len(sizes)}, False)
+    assert names == (("k_fwd", "k_bwdp", "k_bwd") if b_max >= 512 else ("k_fwd", "k_bwd"))
+    m = 5 if adam else 1
+    _check(res, m * TOL32_1, m * TOL32_N, f"f32 cca smooth k={k} adam={adam}")
+
+
+def _bf16_dev(bits):
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(bits).view(np.int16))
+    return t.to("cuda").view(torch.bfloat16).contiguous()
+
+
+def test_smooth_bf16_cca_and_lda():
+    torch = _torch()
+    sg = _sg()
+    # CCA, KP 16, ragged rows
+    dx, dy, k, b = 200, 136, 13, 100
+    gen = synth.CCAPlanted(dx, dy, np.linspace(0.9, 0.3, 6), sigma=0.5, seed=3)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_BF16, k, dx, dy, b,
+                         schedule=sg.SGEP_SCHED_INV, eta0=0.05, t0=100.0, gamma=0.5,
+                         rho=1e-2, nu=10.0, smooth=1)
+    V0 = synth.initial_players(dx + dy, k, 4)
+    s = sg.Solver(cfg, V0)
+    pb = _pb(cfg, oracle.KIND_CCA)
+    st = oracle.State.init(V0)
+    res = []
+    for t in range(1, 31):
+        X, Y = gen.batch(t, b)
+        bx, by = synth.bf16_bits(X), synth.bf16_bits(Y)
+        s.step(_bf16_dev(bx), _bf16_dev(by))
+        oracle.gamma_step(pb, st, synth.bf16_value(bx), synth.bf16_value(by), _eta(cfg, t),
+                          cfg.gamma)
+        if t in (1, 30):
+            res.append((t, s.vectors(), st.V.copy(), s.auxiliary(), st.G.copy(), s.eigvals(),
+                        st.eigvals()))
+    s.close()
+    _check(res, TOLW_1, TOLW_N, "bf16 cca smooth")
+    # LDA, KP 32; within-class variances up to 9 put B-norms where s'(z)^2 reaches ~40
+    # with (rho, nu) = (1e-2, 20), so gamma = 0.03 keeps the z step stable
+    d, c, k, b, eps = 520, 6, 20, 130, 1e-3
+    lg = synth.LDAClasses(d=d, c=c, r=16, seed=5)
+    priors = np.full(c, 1.0 / c)
+    cfg = sg.make_config(sg.SGEP_KIND_LDA, sg.SGEP_BF16, k, d, 0, b,
+                         schedule=sg.SGEP_SCHED_INV, eta0=0.01, t0=100.0, gamma=0.03,
+                         rho=1e-2, nu=20.0, eps_reg=eps, n_classes=c, smooth=1)
+    V0 = synth.initial_players(d, k, 6)
+    s = sg.Solver(cfg, V0, class_means=lg.means, class_priors=priors)
+    pb = _pb(cfg, oracle.KIND_LDA, class_means=lg.means, class_priors=priors)
+    st = oracle.State.init(V0)
+    res = []
+    for t in range(1, 31):
+        X, lab = lg.batch(t, b)
+        bits = synth.bf16_bits(X)
+        s.step(_bf16_dev(bits), torch.from_numpy(lab.astype(np.int32)).cuda())
+        oracle.gamma_step(pb, st, synth.bf16_value(bits), None, _eta(cfg, t), cfg.gamma,
+                          labels=lab)
+        if t in (1, 30):
+            res.append((t, s.vectors(), st.V.copy(), s.auxiliary(), st.G.copy(), s.eigvals(),
+                        st.eigvals()))
+    s.close()
+    _check(res, TOLW_1, TOLW_N, "bf16 lda smooth")
+
+
+def test_smooth_batch_matches_single_and_oracle_and_resumes():
+    torch = _torch()
+    sg = _sg()
+    dims = [64, 130, 13, 300]
+    k, b, T = 8, 100, 6
+    cfg = sg.make_config(sg.SGEP_KIND_GENERAL, sg.SGEP_F32, k, 0, 0, 128,
+                         schedule=sg.SGEP_SCHED_INV, eta0=0.05, t0=50.0, gamma=0.5, rho=1e-2,
+                         nu=30.0, eps_reg=1e-3, smooth=1)
+    gens = [synth.GeneralPlanted(d, k=min(k, d), seed=70 + i) for i, d in enumerate(dims)]
+    V0s = [synth.initial_players(d, k, i) for i, d in enumerate(dims)]
+    host = [[g.batch(t, b) for g in gens] for t in range(1, T + 1)]
+    host = [[(X.astype(np.float32).astype(np.float64), Y.astype(np.float32).astype(np.float64))
+             for X, Y in hs] for hs in host]
+    dev = [[(_dev(X, torch.float32), _dev(Y, torch.float32)) for X, Y in hs] for hs in host]
+    ptrs = [(torch.tensor([x.data_ptr() for x, _ in ds], dtype=torch.int64, device="cuda"),
+             torch.tensor([y.data_ptr() for _, y in ds], dtype=torch.int64, device="cuda"))
+            for ds in dev]
+    bat = sg.BatchSolver(dims, cfg, V0s)
+    singles = [sg.Solver(sg.make_config(sg.SGEP_KIND_GENERAL, sg.SGEP_F32, k, d, d, 128,
+                                        schedule=sg.SGEP_SCHED_INV, eta0=0.05, t0=50.0,
+                                        gamma=0.5, rho=1e-2, nu=30.0, eps_reg=1e-3, smooth=1),
+                         V0s[i]) for i, d in enumerate(dims)]
+    blob = None
+    for t in range(T):
+        bat.step(*ptrs[t], b)
+        for i, (X, Y) in enumerate(dev[t]):
+            singles[i].step(X, Y)
+        if t == 2:
+            blob = singles[3].get_state()
+    bat.sync()
+    for i, d in enumerate(dims):
+        assert np.array_equal(bat.vectors(i), singles[i].vectors()), i
+        pb = oracle.Problem(oracle.KIND_GENERAL, k, d, d, eps_reg=1e-3, rho=1e-2, smooth=True,
+                            nu=30.0)
+        st = oracle.State.init(V0s[i])
+        for t in range(T):
+            X, Y = host[t][i]
+            oracle.gamma_step(pb, st, X, Y, oracle.eta(cfg.schedule, t + 1, 0.05, t0=50.0), 0.5)
+        dv = float(np.abs(bat.vectors(i) - st.V).max())
+        print(f"batch smooth d={d} dV={dv:.2e}", flush=True)
+        assert dv < TOL32_N, (d, dv)
+    # resume instance 3 from its state after 3 iterations (z is part of the state)
+    r = sg.Solver(singles[3].cfg, synth.initial_players(300, k, 9))
+    r.set_state(blob)
+    for t in range(3, T):
+        r.step(*dev[t][3])
+    assert np.array_equal(r.vectors(), singles[3].vectors())
+    # a blob of Alg. 3 is refused by an Alg. 2 handle of otherwise equal configuration
+    plain = sg.Solver(sg.make_config(sg.SGEP_KIND_GENERAL, sg.SGEP_F32, k, 300, 300, 128,
+                                     schedule=sg.SGEP_SCHED_INV, eta0=0.05, t0=50.0, gamma=0.5,
+                                     rho=1e-2, eps_reg=1e-3), V0s[3])
+    with pytest.raises(sg.SgepError):
+        plain.set_state(blob)
+    for s in singles + [r, plain]:
+        s.close()
+    bat.close()
