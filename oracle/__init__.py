@@ -12,7 +12,10 @@ arXiv 2206.04993):
                      Jacobi eigensolve of L^{-1} A L^{-T}).
 * ``gamma_step``     one iteration of Alg. 2 with M = 1, per player, with
                      explicit sums over the minibatch rows; Alg. 3 (smooth
-                     estimate of <v_j, B v_j>, App. G) with Problem.smooth.
+                     estimate of <v_j, B v_j>, App. G) with Problem.smooth;
+                     with Problem.center the minibatch is first centred by
+                     running means of the views (Sec. 1 assumes zero-mean
+                     data; App. H learns mean estimates beside the players).
 * ``alg1_step``      one iteration of Alg. 1 (full batch, exact B y_j).
 * ``utility``        the player utility of Sec. 2 (eq. util_new).
 * ``utility_grad``   its gradient (App. B, gradient lemma).
@@ -162,7 +165,10 @@ class Problem:
     B within-class covariance + eps I).  smooth: Alg. 3 instead of Alg. 2
     (the denominator <v_j, [Bv]_j> clipped at rho is replaced by
     exp(log rho + (log nu - log rho) sigmoid(z_j)), z_j updated at rate
-    gamma toward <v_j, [Bv]_j>); nu bounds lambda_max(B) from above."""
+    gamma toward <v_j, [Bv]_j>); nu bounds lambda_max(B) from above.
+    center (CCA, GENERAL): each view is centred by its running mean before the
+    iteration, and the mean moves toward the minibatch mean at rate gamma
+    afterwards (State.mu_x, State.mu_y, zero at the start)."""
     kind: int
     k: int
     dx: int
@@ -177,6 +183,7 @@ class Problem:
     class_priors: Optional[np.ndarray] = None  # (c,)
     smooth: bool = False
     nu: float = 0.0
+    center: bool = False
 
     @property
     def d(self) -> int:
@@ -211,6 +218,8 @@ class State:
     ema_a: Optional[np.ndarray] = None
     ema_b: Optional[np.ndarray] = None
     z: Optional[np.ndarray] = None
+    mu_x: Optional[np.ndarray] = None
+    mu_y: Optional[np.ndarray] = None
 
     @staticmethod
     def init(V0: np.ndarray, adam: bool = False) -> "State":
@@ -257,6 +266,20 @@ def gamma_step(pb: Problem, st: State, X: np.ndarray, Y: Optional[np.ndarray], e
     X = np.ascontiguousarray(X, dtype=np.float64)
     b = X.shape[0]
     Yc = np.ascontiguousarray(Y if Y is not None else X, dtype=np.float64)
+    if pb.center:
+        # centre each view by the running mean of the iteration's start, then
+        # move the mean toward this minibatch's mean at rate gamma
+        if pb.kind == KIND_LDA:
+            raise NotImplementedError("centring applies to CCA and GENERAL")
+        if st.mu_x is None:
+            st.mu_x = np.zeros(X.shape[1])
+        if st.mu_y is None:
+            st.mu_y = np.zeros(Yc.shape[1])
+        mx, my = st.mu_x, st.mu_y
+        st.mu_x = mx + gamma_t * (X.mean(axis=0) - mx)
+        st.mu_y = my + gamma_t * (Yc.mean(axis=0) - my)
+        X = np.ascontiguousarray(X - mx[None, :])
+        Yc = np.ascontiguousarray(Yc - my[None, :])
     lab = None
     if labels is not None:
         lab_arr = np.ascontiguousarray(labels, dtype=np.int32)

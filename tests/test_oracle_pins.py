@@ -557,3 +557,60 @@ def test_smooth_estimate_tracks_b_norm_and_alg3_converges():
     for t in range(1, 6001):
         oracle.gamma_step_dense(pb, st, A, B, 0.05, 0.1)
     assert oracle.subspace_error(st.V, Vs, B) < 1e-9
+
+
+# --------------------------------------------------------------------------- #
+# Running-mean centring of non-zero-mean streams                              #
+# --------------------------------------------------------------------------- #
+
+def test_centering_removes_a_known_offset_and_tracks_the_mean():
+    """With the running means equal to the streams' offsets, a shifted stream
+    takes exactly the step of the unshifted one without centring (shift
+    invariance of the covariances); the means move toward the minibatch
+    means at rate gamma (closed form after n identical minibatches)."""
+    rng = np.random.default_rng(31)
+    X, Y = _cca_data(rng, b=80)
+    mx, my = rng.normal(3.0, 1.0, 5), rng.normal(-2.0, 1.0, 7)
+    p0 = oracle.Problem(oracle.KIND_CCA, 3, 5, 7, rho=1e-6)
+    p1 = oracle.Problem(oracle.KIND_CCA, 3, 5, 7, rho=1e-6, center=True)
+    V0 = rng.standard_normal((12, 3))
+    s0, s1 = oracle.State.init(V0), oracle.State.init(V0)
+    s1.mu_x, s1.mu_y = mx.copy(), my.copy()
+    _, g0 = oracle.gamma_step(p0, s0, X, Y, 0.2, 0.5, return_grad=True)
+    _, g1 = oracle.gamma_step(p1, s1, X + mx, Y + my, 0.2, 0.5, return_grad=True)
+    assert np.abs(g0 - g1).max() < 1e-12 * np.abs(g0).max()
+    assert np.abs(s0.V - s1.V).max() < 1e-13 and np.abs(s0.G - s1.G).max() < 1e-13
+    # mean update: mu <- mu + gamma (xbar - mu), xbar of the shifted minibatch
+    assert np.allclose(s1.mu_x, mx + 0.5 * (X.mean(0) + mx - mx), atol=1e-14)
+    st = oracle.State.init(V0)
+    xbar = (X + mx).mean(0)
+    for n in range(1, 6):
+        oracle.gamma_step(p1, st, X + mx, Y + my, 0.0, 0.3)
+        assert np.allclose(st.mu_x, (1 - 0.7 ** n) * xbar, atol=1e-13)
+
+
+def test_centered_stochastic_cca_reaches_centered_solution():
+    """A tiny CCA pool shifted by large per-feature offsets: with centring,
+    Alg. 2 reaches 1e-3 subspace error against the exact solution of the
+    pool's covariances (centred); without it the offsets dominate the
+    uncentred second moments and the run misses that solution by far."""
+    gen, pool = synth.tiny_cca_pool(0)
+    rng = np.random.default_rng(32)
+    off_x, off_y = rng.normal(0, 2.0, 8), rng.normal(0, 2.0, 8)
+    PX, PY = pool.X + off_x, pool.Y + off_y
+    Xc, Yc = PX - PX.mean(0), PY - PY.mean(0)
+    pb = oracle.Problem(oracle.KIND_CCA, 4, 8, 8, rho=1e-6, center=True)
+    A, B = oracle.problem_matrices(pb, Xc, Yc)
+    lam, Vs = oracle.gep_topk(A, B, 4)
+    st = oracle.State.init(synth.initial_players(16, 4, 0))
+    plain = oracle.State.init(synth.initial_players(16, 4, 0))
+    p0 = oracle.Problem(oracle.KIND_CCA, 4, 8, 8, rho=1e-6)
+    for t in range(1, 3001):
+        idx = pool.indices(t, 128)
+        eta = oracle.eta(oracle.SCHED_INV, t, 1.0, t0=200.0)
+        oracle.gamma_step(pb, st, PX[idx], PY[idx], eta, 0.5)
+        if t <= 1000:
+            oracle.gamma_step(p0, plain, PX[idx], PY[idx], eta, 0.5)
+    assert oracle.subspace_error(st.V, Vs, B) < 1e-3
+    assert oracle.subspace_error(plain.V, Vs, B) > 1e-2
+    assert np.abs(st.mu_x - PX.mean(0)).max() < 0.1
