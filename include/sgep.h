@@ -116,7 +116,12 @@ typedef struct sgep_config {
                         * starting at 0 and moved at rate gamma by
                         * (<v_j, [Bv]_j> - s_j) s_j (log nu - log rho)
                         * sigmoid(z_j) (1 - sigmoid(z_j)) each iteration) */
-    int32_t reserved;  /* must be 0 */
+    int32_t center;    /* 0: the views are taken as zero-mean (Sec. 1); 1: each
+                        * minibatch view is centred by a running mean before the
+                        * iteration (the mean of the iteration's start), and the
+                        * mean then moves toward the minibatch mean at rate gamma
+                        * (starting at 0).  F64 / F32 CCA and GENERAL single
+                        * handles; SGEP_EUNSUPPORTED elsewhere */
     double nu;         /* Alg. 3: upper bound of lambda_max(B), nu > rho; unused
                         * (any value) with smooth = 0 */
 } sgep_config;
@@ -226,6 +231,12 @@ sgep_status sgep_vectors(sgep_handle *h, int32_t b_normalized, double *out);
 /* The auxiliary variable [Bv] (host, d x k column-major).  Synchronises. */
 sgep_status sgep_auxiliary(sgep_handle *h, double *out);
 
+/* Running means of the views (centring, cfg.center = 1): out receives, on the
+ * host, the dx means of view x followed by the dy means of view y (GENERAL:
+ * dx and dx).  These are the means the next iteration centres with.
+ * Synchronises.  SGEP_EINVAL for a handle without centring. */
+sgep_status sgep_means(sgep_handle *h, double *out);
+
 /* Number of completed iterations.  Synchronises. */
 sgep_status sgep_step_count(sgep_handle *h, int64_t *t);
 
@@ -265,7 +276,8 @@ typedef struct sgep_batch_s sgep_batch;
  *   V0      : host, n pointers to d_i x k column-major starting points
  *   hip_stream : the stream of every instance
  * The initial launch plan is one group with 16-feature backward tiles.
- * Errors: as sgep_init; SGEP_EUNSUPPORTED for another kind or dtype. */
+ * Errors: as sgep_init; SGEP_EUNSUPPORTED for another kind or dtype, or with
+ * centring. */
 sgep_status sgep_batch_init(sgep_batch **out, int32_t n, const int64_t *d, const int64_t *ld,
                             const sgep_config *common, const double *const *V0,
                             void *hip_stream);

@@ -40,7 +40,8 @@ EXPORTS = (
     "sgep_init", "sgep_init_ex", "sgep_step", "sgep_step_lda", "sgep_kernels_per_step",
     "sgep_step_kernel_name",
     "sgep_step_profiled", "sgep_sync", "sgep_eigvals", "sgep_vectors", "sgep_auxiliary",
-    "sgep_step_count", "sgep_state_size", "sgep_get_state", "sgep_set_state", "sgep_destroy",
+    "sgep_step_count", "sgep_means", "sgep_state_size", "sgep_get_state", "sgep_set_state",
+    "sgep_destroy",
     "sgep_status_string", "sgep_version",
     "sgep_batch_init", "sgep_batch_instance", "sgep_batch_step", "sgep_batch_launches",
     "sgep_batch_step_profiled", "sgep_batch_plan", "sgep_batch_set_plan", "sgep_batch_tune",
@@ -59,7 +60,7 @@ class sgep_config(ctypes.Structure):
         ("rho", ctypes.c_double), ("eps_reg", ctypes.c_double),
         ("adam_b1", ctypes.c_double), ("adam_b2", ctypes.c_double),
         ("adam_eps", ctypes.c_double), ("seed", ctypes.c_uint64),
-        ("smooth", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nu", ctypes.c_double),
+        ("smooth", ctypes.c_int32), ("center", ctypes.c_int32), ("nu", ctypes.c_double),
     ]
 
 
@@ -69,11 +70,12 @@ def make_config(kind: int, dtype: int, k: int, dx: int, dy: int, b_max: int, *,
                 T: float = 1.0, gamma: float = 1.0, rho: float = 1e-6, eps_reg: float = 0.0,
                 adam_b1: float = 0.9, adam_b2: float = 0.999, adam_eps: float = 1e-8,
                 n_classes: int = 0, seed: int = 0, smooth: int = 0,
-                nu: float = 0.0) -> sgep_config:
-    """smooth = 1 selects Alg. 3 (smooth estimate between rho and nu)."""
+                nu: float = 0.0, center: int = 0) -> sgep_config:
+    """smooth = 1 selects Alg. 3 (smooth estimate between rho and nu);
+    center = 1 centres the views by running means."""
     return sgep_config(kind, dtype, k, optimizer, schedule, n_classes, dx, dy, b_max, eta0,
                        eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps, seed,
-                       smooth, 0, nu)
+                       smooth, center, nu)
 
 
 class sgep_init_aux(ctypes.Structure):
@@ -125,6 +127,7 @@ def load() -> ctypes.CDLL:
     lib.sgep_vectors.argtypes = [vp, i32, dp]
     lib.sgep_auxiliary.argtypes = [vp, dp]
     lib.sgep_step_count.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.sgep_means.argtypes = [vp, dp]
     lib.sgep_state_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.sgep_get_state.argtypes = [vp, vp, ctypes.c_size_t]
     lib.sgep_set_state.argtypes = [vp, vp, ctypes.c_size_t]
@@ -285,6 +288,14 @@ def sgep_auxiliary(h, d: int, k: int) -> np.ndarray:
     return out.T.copy()
 
 
+def sgep_means(h, n: int) -> np.ndarray:
+    """Running means of the views (centring): n = dx + dy (GENERAL: 2 dx)."""
+    out = np.zeros(n)
+    _check(load().sgep_means(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "sgep_means")
+    return out
+
+
 def sgep_step_count(h) -> int:
     t = ctypes.c_int64()
     _check(load().sgep_step_count(h, ctypes.byref(t)), "sgep_step_count")
@@ -423,6 +434,13 @@ class Solver:
 
     def step_count(self):
         return sgep_step_count(self.h)
+
+    def means(self):
+        """(mu_x, mu_y): the running means of the views (centring only)."""
+        c = self.cfg
+        dy = c.dy if c.kind == SGEP_KIND_CCA else c.dx
+        m = sgep_means(self.h, c.dx + dy)
+        return m[:c.dx], m[c.dx:]
 
     def get_state(self):
         return sgep_get_state(self.h)

@@ -54,6 +54,7 @@ struct sgep_handle_s {
     Coef *coef = nullptr;
     void *cpre = nullptr; // coefficient block of the iteration (k_coef)
     int nsplit = 1;        // row slices of the backward products (1: one pass)
+    void *mu = nullptr;    // running means of the views (centring): 2 ldv elements
     void *bpart = nullptr; // the slices' partial products (nsplit > 1)
     int n_tx = 0, n_ty = 0, n_tiles = 0;
     int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
@@ -87,7 +88,8 @@ uint64_t config_hash(const sgep_config &c)
 {
     // hash every field explicitly (no struct padding in the digest)
     uint64_t h = 1469598103934665603ull;
-    const int32_t ints[] = {c.kind, c.dtype, c.k, c.optimizer, c.schedule, c.n_classes, c.smooth};
+    const int32_t ints[] = {c.kind,      c.dtype,    c.k,      c.optimizer,
+                            c.schedule,  c.n_classes, c.smooth, c.center};
     const int64_t dims[] = {c.dx, c.dy, c.b_max};
     const double reals[] = {c.eta0, c.eta_T, c.t0, c.t_c, c.T, c.gamma, c.rho, c.eps_reg,
                             c.adam_b1, c.adam_b2, c.adam_eps, c.smooth ? c.nu : 0.0};
@@ -107,7 +109,8 @@ void free_all(sgep_handle *h)
 {
     void *ptrs[] = {h->V,  h->G,        h->Am,      h->As,    h->P,  h->Q,    h->gram_part,
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
-                    h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart};
+                    h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
+                    h->mu};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -154,8 +157,10 @@ sgep_status check_cfg(const sgep_config *c)
         return SGEP_EUNSUPPORTED;
     if (!(c->eta0 >= 0.0) || !(c->gamma > 0.0 && c->gamma <= 1.0) || !(c->rho >= 0.0))
         return SGEP_EINVAL;
-    if ((c->smooth != 0 && c->smooth != 1) || c->reserved != 0)
+    if ((c->smooth != 0 && c->smooth != 1) || (c->center != 0 && c->center != 1))
         return SGEP_EINVAL;
+    if (c->center && (narrow || lda))
+        return SGEP_EUNSUPPORTED; // centring: F64 / F32 CCA and GENERAL
     if (c->smooth && !(c->rho > 0.0 && c->nu > c->rho && std::isfinite(c->nu)))
         return SGEP_EINVAL;
     if (c->kind == SGEP_KIND_CCA && c->eps_reg != 0.0)
@@ -224,7 +229,7 @@ bool split_mode(const sgep_config &c, int mb, int n_tiles)
     return c.kind == SGEP_KIND_CCA && mb == 1 && n_tiles <= 128 && c.b_max >= 512;
 }
 
-template <typename T, int KP, int MB, int MODE>
+template <typename T, int KP, int MB, int MODE, bool C>
 void launch_bwd(sgep_handle *h, const StepArgs &a, hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 gb(h->n_tiles);
@@ -233,17 +238,20 @@ void launch_bwd(sgep_handle *h, const StepArgs &a, hipEvent_t e0, hipEvent_t e1)
     const int nt = MODE == sgep::kModeSpec ? 2 * sgep::kNT : sgep::kNT;
     using namespace sgep;
     if (cca && !adam)
-        launch_timed(k_bwd<T, KP, MB, kKindCCA, kOptSGD, MODE>, gb, h->stream, e0, e1, a, nt);
+        launch_timed(k_bwd<T, KP, MB, kKindCCA, kOptSGD, MODE, C>, gb, h->stream, e0, e1, a, nt);
     else if (cca && adam)
-        launch_timed(k_bwd<T, KP, MB, kKindCCA, kOptAdam, MODE>, gb, h->stream, e0, e1, a, nt);
+        launch_timed(k_bwd<T, KP, MB, kKindCCA, kOptAdam, MODE, C>, gb, h->stream, e0, e1, a, nt);
     else if (!adam)
-        launch_timed(k_bwd<T, KP, MB, kKindGeneral, kOptSGD, MODE>, gb, h->stream, e0, e1, a, nt);
+        launch_timed(k_bwd<T, KP, MB, kKindGeneral, kOptSGD, MODE, C>, gb, h->stream, e0, e1, a,
+                     nt);
     else
-        launch_timed(k_bwd<T, KP, MB, kKindGeneral, kOptAdam, MODE>, gb, h->stream, e0, e1, a, nt);
+        launch_timed(k_bwd<T, KP, MB, kKindGeneral, kOptAdam, MODE, C>, gb, h->stream, e0, e1, a,
+                     nt);
 }
 
-template <typename T, int KP>
-sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
+// one iteration; C: the views are centred by their running means
+template <typename T, int KP, bool C>
+sgep_status launch_step_c(sgep_handle *h, const StepArgs &a, void *const *events)
 {
     const dim3 gf(a.n_fwd + 1); // + the norm-totals workgroup
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -254,21 +262,22 @@ sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
             ev[i] = (hipEvent_t)events[i];
     const bool cca = h->cfg.kind == SGEP_KIND_CCA;
     if (cca)
-        launch_timed(sgep::k_fwd<T, KP, sgep::kKindCCA>, gf, h->stream, ev[0], ev[1], a);
+        launch_timed(sgep::k_fwd<T, KP, sgep::kKindCCA, C>, gf, h->stream, ev[0], ev[1], a);
     else
-        launch_timed(sgep::k_fwd<T, KP, sgep::kKindGeneral>, gf, h->stream, ev[0], ev[1], a);
+        launch_timed(sgep::k_fwd<T, KP, sgep::kKindGeneral, C>, gf, h->stream, ev[0], ev[1], a);
     constexpr int MBW = mb_wide<T>(KP);
     constexpr bool can_spec = KP * (int)sizeof(T) <= 128; // spec_mode's player-tile bound
     if (split) {
         const dim3 gp(h->n_tiles * h->nsplit + 1); // + the coefficient workgroup
         if (cca)
-            launch_timed(sgep::k_bwdp<T, KP, sgep::kKindCCA>, gp, h->stream, ev[2], ev[3], a);
+            launch_timed(sgep::k_bwdp<T, KP, sgep::kKindCCA, C>, gp, h->stream, ev[2], ev[3], a);
         else
-            launch_timed(sgep::k_bwdp<T, KP, sgep::kKindGeneral>, gp, h->stream, ev[2], ev[3], a);
-        launch_bwd<T, KP, 1, sgep::kModeFin>(h, a, ev[4], ev[5]);
+            launch_timed(sgep::k_bwdp<T, KP, sgep::kKindGeneral, C>, gp, h->stream, ev[2], ev[3],
+                         a);
+        launch_bwd<T, KP, 1, sgep::kModeFin, C>(h, a, ev[4], ev[5]);
     } else if (spec) {
         if constexpr (can_spec)
-            launch_bwd<T, KP, 1, sgep::kModeSpec>(h, a, ev[2], ev[3]);
+            launch_bwd<T, KP, 1, sgep::kModeSpec, C>(h, a, ev[2], ev[3]);
     } else {
         if (cca)
             launch_timed(sgep::k_coef<T, KP, sgep::kKindCCA>, dim3(1), h->stream, ev[2], ev[3], a);
@@ -276,12 +285,19 @@ sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
             launch_timed(sgep::k_coef<T, KP, sgep::kKindGeneral>, dim3(1), h->stream, ev[2], ev[3],
                          a);
         if (h->mb == 1)
-            launch_bwd<T, KP, 1, sgep::kModePre>(h, a, ev[4], ev[5]);
+            launch_bwd<T, KP, 1, sgep::kModePre, C>(h, a, ev[4], ev[5]);
         else
-            launch_bwd<T, KP, MBW, sgep::kModePre>(h, a, ev[4], ev[5]);
+            launch_bwd<T, KP, MBW, sgep::kModePre, C>(h, a, ev[4], ev[5]);
     }
     HIPCHK(hipGetLastError());
     return SGEP_OK;
+}
+
+template <typename T, int KP>
+sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
+{
+    return h->cfg.center ? launch_step_c<T, KP, true>(h, a, events)
+                         : launch_step_c<T, KP, false>(h, a, events);
 }
 
 // kernels of one iteration of a narrow handle
@@ -695,6 +711,7 @@ StateLayout state_layout(const sgep_handle *h)
         L.add(h->Am, st);
         L.add(h->As, st);
         L.add(h->stat_part, (size_t)h->W * h->lds * sizeof(double));
+        L.add(h->mu, (size_t)2 * h->ldv * h->esz);
     }
     return L;
 }
@@ -816,8 +833,10 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     alloc(&h->cpre, (size_t)(kp * kp + 3 * kp + 4) * h->esz);
     if (split_mode(*cfg, h->mb, h->n_tiles)) {
         h->nsplit = kSplit;
-        alloc(&h->bpart, (size_t)h->n_tiles * kSplit * 2 * h->ft * kp * h->esz);
+        alloc(&h->bpart, (size_t)h->n_tiles * kSplit * (2 * h->ft * kp + 2 * h->ft) * h->esz);
     }
+    if (cfg->center)
+        alloc(&h->mu, (size_t)2 * h->ldv * h->esz);
     if (!ok) {
         free_all(h);
         delete h;
@@ -832,6 +851,8 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     if (h->Am)
         hok = hok && hipMemsetAsync(h->Am, 0, st_bytes, h->stream) == hipSuccess &&
               hipMemsetAsync(h->As, 0, st_bytes, h->stream) == hipSuccess;
+    if (h->mu)
+        hok = hok && hipMemsetAsync(h->mu, 0, (size_t)2 * h->ldv * h->esz, h->stream) == hipSuccess;
     // quad-interleaved with padded views: (feature f, player i) at
     // (sf / 4) 4 KP + 4 i + sf % 4, sf = storage position of f
     std::vector<unsigned char> host(st_bytes, 0);
@@ -896,6 +917,7 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.coef = h->coef;
     a.cpre = h->cpre;
     a.bpart = h->bpart;
+    a.mu = h->mu;
     a.nsplit = h->nsplit;
     a.schedule = h->cfg.schedule;
     a.eta0 = h->cfg.eta0;
@@ -1062,6 +1084,30 @@ sgep_status sgep_auxiliary(sgep_handle *h, double *out)
     return readout(h, h->G, 0, out);
 }
 
+sgep_status sgep_means(sgep_handle *h, double *out)
+{
+    if (!h || !out || !h->mu)
+        return SGEP_EINVAL;
+    if (h->poisoned)
+        return SGEP_EPOISONED;
+    const int64_t n = 2 * h->ldv;
+    std::vector<unsigned char> buf((size_t)n * h->esz);
+    HIPCHK(hipMemcpyAsync(buf.data(), h->mu, buf.size(), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    auto at = [&](int64_t i) {
+        return h->esz == sizeof(double) ? ((const double *)buf.data())[i]
+                                        : (double)((const float *)buf.data())[i];
+    };
+    // storage: CCA view x at 0, view y at dxp; GENERAL view x at 0, view y at ldv
+    const int64_t dx = h->cfg.dx, dy = h->cfg.kind == SGEP_KIND_CCA ? h->cfg.dy : h->cfg.dx;
+    const int64_t oy = h->cfg.kind == SGEP_KIND_CCA ? h->dxp : h->ldv;
+    for (int64_t f = 0; f < dx; ++f)
+        out[f] = at(f);
+    for (int64_t f = 0; f < dy; ++f)
+        out[dx + f] = at(oy + f);
+    return SGEP_OK;
+}
+
 sgep_status sgep_step_count(sgep_handle *h, int64_t *t)
 {
     if (!h || !t)
@@ -1088,7 +1134,7 @@ sgep_status sgep_state_size(const sgep_handle *h, size_t *bytes)
     }
     const size_t st = (size_t)h->ldv * h->kp * h->esz;
     *bytes = sizeof(StateHeader) + sizeof(Coef) + st * (h->Am ? 4 : 2) +
-             (size_t)h->W * h->lds * sizeof(double);
+             (size_t)h->W * h->lds * sizeof(double) + (h->mu ? 2 * h->ldv * h->esz : 0);
     return SGEP_OK;
 }
 
@@ -1460,6 +1506,8 @@ sgep_status sgep_batch_init(sgep_batch **out, int32_t n, const int64_t *d, const
         return SGEP_EUNSUPPORTED;
     if (common->dtype != SGEP_F32 && common->dtype != SGEP_F64)
         return SGEP_EUNSUPPORTED;
+    if (common->center)
+        return SGEP_EUNSUPPORTED; // centring: single handles only
     for (int i = 0; i < n; ++i) {
         if (!V0[i])
             return SGEP_EINVAL;

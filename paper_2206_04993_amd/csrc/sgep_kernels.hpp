@@ -124,7 +124,10 @@ struct StepArgs {
     double *stat_tot;        // [W]: reduced stat_part of the state entering this iteration
     Coef *coef;
     void *cpre;              // coefficient block of the iteration (kModePre, kModeFin)
-    void *bpart;             // [tile][split][2][FT * KP] partial products (kModePart)
+    void *bpart;             // [tile][split][2 FT KP + 2 FT] partial products and
+                             // centred column sums (kModePart)
+    void *mu;                // running means of the views (centring): view x (CCA:
+                             // both views) at storage positions, GENERAL view y at +ldv
     int32_t nsplit;          // row slices of the backward products (kModePart)
     int32_t schedule;
     int32_t smooth;          // Alg. 3 estimate of v_j^T B v_j instead of the clip
@@ -251,16 +254,17 @@ template <> struct VecLoad<double, 4> {
 // loaded from a valid chunk and zeroed; the ragged last chunk runs masked.
 // `row` is a valid row index; rows past the minibatch are zeroed through rv.
 // ---------------------------------------------------------------------------
-template <typename T, int KP>
+template <typename T, int KP, bool CENTER = false>
 __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t ldx, int64_t nf,
                                          int64_t row, bool rv, bool vec_ok,
                                          const SGEP_G T *__restrict__ VQ,
-                                         int lane, int w, typename Mfma<T>::acc (*acc)[KP / 16])
+                                         int lane, int w, typename Mfma<T>::acc (*acc)[KP / 16],
+                                         const SGEP_G T *__restrict__ mu = nullptr)
 {
     constexpr int VEC = 16 / (int)sizeof(T);
     constexpr int CH = 4 * VEC;
     constexpr int NB = KP / 16;
-    constexpr int U = 8 / NB;
+    constexpr int U = (CENTER ? 4 : 8) / NB;
     const int kk = lane >> 4, n = lane & 15;
     const int64_t nch = (nf + CH - 1) / CH;
     const int64_t nfull = nf / CH; // chunks whose features are all valid
@@ -268,7 +272,7 @@ __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t
     const int64_t cf = c1 < nfull ? c1 : nfull;
     const SGEP_G T *xr = X + row * ldx;
     for (int64_t c = c0; c < cf; c += U) {
-        T xv[U][VEC];
+        T xv[U][VEC], mv[U][VEC];
         T bv[U][NB][VEC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -281,6 +285,8 @@ __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t
                 for (int j = 0; j < VEC; ++j)
                     xv[u][j] = xr[fb + j];
             }
+            if (CENTER)
+                VecLoad<T, VEC>::run(mu + fb, mv[u]);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
                 VecLoad<T, VEC>::run(VQ + qidx<KP>(fb, nb * 16 + n), bv[u][nb]);
@@ -293,7 +299,7 @@ __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t
             const bool ok = rv && (c + u < cf);
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
-                const T xs = ok ? xv[u][j] : T(0);
+                const T xs = ok ? (CENTER ? xv[u][j] - mv[u][j] : xv[u][j]) : T(0);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     acc[j & 1][nb] = Mfma<T>::fma(xs, bv[u][nb][j], acc[j & 1][nb]);
@@ -307,7 +313,7 @@ __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t
             const int64_t fe = fb + j;
             const bool fv = fe < nf;
             const int64_t fc = fv ? fe : nf - 1;
-            const T xs = (rv && fv) ? xr[fc] : T(0);
+            const T xs = (rv && fv) ? (CENTER ? xr[fc] - mu[fc] : xr[fc]) : T(0);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const T bvv = fv ? VQ[qidx<KP>(fc, nb * 16 + n)] : T(0);
@@ -325,19 +331,21 @@ __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t
 // run-time one makes the compiler drain all loads in flight around it.
 // LOWREG halves the chunks per batch (fewer registers, more workgroups per
 // CU, for launches with many workgroups); the accumulation order is the same.
-template <typename T, int KP, bool SAMEV, bool LOWREG>
+template <typename T, int KP, bool SAMEV, bool LOWREG, bool CENTER = false>
 __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_t ldx,
                                           const SGEP_G T *__restrict__ Y, int64_t ldy, int64_t nf,
                                           int64_t row, bool rv, bool vec_ok,
                                           const SGEP_G T *__restrict__ VQx,
                                           const SGEP_G T *__restrict__ VQy,
                                           int lane, int w, typename Mfma<T>::acc (*accx)[KP / 16],
-                                          typename Mfma<T>::acc (*accy)[KP / 16])
+                                          typename Mfma<T>::acc (*accy)[KP / 16],
+                                          const SGEP_G T *__restrict__ mux = nullptr,
+                                          const SGEP_G T *__restrict__ muy = nullptr)
 {
     constexpr int VEC = 16 / (int)sizeof(T);
     constexpr int CH = 4 * VEC;
     constexpr int NB = KP / 16;
-    constexpr int U = (LOWREG ? 4 : 8) / NB;
+    constexpr int U = ((LOWREG || CENTER) ? 4 : 8) / NB;
     const int kk = lane >> 4, n = lane & 15;
     const int64_t nch = (nf + CH - 1) / CH;
     const int64_t nfull = nf / CH;
@@ -346,7 +354,7 @@ __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_
     const SGEP_G T *xr = X + row * ldx;
     const SGEP_G T *yr = Y + row * ldy;
     for (int64_t c = c0; c < cf; c += U) {
-        T xv[U][VEC], yv[U][VEC];
+        T xv[U][VEC], yv[U][VEC], mx[U][VEC], my[U][VEC];
         T bx[U][NB][VEC], by[U][NB][VEC];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -362,6 +370,10 @@ __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_
                     yv[u][j] = yr[fb + j];
                 }
             }
+            if (CENTER) {
+                VecLoad<T, VEC>::run(mux + fb, mx[u]);
+                VecLoad<T, VEC>::run(muy + fb, my[u]);
+            }
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 VecLoad<T, VEC>::run(VQx + qidx<KP>(fb, nb * 16 + n), bx[u][nb]);
@@ -375,8 +387,8 @@ __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_
             const bool ok = rv && (c + u < cf);
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
-                const T xs = ok ? xv[u][j] : T(0);
-                const T ys = ok ? yv[u][j] : T(0);
+                const T xs = ok ? (CENTER ? xv[u][j] - mx[u][j] : xv[u][j]) : T(0);
+                const T ys = ok ? (CENTER ? yv[u][j] - my[u][j] : yv[u][j]) : T(0);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     accx[j & 1][nb] = Mfma<T>::fma(xs, bx[u][nb][j], accx[j & 1][nb]);
@@ -393,8 +405,8 @@ __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_
             const int64_t fe = fb + j;
             const bool fv = fe < nf;
             const int64_t fc = fv ? fe : nf - 1;
-            const T xs = (rv && fv) ? xr[fc] : T(0);
-            const T ys = (rv && fv) ? yr[fc] : T(0);
+            const T xs = (rv && fv) ? (CENTER ? xr[fc] - mux[fc] : xr[fc]) : T(0);
+            const T ys = (rv && fv) ? (CENTER ? yr[fc] - muy[fc] : yr[fc]) : T(0);
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const T bxv = fv ? VQx[qidx<KP>(fc, nb * 16 + n)] : T(0);
@@ -409,7 +421,7 @@ __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_
 // Forward body: workgroup blk takes rows 16 blk .. 16 blk + 15; the four waves
 // split the features.  Workgroup blk == n_fwd reduces the norm / parent
 // partials of the current state and advances the step counter.
-template <typename T, int KP, int KIND, bool LOWREG = false>
+template <typename T, int KP, int KIND, bool LOWREG = false, bool CENTER = false>
 __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
 {
     typedef typename Mfma<T>::acc Acc;
@@ -448,12 +460,17 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     // view y's players start at feature dxp (a multiple of 4) for CCA
     const SGEP_G T *VQy = KIND == kKindCCA ? VQ + a.dxp * KP : VQ;
     const int64_t nfy = KIND == kKindCCA ? a.dy : a.dx;
+    // centring: running means at the views' storage positions (GENERAL: view
+    // y's at +ldv)
+    const SGEP_G T *mux = (const SGEP_G T *)a.mu;
+    const SGEP_G T *muy = CENTER ? mux + (KIND == kKindCCA ? a.dxp : a.ldv) : nullptr;
     if (nfy == a.dx) {
-        fwd_view2<T, KP, KIND != kKindCCA, LOWREG>(X, a.ldx, Y, a.ldy, a.dx, row, rv, vec_ok, VQ,
-                                                   VQy, lane, w, aP, aQ);
+        fwd_view2<T, KP, KIND != kKindCCA, LOWREG, CENTER>(X, a.ldx, Y, a.ldy, a.dx, row, rv,
+                                                           vec_ok, VQ, VQy, lane, w, aP, aQ,
+                                                           mux, muy);
     } else {
-        fwd_view<T, KP>(X, a.ldx, a.dx, row, rv, vec_ok, VQ, lane, w, aP);
-        fwd_view<T, KP>(Y, a.ldy, nfy, row, rv, vec_ok, VQy, lane, w, aQ);
+        fwd_view<T, KP, CENTER>(X, a.ldx, a.dx, row, rv, vec_ok, VQ, lane, w, aP, mux);
+        fwd_view<T, KP, CENTER>(Y, a.ldy, nfy, row, rv, vec_ok, VQy, lane, w, aQ, muy);
     }
 
     // sum the accumulator sets and the four waves' tiles in a fixed order
@@ -514,10 +531,10 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     }
 }
 
-template <typename T, int KP, int KIND>
+template <typename T, int KP, int KIND, bool CENTER = false>
 __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 {
-    fwd_body<T, KP, KIND>(a, blockIdx.x);
+    fwd_body<T, KP, KIND, false, CENTER>(a, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -721,7 +738,8 @@ __global__ void __launch_bounds__(kNT) k_coef(StepArgs a)
 // MODE kModeFin: four waves; the products are the fixed-order sum of the
 // slices' partials, the coefficient block comes from k_coef.
 // ---------------------------------------------------------------------------
-template <typename T, int KP, int MB, int KIND, int OPT, int MODE, bool LOWREG = false>
+template <typename T, int KP, int MB, int KIND, int OPT, int MODE, bool LOWREG = false,
+          bool CENTER = false>
 __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split = 0)
 {
     typedef typename Mfma<T>::acc Acc;
@@ -747,6 +765,11 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
     __shared__ T red[4][FT * KP];
     __shared__ T avt[FT * KP], bvt[FT * KP], gt[FT * KP];
     __shared__ CoefTile<T, KP> C;
+    // centring: per (wave, lane group) column sums of the centred views, then
+    // their fixed-order totals (A side, B side)
+    __shared__ T csum[2][CENTER ? 16 : 1][CENTER ? FT : 1];
+    __shared__ T ctot[2][CENTER ? FT : 1];
+    constexpr int PSTR = 2 * FT * KP + 2 * FT; // partial block of one (tile, slice)
     __shared__ double gs[SPEC ? W : 1], ss[SPEC ? W : 1], Td[SPEC ? KP * KP : 1];
     __shared__ double dInv[KP], dS[KP], ema[2 * KP];
 
@@ -783,6 +806,10 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
     SGEP_G T *VQ = (SGEP_G T *)a.V, *GQ = (SGEP_G T *)a.G;
     SGEP_G T *Am = (SGEP_G T *)a.Am, *As = (SGEP_G T *)a.As;
     const int64_t tbase = (fbase + f0) * KP; // first element of this tile's block
+    // centring: running means of the A-side view (Xa) and the B-side view (Xb)
+    SGEP_G T *muA = (SGEP_G T *)a.mu + (KIND == kKindCCA ? fbase : a.ldv);
+    SGEP_G T *muB = (SGEP_G T *)a.mu + fbase;
+    T ma[MB], mbm[MB], sa[MB], sb[MB]; // lane's means; its sums of the centred values
     T pv[EPT], pg[EPT], pm[EPT], ps[EPT];
     T cpr[CPT]; // kModePre: this thread's elements of the coefficient block
     typedef typename Mfma<T>::acc Acc2;
@@ -829,6 +856,15 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
         fcl[jm] = fok[jm] ? fs + jm : nf - 1;
     }
     const bool vrun = vec_ok && fs + MB <= nf;
+    // centring: running means of this lane's features
+#pragma unroll
+    for (int jm = 0; jm < MB; ++jm) {
+        ma[jm] = mbm[jm] = sa[jm] = sb[jm] = T(0);
+        if (CENTER && !FIN) {
+            ma[jm] = muA[fcl[jm]];
+            mbm[jm] = KIND == kKindCCA ? ma[jm] : muB[fcl[jm]];
+        }
+    }
     const SGEP_G T *pa[NB], *pb[NB]; // player (nb*16 + m): rows r..r+3 at p[r * KP]
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
@@ -883,8 +919,16 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
 #pragma unroll
                 for (int jm = 0; jm < MB; ++jm) {
                     const bool ok = gv && fok[jm];
-                    const T va = ok ? xa[u][j][jm] : T(0);
-                    const T vb = ok ? (KIND == kKindCCA ? xa[u][j][jm] : xb[u][j][jm]) : T(0);
+                    const T va = ok ? (CENTER ? xa[u][j][jm] - ma[jm] : xa[u][j][jm]) : T(0);
+                    const T vb = KIND == kKindCCA
+                                     ? va
+                                     : (ok ? (CENTER ? xb[u][j][jm] - mbm[jm] : xb[u][j][jm])
+                                           : T(0));
+                    if (CENTER) {
+                        sa[jm] += va;
+                        if (KIND != kKindCCA)
+                            sb[jm] += vb;
+                    }
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) {
                         aA[j & 1][jm][nb] = Mfma<T>::fma(va, ba[u][nb][j], aA[j & 1][jm][nb]);
@@ -903,8 +947,19 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
 #pragma unroll
             for (int jm = 0; jm < MB; ++jm) {
                 const bool ok = rv && fok[jm];
-                const T va = ok ? Xa[row * lda + fcl[jm]] : T(0);
-                const T vb = ok ? (KIND == kKindCCA ? va : Xb[row * ldb + fcl[jm]]) : T(0);
+                const T va = ok ? (CENTER ? Xa[row * lda + fcl[jm]] - ma[jm]
+                                          : Xa[row * lda + fcl[jm]])
+                                : T(0);
+                const T vb = KIND == kKindCCA
+                                 ? va
+                                 : (ok ? (CENTER ? Xb[row * ldb + fcl[jm]] - mbm[jm]
+                                                 : Xb[row * ldb + fcl[jm]])
+                                       : T(0));
+                if (CENTER) {
+                    sa[jm] += va;
+                    if (KIND != kKindCCA)
+                        sb[jm] += vb;
+                }
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     const T qa = rv ? opA[qidx<KP>(row, nb * 16 + m)] : T(0);
@@ -940,6 +995,13 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
                 for (int r = 0; r < 4; ++r)
                     red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
             }
+        if constexpr (CENTER) {
+#pragma unroll
+            for (int jm = 0; jm < MB; ++jm) {
+                csum[0][4 * w + kk][MB * m + jm] = sa[jm];
+                csum[1][4 * w + kk][MB * m + jm] = sb[jm];
+            }
+        }
     }
     if (main_w) {
         if (!SPEC && !PART) {
@@ -957,17 +1019,40 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
     if (main_w && !FIN) {
         for (int e = tid; e < FT * KP; e += kNT)
             avt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
-    } else if (FIN) {
-        // products = fixed-order sum of the row slices' partials
-        const SGEP_G T *bp = (const SGEP_G T *)a.bpart + (int64_t)tile * a.nsplit * 2 * FT * KP;
-        for (int e = tid; e < FT * KP; e += kNT) {
-            T sa = bp[e], sb = bp[FT * KP + e];
-            for (int sp = 1; sp < a.nsplit; ++sp) {
-                sa += bp[(int64_t)sp * 2 * FT * KP + e];
-                sb += bp[(int64_t)sp * 2 * FT * KP + FT * KP + e];
+        if constexpr (CENTER) {
+            if (tid < FT) {
+                T t0 = T(0), t1 = T(0);
+                for (int q = 0; q < 16; ++q) {
+                    t0 += csum[0][q][tid];
+                    t1 += csum[1][q][tid];
+                }
+                ctot[0][tid] = t0;
+                ctot[1][tid] = t1;
             }
-            avt[e] = sa;
-            bvt[e] = sb;
+        }
+    } else if (FIN) {
+        // products (and centred column sums) = fixed-order sums of the row
+        // slices' partials
+        const SGEP_G T *bp = (const SGEP_G T *)a.bpart + (int64_t)tile * a.nsplit * PSTR;
+        for (int e = tid; e < FT * KP; e += kNT) {
+            T pa = bp[e], pb2 = bp[FT * KP + e];
+            for (int sp = 1; sp < a.nsplit; ++sp) {
+                pa += bp[(int64_t)sp * PSTR + e];
+                pb2 += bp[(int64_t)sp * PSTR + FT * KP + e];
+            }
+            avt[e] = pa;
+            bvt[e] = pb2;
+        }
+        if constexpr (CENTER) {
+            if (tid < FT) {
+                T t0 = bp[2 * FT * KP + tid], t1 = bp[2 * FT * KP + FT + tid];
+                for (int sp = 1; sp < a.nsplit; ++sp) {
+                    t0 += bp[(int64_t)sp * PSTR + 2 * FT * KP + tid];
+                    t1 += bp[(int64_t)sp * PSTR + 2 * FT * KP + FT + tid];
+                }
+                ctot[0][tid] = t0;
+                ctot[1][tid] = t1;
+            }
         }
     } else {
         coef_T<T, KP>(a, gs, dInv, dS, C.Tl, Td, tid - kNT, kNT);
@@ -1002,10 +1087,16 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
     if (PART) {
         // this slice's products for the finishing pass
         __syncthreads();
-        SGEP_G T *bp = (SGEP_G T *)a.bpart + ((int64_t)tile * a.nsplit + split) * 2 * FT * KP;
+        SGEP_G T *bp = (SGEP_G T *)a.bpart + ((int64_t)tile * a.nsplit + split) * PSTR;
         for (int e = tid; e < FT * KP; e += kNT) {
             bp[e] = avt[e];
             bp[FT * KP + e] = bvt[e];
+        }
+        if constexpr (CENTER) {
+            if (tid < FT) {
+                bp[2 * FT * KP + tid] = ctot[0][tid];
+                bp[2 * FT * KP + FT + tid] = ctot[1][tid];
+            }
         }
         return;
     }
@@ -1081,12 +1172,22 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
         }
         sout[(int64_t)tile * W + e] = s;
     }
+    // centring: the running means of this tile's features move toward the
+    // minibatch means, mu += gamma (xbar - mu) = mu + (gamma / b) sum_r (x_r - mu)
+    if constexpr (CENTER) {
+        if (tid < FT && f0 + tid < nf) {
+            const T g = (T)(a.gamma / (double)a.b);
+            muA[f0 + tid] = muA[f0 + tid] + g * ctot[0][tid];
+            if (KIND != kKindCCA)
+                muB[f0 + tid] = muB[f0 + tid] + g * ctot[1][tid];
+        }
+    }
 }
 
-template <typename T, int KP, int MB, int KIND, int OPT, int MODE>
+template <typename T, int KP, int MB, int KIND, int OPT, int MODE, bool CENTER = false>
 __global__ void __launch_bounds__(MODE == kModeSpec ? 2 * kNT : kNT) k_bwd(StepArgs a)
 {
-    bwd_body<T, KP, MB, KIND, OPT, MODE>(a, xcd_tile(blockIdx.x, gridDim.x));
+    bwd_body<T, KP, MB, KIND, OPT, MODE, false, CENTER>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Row-split backward, first pass: workgroup 0 computes the iteration's
@@ -1094,7 +1195,7 @@ __global__ void __launch_bounds__(MODE == kModeSpec ? 2 * kNT : kNT) k_bwd(StepA
 // more compute one row slice of one 16-feature tile each (block b >= 1:
 // tile (b - 1) / nsplit, slice (b - 1) % nsplit).  The second pass is k_bwd
 // with kModeFin.
-template <typename T, int KP, int KIND>
+template <typename T, int KP, int KIND, bool CENTER = false>
 __global__ void __launch_bounds__(kNT) k_bwdp(StepArgs a)
 {
     if (blockIdx.x == 0) {
@@ -1102,7 +1203,7 @@ __global__ void __launch_bounds__(kNT) k_bwdp(StepArgs a)
         return;
     }
     const int b = blockIdx.x - 1;
-    bwd_body<T, KP, 1, KIND, kOptSGD, kModePart>(a, b / a.nsplit, b % a.nsplit);
+    bwd_body<T, KP, 1, KIND, kOptSGD, kModePart, false, CENTER>(a, b / a.nsplit, b % a.nsplit);
 }
 
 // ---------------------------------------------------------------------------

@@ -98,6 +98,9 @@ def test_config_validation_is_synchronous():
         (mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=3), sg.SGEP_EINVAL),   # no class means
         (mk(9, sg.SGEP_F32, 4, 8, 8, 16), sg.SGEP_EINVAL),
         (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=2, nu=10.0), sg.SGEP_EINVAL),    # Alg. 2 or 3
+        (mk(C, sg.SGEP_F32, 4, 8, 8, 16, center=2), sg.SGEP_EINVAL),
+        (mk(C, sg.SGEP_BF16, 4, 8, 8, 16, center=1), sg.SGEP_EUNSUPPORTED),  # centring: F64/F32
+        (mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=3, center=1), sg.SGEP_EUNSUPPORTED),
         (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=1, rho=0.0, nu=10.0), sg.SGEP_EINVAL),  # rho > 0
         (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=1, rho=1e-2, nu=1e-2), sg.SGEP_EINVAL),  # nu > rho
         (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=1, rho=1e-2, nu=float("inf")), sg.SGEP_EINVAL),
@@ -146,6 +149,7 @@ def test_null_arguments_rejected():
     assert lib.sgep_step_lda(None, None, 0, None, 1) == sg.SGEP_EINVAL
     assert lib.sgep_kernels_per_step(None, None) == sg.SGEP_EINVAL
     assert lib.sgep_step_kernel_name(None, 0) is None
+    assert lib.sgep_means(None, None) == sg.SGEP_EINVAL
     assert lib.sgep_step_profiled(None, None, 0, None, 0, None, 1, None, 0) == sg.SGEP_EINVAL
     assert lib.sgep_init_ex(None, None, None, None, None) == sg.SGEP_EINVAL
     assert sg.sgep_status_string(sg.SGEP_EPOISONED).startswith("handle poisoned")
@@ -180,6 +184,8 @@ def test_batch_validation_is_synchronous():
                   V[:1]) == sg.SGEP_EUNSUPPORTED                                # GENERAL only
     assert status(1, [32], [32], mk(G, sg.SGEP_BF16, 4, 0, 0, 16),
                   V[:1]) == sg.SGEP_EUNSUPPORTED                                # F32 / F64 only
+    assert status(1, [32], [32], mk(G, sg.SGEP_F32, 4, 0, 0, 16, center=1),
+                  V[:1]) == sg.SGEP_EUNSUPPORTED                                # no centring
     assert lib.sgep_batch_init(None, 1, None, None, None, None, None) == sg.SGEP_EINVAL
     for fn in ("sgep_batch_sync", "sgep_batch_destroy"):
         assert getattr(lib, fn)(None) == sg.SGEP_EINVAL
