@@ -61,6 +61,15 @@ WORKLOADS = {
         generator="medium_cca", tta=dict(targets=(5e-3, 1e-3), max_steps=100_000, every=1000),
         describe="the medium FP32 CCA (views 512+512, k=16, minibatch 1024) with Alg. 3: "
                  "parents' B-norms estimated in log space between rho=1e-3 and nu=4"),
+    "cca_d1024_k16_b1024_fp32_center": dict(
+        kind="cca", dtype="f32", dx=512, dy=512, k=16, b=1024, ring=128,
+        optimizer="adam", schedule="warmup", eta0=4e-3, t_c=100.0, eta_T=4e-6, T=100_000.0,
+        gamma=0.3, rho=1e-6, center=1, offset=1.0,
+        generator="medium_cca", tta=dict(targets=(5e-3, 1e-3), max_steps=100_000, every=1000),
+        describe="the medium FP32 CCA (views 512+512, k=16, minibatch 1024) shifted by fixed "
+                 "per-feature offsets N(0, 1), centred by running means of the views; "
+                 "eta warms up over 100 steps while the means settle, then decays "
+                 "harmonically"),
     "cca_d16_k4_b128_fp64": dict(
         kind="cca", dtype="f64", dx=8, dy=8, k=4, b=128, ring=128,
         optimizer="sgd", schedule="inv", eta0=1.0, t0=200.0, gamma=1.0, rho=1e-6,
@@ -173,6 +182,23 @@ def _generator(w):
     return synth.tiny_cca_pool(0)[1]
 
 
+def offsets(w):
+    """Fixed per-feature offsets of a non-zero-mean stream (None: zero-mean)."""
+    if not w.get("offset"):
+        return None
+    rng = np.random.default_rng([7, 0])
+    return rng.normal(0.0, w["offset"], w["dx"]), rng.normal(0.0, w["offset"], w["dy"])
+
+
+def _eta(w, t):
+    """eta_t of the workload's schedule (the oracle's definition)."""
+    import oracle
+    sched = {"const": oracle.SCHED_CONST, "inv": oracle.SCHED_INV,
+             "warmup": oracle.SCHED_WARMUP_HARMONIC}[w["schedule"]]
+    return oracle.eta(sched, t, w["eta0"], eta_T=w.get("eta_T", 0.0), t0=w.get("t0", 1.0),
+                      t_c=w.get("t_c", 1.0), T=w.get("T", 1.0))
+
+
 def host_batches(w, n):
     """The first n minibatches of the workload's seeded stream (host arrays;
     LDA: data and int32 labels)."""
@@ -180,6 +206,9 @@ def host_batches(w, n):
     b = w["b"]
     if w["generator"] == "medium_cca":
         X, Y = gen.sample(n * b, np.random.default_rng([1, 0]))
+        off = offsets(w)
+        if off is not None:
+            X, Y = X + off[0], Y + off[1]
         return [(X[i * b:(i + 1) * b], Y[i * b:(i + 1) * b]) for i in range(n)]
     return [gen.batch(t, b) for t in range(1, n + 1)]
 
@@ -213,10 +242,12 @@ def config_for(sg, w):
     return sg.make_config(
         kind, dtype, w["k"], w["dx"], w["dy"], w["b"],
         optimizer=sg.SGEP_ADAM if w["optimizer"] == "adam" else sg.SGEP_SGD,
-        schedule={"const": sg.SGEP_SCHED_CONST, "inv": sg.SGEP_SCHED_INV}[w["schedule"]],
-        eta0=w["eta0"], t0=w.get("t0", 1.0), gamma=w["gamma"], rho=w["rho"],
+        schedule={"const": sg.SGEP_SCHED_CONST, "inv": sg.SGEP_SCHED_INV,
+                  "warmup": sg.SGEP_SCHED_WARMUP_HARMONIC}[w["schedule"]],
+        eta0=w["eta0"], t0=w.get("t0", 1.0), t_c=w.get("t_c", 1.0), eta_T=w.get("eta_T", 0.0),
+        T=w.get("T", 1.0), gamma=w["gamma"], rho=w["rho"],
         eps_reg=w.get("eps_reg", 0.0), n_classes=w.get("n_classes", 0),
-        smooth=w.get("smooth", 0), nu=w.get("nu", 0.0))
+        smooth=w.get("smooth", 0), nu=w.get("nu", 0.0), center=w.get("center", 0))
 
 
 def algorithmic_work(w, kernel, names=()):
@@ -268,14 +299,15 @@ def cpu_baseline(w, budget_s: float, host):
     pb = oracle.Problem(oracle.KIND_LDA if lda else oracle.KIND_CCA, w["k"], w["dx"], w["dy"],
                         rho=w["rho"], eps_reg=w.get("eps_reg", 0.0),
                         optimizer=oracle.OPT_ADAM if w["optimizer"] == "adam" else oracle.OPT_SGD,
-                        smooth=bool(w.get("smooth", 0)), nu=w.get("nu", 0.0), **extra)
+                        smooth=bool(w.get("smooth", 0)), nu=w.get("nu", 0.0),
+                        center=bool(w.get("center", 0)), **extra)
     st = oracle.State.init(synth.initial_players(w["dx"] + w["dy"], w["k"], 0),
                            adam=w["optimizer"] == "adam")
     n = 0
     t0 = time.perf_counter()
     while True:
         X, Y = host[n % len(host)]
-        eta = oracle.eta(oracle.SCHED_INV, n + 1, w["eta0"], t0=w.get("t0", 1.0))
+        eta = _eta(w, n + 1)
         if lda:
             oracle.gamma_step(pb, st, X, None, eta, w["gamma"], labels=Y)
         else:
@@ -348,8 +380,14 @@ def time_to_accuracy(w, targets, max_steps: int, every: int, hyper=None, log=Non
                 return torch.clamp(v / sc, -448.0, 448.0).to(torch.float8_e4m3fn).view(torch.uint8)
             return v.to(store)
 
+        off = offsets(w)
+        if off is not None:
+            off = tuple(torch.from_numpy(o).to("cuda", torch.float32) for o in off)
+
         def fill(c, Xb, Yb):
             x, y = gen.sample_torch(E * b, 1_000_000 + c, "cuda", torch.float32)
+            if off is not None:
+                x, y = x + off[0], y + off[1]
             Xb.copy_(conv(x, sx if fmt == "fp8" else None).view(E, b, -1))
             Yb.copy_(conv(y, sy if fmt == "fp8" else None).view(E, b, -1))
     else:
