@@ -36,7 +36,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-KIND_CCA, KIND_GENERAL, KIND_LDA = 0, 1, 2
+KIND_CCA, KIND_GENERAL, KIND_LDA, KIND_ICA = 0, 1, 2, 3
 OPT_SGD, OPT_ADAM = 0, 1
 SCHED_CONST, SCHED_INV, SCHED_WARMUP_HARMONIC = 0, 1, 2
 
@@ -161,8 +161,10 @@ class Problem:
     """Problem description shared by the step functions.
 
     kind: KIND_CCA (A, B the block matrices of Sec. 1), KIND_GENERAL
-    (A = E[y y^T], B = E[x x^T] + eps I) or KIND_LDA (A between-class,
-    B within-class covariance + eps I).  smooth: Alg. 3 instead of Alg. 2
+    (A = E[y y^T], B = E[x x^T] + eps I), KIND_LDA (A between-class,
+    B within-class covariance + eps I) or KIND_ICA (the kurtosis form of
+    Sec. 1: A = E[<x, x> x x^T] - tr(C) C - 2 C^2, B = C + eps I with
+    C = E[x x^T]; data X only, dy = 0).  smooth: Alg. 3 instead of Alg. 2
     (the denominator <v_j, [Bv]_j> clipped at rho is replaced by
     exp(log rho + (log nu - log rho) sigmoid(z_j)), z_j updated at rate
     gamma toward <v_j, [Bv]_j>); nu bounds lambda_max(B) from above.
@@ -425,6 +427,12 @@ def problem_matrices(pb: Problem, X: np.ndarray, Y: Optional[np.ndarray] = None,
     if pb.kind == KIND_GENERAL:
         Y = np.asarray(Y, dtype=np.float64)
         return Y.T @ Y / n, X.T @ X / n + pb.eps_reg * np.eye(X.shape[1])
+    if pb.kind == KIND_ICA:
+        # kurtosis form of Sec. 1 with the empirical moments of the dataset
+        C = X.T @ X / n
+        nr = (X * X).sum(axis=1)
+        K = (X * nr[:, None]).T @ X / n
+        return K - np.trace(C) * C - 2.0 * C @ C, C + pb.eps_reg * np.eye(X.shape[1])
     means = np.asarray(pb.class_means, dtype=np.float64)
     c = means.shape[0]
     pri = np.full(c, 1.0 / c) if pb.class_priors is None else np.asarray(pb.class_priors)

@@ -22,7 +22,8 @@
  *                          App. H neural-CCA table: warmup + harmonic decay)
  *   oracle_gamma_step      one iteration of Alg. 2 (stochastic gamma-EigenGame)
  *                          with M = 1, written per player with explicit sums
- *                          over the minibatch rows; with pb->smooth, Alg. 3
+ *                          over the minibatch rows (CCA, GENERAL, LDA and the
+ *                          kurtosis form of ICA of Sec. 1); with pb->smooth, Alg. 3
  *                          (App. G: the clipped denominator replaced by a
  *                          smooth log-space estimate with its own variable)
  *   oracle_gamma_step_dense  the same Alg. 2 iteration with exact A and B
@@ -42,6 +43,7 @@
 #define OR_KIND_CCA 0
 #define OR_KIND_GENERAL 1
 #define OR_KIND_LDA 2
+#define OR_KIND_ICA 3
 
 #define OR_OPT_SGD 0
 #define OR_OPT_ADAM 1
@@ -388,6 +390,37 @@ static void minibatch_products(const oracle_problem *pb, int64_t b,
         for (int64_t f = 0; f < d; ++f) {
             Av[f] /= (double)b;
             Bv[f] = Bv[f] / (double)b + pb->eps_reg * v[f];
+        }
+    } else if (pb->kind == OR_KIND_ICA) {
+        /* ICA in its kurtosis form (Sec. 1): with C_t = (1/b) sum_r x_r x_r^T,
+         *   A_t v = (1/b) sum_r ||x_r||^2 x_r (x_r^T v) - tr(C_t) C_t v - 2 C_t (C_t v)
+         *   B_t v = C_t v + eps v
+         * all from the one minibatch; C_t (C_t v) is a second pass over the rows. */
+        double *Cv = tmp, tr = 0.0;
+        memset(Cv, 0, (size_t)d * sizeof(double));
+        for (int64_t r = 0; r < b; ++r) {
+            const double *x = X + r * ldx;
+            double nr = dot(d, x, x), p = dot(d, x, v);
+            tr += nr;
+            for (int64_t f = 0; f < d; ++f) {
+                Cv[f] += x[f] * p;
+                Av[f] += nr * x[f] * p;
+            }
+        }
+        tr /= (double)b;
+        for (int64_t f = 0; f < d; ++f) {
+            Cv[f] /= (double)b;
+            Av[f] /= (double)b;
+        }
+        for (int64_t r = 0; r < b; ++r) {
+            const double *x = X + r * ldx;
+            double q = dot(d, x, Cv);
+            for (int64_t f = 0; f < d; ++f)
+                Av[f] -= 2.0 * x[f] * q / (double)b;
+        }
+        for (int64_t f = 0; f < d; ++f) {
+            Av[f] -= tr * Cv[f];
+            Bv[f] = Cv[f] + pb->eps_reg * v[f];
         }
     } else { /* LDA */
         int c = pb->n_classes;

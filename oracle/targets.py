@@ -51,3 +51,22 @@ def general_planted_topk(gen, k: int):
     order = np.argsort(-gen.lam)[:k]
     E = np.eye(gen.d)[:, order]
     return gen.lam[order].copy(), np.linalg.solve(LO.T, E)
+
+
+def ica_population_AB(gen):
+    """Kurtosis-form ICA matrices of ``synth.ICAMixed`` (orthogonal mixing,
+    independent unit-variance sources with excess kurtosis kappa_i):
+    E[||s||^2 s s^T] = diag(kappa) + (d + 2) I, so with C = M M^T = I,
+    A = M (diag(kappa) + (d + 2) I) M^T - d I - 2 I = M diag(kappa) M^T and
+    B = I."""
+    kap = np.zeros(gen.d)
+    kap[:len(gen.kurtosis)] = gen.kurtosis
+    return (gen.M * kap[None, :]) @ gen.M.T, np.eye(gen.d)
+
+
+def ica_planted_topk(gen, k: int):
+    """Top-k of the population ICA problem: the mixing columns of the k most
+    kurtotic sources, eigenvalues their excess kurtoses (unit vectors; B = I)."""
+    kap = np.asarray(gen.kurtosis, dtype=np.float64)
+    order = np.argsort(-kap)[:k]
+    return kap[order].copy(), gen.M[:, order].copy()

@@ -17,6 +17,9 @@ shapes of the benchmark configurations):
                    B = E[x x^T] + eps I and planted generalized eigenvalues.
 * ``LDAClasses``   Gaussian classes with means on a random low-dimensional
                    subspace and diagonal within-class covariance.
+* ``ICAMixed``     independent sources (Bernoulli-Gaussian with chosen
+                   excess kurtosis, the rest Gaussian) under an orthogonal
+                   mixing map (pre-whitened mixtures, the ICA problem).
 
 Generator seeds: parameters use ``seed``, the minibatch stream uses
 ``(seed + 1, t)`` and the initial players ``seed + 2``.
@@ -380,6 +383,49 @@ class LDAClasses:
 
     def batch(self, t: int, b: int, dtype=np.float32):
         return self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)
+
+
+@dataclass
+class ICAMixed:
+    """x = M s with M (d x d) orthogonal and independent unit-variance sources
+    s: source i < len(kurtosis) is Bernoulli-Gaussian, g * z / sqrt(p_i) with
+    g ~ N(0, 1), z ~ Bernoulli(p_i), p_i = 3 / (kurtosis_i + 3), whose excess
+    kurtosis is kurtosis_i; the other sources are N(0, 1)."""
+    d: int = 1024
+    kurtosis: Tuple[float, ...] = tuple(np.linspace(20.0, 2.0, 16))
+    seed: int = 0
+    M: np.ndarray = field(init=False, repr=False)
+    p: np.ndarray = field(init=False, repr=False)
+
+    def __post_init__(self):
+        rng = np.random.default_rng(self.seed)
+        self.M = _orth(rng, self.d, self.d)
+        self.p = 3.0 / (np.asarray(self.kurtosis, dtype=np.float64) + 3.0)
+
+    def sample(self, n: int, rng: np.random.Generator, dtype=np.float64):
+        m = len(self.p)
+        S = rng.standard_normal((n, self.d))
+        z = rng.random((n, m)) < self.p[None, :]
+        S[:, :m] = S[:, :m] * z / np.sqrt(self.p)[None, :]
+        return (S @ self.M.T).astype(dtype, copy=False)
+
+    def batch(self, t: int, b: int, dtype=np.float64):
+        X = self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)
+        return X, None
+
+    def sample_torch(self, n: int, t: int, device, dtype):
+        """n fresh rows drawn on `device` from a torch generator seeded by
+        (seed, t), M in FP32 (same distribution as ``sample``)."""
+        import torch
+        g = torch.Generator(device=device)
+        g.manual_seed((int(self.seed) * 1_000_003 + 7919 * int(t) + 5) & ((1 << 63) - 1))
+        f32 = torch.float32
+        m = len(self.p)
+        S = torch.randn((n, self.d), generator=g, device=device, dtype=f32)
+        p = torch.from_numpy(self.p).to(device=device, dtype=f32)
+        z = (torch.rand((n, m), generator=g, device=device, dtype=f32) < p).to(f32)
+        S[:, :m] = S[:, :m] * z / torch.sqrt(p)
+        return (S @ torch.from_numpy(self.M.T).to(device=device, dtype=f32)).to(dtype)
 
 
 # ---------------------------------------------------------------------------
