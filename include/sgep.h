@@ -18,8 +18,12 @@
  *                      A = sum_c pi_c (mu_c - mu)(mu_c - mu)^T, mu = sum_c pi_c mu_c
  *                      (between-class), B = E[(x - mu_l)(x - mu_l)^T] + eps I
  *                      (within-class, l the sample's label)
- * Expectations are estimated by minibatch means (1/b) sum over the rows; the
- * data are taken as zero-mean (Sec. 1); no centring is applied.
+ *   SGEP_KIND_ICA      one stream x of width d, the kurtosis form of ICA:
+ *                      A = E[<x, x> x x^T] - tr(C) C - 2 C^2, B = C + eps I,
+ *                      C = E[x x^T] (F64 / F32 single handles)
+ * Expectations are estimated by minibatch means (1/b) sum over the rows (ICA:
+ * every term, C^2 included, from the one minibatch); the data are taken as
+ * zero-mean (Sec. 1) unless cfg.center asks for running-mean centring.
  *
  * Conventions
  *   - Every call returns an sgep_status; 0 is success.
@@ -65,6 +69,7 @@ typedef int32_t sgep_status;
 #define SGEP_KIND_CCA 0
 #define SGEP_KIND_GENERAL 1
 #define SGEP_KIND_LDA 2
+#define SGEP_KIND_ICA 3
 
 /* element type of the minibatch views (and of the arithmetic) */
 #define SGEP_F64 0     /* FP64 data, FP64 MFMA, FP64 state */
@@ -97,8 +102,8 @@ typedef struct sgep_config {
     int32_t optimizer; /* SGEP_SGD or SGEP_ADAM */
     int32_t schedule;  /* SGEP_SCHED_* */
     int32_t n_classes; /* LDA: 2 .. 16 classes; 0 otherwise */
-    int64_t dx;        /* CCA: width of view x. GENERAL, LDA: d */
-    int64_t dy;        /* CCA: width of view y. GENERAL: must equal dx. LDA: 0.
+    int64_t dx;        /* CCA: width of view x. GENERAL, LDA, ICA: d */
+    int64_t dy;        /* CCA: width of view y. GENERAL: must equal dx. LDA, ICA: 0.
                         * BF16 and FP8: dx and dy multiples of 8 */
     int64_t b_max;     /* largest minibatch that sgep_step will receive */
     double eta0, eta_T, t0, t_c, T; /* schedule parameters (see above) */
@@ -165,7 +170,7 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
 
 /* Enqueue one iteration of Alg. 2 on the minibatch (X, Y) of b rows.
  *   X   : device, b x dx row-major (element type cfg.dtype), leading dim ldx
- *   Y   : device, b x dy row-major, leading dim ldy
+ *   Y   : device, b x dy row-major, leading dim ldy (ICA: NULL, ldy ignored)
  *   1 <= b <= b_max.  X and Y must be 16-byte aligned and ldx, ldy multiples
  *   of 16 bytes / element size (2 for F64, 4 for F32), ldx >= dx, ldy >= dy.
  * Per iteration, with v_i the current unit players, [Bv]_i the auxiliary
@@ -192,13 +197,15 @@ sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int3
  * sum of the slices and update); else 2 (forward products; backward products,
  * k x k coefficients and update) when the backward tile is one 16-feature
  * block and k * element size <= 128 bytes after padding; else 3 (forward
- * products; k x k coefficients; backward products and update).  BF16 / FP8:
- * 3 (forward products; operand preparation and reductions; backward products
- * and update). */
+ * products; k x k coefficients; backward products and update).  ICA: 4
+ * (forward products and row norms; X^T P and X^T diag(||x_r||^2) P; the
+ * second forward pass X C_t V with the k x k coefficients; X^T X C_t V and
+ * update).  BF16 / FP8: 3 (forward products; operand preparation and
+ * reductions; backward products and update). */
 sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n);
 
 /* Short name of kernel i (0 <= i < sgep_kernels_per_step) of one iteration,
- * in launch order: "k_fwd", "k_coef", "k_bwdp", "k_bwd", "k_wfwd", "k_wmid"
+ * in launch order: "k_fwd", "k_coef", "k_bwdp", "k_bwd1", "k_fwd2", "k_bwd", "k_wfwd", "k_wmid"
  * or "k_wbwd" -- a static string, not to be freed; NULL for a NULL handle or
  * an index out of range. */
 const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i);

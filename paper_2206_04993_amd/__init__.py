@@ -30,7 +30,7 @@ SGEP_ENONFINITE = -5
 SGEP_EUNSUPPORTED = -6
 SGEP_EPOISONED = -7
 
-SGEP_KIND_CCA, SGEP_KIND_GENERAL, SGEP_KIND_LDA = 0, 1, 2
+SGEP_KIND_CCA, SGEP_KIND_GENERAL, SGEP_KIND_LDA, SGEP_KIND_ICA = 0, 1, 2, 3
 SGEP_F64, SGEP_F32, SGEP_BF16, SGEP_FP8_E4M3 = 0, 1, 2, 3
 SGEP_SGD, SGEP_ADAM = 0, 1
 SGEP_SCHED_CONST, SGEP_SCHED_INV, SGEP_SCHED_WARMUP_HARMONIC = 0, 1, 2
@@ -404,11 +404,15 @@ class Solver:
 
     def step(self, X, Y, b: Optional[int] = None, ldx: Optional[int] = None,
              ldy: Optional[int] = None):
-        """One iteration; for LDA, Y is the int32 label vector."""
+        """One iteration; for LDA, Y is the int32 label vector; for ICA, Y is
+        None."""
         b = X.shape[0] if b is None else b
         ldx = X.stride(0) if ldx is None else ldx
         if self.cfg.kind == SGEP_KIND_LDA:
             sgep_step_lda(self.h, X, ldx, Y, b)
+            return
+        if self.cfg.kind == SGEP_KIND_ICA:
+            sgep_step(self.h, X, ldx, None, 0, b)
             return
         ldy = Y.stride(0) if ldy is None else ldy
         sgep_step(self.h, X, ldx, Y, ldy, b)

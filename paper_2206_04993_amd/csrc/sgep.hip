@@ -55,6 +55,8 @@ struct sgep_handle_s {
     void *cpre = nullptr; // coefficient block of the iteration (k_coef)
     int nsplit = 1;        // row slices of the backward products (1: one pass)
     void *mu = nullptr;    // running means of the views (centring): 2 ldv elements
+    void *S1 = nullptr, *S2 = nullptr; // ICA: first backward pass products
+    double *bb_part = nullptr;         // ICA: S1^T S1 tile partials
     void *bpart = nullptr; // the slices' partial products (nsplit > 1)
     int n_tx = 0, n_ty = 0, n_tiles = 0;
     int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
@@ -110,7 +112,7 @@ void free_all(sgep_handle *h)
     void *ptrs[] = {h->V,  h->G,        h->Am,      h->As,    h->P,  h->Q,    h->gram_part,
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
                     h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
-                    h->mu};
+                    h->mu,   h->S1, h->S2,     h->bb_part};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -120,14 +122,16 @@ sgep_status check_cfg(const sgep_config *c)
 {
     if (!c)
         return SGEP_EINVAL;
-    if (c->kind != SGEP_KIND_CCA && c->kind != SGEP_KIND_GENERAL && c->kind != SGEP_KIND_LDA)
+    if (c->kind != SGEP_KIND_CCA && c->kind != SGEP_KIND_GENERAL && c->kind != SGEP_KIND_LDA &&
+        c->kind != SGEP_KIND_ICA)
         return SGEP_EINVAL;
     if (c->dtype < SGEP_F64 || c->dtype > SGEP_FP8_E4M3)
         return SGEP_EINVAL;
     const bool narrow = c->dtype == SGEP_BF16 || c->dtype == SGEP_FP8_E4M3;
     const bool lda = c->kind == SGEP_KIND_LDA;
     // LDA runs on the BF16 path only; GENERAL on the F64 / F32 path only
-    if ((lda && c->dtype != SGEP_BF16) || (narrow && c->kind == SGEP_KIND_GENERAL))
+    const bool ica = c->kind == SGEP_KIND_ICA;
+    if ((lda && c->dtype != SGEP_BF16) || (narrow && (c->kind == SGEP_KIND_GENERAL || ica)))
         return SGEP_EUNSUPPORTED;
     if (c->k < 1)
         return SGEP_EINVAL;
@@ -139,6 +143,11 @@ sgep_status check_cfg(const sgep_config *c)
         return SGEP_EINVAL;
     if (lda) {
         if (c->n_classes < 2 || c->n_classes > sgep::wide::kMaxCls)
+            return SGEP_EINVAL;
+        if (c->dx < 1 || c->dy != 0 || c->b_max < 1)
+            return SGEP_ESHAPE;
+    } else if (ica) {
+        if (c->n_classes != 0)
             return SGEP_EINVAL;
         if (c->dx < 1 || c->dy != 0 || c->b_max < 1)
             return SGEP_ESHAPE;
@@ -159,7 +168,7 @@ sgep_status check_cfg(const sgep_config *c)
         return SGEP_EINVAL;
     if ((c->smooth != 0 && c->smooth != 1) || (c->center != 0 && c->center != 1))
         return SGEP_EINVAL;
-    if (c->center && (narrow || lda))
+    if (c->center && (narrow || lda || ica))
         return SGEP_EUNSUPPORTED; // centring: F64 / F32 CCA and GENERAL
     if (c->smooth && !(c->rho > 0.0 && c->nu > c->rho && std::isfinite(c->nu)))
         return SGEP_EINVAL;
@@ -293,9 +302,36 @@ sgep_status launch_step_c(sgep_handle *h, const StepArgs &a, void *const *events
     return SGEP_OK;
 }
 
+// ICA: forward (P, Q = diag(||x_r||^2) P, Grams), first backward pass (S1 =
+// X^T P, S2 = X^T Q, S1^T S1 partials), second forward pass (R = X S1 / b and
+// the coefficient block), second backward pass (X^T R, update)
+template <typename T, int KP>
+sgep_status launch_step_ica(sgep_handle *h, const StepArgs &a, void *const *events)
+{
+    using namespace sgep;
+    hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (events)
+        for (int i = 0; i < 8; ++i)
+            ev[i] = (hipEvent_t)events[i];
+    const dim3 gf(a.n_fwd + 1), gb(h->n_tiles);
+    launch_timed(k_fwd<T, KP, kKindICA>, gf, h->stream, ev[0], ev[1], a);
+    launch_timed(k_bwd<T, KP, 1, kKindICA, kOptSGD, kModeIca1>, gb, h->stream, ev[2], ev[3], a);
+    launch_timed(k_fwd2<T, KP>, gf, h->stream, ev[4], ev[5], a);
+    if (h->cfg.optimizer == SGEP_ADAM)
+        launch_timed(k_bwd<T, KP, 1, kKindICA, kOptAdam, kModeIca2>, gb, h->stream, ev[6], ev[7],
+                     a);
+    else
+        launch_timed(k_bwd<T, KP, 1, kKindICA, kOptSGD, kModeIca2>, gb, h->stream, ev[6], ev[7],
+                     a);
+    HIPCHK(hipGetLastError());
+    return SGEP_OK;
+}
+
 template <typename T, int KP>
 sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
 {
+    if (h->cfg.kind == SGEP_KIND_ICA)
+        return launch_step_ica<T, KP>(h, a, events);
     return h->cfg.center ? launch_step_c<T, KP, true>(h, a, events)
                          : launch_step_c<T, KP, false>(h, a, events);
 }
@@ -303,6 +339,8 @@ sgep_status launch_step(sgep_handle *h, const StepArgs &a, void *const *events)
 // kernels of one iteration of a narrow handle
 int narrow_kernels(const sgep_handle *h)
 {
+    if (h->cfg.kind == SGEP_KIND_ICA)
+        return 4;
     const bool spec = h->esz == sizeof(double) ? spec_mode<double>(h->kp, h->mb)
                                                : spec_mode<float>(h->kp, h->mb);
     return (spec && h->nsplit == 1) ? 2 : 3;
@@ -780,7 +818,9 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     }
     h->esz = cfg->dtype == SGEP_F64 ? sizeof(double) : sizeof(float);
     const bool wide = h->d >= kWideD;
-    h->mb = !wide ? 1 : (cfg->dtype == SGEP_F64 ? mb_wide<double>(h->kp) : mb_wide<float>(h->kp));
+    h->mb = (!wide || cfg->kind == SGEP_KIND_ICA)
+                ? 1
+                : (cfg->dtype == SGEP_F64 ? mb_wide<double>(h->kp) : mb_wide<float>(h->kp));
     h->ft = 16 * h->mb;
     if (cfg->kind == SGEP_KIND_CCA) {
         h->n_tx = (int)((cfg->dx + h->ft - 1) / h->ft);
@@ -825,7 +865,11 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     }
     alloc(&h->P, (size_t)h->ldp * kp * h->esz);
     alloc(&h->Q, (size_t)h->ldp * kp * h->esz);
-    alloc((void **)&h->gram_part, (size_t)h->W * h->ldg * sizeof(double));
+    const bool ica = cfg->kind == SGEP_KIND_ICA;
+    const int64_t tri = (int64_t)kp * (kp + 1) / 2;
+    // ICA Gram rows: P^T diag(n) P and P^T P (lower triangles) and sum_r n_r
+    const int64_t wg = ica ? 2 * tri + 1 : h->W;
+    alloc((void **)&h->gram_part, (size_t)wg * h->ldg * sizeof(double));
     alloc((void **)&h->stat_part, (size_t)h->W * h->lds * sizeof(double));
     alloc((void **)&h->stat_tot, (size_t)h->W * sizeof(double));
     alloc((void **)&h->readout, (size_t)d * cfg->k * sizeof(double));
@@ -837,6 +881,11 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     }
     if (cfg->center)
         alloc(&h->mu, (size_t)2 * h->ldv * h->esz);
+    if (ica) {
+        alloc(&h->S1, st_bytes);
+        alloc(&h->S2, st_bytes);
+        alloc((void **)&h->bb_part, (size_t)tri * h->lds * sizeof(double));
+    }
     if (!ok) {
         free_all(h);
         delete h;
@@ -846,13 +895,16 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     bool hok = hipMemsetAsync(h->coef, 0, sizeof(Coef), h->stream) == hipSuccess &&
                hipMemsetAsync(h->stat_part, 0, (size_t)h->W * h->lds * sizeof(double),
                               h->stream) == hipSuccess &&
-               hipMemsetAsync(h->gram_part, 0, (size_t)h->W * h->ldg * sizeof(double),
+               hipMemsetAsync(h->gram_part, 0, (size_t)wg * h->ldg * sizeof(double),
                               h->stream) == hipSuccess;
     if (h->Am)
         hok = hok && hipMemsetAsync(h->Am, 0, st_bytes, h->stream) == hipSuccess &&
               hipMemsetAsync(h->As, 0, st_bytes, h->stream) == hipSuccess;
     if (h->mu)
         hok = hok && hipMemsetAsync(h->mu, 0, (size_t)2 * h->ldv * h->esz, h->stream) == hipSuccess;
+    if (h->S1) // features past d are never written and must read as zero
+        hok = hok && hipMemsetAsync(h->S1, 0, st_bytes, h->stream) == hipSuccess &&
+              hipMemsetAsync(h->S2, 0, st_bytes, h->stream) == hipSuccess;
     // quad-interleaved with padded views: (feature f, player i) at
     // (sf / 4) 4 KP + 4 i + sf % 4, sf = storage position of f
     std::vector<unsigned char> host(st_bytes, 0);
@@ -918,6 +970,9 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.cpre = h->cpre;
     a.bpart = h->bpart;
     a.mu = h->mu;
+    a.S1 = h->S1;
+    a.S2 = h->S2;
+    a.bb_part = h->bb_part;
     a.nsplit = h->nsplit;
     a.schedule = h->cfg.schedule;
     a.eta0 = h->cfg.eta0;
@@ -946,8 +1001,13 @@ static sgep_status step_impl(sgep_handle *h, const void *X, int64_t ldx, const v
         return SGEP_EPOISONED;
     if (h->wide)
         return step_wide(h, X, ldx, Y, ldy, labels, b, events);
-    if (!X || !Y || labels)
+    const bool ica = h->cfg.kind == SGEP_KIND_ICA;
+    if (!X || labels || (ica ? Y != nullptr : !Y))
         return SGEP_EINVAL;
+    if (ica) { // one stream: the second view's slots point at it
+        Y = X;
+        ldy = ldx;
+    }
     if (b < 1 || b > h->cfg.b_max)
         return SGEP_ESHAPE;
     if (ldx < h->cfg.dx || ldy < h->cfg.dy)
@@ -998,11 +1058,14 @@ const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i)
     static const char *spec[] = {"k_fwd", "k_bwd"};
     static const char *pre[] = {"k_fwd", "k_coef", "k_bwd"};
     static const char *split[] = {"k_fwd", "k_bwdp", "k_bwd"};
+    static const char *ica[] = {"k_fwd", "k_bwd1", "k_fwd2", "k_bwd"};
     if (h->wide)
         return i < 3 ? wide[i] : nullptr;
     const int n = narrow_kernels(h);
     if (i >= n)
         return nullptr;
+    if (h->cfg.kind == SGEP_KIND_ICA)
+        return ica[i];
     return n == 2 ? spec[i] : (h->nsplit > 1 ? split[i] : pre[i]);
 }
 

@@ -52,6 +52,7 @@ constexpr int kKPMax = 64;   // largest padded player count
 
 constexpr int kKindCCA = 0;
 constexpr int kKindGeneral = 1;
+constexpr int kKindICA = 3; // kurtosis form of ICA: one view, A and B from its moments
 constexpr int kOptSGD = 0;
 constexpr int kOptAdam = 1;
 
@@ -128,6 +129,9 @@ struct StepArgs {
                              // centred column sums (kModePart)
     void *mu;                // running means of the views (centring): view x (CCA:
                              // both views) at storage positions, GENERAL view y at +ldv
+    void *S1, *S2;           // ICA: X^T P and X^T diag(||x_r||^2) P of the iteration,
+                             // quad-interleaved like V (raw sums over the rows)
+    double *bb_part;         // ICA: [tiles][KP(KP+1)/2] partials of S1^T S1
     int32_t nsplit;          // row slices of the backward products (kModePart)
     int32_t schedule;
     int32_t smooth;          // Alg. 3 estimate of v_j^T B v_j instead of the clip
@@ -254,12 +258,13 @@ template <> struct VecLoad<double, 4> {
 // loaded from a valid chunk and zeroed; the ragged last chunk runs masked.
 // `row` is a valid row index; rows past the minibatch are zeroed through rv.
 // ---------------------------------------------------------------------------
-template <typename T, int KP, bool CENTER = false>
+template <typename T, int KP, bool CENTER = false, bool SQ = false>
 __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t ldx, int64_t nf,
                                          int64_t row, bool rv, bool vec_ok,
                                          const SGEP_G T *__restrict__ VQ,
                                          int lane, int w, typename Mfma<T>::acc (*acc)[KP / 16],
-                                         const SGEP_G T *__restrict__ mu = nullptr)
+                                         const SGEP_G T *__restrict__ mu = nullptr,
+                                         T *sq = nullptr)
 {
     constexpr int VEC = 16 / (int)sizeof(T);
     constexpr int CH = 4 * VEC;
@@ -300,6 +305,8 @@ __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
                 const T xs = ok ? (CENTER ? xv[u][j] - mv[u][j] : xv[u][j]) : T(0);
+                if (SQ)
+                    *sq += xs * xs; // this lane's part of ||x_row||^2
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     acc[j & 1][nb] = Mfma<T>::fma(xs, bv[u][nb][j], acc[j & 1][nb]);
@@ -314,6 +321,8 @@ __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t
             const bool fv = fe < nf;
             const int64_t fc = fv ? fe : nf - 1;
             const T xs = (rv && fv) ? (CENTER ? xr[fc] - mu[fc] : xr[fc]) : T(0);
+            if (SQ)
+                *sq += xs * xs;
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const T bvv = fv ? VQ[qidx<KP>(fc, nb * 16 + n)] : T(0);
@@ -428,8 +437,11 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     constexpr int NB = KP / 16;
     constexpr int TRI = KP * (KP + 1) / 2;
     constexpr int GW = TRI + KP;
+    constexpr bool ICA = KIND == kKindICA;
+    constexpr int GWF = ICA ? 2 * TRI + 1 : GW; // width of this kernel's Gram rows
     __shared__ T red[4][16 * KP];
     __shared__ T pt[16][KP], qt[16][KP];
+    __shared__ T rn[ICA ? 16 : 1][16], nrow[16]; // ICA: ||x_r||^2 partials and totals
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int kk = lane >> 4, n = lane & 15;
@@ -464,7 +476,11 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     // y's at +ldv)
     const SGEP_G T *mux = (const SGEP_G T *)a.mu;
     const SGEP_G T *muy = CENTER ? mux + (KIND == kKindCCA ? a.dxp : a.ldv) : nullptr;
-    if (nfy == a.dx) {
+    T sq = T(0); // ICA: this lane's part of its row's squared norm
+    if constexpr (ICA) {
+        fwd_view<T, KP, false, true>(X, a.ldx, a.dx, row, rv, vec_ok, VQ, lane, w, aP, nullptr,
+                                     &sq);
+    } else if (nfy == a.dx) {
         fwd_view2<T, KP, KIND != kKindCCA, LOWREG, CENTER>(X, a.ldx, Y, a.ldy, a.dx, row, rv,
                                                            vec_ok, VQ, VQy, lane, w, aP, aQ,
                                                            mux, muy);
@@ -485,17 +501,33 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     for (int e = tid; e < 16 * KP; e += kNT)
         (&pt[0][0])[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
     __syncthreads();
+    if constexpr (ICA) {
+        // Q = diag(||x_r||^2) P: row norms from the lanes' partials, fixed order
+        rn[4 * w + kk][n] = sq;
+        __syncthreads();
+        if (tid < 16) {
+            T s = T(0);
+            for (int q = 0; q < 16; ++q)
+                s += rn[q][tid];
+            nrow[tid] = s;
+        }
+        __syncthreads();
+        for (int e = tid; e < 16 * KP; e += kNT)
+            (&qt[0][0])[e] = nrow[e / KP] * (&pt[0][0])[e];
+        __syncthreads();
+    } else {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-        const Acc s = aQ[0][nb] + aQ[1][nb];
+        for (int nb = 0; nb < NB; ++nb) {
+            const Acc s = aQ[0][nb] + aQ[1][nb];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            red[w][Mfma<T>::drow(kk, r) * KP + nb * 16 + n] = s[r];
+            for (int r = 0; r < 4; ++r)
+                red[w][Mfma<T>::drow(kk, r) * KP + nb * 16 + n] = s[r];
+        }
+        __syncthreads();
+        for (int e = tid; e < 16 * KP; e += kNT)
+            (&qt[0][0])[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < 16 * KP; e += kNT)
-        (&qt[0][0])[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
-    __syncthreads();
     // P, Q of these 16 rows: one contiguous quad-interleaved block
     for (int e = tid; e < 16 * KP; e += kNT) {
         const int rq = e / (4 * KP), c = (e / 4) % KP, r = 4 * rq + (e & 3);
@@ -506,10 +538,21 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     }
 
     // partial Grams over these 16 rows (raw players, FP64): lower triangle of
-    // b V^T A_t V and the diagonal of b V^T B_t V (without the ridge)
-    for (int e = tid; e < GW; e += kNT) {
+    // b V^T A_t V and the diagonal of b V^T B_t V (without the ridge); ICA:
+    // lower triangles of P^T diag(n) P and P^T P, and sum_r ||x_r||^2
+    for (int e = tid; e < GWF; e += kNT) {
         double s = 0.0;
-        if (e < TRI) {
+        if (ICA) {
+            if (e < 2 * TRI) {
+                int i, j;
+                tri_ij(e < TRI ? e : e - TRI, i, j);
+                for (int r = 0; r < 16; ++r)
+                    s += (double)pt[r][i] * (double)(e < TRI ? qt[r][j] : pt[r][j]);
+            } else {
+                for (int r = 0; r < 16; ++r)
+                    s += (double)nrow[r];
+            }
+        } else if (e < TRI) {
             int i, j;
             tri_ij(e, i, j);
             for (int r = 0; r < 16; ++r) {
@@ -527,7 +570,7 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
                     s += (double)pt[r][i] * (double)pt[r][i];
             }
         }
-        ((SGEP_G double *)a.gram_part)[(int64_t)blk * GW + e] = s;
+        ((SGEP_G double *)a.gram_part)[(int64_t)blk * GWF + e] = s;
     }
 }
 
@@ -536,6 +579,7 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 {
     fwd_body<T, KP, KIND, false, CENTER>(a, blockIdx.x);
 }
+
 
 // ---------------------------------------------------------------------------
 // Coefficients of one iteration, as the backward epilogue uses them: with the
@@ -553,11 +597,13 @@ constexpr int kModePre = 0;  // backward reads the block k_coef wrote
 constexpr int kModeSpec = 1; // backward computes it on four extra waves
 constexpr int kModePart = 2; // one row slice of the products -> partial tiles
 constexpr int kModeFin = 3;  // sum of the partial tiles, block from k_coef, epilogue
+constexpr int kModeIca1 = 4; // ICA: S1 = X^T P, S2 = X^T Q to memory, S1^T S1 partials
+constexpr int kModeIca2 = 5; // ICA: S3 = X^T R, A-side = S2 - tr S1 - 2 S3, epilogue
 
 template <typename T, int KP> struct CoefTile {
     T Tl[KP * KP];            // T_ij, row i
     T mB[KP], mAc[KP], inv[KP];
-    T eta, c1, c2, pad;       // eta_t, 1 - b1^t, 1 - b2^t
+    T eta, c1, c2, pad;       // eta_t, 1 - b1^t, 1 - b2^t; pad: ICA tr(C_t)
 };
 
 // Alg. 3 estimate of v_j^T B v_j from its log-space variable z
@@ -701,7 +747,25 @@ __device__ __forceinline__ void coef_body(const StepArgs &a)
     coef_early<T, KP>(a, t, C, ema, true, tid);
     for (int e = tid; e < W; e += kNT)
         ss[e] = ((const SGEP_G double *)a.stat_tot)[e];
-    colsum((const SGEP_G double *)a.gram_part, a.n_fwd, W, W, gs, tid, kNT);
+    if constexpr (KIND == kKindICA) {
+        // b V^T A_t V = P^T diag(n) P - tr(C_t) P^T P - (2 / b) S1^T S1 (S1 = X^T P),
+        // b diag(V^T B_t V) = diag(P^T P) (before the ridge); tr(C_t) = sum_r n_r / b
+        constexpr int TRI = KP * (KP + 1) / 2;
+        __shared__ double gi[2 * TRI + 1], gb2[TRI];
+        colsum((const SGEP_G double *)a.gram_part, a.n_fwd, 2 * TRI + 1, 2 * TRI + 1, gi, tid,
+               kNT);
+        colsum((const SGEP_G double *)a.bb_part, a.n_tx, TRI, TRI, gb2, tid, kNT);
+        __syncthreads();
+        const double ib = 1.0 / (double)a.b, tr = gi[2 * TRI] * ib;
+        for (int e = tid; e < TRI; e += kNT)
+            gs[e] = gi[e] - tr * gi[TRI + e] - 2.0 * ib * gb2[e];
+        for (int i = tid; i < KP; i += kNT)
+            gs[TRI + i] = gi[TRI + tri_idx(i, i)];
+        if (tid == 0)
+            C.pad = (T)tr; // read by the second backward pass
+    } else {
+        colsum((const SGEP_G double *)a.gram_part, a.n_fwd, W, W, gs, tid, kNT);
+    }
     __syncthreads();
     coef_norms<KP>(a, ss, dInv, dS, t, tid);
     __syncthreads();
@@ -718,6 +782,52 @@ template <typename T, int KP, int KIND>
 __global__ void __launch_bounds__(kNT) k_coef(StepArgs a)
 {
     coef_body<T, KP, KIND>(a);
+}
+
+// ICA, second forward pass: R = X (S1 / b) = X C_t V for 16-row tiles (S1 =
+// X^T P from the first backward pass, read like V), stored where Q was; the
+// extra workgroup n_fwd computes the iteration's coefficient block (it needs
+// the S1^T S1 partials of the first backward pass).
+template <typename T, int KP>
+__global__ void __launch_bounds__(kNT) k_fwd2(StepArgs a)
+{
+    typedef typename Mfma<T>::acc Acc;
+    constexpr int NB = KP / 16;
+    const int blk = blockIdx.x;
+    if (blk == a.n_fwd) {
+        coef_body<T, KP, kKindICA>(a);
+        return;
+    }
+    __shared__ T red[4][16 * KP];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int kk = lane >> 4, n = lane & 15;
+    const int64_t r0 = (int64_t)blk * 16;
+    const bool rv = r0 + n < a.b;
+    const int64_t row = rv ? r0 + n : a.b - 1;
+    Acc aR[2][NB];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            aR[h][nb] = Acc{0, 0, 0, 0};
+    fwd_view<T, KP>((const SGEP_G T *)a.X, a.ldx, a.dx, row, rv, a.vec_ok != 0,
+                    (const SGEP_G T *)a.S1, lane, w, aR);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const Acc s = aR[0][nb] + aR[1][nb];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            red[w][Mfma<T>::drow(kk, r) * KP + nb * 16 + n] = s[r];
+    }
+    __syncthreads();
+    const T ib = (T)(1.0 / (double)a.b);
+    SGEP_G T *RQ = (SGEP_G T *)a.Q;
+    for (int e = tid; e < 16 * KP; e += kNT) {
+        const int rq = e / (4 * KP), c = (e / 4) % KP, r = 4 * rq + (e & 3);
+        const int ti = r * KP + c;
+        if (r0 + r < a.b)
+            RQ[r0 * KP + e] = (red[0][ti] + red[1][ti] + red[2][ti] + red[3][ti]) * ib;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -747,7 +857,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
     constexpr int FT = 16 * MB;
     constexpr int TRI = KP * (KP + 1) / 2;
     constexpr int W = TRI + KP; // width of both partial kinds
-    constexpr int XPG = (KIND == kKindCCA ? 4 : 8) * MB; // X registers per group
+    constexpr int XPG = (KIND == kKindGeneral ? 8 : 4) * MB; // X registers per group
     // loads in flight per batch: ~128 VGPRs; ~192 for the smallest player
     // tile with eight waves (kModeSpec; one workgroup per CU, fewer round
     // trips, still within 256 VGPRs); ~64 with LOWREG (more workgroups per
@@ -761,7 +871,10 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
     constexpr int NTH = SPEC ? 2 * kNT : kNT; // threads of the workgroup
     constexpr int NC = (int)(sizeof(CoefTile<T, KP>) / sizeof(T));
     constexpr bool PART = MODE == kModePart, FIN = MODE == kModeFin;
-    constexpr int CPT = (SPEC || PART) ? 1 : (NC + kNT - 1) / kNT;
+    constexpr bool ICA1 = MODE == kModeIca1, ICA2 = MODE == kModeIca2;
+    constexpr bool NOCOEF = SPEC || PART || ICA1; // no coefficient block read from memory
+    constexpr bool TWOX = KIND == kKindGeneral;   // two views per feature tile
+    constexpr int CPT = NOCOEF ? 1 : (NC + kNT - 1) / kNT;
     __shared__ T red[4][FT * KP];
     __shared__ T avt[FT * KP], bvt[FT * KP], gt[FT * KP];
     __shared__ CoefTile<T, KP> C;
@@ -794,6 +907,11 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
             opA = PQ; opB = QQ;
         }
         Xb = Xa; ldb = lda;
+    } else if (KIND == kKindICA) { // first pass: A side X^T Q = S2, B side X^T P = S1;
+                                   // second pass: A side X^T R = S3 (R stored in Q)
+        Xa = X; lda = a.ldx; Xb = X; ldb = a.ldx;
+        nf = a.dx; fbase = 0; f0 = (int64_t)tile * FT;
+        opA = QQ; opB = PQ;
     } else {                 // GENERAL: A_t V = Y^T Q / b, B_t V = X^T P / b + eps V
         Xa = Y; lda = a.ldy; Xb = X; ldb = a.ldx;
         nf = a.dx; fbase = 0; f0 = (int64_t)tile * FT;
@@ -825,7 +943,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
             }
     double t_it = 0.0; // helper waves: this iteration's number (set by k_fwd)
     if (main_w) {
-    if (!SPEC && !PART) {
+    if (!NOCOEF) {
 #pragma unroll
         for (int q = 0; q < CPT; ++q) {
             const int e = tid + q * kNT;
@@ -833,7 +951,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
         }
     }
 #pragma unroll
-    for (int q = 0; q < (PART ? 0 : EPT); ++q) {
+    for (int q = 0; q < ((PART || ICA1) ? 0 : EPT); ++q) {
         const int e = tid + q * kNT;
         const int fl = 4 * (e / (4 * KP)) + (e & 3);
         const bool ok = f0 + fl < nf;
@@ -862,7 +980,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
         ma[jm] = mbm[jm] = sa[jm] = sb[jm] = T(0);
         if (CENTER && !FIN) {
             ma[jm] = muA[fcl[jm]];
-            mbm[jm] = KIND == kKindCCA ? ma[jm] : muB[fcl[jm]];
+            mbm[jm] = !TWOX ? ma[jm] : muB[fcl[jm]];
         }
     }
     const SGEP_G T *pa[NB], *pb[NB]; // player (nb*16 + m): rows r..r+3 at p[r * KP]
@@ -893,13 +1011,13 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
                 const int64_t row = r4 + j;
                 if (vrun) {
                     VecLoad<T, MB>::run(Xa + row * lda + fs, xa[u][j]);
-                    if (KIND != kKindCCA)
+                    if (TWOX)
                         VecLoad<T, MB>::run(Xb + row * ldb + fs, xb[u][j]);
                 } else {
 #pragma unroll
                     for (int jm = 0; jm < MB; ++jm) {
                         xa[u][j][jm] = Xa[row * lda + fcl[jm]];
-                        if (KIND != kKindCCA)
+                        if (TWOX)
                             xb[u][j][jm] = Xb[row * ldb + fcl[jm]];
                     }
                 }
@@ -907,7 +1025,8 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 VecLoad<T, 4>::run(pa[nb] + r4 * KP, ba[u][nb]);
-                VecLoad<T, 4>::run(pb[nb] + r4 * KP, bb[u][nb]);
+                if (!ICA2) // the second ICA pass has the A side only
+                    VecLoad<T, 4>::run(pb[nb] + r4 * KP, bb[u][nb]);
             }
         }
         __builtin_amdgcn_sched_barrier(0); // all of the batch's loads first
@@ -920,19 +1039,21 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
                 for (int jm = 0; jm < MB; ++jm) {
                     const bool ok = gv && fok[jm];
                     const T va = ok ? (CENTER ? xa[u][j][jm] - ma[jm] : xa[u][j][jm]) : T(0);
-                    const T vb = KIND == kKindCCA
+                    const T vb = !TWOX
                                      ? va
                                      : (ok ? (CENTER ? xb[u][j][jm] - mbm[jm] : xb[u][j][jm])
                                            : T(0));
                     if (CENTER) {
                         sa[jm] += va;
-                        if (KIND != kKindCCA)
+                        if (TWOX)
                             sb[jm] += vb;
                     }
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb) {
                         aA[j & 1][jm][nb] = Mfma<T>::fma(va, ba[u][nb][j], aA[j & 1][jm][nb]);
-                        aB[j & 1][jm][nb] = Mfma<T>::fma(vb, bb[u][nb][j], aB[j & 1][jm][nb]);
+                        if (!ICA2)
+                            aB[j & 1][jm][nb] =
+                                Mfma<T>::fma(vb, bb[u][nb][j], aB[j & 1][jm][nb]);
                     }
                 }
         }
@@ -950,22 +1071,24 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
                 const T va = ok ? (CENTER ? Xa[row * lda + fcl[jm]] - ma[jm]
                                           : Xa[row * lda + fcl[jm]])
                                 : T(0);
-                const T vb = KIND == kKindCCA
+                const T vb = !TWOX
                                  ? va
                                  : (ok ? (CENTER ? Xb[row * ldb + fcl[jm]] - mbm[jm]
                                                  : Xb[row * ldb + fcl[jm]])
                                        : T(0));
                 if (CENTER) {
                     sa[jm] += va;
-                    if (KIND != kKindCCA)
+                    if (TWOX)
                         sb[jm] += vb;
                 }
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     const T qa = rv ? opA[qidx<KP>(row, nb * 16 + m)] : T(0);
-                    const T qb = rv ? opB[qidx<KP>(row, nb * 16 + m)] : T(0);
                     aA[0][jm][nb] = Mfma<T>::fma(va, qa, aA[0][jm][nb]);
-                    aB[0][jm][nb] = Mfma<T>::fma(vb, qb, aB[0][jm][nb]);
+                    if (!ICA2) {
+                        const T qb = rv ? opB[qidx<KP>(row, nb * 16 + m)] : T(0);
+                        aB[0][jm][nb] = Mfma<T>::fma(vb, qb, aB[0][jm][nb]);
+                    }
                 }
             }
         }
@@ -1004,7 +1127,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
         }
     }
     if (main_w) {
-        if (!SPEC && !PART) {
+        if (!NOCOEF) {
 #pragma unroll
             for (int q = 0; q < CPT; ++q) {
                 const int e = tid + q * kNT;
@@ -1058,7 +1181,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
         coef_T<T, KP>(a, gs, dInv, dS, C.Tl, Td, tid - kNT, kNT);
     }
     __syncthreads();
-    if (main_w && !FIN) {
+    if (main_w && !FIN && !ICA2) {
 #pragma unroll
         for (int jm = 0; jm < MB; ++jm)
 #pragma unroll
@@ -1069,7 +1192,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
                     red[w][(MB * Mfma<T>::drow(kk, r) + jm) * KP + nb * 16 + m] = s[r];
             }
     }
-    if (main_w && !PART) {
+    if (main_w && !PART && !ICA1) {
 #pragma unroll
         for (int q = 0; q < EPT; ++q) {
             const int e = tid + q * kNT;
@@ -1080,9 +1203,48 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
         coef_rows<T, KP, KIND>(a, gs, ss, dInv, dS, Td, ema, t_it, C, tile == 0, tid - kNT);
     }
     __syncthreads();
-    if (main_w && !FIN) {
+    if (main_w && !FIN && !ICA2) {
         for (int e = tid; e < FT * KP; e += kNT)
             bvt[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    }
+    if (ICA2) {
+        // B side S1 and A side S2 - tr(C_t) S1 - 2 S3 (each b times the
+        // products of the raw players), S1 and S2 from the first pass
+        const SGEP_G T *S1 = (const SGEP_G T *)a.S1, *S2 = (const SGEP_G T *)a.S2;
+        const T tr = C.pad;
+        for (int e = tid; e < FT * KP; e += kNT) {
+            const int fl = e / KP, i = e % KP;
+            T s1 = T(0), s2 = T(0);
+            if (f0 + fl < nf) {
+                const int64_t qi = tbase + (int64_t)(fl / 4) * 4 * KP + 4 * i + (fl & 3);
+                s1 = S1[qi];
+                s2 = S2[qi];
+            }
+            bvt[e] = s1;
+            avt[e] = s2 - tr * s1 - T(2) * avt[e];
+        }
+    }
+    if (ICA1) {
+        // S1 = X^T P and S2 = X^T Q of this tile to memory (quad-interleaved),
+        // and the tile's partial of S1^T S1 (lower triangle, FP64)
+        __syncthreads();
+        SGEP_G T *S1 = (SGEP_G T *)a.S1, *S2 = (SGEP_G T *)a.S2;
+        for (int e = tid; e < FT * KP; e += kNT) {
+            const int fl = 4 * (e / (4 * KP)) + (e & 3), i = (e / 4) % KP;
+            if (f0 + fl < nf) {
+                S1[tbase + e] = bvt[fl * KP + i];
+                S2[tbase + e] = avt[fl * KP + i];
+            }
+        }
+        for (int e = tid; e < TRI; e += kNT) {
+            int i, j;
+            tri_ij(e, i, j);
+            double sum = 0.0;
+            for (int fl = 0; fl < FT; ++fl)
+                sum += (double)bvt[fl * KP + i] * (double)bvt[fl * KP + j];
+            ((SGEP_G double *)a.bb_part)[(int64_t)tile * TRI + e] = sum;
+        }
+        return;
     }
     if (PART) {
         // this slice's products for the finishing pass

@@ -1,0 +1,104 @@
+"""GPU parity of the ICA problem (kurtosis form of Sec. 1: A = E[<x,x> x x^T]
+- tr(C) C - 2 C^2, B = C + eps I, every term from the one minibatch) against
+the FP64 oracle, through the C ABI: the four-launch iteration (forward with
+row norms, first backward pass, second forward pass with the coefficient
+block, second backward pass with the update), ragged features and rows,
+16, 32 and 64 player tiles, SGD and Adam.  Bars: FP64 1e-11; FP32 the Alg. 2
+bars times 5, because the A side cancels: E[<x,x> x x^T] and tr(C) C are both
+about d times larger than their difference."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32_1, TOL32_N = 1e-4, 1.5e-3
+
+
+def _sg():
+    import paper_2206_04993_amd as sg
+    sg.load()
+    return sg
+
+
+def _run(cfg, gen, sizes, V0, checkpoints, f64):
+    import torch
+    sg = _sg()
+    tdt, ndt = (torch.float64, np.float64) if f64 else (torch.float32, np.float32)
+    s = sg.Solver(cfg, V0)
+    pb = oracle.Problem(oracle.KIND_ICA, cfg.k, cfg.dx, 0, eps_reg=cfg.eps_reg, rho=cfg.rho,
+                        optimizer=cfg.optimizer)
+    st = oracle.State.init(V0, adam=cfg.optimizer == sg.SGEP_ADAM)
+    out = []
+    for t, n in enumerate(sizes, start=1):
+        X, _ = gen.batch(t, n)
+        Xr = X.astype(ndt).astype(np.float64)
+        s.step(torch.from_numpy(Xr).to("cuda", tdt).contiguous(), None)
+        eta = oracle.eta(cfg.schedule, t, cfg.eta0, cfg.eta_T, cfg.t0, cfg.t_c, cfg.T)
+        oracle.gamma_step(pb, st, Xr, None, eta, cfg.gamma)
+        if t in checkpoints:
+            out.append((t, s.vectors(), st.V.copy(), s.auxiliary(), st.G.copy(), s.eigvals(),
+                        st.eigvals()))
+    names = s.kernel_names()
+    s.close()
+    return out, names
+
+
+def _check(res, tol1, tolN, label):
+    for t, vg, vo, gg, go, lg, lo in res:
+        dv = float(np.abs(vg - vo).max())
+        dg = float(np.abs(gg - go).max()) / max(1.0, float(np.abs(go).max()))
+        print(f"{label} t={t} dV={dv:.2e} dG={dg:.2e}", flush=True)
+        tol = tol1 if t == 1 else tolN
+        assert dv < tol and dg < tol, (t, dv, dg)
+        assert np.allclose(lg, lo, rtol=10 * tol, atol=10 * tol), (t, lg, lo)
+
+
+@pytest.mark.parametrize("adam", [False, True])
+def test_ica_f64_parity(adam):
+    sg = _sg()
+    d, k = 40, 6
+    gen = synth.ICAMixed(d=d, kurtosis=(12.0, 8.0, 5.0, 3.0, 2.0, 1.0), seed=1)
+    cfg = sg.make_config(sg.SGEP_KIND_ICA, sg.SGEP_F64, k, d, 0, 300,
+                         optimizer=sg.SGEP_ADAM if adam else sg.SGEP_SGD,
+                         schedule=sg.SGEP_SCHED_INV, eta0=2e-3 if adam else 0.01, t0=50.0,
+                         gamma=0.5, rho=1e-6, eps_reg=1e-3)
+    sizes = [300, 257, 31, 300, 1, 300] * 5
+    res, names = _run(cfg, gen, sizes, synth.initial_players(d, k, 1), {1, len(sizes)}, True)
+    assert names == ("k_fwd", "k_bwd1", "k_fwd2", "k_bwd")
+    _check(res, TOL64, TOL64, f"f64 ica adam={adam}")
+
+
+@pytest.mark.parametrize("d,k,b", [(72, 13, 200), (130, 20, 77), (100, 40, 64)])
+def test_ica_f32_parity(d, k, b):
+    sg = _sg()
+    gen = synth.ICAMixed(d=d, kurtosis=tuple(np.linspace(12.0, 1.0, min(k, 8))), seed=d)
+    cfg = sg.make_config(sg.SGEP_KIND_ICA, sg.SGEP_F32, k, d, 0, b,
+                         schedule=sg.SGEP_SCHED_INV, eta0=0.01, t0=50.0, gamma=0.5, rho=1e-6,
+                         eps_reg=1e-3)
+    sizes = [b, b - 5, b] * 7
+    res, _ = _run(cfg, gen, sizes, synth.initial_players(d, k, 2), {1, len(sizes)}, False)
+    _check(res, TOL32_1, TOL32_N, f"f32 ica d={d} k={k}")
+
+
+def test_ica_determinism_and_argument_errors():
+    import torch
+    sg = _sg()
+    d, k, b = 72, 8, 128
+    gen = synth.ICAMixed(d=d, kurtosis=(9.0, 6.0, 3.0), seed=4)
+    cfg = sg.make_config(sg.SGEP_KIND_ICA, sg.SGEP_F32, k, d, 0, b, eta0=0.01, gamma=0.5)
+    Xs = [torch.from_numpy(gen.batch(t, b)[0].astype(np.float32)).cuda() for t in range(1, 6)]
+    runs = []
+    for _ in range(2):
+        s = sg.Solver(cfg, synth.initial_players(d, k, 3))
+        for X in Xs:
+            s.step(X, None)
+        runs.append((s.vectors(), s.auxiliary()))
+        if _ == 0:
+            with pytest.raises(sg.SgepError):   # ICA takes one stream
+                sg.sgep_step(s.h, Xs[0], d, Xs[0], d, b)
+        s.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
