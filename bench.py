@@ -70,6 +70,14 @@ WORKLOADS = {
                  "per-feature offsets N(0, 1), centred by running means of the views; "
                  "eta warms up over 100 steps while the means settle, then decays "
                  "harmonically"),
+    "ica_d1024_k16_b1024_fp32": dict(
+        kind="ica", dtype="f32", dx=1024, dy=0, k=16, b=1024, ring=128,
+        optimizer="adam", schedule="inv", eta0=1e-3, t0=1000.0, gamma=0.3, rho=1e-6,
+        eps_reg=1e-4, generator="ica_mixed",
+        tta=dict(targets=(1e-1, 7e-2), max_steps=60_000, every=1000),
+        describe="ICA (kurtosis form): d=1024 orthogonal mixtures of 16 Bernoulli-Gaussian "
+                 "sources with excess kurtosis linspace(20, 2, 16) and 1008 Gaussian ones, "
+                 "k=16, minibatch 1024, B ridge 1e-4"),
     "cca_d16_k4_b128_fp64": dict(
         kind="cca", dtype="f64", dx=8, dy=8, k=4, b=128, ring=128,
         optimizer="sgd", schedule="inv", eta0=1.0, t0=200.0, gamma=1.0, rho=1e-6,
@@ -122,6 +130,7 @@ DEFAULT = "cca_d1024_k16_b1024_fp32"
 # the header holding each kernel's code
 KERNEL_HEADER = {"k_fwd": "sgep_kernels.hpp", "k_bwd": "sgep_kernels.hpp",
                  "k_coef": "sgep_kernels.hpp", "k_bwdp": "sgep_kernels.hpp",
+                 "k_bwd1": "sgep_kernels.hpp", "k_fwd2": "sgep_kernels.hpp",
                  "k_wfwd": "sgep_wide.hpp", "k_wmid": "sgep_wide.hpp", "k_wbwd": "sgep_wide.hpp",
                  "k_bfwd": ("sgep_kernels.hpp", "sgep_batch.hpp"),
                  "k_bcoef": ("sgep_kernels.hpp", "sgep_batch.hpp"),
@@ -179,6 +188,8 @@ def _generator(w):
         return synth.CCAActivation(dx=w["dx"], dy=w["dy"], seed=0)
     if g == "lda_classes":
         return synth.LDAClasses(d=w["dx"], c=w["n_classes"], seed=0)
+    if g == "ica_mixed":
+        return synth.ICAMixed(d=w["dx"], kurtosis=tuple(np.linspace(20.0, 2.0, 16)), seed=0)
     return synth.tiny_cca_pool(0)[1]
 
 
@@ -238,7 +249,7 @@ def encode(w, X, scales=None):
 def config_for(sg, w):
     dtype = {"f64": sg.SGEP_F64, "f32": sg.SGEP_F32, "bf16": sg.SGEP_BF16,
              "fp8": sg.SGEP_FP8_E4M3}[w["dtype"]]
-    kind = {"cca": sg.SGEP_KIND_CCA, "lda": sg.SGEP_KIND_LDA}[w["kind"]]
+    kind = {"cca": sg.SGEP_KIND_CCA, "lda": sg.SGEP_KIND_LDA, "ica": sg.SGEP_KIND_ICA}[w["kind"]]
     return sg.make_config(
         kind, dtype, w["k"], w["dx"], w["dy"], w["b"],
         optimizer=sg.SGEP_ADAM if w["optimizer"] == "adam" else sg.SGEP_SGD,
@@ -264,6 +275,14 @@ def algorithmic_work(w, kernel, names=()):
     data = b * d * e + (4 * b if lda else 0)
     se = 8 if w["dtype"] == "f64" else 4                       # state element
     state = (4 + (4 if adam else 0)) * se * d * k               # V, G (+ moments) read + written
+    if w["kind"] == "ica":  # four passes: P; X^T [P|Q]; X C V; X^T X C V + update
+        if kernel == "k_fwd":
+            return 2.0 * b * d * k, float(data + se * d * k + se * 2 * b * k)
+        if kernel == "k_bwd1":
+            return 4.0 * b * d * k, float(data + se * 2 * b * k + se * 2 * d * k)
+        if kernel == "k_fwd2":
+            return 2.0 * b * d * k, float(data + se * d * k + se * b * k)
+        return 2.0 * b * d * k, float(data + se * b * k + se * 2 * d * k + state)
     if kernel == "k_fwd":
         return 2.0 * b * d * k, float(data + se * d * k + se * 2 * b * k)
     if kernel == "k_coef":  # the Gram partials of the forward row tiles, once
@@ -296,7 +315,8 @@ def cpu_baseline(w, budget_s: float, host):
         gen = _generator(w)
         extra = dict(class_means=gen.means,
                      class_priors=np.full(w["n_classes"], 1.0 / w["n_classes"]))
-    pb = oracle.Problem(oracle.KIND_LDA if lda else oracle.KIND_CCA, w["k"], w["dx"], w["dy"],
+    okind = {"cca": oracle.KIND_CCA, "lda": oracle.KIND_LDA, "ica": oracle.KIND_ICA}[w["kind"]]
+    pb = oracle.Problem(okind, w["k"], w["dx"], w["dy"],
                         rho=w["rho"], eps_reg=w.get("eps_reg", 0.0),
                         optimizer=oracle.OPT_ADAM if w["optimizer"] == "adam" else oracle.OPT_SGD,
                         smooth=bool(w.get("smooth", 0)), nu=w.get("nu", 0.0),
@@ -361,7 +381,17 @@ def time_to_accuracy(w, targets, max_steps: int, every: int, hyper=None, log=Non
     store = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
              "fp8": torch.uint8}[fmt]
     aux = {}
-    if w["generator"] == "medium_cca":
+    if w["generator"] == "ica_mixed":
+        gen = _generator(w)
+        _, Vs = otargets.ica_planted_topk(gen, k)
+        A_, B = otargets.ica_population_AB(gen)
+        B = B + w.get("eps_reg", 0.0) * np.eye(d)
+        ref = "population solution of the generator (mixing columns of the most kurtotic sources)"
+
+        def fill(c, Xb, Yb):
+            Xb.copy_(gen.sample_torch(E * b, 1_000_000 + c, "cuda", torch.float32)
+                     .to(store).view(E, b, -1))
+    elif w["generator"] == "medium_cca":
         gen = synth.medium_cca(0)
         _, Vs = otargets.cca_planted_topk(gen, k)
         _, B = otargets.cca_population_AB(gen)
@@ -405,7 +435,8 @@ def time_to_accuracy(w, targets, max_steps: int, every: int, hyper=None, log=Non
             Xb.copy_(PX.index_select(0, it).view(E, b, -1))
             Yb.copy_(PY.index_select(0, it).view(E, b, -1))
     Xb = torch.empty((E, b, w["dx"]), device="cuda", dtype=store)
-    Yb = torch.empty((E, b, w["dy"]), device="cuda", dtype=store)
+    Yb = (torch.empty((E, b, w["dy"]), device="cuda", dtype=store) if w["dy"] else
+          [None] * E)
     stream = torch.cuda.Stream()
     solver = sg.Solver(config_for(sg, w), synth.initial_players(d, k, 0), stream=stream, **aux)
     fill(0, Xb, Yb)
@@ -441,8 +472,8 @@ def time_to_accuracy(w, targets, max_steps: int, every: int, hyper=None, log=Non
             break
     solver.close()
     out = {"targets": {}, "eval_every_steps": E, "reference": ref,
-           "stream": ("fresh device-drawn pairs" if w["generator"] == "medium_cca" else
-                      "i.i.d. minibatches of the pool") + f", stored as {fmt}",
+           "stream": ("fresh device-drawn samples" if w["generator"] in ("medium_cca", "ica_mixed")
+                      else "i.i.d. minibatches of the pool") + f", stored as {fmt}",
            "final_error": hist[-1][2], "steps_run": steps, "gpu_seconds_run": round(t_gpu, 4)}
     for tg in targets:
         h = hits.get(tg)
@@ -689,6 +720,8 @@ def main():
         if lda:
             ty = torch.from_numpy(np.ascontiguousarray(Yr, dtype=np.int32))
             vy = ty.numpy()
+        elif Yr is None:  # one stream (ICA)
+            ty, vy = None, None
         else:
             ty, vy = encode(w, Yr, scales[1] if scales else None)
         Xs.append(tx)
@@ -697,7 +730,7 @@ def main():
             host.append((vx, vy))
     del raw
     X = torch.stack(Xs).to("cuda").contiguous()
-    Y = torch.stack(Ys).to("cuda").contiguous()
+    Y = torch.stack(Ys).to("cuda").contiguous() if Ys[0] is not None else [None] * R
     del Xs, Ys
     torch.cuda.synchronize()
     stream = torch.cuda.Stream()
@@ -751,6 +784,8 @@ def main():
         ev = [evs[2 * nk * t + i].value for i in range(2 * nk)]
         if lda:
             sg.sgep_step_profiled(solver.h, X[s], X[s].stride(0), None, 0, Y[s], b, ev)
+        elif Y[s] is None:
+            sg.sgep_step_profiled(solver.h, X[s], X[s].stride(0), None, 0, None, b, ev)
         else:
             sg.sgep_step_profiled(solver.h, X[s], X[s].stride(0), Y[s], Y[s].stride(0), None, b,
                                   ev)
