@@ -277,7 +277,7 @@ sgep_status launch_step_c(sgep_handle *h, const StepArgs &a, void *const *events
     constexpr int MBW = mb_wide<T>(KP);
     constexpr bool can_spec = KP * (int)sizeof(T) <= 128; // spec_mode's player-tile bound
     if (split) {
-        const dim3 gp(h->n_tiles * h->nsplit + 1); // + the coefficient workgroup
+        const dim3 gp(h->n_tiles * h->nsplit + 8); // + the coefficient workgroup and 7 idle
         if (cca)
             launch_timed(sgep::k_bwdp<T, KP, sgep::kKindCCA, C>, gp, h->stream, ev[2], ev[3], a);
         else

@@ -1353,19 +1353,23 @@ __global__ void __launch_bounds__(MODE == kModeSpec ? 2 * kNT : kNT) k_bwd(StepA
 }
 
 // Row-split backward, first pass: workgroup 0 computes the iteration's
-// coefficient block (coef_body; first, as the longest), and n_tiles * nsplit
-// more compute one row slice of one 16-feature tile each (block b >= 1:
-// tile (b - 1) / nsplit, slice (b - 1) % nsplit).  The second pass is k_bwd
+// coefficient block (coef_body; first, as the longest) and workgroups 1..7
+// only align the rest to the XCDs; workgroups 8.. compute one row slice of
+// one 16-feature tile each.  Partial j = xcd_tile(b - 8) is tile j / nsplit,
+// slice j % nsplit, so each XCD takes a contiguous run of tiles with all
+// their slices: neighbouring tiles share the 128-byte lines of a minibatch
+// row, which are then fetched into one L2 only.  The second pass is k_bwd
 // with kModeFin.
 template <typename T, int KP, int KIND, bool CENTER = false>
 __global__ void __launch_bounds__(kNT) k_bwdp(StepArgs a)
 {
-    if (blockIdx.x == 0) {
-        coef_body<T, KP, KIND>(a);
+    if (blockIdx.x < 8) {
+        if (blockIdx.x == 0)
+            coef_body<T, KP, KIND>(a);
         return;
     }
-    const int b = blockIdx.x - 1;
-    bwd_body<T, KP, 1, KIND, kOptSGD, kModePart, false, CENTER>(a, b / a.nsplit, b % a.nsplit);
+    const int j = xcd_tile(blockIdx.x - 8, (a.n_tx + a.n_ty) * a.nsplit);
+    bwd_body<T, KP, 1, KIND, kOptSGD, kModePart, false, CENTER>(a, j / a.nsplit, j % a.nsplit);
 }
 
 // ---------------------------------------------------------------------------
