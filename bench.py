@@ -131,6 +131,7 @@ DEFAULT = "cca_d1024_k16_b1024_fp32"
 KERNEL_HEADER = {"k_fwd": "sgep_kernels.hpp", "k_bwd": "sgep_kernels.hpp",
                  "k_coef": "sgep_kernels.hpp", "k_bwdp": "sgep_kernels.hpp",
                  "k_bwd1": "sgep_kernels.hpp", "k_fwd2": "sgep_kernels.hpp",
+                 "k_coefa": "sgep_kernels.hpp", "k_coefb": "sgep_kernels.hpp",
                  "k_wfwd": "sgep_wide.hpp", "k_wmid": "sgep_wide.hpp", "k_wbwd": "sgep_wide.hpp",
                  "k_bfwd": ("sgep_kernels.hpp", "sgep_batch.hpp"),
                  "k_bcoef": ("sgep_kernels.hpp", "sgep_batch.hpp"),
@@ -285,7 +286,10 @@ def algorithmic_work(w, kernel, names=()):
         return 2.0 * b * d * k, float(data + se * b * k + se * 2 * d * k + state)
     if kernel == "k_fwd":
         return 2.0 * b * d * k, float(data + se * d * k + se * 2 * b * k)
-    if kernel == "k_coef":  # the Gram partials of the forward row tiles, once
+    if kernel == "k_coefb":  # the column totals of k_coefa
+        kp = 16 if k <= 16 else (32 if k <= 32 else 64)
+        return 0.0, float(8 * (kp * (kp + 1) // 2 + kp))
+    if kernel in ("k_coef", "k_coefa"):  # the Gram partials of the forward row tiles, once
         kp = 16 if k <= 16 else (32 if k <= 32 else 64)
         return 0.0, float(8 * (kp * (kp + 1) // 2 + kp) * ((b + 15) // 16))
     if kernel == "k_bwdp":

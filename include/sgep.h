@@ -197,7 +197,9 @@ sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int3
  * sum of the slices and update); else 2 (forward products; backward products,
  * k x k coefficients and update) when the backward tile is one 16-feature
  * block and k * element size <= 128 bytes after padding; else 3 (forward
- * products; k x k coefficients; backward products and update).  ICA: 4
+ * products; k x k coefficients; backward products and update), or 4 when
+ * ceil(b_max / 16) (k'(k'+1)/2 + k') >= 32768 for k' the padded k (the
+ * coefficients' reduction first spread over many workgroups).  ICA: 4
  * (forward products and row norms; X^T P and X^T diag(||x_r||^2) P; the
  * second forward pass X C_t V with the k x k coefficients; X^T X C_t V and
  * update).  BF16 / FP8: 3 (forward products; operand preparation and
@@ -205,7 +207,8 @@ sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int3
 sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n);
 
 /* Short name of kernel i (0 <= i < sgep_kernels_per_step) of one iteration,
- * in launch order: "k_fwd", "k_coef", "k_bwdp", "k_bwd1", "k_fwd2", "k_bwd", "k_wfwd", "k_wmid"
+ * in launch order: "k_fwd", "k_coef", "k_coefa", "k_coefb", "k_bwdp", "k_bwd1", "k_fwd2",
+ * "k_bwd", "k_wfwd", "k_wmid"
  * or "k_wbwd" -- a static string, not to be freed; NULL for a NULL handle or
  * an index out of range. */
 const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i);

@@ -57,6 +57,8 @@ struct sgep_handle_s {
     void *mu = nullptr;    // running means of the views (centring): 2 ldv elements
     void *S1 = nullptr, *S2 = nullptr; // ICA: first backward pass products
     double *bb_part = nullptr;         // ICA: S1^T S1 tile partials
+    double *gsum = nullptr; // column totals of the Gram partials (two-stage coefficients)
+    bool coef2 = false;     // coefficients in two stages (k_coefa, k_coefb)
     void *bpart = nullptr; // the slices' partial products (nsplit > 1)
     int n_tx = 0, n_ty = 0, n_tiles = 0;
     int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
@@ -112,7 +114,7 @@ void free_all(sgep_handle *h)
     void *ptrs[] = {h->V,  h->G,        h->Am,      h->As,    h->P,  h->Q,    h->gram_part,
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
                     h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
-                    h->mu,   h->S1, h->S2,     h->bb_part};
+                    h->mu,   h->S1, h->S2,     h->bb_part, h->gsum};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -258,16 +260,18 @@ void launch_bwd(sgep_handle *h, const StepArgs &a, hipEvent_t e0, hipEvent_t e1)
                      nt);
 }
 
+int narrow_kernels(const sgep_handle *h);
+
 // one iteration; C: the views are centred by their running means
 template <typename T, int KP, bool C>
 sgep_status launch_step_c(sgep_handle *h, const StepArgs &a, void *const *events)
 {
     const dim3 gf(a.n_fwd + 1); // + the norm-totals workgroup
-    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     const bool split = h->nsplit > 1;
     const bool spec = !split && spec_mode<T>(KP, h->mb);
     if (events)
-        for (int i = 0; i < (spec ? 4 : 6); ++i)
+        for (int i = 0; i < 2 * narrow_kernels(h); ++i)
             ev[i] = (hipEvent_t)events[i];
     const bool cca = h->cfg.kind == SGEP_KIND_CCA;
     if (cca)
@@ -288,15 +292,30 @@ sgep_status launch_step_c(sgep_handle *h, const StepArgs &a, void *const *events
         if constexpr (can_spec)
             launch_bwd<T, KP, 1, sgep::kModeSpec, C>(h, a, ev[2], ev[3]);
     } else {
-        if (cca)
+        int e = 2; // next event pair
+        if (h->coef2) {
+            const int W = KP * (KP + 1) / 2 + KP;
+            launch_timed(sgep::k_coefa<KP>, dim3((W + sgep::kCoefCols - 1) / sgep::kCoefCols),
+                         h->stream, ev[2], ev[3], a, 64);
+            if (cca)
+                launch_timed(sgep::k_coefb<T, KP, sgep::kKindCCA>, dim3(1), h->stream, ev[4],
+                             ev[5], a);
+            else
+                launch_timed(sgep::k_coefb<T, KP, sgep::kKindGeneral>, dim3(1), h->stream, ev[4],
+                             ev[5], a);
+            e = 6;
+        } else if (cca) {
             launch_timed(sgep::k_coef<T, KP, sgep::kKindCCA>, dim3(1), h->stream, ev[2], ev[3], a);
-        else
+            e = 4;
+        } else {
             launch_timed(sgep::k_coef<T, KP, sgep::kKindGeneral>, dim3(1), h->stream, ev[2], ev[3],
                          a);
+            e = 4;
+        }
         if (h->mb == 1)
-            launch_bwd<T, KP, 1, sgep::kModePre, C>(h, a, ev[4], ev[5]);
+            launch_bwd<T, KP, 1, sgep::kModePre, C>(h, a, ev[e], ev[e + 1]);
         else
-            launch_bwd<T, KP, MBW, sgep::kModePre, C>(h, a, ev[4], ev[5]);
+            launch_bwd<T, KP, MBW, sgep::kModePre, C>(h, a, ev[e], ev[e + 1]);
     }
     HIPCHK(hipGetLastError());
     return SGEP_OK;
@@ -343,7 +362,9 @@ int narrow_kernels(const sgep_handle *h)
         return 4;
     const bool spec = h->esz == sizeof(double) ? spec_mode<double>(h->kp, h->mb)
                                                : spec_mode<float>(h->kp, h->mb);
-    return (spec && h->nsplit == 1) ? 2 : 3;
+    if (spec && h->nsplit == 1)
+        return 2;
+    return (h->nsplit == 1 && h->coef2) ? 4 : 3;
 }
 
 template <typename T, int KP>
@@ -881,6 +902,9 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     }
     if (cfg->center)
         alloc(&h->mu, (size_t)2 * h->ldv * h->esz);
+    alloc((void **)&h->gsum, (size_t)h->W * sizeof(double));
+    // many Gram partials: sum their columns over many workgroups first
+    h->coef2 = !ica && h->fwd_blocks_max * h->W >= 32768;
     if (ica) {
         alloc(&h->S1, st_bytes);
         alloc(&h->S2, st_bytes);
@@ -973,6 +997,7 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.S1 = h->S1;
     a.S2 = h->S2;
     a.bb_part = h->bb_part;
+    a.gsum = h->gsum;
     a.nsplit = h->nsplit;
     a.schedule = h->cfg.schedule;
     a.eta0 = h->cfg.eta0;
@@ -1059,6 +1084,7 @@ const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i)
     static const char *pre[] = {"k_fwd", "k_coef", "k_bwd"};
     static const char *split[] = {"k_fwd", "k_bwdp", "k_bwd"};
     static const char *ica[] = {"k_fwd", "k_bwd1", "k_fwd2", "k_bwd"};
+    static const char *pre2[] = {"k_fwd", "k_coefa", "k_coefb", "k_bwd"};
     if (h->wide)
         return i < 3 ? wide[i] : nullptr;
     const int n = narrow_kernels(h);
@@ -1066,6 +1092,8 @@ const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i)
         return nullptr;
     if (h->cfg.kind == SGEP_KIND_ICA)
         return ica[i];
+    if (n == 4)
+        return pre2[i];
     return n == 2 ? spec[i] : (h->nsplit > 1 ? split[i] : pre[i]);
 }
 

@@ -132,6 +132,7 @@ struct StepArgs {
     void *S1, *S2;           // ICA: X^T P and X^T diag(||x_r||^2) P of the iteration,
                              // quad-interleaved like V (raw sums over the rows)
     double *bb_part;         // ICA: [tiles][KP(KP+1)/2] partials of S1^T S1
+    double *gsum;            // column totals of the Gram partials (two-stage k_coef)
     int32_t nsplit;          // row slices of the backward products (kModePart)
     int32_t schedule;
     int32_t smooth;          // Alg. 3 estimate of v_j^T B v_j instead of the clip
@@ -188,12 +189,14 @@ __device__ inline double eta_at(const StepArgs &a, double t)
 // order, for c < W: thread q of nthr takes columns q, q + nthr, ...  Rows
 // are the partials of one workgroup each (W contiguous values), so the
 // threads of a wave read consecutive addresses; R rows per thread are in
-// flight together.  No synchronisation inside (the caller orders the writes
-// to out).  Every caller uses this one order, so all obtain the same bits.
+// flight together (more for the one-workgroup coefficient kernel, which has
+// the registers).  No synchronisation inside (the caller orders the writes
+// to out).  Every caller uses the same order of the sums, so all obtain the
+// same bits.
+template <int R = 32>
 __device__ inline void colsum(const SGEP_G double *__restrict__ part, int n, int ld, int W,
                               double *__restrict__ out, int q, int nthr)
 {
-    constexpr int R = 32;
     for (int c = q; c < W; c += nthr) {
         double s = 0.0;
         for (int r0 = 0; r0 < n; r0 += R) {
@@ -735,7 +738,7 @@ __device__ __forceinline__ void coef_rows(const StepArgs &a, const double *gs, c
 
 // k_coef: one workgroup computes the iteration's coefficient block into
 // a.cpre (used with the backward mode kModePre)
-template <typename T, int KP, int KIND>
+template <typename T, int KP, int KIND, int R = 32, bool PRESUM = false>
 __device__ __forceinline__ void coef_body(const StepArgs &a)
 {
     constexpr int W = KP * (KP + 1) / 2 + KP;
@@ -763,8 +766,11 @@ __device__ __forceinline__ void coef_body(const StepArgs &a)
             gs[TRI + i] = gi[TRI + tri_idx(i, i)];
         if (tid == 0)
             C.pad = (T)tr; // read by the second backward pass
+    } else if (PRESUM) { // the totals of k_coefa, summed in the same order
+        for (int e = tid; e < W; e += kNT)
+            gs[e] = ((const SGEP_G double *)a.gsum)[e];
     } else {
-        colsum((const SGEP_G double *)a.gram_part, a.n_fwd, W, W, gs, tid, kNT);
+        colsum<R>((const SGEP_G double *)a.gram_part, a.n_fwd, W, W, gs, tid, kNT);
     }
     __syncthreads();
     coef_norms<KP>(a, ss, dInv, dS, t, tid);
@@ -781,7 +787,28 @@ __device__ __forceinline__ void coef_body(const StepArgs &a)
 template <typename T, int KP, int KIND>
 __global__ void __launch_bounds__(kNT) k_coef(StepArgs a)
 {
-    coef_body<T, KP, KIND>(a);
+    coef_body<T, KP, KIND, 64>(a);
+}
+
+// Two-stage coefficient kernel for many Gram partials (one CU streams only
+// ~30 GB/s): k_coefa sums 16 columns per workgroup over all rows (thread per
+// column, rows ascending: the order of colsum, so the totals carry the same
+// bits), then k_coefb (one workgroup) computes the block from the totals.
+constexpr int kCoefCols = 16;
+template <int KP>
+__global__ void __launch_bounds__(64) k_coefa(StepArgs a)
+{
+    constexpr int W = KP * (KP + 1) / 2 + KP;
+    const int c0 = blockIdx.x * kCoefCols;
+    const int nc = W - c0 < kCoefCols ? W - c0 : kCoefCols;
+    colsum<64>((const SGEP_G double *)a.gram_part + c0, a.n_fwd, W, nc, a.gsum + c0,
+               threadIdx.x, kCoefCols);
+}
+
+template <typename T, int KP, int KIND>
+__global__ void __launch_bounds__(kNT) k_coefb(StepArgs a)
+{
+    coef_body<T, KP, KIND, 32, true>(a);
 }
 
 // ICA, second forward pass: R = X (S1 / b) = X C_t V for 16-row tiles (S1 =

@@ -207,6 +207,26 @@ def test_f64_general_kp32_parity():
         assert _maxdiff(gg, go) < TOL64 * max(1.0, np.abs(go).max())
 
 
+def test_f64_general_two_stage_coefficients():
+    """Many Gram partials (ceil(b_max / 16) x 560 columns >= 32768): the
+    coefficient reduction runs in two stages (k_coefa over many workgroups,
+    then k_coefb)."""
+    sg = _sg()
+    gen = synth.GeneralPlanted(80, k=8, seed=1)
+    cfg = sg.make_config(sg.SGEP_KIND_GENERAL, sg.SGEP_F64, 24, 80, 80, 1024,
+                         schedule=sg.SGEP_SCHED_CONST, eta0=0.02, gamma=0.3, rho=1e-4,
+                         eps_reg=1e-3)
+    probe = sg.Solver(cfg, synth.initial_players(80, 24, 2))
+    assert probe.kernel_names() == ("k_fwd", "k_coefa", "k_coefb", "k_bwd")
+    probe.close()
+    batches = [gen.batch(t, n) for t, n in enumerate([1024, 1000, 17, 600] * 4, start=1)]
+    res = run_both(cfg, batches, synth.initial_players(80, 24, 2), {1, 16})
+    for t, vg, vo, gg, go, lg, lo in res:
+        print(f"f64 general two-stage coefficients t={t} dV={_maxdiff(vg, vo):.2e}")
+        assert _maxdiff(vg, vo) < TOL64
+        assert _maxdiff(gg, go) < TOL64 * max(1.0, np.abs(go).max())
+
+
 # --------------------------------------------------------------------------- #
 # Row-split backward (CCA, b_max >= 512): two row slices per feature tile,     #
 # minibatches of varying length (ragged last group, empty slices)              #
