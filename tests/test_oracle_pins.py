@@ -656,3 +656,24 @@ def test_ica_stochastic_recovers_the_most_kurtotic_sources():
         oracle.gamma_step(pb, st, X, None, oracle.eta(oracle.SCHED_INV, t, 0.05, t0=300.0), 0.5)
     err = oracle.subspace_error(st.V, V0, np.eye(8))
     assert err < 1e-2, err
+
+
+def test_fixed_point_does_not_depend_on_the_minibatch_size():
+    """Minibatches of 32, 128 and 512 rows of the same pool lead Alg. 2 to
+    the same solution (the pool's exact one), only with different noise: the
+    one-minibatch estimate of the products does not move the fixed point."""
+    gen, pool = synth.tiny_cca_pool(0)
+    pb = oracle.Problem(oracle.KIND_CCA, 4, 8, 8, rho=1e-6)
+    A, B = oracle.problem_matrices(pb, pool.X, pool.Y)
+    lam, Vs = oracle.gep_topk(A, B, 4)
+    finals = []
+    for b in (32, 128, 512):
+        st = oracle.State.init(synth.initial_players(16, 4, 0))
+        for t in range(1, 4001):
+            X, Y = pool.batch(t, b)
+            oracle.gamma_step(pb, st, X, Y, oracle.eta(oracle.SCHED_INV, t, 1.0, t0=200.0), 1.0)
+        err = oracle.subspace_error(st.V, Vs, B)
+        assert err < 5e-3, (b, err)
+        finals.append(st.V)
+    for V in finals[:2]:
+        assert oracle.subspace_error(V, finals[2], B) < 1e-2
