@@ -674,6 +674,6 @@ def test_fixed_point_does_not_depend_on_the_minibatch_size():
             oracle.gamma_step(pb, st, X, Y, oracle.eta(oracle.SCHED_INV, t, 1.0, t0=200.0), 1.0)
         err = oracle.subspace_error(st.V, Vs, B)
         assert err < 5e-3, (b, err)
-        finals.append(st.V)
-    for V in finals[:2]:
-        assert oracle.subspace_error(V, finals[2], B) < 1e-2
+        finals.append(err)
+    # the noise, not the limit, depends on b: larger minibatches end closer
+    assert finals[2] < finals[0]
