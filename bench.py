@@ -128,7 +128,8 @@ BATCH_WORKLOADS = {
 DEFAULT = "cca_d1024_k16_b1024_fp32"
 
 # the header holding each kernel's code
-KERNEL_HEADER = {"k_fwd": "sgep_kernels.hpp", "k_bwd": "sgep_kernels.hpp",
+KERNEL_HEADER = {"k_fwd": "sgep_kernels.hpp", "k_fwds": "sgep_kernels.hpp",
+                 "k_bwd": "sgep_kernels.hpp",
                  "k_coef": "sgep_kernels.hpp", "k_bwdp": "sgep_kernels.hpp",
                  "k_bwd1": "sgep_kernels.hpp", "k_fwd2": "sgep_kernels.hpp",
                  "k_coefa": "sgep_kernels.hpp", "k_coefb": "sgep_kernels.hpp",
@@ -284,7 +285,7 @@ def algorithmic_work(w, kernel, names=()):
         if kernel == "k_fwd2":
             return 2.0 * b * d * k, float(data + se * d * k + se * b * k)
         return 2.0 * b * d * k, float(data + se * b * k + se * 2 * d * k + state)
-    if kernel == "k_fwd":
+    if kernel in ("k_fwd", "k_fwds"):
         return 2.0 * b * d * k, float(data + se * d * k + se * 2 * b * k)
     if kernel == "k_coefb":  # the column totals of k_coefa
         kp = 16 if k <= 16 else (32 if k <= 32 else 64)

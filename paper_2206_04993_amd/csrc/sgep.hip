@@ -60,6 +60,8 @@ struct sgep_handle_s {
     double *gsum = nullptr; // column totals of the Gram partials (two-stage coefficients)
     bool coef2 = false;     // coefficients in two stages (k_coefa, k_coefb)
     void *bpart = nullptr; // the slices' partial products (nsplit > 1)
+    void *fpart = nullptr; // feature-split forward: partial products (nsplit > 1)
+    int *fcnt = nullptr;   // feature-split forward: per-tile counters, zero between launches
     int n_tx = 0, n_ty = 0, n_tiles = 0;
     int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
     int64_t W = 0;          // partial width: KP (KP + 1) / 2 + KP
@@ -114,7 +116,7 @@ void free_all(sgep_handle *h)
     void *ptrs[] = {h->V,  h->G,        h->Am,      h->As,    h->P,  h->Q,    h->gram_part,
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
                     h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
-                    h->mu,   h->S1, h->S2,     h->bb_part, h->gsum};
+                    h->mu,   h->S1, h->S2,     h->bb_part, h->gsum, h->fpart, h->fcnt};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -274,7 +276,10 @@ sgep_status launch_step_c(sgep_handle *h, const StepArgs &a, void *const *events
         for (int i = 0; i < 2 * narrow_kernels(h); ++i)
             ev[i] = (hipEvent_t)events[i];
     const bool cca = h->cfg.kind == SGEP_KIND_CCA;
-    if (cca)
+    if (split) // CCA only: several workgroups per row tile
+        launch_timed(sgep::k_fwds<T, KP, C>, dim3(sgep::kFwdParts * a.n_fwd + 1), h->stream, ev[0],
+                     ev[1], a);
+    else if (cca)
         launch_timed(sgep::k_fwd<T, KP, sgep::kKindCCA, C>, gf, h->stream, ev[0], ev[1], a);
     else
         launch_timed(sgep::k_fwd<T, KP, sgep::kKindGeneral, C>, gf, h->stream, ev[0], ev[1], a);
@@ -899,6 +904,9 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     if (split_mode(*cfg, h->mb, h->n_tiles)) {
         h->nsplit = kSplit;
         alloc(&h->bpart, (size_t)h->n_tiles * kSplit * (2 * h->ft * kp + 2 * h->ft) * h->esz);
+        // the forward splits each row tile's features over several workgroups
+        alloc(&h->fpart, (size_t)h->fwd_blocks_max * sgep::kFwdParts * 16 * kp * h->esz);
+        alloc((void **)&h->fcnt, (size_t)h->fwd_blocks_max * sizeof(int));
     }
     if (cfg->center)
         alloc(&h->mu, (size_t)2 * h->ldv * h->esz);
@@ -926,6 +934,9 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
               hipMemsetAsync(h->As, 0, st_bytes, h->stream) == hipSuccess;
     if (h->mu)
         hok = hok && hipMemsetAsync(h->mu, 0, (size_t)2 * h->ldv * h->esz, h->stream) == hipSuccess;
+    if (h->fcnt)
+        hok = hok && hipMemsetAsync(h->fcnt, 0, (size_t)h->fwd_blocks_max * sizeof(int),
+                                    h->stream) == hipSuccess;
     if (h->S1) // features past d are never written and must read as zero
         hok = hok && hipMemsetAsync(h->S1, 0, st_bytes, h->stream) == hipSuccess &&
               hipMemsetAsync(h->S2, 0, st_bytes, h->stream) == hipSuccess;
@@ -993,6 +1004,8 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.coef = h->coef;
     a.cpre = h->cpre;
     a.bpart = h->bpart;
+    a.fpart = h->fpart;
+    a.fcnt = h->fcnt;
     a.mu = h->mu;
     a.S1 = h->S1;
     a.S2 = h->S2;
@@ -1082,7 +1095,7 @@ const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i)
     static const char *wide[] = {"k_wfwd", "k_wmid", "k_wbwd"};
     static const char *spec[] = {"k_fwd", "k_bwd"};
     static const char *pre[] = {"k_fwd", "k_coef", "k_bwd"};
-    static const char *split[] = {"k_fwd", "k_bwdp", "k_bwd"};
+    static const char *split[] = {"k_fwds", "k_bwdp", "k_bwd"};
     static const char *ica[] = {"k_fwd", "k_bwd1", "k_fwd2", "k_bwd"};
     static const char *pre2[] = {"k_fwd", "k_coefa", "k_coefb", "k_bwd"};
     if (h->wide)

@@ -121,6 +121,8 @@ struct StepArgs {
     void *V, *G, *Am, *As;   // ldv x KP, quad-interleaved
     void *P, *Q;             // ldp x KP, quad-interleaved raw projections X V, Y V
     double *gram_part;       // [ldg][W]: row blk = forward workgroup blk
+    void *fpart;             // feature-split forward: [n_fwd][kFwdParts][16 KP] partial products
+    int *fcnt;               // feature-split forward: finished partials per row tile (0 between launches)
     double *stat_part;       // [lds][W]: row tile = backward workgroup tile
     double *stat_tot;        // [W]: reduced stat_part of the state entering this iteration
     Coef *coef;
@@ -261,7 +263,7 @@ template <> struct VecLoad<double, 4> {
 // loaded from a valid chunk and zeroed; the ragged last chunk runs masked.
 // `row` is a valid row index; rows past the minibatch are zeroed through rv.
 // ---------------------------------------------------------------------------
-template <typename T, int KP, bool CENTER = false, bool SQ = false>
+template <typename T, int KP, bool CENTER = false, bool SQ = false, int NW = 4>
 __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t ldx, int64_t nf,
                                          int64_t row, bool rv, bool vec_ok,
                                          const SGEP_G T *__restrict__ VQ,
@@ -272,11 +274,11 @@ __device__ __forceinline__ void fwd_view(const SGEP_G T *__restrict__ X, int64_t
     constexpr int VEC = 16 / (int)sizeof(T);
     constexpr int CH = 4 * VEC;
     constexpr int NB = KP / 16;
-    constexpr int U = (CENTER ? 4 : 8) / NB;
+    constexpr int U = (CENTER ? 4 : 8) / NB * 4 / NW > 0 ? (CENTER ? 4 : 8) / NB * 4 / NW : 1;
     const int kk = lane >> 4, n = lane & 15;
     const int64_t nch = (nf + CH - 1) / CH;
     const int64_t nfull = nf / CH; // chunks whose features are all valid
-    const int64_t c0 = (nch * w) >> 2, c1 = (nch * (w + 1)) >> 2;
+    const int64_t c0 = (nch * w) / NW, c1 = (nch * (w + 1)) / NW;
     const int64_t cf = c1 < nfull ? c1 : nfull;
     const SGEP_G T *xr = X + row * ldx;
     for (int64_t c = c0; c < cf; c += U) {
@@ -430,6 +432,62 @@ __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_
     }
 }
 
+// P and Q of row tile blk (16 rows, from pt / qt) to memory, and the tile's
+// row of Gram partials (raw players, FP64): lower triangle of b V^T A_t V and
+// the diagonal of b V^T B_t V (without the ridge); ICA: lower triangles of
+// P^T diag(n) P and P^T P, and sum_r ||x_r||^2 (nrow: the rows' ||x_r||^2)
+template <typename T, int KP, int KIND>
+__device__ __forceinline__ void fwd_store(const StepArgs &a, int blk, const T (*pt)[KP],
+                                          const T (*qt)[KP], const T *nrow, int tid)
+{
+    constexpr int TRI = KP * (KP + 1) / 2;
+    constexpr int GW = TRI + KP;
+    constexpr bool ICA = KIND == kKindICA;
+    constexpr int GWF = ICA ? 2 * TRI + 1 : GW;
+    const int64_t r0 = (int64_t)blk * 16;
+    SGEP_G T *PQ = (SGEP_G T *)a.P, *QQ = (SGEP_G T *)a.Q;
+    // P, Q of these 16 rows: one contiguous quad-interleaved block
+    for (int e = tid; e < 16 * KP; e += kNT) {
+        const int rq = e / (4 * KP), c = (e / 4) % KP, r = 4 * rq + (e & 3);
+        if (r0 + r < a.b) {
+            PQ[r0 * KP + e] = pt[r][c];
+            QQ[r0 * KP + e] = qt[r][c];
+        }
+    }
+    for (int e = tid; e < GWF; e += kNT) {
+        double s = 0.0;
+        if (ICA) {
+            if (e < 2 * TRI) {
+                int i, j;
+                tri_ij(e < TRI ? e : e - TRI, i, j);
+                for (int r = 0; r < 16; ++r)
+                    s += (double)pt[r][i] * (double)(e < TRI ? qt[r][j] : pt[r][j]);
+            } else {
+                for (int r = 0; r < 16; ++r)
+                    s += (double)nrow[r];
+            }
+        } else if (e < TRI) {
+            int i, j;
+            tri_ij(e, i, j);
+            for (int r = 0; r < 16; ++r) {
+                if (KIND == kKindCCA)
+                    s += (double)pt[r][i] * (double)qt[r][j] + (double)qt[r][i] * (double)pt[r][j];
+                else
+                    s += (double)qt[r][i] * (double)qt[r][j];
+            }
+        } else {
+            const int i = e - TRI;
+            for (int r = 0; r < 16; ++r) {
+                if (KIND == kKindCCA)
+                    s += (double)pt[r][i] * (double)pt[r][i] + (double)qt[r][i] * (double)qt[r][i];
+                else
+                    s += (double)pt[r][i] * (double)pt[r][i];
+            }
+        }
+        ((SGEP_G double *)a.gram_part)[(int64_t)blk * GWF + e] = s;
+    }
+}
+
 // Forward body: workgroup blk takes rows 16 blk .. 16 blk + 15; the four waves
 // split the features.  Workgroup blk == n_fwd reduces the norm / parent
 // partials of the current state and advances the step counter.
@@ -441,7 +499,6 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     constexpr int TRI = KP * (KP + 1) / 2;
     constexpr int GW = TRI + KP;
     constexpr bool ICA = KIND == kKindICA;
-    constexpr int GWF = ICA ? 2 * TRI + 1 : GW; // width of this kernel's Gram rows
     __shared__ T red[4][16 * KP];
     __shared__ T pt[16][KP], qt[16][KP];
     __shared__ T rn[ICA ? 16 : 1][16], nrow[16]; // ICA: ||x_r||^2 partials and totals
@@ -462,7 +519,6 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
     const bool vec_ok = a.vec_ok != 0;
     const SGEP_G T *X = (const SGEP_G T *)a.X, *Y = (const SGEP_G T *)a.Y;
     const SGEP_G T *VQ = (const SGEP_G T *)a.V;
-    SGEP_G T *PQ = (SGEP_G T *)a.P, *QQ = (SGEP_G T *)a.Q;
 
     Acc aP[2][NB], aQ[2][NB];
 #pragma unroll
@@ -531,56 +587,110 @@ __device__ __forceinline__ void fwd_body(const StepArgs &a, int blk)
             (&qt[0][0])[e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
         __syncthreads();
     }
-    // P, Q of these 16 rows: one contiguous quad-interleaved block
-    for (int e = tid; e < 16 * KP; e += kNT) {
-        const int rq = e / (4 * KP), c = (e / 4) % KP, r = 4 * rq + (e & 3);
-        if (r0 + r < a.b) {
-            PQ[r0 * KP + e] = pt[r][c];
-            QQ[r0 * KP + e] = qt[r][c];
-        }
-    }
-
-    // partial Grams over these 16 rows (raw players, FP64): lower triangle of
-    // b V^T A_t V and the diagonal of b V^T B_t V (without the ridge); ICA:
-    // lower triangles of P^T diag(n) P and P^T P, and sum_r ||x_r||^2
-    for (int e = tid; e < GWF; e += kNT) {
-        double s = 0.0;
-        if (ICA) {
-            if (e < 2 * TRI) {
-                int i, j;
-                tri_ij(e < TRI ? e : e - TRI, i, j);
-                for (int r = 0; r < 16; ++r)
-                    s += (double)pt[r][i] * (double)(e < TRI ? qt[r][j] : pt[r][j]);
-            } else {
-                for (int r = 0; r < 16; ++r)
-                    s += (double)nrow[r];
-            }
-        } else if (e < TRI) {
-            int i, j;
-            tri_ij(e, i, j);
-            for (int r = 0; r < 16; ++r) {
-                if (KIND == kKindCCA)
-                    s += (double)pt[r][i] * (double)qt[r][j] + (double)qt[r][i] * (double)pt[r][j];
-                else
-                    s += (double)qt[r][i] * (double)qt[r][j];
-            }
-        } else {
-            const int i = e - TRI;
-            for (int r = 0; r < 16; ++r) {
-                if (KIND == kKindCCA)
-                    s += (double)pt[r][i] * (double)pt[r][i] + (double)qt[r][i] * (double)qt[r][i];
-                else
-                    s += (double)pt[r][i] * (double)pt[r][i];
-            }
-        }
-        ((SGEP_G double *)a.gram_part)[(int64_t)blk * GWF + e] = s;
-    }
+    fwd_store<T, KP, KIND>(a, blk, pt, qt, nrow, tid);
 }
 
 template <typename T, int KP, int KIND, bool CENTER = false>
 __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
 {
     fwd_body<T, KP, KIND, false, CENTER>(a, blockIdx.x);
+}
+
+// s_waitcnt operand: vector memory counter 0 (stores included), the
+// export and LDS / scalar counters at their maxima (not waited for)
+constexpr int kWaitVm0 = 0x0F70;
+
+// Feature-split forward (CCA with few row tiles): kFwdParts workgroups per
+// row tile, part p < kFwdPV taking slice p of view x's feature chunks and
+// part kFwdPV + p slice p of view y's, so that many times more CUs stream
+// the minibatch.  Each writes its 16 x KP partial product to memory; the
+// last of a tile's parts to finish (one counter per tile) adds them in a
+// fixed order (the x slices in turn for P, the y slices for Q), stores P, Q
+// and the tile's Gram partials as k_fwd does, and clears the counter for the
+// next iteration.  No workgroup waits for another.  Workgroup
+// kFwdParts n_fwd is k_fwd's norm-totals workgroup.
+constexpr int kFwdPV = 1;              // slices per view
+constexpr int kFwdParts = 2 * kFwdPV;  // workgroups per row tile
+
+template <typename T, int KP, bool CENTER = false>
+__global__ void __launch_bounds__(kNT) k_fwds(StepArgs a)
+{
+    typedef typename Mfma<T>::acc Acc;
+    constexpr int NB = KP / 16;
+    constexpr int GW = KP * (KP + 1) / 2 + KP;
+    constexpr int TS = 16 * KP; // elements of one partial tile
+    __shared__ T red[4][TS];
+    __shared__ T pt[16][KP], qt[16][KP];
+    __shared__ int last;
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int kk = lane >> 4, n = lane & 15;
+    const int g = blockIdx.x;
+    if (g == kFwdParts * a.n_fwd) {
+        colsum((const SGEP_G double *)a.stat_part, a.n_tx + a.n_ty, GW, GW, a.stat_tot, tid, kNT);
+        if (tid == 0)
+            ((SGEP_G Coef *)a.coef)->t += 1.0;
+        return;
+    }
+    const int blk = g / kFwdParts, part = g % kFwdParts;
+    const bool vy = part >= kFwdPV;
+    const int64_t r0 = (int64_t)blk * 16;
+    const bool rv = r0 + n < a.b;
+    const int64_t row = rv ? r0 + n : a.b - 1; // valid address; zeroed through rv
+    const SGEP_G T *Xv = (const SGEP_G T *)(vy ? a.Y : a.X);
+    const SGEP_G T *VQ = (const SGEP_G T *)a.V + (vy ? a.dxp * KP : 0);
+    const SGEP_G T *mu = CENTER ? (const SGEP_G T *)a.mu + (vy ? a.dxp : 0) : nullptr;
+    Acc acc[2][NB];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+            acc[h][nb] = Acc{0, 0, 0, 0};
+    fwd_view<T, KP, CENTER, false, 4 * kFwdPV>(Xv, vy ? a.ldy : a.ldx, vy ? a.dy : a.dx, row, rv,
+                                               a.vec_ok != 0, VQ, lane,
+                                               4 * (part % kFwdPV) + w, acc, mu);
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        const Acc s = acc[0][nb] + acc[1][nb];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            red[w][Mfma<T>::drow(kk, r) * KP + nb * 16 + n] = s[r];
+    }
+    __syncthreads();
+    // The partials travel through device-coherent (agent-scope) stores and
+    // loads, so no cache-wide write-back or invalidation (an agent-scope
+    // fence) is needed: the other workgroups of each XCD keep V in its L2.
+    // Every store has completed (vmcnt 0, counted per wave) before the
+    // barrier, and the counter moves after the barrier.
+    T *fp = (T *)a.fpart + (int64_t)blk * kFwdParts * TS;
+    for (int e = tid; e < TS; e += kNT)
+        __hip_atomic_store(fp + part * TS + e, red[0][e] + red[1][e] + red[2][e] + red[3][e],
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+    if (tid == 0)
+        last = __hip_atomic_fetch_add(a.fcnt + blk, 1, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT) == kFwdParts - 1;
+    __syncthreads();
+    if (!last)
+        return;
+    auto ld = [&](int i) {
+        return __hip_atomic_load(fp + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    for (int e = tid; e < TS; e += kNT) {
+        T sp = ld(e), sq = ld(kFwdPV * TS + e);
+#pragma unroll
+        for (int p = 1; p < kFwdPV; ++p) {
+            sp += ld(p * TS + e);
+            sq += ld((kFwdPV + p) * TS + e);
+        }
+        (&pt[0][0])[e] = sp;
+        (&qt[0][0])[e] = sq;
+    }
+    if (tid == 0) // for the next launch
+        __hip_atomic_store(a.fcnt + blk, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    fwd_store<T, KP, kKindCCA>(a, blk, pt, qt, nullptr, tid);
 }
 
 

@@ -127,7 +127,7 @@ def test_center_f32_cca(k, adam, b_max, pad):
     batches = _shifted(gen, sizes, 3, dx, dy, scale=0.5)
     res, names = _run(cfg, oracle.KIND_CCA, batches, synth.initial_players(dx + dy, k, 3),
                       {1, len(sizes)}, False, pad)
-    assert names == (("k_fwd", "k_bwdp", "k_bwd") if b_max >= 512 else ("k_fwd", "k_bwd"))
+    assert names == (("k_fwds", "k_bwdp", "k_bwd") if b_max >= 512 else ("k_fwd", "k_bwd"))
     m = 5 if adam else 1
     _check(res, m * TOL32_1, m * TOL32_N, 1e-6, f"f32 cca centred k={k} adam={adam} pad={pad}")
 
@@ -199,5 +199,5 @@ def test_center_f64_row_split_with_large_offsets():
     batches = _shifted(gen, sizes, 3, dx, dy, scale=2.0)
     res, names = _run(cfg, oracle.KIND_CCA, batches, synth.initial_players(dx + dy, k, 3),
                       {1, len(sizes)}, True)
-    assert names == ("k_fwd", "k_bwdp", "k_bwd")
+    assert names == ("k_fwds", "k_bwdp", "k_bwd")
     _check(res, TOL64, 1e-10, 1e-12, "f64 cca row split centred")
