@@ -293,8 +293,8 @@ def algorithmic_work(w, kernel, names=()):
     if kernel in ("k_coef", "k_coefa"):  # the Gram partials of the forward row tiles, once
         kp = 16 if k <= 16 else (32 if k <= 32 else 64)
         return 0.0, float(8 * (kp * (kp + 1) // 2 + kp) * ((b + 15) // 16))
-    if kernel == "k_bwdp":
-        return 4.0 * b * d * k, float(data + se * 2 * b * k)
+    if kernel == "k_bwdp":  # without a finishing pass it also runs the update
+        return 4.0 * b * d * k, float(data + se * 2 * b * k + (0 if "k_bwd" in names else state))
     if kernel == "k_bwd" and "k_bwdp" in names:
         return 0.0, float(state)
     if kernel == "k_bwd":

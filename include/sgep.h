@@ -29,10 +29,11 @@
  *   - Every call returns an sgep_status; 0 is success.
  *   - Argument and shape errors are returned synchronously and leave the
  *     handle unchanged.
- *   - Device faults detected inside a step (non-finite Gram terms or norms)
- *     are latched in a device status word and reported by the next call that
- *     synchronises (sgep_eigvals, sgep_vectors, sgep_auxiliary,
- *     sgep_get_state, sgep_sync).  The handle is then POISONED: every later
+ *   - Device faults detected inside a step (non-finite Gram terms or norms:
+ *     SGEP_ENONFINITE; a workgroup that gave up its bounded wait for the
+ *     iteration's coefficients: SGEP_EDEVICE) are latched in a device status
+ *     word and reported by the next call that synchronises (sgep_eigvals,
+ *     sgep_vectors, sgep_auxiliary, sgep_get_state, sgep_sync).  The handle is then POISONED: every later
  *     call except sgep_set_state and sgep_destroy returns SGEP_EPOISONED.
  *   - Host arrays of player vectors are d x k COLUMN-major doubles: column i
  *     (elements i*d .. i*d+d-1) is player i.
@@ -191,10 +192,12 @@ sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
 sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int32_t *labels,
                           int64_t b);
 
-/* Number of kernels one iteration launches.  F64 / F32: 3 for a CCA handle
- * with b_max >= 512 and at most 128 backward tiles (forward products; two
- * row slices of the backward products per tile plus the k x k coefficients;
- * sum of the slices and update); else 2 (forward products; backward products,
+/* Number of kernels one iteration launches.  F64 / F32: for a CCA handle
+ * with b_max >= 512 and at most 128 backward tiles, 2 (forward products, one
+ * workgroup per view and row tile; two row slices of the backward products
+ * per tile plus the k x k coefficients, the last slice of each tile summing
+ * them and running the update), or 3 with centring (the sum of the slices
+ * and the update as a third kernel); else 2 (forward products; backward products,
  * k x k coefficients and update) when the backward tile is one 16-feature
  * block and k * element size <= 128 bytes after padding; else 3 (forward
  * products; k x k coefficients; backward products and update), or 4 when
@@ -207,7 +210,7 @@ sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int3
 sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n);
 
 /* Short name of kernel i (0 <= i < sgep_kernels_per_step) of one iteration,
- * in launch order: "k_fwd", "k_coef", "k_coefa", "k_coefb", "k_bwdp", "k_bwd1", "k_fwd2",
+ * in launch order: "k_fwd", "k_fwds", "k_coef", "k_coefa", "k_coefb", "k_bwdp", "k_bwd1", "k_fwd2",
  * "k_bwd", "k_wfwd", "k_wmid"
  * or "k_wbwd" -- a static string, not to be freed; NULL for a NULL handle or
  * an index out of range. */

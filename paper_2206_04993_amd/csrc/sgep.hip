@@ -62,6 +62,9 @@ struct sgep_handle_s {
     void *bpart = nullptr; // the slices' partial products (nsplit > 1)
     void *fpart = nullptr; // feature-split forward: partial products (nsplit > 1)
     int *fcnt = nullptr;   // feature-split forward: per-tile counters, zero between launches
+    bool fused = false;    // row split without a finishing pass (no centring)
+    int *bcnt = nullptr;   // fused row split: per-tile slice counters, zero between launches
+    unsigned long long *cflag = nullptr; // fused row split: iteration of the published block
     int n_tx = 0, n_ty = 0, n_tiles = 0;
     int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
     int64_t W = 0;          // partial width: KP (KP + 1) / 2 + KP
@@ -116,7 +119,8 @@ void free_all(sgep_handle *h)
     void *ptrs[] = {h->V,  h->G,        h->Am,      h->As,    h->P,  h->Q,    h->gram_part,
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
                     h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
-                    h->mu,   h->S1, h->S2,     h->bb_part, h->gsum, h->fpart, h->fcnt};
+                    h->mu,   h->S1, h->S2,     h->bb_part, h->gsum, h->fpart, h->fcnt,
+                    h->bcnt, h->cflag};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -285,7 +289,15 @@ sgep_status launch_step_c(sgep_handle *h, const StepArgs &a, void *const *events
         launch_timed(sgep::k_fwd<T, KP, sgep::kKindGeneral, C>, gf, h->stream, ev[0], ev[1], a);
     constexpr int MBW = mb_wide<T>(KP);
     constexpr bool can_spec = KP * (int)sizeof(T) <= 128; // spec_mode's player-tile bound
-    if (split) {
+    if (split && h->fused) { // CCA without centring
+        const dim3 gp(h->n_tiles * h->nsplit + 8);
+        if (h->cfg.optimizer == SGEP_ADAM)
+            launch_timed(sgep::k_bwdp<T, KP, sgep::kKindCCA, false, true, sgep::kOptAdam>, gp,
+                         h->stream, ev[2], ev[3], a);
+        else
+            launch_timed(sgep::k_bwdp<T, KP, sgep::kKindCCA, false, true, sgep::kOptSGD>, gp,
+                         h->stream, ev[2], ev[3], a);
+    } else if (split) {
         const dim3 gp(h->n_tiles * h->nsplit + 8); // + the coefficient workgroup and 7 idle
         if (cca)
             launch_timed(sgep::k_bwdp<T, KP, sgep::kKindCCA, C>, gp, h->stream, ev[2], ev[3], a);
@@ -367,7 +379,7 @@ int narrow_kernels(const sgep_handle *h)
         return 4;
     const bool spec = h->esz == sizeof(double) ? spec_mode<double>(h->kp, h->mb)
                                                : spec_mode<float>(h->kp, h->mb);
-    if (spec && h->nsplit == 1)
+    if ((spec && h->nsplit == 1) || h->fused)
         return 2;
     return (h->nsplit == 1 && h->coef2) ? 4 : 3;
 }
@@ -493,7 +505,7 @@ sgep_status latch_status(sgep_handle *h)
     HIPCHK(hipStreamSynchronize(h->stream));
     if (st != 0) {
         h->poisoned = true;
-        return SGEP_ENONFINITE;
+        return (st & sgep::kStatusSync) ? SGEP_EDEVICE : SGEP_ENONFINITE;
     }
     return SGEP_OK;
 }
@@ -907,6 +919,12 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
         // the forward splits each row tile's features over several workgroups
         alloc(&h->fpart, (size_t)h->fwd_blocks_max * sgep::kFwdParts * 16 * kp * h->esz);
         alloc((void **)&h->fcnt, (size_t)h->fwd_blocks_max * sizeof(int));
+        // without centring the last slice of each tile runs the epilogue
+        h->fused = !cfg->center;
+        if (h->fused) {
+            alloc((void **)&h->bcnt, (size_t)h->n_tiles * sizeof(int));
+            alloc((void **)&h->cflag, sizeof(unsigned long long));
+        }
     }
     if (cfg->center)
         alloc(&h->mu, (size_t)2 * h->ldv * h->esz);
@@ -937,6 +955,10 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     if (h->fcnt)
         hok = hok && hipMemsetAsync(h->fcnt, 0, (size_t)h->fwd_blocks_max * sizeof(int),
                                     h->stream) == hipSuccess;
+    if (h->bcnt)
+        hok = hok && hipMemsetAsync(h->bcnt, 0, (size_t)h->n_tiles * sizeof(int), h->stream) ==
+                         hipSuccess &&
+              hipMemsetAsync(h->cflag, 0, sizeof(unsigned long long), h->stream) == hipSuccess;
     if (h->S1) // features past d are never written and must read as zero
         hok = hok && hipMemsetAsync(h->S1, 0, st_bytes, h->stream) == hipSuccess &&
               hipMemsetAsync(h->S2, 0, st_bytes, h->stream) == hipSuccess;
@@ -1006,6 +1028,8 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.bpart = h->bpart;
     a.fpart = h->fpart;
     a.fcnt = h->fcnt;
+    a.bcnt = h->bcnt;
+    a.cflag = h->cflag;
     a.mu = h->mu;
     a.S1 = h->S1;
     a.S2 = h->S2;
@@ -1096,6 +1120,7 @@ const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i)
     static const char *spec[] = {"k_fwd", "k_bwd"};
     static const char *pre[] = {"k_fwd", "k_coef", "k_bwd"};
     static const char *split[] = {"k_fwds", "k_bwdp", "k_bwd"};
+    static const char *fused[] = {"k_fwds", "k_bwdp"};
     static const char *ica[] = {"k_fwd", "k_bwd1", "k_fwd2", "k_bwd"};
     static const char *pre2[] = {"k_fwd", "k_coefa", "k_coefb", "k_bwd"};
     if (h->wide)
@@ -1107,6 +1132,8 @@ const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i)
         return ica[i];
     if (n == 4)
         return pre2[i];
+    if (h->fused)
+        return fused[i];
     return n == 2 ? spec[i] : (h->nsplit > 1 ? split[i] : pre[i]);
 }
 
@@ -1295,6 +1322,8 @@ sgep_status sgep_set_state(sgep_handle *h, const void *host_buf, size_t bytes)
         HIPCHK(hipMemcpyAsync(L.ptr[i], p, L.bytes[i], hipMemcpyHostToDevice, h->stream));
         p += L.bytes[i];
     }
+    if (h->cflag) // a stamp left by a later iteration must not match the next one
+        HIPCHK(hipMemsetAsync(h->cflag, 0, sizeof(unsigned long long), h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     int st_word = 0;
     memcpy(&st_word, (const unsigned char *)host_buf + sizeof(hd) + offsetof(Coef, status),

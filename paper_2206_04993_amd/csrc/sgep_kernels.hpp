@@ -57,6 +57,11 @@ constexpr int kOptSGD = 0;
 constexpr int kOptAdam = 1;
 
 constexpr int kStatusNonFinite = 1;
+constexpr int kStatusSync = 4; // a workgroup gave up waiting for the coefficient block (2: wide path, bad label)
+// s_waitcnt operand: vector memory counter 0 (stores included), the
+// export and LDS / scalar counters at their maxima (not waited for)
+constexpr int kWaitVm0 = 0x0F70;
+constexpr int kSpinMax = 1 << 20; // polls of a bounded wait (each with a short sleep)
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -123,6 +128,8 @@ struct StepArgs {
     double *gram_part;       // [ldg][W]: row blk = forward workgroup blk
     void *fpart;             // feature-split forward: [n_fwd][kFwdParts][16 KP] partial products
     int *fcnt;               // feature-split forward: finished partials per row tile (0 between launches)
+    int *bcnt;               // fused row-split backward: finished slices per tile (0 between launches)
+    unsigned long long *cflag; // fused row-split backward: iteration whose coefficient block is in cpre
     double *stat_part;       // [lds][W]: row tile = backward workgroup tile
     double *stat_tot;        // [W]: reduced stat_part of the state entering this iteration
     Coef *coef;
@@ -596,10 +603,6 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
     fwd_body<T, KP, KIND, false, CENTER>(a, blockIdx.x);
 }
 
-// s_waitcnt operand: vector memory counter 0 (stores included), the
-// export and LDS / scalar counters at their maxima (not waited for)
-constexpr int kWaitVm0 = 0x0F70;
-
 // Feature-split forward (CCA with few row tiles): kFwdParts workgroups per
 // row tile, part p < kFwdPV taking slice p of view x's feature chunks and
 // part kFwdPV + p slice p of view y's, so that many times more CUs stream
@@ -712,6 +715,7 @@ constexpr int kModePart = 2; // one row slice of the products -> partial tiles
 constexpr int kModeFin = 3;  // sum of the partial tiles, block from k_coef, epilogue
 constexpr int kModeIca1 = 4; // ICA: S1 = X^T P, S2 = X^T Q to memory, S1^T S1 partials
 constexpr int kModeIca2 = 5; // ICA: S3 = X^T R, A-side = S2 - tr S1 - 2 S3, epilogue
+constexpr int kModeFused = 6; // one row slice; the tile's last slice sums them and runs the epilogue
 
 template <typename T, int KP> struct CoefTile {
     T Tl[KP * KP];            // T_ij, row i
@@ -889,9 +893,19 @@ __device__ __forceinline__ void coef_body(const StepArgs &a)
     __syncthreads();
     coef_rows<T, KP, KIND>(a, gs, ss, dInv, dS, Td, ema, t, C, true, tid);
     __syncthreads();
-    SGEP_G T *out = (SGEP_G T *)a.cpre;
+    // device-coherent stores: with the fused row-split backward, workgroups
+    // of the same launch on other XCDs read the block once the stamp shows
+    // this iteration
+    T *out = (T *)a.cpre;
     for (int e = tid; e < NC; e += kNT)
-        out[e] = (&C.Tl[0])[e];
+        __hip_atomic_store(out + e, (&C.Tl[0])[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (a.cflag) {
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        __syncthreads();
+        if (tid == 0)
+            __hip_atomic_store(a.cflag, (unsigned long long)t, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 template <typename T, int KP, int KIND>
@@ -1009,7 +1023,10 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
     constexpr int NC = (int)(sizeof(CoefTile<T, KP>) / sizeof(T));
     constexpr bool PART = MODE == kModePart, FIN = MODE == kModeFin;
     constexpr bool ICA1 = MODE == kModeIca1, ICA2 = MODE == kModeIca2;
-    constexpr bool NOCOEF = SPEC || PART || ICA1; // no coefficient block read from memory
+    constexpr bool FUSED = MODE == kModeFused;
+    static_assert(!(FUSED && CENTER), "the fused row split runs without centring");
+    // no coefficient block read from memory at the start (FUSED: read later)
+    constexpr bool NOCOEF = SPEC || PART || ICA1 || FUSED;
     constexpr bool TWOX = KIND == kKindGeneral;   // two views per feature tile
     constexpr int CPT = NOCOEF ? 1 : (NC + kNT - 1) / kNT;
     __shared__ T red[4][FT * KP];
@@ -1131,7 +1148,7 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
     // owns the ragged last group; kModeFin runs no main loop
     int64_t gb = 0, ge = FIN ? 0 : ngf;
     bool ragged = !FIN && ngf * 16 < a.b;
-    if (PART) {
+    if (PART || FUSED) {
         const int64_t gps = (ngf + a.nsplit - 1) / a.nsplit;
         gb = split * gps < ngf ? split * gps : ngf;
         ge = gb + gps < ngf ? gb + gps : ngf;
@@ -1383,6 +1400,73 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
         }
         return;
     }
+    if constexpr (FUSED) {
+        // this slice's products to memory (device-coherent stores, complete
+        // before the barrier), then the tile's counter; the last slice to
+        // arrive continues with the epilogue
+        __shared__ int last;
+        // this iteration's stamp (t was set by the forward launch)
+        const unsigned long long want =
+            tid == 0 ? (unsigned long long)((const SGEP_G Coef *)a.coef)->t : 0ull;
+        __syncthreads();
+        T *bq = (T *)a.bpart + (int64_t)tile * a.nsplit * PSTR;
+        for (int e = tid; e < FT * KP; e += kNT) {
+            __hip_atomic_store(bq + (int64_t)split * PSTR + e, avt[e], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(bq + (int64_t)split * PSTR + FT * KP + e, bvt[e],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        __syncthreads();
+        if (tid == 0) {
+            // the count and the stamp of the coefficient block travel
+            // together (the block itself is read only after the stamp)
+            const int old = __hip_atomic_fetch_add(a.bcnt + tile, 1, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            unsigned long long got =
+                __hip_atomic_load(a.cflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = old == a.nsplit - 1;
+            if (last) {
+                // the coefficient block of this iteration (workgroup 0 of the
+                // launch, dispatched first, so it runs or has finished); a
+                // bounded wait that flags the status word if it gives up
+                int n = 0;
+                while (got != want) {
+                    if (++n > kSpinMax) {
+                        atomicOr(&((Coef *)a.coef)->status, kStatusSync);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                    got = __hip_atomic_load(a.cflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __hip_atomic_store(a.bcnt + tile, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+        if (!last)
+            return;
+        const T *cq = (const T *)a.cpre;
+        for (int e = tid; e < NC; e += kNT)
+            (&C.Tl[0])[e] = __hip_atomic_load(cq + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the slices' products summed in slice order (this slice's from LDS)
+        for (int e = tid; e < FT * KP; e += kNT) {
+            T pa = T(0), pb2 = T(0);
+            for (int sp = 0; sp < a.nsplit; ++sp) {
+                const T xa = sp == split ? avt[e]
+                                         : __hip_atomic_load(bq + (int64_t)sp * PSTR + e,
+                                                             __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                const T xb = sp == split ? bvt[e]
+                                         : __hip_atomic_load(bq + (int64_t)sp * PSTR + FT * KP + e,
+                                                             __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                pa = sp == 0 ? xa : pa + xa;
+                pb2 = sp == 0 ? xb : pb2 + xb;
+            }
+            avt[e] = pa; // element e is read and written by this thread only
+            bvt[e] = pb2;
+        }
+    }
     if (PART) {
         // this slice's products for the finishing pass
         __syncthreads();
@@ -1496,8 +1580,10 @@ __global__ void __launch_bounds__(MODE == kModeSpec ? 2 * kNT : kNT) k_bwd(StepA
 // slice j % nsplit, so each XCD takes a contiguous run of tiles with all
 // their slices: neighbouring tiles share the 128-byte lines of a minibatch
 // row, which are then fetched into one L2 only.  The second pass is k_bwd
-// with kModeFin.
-template <typename T, int KP, int KIND, bool CENTER = false>
+// with kModeFin, or (FUSE) none: the last slice of each tile to finish
+// sums the slices' products and runs the epilogue itself once workgroup 0
+// has published the coefficient block (kModeFused).
+template <typename T, int KP, int KIND, bool CENTER = false, bool FUSE = false, int OPT = kOptSGD>
 __global__ void __launch_bounds__(kNT) k_bwdp(StepArgs a)
 {
     if (blockIdx.x < 8) {
@@ -1506,7 +1592,8 @@ __global__ void __launch_bounds__(kNT) k_bwdp(StepArgs a)
         return;
     }
     const int j = xcd_tile(blockIdx.x - 8, (a.n_tx + a.n_ty) * a.nsplit);
-    bwd_body<T, KP, 1, KIND, kOptSGD, kModePart, false, CENTER>(a, j / a.nsplit, j % a.nsplit);
+    bwd_body<T, KP, 1, KIND, OPT, FUSE ? kModeFused : kModePart, false, CENTER>(a, j / a.nsplit,
+                                                                              j % a.nsplit);
 }
 
 // ---------------------------------------------------------------------------

@@ -241,7 +241,7 @@ def test_cca_row_split_parity(dtype, k):
                          dx, dy, 1024, schedule=sg.SGEP_SCHED_INV, eta0=0.3, t0=20.0, gamma=0.5,
                          rho=1e-6)
     probe = sg.Solver(cfg, synth.initial_players(dx + dy, k, 0))
-    assert probe.kernel_names() == ("k_fwds", "k_bwdp", "k_bwd")
+    assert probe.kernel_names() == ("k_fwds", "k_bwdp")
     probe.close()
     sizes = [1024, 1000, 17, 600, 513, 1, 777, 1024]
     batches = [gen.batch(t, n) for t, n in enumerate(sizes, start=1)]

@@ -115,7 +115,7 @@ def test_smooth_f32_cca(k, adam, b_max):
     batches = [gen.batch(t, n) for t, n in enumerate(sizes, start=1)]
     res, names = _run_narrow(cfg, oracle.KIND_CCA, batches, synth.initial_players(dx + dy, k, 3),
                              {1, len(sizes)}, False)
-    assert names == (("k_fwds", "k_bwdp", "k_bwd") if b_max >= 512 else ("k_fwd", "k_bwd"))
+    assert names == (("k_fwds", "k_bwdp") if b_max >= 512 else ("k_fwd", "k_bwd"))
     m = 5 if adam else 1
     _check(res, m * TOL32_1, m * TOL32_N, f"f32 cca smooth k={k} adam={adam}")
 
