@@ -316,6 +316,33 @@ def test_bitwise_determinism_and_resume():
         s.close()
 
 
+def test_row_split_rewind_in_place():
+    """The fused row-split backward publishes the coefficient block with an
+    iteration stamp.  A handle rewound in place by set_state (the stamp of
+    the discarded iteration t + 1 still in device memory) and fed another
+    minibatch for t + 1 matches a handle that never ran the discarded
+    iteration, bit for bit."""
+    sg = _sg()
+    gen = synth.CCAPlanted(130, 70, np.linspace(0.9, 0.3, 4), sigma=0.3, seed=11)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 16, 130, 70, 600,
+                         optimizer=sg.SGEP_ADAM, eta0=1e-3, gamma=0.3)
+    batches = _cca_batches(gen, 9, 600)
+    V0 = synth.initial_players(200, 16, 2)
+    a = _solver_run(cfg, batches[:6], V0)
+    assert a.kernel_names() == ("k_fwds", "k_bwdp")
+    blob = a.get_state()
+    _solver_run(cfg, batches[6:7], V0, solver=a)  # iteration 7, then discarded
+    a.set_state(blob)
+    assert a.step_count() == 6
+    _solver_run(cfg, batches[7:9], V0, solver=a)  # iterations 7 and 8, other data
+    ref = _solver_run(cfg, batches[:6] + batches[7:9], V0)
+    assert np.array_equal(a.vectors(), ref.vectors())
+    assert np.array_equal(a.auxiliary(), ref.auxiliary())
+    assert np.array_equal(a.eigvals(), ref.eigvals())
+    for s in (a, ref):
+        s.close()
+
+
 @pytest.mark.parametrize("b", [256, 640])  # one backward pass; row-split backward
 def test_hipgraph_replay_matches_eager(b):
     torch = _torch()
