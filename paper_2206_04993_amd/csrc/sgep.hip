@@ -60,8 +60,8 @@ struct sgep_handle_s {
     double *gsum = nullptr; // column totals of the Gram partials (two-stage coefficients)
     bool coef2 = false;     // coefficients in two stages (k_coefa, k_coefb)
     void *bpart = nullptr; // the slices' partial products (nsplit > 1)
-    void *fpart = nullptr; // feature-split forward: partial products (nsplit > 1)
-    int *fcnt = nullptr;   // feature-split forward: per-tile counters, zero between launches
+    void *fpart = nullptr; // per-view forward: stamped words of P (nsplit > 1)
+    size_t fpart_bytes = 0;
     bool fused = false;    // row split without a finishing pass (no centring)
     int *bcnt = nullptr;   // fused row split: per-tile slice counters, zero between launches
     unsigned long long *cflag = nullptr; // fused row split: iteration of the published block
@@ -119,7 +119,7 @@ void free_all(sgep_handle *h)
     void *ptrs[] = {h->V,  h->G,        h->Am,      h->As,    h->P,  h->Q,    h->gram_part,
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
                     h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
-                    h->mu,   h->S1, h->S2,     h->bb_part, h->gsum, h->fpart, h->fcnt,
+                    h->mu,   h->S1, h->S2,     h->bb_part, h->gsum, h->fpart,
                     h->bcnt, h->cflag};
     for (void *p : ptrs)
         if (p)
@@ -281,8 +281,7 @@ sgep_status launch_step_c(sgep_handle *h, const StepArgs &a, void *const *events
             ev[i] = (hipEvent_t)events[i];
     const bool cca = h->cfg.kind == SGEP_KIND_CCA;
     if (split) // CCA only: several workgroups per row tile
-        launch_timed(sgep::k_fwds<T, KP, C>, dim3(sgep::kFwdParts * a.n_fwd + 1), h->stream, ev[0],
-                     ev[1], a);
+        launch_timed(sgep::k_fwds<T, KP, C>, dim3(2 * a.n_fwd + 1), h->stream, ev[0], ev[1], a);
     else if (cca)
         launch_timed(sgep::k_fwd<T, KP, sgep::kKindCCA, C>, gf, h->stream, ev[0], ev[1], a);
     else
@@ -916,15 +915,15 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     if (split_mode(*cfg, h->mb, h->n_tiles)) {
         h->nsplit = kSplit;
         alloc(&h->bpart, (size_t)h->n_tiles * kSplit * (2 * h->ft * kp + 2 * h->ft) * h->esz);
-        // the forward splits each row tile's features over several workgroups
-        alloc(&h->fpart, (size_t)h->fwd_blocks_max * sgep::kFwdParts * 16 * kp * h->esz);
-        alloc((void **)&h->fcnt, (size_t)h->fwd_blocks_max * sizeof(int));
+        // the per-view forward's stamped words of P (two per FP64 value)
+        h->fpart_bytes = (size_t)h->fwd_blocks_max * 16 * kp * (h->esz / 4) * 8;
+        alloc(&h->fpart, h->fpart_bytes);
+        // iteration stamp of the coefficient block (also the forward's stamp base)
+        alloc((void **)&h->cflag, sizeof(unsigned long long));
         // without centring the last slice of each tile runs the epilogue
         h->fused = !cfg->center;
-        if (h->fused) {
+        if (h->fused)
             alloc((void **)&h->bcnt, (size_t)h->n_tiles * sizeof(int));
-            alloc((void **)&h->cflag, sizeof(unsigned long long));
-        }
     }
     if (cfg->center)
         alloc(&h->mu, (size_t)2 * h->ldv * h->esz);
@@ -952,13 +951,12 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
               hipMemsetAsync(h->As, 0, st_bytes, h->stream) == hipSuccess;
     if (h->mu)
         hok = hok && hipMemsetAsync(h->mu, 0, (size_t)2 * h->ldv * h->esz, h->stream) == hipSuccess;
-    if (h->fcnt)
-        hok = hok && hipMemsetAsync(h->fcnt, 0, (size_t)h->fwd_blocks_max * sizeof(int),
-                                    h->stream) == hipSuccess;
+    if (h->fpart) // stamps are at least 1: zero words never match
+        hok = hok && hipMemsetAsync(h->fpart, 0, h->fpart_bytes, h->stream) == hipSuccess &&
+              hipMemsetAsync(h->cflag, 0, sizeof(unsigned long long), h->stream) == hipSuccess;
     if (h->bcnt)
         hok = hok && hipMemsetAsync(h->bcnt, 0, (size_t)h->n_tiles * sizeof(int), h->stream) ==
-                         hipSuccess &&
-              hipMemsetAsync(h->cflag, 0, sizeof(unsigned long long), h->stream) == hipSuccess;
+                         hipSuccess;
     if (h->S1) // features past d are never written and must read as zero
         hok = hok && hipMemsetAsync(h->S1, 0, st_bytes, h->stream) == hipSuccess &&
               hipMemsetAsync(h->S2, 0, st_bytes, h->stream) == hipSuccess;
@@ -1027,7 +1025,6 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.cpre = h->cpre;
     a.bpart = h->bpart;
     a.fpart = h->fpart;
-    a.fcnt = h->fcnt;
     a.bcnt = h->bcnt;
     a.cflag = h->cflag;
     a.mu = h->mu;
@@ -1322,8 +1319,12 @@ sgep_status sgep_set_state(sgep_handle *h, const void *host_buf, size_t bytes)
         HIPCHK(hipMemcpyAsync(L.ptr[i], p, L.bytes[i], hipMemcpyHostToDevice, h->stream));
         p += L.bytes[i];
     }
-    if (h->cflag) // a stamp left by a later iteration must not match the next one
+    if (h->cflag) { // stamps left by later iterations must not match the next ones
         HIPCHK(hipMemsetAsync(h->cflag, 0, sizeof(unsigned long long), h->stream));
+        HIPCHK(hipMemsetAsync(h->fpart, 0, h->fpart_bytes, h->stream));
+    }
+    if (h->bcnt) // zero between launches unless a bounded wait gave up
+        HIPCHK(hipMemsetAsync(h->bcnt, 0, (size_t)h->n_tiles * sizeof(int), h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     int st_word = 0;
     memcpy(&st_word, (const unsigned char *)host_buf + sizeof(hd) + offsetof(Coef, status),

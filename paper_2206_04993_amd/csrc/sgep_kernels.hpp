@@ -126,8 +126,7 @@ struct StepArgs {
     void *V, *G, *Am, *As;   // ldv x KP, quad-interleaved
     void *P, *Q;             // ldp x KP, quad-interleaved raw projections X V, Y V
     double *gram_part;       // [ldg][W]: row blk = forward workgroup blk
-    void *fpart;             // feature-split forward: [n_fwd][kFwdParts][16 KP] partial products
-    int *fcnt;               // feature-split forward: finished partials per row tile (0 between launches)
+    void *fpart;             // per-view forward: [n_fwd][16 KP] stamped words of P (Stamped<T>)
     int *bcnt;               // fused row-split backward: finished slices per tile (0 between launches)
     unsigned long long *cflag; // fused row-split backward: iteration whose coefficient block is in cpre
     double *stat_part;       // [lds][W]: row tile = backward workgroup tile
@@ -443,6 +442,35 @@ __device__ __forceinline__ void fwd_view2(const SGEP_G T *__restrict__ X, int64_
 // row of Gram partials (raw players, FP64): lower triangle of b V^T A_t V and
 // the diagonal of b V^T B_t V (without the ridge); ICA: lower triangles of
 // P^T diag(n) P and P^T P, and sum_r ||x_r||^2 (nrow: the rows' ||x_r||^2)
+// Entry e of a row tile's Gram partial row (CCA / GENERAL; raw players,
+// FP64 products summed over the 16 rows in order): e < TRI the lower
+// triangle of b V^T A_t V, else the diagonal of b V^T B_t V (no ridge)
+template <typename T, int KP, int KIND>
+__device__ __forceinline__ double gram_entry(const T (*pt)[KP], const T (*qt)[KP], int e)
+{
+    constexpr int TRI = KP * (KP + 1) / 2;
+    double s = 0.0;
+    if (e < TRI) {
+        int i, j;
+        tri_ij(e, i, j);
+        for (int r = 0; r < 16; ++r) {
+            if (KIND == kKindCCA)
+                s += (double)pt[r][i] * (double)qt[r][j] + (double)qt[r][i] * (double)pt[r][j];
+            else
+                s += (double)qt[r][i] * (double)qt[r][j];
+        }
+    } else {
+        const int i = e - TRI;
+        for (int r = 0; r < 16; ++r) {
+            if (KIND == kKindCCA)
+                s += (double)pt[r][i] * (double)pt[r][i] + (double)qt[r][i] * (double)qt[r][i];
+            else
+                s += (double)pt[r][i] * (double)pt[r][i];
+        }
+    }
+    return s;
+}
+
 template <typename T, int KP, int KIND>
 __device__ __forceinline__ void fwd_store(const StepArgs &a, int blk, const T (*pt)[KP],
                                           const T (*qt)[KP], const T *nrow, int tid)
@@ -473,23 +501,8 @@ __device__ __forceinline__ void fwd_store(const StepArgs &a, int blk, const T (*
                 for (int r = 0; r < 16; ++r)
                     s += (double)nrow[r];
             }
-        } else if (e < TRI) {
-            int i, j;
-            tri_ij(e, i, j);
-            for (int r = 0; r < 16; ++r) {
-                if (KIND == kKindCCA)
-                    s += (double)pt[r][i] * (double)qt[r][j] + (double)qt[r][i] * (double)pt[r][j];
-                else
-                    s += (double)qt[r][i] * (double)qt[r][j];
-            }
         } else {
-            const int i = e - TRI;
-            for (int r = 0; r < 16; ++r) {
-                if (KIND == kKindCCA)
-                    s += (double)pt[r][i] * (double)pt[r][i] + (double)qt[r][i] * (double)qt[r][i];
-                else
-                    s += (double)pt[r][i] * (double)pt[r][i];
-            }
+            s = gram_entry<T, KP, KIND>(pt, qt, e);
         }
         ((SGEP_G double *)a.gram_part)[(int64_t)blk * GWF + e] = s;
     }
@@ -603,40 +616,100 @@ __global__ void __launch_bounds__(kNT) k_fwd(StepArgs a)
     fwd_body<T, KP, KIND, false, CENTER>(a, blockIdx.x);
 }
 
-// Feature-split forward (CCA with few row tiles): kFwdParts workgroups per
-// row tile, part p < kFwdPV taking slice p of view x's feature chunks and
-// part kFwdPV + p slice p of view y's, so that many times more CUs stream
-// the minibatch.  Each writes its 16 x KP partial product to memory; the
-// last of a tile's parts to finish (one counter per tile) adds them in a
-// fixed order (the x slices in turn for P, the y slices for Q), stores P, Q
-// and the tile's Gram partials as k_fwd does, and clears the counter for the
-// next iteration.  No workgroup waits for another.  Workgroup
-// kFwdParts n_fwd is k_fwd's norm-totals workgroup.
-constexpr int kFwdPV = 1;              // slices per view
-constexpr int kFwdParts = 2 * kFwdPV;  // workgroups per row tile
+// Stamped words for exchanges inside one launch: the high 32 bits carry the
+// iteration stamp, the low 32 bits one half of the value (FP32: all of it;
+// FP64: word 0 the low half, word 1 the high half).  A reader polls the
+// words themselves with device-coherent loads until every stamp matches, so
+// no completion wait, counter or flag is needed; words are written with
+// single 64-bit device-coherent stores, so a matching stamp implies its value.
+template <typename T> struct Stamped;
+template <> struct Stamped<float> {
+    static constexpr int N = 1; // words per value
+    static __device__ __forceinline__ void put(unsigned long long *w, float v, unsigned st)
+    {
+        __hip_atomic_store(w, ((unsigned long long)st << 32) | __float_as_uint(v),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // false if the bounded wait gave up (value then zero)
+    static __device__ __forceinline__ bool get(const unsigned long long *w, unsigned st, float &v)
+    {
+        unsigned long long x;
+        for (int n = 0;; ++n) {
+            x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((unsigned)(x >> 32) == st)
+                break;
+            if (n > kSpinMax) {
+                v = 0.0f;
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        v = __uint_as_float((unsigned)x);
+        return true;
+    }
+};
+template <> struct Stamped<double> {
+    static constexpr int N = 2;
+    static __device__ __forceinline__ void put(unsigned long long *w, double v, unsigned st)
+    {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        const unsigned long long hs = (unsigned long long)st << 32;
+        __hip_atomic_store(w, hs | (b & 0xffffffffull), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(w + 1, hs | (b >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    static __device__ __forceinline__ bool get(const unsigned long long *w, unsigned st, double &v)
+    {
+        unsigned long long x[2];
+        for (int h = 0; h < 2; ++h) {
+            for (int n = 0;; ++n) {
+                x[h] = __hip_atomic_load(w + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((unsigned)(x[h] >> 32) == st)
+                    break;
+                if (n > kSpinMax) {
+                    v = 0.0;
+                    return false;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        v = __longlong_as_double((long long)((x[1] << 32) | (x[0] & 0xffffffffull)));
+        return true;
+    }
+};
 
+// Per-view forward (CCA handles with the row-split backward): two
+// workgroups per 16-row tile, 2 blk streaming view x's features of the rows
+// and 2 blk + 1 view y's, so twice as many CUs stream the minibatch as with
+// k_fwd (same chunk order and accumulators as k_fwd's per-view pass, hence
+// the same P and Q).  The x workgroup stores P and publishes it as stamped
+// words; the y workgroup stores Q, reads P from the stamped words and writes
+// the tile's Gram partials as k_fwd does.  The stamp is this iteration's
+// number, one past the stamp the previous backward launch left in a.cflag.
+// Workgroup 2 n_fwd is k_fwd's norm-totals workgroup.
 template <typename T, int KP, bool CENTER = false>
 __global__ void __launch_bounds__(kNT) k_fwds(StepArgs a)
 {
     typedef typename Mfma<T>::acc Acc;
     constexpr int NB = KP / 16;
     constexpr int GW = KP * (KP + 1) / 2 + KP;
-    constexpr int TS = 16 * KP; // elements of one partial tile
+    constexpr int TS = 16 * KP; // elements of one tile of P or Q
     __shared__ T red[4][TS];
     __shared__ T pt[16][KP], qt[16][KP];
-    __shared__ int last;
+    __shared__ int bad;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int kk = lane >> 4, n = lane & 15;
     const int g = blockIdx.x;
-    if (g == kFwdParts * a.n_fwd) {
+    if (g == 2 * a.n_fwd) {
         colsum((const SGEP_G double *)a.stat_part, a.n_tx + a.n_ty, GW, GW, a.stat_tot, tid, kNT);
         if (tid == 0)
             ((SGEP_G Coef *)a.coef)->t += 1.0;
         return;
     }
-    const int blk = g / kFwdParts, part = g % kFwdParts;
-    const bool vy = part >= kFwdPV;
+    const unsigned stamp = (unsigned)*(const SGEP_G unsigned long long *)a.cflag + 1u;
+    const int blk = g >> 1;
+    const bool vy = (g & 1) != 0;
     const int64_t r0 = (int64_t)blk * 16;
     const bool rv = r0 + n < a.b;
     const int64_t row = rv ? r0 + n : a.b - 1; // valid address; zeroed through rv
@@ -649,9 +722,8 @@ __global__ void __launch_bounds__(kNT) k_fwds(StepArgs a)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
             acc[h][nb] = Acc{0, 0, 0, 0};
-    fwd_view<T, KP, CENTER, false, 4 * kFwdPV>(Xv, vy ? a.ldy : a.ldx, vy ? a.dy : a.dx, row, rv,
-                                               a.vec_ok != 0, VQ, lane,
-                                               4 * (part % kFwdPV) + w, acc, mu);
+    fwd_view<T, KP, CENTER>(Xv, vy ? a.ldy : a.ldx, vy ? a.dy : a.dx, row, rv, a.vec_ok != 0, VQ,
+                            lane, w, acc, mu);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const Acc s = acc[0][nb] + acc[1][nb];
@@ -659,41 +731,36 @@ __global__ void __launch_bounds__(kNT) k_fwds(StepArgs a)
         for (int r = 0; r < 4; ++r)
             red[w][Mfma<T>::drow(kk, r) * KP + nb * 16 + n] = s[r];
     }
-    __syncthreads();
-    // The partials travel through device-coherent (agent-scope) stores and
-    // loads, so no cache-wide write-back or invalidation (an agent-scope
-    // fence) is needed: the other workgroups of each XCD keep V in its L2.
-    // Every store has completed (vmcnt 0, counted per wave) before the
-    // barrier, and the counter moves after the barrier.
-    T *fp = (T *)a.fpart + (int64_t)blk * kFwdParts * TS;
-    for (int e = tid; e < TS; e += kNT)
-        __hip_atomic_store(fp + part * TS + e, red[0][e] + red[1][e] + red[2][e] + red[3][e],
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    __syncthreads();
     if (tid == 0)
-        last = __hip_atomic_fetch_add(a.fcnt + blk, 1, __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT) == kFwdParts - 1;
+        bad = 0;
     __syncthreads();
-    if (!last)
-        return;
-    auto ld = [&](int i) {
-        return __hip_atomic_load(fp + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    };
+    // this view's 16 x KP product (the four waves' tiles summed in order),
+    // one contiguous quad-interleaved block
+    SGEP_G T *out = (SGEP_G T *)(vy ? a.Q : a.P) + r0 * KP;
+    unsigned long long *pw = (unsigned long long *)a.fpart + (int64_t)blk * TS * Stamped<T>::N;
     for (int e = tid; e < TS; e += kNT) {
-        T sp = ld(e), sq = ld(kFwdPV * TS + e);
-#pragma unroll
-        for (int p = 1; p < kFwdPV; ++p) {
-            sp += ld(p * TS + e);
-            sq += ld((kFwdPV + p) * TS + e);
+        const int rq = e / (4 * KP), c = (e / 4) % KP, r = 4 * rq + (e & 3);
+        const int ti = r * KP + c;
+        const T v = red[0][ti] + red[1][ti] + red[2][ti] + red[3][ti];
+        if (r0 + r < a.b)
+            out[e] = v;
+        if (vy) {
+            qt[r][c] = v;
+            T p;
+            if (!Stamped<T>::get(pw + e * Stamped<T>::N, stamp, p))
+                bad = 1;
+            pt[r][c] = p;
+        } else {
+            Stamped<T>::put(pw + e * Stamped<T>::N, v, stamp);
         }
-        (&pt[0][0])[e] = sp;
-        (&qt[0][0])[e] = sq;
     }
-    if (tid == 0) // for the next launch
-        __hip_atomic_store(a.fcnt + blk, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!vy)
+        return;
     __syncthreads();
-    fwd_store<T, KP, kKindCCA>(a, blk, pt, qt, nullptr, tid);
+    if (tid == 0 && bad)
+        atomicOr(&((Coef *)a.coef)->status, kStatusSync);
+    for (int e = tid; e < GW; e += kNT)
+        ((SGEP_G double *)a.gram_part)[(int64_t)blk * GW + e] = gram_entry<T, KP, kKindCCA>(pt, qt, e);
 }
 
 
