@@ -63,7 +63,9 @@ struct sgep_handle_s {
     void *fpart = nullptr; // per-view forward: stamped words of P (nsplit > 1)
     size_t fpart_bytes = 0;
     bool fused = false;    // row split without a finishing pass (no centring)
-    int *bcnt = nullptr;   // fused row split: per-tile slice counters, zero between launches
+    void *xw = nullptr;    // fused row split: stamped words (slices' products, coefficient block)
+    size_t xw_bytes = 0;
+    int64_t xw_coef = 0;   // word offset of the coefficient block in xw
     unsigned long long *cflag = nullptr; // fused row split: iteration of the published block
     int n_tx = 0, n_ty = 0, n_tiles = 0;
     int ldg = 0, lds = 0;   // leading dimensions of the partial arrays
@@ -120,7 +122,7 @@ void free_all(sgep_handle *h)
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
                     h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
                     h->mu,   h->S1, h->S2,     h->bb_part, h->gsum, h->fpart,
-                    h->bcnt, h->cflag};
+                    h->xw, h->cflag};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -922,8 +924,12 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
         alloc((void **)&h->cflag, sizeof(unsigned long long));
         // without centring the last slice of each tile runs the epilogue
         h->fused = !cfg->center;
-        if (h->fused)
-            alloc((void **)&h->bcnt, (size_t)h->n_tiles * sizeof(int));
+        if (h->fused) {
+            const int64_t nw = h->esz / 4; // words per value
+            h->xw_coef = (int64_t)h->n_tiles * kSplit * 2 * h->ft * kp * nw;
+            h->xw_bytes = (size_t)(h->xw_coef + (kp * kp + 3 * kp + 4) * nw) * 8;
+            alloc(&h->xw, h->xw_bytes);
+        }
     }
     if (cfg->center)
         alloc(&h->mu, (size_t)2 * h->ldv * h->esz);
@@ -954,9 +960,8 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     if (h->fpart) // stamps are at least 1: zero words never match
         hok = hok && hipMemsetAsync(h->fpart, 0, h->fpart_bytes, h->stream) == hipSuccess &&
               hipMemsetAsync(h->cflag, 0, sizeof(unsigned long long), h->stream) == hipSuccess;
-    if (h->bcnt)
-        hok = hok && hipMemsetAsync(h->bcnt, 0, (size_t)h->n_tiles * sizeof(int), h->stream) ==
-                         hipSuccess;
+    if (h->xw)
+        hok = hok && hipMemsetAsync(h->xw, 0, h->xw_bytes, h->stream) == hipSuccess;
     if (h->S1) // features past d are never written and must read as zero
         hok = hok && hipMemsetAsync(h->S1, 0, st_bytes, h->stream) == hipSuccess &&
               hipMemsetAsync(h->S2, 0, st_bytes, h->stream) == hipSuccess;
@@ -1025,7 +1030,8 @@ static StepArgs make_args(const sgep_handle *h, int64_t ldx, int64_t ldy, bool v
     a.cpre = h->cpre;
     a.bpart = h->bpart;
     a.fpart = h->fpart;
-    a.bcnt = h->bcnt;
+    a.xw = h->xw;
+    a.xw_coef = h->xw_coef;
     a.cflag = h->cflag;
     a.mu = h->mu;
     a.S1 = h->S1;
@@ -1323,8 +1329,8 @@ sgep_status sgep_set_state(sgep_handle *h, const void *host_buf, size_t bytes)
         HIPCHK(hipMemsetAsync(h->cflag, 0, sizeof(unsigned long long), h->stream));
         HIPCHK(hipMemsetAsync(h->fpart, 0, h->fpart_bytes, h->stream));
     }
-    if (h->bcnt) // zero between launches unless a bounded wait gave up
-        HIPCHK(hipMemsetAsync(h->bcnt, 0, (size_t)h->n_tiles * sizeof(int), h->stream));
+    if (h->xw)
+        HIPCHK(hipMemsetAsync(h->xw, 0, h->xw_bytes, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     int st_word = 0;
     memcpy(&st_word, (const unsigned char *)host_buf + sizeof(hd) + offsetof(Coef, status),

@@ -127,8 +127,9 @@ struct StepArgs {
     void *P, *Q;             // ldp x KP, quad-interleaved raw projections X V, Y V
     double *gram_part;       // [ldg][W]: row blk = forward workgroup blk
     void *fpart;             // per-view forward: [n_fwd][16 KP] stamped words of P (Stamped<T>)
-    int *bcnt;               // fused row-split backward: finished slices per tile (0 between launches)
-    unsigned long long *cflag; // fused row-split backward: iteration whose coefficient block is in cpre
+    unsigned long long *cflag; // row split: iteration of the latest coefficient block
+    void *xw;                // fused row split: stamped words of the slices' products, then of
+    int64_t xw_coef;         //   the coefficient block from word xw_coef on
     double *stat_part;       // [lds][W]: row tile = backward workgroup tile
     double *stat_tot;        // [W]: reduced stat_part of the state entering this iteration
     Coef *coef;
@@ -960,19 +961,19 @@ __device__ __forceinline__ void coef_body(const StepArgs &a)
     __syncthreads();
     coef_rows<T, KP, KIND>(a, gs, ss, dInv, dS, Td, ema, t, C, true, tid);
     __syncthreads();
-    // device-coherent stores: with the fused row-split backward, workgroups
-    // of the same launch on other XCDs read the block once the stamp shows
-    // this iteration
-    T *out = (T *)a.cpre;
+    // the block for the backward epilogue (kModePre / kModeFin, a later launch)
+    SGEP_G T *out = (SGEP_G T *)a.cpre;
     for (int e = tid; e < NC; e += kNT)
-        __hip_atomic_store(out + e, (&C.Tl[0])[e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (a.cflag) {
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        __syncthreads();
-        if (tid == 0)
-            __hip_atomic_store(a.cflag, (unsigned long long)t, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        out[e] = (&C.Tl[0])[e];
+    if (a.xw) { // fused row split: the last slices read the block as stamped words
+        unsigned long long *cw = (unsigned long long *)a.xw + a.xw_coef;
+        for (int e = tid; e < NC; e += kNT)
+            Stamped<T>::put(cw + e * Stamped<T>::N, (&C.Tl[0])[e], (unsigned)t);
     }
+    // this iteration's number: the next per-view forward stamps with t + 1
+    if (a.cflag && tid == 0)
+        __hip_atomic_store(a.cflag, (unsigned long long)t, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <typename T, int KP, int KIND>
@@ -1468,71 +1469,52 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
         return;
     }
     if constexpr (FUSED) {
-        // this slice's products to memory (device-coherent stores, complete
-        // before the barrier), then the tile's counter; the last slice to
-        // arrive continues with the epilogue
-        __shared__ int last;
-        // this iteration's stamp (t was set by the forward launch)
-        const unsigned long long want =
-            tid == 0 ? (unsigned long long)((const SGEP_G Coef *)a.coef)->t : 0ull;
+        // slices other than the last publish their products as stamped
+        // words and finish; the last slice reads them and the coefficient
+        // block (stamped words of workgroup 0) and runs the epilogue
+        constexpr int NW = Stamped<T>::N;
+        __shared__ int bad;
+        const unsigned st = (unsigned)((const SGEP_G Coef *)a.coef)->t; // set by the forward
+        unsigned long long *tw =
+            (unsigned long long *)a.xw + (int64_t)tile * a.nsplit * (2 * FT * KP) * NW;
+        if (tid == 0)
+            bad = 0;
         __syncthreads();
-        T *bq = (T *)a.bpart + (int64_t)tile * a.nsplit * PSTR;
-        for (int e = tid; e < FT * KP; e += kNT) {
-            __hip_atomic_store(bq + (int64_t)split * PSTR + e, avt[e], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(bq + (int64_t)split * PSTR + FT * KP + e, bvt[e],
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
-        __syncthreads();
-        if (tid == 0) {
-            // the count and the stamp of the coefficient block travel
-            // together (the block itself is read only after the stamp)
-            const int old = __hip_atomic_fetch_add(a.bcnt + tile, 1, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_AGENT);
-            unsigned long long got =
-                __hip_atomic_load(a.cflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            last = old == a.nsplit - 1;
-            if (last) {
-                // the coefficient block of this iteration (workgroup 0 of the
-                // launch, dispatched first, so it runs or has finished); a
-                // bounded wait that flags the status word if it gives up
-                int n = 0;
-                while (got != want) {
-                    if (++n > kSpinMax) {
-                        atomicOr(&((Coef *)a.coef)->status, kStatusSync);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                    got = __hip_atomic_load(a.cflag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
-                __hip_atomic_store(a.bcnt + tile, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (split != a.nsplit - 1) {
+            unsigned long long *mw = tw + (int64_t)split * (2 * FT * KP) * NW;
+            for (int e = tid; e < FT * KP; e += kNT) {
+                Stamped<T>::put(mw + e * NW, avt[e], st);
+                Stamped<T>::put(mw + (FT * KP + e) * NW, bvt[e], st);
             }
-        }
-        __syncthreads();
-        if (!last)
             return;
-        const T *cq = (const T *)a.cpre;
-        for (int e = tid; e < NC; e += kNT)
-            (&C.Tl[0])[e] = __hip_atomic_load(cq + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const unsigned long long *cw = (const unsigned long long *)a.xw + a.xw_coef;
+        for (int e = tid; e < NC; e += kNT) {
+            T v;
+            if (!Stamped<T>::get(cw + e * NW, st, v))
+                bad = 1;
+            (&C.Tl[0])[e] = v;
+        }
         // the slices' products summed in slice order (this slice's from LDS)
         for (int e = tid; e < FT * KP; e += kNT) {
             T pa = T(0), pb2 = T(0);
             for (int sp = 0; sp < a.nsplit; ++sp) {
-                const T xa = sp == split ? avt[e]
-                                         : __hip_atomic_load(bq + (int64_t)sp * PSTR + e,
-                                                             __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
-                const T xb = sp == split ? bvt[e]
-                                         : __hip_atomic_load(bq + (int64_t)sp * PSTR + FT * KP + e,
-                                                             __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT);
+                T xa = avt[e], xb = bvt[e];
+                if (sp != split) {
+                    const unsigned long long *ow = tw + (int64_t)sp * (2 * FT * KP) * NW;
+                    if (!Stamped<T>::get(ow + e * NW, st, xa) ||
+                        !Stamped<T>::get(ow + (FT * KP + e) * NW, st, xb))
+                        bad = 1;
+                }
                 pa = sp == 0 ? xa : pa + xa;
                 pb2 = sp == 0 ? xb : pb2 + xb;
             }
             avt[e] = pa; // element e is read and written by this thread only
             bvt[e] = pb2;
         }
+        __syncthreads();
+        if (tid == 0 && bad)
+            atomicOr(&((Coef *)a.coef)->status, kStatusSync);
     }
     if (PART) {
         // this slice's products for the finishing pass
