@@ -1,8 +1,7 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
 Both sides consume the same seeded minibatches (already rounded to the GPU's
-element type) and the same starting points.  Tolerances (see the design doc,
-"Parity tolerances"): FP64 runs agree to 1e-11 on unit players after 100
+element type) and the same starting points.  Tolerances: FP64 runs agree to 1e-11 on unit players after 100
 iterations; FP32 runs agree to TOL32_1 after one iteration and TOL32_N after
 N iterations, which is the FP32 rounding of length-d and length-b dot
 products (unit round-off 6e-8 times sqrt-length growth, times the step-size
