@@ -63,7 +63,7 @@ typedef int32_t sgep_status;
 #define SGEP_ENOMEM (-3)       /* device allocation failed (init only) */
 #define SGEP_EDEVICE (-4)      /* HIP runtime error */
 #define SGEP_ENONFINITE (-5)   /* a step produced a non-finite or zero norm / Gram term */
-#define SGEP_EUNSUPPORTED (-6) /* valid request this build does not implement */
+#define SGEP_EUNSUPPORTED (-6) /* valid request the library does not implement */
 #define SGEP_EPOISONED (-7)    /* an earlier fault poisoned the handle */
 
 /* problem kinds */

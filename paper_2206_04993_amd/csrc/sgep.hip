@@ -808,7 +808,7 @@ const char *sgep_status_string(sgep_status s)
     case SGEP_ENOMEM: return "device allocation failed";
     case SGEP_EDEVICE: return "HIP runtime error";
     case SGEP_ENONFINITE: return "non-finite or zero norm / Gram term in a step";
-    case SGEP_EUNSUPPORTED: return "not supported by this build";
+    case SGEP_EUNSUPPORTED: return "not supported by the library";
     case SGEP_EPOISONED: return "handle poisoned by an earlier fault";
     default: return "unknown status";
     }
