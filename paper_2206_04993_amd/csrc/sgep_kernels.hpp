@@ -879,8 +879,10 @@ __device__ __forceinline__ void coef_rows(const StepArgs &a, const double *gs, c
             const double ii2 = dInv[i] * dInv[i];
             mA = gs[tri_idx(i, i)] * ii2 * ib;
             mB = gs[TRI + i] * ii2 * ib + (KIND == kKindCCA ? 0.0 : a.eps_reg);
-            for (int j = 0; j < i; ++j)
-                c += Td[i * KP + j] * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
+#pragma unroll
+            for (int j = 0; j < KP - 1; ++j) // j < i, in order; unrolled so the LDS reads overlap
+                if (j < i)
+                    c += Td[i * KP + j] * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
         }
         C.mB[i] = (T)mB;
         C.mAc[i] = (T)(mA - c);
@@ -929,7 +931,11 @@ __device__ __forceinline__ void coef_body(const StepArgs &a)
     __shared__ CoefTile<T, KP> C;
     const int tid = threadIdx.x;
     const double t = ((const SGEP_G Coef *)a.coef)->t; // this iteration's number (k_fwd)
-    coef_early<T, KP>(a, t, C, ema, true, tid);
+    // the t-dependent terms (three FP64 pow) on the last wave, which has no
+    // column of the sums below (W <= kNT - 64 for KP <= 16; otherwise the
+    // wave also sums columns and only the placement changes)
+    if (tid >= kNT - 64)
+        coef_early<T, KP>(a, t, C, ema, true, tid - (kNT - 64));
     for (int e = tid; e < W; e += kNT)
         ss[e] = ((const SGEP_G double *)a.stat_tot)[e];
     if constexpr (KIND == kKindICA) {
@@ -1637,7 +1643,7 @@ __global__ void __launch_bounds__(kNT) k_bwdp(StepArgs a)
 {
     if (blockIdx.x < 8) {
         if (blockIdx.x == 0)
-            coef_body<T, KP, KIND>(a);
+            coef_body<T, KP, KIND, 64>(a); // its column sums are on the critical path
         return;
     }
     const int j = xcd_tile(blockIdx.x - 8, (a.n_tx + a.n_ty) * a.nsplit);
