@@ -7,7 +7,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import cca_matrices
+from . import cca_matrices, jacobi_eigh
 
 
 def cca_population(gen):
@@ -70,3 +70,64 @@ def ica_planted_topk(gen, k: int):
     kap = np.asarray(gen.kurtosis, dtype=np.float64)
     order = np.argsort(-kap)[:k]
     return kap[order].copy(), gen.M[:, order].copy()
+
+
+def lda_population_AB(gen, eps: float, priors=None):
+    """Population matrices of ``synth.LDAClasses`` (Sec. 1, LDA as a GEP):
+    A = sum_c pi_c (mu_c - mubar)(mu_c - mubar)^T with mubar = sum_c pi_c mu_c
+    (between-class), B = diag(sigma_f^2) + eps I (within-class covariance of
+    the generator plus the ridge).  Dense d x d: small d only."""
+    pri = _lda_priors(gen, priors)
+    Mt = gen.means - pri @ gen.means
+    A = Mt.T @ (pri[:, None] * Mt)
+    B = np.diag(gen.sigma ** 2 + eps)
+    return A, B
+
+
+def _lda_priors(gen, priors):
+    if priors is None:
+        return np.full(gen.c, 1.0 / gen.c)
+    p = np.asarray(priors, dtype=np.float64)
+    assert p.shape == (gen.c,) and np.all(p > 0)
+    return p
+
+
+def lda_reduced_topk(gen, k: int, eps: float, priors=None):
+    """Exact top-k (k <= c - 1) generalized eigenpairs of the population LDA
+    problem of ``synth.LDAClasses`` through its c x c reduced form.
+
+    With N = diag(pi)^{1/2} (M - 1 mubar^T) (c x d), A = N^T N has rank at
+    most c - 1, so every eigenvector of A v = lambda B v with lambda != 0 lies
+    in B^{-1} N^T (the span of the class-mean directions after B^{-1}).
+    Writing v = B^{-1} N^T u / sqrt(lambda) turns the problem into the
+    symmetric c x c eigenproblem K u = lambda u with K = N B^{-1} N^T, and
+    then A v = N^T K u / sqrt(lambda) = lambda B v and v^T B v = u^T K u /
+    lambda = 1 (B-orthonormal).  B is diagonal for this generator, so the
+    route costs O(c^2 d) and K's eigenproblem is solved by the oracle's
+    cyclic Jacobi.  Returns (lam descending, V (d, k)), signs canonical
+    (largest-magnitude component positive)."""
+    pri = _lda_priors(gen, priors)
+    if not 1 <= k <= gen.c - 1:
+        raise ValueError("the between-class matrix has rank <= c - 1")
+    Binv = 1.0 / (gen.sigma ** 2 + eps)
+    N = np.sqrt(pri)[:, None] * (gen.means - pri @ gen.means)
+    K = (N * Binv[None, :]) @ N.T
+    K = 0.5 * (K + K.T)
+    w, U = jacobi_eigh(K)
+    order = np.argsort(-w, kind="stable")[:k]
+    lam = w[order]
+    if not np.all(lam > 0):
+        raise ValueError("fewer than k positive between-class eigenvalues")
+    V = (Binv[:, None] * (N.T @ U[:, order])) / np.sqrt(lam)[None, :]
+    return lam.copy(), _canon(V)
+
+
+def _canon(V):
+    """Each column's largest-magnitude component made positive (lowest index
+    on ties)."""
+    V = np.array(V, dtype=np.float64, copy=True)
+    for i in range(V.shape[1]):
+        j = int(np.argmax(np.abs(V[:, i])))
+        if V[j, i] < 0:
+            V[:, i] = -V[:, i]
+    return V

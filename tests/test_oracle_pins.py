@@ -677,3 +677,73 @@ def test_fixed_point_does_not_depend_on_the_minibatch_size():
         finals.append(err)
     # the noise, not the limit, depends on b: larger minibatches end closer
     assert finals[2] < finals[0]
+
+
+# --------------------------------------------------------------------------- #
+# LDA (Sec. 1): the reduced c x c route and the stochastic step              #
+# --------------------------------------------------------------------------- #
+
+@pytest.mark.parametrize("priors", [None, (0.1, 0.15, 0.2, 0.25, 0.3)])
+def test_lda_reduced_solve_equals_dense_exact_solver(priors):
+    """The c x c reduced route (A = N^T N has rank <= c - 1, so v lies in
+    B^{-1} N^T) gives the same top c - 1 pairs as the dense Cholesky + Jacobi
+    route and scipy's generalized eigh on the population matrices, with
+    v^T B v = I and A v = lambda B v; the c-th eigenvalue of the dense problem
+    is zero (rank c - 1)."""
+    g = synth.LDAClasses(d=40, c=5, r=7, seed=3)
+    eps = 1e-4
+    A, B = targets.lda_population_AB(g, eps, priors)
+    lam, V = targets.lda_reduced_topk(g, 4, eps, priors)
+    lam_d, Vd = oracle.gep_topk(A, B, 5)
+    assert np.allclose(lam, lam_d[:4], rtol=1e-11, atol=0)
+    assert abs(lam_d[4]) < 1e-10 * lam_d[0]
+    assert oracle.subspace_error(V, Vd[:, :4], B) < 1e-13
+    for i in range(4):  # distinct eigenvalues: the vectors agree up to sign
+        s = np.sign(V[:, i] @ B @ Vd[:, i])
+        assert np.abs(V[:, i] - s * Vd[:, i]).max() < 1e-10 * np.abs(V[:, i]).max()
+    assert np.abs(V.T @ B @ V - np.eye(4)).max() < 1e-12
+    assert np.abs(A @ V - (B @ V) * lam[None, :]).max() < 1e-11 * np.abs(A).max()
+    w = sla.eigh(A, B, eigvals_only=True)[::-1]
+    assert np.allclose(lam, w[:4], rtol=1e-10, atol=0)
+
+
+def test_lda_reduced_solve_at_the_benchmark_width():
+    """At d = 65536 the reduced route still satisfies A v = lambda B v and
+    v^T B v = I, checked through products with the class means only (A is
+    never formed): A v = N^T (N v)."""
+    g = synth.LDAClasses()
+    eps = 1e-4
+    lam, V = targets.lda_reduced_topk(g, 9, eps)
+    pri = np.full(g.c, 1.0 / g.c)
+    N = np.sqrt(pri)[:, None] * (g.means - pri @ g.means)
+    Bd = g.sigma ** 2 + eps
+    AV = N.T @ (N @ V)
+    BV = Bd[:, None] * V
+    assert np.abs(AV - BV * lam[None, :]).max() < 1e-10 * np.abs(AV).max()
+    assert np.abs(V.T @ BV - np.eye(9)).max() < 1e-11
+    assert np.all(np.diff(lam) < 0) and lam[-1] > 1.0
+
+
+def test_lda_stochastic_alg2_reaches_the_reduced_solution():
+    """Alg. 2 on fresh labelled minibatches of the Gaussian classes, with the
+    oracle's minibatch within-class B (samples minus their class mean) and
+    between-class A (given means and priors), converges to the exact top
+    c - 1 subspace of the population problem.  A wrong reading of either
+    matrix (e.g. B from uncentred samples) converges elsewhere."""
+    g = synth.LDAClasses(d=24, c=4, r=6, seed=5)
+    eps = 1e-4
+    lam, Vs = targets.lda_reduced_topk(g, 3, eps)
+    A, B = targets.lda_population_AB(g, eps)
+    pb = oracle.Problem(oracle.KIND_LDA, 3, 24, eps_reg=eps, class_means=g.means, rho=1e-6)
+    st = oracle.State.init(synth.initial_players(24, 3, 5))
+    for t in range(1, 2501):
+        X, lab = g.batch(t, 256, dtype=np.float64)
+        oracle.gamma_step(pb, st, X, None, oracle.eta(oracle.SCHED_INV, t, 0.05, t0=200.0), 0.5,
+                          labels=lab)
+    err = oracle.subspace_error(st.V, Vs, B)
+    assert err < 3e-3, err
+    # the same run with B taken from the raw (uncentred) samples: the class
+    # means enter B and the top subspace changes
+    Xs, _ = g.batch(0, 4096, dtype=np.float64)
+    Bw = Xs.T @ Xs / 4096 + eps * np.eye(24)
+    assert oracle.subspace_error(oracle.gep_topk(A, Bw, 3)[1], Vs, B) > 10 * err
