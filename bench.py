@@ -112,6 +112,10 @@ WORKLOADS = {
         _C5, dtype="bf16",
         describe="LDA BF16: d=65536, 10 Gaussian classes with means on a random 64-dim "
                  "subspace, within-class B + 1e-4 I, k=64, minibatch 2048"),
+    "lda_d65536_k64_b2048_fp32": dict(
+        _C5, dtype="f32",
+        describe="LDA FP32 reference: d=65536, 10 Gaussian classes with means on a random "
+                 "64-dim subspace, within-class B + 1e-4 I, k=64, minibatch 2048"),
 }
 # many independent GENERAL instances advanced together (widths uniform in
 # [64, 2048], planted generalized eigenvalues geomspace(10, 0.1, 8), B ridge
@@ -300,12 +304,13 @@ def algorithmic_work(w, kernel, names=()):
     if kernel == "k_bwd":
         return 4.0 * b * d * k, float(data + se * 2 * b * k + state)
     mw = k + c if lda else 2 * k                                # rows of the backward operand W
+    mp = k if lda else 2 * k                                    # of them, rows multiplied by X^T
     if kernel == "k_wfwd":
         return 2.0 * b * d * k, float(data + 4 * d * k + 4 * b * k * (1 if lda else 2))
     if kernel == "k_wmid":
         return 0.0, float(4 * b * k * (1 if lda else 2) + 4 * b * mw)
     extra = (4 * c * d + 4 * d) if lda else 0                   # class means, their mean
-    return 2.0 * b * d * mw, float(data + 4 * b * mw + state + 4 * d * k + extra)
+    return 2.0 * b * d * mp, float(data + 4 * b * mw + state + 4 * d * k + extra)
 
 
 def cpu_baseline(w, budget_s: float, host):

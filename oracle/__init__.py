@@ -382,11 +382,16 @@ def subspace_error(Vhat: np.ndarray, Vstar: np.ndarray, B: np.ndarray) -> float:
     With Vstar B-orthonormal (Vstar^T B Vstar = I), W = B^{1/2} Vstar is
     orthonormal and 1 - tr(U* P)/k = 1 - tr(C^T G^{-1} C)/k where
     C = Vhat^T B Vstar and G = Vhat^T B Vhat.  The sign and scale of each
-    column of Vhat do not matter."""
+    column of Vhat do not matter.  A one-dimensional B is the diagonal of a
+    diagonal B (large d)."""
     k = Vstar.shape[1]
-    BVs = B @ Vstar
-    C = Vhat.T @ BVs
-    G = Vhat.T @ (B @ Vhat)
+    B = np.asarray(B)
+
+    def mulB(M):
+        return B[:, None] * M if B.ndim == 1 else B @ M
+
+    C = Vhat.T @ mulB(Vstar)
+    G = Vhat.T @ mulB(Vhat)
     return float(1.0 - np.trace(C.T @ np.linalg.solve(G, C)) / k)
 
 

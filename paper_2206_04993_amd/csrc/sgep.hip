@@ -81,6 +81,7 @@ struct sgep_handle_s {
     WideArgs wa;
     void *Vh = nullptr, *Vl = nullptr, *colscale = nullptr, *Ppart = nullptr;
     void *Wh = nullptr, *Wl = nullptr, *Mcls = nullptr, *Mbar = nullptr, *prior = nullptr;
+    void *Vf = nullptr, *Wf = nullptr; // FP32 input: V operand and W rows
 };
 
 namespace {
@@ -122,7 +123,7 @@ void free_all(sgep_handle *h)
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
                     h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
                     h->mu,   h->S1, h->S2,     h->bb_part, h->gsum, h->fpart,
-                    h->xw, h->cflag};
+                    h->xw, h->cflag, h->Vf, h->Wf};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -139,9 +140,11 @@ sgep_status check_cfg(const sgep_config *c)
         return SGEP_EINVAL;
     const bool narrow = c->dtype == SGEP_BF16 || c->dtype == SGEP_FP8_E4M3;
     const bool lda = c->kind == SGEP_KIND_LDA;
-    // LDA runs on the BF16 path only; GENERAL on the F64 / F32 path only
+    // LDA runs on the large-d path in BF16 or FP32; GENERAL and ICA on the
+    // F64 / F32 path only
     const bool ica = c->kind == SGEP_KIND_ICA;
-    if ((lda && c->dtype != SGEP_BF16) || (narrow && (c->kind == SGEP_KIND_GENERAL || ica)))
+    if ((lda && c->dtype != SGEP_BF16 && c->dtype != SGEP_F32) ||
+        (narrow && (c->kind == SGEP_KIND_GENERAL || ica)))
         return SGEP_EUNSUPPORTED;
     if (c->k < 1)
         return SGEP_EINVAL;
@@ -166,7 +169,7 @@ sgep_status check_cfg(const sgep_config *c)
     }
     if (c->kind == SGEP_KIND_GENERAL && c->dx != c->dy)
         return SGEP_ESHAPE;
-    if (narrow && (c->dx % 8 != 0 || c->dy % 8 != 0))
+    if ((narrow || lda) && (c->dx % 8 != 0 || c->dy % 8 != 0))
         return SGEP_ESHAPE;
     const int64_t d = c->kind == SGEP_KIND_CCA ? c->dx + c->dy : c->dx;
     if (c->k > d)
@@ -422,7 +425,7 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
     const bool adam = h->cfg.optimizer == SGEP_ADAM;
     // forward workgroups, then the statistics reductions
     const dim3 gf(a.n_rb * a.nview * a.n_split + wide_stat_blocks(a));
-    if constexpr (KP <= 32) {
+    if constexpr (KP <= 32 && IN != kInF32) {
         if (a.rbf == 128)
             launch_k(k_wfwd<KP, IN, 128>, gf, blk, h->stream, ev[0], ev[1], a);
         else
@@ -430,7 +433,7 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
     } else {
         launch_k(k_wfwd<KP, IN, 64>, gf, blk, h->stream, ev[0], ev[1], a);
     }
-    launch_k(k_wmid<KP, KIND>, dim3(a.nA), blk, h->stream, ev[2], ev[3], a);
+    launch_k(k_wmid<KP, IN, KIND>, dim3(a.nA), blk, h->stream, ev[2], ev[3], a);
     const dim3 bblk(kBT);
     if (adam)
         launch_k(k_wbwd<KP, IN, KIND, sgep::kOptAdam>, dim3(a.nwg), bblk, h->stream, ev[4], ev[5], a);
@@ -471,7 +474,11 @@ sgep_status wide_readout_t(sgep_handle *h, const WideArgs &a, const void *S, int
 #define WIDE_DISPATCH(h, FN, ...)                                                          \
     ([&]() -> sgep_status {                                                                \
         using namespace sgep::wide;                                                        \
-        if ((h)->cfg.kind == SGEP_KIND_LDA) {                                              \
+        if ((h)->cfg.kind == SGEP_KIND_LDA && (h)->cfg.dtype == SGEP_F32) {                \
+            if ((h)->kp == 16) return FN<16, kInF32, kKindLDA>(__VA_ARGS__);               \
+            if ((h)->kp == 32) return FN<32, kInF32, kKindLDA>(__VA_ARGS__);               \
+            if ((h)->kp == 64) return FN<64, kInF32, kKindLDA>(__VA_ARGS__);               \
+        } else if ((h)->cfg.kind == SGEP_KIND_LDA) {                                       \
             if ((h)->kp == 16) return FN<16, kInBF16, kKindLDA>(__VA_ARGS__);              \
             if ((h)->kp == 32) return FN<32, kInBF16, kKindLDA>(__VA_ARGS__);              \
             if ((h)->kp == 64) return FN<64, kInBF16, kKindLDA>(__VA_ARGS__);              \
@@ -549,11 +556,12 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     using namespace sgep::wide;
     const sgep_config &c = h->cfg;
     const bool lda = c.kind == SGEP_KIND_LDA, fp8 = c.dtype == SGEP_FP8_E4M3;
+    const bool f32 = c.dtype == SGEP_F32;
     const int64_t KP = h->kp, d = h->d;
     auto r64 = [](int64_t x) { return (x + 63) / 64 * 64; };
     WideArgs &a = h->wa;
     memset(&a, 0, sizeof(a));
-    h->esz = fp8 ? 1 : 2; // element size of the minibatch (checkpoint header)
+    h->esz = fp8 ? 1 : (f32 ? 4 : 2); // element size of the minibatch (checkpoint header)
     a.nview = lda ? 1 : 2;
     a.dv[0] = c.dx;
     a.dv[1] = lda ? 0 : c.dy;
@@ -569,7 +577,7 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     const int64_t dvmax = a.dv[0] > a.dv[1] ? a.dv[0] : a.dv[1];
     const int64_t nf64 = (dvmax + 63) / 64;
     const int64_t ns_cap = (nf64 + kNW - 1) / kNW;
-    a.rbf = (KP <= 32 && (a.ldr / 128) * a.nview * ns_cap >= 256) ? 128 : 64;
+    a.rbf = (KP <= 32 && !f32 && (a.ldr / 128) * a.nview * ns_cap >= 256) ? 128 : 64;
     const int64_t rbf = a.rbf;
     const int64_t nrb = a.ldr / rbf;
     const int64_t target = 512 * kRB / rbf;
@@ -602,7 +610,7 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     };
     const size_t st = (size_t)a.dtot * KP * sizeof(float);
     const size_t op = (size_t)KP * a.dtot * sizeof(uint16_t);
-    const size_t wbytes = (size_t)MW * a.ldr * sizeof(uint16_t);
+    const size_t wbytes = (size_t)MW * a.ldr * sizeof(uint16_t); // FP32 input: twice this
     const size_t spb = (size_t)a.Ws * a.lds * sizeof(double);
     alloc(&h->V, st);
     alloc(&h->G, st);
@@ -610,13 +618,21 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
         alloc(&h->Am, st);
         alloc(&h->As, st);
     }
-    alloc(&h->Vh, op);
-    alloc(&h->Vl, op);
+    if (f32) {
+        alloc(&h->Vf, 2 * op);
+    } else {
+        alloc(&h->Vh, op);
+        alloc(&h->Vl, op);
+    }
     if (fp8)
         alloc(&h->colscale, (size_t)a.dtot * sizeof(float));
     alloc(&h->Ppart, (size_t)a.n_split * a.nview * a.ldr * KP * sizeof(float));
-    alloc(&h->Wh, wbytes);
-    alloc(&h->Wl, wbytes);
+    if (f32) {
+        alloc(&h->Wf, 2 * wbytes);
+    } else {
+        alloc(&h->Wh, wbytes);
+        alloc(&h->Wl, wbytes);
+    }
     if (lda) {
         alloc(&h->Mcls, (size_t)a.ncls * a.dtot * sizeof(float));
         alloc(&h->Mbar, (size_t)a.dtot * sizeof(float));
@@ -634,10 +650,12 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.As = (float *)h->As;
     a.Vh = (uint16_t *)h->Vh;
     a.Vl = (uint16_t *)h->Vl;
+    a.Vf = (float *)h->Vf;
     a.colscale = (const float *)h->colscale;
     a.Ppart = (float *)h->Ppart;
     a.Wh = (uint16_t *)h->Wh;
     a.Wl = (uint16_t *)h->Wl;
+    a.Wf = (float *)h->Wf;
     a.M = (const float *)h->Mcls;
     a.Mbar = (const float *)h->Mbar;
     a.prior = (const double *)h->prior;
@@ -677,11 +695,16 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     std::vector<double> hp;
     bool hok = hipMemsetAsync(h->coef, 0, sizeof(Coef), h->stream) == hipSuccess &&
                hipMemsetAsync(h->stat_part, 0, spb, h->stream) == hipSuccess &&
-               hipMemsetAsync(h->Vh, 0, op, h->stream) == hipSuccess &&
-               hipMemsetAsync(h->Vl, 0, op, h->stream) == hipSuccess &&
-               hipMemsetAsync(h->Wh, 0, wbytes, h->stream) == hipSuccess &&
-               hipMemsetAsync(h->Wl, 0, wbytes, h->stream) == hipSuccess &&
                hipMemcpyAsync(h->V, hv.data(), st, hipMemcpyHostToDevice, h->stream) == hipSuccess;
+    // operand copies and W rows (rows past the minibatch must read as zero)
+    if (f32)
+        hok = hok && hipMemsetAsync(h->Vf, 0, 2 * op, h->stream) == hipSuccess &&
+              hipMemsetAsync(h->Wf, 0, 2 * wbytes, h->stream) == hipSuccess;
+    else
+        hok = hok && hipMemsetAsync(h->Vh, 0, op, h->stream) == hipSuccess &&
+              hipMemsetAsync(h->Vl, 0, op, h->stream) == hipSuccess &&
+              hipMemsetAsync(h->Wh, 0, wbytes, h->stream) == hipSuccess &&
+              hipMemsetAsync(h->Wl, 0, wbytes, h->stream) == hipSuccess;
     if (h->Am)
         hok = hok && hipMemsetAsync(h->Am, 0, st, h->stream) == hipSuccess &&
               hipMemsetAsync(h->As, 0, st, h->stream) == hipSuccess;
@@ -780,6 +803,7 @@ StateLayout state_layout(const sgep_handle *h)
         L.add(h->As, st);
         L.add(h->Vh, op);
         L.add(h->Vl, op);
+        L.add(h->Vf, 2 * op); // FP32 input: in place of Vh, Vl
         L.add(h->stat_part, (size_t)h->wa.Ws * h->wa.lds * sizeof(double));
     } else {
         const size_t st = (size_t)h->ldv * h->kp * h->esz;
@@ -840,7 +864,7 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     h->stream = (hipStream_t)hip_stream;
     h->d = cfg->kind == SGEP_KIND_CCA ? cfg->dx + cfg->dy : cfg->dx;
     h->kp = cfg->k <= 16 ? 16 : (cfg->k <= 32 ? 32 : 64);
-    if (cfg->dtype == SGEP_BF16 || cfg->dtype == SGEP_FP8_E4M3) {
+    if (cfg->dtype == SGEP_BF16 || cfg->dtype == SGEP_FP8_E4M3 || cfg->kind == SGEP_KIND_LDA) {
         h->wide = true;
         if (hipGetDevice(&h->device) != hipSuccess) {
             delete h;

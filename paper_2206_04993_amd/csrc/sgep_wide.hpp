@@ -1,7 +1,8 @@
 // sgep_wide.hpp -- CDNA4 (gfx950) kernels of the large-d form of the
 // stochastic gamma-EigenGame step (Alg. 2, M = 1) for minibatches stored in
 // BF16 or in FP8-e4m3 with per-column FP32 scales, problem kinds CCA (two
-// views, Sec. 1) and LDA (between-class A, within-class B, Sec. 1).
+// views, Sec. 1) and LDA (between-class A, within-class B, Sec. 1); and the
+// same decomposition for FP32 minibatches (LDA), on the FP32 MFMA.
 //
 // The minibatch is the only large operand and is read by two products per
 // iteration, X V and X^T W.  Both run on the BF16 MFMA (16x16x32, FP32
@@ -36,6 +37,14 @@
 //
 // Both streaming loops are software-pipelined: the loads of the next chunk are
 // issued before the MFMAs of the current one.
+//
+// FP32 minibatches (kInF32) use the same launches, partials and epilogue with
+// the 16x16x4 FP32 MFMA: the operands V and W are FP32 (player-major V copy
+// Vf, W rows Wf), with no hi/lo split, and a lane's eight consecutive
+// k-values of a 32-wide chunk feed eight MFMAs, MFMA j taking the lane's
+// element j (the k-index l / 16 of MFMA j stands for k-value 8 (l / 16) + j;
+// both operands use the same assignment, so each product sums every k-value
+// once).
 #pragma once
 
 #include "sgep_kernels.hpp"
@@ -55,6 +64,7 @@ constexpr int kRowPad = 128;   // padding of the row dimension (a multiple of ev
 constexpr int kMaxCls = 16;    // LDA classes
 constexpr int kInBF16 = 0;
 constexpr int kInFP8 = 1;
+constexpr int kInF32 = 2;
 constexpr int kKindLDA = 2;
 constexpr int kStatusBadLabel = 2;
 constexpr int kStatCols = 16;  // statistics columns per reduction workgroup
@@ -85,9 +95,11 @@ struct WideArgs {
     int32_t nsubv[2];
     float *V, *G, *Am, *As;     // dtot x KP, feature-major
     uint16_t *Vh, *Vl;          // KP x dtot, player-major BF16 hi / lo of s_f V
+    float *Vf;                  // FP32 input: KP x dtot, player-major copy of V
     const float *colscale;      // dtot (FP8 only): s_f, 0 on padding
     float *Ppart;               // [n_split][nview][ldr][KP]
     uint16_t *Wh, *Wl;          // [rows of W][ldr]
+    float *Wf;                  // FP32 input: [rows of W][ldr]
     const float *M;             // LDA: ncls x dtot class means
     const float *Mbar;          // LDA: dtot, prior-weighted mean of the class means
     const double *prior;        // LDA: ncls
@@ -130,6 +142,23 @@ __device__ __forceinline__ f32x4 mfma_bf16(u32x4 a, u32x4 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Eight k-values per lane (two f32x4 of A and of B) through eight 16x16x4
+// MFMAs: MFMA j takes element j of both.
+__device__ __forceinline__ f32x4 mfma_f32x8(const f32x4 (&a)[2], const f32x4 (&b)[2], f32x4 c)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            c = mfma_f32(a[h][j], b[h][j], c);
+    return c;
 }
 
 // Four FP8-e4m3 codes (one dword) to BF16: features 0,1 in d0 and 2,3 in d1.
@@ -213,13 +242,11 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
     const int64_t dv = a.dv[v];
     const int64_t ld = v ? a.ldy : a.ldx;
     const uint8_t *Xb = (const uint8_t *)(v ? a.Y : a.X);
-    constexpr int ES = IN == kInBF16 ? 2 : 1;
+    constexpr int ES = IN == kInBF16 ? 2 : (IN == kInF32 ? 4 : 1);
     const int64_t row0 = (int64_t)rb * RBF;
     const int64_t fbeg = (int64_t)s * a.fs + (int64_t)w * a.fw;
     const int64_t fend = (fbeg + a.fw < dv) ? fbeg + a.fw : dv;
     const int nst = fend > fbeg ? (int)((fend - fbeg + 31) / 32) : 0;
-    const uint16_t *Vh = a.Vh + a.off[v] + (int64_t)r16 * a.dtot + 8 * g;
-    const uint16_t *Vl = a.Vl + a.off[v] + (int64_t)r16 * a.dtot + 8 * g;
     // Loads are unconditional, from clamped in-bounds addresses (a row past the
     // minibatch reads the last row, a feature unit past the view the last
     // unit); the data are zeroed where they are consumed.  Branch-free loads
@@ -240,58 +267,108 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
         for (int u = 0; u < NT; ++u)
             acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // one 32-feature chunk: raw X (BF16: 4 dwords; FP8: 2 dwords) and V hi/lo
-    auto load = [&](int st, u32x4(&xa)[TR], u32x4(&vh)[NT], u32x4(&vl)[NT]) {
-        const int64_t f0 = fbeg + 32 * (int64_t)(st < nst ? st : nst - 1);
-        const int64_t fx = f0 + 8 * g < dv ? f0 + 8 * g : dv - 8;
+    if constexpr (IN == kInF32) {
+        // one 32-feature chunk: eight FP32 features of X per row tile and of V
+        // per player tile (two 16-byte loads each)
+        const float *Vf = a.Vf + a.off[v] + (int64_t)r16 * a.dtot + 8 * g;
+        auto load = [&](int st, f32x4(&xa)[TR][2], f32x4(&va)[NT][2]) {
+            const int64_t f0 = fbeg + 32 * (int64_t)(st < nst ? st : nst - 1);
+            const int64_t fx = f0 + 8 * g < dv ? f0 + 8 * g : dv - 8;
 #pragma unroll
-        for (int t = 0; t < TR; ++t) {
-            if (IN == kInBF16) {
-                xa[t] = *reinterpret_cast<const u32x4 *>(xr[t] + 2 * fx);
-            } else {
-                const u32x2 q = *reinterpret_cast<const u32x2 *>(xr[t] + fx);
-                xa[t] = u32x4{q[0], q[1], 0u, 0u};
+            for (int t = 0; t < TR; ++t) {
+                const float *p = reinterpret_cast<const float *>(xr[t]) + fx;
+                xa[t][0] = *reinterpret_cast<const f32x4 *>(p);
+                xa[t][1] = *reinterpret_cast<const f32x4 *>(p + 4);
             }
-        }
-#pragma unroll
-        for (int u = 0; u < NT; ++u) {
-            const int64_t vo = (int64_t)16 * u * a.dtot + f0;
-            vh[u] = *reinterpret_cast<const u32x4 *>(Vh + vo);
-            vl[u] = *reinterpret_cast<const u32x4 *>(Vl + vo);
-        }
-    };
-    auto mma = [&](int st, const u32x4(&xa)[TR], const u32x4(&vh)[NT], const u32x4(&vl)[NT]) {
-        if (st >= nst)
-            return; // wave-uniform
-        const bool fok = fbeg + 32 * (int64_t)st + 8 * g < dv;
-#pragma unroll
-        for (int t = 0; t < TR; ++t) {
-            u32x4 x = xa[t];
-            if (IN == kInFP8) {
-                uint32_t e0, e1, e2, e3;
-                fp8x4_to_bf16(xa[t][0], e0, e1);
-                fp8x4_to_bf16(xa[t][1], e2, e3);
-                x = u32x4{e0, e1, e2, e3};
-            }
-            if (!(fok && rok[t]))
-                x = u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
             for (int u = 0; u < NT; ++u) {
-                acc[t][u] = mfma_bf16(x, vh[u], acc[t][u]);
-                acc[t][u] = mfma_bf16(x, vl[u], acc[t][u]);
+                const float *q = Vf + (int64_t)16 * u * a.dtot + f0;
+                va[u][0] = *reinterpret_cast<const f32x4 *>(q);
+                va[u][1] = *reinterpret_cast<const f32x4 *>(q + 4);
+            }
+        };
+        auto mma = [&](int st, const f32x4(&xa)[TR][2], const f32x4(&va)[NT][2]) {
+            if (st >= nst)
+                return; // wave-uniform
+            const bool fok = fbeg + 32 * (int64_t)st + 8 * g < dv;
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                f32x4 x[2] = {xa[t][0], xa[t][1]};
+                if (!(fok && rok[t]))
+                    x[0] = x[1] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int u = 0; u < NT; ++u)
+                    acc[t][u] = mfma_f32x8(x, va[u], acc[t][u]);
+            }
+        };
+        f32x4 xa0[TR][2], va0[NT][2], xa1[TR][2], va1[NT][2];
+        if (nst > 0) {
+            load(0, xa0, va0);
+            for (int st = 0; st < nst; st += 2) {
+                load(st + 1, xa1, va1);
+                __builtin_amdgcn_sched_barrier(0);
+                mma(st, xa0, va0);
+                load(st + 2, xa0, va0);
+                __builtin_amdgcn_sched_barrier(0);
+                mma(st + 1, xa1, va1);
             }
         }
-    };
-    u32x4 xa0[TR], vh0[NT], vl0[NT], xa1[TR], vh1[NT], vl1[NT];
-    if (nst > 0) {
-        load(0, xa0, vh0, vl0);
-        for (int st = 0; st < nst; st += 2) {
-            load(st + 1, xa1, vh1, vl1);
-            __builtin_amdgcn_sched_barrier(0);
-            mma(st, xa0, vh0, vl0);
-            load(st + 2, xa0, vh0, vl0);
-            __builtin_amdgcn_sched_barrier(0);
-            mma(st + 1, xa1, vh1, vl1);
+    } else {
+        // one 32-feature chunk: raw X (BF16: 4 dwords; FP8: 2 dwords) and V hi/lo
+        const uint16_t *Vh = a.Vh + a.off[v] + (int64_t)r16 * a.dtot + 8 * g;
+        const uint16_t *Vl = a.Vl + a.off[v] + (int64_t)r16 * a.dtot + 8 * g;
+        auto load = [&](int st, u32x4(&xa)[TR], u32x4(&vh)[NT], u32x4(&vl)[NT]) {
+            const int64_t f0 = fbeg + 32 * (int64_t)(st < nst ? st : nst - 1);
+            const int64_t fx = f0 + 8 * g < dv ? f0 + 8 * g : dv - 8;
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                if (IN == kInBF16) {
+                    xa[t] = *reinterpret_cast<const u32x4 *>(xr[t] + 2 * fx);
+                } else {
+                    const u32x2 q = *reinterpret_cast<const u32x2 *>(xr[t] + fx);
+                    xa[t] = u32x4{q[0], q[1], 0u, 0u};
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                const int64_t vo = (int64_t)16 * u * a.dtot + f0;
+                vh[u] = *reinterpret_cast<const u32x4 *>(Vh + vo);
+                vl[u] = *reinterpret_cast<const u32x4 *>(Vl + vo);
+            }
+        };
+        auto mma = [&](int st, const u32x4(&xa)[TR], const u32x4(&vh)[NT], const u32x4(&vl)[NT]) {
+            if (st >= nst)
+                return; // wave-uniform
+            const bool fok = fbeg + 32 * (int64_t)st + 8 * g < dv;
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                u32x4 x = xa[t];
+                if (IN == kInFP8) {
+                    uint32_t e0, e1, e2, e3;
+                    fp8x4_to_bf16(xa[t][0], e0, e1);
+                    fp8x4_to_bf16(xa[t][1], e2, e3);
+                    x = u32x4{e0, e1, e2, e3};
+                }
+                if (!(fok && rok[t]))
+                    x = u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int u = 0; u < NT; ++u) {
+                    acc[t][u] = mfma_bf16(x, vh[u], acc[t][u]);
+                    acc[t][u] = mfma_bf16(x, vl[u], acc[t][u]);
+                }
+            }
+        };
+        u32x4 xa0[TR], vh0[NT], vl0[NT], xa1[TR], vh1[NT], vl1[NT];
+        if (nst > 0) {
+            load(0, xa0, vh0, vl0);
+            for (int st = 0; st < nst; st += 2) {
+                load(st + 1, xa1, vh1, vl1);
+                __builtin_amdgcn_sched_barrier(0);
+                mma(st, xa0, vh0, vl0);
+                load(st + 2, xa0, vh0, vl0);
+                __builtin_amdgcn_sched_barrier(0);
+                mma(st + 1, xa1, vh1, vl1);
+            }
         }
     }
 
@@ -326,11 +403,12 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
 
 // ---------------------------------------------------------------------------
 // Middle pass, 16 rows per workgroup: sum the forward slices in a fixed order
-// and write row m of W (BF16 hi/lo over the minibatch rows) = column m of
-// [P | Q] (CCA) or of R = P - (M V)[labels] followed by the one-hot L (LDA,
-// M V from the statistics totals of this iteration); block 0 advances t.
+// and write row m of W (BF16 hi/lo over the minibatch rows; FP32 input: FP32)
+// = column m of [P | Q] (CCA) or of R = P - (M V)[labels] followed by the
+// one-hot L (LDA, M V from the statistics totals of this iteration); block 0
+// advances t.
 // ---------------------------------------------------------------------------
-template <int KP, int KIND>
+template <int KP, int IN, int KIND>
 __global__ void __launch_bounds__(kWT) k_wmid(WideArgs a)
 {
     constexpr bool LDA = KIND == kKindLDA;
@@ -365,17 +443,31 @@ __global__ void __launch_bounds__(kWT) k_wmid(WideArgs a)
         tile[e] = s;
     }
     __syncthreads();
-    for (int e = tid; e < NV * KP * 16; e += kWT) {
-        const int m = e / 16, rl = e % 16;
-        uint32_t hi, lo;
-        split_bf16(tile[rl * NV * KP + m], hi, lo);
-        a.Wh[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)hi;
-        a.Wl[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)lo;
-    }
-    if (LDA) {
-        for (int e = tid; e < 16 * 16; e += kWT) {
-            const int c = e / 16, rl = e % 16;
-            a.Wh[(int64_t)(KP + c) * a.ldr + r0 + rl] = lab[rl] == c ? (uint16_t)0x3F80 : (uint16_t)0;
+    if constexpr (IN == kInF32) {
+        for (int e = tid; e < NV * KP * 16; e += kWT) {
+            const int m = e / 16, rl = e % 16;
+            a.Wf[(int64_t)m * a.ldr + r0 + rl] = tile[rl * NV * KP + m];
+        }
+        if (LDA) {
+            for (int e = tid; e < 16 * 16; e += kWT) {
+                const int c = e / 16, rl = e % 16;
+                a.Wf[(int64_t)(KP + c) * a.ldr + r0 + rl] = lab[rl] == c ? 1.f : 0.f;
+            }
+        }
+    } else {
+        for (int e = tid; e < NV * KP * 16; e += kWT) {
+            const int m = e / 16, rl = e % 16;
+            uint32_t hi, lo;
+            split_bf16(tile[rl * NV * KP + m], hi, lo);
+            a.Wh[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)hi;
+            a.Wl[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)lo;
+        }
+        if (LDA) {
+            for (int e = tid; e < 16 * 16; e += kWT) {
+                const int c = e / 16, rl = e % 16;
+                a.Wh[(int64_t)(KP + c) * a.ldr + r0 + rl] =
+                    lab[rl] == c ? (uint16_t)0x3F80 : (uint16_t)0;
+            }
         }
     }
     if (q == 0 && tid == 0)
@@ -471,11 +563,19 @@ __device__ __forceinline__ void write_stats(const WideArgs &a, int wg,
 }
 
 // Player-major BF16 hi/lo operand of s_f Vn for the 64 features of a tile
-// (two features per thread per pass, one 128-byte run per player).
+// (two features per thread per pass, one 128-byte run per player); FP32
+// input: the FP32 copy of Vn.
 template <int KP, int KIND, int IN>
 __device__ __forceinline__ void write_vop(const WideArgs &a, const float *Vn, int64_t frow)
 {
     constexpr int VLD = Shape<KP, KIND>::VLD;
+    if constexpr (IN == kInF32) { // player-major FP32 copy, one 256-byte run per player
+        for (int e = threadIdx.x; e < KP * kFT; e += kBT) {
+            const int i = e / kFT, fl = e % kFT;
+            a.Vf[(int64_t)i * a.dtot + frow + fl] = Vn[fl * VLD + i];
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < KP * (kFT / 2); e += kBT) {
         const int i = e / (kFT / 2), fl = 2 * (e % (kFT / 2));
         float x0 = Vn[fl * VLD + i], x1 = Vn[(fl + 1) * VLD + i];
@@ -522,6 +622,14 @@ template <int NU> struct BwdChunk {
     u32x4 lh;
 };
 
+// The same chunk for FP32 input: X (8 rows x 4 features per lane), the W
+// tiles and the one-hot tile, eight rows per lane each.
+template <int NU> struct BwdChunk32 {
+    f32x4 x[8];
+    f32x4 w[NU][2];
+    f32x4 l[2];
+};
+
 // ---------------------------------------------------------------------------
 // Backward products, coefficients and fused epilogue.
 // Main loop over 32-row chunks (wave w takes chunks w, w + 8, ...): lane l
@@ -559,7 +667,7 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
     const int64_t dv = a.dv[v];
     const int64_t ld = v ? a.ldy : a.ldx;
     const uint8_t *Xb = (const uint8_t *)(v ? a.Y : a.X);
-    constexpr int ES = IN == kInBF16 ? 2 : 1;
+    constexpr int ES = IN == kInBF16 ? 2 : (IN == kInF32 ? 4 : 1);
     const int nch = (int)((a.b + 31) / 32);
     const double t = a.coef->t; // this iteration's number, set by k_wmid
     const double ib = 1.0 / (double)a.b;
@@ -570,8 +678,9 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
     const float c1 = (float)(1.0 - pow(a.adam_b1, t)), c2 = (float)(1.0 - pow(a.adam_b2, t));
     if (LDA && tid < NC)
         sprior[tid] = tid < a.ncls ? a.prior[tid] : 0.0; // read after the loop's barriers
-    const uint16_t *Wh = a.Wh + (int64_t)l16 * a.ldr + 8 * g;
-    const uint16_t *Wl = a.Wl + (int64_t)l16 * a.ldr + 8 * g;
+    const uint16_t *Wh = IN == kInF32 ? nullptr : a.Wh + (int64_t)l16 * a.ldr + 8 * g;
+    const uint16_t *Wl = IN == kInF32 ? nullptr : a.Wl + (int64_t)l16 * a.ldr + 8 * g;
+    const float *Wf = IN == kInF32 ? a.Wf + (int64_t)l16 * a.ldr + 8 * g : nullptr;
 
     f64x4 sacc[StatTiles<KP, KIND>::H];
 #pragma unroll
@@ -606,108 +715,190 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
         const bool fok = fu < dv;
         const uint8_t *xc = Xb + (fok ? fu : dv - 4) * ES;
 
-        auto loadc = [&](int ch, BwdChunk<NU> &B) {
-            const int64_t r0 = (int64_t)(ch < nch ? ch : nch - 1) * 32;
+        if constexpr (IN == kInF32) {
+            auto loadc = [&](int ch, BwdChunk32<NU> &B) {
+                const int64_t r0 = (int64_t)(ch < nch ? ch : nch - 1) * 32;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t row = r0 + 8 * g + j < a.b ? r0 + 8 * g + j : a.b - 1;
-                if (IN == kInBF16)
-                    B.x[j] = *reinterpret_cast<const u32x2 *>(xc + row * ld * 2);
-                else
-                    B.x[j] = u32x2{*reinterpret_cast<const uint32_t *>(xc + row * ld), 0u};
-            }
-#pragma unroll
-            for (int u = 0; u < NU; ++u) {
-                const int64_t wo = (int64_t)16 * u * a.ldr + r0;
-                B.wh[u] = *reinterpret_cast<const u32x4 *>(Wh + wo);
-                B.wl[u] = *reinterpret_cast<const u32x4 *>(Wl + wo);
-            }
-            if (LDA)
-                B.lh = *reinterpret_cast<const u32x4 *>(Wh + (int64_t)KP * a.ldr + r0);
-        };
-        auto compute = [&](int ch, const BwdChunk<NU> &B) {
-            if (ch >= nch)
-                return; // wave-uniform
-            const int64_t r0 = (int64_t)ch * 32;
-            uint32_t d0[8], d1[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (IN == kInBF16) {
-                    d0[j] = B.x[j][0];
-                    d1[j] = B.x[j][1];
-                } else {
-                    fp8x4_to_bf16(B.x[j][0], d0[j], d1[j]);
+                for (int j = 0; j < 8; ++j) {
+                    const int64_t row = r0 + 8 * g + j < a.b ? r0 + 8 * g + j : a.b - 1;
+                    B.x[j] = *reinterpret_cast<const f32x4 *>(xc + row * ld * 4);
                 }
-                if (!(fok && r0 + 8 * g + j < a.b))
-                    d0[j] = d1[j] = 0u;
-            }
-            u32x4 bx[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t a0 = d0[2 * q], a1 = d0[2 * q + 1];
-                const uint32_t b0 = d1[2 * q], b1 = d1[2 * q + 1];
-                bx[0][q] = (a0 & 0xFFFFu) | (a1 << 16);
-                bx[1][q] = (a0 >> 16) | (a1 & 0xFFFF0000u);
-                bx[2][q] = (b0 & 0xFFFFu) | (b1 << 16);
-                bx[3][q] = (b0 >> 16) | (b1 & 0xFFFF0000u);
-            }
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
-                    acc[c][u] = mfma_bf16(B.wh[u], bx[c], acc[c][u]);
-                    acc[c][u] = mfma_bf16(B.wl[u], bx[c], acc[c][u]);
+                    const float *q = Wf + (int64_t)16 * u * a.ldr + r0;
+                    B.w[u][0] = *reinterpret_cast<const f32x4 *>(q);
+                    B.w[u][1] = *reinterpret_cast<const f32x4 *>(q + 4);
                 }
-            if (first) {
-                // Gram terms from the W fragments: lane (m, g) holds rows 8g..8g+7 of
-                // W row m, which is both the A layout (A[m][k]) and the B layout
-                // (B[k][m]) of a 16x16x32 MFMA over those 32 rows.
-                if (!LDA) {
+                if (LDA) {
+                    const float *q = Wf + (int64_t)KP * a.ldr + r0;
+                    B.l[0] = *reinterpret_cast<const f32x4 *>(q);
+                    B.l[1] = *reinterpret_cast<const f32x4 *>(q + 4);
+                }
+            };
+            auto compute = [&](int ch, const BwdChunk32<NU> &B) {
+                if (ch >= nch)
+                    return; // wave-uniform
+                const int64_t r0 = (int64_t)ch * 32;
+                // B operand of feature column c: xb[c][h][j] = X[row 8 g + 4 h + j][4 n + c]
+                f32x4 xb[4][2];
 #pragma unroll
-                    for (int up = 0; up < NT; ++up)
+                for (int j = 0; j < 8; ++j) {
+                    const bool ok = fok && r0 + 8 * g + j < a.b;
 #pragma unroll
-                        for (int uq = 0; uq < NT; ++uq) {
-                            f32x4 &ga = gacc[up * NT + uq];
-                            ga = mfma_bf16(B.wh[up], B.wh[NT + uq], ga);
-                            ga = mfma_bf16(B.wh[up], B.wl[NT + uq], ga);
-                            ga = mfma_bf16(B.wl[up], B.wh[NT + uq], ga);
-                        }
-                } else {
-#pragma unroll
-                    for (int u = 0; u < NT; ++u) {
-                        gacc[u] = mfma_bf16(B.lh, B.wh[u], gacc[u]);
-                        gacc[u] = mfma_bf16(B.lh, B.wl[u], gacc[u]);
-                    }
+                    for (int c = 0; c < 4; ++c)
+                        xb[c][j >> 2][j & 3] = ok ? B.x[j][c] : 0.f;
                 }
 #pragma unroll
-                for (int u = 0; u < NT; ++u)
+                for (int c = 0; c < 4; ++c)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const float p0 = bf16_val(B.wh[u][q] & 0xFFFFu) + bf16_val(B.wl[u][q] & 0xFFFFu);
-                        const float p1 = bf16_val(B.wh[u][q] >> 16) + bf16_val(B.wl[u][q] >> 16);
-                        dP[u] += p0 * p0 + p1 * p1;
-                        if (!LDA) {
-                            const float q0 = bf16_val(B.wh[NT + u][q] & 0xFFFFu) +
-                                             bf16_val(B.wl[NT + u][q] & 0xFFFFu);
-                            const float q1 = bf16_val(B.wh[NT + u][q] >> 16) + bf16_val(B.wl[NT + u][q] >> 16);
-                            dQ[u] += q0 * q0 + q1 * q1;
-                        }
+                    for (int u = 0; u < NU; ++u)
+                        acc[c][u] = mfma_f32x8(B.w[u], xb[c], acc[c][u]);
+                if (first) {
+                    // Gram terms from the W fragments (lane (m, g): rows 8g..8g+7 of
+                    // W row m, the A and the B layout of the eight MFMAs)
+                    if (!LDA) {
+#pragma unroll
+                        for (int up = 0; up < NT; ++up)
+#pragma unroll
+                            for (int uq = 0; uq < NT; ++uq)
+                                gacc[up * NT + uq] =
+                                    mfma_f32x8(B.w[up], B.w[NT + uq], gacc[up * NT + uq]);
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < NT; ++u)
+                            gacc[u] = mfma_f32x8(B.l, B.w[u], gacc[u]);
                     }
+#pragma unroll
+                    for (int u = 0; u < NT; ++u)
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const float p = B.w[u][h][j];
+                                dP[u] += p * p;
+                                if (!LDA) {
+                                    const float q = B.w[NT + u][h][j];
+                                    dQ[u] += q * q;
+                                }
+                            }
+                }
+            };
+            // two chunks in flight (the FP32 products are MFMA-bound)
+            constexpr int NB = 2;
+            BwdChunk32<NU> cb[NB];
+            loadc(w, cb[0]);
+            for (int ch = w; ch < nch; ch += NB * kBW) {
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    loadc(ch + kBW * (q + 1), cb[(q + 1) % NB]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    compute(ch + kBW * q, cb[q]);
+                }
             }
-        };
-        // ring of NB chunks in flight: the loads of chunk i + NB - 1 are issued
-        // before the MFMAs of chunk i (wave w takes chunks w, w + kBW, ...)
-        constexpr int NB = 3;
-        BwdChunk<NU> cb[NB];
+        } else {
+            auto loadc = [&](int ch, BwdChunk<NU> &B) {
+                const int64_t r0 = (int64_t)(ch < nch ? ch : nch - 1) * 32;
 #pragma unroll
-        for (int p = 0; p < NB - 1; ++p)
-            loadc(w + kBW * p, cb[p]);
-        for (int ch = w; ch < nch; ch += NB * kBW) {
+                for (int j = 0; j < 8; ++j) {
+                    const int64_t row = r0 + 8 * g + j < a.b ? r0 + 8 * g + j : a.b - 1;
+                    if (IN == kInBF16)
+                        B.x[j] = *reinterpret_cast<const u32x2 *>(xc + row * ld * 2);
+                    else
+                        B.x[j] = u32x2{*reinterpret_cast<const uint32_t *>(xc + row * ld), 0u};
+                }
 #pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                loadc(ch + kBW * (q + NB - 1), cb[(q + NB - 1) % NB]);
-                __builtin_amdgcn_sched_barrier(0);
-                compute(ch + kBW * q, cb[q]);
+                for (int u = 0; u < NU; ++u) {
+                    const int64_t wo = (int64_t)16 * u * a.ldr + r0;
+                    B.wh[u] = *reinterpret_cast<const u32x4 *>(Wh + wo);
+                    B.wl[u] = *reinterpret_cast<const u32x4 *>(Wl + wo);
+                }
+                if (LDA)
+                    B.lh = *reinterpret_cast<const u32x4 *>(Wh + (int64_t)KP * a.ldr + r0);
+            };
+            auto compute = [&](int ch, const BwdChunk<NU> &B) {
+                if (ch >= nch)
+                    return; // wave-uniform
+                const int64_t r0 = (int64_t)ch * 32;
+                uint32_t d0[8], d1[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (IN == kInBF16) {
+                        d0[j] = B.x[j][0];
+                        d1[j] = B.x[j][1];
+                    } else {
+                        fp8x4_to_bf16(B.x[j][0], d0[j], d1[j]);
+                    }
+                    if (!(fok && r0 + 8 * g + j < a.b))
+                        d0[j] = d1[j] = 0u;
+                }
+                u32x4 bx[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t a0 = d0[2 * q], a1 = d0[2 * q + 1];
+                    const uint32_t b0 = d1[2 * q], b1 = d1[2 * q + 1];
+                    bx[0][q] = (a0 & 0xFFFFu) | (a1 << 16);
+                    bx[1][q] = (a0 >> 16) | (a1 & 0xFFFF0000u);
+                    bx[2][q] = (b0 & 0xFFFFu) | (b1 << 16);
+                    bx[3][q] = (b0 >> 16) | (b1 & 0xFFFF0000u);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int u = 0; u < NU; ++u) {
+                        acc[c][u] = mfma_bf16(B.wh[u], bx[c], acc[c][u]);
+                        acc[c][u] = mfma_bf16(B.wl[u], bx[c], acc[c][u]);
+                    }
+                if (first) {
+                    // Gram terms from the W fragments: lane (m, g) holds rows 8g..8g+7 of
+                    // W row m, which is both the A layout (A[m][k]) and the B layout
+                    // (B[k][m]) of a 16x16x32 MFMA over those 32 rows.
+                    if (!LDA) {
+#pragma unroll
+                        for (int up = 0; up < NT; ++up)
+#pragma unroll
+                            for (int uq = 0; uq < NT; ++uq) {
+                                f32x4 &ga = gacc[up * NT + uq];
+                                ga = mfma_bf16(B.wh[up], B.wh[NT + uq], ga);
+                                ga = mfma_bf16(B.wh[up], B.wl[NT + uq], ga);
+                                ga = mfma_bf16(B.wl[up], B.wh[NT + uq], ga);
+                            }
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < NT; ++u) {
+                            gacc[u] = mfma_bf16(B.lh, B.wh[u], gacc[u]);
+                            gacc[u] = mfma_bf16(B.lh, B.wl[u], gacc[u]);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < NT; ++u)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const float p0 = bf16_val(B.wh[u][q] & 0xFFFFu) + bf16_val(B.wl[u][q] & 0xFFFFu);
+                            const float p1 = bf16_val(B.wh[u][q] >> 16) + bf16_val(B.wl[u][q] >> 16);
+                            dP[u] += p0 * p0 + p1 * p1;
+                            if (!LDA) {
+                                const float q0 = bf16_val(B.wh[NT + u][q] & 0xFFFFu) +
+                                                 bf16_val(B.wl[NT + u][q] & 0xFFFFu);
+                                const float q1 = bf16_val(B.wh[NT + u][q] >> 16) + bf16_val(B.wl[NT + u][q] >> 16);
+                                dQ[u] += q0 * q0 + q1 * q1;
+                            }
+                        }
+                }
+            };
+            // ring of NB chunks in flight: the loads of chunk i + NB - 1 are issued
+            // before the MFMAs of chunk i (wave w takes chunks w, w + kBW, ...)
+            constexpr int NB = 3;
+            BwdChunk<NU> cb[NB];
+#pragma unroll
+            for (int p = 0; p < NB - 1; ++p)
+                loadc(w + kBW * p, cb[p]);
+            for (int ch = w; ch < nch; ch += NB * kBW) {
+#pragma unroll
+                for (int q = 0; q < NB; ++q) {
+                    loadc(ch + kBW * (q + NB - 1), cb[(q + NB - 1) % NB]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    compute(ch + kBW * q, cb[q]);
+                }
             }
         }
 

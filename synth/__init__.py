@@ -384,6 +384,33 @@ class LDAClasses:
     def batch(self, t: int, b: int, dtype=np.float32):
         return self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)
 
+    def device_tables(self, device):
+        """The class means and per-feature standard deviations as FP32
+        device tensors (kept by the caller across calls of sample_torch)."""
+        import torch
+        return (torch.from_numpy(self.means).to(device=device, dtype=torch.float32),
+                torch.from_numpy(self.sigma).to(device=device, dtype=torch.float32))
+
+    def sample_torch(self, n: int, t: int, device, dtype, tables=None, out=None):
+        """n fresh labelled rows drawn on `device` from a torch generator
+        seeded by (seed, t): uniform labels, x = mu_label + sigma * g in FP32
+        (same distribution as ``sample``, different values).  Returns
+        (x in `dtype`, int32 labels); `out` (n x d, `dtype`) receives x when
+        given."""
+        import torch
+        g = torch.Generator(device=device)
+        g.manual_seed((int(self.seed) * 1_000_003 + 7919 * int(t) + 5) & ((1 << 63) - 1))
+        means, sig = tables if tables is not None else self.device_tables(device)
+        lab = torch.randint(0, self.c, (n,), generator=g, device=device, dtype=torch.int64)
+        x = torch.randn((n, self.d), generator=g, device=device, dtype=torch.float32)
+        x.mul_(sig).add_(means.index_select(0, lab))
+        if out is not None:
+            out.copy_(x)
+            x = out
+        else:
+            x = x.to(dtype)
+        return x, lab.to(torch.int32)
+
 
 @dataclass
 class ICAMixed:

@@ -6,7 +6,8 @@ receives.  Two iterations; every output compared.
 * activation-like CCA, d = 8192 + 8192, k = 32, b = 4096: BF16, FP8-e4m3 with
   per-column scales (BF16 / FP8 path), FP32 (narrow path, 64-feature tiles,
   coefficients in k_coef)
-* LDA, d = 65536, 10 classes, k = 64, b = 2048, BF16
+* LDA, d = 65536, 10 classes, k = 64, b = 2048, BF16 and FP32 (both on the
+  large-d path)
 
 Bars: the N-iteration bars of the small-size tests (BF16 / FP8: 1.2e-3;
 FP32: 3e-4) on unit players and relative on [Bv] and the eigenvalue
@@ -28,7 +29,8 @@ pytestmark = pytest.mark.gpu
 TOL = {"bf16": 1.2e-3, "fp8": 1.2e-3, "f32": 3e-4}
 
 WORKLOADS = ["cca_d16384_k32_b4096_bf16", "cca_d16384_k32_b4096_fp8",
-             "cca_d16384_k32_b4096_fp32", "lda_d65536_k64_b2048_bf16"]
+             "cca_d16384_k32_b4096_fp32", "lda_d65536_k64_b2048_bf16",
+             "lda_d65536_k64_b2048_fp32"]
 
 
 @pytest.mark.parametrize("opt", ["adam", "sgd"])

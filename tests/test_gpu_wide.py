@@ -138,18 +138,29 @@ def _lda_problem(d, c, k, seed=5):
     return gen, priors
 
 
+# FP32 minibatches on the large-d path: FP32 operands and FP32 MFMA, so the
+# bars of the FP32 tests (TOLF_1 after one iteration, TOLF_N after N)
+TOLF_1 = 2e-5
+TOLF_N = 3e-4
+
+
+@pytest.mark.parametrize("fmt", ["bf16", "f32"])
 @pytest.mark.parametrize("d,c,k,b,opt", [
     (200, 10, 9, 300, "sgd"),     # KP 16, 4 subtiles, ragged rows
     (520, 6, 20, 130, "adam"),    # KP 32
     (136, 10, 64, 77, "sgd"),     # KP 64, k > classes (zero eigenvalues beyond c - 1)
+    (4104, 5, 40, 200, "adam"),   # KP 64, several forward slices, ragged last subtile
 ])
-def test_wide_lda_parity(d, c, k, b, opt):
+def test_wide_lda_parity(d, c, k, b, opt, fmt):
     sg = _sg()
-    print(f"wide LDA bf16 d={d} c={c} k={k} b={b} {opt}", flush=True)
+    torch = _torch()
+    print(f"wide LDA {fmt} d={d} c={c} k={k} b={b} {opt}", flush=True)
     gen, priors = _lda_problem(d, c, k)
     adam = opt == "adam"
     eps = 1e-3
-    cfg = sg.make_config(sg.SGEP_KIND_LDA, sg.SGEP_BF16, k, d, 0, b,
+    dt = sg.SGEP_BF16 if fmt == "bf16" else sg.SGEP_F32
+    tol1, tolN = (TOLW_1, TOLW_N) if fmt == "bf16" else (TOLF_1, TOLF_N)
+    cfg = sg.make_config(sg.SGEP_KIND_LDA, dt, k, d, 0, b,
                          optimizer=sg.SGEP_ADAM if adam else sg.SGEP_SGD,
                          schedule=sg.SGEP_SCHED_INV, eta0=1e-3 if adam else 0.01, t0=100.0,
                          gamma=0.5, rho=1e-6, eps_reg=eps, n_classes=c)
@@ -161,12 +172,17 @@ def test_wide_lda_parity(d, c, k, b, opt):
     N = 30
     for t in range(1, N + 1):
         X, lab = gen.batch(t, b)
-        bits = synth.bf16_bits(X)
-        s.step(_bf16_dev(bits), _i32_dev(lab))
-        oracle.gamma_step(pb, st, synth.bf16_value(bits), None, _eta(cfg, t), cfg.gamma,
-                          labels=lab)
+        if fmt == "bf16":
+            bits = synth.bf16_bits(X)
+            s.step(_bf16_dev(bits), _i32_dev(lab))
+            Xo = synth.bf16_value(bits)
+        else:
+            X32 = np.ascontiguousarray(X, dtype=np.float32)
+            s.step(torch.from_numpy(X32).cuda(), _i32_dev(lab))
+            Xo = X32.astype(np.float64)
+        oracle.gamma_step(pb, st, Xo, None, _eta(cfg, t), cfg.gamma, labels=lab)
         if t in (1, N):
-            tol = TOLW_1 if t == 1 else TOLW_N
+            tol = tol1 if t == 1 else tolN
             Vg, Gg = s.vectors(), s.auxiliary()
             dv, dg = _maxdiff(Vg, st.V), _maxdiff(Gg, st.G)
             print(f"  t={t}: max|dV|={dv:.2e} max|dG|={dg:.2e}", flush=True)

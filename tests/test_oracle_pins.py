@@ -747,3 +747,19 @@ def test_lda_stochastic_alg2_reaches_the_reduced_solution():
     Xs, _ = g.batch(0, 4096, dtype=np.float64)
     Bw = Xs.T @ Xs / 4096 + eps * np.eye(24)
     assert oracle.subspace_error(oracle.gep_topk(A, Bw, 3)[1], Vs, B) > 10 * err
+
+
+def test_subspace_error_diagonal_b_equals_dense_diagonal():
+    """The diagonal form of the metric (B given by its diagonal) equals the
+    dense form with np.diag(B), and App. A's definition."""
+    rng = np.random.default_rng(21)
+    d, k = 30, 4
+    bd = np.exp(rng.uniform(-2, 2, d))
+    Vs = rng.standard_normal((d, k))
+    L = np.linalg.cholesky(Vs.T @ (bd[:, None] * Vs))
+    Vs = Vs @ np.linalg.inv(L).T  # B-orthonormal
+    Vh = Vs + 0.1 * rng.standard_normal((d, k))
+    e1 = oracle.subspace_error(Vh, Vs, bd)
+    e2 = oracle.subspace_error(Vh, Vs, np.diag(bd))
+    e3 = oracle.subspace_error_definition(Vh, Vs, np.diag(bd))
+    assert abs(e1 - e2) < 1e-14 and abs(e1 - e3) < 1e-12 and 0.0 < e1 < 1.0
