@@ -395,6 +395,31 @@ def subspace_error(Vhat: np.ndarray, Vstar: np.ndarray, B: np.ndarray) -> float:
     return float(1.0 - np.trace(C.T @ np.linalg.solve(G, C)) / k)
 
 
+def subspace_containment_error(Vhat: np.ndarray, Vstar: np.ndarray, B: np.ndarray) -> float:
+    """App. A's normalised subspace error when the exact subspace is larger
+    than the players' (Vstar: the m >= k columns of a B-orthonormal
+    eigenspace block whose eigenvalues are separated from the rest, Vhat: k
+    players): 1 - tr(U* P)/k with U* the B-projector on span(Vstar) and P the
+    one on span(Vhat), i.e. the mean sin^2 of the angles between the players'
+    subspace and the block in the B-inner product.  0 when span(Vhat) lies in
+    span(Vstar), 1 when it is B-orthogonal to it; equal to subspace_error when
+    m = k.  With C = Vhat^T B Vstar and G = Vhat^T B Vhat this is
+    1 - tr(G^{-1} C C^T)/k.  B: a matrix, its diagonal (1-D), or a function
+    applying B to a block of columns."""
+    k = Vhat.shape[1]
+    if callable(B):
+        mulB = B
+    else:
+        B = np.asarray(B)
+
+        def mulB(M):
+            return B[:, None] * M if B.ndim == 1 else B @ M
+
+    C = Vhat.T @ mulB(Vstar)
+    G = Vhat.T @ mulB(Vhat)
+    return float(1.0 - np.trace(np.linalg.solve(G, C @ C.T)) / k)
+
+
 def subspace_error_definition(Vhat: np.ndarray, Vstar: np.ndarray, B: np.ndarray) -> float:
     """The same error written as App. A defines it: W holds the top-k
     eigenvectors of B^{-1/2} A B^{-1/2} (= B^{1/2} Vstar), What = B^{1/2} Vhat,

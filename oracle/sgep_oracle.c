@@ -35,6 +35,7 @@
  * i occupies V[i*d .. i*d+d-1].  Minibatch views are row-major, one sample
  * per row, with an explicit leading dimension.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -102,61 +103,87 @@ static void frob_parts(int n, const double *a, double *off, double *all)
  * on return its diagonal holds the eigenvalues.  z (n x n, row-major) receives
  * the eigenvectors as COLUMNS (z[r*n + c] is component r of vector c); w the
  * eigenvalues (unsorted, w[c] belongs to column c).  Sweeps until
- * off(a) <= tol * ||a||_F or max_sweeps is reached.  Returns the number of
- * sweeps used, or -1 if it did not converge. */
+ * off(a) <= tol * ||a||_F, or until a sweep finds every off-diagonal element
+ * negligible at working precision against its diagonal pair
+ * (|a_pq| <= eps sqrt(|a_pp a_qq|), the relative threshold of Demmel and
+ * Veselic, 1992: the off-diagonal norm of a large matrix stops shrinking at
+ * a rounding floor that can lie above tol * ||a||_F), or max_sweeps is
+ * reached.  Returns the number of sweeps used, or -1 if it did not
+ * converge. */
 int oracle_jacobi_eigh(int n, double *a, double *w, double *z, double tol, int max_sweeps)
 {
+    /* the eigenvectors are accumulated as ROWS of zt (contiguous updates) */
+    double *zt = (double *)malloc((size_t)n * n * sizeof(double));
+    if (!zt)
+        return -1;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j)
-            z[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
+            zt[(size_t)i * n + j] = (i == j) ? 1.0 : 0.0;
     double off, all;
     frob_parts(n, a, &off, &all);
-    int sweep = 0;
+    int sweep = 0, rc = 0;
     while (off > tol * all) {
-        if (sweep >= max_sweeps)
-            return -1;
+        if (sweep >= max_sweeps) {
+            rc = -1;
+            break;
+        }
+        int rotated = 0;
         for (int p = 0; p < n - 1; ++p) {
             for (int q = p + 1; q < n; ++q) {
-                double apq = a[(size_t)p * n + q];
-                if (apq == 0.0)
-                    continue;
-                /* two-by-two symmetric Schur decomposition: choose (c, s) so
-                 * that J^T a J has a zero in position (p, q), taking the
-                 * smaller rotation angle for stability */
-                double tau = (a[(size_t)q * n + q] - a[(size_t)p * n + p]) / (2.0 * apq);
+                const double apq = a[(size_t)p * n + q];
+                const double app = a[(size_t)p * n + p], aqq = a[(size_t)q * n + q];
+                if (fabs(apq) <= DBL_EPSILON * sqrt(fabs(app * aqq)))
+                    continue; /* negligible (zero included) */
+                rotated = 1;
+                /* two-by-two symmetric Schur decomposition: J = [[c, s], [-s, c]]
+                 * on (p, q) with t = s / c the smaller root of
+                 * t^2 + 2 tau t - 1 = 0, so that J^T a J has a zero in
+                 * position (p, q) (Golub and Van Loan, Sec. 8.5) */
+                const double tau = (aqq - app) / (2.0 * apq);
                 double t;
                 if (tau >= 0.0)
                     t = 1.0 / (tau + sqrt(1.0 + tau * tau));
                 else
                     t = -1.0 / (-tau + sqrt(1.0 + tau * tau));
-                double c = 1.0 / sqrt(1.0 + t * t);
-                double s = t * c;
-                /* a <- a J (columns p and q) */
+                const double c = 1.0 / sqrt(1.0 + t * t);
+                const double sn = t * c;
+                /* rows p and q of J^T a J outside the 2 x 2 block, mirrored into
+                 * columns p and q (a stays symmetric) */
                 for (int r = 0; r < n; ++r) {
-                    double arp = a[(size_t)r * n + p], arq = a[(size_t)r * n + q];
-                    a[(size_t)r * n + p] = c * arp - s * arq;
-                    a[(size_t)r * n + q] = s * arp + c * arq;
+                    if (r == p || r == q)
+                        continue;
+                    const double apr = a[(size_t)p * n + r], aqr = a[(size_t)q * n + r];
+                    const double np = c * apr - sn * aqr, nq = sn * apr + c * aqr;
+                    a[(size_t)p * n + r] = np;
+                    a[(size_t)r * n + p] = np;
+                    a[(size_t)q * n + r] = nq;
+                    a[(size_t)r * n + q] = nq;
                 }
-                /* a <- J^T a (rows p and q) */
+                /* the 2 x 2 block in closed form */
+                a[(size_t)p * n + p] = app - t * apq;
+                a[(size_t)q * n + q] = aqq + t * apq;
+                a[(size_t)p * n + q] = 0.0;
+                a[(size_t)q * n + p] = 0.0;
+                /* vectors: z <- z J, i.e. rows p and q of zt */
                 for (int r = 0; r < n; ++r) {
-                    double apr = a[(size_t)p * n + r], aqr = a[(size_t)q * n + r];
-                    a[(size_t)p * n + r] = c * apr - s * aqr;
-                    a[(size_t)q * n + r] = s * apr + c * aqr;
-                }
-                /* z <- z J */
-                for (int r = 0; r < n; ++r) {
-                    double zrp = z[(size_t)r * n + p], zrq = z[(size_t)r * n + q];
-                    z[(size_t)r * n + p] = c * zrp - s * zrq;
-                    z[(size_t)r * n + q] = s * zrp + c * zrq;
+                    const double zp = zt[(size_t)p * n + r], zq = zt[(size_t)q * n + r];
+                    zt[(size_t)p * n + r] = c * zp - sn * zq;
+                    zt[(size_t)q * n + r] = sn * zp + c * zq;
                 }
             }
         }
         ++sweep;
         frob_parts(n, a, &off, &all);
+        if (!rotated)
+            break;
     }
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
         w[i] = a[(size_t)i * n + i];
-    return sweep;
+        for (int j = 0; j < n; ++j)
+            z[(size_t)j * n + i] = zt[(size_t)i * n + j];
+    }
+    free(zt);
+    return rc < 0 ? rc : sweep;
 }
 
 /* Forward substitution: solve L x = rhs for lower-triangular L (n x n,

@@ -131,3 +131,82 @@ def _canon(V):
         if V[j, i] < 0:
             V[:, i] = -V[:, i]
     return V
+
+
+def relu_pair_cov(C, sa, sb):
+    """Covariance of relu(a) and relu(b) for zero-mean jointly Gaussian (a, b)
+    with standard deviations sa, sb and covariance C (arrays broadcast as
+    C[i, j], sa[i], sb[j]): E[relu(a) relu(b)] is the degree-1 arc-cosine
+    kernel (Cho and Saul, 2009), sa sb (sin t + (pi - t) cos t) / (2 pi) with
+    cos t = C / (sa sb), and E[relu(a)] = sa / sqrt(2 pi)."""
+    S = np.outer(sa, sb)
+    cos = np.clip(C / S, -1.0, 1.0)
+    th = np.arccos(cos)
+    K = S * (np.sin(th) + (np.pi - th) * cos) / (2.0 * np.pi)
+    return K - S / (2.0 * np.pi)
+
+
+def cca_activation_population(gen):
+    """Population covariances of ``synth.CCAActivation``: with
+    u_x = Wx h + xi (covariance Wx Wx^T + I), u_y = Wy h + xi' and
+    cov(u_x, u_y) = Wx Wy^T, the views x = Dx (relu(u_x) - mu_x) and
+    y = Dy (relu(u_y) - mu_y) have Sxx = Dx cov(relu(u_x)) Dx,
+    Syy = Dy cov(relu(u_y)) Dy and Sxy = Dx cov(relu(u_x), relu(u_y)) Dy,
+    each entry from ``relu_pair_cov``."""
+    sx = np.sqrt((gen.Wx ** 2).sum(axis=1) + 1.0)
+    sy = np.sqrt((gen.Wy ** 2).sum(axis=1) + 1.0)
+    Cxx = gen.Wx @ gen.Wx.T
+    Cxx[np.diag_indices_from(Cxx)] += 1.0
+    Cyy = gen.Wy @ gen.Wy.T
+    Cyy[np.diag_indices_from(Cyy)] += 1.0
+    Sxx = relu_pair_cov(Cxx, sx, sx) * np.outer(gen.Dx, gen.Dx)
+    Syy = relu_pair_cov(Cyy, sy, sy) * np.outer(gen.Dy, gen.Dy)
+    Sxy = relu_pair_cov(gen.Wx @ gen.Wy.T, sx, sy) * np.outer(gen.Dx, gen.Dy)
+    return Sxx, Syy, Sxy
+
+
+def cca_topk_subspace(Sxx, Syy, Sxy, k: int, p: int = None, tol: float = 1e-10,
+                      max_iter: int = 5000, seed: int = 0):
+    """Exact top-k of the CCA problem (Sec. 1) through the singular pairs of
+    K = Lx^{-1} Sxy Ly^{-T} (Lx Lx^T = Sxx, Ly Ly^T = Syy): the generalized
+    eigenvalues of A v = lambda B v are +-sigma_i, and the B-orthonormal
+    vectors of +sigma_i are v_i = [Lx^{-T} u_i; Ly^{-T} w_i] / sqrt(2) for the
+    singular pair (u_i, w_i).  The top-k left singular vectors come from
+    block subspace iteration on K K^T (block of p >= k columns, a QR
+    re-orthonormalisation per iteration) with a Rayleigh-Ritz step by the
+    oracle's cyclic Jacobi, until every leading residual
+    ||K K^T u_i - sigma_i^2 u_i|| <= tol sigma_1^2.  Cholesky factors,
+    triangular solves, QR and matrix products are library routines.
+    Returns (sigma descending (k,), V (dx + dy, k)), signs canonical."""
+    import scipy.linalg as sla
+    dx = Sxx.shape[0]
+    p = p or min(dx, 2 * k)
+    Lx = np.linalg.cholesky(Sxx)
+    Ly = np.linalg.cholesky(Syy)
+    K = sla.solve_triangular(Lx, Sxy, lower=True)
+    K = sla.solve_triangular(Ly, K.T, lower=True).T
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((dx, p)))
+    it = 0
+    while True:
+        Z = K @ (K.T @ Q)
+        Q, _ = np.linalg.qr(Z)
+        KtQ = K.T @ Q
+        M = KtQ.T @ KtQ
+        w, U = jacobi_eigh(0.5 * (M + M.T))
+        order = np.argsort(-w, kind="stable")
+        w, U = w[order], U[:, order]
+        Q = Q @ U
+        KtQ = KtQ @ U
+        R = K @ KtQ[:, :k] - Q[:, :k] * w[None, :k]
+        it += 1
+        if np.linalg.norm(R, axis=0).max() <= tol * w[0]:
+            break
+        if it >= max_iter:
+            raise RuntimeError("subspace iteration did not converge")
+    sig = np.sqrt(w[:k])
+    Uk = Q[:, :k]
+    Wk = KtQ[:, :k] / sig[None, :]
+    Vx = sla.solve_triangular(Lx.T, Uk, lower=False)
+    Vy = sla.solve_triangular(Ly.T, Wk, lower=False)
+    return sig.copy(), _canon(np.vstack([Vx, Vy]) / np.sqrt(2.0))

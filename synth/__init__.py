@@ -202,6 +202,31 @@ class CCAActivation:
     def batch(self, t: int, b: int, dtype=np.float32):
         return self.sample(b, np.random.default_rng([self.seed + 1, t]), dtype)
 
+    def device_tables(self, device):
+        """Maps, feature scales and ReLU means as FP32 device tensors (kept
+        by the caller across calls of sample_torch)."""
+        import torch
+        f32 = torch.float32
+        mx, my = self.relu_means()
+        return tuple(torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=f32)
+                     for a in (self.Wx.T, self.Wy.T, self.Dx, self.Dy, mx, my))
+
+    def sample_torch(self, n: int, t: int, device, dtype, tables=None):
+        """n fresh pairs drawn on `device` from a torch generator seeded by
+        (seed, t), in FP32 (same distribution as ``sample``, different
+        values), returned in `dtype`."""
+        import torch
+        g = torch.Generator(device=device)
+        g.manual_seed((int(self.seed) * 1_000_003 + 7919 * int(t) + 3) & ((1 << 63) - 1))
+        WxT, WyT, Dx, Dy, mx, my = tables if tables is not None else self.device_tables(device)
+        f32 = torch.float32
+        h = torch.randn((n, self.r), generator=g, device=device, dtype=f32)
+        x = torch.randn((n, self.dx), generator=g, device=device, dtype=f32)
+        x.addmm_(h, WxT).clamp_(min=0.0).sub_(mx).mul_(Dx)
+        y = torch.randn((n, self.dy), generator=g, device=device, dtype=f32)
+        y.addmm_(h, WyT).clamp_(min=0.0).sub_(my).mul_(Dy)
+        return x.to(dtype), y.to(dtype)
+
 
 class _FastOrth:
     """Dense random orthogonal d x d matrix Q = H2 H1 C Pi: Pi a signed random

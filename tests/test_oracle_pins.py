@@ -763,3 +763,109 @@ def test_subspace_error_diagonal_b_equals_dense_diagonal():
     e2 = oracle.subspace_error(Vh, Vs, np.diag(bd))
     e3 = oracle.subspace_error_definition(Vh, Vs, np.diag(bd))
     assert abs(e1 - e2) < 1e-14 and abs(e1 - e3) < 1e-12 and 0.0 < e1 < 1.0
+
+
+
+# --------------------------------------------------------------------------- #
+# The activation-like CCA: population covariances and the top-k route        #
+# --------------------------------------------------------------------------- #
+
+def test_relu_pair_cov_special_cases_and_quadrature():
+    """Covariance of relu of jointly Gaussian pairs: E[relu(a)^2] = s^2/2
+    (so the variance is s^2 (1/2 - 1/(2 pi))); independent pairs have zero
+    covariance; relu(a) relu(-a) = 0, so a perfectly anti-correlated pair
+    has covariance -E relu(a) E relu(-a); a generic pair agrees with direct
+    numerical integration of the bivariate normal density."""
+    from scipy import integrate
+    sa, sb = np.array([1.3]), np.array([0.7])
+    v = targets.relu_pair_cov(np.array([[1.3 * 1.3]]), sa, sa)[0, 0]
+    assert abs(v - 1.69 * (0.5 - 0.5 / np.pi)) < 1e-14
+    assert abs(targets.relu_pair_cov(np.array([[0.0]]), sa, sb)[0, 0]) < 1e-15
+    anti = targets.relu_pair_cov(np.array([[-1.3 * 0.7]]), sa, sb)[0, 0]
+    assert abs(anti + 1.3 * 0.7 / (2 * np.pi)) < 1e-14
+    for c in (0.35, -0.6, 0.9):
+        cab = c * 1.3 * 0.7
+
+        q = np.sqrt(1 - c * c)
+
+        def f(z2, z1):  # on the region a > 0, b > 0 the integrand is smooth
+            a = 1.3 * z1
+            b = 0.7 * (c * z1 + q * z2)
+            return a * b * np.exp(-0.5 * (z1 * z1 + z2 * z2)) / (2 * np.pi)
+
+        e_ab, _ = integrate.dblquad(f, 0.0, 12.0, lambda z1: -c * z1 / q, 12.0,
+                                    epsabs=1e-13, epsrel=1e-12)
+        ref = e_ab - (1.3 / np.sqrt(2 * np.pi)) * (0.7 / np.sqrt(2 * np.pi))
+        got = targets.relu_pair_cov(np.array([[cab]]), sa, sb)[0, 0]
+        assert abs(got - ref) < 1e-11, (c, got, ref)
+
+
+def test_activation_cca_population_matches_a_large_sample():
+    """The closed-form covariances of the activation-like views agree with
+    the empirical covariances of 400,000 drawn pairs (statistical, 5 sigma
+    of the sampling error) and the views have mean zero."""
+    g = synth.CCAActivation(dx=6, dy=5, r=4, seed=2)
+    Sxx, Syy, Sxy = targets.cca_activation_population(g)
+    X, Y = g.sample(400_000, np.random.default_rng(9), dtype=np.float64)
+    n = X.shape[0]
+    for M, E in ((Sxx, X.T @ X / n), (Syy, Y.T @ Y / n), (Sxy, X.T @ Y / n)):
+        scale = np.sqrt(np.outer(np.diag(Sxx if M is not Syy else Syy),
+                                 np.diag(Syy if M is not Sxx else Sxx)))
+        assert np.abs(E - M).max() < 5 * 3 * scale.max() / np.sqrt(n)
+    assert np.abs(X.mean(axis=0)).max() < 5 * np.sqrt(np.diag(Sxx).max() / n)
+
+
+@pytest.mark.parametrize("dxy", [64, 256])
+def test_activation_cca_topk_route_equals_dense_solver(dxy):
+    """The singular-pair route (block subspace iteration on K K^T with a
+    Jacobi Rayleigh-Ritz step) gives the top canonical correlations and
+    B-orthonormal vectors of the dense Cholesky + Jacobi solve of the same
+    population problem: eigenvalues to 1e-10, subspaces to 1e-10."""
+    g = synth.CCAActivation(dx=dxy, dy=dxy, r=16, seed=1)
+    Sxx, Syy, Sxy = targets.cca_activation_population(g)
+    k = 8
+    sig, V = targets.cca_topk_subspace(Sxx, Syy, Sxy, k, tol=1e-12)
+    A, B = oracle.cca_matrices(Sxx, Syy, Sxy)
+    lam, Vd = oracle.gep_topk(A, B, k)
+    assert np.abs(sig - lam).max() < 1e-10
+    assert abs(oracle.subspace_error(V, Vd, B)) < 1e-10
+    assert np.abs(V.T @ B @ V - np.eye(k)).max() < 1e-10
+    assert np.abs(A @ V - (B @ V) * sig[None, :]).max() < 1e-9 * np.abs(A).max()
+
+
+@pytest.mark.slow
+def test_activation_cca_topk_route_at_d1024_equals_dense_jacobi():
+    """The same check on a d = 512 + 512 instance of the benchmark's
+    activation-like generator (r = 64), the top 64-block included (about
+    two minutes of dense Jacobi)."""
+    g = synth.CCAActivation(dx=512, dy=512, seed=0)
+    Sxx, Syy, Sxy = targets.cca_activation_population(g)
+    sig, V = targets.cca_topk_subspace(Sxx, Syy, Sxy, 66, p=132, tol=1e-11)
+    A, B = oracle.cca_matrices(Sxx, Syy, Sxy)
+    lam, Vd = oracle.gep_topk(A, B, 66)
+    assert np.abs(sig - lam).max() < 1e-10
+    assert abs(oracle.subspace_error(V[:, :64], Vd[:, :64], B)) < 1e-10
+
+
+def test_subspace_containment_error_properties():
+    """Players inside the exact block give 0, players B-orthogonal to it 1,
+    a block of the players' own size reduces to subspace_error, and a
+    rotation of the players does not change it."""
+    rng = np.random.default_rng(4)
+    d, m, k = 20, 6, 3
+    B = _rand_spd(rng, d)
+    W = rng.standard_normal((d, d))
+    L = np.linalg.cholesky(B)
+    Q, _ = np.linalg.qr(W)
+    Vall = np.linalg.solve(L.T, Q)  # B-orthonormal basis of R^d
+    Vs = Vall[:, :m]
+    inside = Vs @ rng.standard_normal((m, k))
+    assert abs(oracle.subspace_containment_error(inside, Vs, B)) < 1e-13
+    outside = Vall[:, m:m + k] @ rng.standard_normal((k, k))
+    assert abs(oracle.subspace_containment_error(outside, Vs, B) - 1.0) < 1e-13
+    Vh = rng.standard_normal((d, k))
+    assert abs(oracle.subspace_containment_error(Vh, Vs[:, :k], B)
+               - oracle.subspace_error(Vh, Vs[:, :k], B)) < 1e-13
+    R = rng.standard_normal((k, k))
+    assert abs(oracle.subspace_containment_error(Vh @ R, Vs, B)
+               - oracle.subspace_containment_error(Vh, Vs, B)) < 1e-12
