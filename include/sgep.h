@@ -30,8 +30,9 @@
  *   - Argument and shape errors are returned synchronously and leave the
  *     handle unchanged.
  *   - Device faults detected inside a step (non-finite Gram terms or norms:
- *     SGEP_ENONFINITE; a workgroup that gave up its bounded wait for the
- *     iteration's coefficients: SGEP_EDEVICE) are latched in a device status
+ *     SGEP_ENONFINITE; an LDA label outside [0, n_classes): SGEP_ELABEL; a
+ *     workgroup that gave up its bounded wait for data another workgroup of
+ *     the same launch publishes: SGEP_EDEVICE) are latched in a device status
  *     word and reported by the next call that synchronises (sgep_eigvals,
  *     sgep_vectors, sgep_auxiliary, sgep_get_state, sgep_sync).  The handle is then POISONED: every later
  *     call except sgep_set_state and sgep_destroy returns SGEP_EPOISONED.
@@ -65,6 +66,7 @@ typedef int32_t sgep_status;
 #define SGEP_ENONFINITE (-5)   /* a step produced a non-finite or zero norm / Gram term */
 #define SGEP_EUNSUPPORTED (-6) /* valid request the library does not implement */
 #define SGEP_EPOISONED (-7)    /* an earlier fault poisoned the handle */
+#define SGEP_ELABEL (-8)       /* an LDA step received a label outside [0, n_classes) */
 
 /* problem kinds */
 #define SGEP_KIND_CCA 0
@@ -96,8 +98,8 @@ typedef int32_t sgep_status;
 
 typedef struct sgep_config {
     int32_t kind;      /* SGEP_KIND_* */
-    int32_t dtype;     /* SGEP_F64, SGEP_F32 (CCA, GENERAL); SGEP_BF16 (CCA, LDA);
-                        * SGEP_FP8_E4M3 (CCA) */
+    int32_t dtype;     /* SGEP_F64 (CCA, GENERAL, ICA); SGEP_F32 (CCA, GENERAL, ICA,
+                        * LDA); SGEP_BF16 (CCA, LDA); SGEP_FP8_E4M3 (CCA) */
     int32_t k;         /* number of players, 1 <= k <= 64 (F64, and CCA in BF16 or
                         * FP8: k <= 32) */
     int32_t optimizer; /* SGEP_SGD or SGEP_ADAM */
@@ -105,7 +107,7 @@ typedef struct sgep_config {
     int32_t n_classes; /* LDA: 2 .. 16 classes; 0 otherwise */
     int64_t dx;        /* CCA: width of view x. GENERAL, LDA, ICA: d */
     int64_t dy;        /* CCA: width of view y. GENERAL: must equal dx. LDA, ICA: 0.
-                        * BF16 and FP8: dx and dy multiples of 8 */
+                        * BF16, FP8 and LDA: dx and dy multiples of 8 */
     int64_t b_max;     /* largest minibatch that sgep_step will receive */
     double eta0, eta_T, t0, t_c, T; /* schedule parameters (see above) */
     double gamma;      /* rate gamma_t (constant) of the auxiliary [Bv] update
@@ -187,8 +189,9 @@ sgep_status sgep_step(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
 
 /* LDA iteration: X is b x d row-major as in sgep_step, labels a device array
  * of b int32 class indices in [0, n_classes).  A label outside that range
- * poisons the handle (reported by the next synchronising call).  BF16 and
- * FP8 views: 16-byte aligned, ldx a multiple of 8 elements. */
+ * poisons the handle (SGEP_ELABEL from the next synchronising call; that
+ * iteration's result is unspecified).  X (BF16 or F32) must be 16-byte
+ * aligned with ldx a multiple of 8 elements. */
 sgep_status sgep_step_lda(sgep_handle *h, const void *X, int64_t ldx, const int32_t *labels,
                           int64_t b);
 
@@ -236,10 +239,19 @@ sgep_status sgep_sync(sgep_handle *h);
  * out: host, k doubles.  Synchronises. */
 sgep_status sgep_eigvals(sgep_handle *h, double *out);
 
-/* Current players.  b_normalized = 0: the unit vectors v_i (Alg. 2 output);
- * 1: v_i / sqrt(s_i), the estimate of the B-normalised eigenvector.
- * out: host, d x k column-major doubles.  Synchronises. */
-sgep_status sgep_vectors(sgep_handle *h, int32_t b_normalized, double *out);
+/* Flags of sgep_vectors. */
+#define SGEP_VEC_BNORM 1     /* v_i / sqrt(s_i), the estimate of the B-normalised
+                              * eigenvector, instead of the unit v_i */
+#define SGEP_VEC_CANONICAL 2 /* sign convention: each column negated if needed so
+                              * that its largest-magnitude component (lowest index
+                              * on ties) is positive (v and -v solve the same
+                              * problem, Sec. 2) */
+
+/* Current players (Alg. 2 output: the unit vectors v_i), with the read-out
+ * options of flags (0 or an OR of SGEP_VEC_*).  Without SGEP_VEC_CANONICAL
+ * the signs are those of the iterate.  out: host, d x k column-major doubles.
+ * Synchronises.  SGEP_EINVAL for unknown flag bits. */
+sgep_status sgep_vectors(sgep_handle *h, int32_t flags, double *out);
 
 /* The auxiliary variable [Bv] (host, d x k column-major).  Synchronises. */
 sgep_status sgep_auxiliary(sgep_handle *h, double *out);

@@ -29,6 +29,9 @@ SGEP_EDEVICE = -4
 SGEP_ENONFINITE = -5
 SGEP_EUNSUPPORTED = -6
 SGEP_EPOISONED = -7
+SGEP_ELABEL = -8
+
+SGEP_VEC_BNORM, SGEP_VEC_CANONICAL = 1, 2  # flags of sgep_vectors
 
 SGEP_KIND_CCA, SGEP_KIND_GENERAL, SGEP_KIND_LDA, SGEP_KIND_ICA = 0, 1, 2, 3
 SGEP_F64, SGEP_F32, SGEP_BF16, SGEP_FP8_E4M3 = 0, 1, 2, 3
@@ -273,9 +276,11 @@ def sgep_eigvals(h, k: int) -> np.ndarray:
     return out
 
 
-def sgep_vectors(h, d: int, k: int, b_normalized: int = 0) -> np.ndarray:
+def sgep_vectors(h, d: int, k: int, flags: int = 0) -> np.ndarray:
+    """Players as a (d, k) array; flags: an OR of SGEP_VEC_BNORM and
+    SGEP_VEC_CANONICAL."""
     out = np.zeros((k, d))
-    _check(load().sgep_vectors(h, int(b_normalized),
+    _check(load().sgep_vectors(h, int(flags),
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
            "sgep_vectors")
     return out.T.copy()
@@ -430,8 +435,8 @@ class Solver:
     def eigvals(self):
         return sgep_eigvals(self.h, self.k)
 
-    def vectors(self, b_normalized: int = 0):
-        return sgep_vectors(self.h, self.d, self.k, b_normalized)
+    def vectors(self, flags: int = 0):
+        return sgep_vectors(self.h, self.d, self.k, flags)
 
     def auxiliary(self):
         return sgep_auxiliary(self.h, self.d, self.k)
@@ -503,8 +508,8 @@ class BatchSolver:
     def instance(self, i):
         return sgep_batch_instance(self.bt, i)
 
-    def vectors(self, i, b_normalized: int = 0):
-        return sgep_vectors(self.instance(i), self.d[i], self.k, b_normalized)
+    def vectors(self, i, flags: int = 0):
+        return sgep_vectors(self.instance(i), self.d[i], self.k, flags)
 
     def auxiliary(self, i):
         return sgep_auxiliary(self.instance(i), self.d[i], self.k)

@@ -389,12 +389,12 @@ int narrow_kernels(const sgep_handle *h)
 }
 
 template <typename T, int KP>
-sgep_status launch_readout(sgep_handle *h, const void *S, int mode)
+sgep_status launch_readout(sgep_handle *h, const void *S, int mode, double *dst)
 {
     const int64_t dx = h->cfg.kind == SGEP_KIND_CCA ? h->cfg.dx : h->d;
     hipLaunchKernelGGL((sgep::k_readout<T, KP>), dim3(1), dim3(sgep::kNT), 0, h->stream,
                        (const T *)S, h->d, dx, h->dxp, h->ldv, h->cfg.k, h->stat_part, h->n_tiles,
-                       h->lds, h->cfg.rho, h->coef, mode, h->readout);
+                       h->lds, h->cfg.rho, h->coef, mode, dst);
     HIPCHK(hipGetLastError());
     return SGEP_OK;
 }
@@ -452,9 +452,10 @@ sgep_status wide_init_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *)
     return SGEP_OK;
 }
 
-// reduce the latest statistics, then scale the state rows into h->readout
+// reduce the latest statistics, then scale the state rows into dst
 template <int KP, int IN, int KIND>
-sgep_status wide_readout_t(sgep_handle *h, const WideArgs &a, const void *S, int mode)
+sgep_status wide_readout_t(sgep_handle *h, const WideArgs &a, const void *S, int mode,
+                           double *dst)
 {
     using namespace sgep::wide;
     hipLaunchKernelGGL(k_wstats, dim3(wide_stat_blocks(a)), dim3(kWT), 0, h->stream, a);
@@ -465,7 +466,7 @@ sgep_status wide_readout_t(sgep_handle *h, const WideArgs &a, const void *S, int
     const int64_t dx = h->cfg.kind == SGEP_KIND_CCA ? h->cfg.dx : h->d;
     hipLaunchKernelGGL((k_wreadout<KP>), dim3((unsigned)nb), dim3(256), 0, h->stream,
                        (const float *)S, (const double *)a.stot, h->d, dx, a.off[1], h->cfg.k,
-                       h->cfg.rho, h->coef, mode, h->readout);
+                       h->cfg.rho, h->coef, mode, dst);
     HIPCHK(hipGetLastError());
     return SGEP_OK;
 }
@@ -513,7 +514,11 @@ sgep_status latch_status(sgep_handle *h)
     HIPCHK(hipStreamSynchronize(h->stream));
     if (st != 0) {
         h->poisoned = true;
-        return (st & sgep::kStatusSync) ? SGEP_EDEVICE : SGEP_ENONFINITE;
+        if (st & sgep::kStatusSync)
+            return SGEP_EDEVICE;
+        if (st & sgep::wide::kStatusBadLabel)
+            return SGEP_ELABEL;
+        return SGEP_ENONFINITE;
     }
     return SGEP_OK;
 }
@@ -834,6 +839,7 @@ const char *sgep_status_string(sgep_status s)
     case SGEP_ENONFINITE: return "non-finite or zero norm / Gram term in a step";
     case SGEP_EUNSUPPORTED: return "not supported by the library";
     case SGEP_EPOISONED: return "handle poisoned by an earlier fault";
+    case SGEP_ELABEL: return "LDA label outside [0, n_classes) in a step";
     default: return "unknown status";
     }
 }
@@ -1207,7 +1213,11 @@ sgep_status sgep_eigvals(sgep_handle *h, double *out)
     return SGEP_OK;
 }
 
-static sgep_status readout(sgep_handle *h, const void *S, int mode, double *out)
+// The state rows S scaled per player (mode 0: as stored, 1: unit, 2:
+// B-normalised), staged as FP64 d x k column-major in dst (device), signs
+// canonicalised when canon is set, then copied to the host array out.
+static sgep_status readout(sgep_handle *h, const void *S, int mode, bool canon, double *dst,
+                           double *out)
 {
     if (!h || !out)
         return SGEP_EINVAL;
@@ -1217,29 +1227,35 @@ static sgep_status readout(sgep_handle *h, const void *S, int mode, double *out)
     if (rc != SGEP_OK)
         return rc;
     if (h->wide)
-        rc = WIDE_DISPATCH(h, wide_readout_t, h, h->wa, S, mode);
+        rc = WIDE_DISPATCH(h, wide_readout_t, h, h->wa, S, mode, dst);
     else
-        rc = SGEP_DISPATCH(h, launch_readout, h, S, mode);
+        rc = SGEP_DISPATCH(h, launch_readout, h, S, mode, dst);
     if (rc != SGEP_OK)
         return rc;
-    HIPCHK(hipMemcpyAsync(out, h->readout, (size_t)h->d * h->cfg.k * sizeof(double),
+    if (canon) {
+        hipLaunchKernelGGL(sgep::k_canon, dim3(h->cfg.k), dim3(sgep::kNT), 0, h->stream, dst,
+                           h->d);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(out, dst, (size_t)h->d * h->cfg.k * sizeof(double),
                           hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     return SGEP_OK;
 }
 
-sgep_status sgep_vectors(sgep_handle *h, int32_t b_normalized, double *out)
+sgep_status sgep_vectors(sgep_handle *h, int32_t flags, double *out)
 {
-    if (!h)
+    if (!h || (flags & ~(SGEP_VEC_BNORM | SGEP_VEC_CANONICAL)) != 0)
         return SGEP_EINVAL;
-    return readout(h, h->V, b_normalized ? 2 : 1, out);
+    return readout(h, h->V, (flags & SGEP_VEC_BNORM) ? 2 : 1, (flags & SGEP_VEC_CANONICAL) != 0,
+                   h->readout, out);
 }
 
 sgep_status sgep_auxiliary(sgep_handle *h, double *out)
 {
     if (!h)
         return SGEP_EINVAL;
-    return readout(h, h->G, 0, out);
+    return readout(h, h->G, 0, false, h->readout, out);
 }
 
 sgep_status sgep_means(sgep_handle *h, double *out)

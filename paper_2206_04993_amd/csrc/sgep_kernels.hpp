@@ -1748,4 +1748,42 @@ __global__ void __launch_bounds__(kNT) k_readout(const T *S, int64_t d, int64_t 
     }
 }
 
+// Sign convention of a read-out: column blockIdx.x of out (d x k,
+// column-major FP64) is negated when its largest-magnitude component (the
+// lowest index among equal magnitudes) is negative, so that component is
+// positive.  One workgroup per column: strided per-thread maxima, then a
+// fixed-order reduction in LDS.
+__global__ void __launch_bounds__(kNT) k_canon(double *out, int64_t d)
+{
+    __shared__ double bm[kNT];
+    __shared__ int64_t bi[kNT];
+    double *col = out + (int64_t)blockIdx.x * d;
+    double m = -1.0;
+    int64_t mi = 0;
+    for (int64_t f = threadIdx.x; f < d; f += kNT) {
+        const double a = fabs(col[f]);
+        if (a > m) { // strictly larger: the lowest index of this thread's ties
+            m = a;
+            mi = f;
+        }
+    }
+    bm[threadIdx.x] = m;
+    bi[threadIdx.x] = mi;
+    __syncthreads();
+    for (int h = kNT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            const double m2 = bm[threadIdx.x + h];
+            const int64_t i2 = bi[threadIdx.x + h];
+            if (m2 > bm[threadIdx.x] || (m2 == bm[threadIdx.x] && i2 < bi[threadIdx.x])) {
+                bm[threadIdx.x] = m2;
+                bi[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (col[bi[0]] < 0.0)
+        for (int64_t f = threadIdx.x; f < d; f += kNT)
+            col[f] = -col[f];
+}
+
 } // namespace sgep

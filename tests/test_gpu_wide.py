@@ -268,7 +268,7 @@ def test_wide_step_errors_and_bad_label():
     s.step(Xd, _i32_dev(bad))
     with pytest.raises(sg.SgepError) as e:
         s.sync()
-    assert e.value.status == sg.SGEP_ENONFINITE
+    assert e.value.status == sg.SGEP_ELABEL
     with pytest.raises(sg.SgepError) as e:
         s.step(Xd, _i32_dev(lab))
     assert e.value.status == sg.SGEP_EPOISONED
@@ -303,3 +303,43 @@ def test_wide_profiled_step_matches_plain():
         hip.hipEventDestroy(e)
     plain.close()
     timed.close()
+
+
+@pytest.mark.parametrize("path", ["narrow_f32_cca", "wide_bf16_lda", "wide_f32_lda"])
+def test_vectors_sign_convention(path):
+    """SGEP_VEC_CANONICAL: each column of the read-out is negated exactly when
+    its largest-magnitude component (lowest index on ties) is negative; with
+    and without B-normalisation; unknown flag bits are rejected."""
+    torch = _torch()
+    sg = _sg()
+    if path == "narrow_f32_cca":
+        gen = synth.CCAPlanted(40, 24, np.linspace(0.9, 0.3, 4), sigma=0.5, seed=3)
+        cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 6, 40, 24, 64, eta0=0.05, gamma=0.5)
+        s = sg.Solver(cfg, synth.initial_players(64, 6, 2))
+        for t in range(1, 4):
+            X, Y = gen.batch(t, 64)
+            s.step(torch.from_numpy(X.astype(np.float32)).cuda(),
+                   torch.from_numpy(Y.astype(np.float32)).cuda())
+    else:
+        fmt = "bf16" if path == "wide_bf16_lda" else "f32"
+        gen, priors = _lda_problem(136, 5, 12)
+        cfg = sg.make_config(sg.SGEP_KIND_LDA, sg.SGEP_BF16 if fmt == "bf16" else sg.SGEP_F32,
+                             12, 136, 0, 64, eta0=0.01, eps_reg=1e-3, n_classes=5)
+        s = sg.Solver(cfg, synth.initial_players(136, 12, 2), class_means=gen.means,
+                      class_priors=priors)
+        for t in range(1, 4):
+            X, lab = gen.batch(t, 64)
+            Xd = (_bf16_dev(synth.bf16_bits(X)) if fmt == "bf16"
+                  else torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda())
+            s.step(Xd, _i32_dev(lab))
+    for base in (0, sg.SGEP_VEC_BNORM):
+        V = s.vectors(base)
+        C = s.vectors(base | sg.SGEP_VEC_CANONICAL)
+        idx = np.argmax(np.abs(V), axis=0)
+        sign = np.sign(V[idx, np.arange(V.shape[1])])
+        assert np.array_equal(C, V * sign[None, :])
+        assert np.all(C[idx, np.arange(V.shape[1])] > 0)
+    with pytest.raises(sg.SgepError) as e:
+        s.vectors(4)
+    assert e.value.status == sg.SGEP_EINVAL
+    s.close()
