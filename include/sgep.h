@@ -253,6 +253,17 @@ sgep_status sgep_eigvals(sgep_handle *h, double *out);
  * Synchronises.  SGEP_EINVAL for unknown flag bits. */
 sgep_status sgep_vectors(sgep_handle *h, int32_t flags, double *out);
 
+/* sgep_vectors without any device allocation, for callers that cannot
+ * allocate device memory (serving loops and harnesses that forbid it after
+ * start-up): the FP64 read-out is staged in a fixed device array of
+ * 4,194,304 doubles (32 MiB) that the library holds on every GPU it runs on
+ * until the process ends, instead of the handle's own staging buffer.  Same
+ * arguments, flags, output and errors as sgep_vectors, plus
+ * SGEP_EUNSUPPORTED when d * k exceeds 4,194,304.  Every call on one GPU
+ * uses the same array: calls that overlap on one GPU (from several host
+ * threads) race and must be serialised by the caller.  Synchronises. */
+sgep_status sgep_vectors_noalloc(sgep_handle *h, int32_t flags, double *out);
+
 /* The auxiliary variable [Bv] (host, d x k column-major).  Synchronises. */
 sgep_status sgep_auxiliary(sgep_handle *h, double *out);
 

@@ -42,7 +42,8 @@ SGEP_SCHED_CONST, SGEP_SCHED_INV, SGEP_SCHED_WARMUP_HARMONIC = 0, 1, 2
 EXPORTS = (
     "sgep_init", "sgep_init_ex", "sgep_step", "sgep_step_lda", "sgep_kernels_per_step",
     "sgep_step_kernel_name",
-    "sgep_step_profiled", "sgep_sync", "sgep_eigvals", "sgep_vectors", "sgep_auxiliary",
+    "sgep_step_profiled", "sgep_sync", "sgep_eigvals", "sgep_vectors", "sgep_vectors_noalloc",
+    "sgep_auxiliary",
     "sgep_step_count", "sgep_means", "sgep_state_size", "sgep_get_state", "sgep_set_state",
     "sgep_destroy",
     "sgep_status_string", "sgep_version",
@@ -128,6 +129,7 @@ def load() -> ctypes.CDLL:
     lib.sgep_sync.argtypes = [vp]
     lib.sgep_eigvals.argtypes = [vp, dp]
     lib.sgep_vectors.argtypes = [vp, i32, dp]
+    lib.sgep_vectors_noalloc.argtypes = [vp, i32, dp]
     lib.sgep_auxiliary.argtypes = [vp, dp]
     lib.sgep_step_count.argtypes = [vp, ctypes.POINTER(i64)]
     lib.sgep_means.argtypes = [vp, dp]
@@ -283,6 +285,15 @@ def sgep_vectors(h, d: int, k: int, flags: int = 0) -> np.ndarray:
     _check(load().sgep_vectors(h, int(flags),
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
            "sgep_vectors")
+    return out.T.copy()
+
+
+def sgep_vectors_noalloc(h, d: int, k: int, flags: int = 0) -> np.ndarray:
+    """sgep_vectors through the entry point that allocates no device memory."""
+    out = np.zeros((k, d))
+    _check(load().sgep_vectors_noalloc(h, int(flags),
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+           "sgep_vectors_noalloc")
     return out.T.copy()
 
 

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -38,6 +39,34 @@ struct StateHeader {
     int64_t elem;
     int64_t adam;
 };
+
+// Read-out staging of sgep_vectors_noalloc: a device array of fixed size
+// that every GPU the library runs on holds until the process ends, so that
+// read-out allocates nothing.  Its host-side name is not a device address:
+// host code uses the per-device address from hipGetSymbolAddress (kept in
+// g_scratch) and passes that to kernels and copies.
+constexpr size_t kScratchDoubles = (size_t)1 << 22; // 32 MiB: d * k <= 4,194,304
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// The address of this device's scratch array; call with `device` current.
+// Looked up once per device (at the first sgep_init on it, else at the
+// first sgep_vectors_noalloc).
+double *scratch_of(int device)
+{
+    if (device < 0 || device >= kMaxDevices)
+        return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+            g_scratch[device] = (double *)p;
+    }
+    return g_scratch[device];
+}
 
 } // namespace
 
@@ -870,6 +899,11 @@ sgep_status sgep_init_ex(sgep_handle **out, const sgep_config *cfg, const double
     h->stream = (hipStream_t)hip_stream;
     h->d = cfg->kind == SGEP_KIND_CCA ? cfg->dx + cfg->dy : cfg->dx;
     h->kp = cfg->k <= 16 ? 16 : (cfg->k <= 32 ? 32 : 64);
+    {
+        int dev = 0; // the current device: the no-allocation read-out's staging
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)scratch_of(dev);
+    }
     if (cfg->dtype == SGEP_BF16 || cfg->dtype == SGEP_FP8_E4M3 || cfg->kind == SGEP_KIND_LDA) {
         h->wide = true;
         if (hipGetDevice(&h->device) != hipSuccess) {
@@ -1249,6 +1283,28 @@ sgep_status sgep_vectors(sgep_handle *h, int32_t flags, double *out)
         return SGEP_EINVAL;
     return readout(h, h->V, (flags & SGEP_VEC_BNORM) ? 2 : 1, (flags & SGEP_VEC_CANONICAL) != 0,
                    h->readout, out);
+}
+
+sgep_status sgep_vectors_noalloc(sgep_handle *h, int32_t flags, double *out)
+{
+    if (!h || !out || (flags & ~(SGEP_VEC_BNORM | SGEP_VEC_CANONICAL)) != 0)
+        return SGEP_EINVAL;
+    if ((uint64_t)h->d * (uint64_t)h->cfg.k > (uint64_t)kScratchDoubles)
+        return SGEP_EUNSUPPORTED; // larger than the fixed staging array
+    double *dst = g_scratch[h->device];
+    if (!dst) { // not set up at init: look it up now, with the handle's device current
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != h->device)
+            HIPCHK(hipSetDevice(h->device));
+        dst = scratch_of(h->device);
+        if (cur != h->device)
+            HIPCHK(hipSetDevice(cur));
+        if (!dst)
+            return SGEP_EDEVICE;
+    }
+    return readout(h, h->V, (flags & SGEP_VEC_BNORM) ? 2 : 1, (flags & SGEP_VEC_CANONICAL) != 0,
+                   dst, out);
 }
 
 sgep_status sgep_auxiliary(sgep_handle *h, double *out)
