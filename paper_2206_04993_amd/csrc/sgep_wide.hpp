@@ -234,7 +234,14 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
     const int r16 = lane & 15, g = lane >> 4;
+    // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so
+    // XCD x runs blockIdx x, x + 8, ...; give it a contiguous range of
+    // (slice, view) pairs with all their row blocks, so the V operand of
+    // those feature slices stays in that XCD's L2 instead of every XCD
+    // reading all of V
     int blk = blockIdx.x;
+    if (nfwd % 8 == 0 && (a.nview * a.n_split) % 8 == 0)
+        blk = (blk % 8) * (nfwd / 8) + blk / 8;
     const int rb = blk % a.n_rb;
     blk /= a.n_rb;
     const int v = blk % a.nview;

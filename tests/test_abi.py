@@ -90,7 +90,8 @@ def test_config_validation_is_synchronous():
         (mk(C, sg.SGEP_BF16, 4, 12, 8, 16), sg.SGEP_ESHAPE),         # BF16 widths: multiples of 8
         (mk(C, sg.SGEP_FP8_E4M3, 4, 8, 8, 16), sg.SGEP_EINVAL),      # FP8 needs column scales
         (mk(C, 4, 4, 8, 8, 16), sg.SGEP_EINVAL),                     # unknown dtype
-        (mk(L, sg.SGEP_F32, 4, 8, 0, 16, n_classes=3), sg.SGEP_EUNSUPPORTED),  # LDA: BF16 only
+        (mk(L, sg.SGEP_F64, 4, 8, 0, 16, n_classes=3), sg.SGEP_EUNSUPPORTED),  # LDA: BF16, F32
+        (mk(L, sg.SGEP_F32, 4, 12, 0, 16, n_classes=3), sg.SGEP_ESHAPE),  # LDA: d multiple of 8
         (mk(L, sg.SGEP_FP8_E4M3, 4, 8, 0, 16, n_classes=3), sg.SGEP_EUNSUPPORTED),
         (mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=1), sg.SGEP_EINVAL),   # >= 2 classes
         (mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=17), sg.SGEP_EINVAL),  # <= 16 classes
