@@ -152,6 +152,7 @@ KERNEL_HEADER = {"k_fwd": "sgep_kernels.hpp", "k_fwds": "sgep_kernels.hpp",
                  "k_bwd1": "sgep_kernels.hpp", "k_fwd2": "sgep_kernels.hpp",
                  "k_coefa": "sgep_kernels.hpp", "k_coefb": "sgep_kernels.hpp",
                  "k_wfwd": "sgep_wide.hpp", "k_wmid": "sgep_wide.hpp", "k_wbwd": "sgep_wide.hpp",
+                 "k_wprod": "sgep_wide.hpp", "k_wepi": "sgep_wide.hpp",
                  "k_bfwd": ("sgep_kernels.hpp", "sgep_batch.hpp"),
                  "k_bcoef": ("sgep_kernels.hpp", "sgep_batch.hpp"),
                  "k_bbwd": ("sgep_kernels.hpp", "sgep_batch.hpp")}
@@ -324,6 +325,10 @@ def algorithmic_work(w, kernel, names=()):
     if kernel == "k_wmid":
         return 0.0, float(4 * b * k * (1 if lda else 2) + 4 * b * mw)
     extra = (4 * c * d + 4 * d) if lda else 0                   # class means, their mean
+    if kernel == "k_wprod":  # X^T W of the split backward: products to memory
+        return 2.0 * b * d * mp, float(data + 4 * b * mw + 4 * d * mp)
+    if kernel == "k_wepi":   # its epilogue: products in, state, next V operand out
+        return 0.0, float(4 * d * mp + state + 4 * d * k + extra)
     return 2.0 * b * d * mp, float(data + 4 * b * mw + state + 4 * d * k + extra)
 
 

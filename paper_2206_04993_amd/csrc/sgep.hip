@@ -111,6 +111,7 @@ struct sgep_handle_s {
     void *Vh = nullptr, *Vl = nullptr, *colscale = nullptr, *Ppart = nullptr;
     void *Wh = nullptr, *Wl = nullptr, *Mcls = nullptr, *Mbar = nullptr, *prior = nullptr;
     void *Vf = nullptr, *Wf = nullptr; // FP32 input: V operand and W rows
+    void *prod = nullptr, *ctile = nullptr; // split backward: products, coefficient tile
 };
 
 namespace {
@@ -152,7 +153,7 @@ void free_all(sgep_handle *h)
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
                     h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
                     h->mu,   h->S1, h->S2,     h->bb_part, h->gsum, h->fpart,
-                    h->xw, h->cflag, h->Vf, h->Wf};
+                    h->xw, h->cflag, h->Vf, h->Wf, h->prod, h->ctile};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -301,6 +302,9 @@ void launch_bwd(sgep_handle *h, const StepArgs &a, hipEvent_t e0, hipEvent_t e1)
 }
 
 int narrow_kernels(const sgep_handle *h);
+// kernels of one iteration of a large-d handle: forward, middle pass and the
+// backward in one kernel, or split into products and epilogue
+int wide_kernels(const sgep_handle *h) { return h->wa.ft == sgep::wide::kFT ? 3 : 4; }
 
 // one iteration; C: the views are centred by their running means
 template <typename T, int KP, bool C>
@@ -464,10 +468,22 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
     }
     launch_k(k_wmid<KP, IN, KIND>, dim3(a.nA), blk, h->stream, ev[2], ev[3], a);
     const dim3 bblk(kBT);
-    if (adam)
+    constexpr bool can128 = IN != kInF32; // 128-feature subtiles: BF16 / FP8 only
+    if (can128 && a.ft == 2 * kFT) {
+        if constexpr (can128) { // products, then the epilogue per 64-feature tile
+            launch_k(k_wprod<KP, IN, KIND>, dim3(a.nwg), bblk, h->stream, ev[4], ev[5], a);
+            if (adam)
+                launch_k(k_wepi<KP, IN, KIND, sgep::kOptAdam>, dim3(a.nstat), bblk, h->stream,
+                         ev[6], ev[7], a);
+            else
+                launch_k(k_wepi<KP, IN, KIND, sgep::kOptSGD>, dim3(a.nstat), bblk, h->stream,
+                         ev[6], ev[7], a);
+        }
+    } else if (adam) {
         launch_k(k_wbwd<KP, IN, KIND, sgep::kOptAdam>, dim3(a.nwg), bblk, h->stream, ev[4], ev[5], a);
-    else
+    } else {
         launch_k(k_wbwd<KP, IN, KIND, sgep::kOptSGD>, dim3(a.nwg), bblk, h->stream, ev[4], ev[5], a);
+    }
     HIPCHK(hipGetLastError());
     return SGEP_OK;
 }
@@ -592,9 +608,16 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     const bool lda = c.kind == SGEP_KIND_LDA, fp8 = c.dtype == SGEP_FP8_E4M3;
     const bool f32 = c.dtype == SGEP_F32;
     const int64_t KP = h->kp, d = h->d;
-    auto r64 = [](int64_t x) { return (x + 63) / 64 * 64; };
     WideArgs &a = h->wa;
     memset(&a, 0, sizeof(a));
+    // backward subtiles of 128 features where the views keep >= 256 of them
+    // (one per workgroup): fewer W loads per byte of X; else 64
+    {
+        const int64_t n128 = (c.dx + 127) / 128 + (lda ? 0 : (c.dy + 127) / 128);
+        a.ft = (!f32 && n128 >= 256) ? 2 * kFT : kFT;
+    }
+    const int64_t ft = a.ft;
+    auto r64 = [ft](int64_t x) { return (x + ft - 1) / ft * ft; }; // views padded to subtiles
     h->esz = fp8 ? 1 : (f32 ? 4 : 2); // element size of the minibatch (checkpoint header)
     a.nview = lda ? 1 : 2;
     a.dv[0] = c.dx;
@@ -624,14 +647,18 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.fw = 64 * ((nf64 + kNW * ns - 1) / (kNW * ns));
     a.fs = kNW * a.fw;
     a.n_split = (int32_t)((dvmax + a.fs - 1) / a.fs);
-    // backward: 64-feature subtiles, about 256 workgroups
-    a.nsubv[0] = (int32_t)((a.dv[0] + kFT - 1) / kFT);
-    a.nsubv[1] = (int32_t)((a.dv[1] + kFT - 1) / kFT);
+    // backward: subtiles of ft features, about 256 workgroups (64-feature
+    // subtiles) or one 128-feature subtile per workgroup
+    a.nsubv[0] = (int32_t)((a.dv[0] + ft - 1) / ft);
+    a.nsubv[1] = (int32_t)((a.dv[1] + ft - 1) / ft);
     const int nsubt = a.nsubv[0] + a.nsubv[1];
-    a.nsub = nsubt / 256 > 1 ? nsubt / 256 : 1;
+    a.nsub = (ft == kFT && nsubt / 256 > 1) ? nsubt / 256 : 1;
     a.nwg0 = (a.nsubv[0] + a.nsub - 1) / a.nsub;
     a.nwg = a.nwg0 + (a.nsubv[1] + a.nsub - 1) / a.nsub;
-    a.lds = (a.nwg + 1) / 2 * 2;
+    // statistics partials: one column per backward workgroup, or per epilogue
+    // workgroup (64-feature tile) of the split backward
+    a.nstat = ft == kFT ? a.nwg : (int32_t)(nsubt * (ft / kFT));
+    a.lds = (a.nstat + 1) / 2 * 2;
     a.Ws = (int32_t)(KP * (KP + 1) / 2 + KP + (lda ? a.ncls * KP : 0));
     const int64_t MW = lda ? KP + 16 : 2 * KP;
 
@@ -667,6 +694,11 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
         alloc(&h->Wh, wbytes);
         alloc(&h->Wl, wbytes);
     }
+    if (ft != kFT) {
+        const int64_t mwa = lda ? KP : 2 * KP; // rows of W in the products
+        alloc(&h->prod, (size_t)a.dtot * mwa * sizeof(float));
+        alloc(&h->ctile, (size_t)(KP * KP + 4 * KP + 2 * kMaxCls * KP) * sizeof(float));
+    }
     if (lda) {
         alloc(&h->Mcls, (size_t)a.ncls * a.dtot * sizeof(float));
         alloc(&h->Mbar, (size_t)a.dtot * sizeof(float));
@@ -690,6 +722,8 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.Wh = (uint16_t *)h->Wh;
     a.Wl = (uint16_t *)h->Wl;
     a.Wf = (float *)h->Wf;
+    a.prod = (float *)h->prod;
+    a.ctile = (float *)h->ctile;
     a.M = (const float *)h->Mcls;
     a.Mbar = (const float *)h->Mbar;
     a.prior = (const double *)h->prior;
@@ -803,9 +837,9 @@ sgep_status step_wide(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
     a.b = b;
     a.n_rb = (int32_t)((b + a.rbf - 1) / a.rbf);
     a.nA = 4 * (int32_t)((b + sgep::wide::kRB - 1) / sgep::wide::kRB);
-    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (events)
-        for (int i = 0; i < 6; ++i)
+        for (int i = 0; i < 2 * wide_kernels(h); ++i)
             ev[i] = (hipEvent_t)events[i];
     return WIDE_DISPATCH(h, wide_step_t, h, a, ev);
 }
@@ -1175,7 +1209,7 @@ sgep_status sgep_kernels_per_step(const sgep_handle *h, int32_t *n)
 {
     if (!h || !n)
         return SGEP_EINVAL;
-    *n = h->wide ? 3 : narrow_kernels(h);
+    *n = h->wide ? wide_kernels(h) : narrow_kernels(h);
     return SGEP_OK;
 }
 
@@ -1184,14 +1218,18 @@ const char *sgep_step_kernel_name(const sgep_handle *h, int32_t i)
     if (!h || i < 0)
         return nullptr;
     static const char *wide[] = {"k_wfwd", "k_wmid", "k_wbwd"};
+    static const char *wide4[] = {"k_wfwd", "k_wmid", "k_wprod", "k_wepi"};
     static const char *spec[] = {"k_fwd", "k_bwd"};
     static const char *pre[] = {"k_fwd", "k_coef", "k_bwd"};
     static const char *split[] = {"k_fwds", "k_bwdp", "k_bwd"};
     static const char *fused[] = {"k_fwds", "k_bwdp"};
     static const char *ica[] = {"k_fwd", "k_bwd1", "k_fwd2", "k_bwd"};
     static const char *pre2[] = {"k_fwd", "k_coefa", "k_coefb", "k_bwd"};
-    if (h->wide)
+    if (h->wide) {
+        if (h->wa.ft != sgep::wide::kFT)
+            return i < 4 ? wide4[i] : nullptr;
         return i < 3 ? wide[i] : nullptr;
+    }
     const int n = narrow_kernels(h);
     if (i >= n)
         return nullptr;
@@ -1210,7 +1248,7 @@ sgep_status sgep_step_profiled(sgep_handle *h, const void *X, int64_t ldx, const
 {
     if (!h || !events)
         return SGEP_EINVAL;
-    const int32_t need = 2 * (h->wide ? 3 : narrow_kernels(h));
+    const int32_t need = 2 * (h->wide ? wide_kernels(h) : narrow_kernels(h));
     if (n_events != need)
         return SGEP_EINVAL;
     for (int i = 0; i < need; ++i)

@@ -93,6 +93,11 @@ struct WideArgs {
     // each covers nsub consecutive subtiles of its view (nsubv[v] subtiles in all)
     int32_t nwg0, nwg, nsub;
     int32_t nsubv[2];
+    int32_t ft;                 // features per backward subtile: 64 (one kernel) or 128
+                                // (products k_wprod, then the epilogue k_wepi per 64)
+    int32_t nstat;              // columns of the statistics partials (writing workgroups)
+    float *prod;                // ft = 128: X^T W per state row, [dtot][rows of W in X^T W]
+    float *ctile;               // ft = 128: the iteration's coefficient tile (k_wprod -> k_wepi)
     float *V, *G, *Am, *As;     // dtot x KP, feature-major
     uint16_t *Vh, *Vl;          // KP x dtot, player-major BF16 hi / lo of s_f V
     float *Vf;                  // FP32 input: KP x dtot, player-major copy of V
@@ -201,7 +206,7 @@ __device__ inline void reduce_stats(const WideArgs &a, int qb)
         if (e >= a.Ws)
             break;
         double s = 0.0;
-        for (int j = lane; j < a.nwg; j += 64)
+        for (int j = lane; j < a.nstat; j += 64)
             s += a.spart[(int64_t)e * a.lds + j];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1)
@@ -621,10 +626,11 @@ __device__ __forceinline__ void wg_range(const WideArgs &a, int wg, int &v, int 
     sub1 = sub0 + a.nsub < a.nsubv[v] ? sub0 + a.nsub : a.nsubv[v];
 }
 
-// One 32-row chunk of the backward stream held in registers: X (8 rows x 4
-// features per lane, raw), the W tiles (hi, lo), and the one-hot tile (LDA).
-template <int NU> struct BwdChunk {
-    u32x2 x[8];
+// One 32-row chunk of the backward stream held in registers: X (8 rows x NCF
+// features per lane, raw: XD dwords per row), the W tiles (hi, lo), and the
+// one-hot tile (LDA).
+template <int NU, int XD> struct BwdChunk {
+    uint32_t x[8][XD];
     u32x4 wh[NU], wl[NU];
     u32x4 lh;
 };
@@ -639,16 +645,27 @@ template <int NU> struct BwdChunk32 {
 
 // ---------------------------------------------------------------------------
 // Backward products, coefficients and fused epilogue.
-// Main loop over 32-row chunks (wave w takes chunks w, w + 8, ...): lane l
+// A workgroup takes subtiles of FT features (64, or 128 where the view is
+// wide enough to keep >= 256 workgroups: fewer W loads per X byte).
+// Main loop over 32-row chunks (wave w takes chunks w, w + 4, ...): lane l
 // (n = l % 16, g = l / 16) loads rows 8 g .. 8 g + 7 of the chunk at features
-// 4 n .. 4 n + 3 of the subtile and transposes them in registers, so MFMA c
-// (c < 4) gets the B operand B[8 g + j][n] = X[row 8 g + j][feature 4 n + c];
+// NCF n .. NCF n + NCF - 1 of the subtile (NCF = FT / 16; one 16-byte load per
+// row for BF16 at FT = 128) and transposes them in registers, so MFMA c
+// (c < NCF) gets the B operand B[8 g + j][n] = X[row 8 g + j][feature NCF n + c];
 // the A operand is a 16-row tile of W, lane l holding W[l % 16][rows 8 g ..
-// 8 g + 7] in one 16-byte load.  D[m][n] is then (X^T W^T)[4 n + c][m].
+// 8 g + 7] in one 16-byte load.  D[m][n] is then (X^T W^T)[NCF n + c][m].
+// With PART (k_wprod, 128-feature subtiles, one per workgroup) the summed
+// products go to memory instead of an epilogue, and workgroup 0 alone forms
+// the Gram terms and the coefficients, publishing them as the coefficient
+// tile; k_wepi then runs the epilogue per 64-feature tile.
 // ---------------------------------------------------------------------------
-template <int KP, int IN, int KIND, int OPT>
-__global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
+template <int KP, int IN, int KIND, int OPT, int FT = kFT, bool PART = false>
+__device__ __forceinline__ void wbwd_body(WideArgs a)
 {
+    static_assert(FT == kFT || (FT == 2 * kFT && IN != kInF32 && PART), "backward subtile");
+    constexpr int NCF = FT / 16;  // features per lane
+    constexpr int NH = FT / kFT;  // 64-feature halves of a subtile
+    constexpr int XD = NCF * (IN == kInBF16 ? 2 : 1) / 4; // dwords of X per lane and row
     typedef Shape<KP, KIND> S;
     constexpr int NT = S::NT, NU = S::NU, MWP = S::MWP, SLOT = S::SLOT, TRI = S::TRI;
     constexpr int GLD = S::GLD, VLD = S::VLD, NG = S::NG;
@@ -696,11 +713,11 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
     double nrm = 0.0;
 
     for (int sub = sub0; sub < sub1; ++sub) {
-        const bool first = sub == sub0;
-        const int64_t fv0 = (int64_t)sub * kFT;
-        f32x4 acc[4][NU];
+        const bool first = PART ? wg == 0 : sub == sub0; // forms the Gram terms
+        const int64_t fv0 = (int64_t)sub * FT;
+        f32x4 acc[NCF][NU];
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < NCF; ++c)
 #pragma unroll
             for (int u = 0; u < NU; ++u)
                 acc[c][u] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -718,9 +735,9 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
         // feature unit past the view the last unit); invalid X is zeroed where
         // it is consumed and an invalid chunk is skipped (wave-uniform), so the
         // ring of chunks stays in flight.
-        const int64_t fu = fv0 + 4 * l16;
+        const int64_t fu = fv0 + NCF * l16;
         const bool fok = fu < dv;
-        const uint8_t *xc = Xb + (fok ? fu : dv - 4) * ES;
+        const uint8_t *xc = Xb + (fok ? fu : dv - NCF) * ES;
 
         if constexpr (IN == kInF32) {
             auto loadc = [&](int ch, BwdChunk32<NU> &B) {
@@ -736,7 +753,7 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                     B.w[u][0] = *reinterpret_cast<const f32x4 *>(q);
                     B.w[u][1] = *reinterpret_cast<const f32x4 *>(q + 4);
                 }
-                if (LDA) {
+                if (LDA && first) { // the one-hot rows only feed the Gram terms
                     const float *q = Wf + (int64_t)KP * a.ldr + r0;
                     B.l[0] = *reinterpret_cast<const f32x4 *>(q);
                     B.l[1] = *reinterpret_cast<const f32x4 *>(q + 4);
@@ -803,15 +820,21 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                 }
             }
         } else {
-            auto loadc = [&](int ch, BwdChunk<NU> &B) {
+            auto loadc = [&](int ch, BwdChunk<NU, XD> &B) {
                 const int64_t r0 = (int64_t)(ch < nch ? ch : nch - 1) * 32;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int64_t row = r0 + 8 * g + j < a.b ? r0 + 8 * g + j : a.b - 1;
-                    if (IN == kInBF16)
-                        B.x[j] = *reinterpret_cast<const u32x2 *>(xc + row * ld * 2);
-                    else
-                        B.x[j] = u32x2{*reinterpret_cast<const uint32_t *>(xc + row * ld), 0u};
+                    const uint8_t *px = xc + row * ld * ES;
+                    if constexpr (XD == 4) {
+                        const u32x4 q = *reinterpret_cast<const u32x4 *>(px);
+                        B.x[j][0] = q[0]; B.x[j][1] = q[1]; B.x[j][2] = q[2]; B.x[j][3] = q[3];
+                    } else if constexpr (XD == 2) {
+                        const u32x2 q = *reinterpret_cast<const u32x2 *>(px);
+                        B.x[j][0] = q[0]; B.x[j][1] = q[1];
+                    } else {
+                        B.x[j][0] = *reinterpret_cast<const uint32_t *>(px);
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
@@ -819,42 +842,50 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
                     B.wh[u] = *reinterpret_cast<const u32x4 *>(Wh + wo);
                     B.wl[u] = *reinterpret_cast<const u32x4 *>(Wl + wo);
                 }
-                if (LDA)
+                if (LDA && first) // the one-hot rows only feed the Gram terms
                     B.lh = *reinterpret_cast<const u32x4 *>(Wh + (int64_t)KP * a.ldr + r0);
             };
-            auto compute = [&](int ch, const BwdChunk<NU> &B) {
+            auto compute = [&](int ch, const BwdChunk<NU, XD> &B) {
                 if (ch >= nch)
                     return; // wave-uniform
                 const int64_t r0 = (int64_t)ch * 32;
-                uint32_t d0[8], d1[8];
+                // feature pairs p: column c = 2 p, 2 p + 1 of the transposed chunk;
+                // row j's BF16 pair is dword p of the row (FP8 codes decode exactly)
+                bool rvalid[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    if (IN == kInBF16) {
-                        d0[j] = B.x[j][0];
-                        d1[j] = B.x[j][1];
-                    } else {
-                        fp8x4_to_bf16(B.x[j][0], d0[j], d1[j]);
+                for (int j = 0; j < 8; ++j)
+                    rvalid[j] = fok && r0 + 8 * g + j < a.b;
+#pragma unroll
+                for (int p = 0; p < NCF / 2; ++p) {
+                    uint32_t col[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        uint32_t x;
+                        if (IN == kInBF16) {
+                            x = B.x[j][p];
+                        } else {
+                            uint32_t e0, e1;
+                            fp8x4_to_bf16(B.x[j][p >> 1], e0, e1);
+                            x = (p & 1) ? e1 : e0;
+                        }
+                        col[j] = rvalid[j] ? x : 0u;
                     }
-                    if (!(fok && r0 + 8 * g + j < a.b))
-                        d0[j] = d1[j] = 0u;
-                }
-                u32x4 bx[4];
+                    // B operands: the BF16 of rows 2q, 2q + 1 in dword q
+                    u32x4 b0, b1;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const uint32_t a0 = d0[2 * q], a1 = d0[2 * q + 1];
-                    const uint32_t b0 = d1[2 * q], b1 = d1[2 * q + 1];
-                    bx[0][q] = (a0 & 0xFFFFu) | (a1 << 16);
-                    bx[1][q] = (a0 >> 16) | (a1 & 0xFFFF0000u);
-                    bx[2][q] = (b0 & 0xFFFFu) | (b1 << 16);
-                    bx[3][q] = (b0 >> 16) | (b1 & 0xFFFF0000u);
-                }
-#pragma unroll
-                for (int c = 0; c < 4; ++c)
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t a0 = col[2 * q], a1 = col[2 * q + 1];
+                        b0[q] = (a0 & 0xFFFFu) | (a1 << 16);
+                        b1[q] = (a0 >> 16) | (a1 & 0xFFFF0000u);
+                    }
 #pragma unroll
                     for (int u = 0; u < NU; ++u) {
-                        acc[c][u] = mfma_bf16(B.wh[u], bx[c], acc[c][u]);
-                        acc[c][u] = mfma_bf16(B.wl[u], bx[c], acc[c][u]);
+                        acc[2 * p][u] = mfma_bf16(B.wh[u], b0, acc[2 * p][u]);
+                        acc[2 * p][u] = mfma_bf16(B.wl[u], b0, acc[2 * p][u]);
+                        acc[2 * p + 1][u] = mfma_bf16(B.wh[u], b1, acc[2 * p + 1][u]);
+                        acc[2 * p + 1][u] = mfma_bf16(B.wl[u], b1, acc[2 * p + 1][u]);
                     }
+                }
                 if (first) {
                     // Gram terms from the W fragments: lane (m, g) holds rows 8g..8g+7 of
                     // W row m, which is both the A layout (A[m][k]) and the B layout
@@ -894,8 +925,8 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
             };
             // ring of NB chunks in flight: the loads of chunk i + NB - 1 are issued
             // before the MFMAs of chunk i (wave w takes chunks w, w + kBW, ...)
-            constexpr int NB = 3;
-            BwdChunk<NU> cb[NB];
+            constexpr int NB = FT == kFT ? 3 : 2; // 128-feature chunks hold twice the X
+            BwdChunk<NU, XD> cb[NB];
 #pragma unroll
             for (int p = 0; p < NB - 1; ++p)
                 loadc(w + kBW * p, cb[p]);
@@ -909,279 +940,569 @@ __global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
             }
         }
 
-        // the old auxiliary tile of this subtile, into registers now (written
-        // to LDS once the products and Gram terms no longer need the space)
-        const int64_t frow = a.off[v] + fv0; // state row of the subtile's first feature
-        constexpr int GPT = kFT * KP / kBT;
-        float gpre[GPT];
+        for (int hh = 0; hh < NH; ++hh) { // 64-feature halves
+            // the old auxiliary tile of this subtile, into registers now (written
+            // to LDS once the products and Gram terms no longer need the space)
+            const int64_t fvh = fv0 + (int64_t)kFT * hh; // the half's first feature
+            const int64_t frow = a.off[v] + fvh;          // and its state row
+            constexpr int GPT = kFT * KP / kBT;
+            float gpre[GPT];
+            if constexpr (!PART) {
 #pragma unroll
-        for (int q = 0; q < GPT; ++q)
-            gpre[q] = a.G[frow * KP + tid + q * kBT];
-        // ---- products: four waves -> prod = slot 0, element (feature, m) ----
+                for (int q = 0; q < GPT; ++q)
+                    gpre[q] = a.G[frow * KP + tid + q * kBT];
+            }
+            if constexpr (PART) {
+                // ---- products of the whole subtile: waves 0, 1 write slots A, B
+                // (FT features each), waves 2, 3 add theirs, A + B to memory ----
+                float *slot = red + (w & 1) * 2 * SLOT;
+                if (w < 2) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+                    for (int c = 0; c < NCF; ++c)
 #pragma unroll
-            for (int u = 0; u < NU; ++u)
-                *reinterpret_cast<f32x4 *>(&red[w * SLOT + (4 * l16 + c) * MWP + 16 * u + 4 * g]) = acc[c][u];
-        __syncthreads();
-        for (int e = tid; e < kFT * S::MWA; e += kBT) {
-            const int idx = (e / S::MWA) * MWP + e % S::MWA;
-            red[idx] = ((red[idx] + red[SLOT + idx]) + red[2 * SLOT + idx]) + red[3 * SLOT + idx];
-        }
-        __syncthreads();
-        float *ext = red + SLOT; // three free slots from here on
+                        for (int u = 0; u < NU; ++u)
+                            *reinterpret_cast<f32x4 *>(&slot[(NCF * l16 + c) * MWP + 16 * u + 4 * g]) =
+                                acc[c][u];
+                }
+                __syncthreads();
+                if (w >= 2) {
+#pragma unroll
+                    for (int c = 0; c < NCF; ++c)
+#pragma unroll
+                        for (int u = 0; u < NU; ++u) {
+                            f32x4 *q = reinterpret_cast<f32x4 *>(
+                                &slot[(NCF * l16 + c) * MWP + 16 * u + 4 * g]);
+                            *q = *q + acc[c][u];
+                        }
+                }
+                __syncthreads();
+                float *out = a.prod + (a.off[v] + fv0) * S::MWA;
+                for (int e = tid; e < FT * S::MWA; e += kBT) {
+                    const int idx = (e / S::MWA) * MWP + e % S::MWA;
+                    out[e] = red[idx] + red[2 * SLOT + idx];
+                }
+                if (!first)
+                    return;
+                __syncthreads();
+            } else {
+                // ---- products: four waves -> prod = slot 0, element (feature, m); the
+                // lanes holding this half's features write ----
+                if ((NCF * l16) / kFT == hh) {
+                    const int fl0 = NCF * l16 - kFT * hh;
+#pragma unroll
+                    for (int c = 0; c < NCF; ++c)
+#pragma unroll
+                        for (int u = 0; u < NU; ++u)
+                            *reinterpret_cast<f32x4 *>(
+                                &red[w * SLOT + (fl0 + c) * MWP + 16 * u + 4 * g]) = acc[c][u];
+                }
+                __syncthreads();
+                for (int e = tid; e < kFT * S::MWA; e += kBT) {
+                    const int idx = (e / S::MWA) * MWP + e % S::MWA;
+                    red[idx] =
+                        ((red[idx] + red[SLOT + idx]) + red[2 * SLOT + idx]) + red[3 * SLOT + idx];
+                }
+                __syncthreads();
+            }
+            float *ext = red + SLOT; // three free slots from here on
 
-        if (first) {
-            // ---- Gram terms: four waves x lane groups, fixed-order sum ----
-            float *gw = ext + w * S::GW;
-            if (!LDA) {
+            if (first && hh == 0) {
+                // ---- Gram terms: four waves x lane groups, fixed-order sum ----
+                float *gw = ext + w * S::GW;
+                if (!LDA) {
 #pragma unroll
-                for (int up = 0; up < NT; ++up)
+                    for (int up = 0; up < NT; ++up)
 #pragma unroll
-                    for (int uq = 0; uq < NT; ++uq)
+                        for (int uq = 0; uq < NT; ++uq)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                gw[(16 * up + 4 * g + q) * KP + 16 * uq + l16] = gacc[up * NT + uq][q];
+#pragma unroll
+                    for (int u = 0; u < NT; ++u) {
+                        gw[KP * KP + g * KP + 16 * u + l16] = dP[u];
+                        gw[KP * KP + 4 * KP + g * KP + 16 * u + l16] = dQ[u];
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < NT; ++u)
 #pragma unroll
                         for (int q = 0; q < 4; ++q)
-                            gw[(16 * up + 4 * g + q) * KP + 16 * uq + l16] = gacc[up * NT + uq][q];
+                            gw[(4 * g + q) * KP + 16 * u + l16] = gacc[u][q];
 #pragma unroll
-                for (int u = 0; u < NT; ++u) {
-                    gw[KP * KP + g * KP + 16 * u + l16] = dP[u];
-                    gw[KP * KP + 4 * KP + g * KP + 16 * u + l16] = dQ[u];
+                    for (int u = 0; u < NT; ++u)
+                        gw[16 * KP + g * KP + 16 * u + l16] = dP[u];
                 }
-            } else {
-#pragma unroll
-                for (int u = 0; u < NT; ++u)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        gw[(4 * g + q) * KP + 16 * u + l16] = gacc[u][q];
-#pragma unroll
-                for (int u = 0; u < NT; ++u)
-                    gw[16 * KP + g * KP + 16 * u + l16] = dP[u];
-            }
-            __syncthreads();
-            for (int e = tid; e < S::GT; e += kBT) {
-                double s = 0.0;
-                const int base = LDA ? 16 * KP : KP * KP;
-                if (e < base) {
-                    for (int ww = 0; ww < kBW; ++ww)
-                        s += (double)ext[ww * S::GW + e];
-                } else {
-                    const int which = (e - base) / KP, col = (e - base) % KP;
-                    for (int ww = 0; ww < kBW; ++ww)
-                        for (int gg = 0; gg < 4; ++gg)
-                            s += (double)ext[ww * S::GW + base + which * 4 * KP + gg * KP + col];
+                __syncthreads();
+                for (int e = tid; e < S::GT; e += kBT) {
+                    double s = 0.0;
+                    const int base = LDA ? 16 * KP : KP * KP;
+                    if (e < base) {
+                        for (int ww = 0; ww < kBW; ++ww)
+                            s += (double)ext[ww * S::GW + e];
+                    } else {
+                        const int which = (e - base) / KP, col = (e - base) % KP;
+                        for (int ww = 0; ww < kBW; ++ww)
+                            for (int gg = 0; gg < 4; ++gg)
+                                s += (double)ext[ww * S::GW + base + which * 4 * KP + gg * KP + col];
+                    }
+                    gd[e] = s;
                 }
-                gd[e] = s;
-            }
-            __syncthreads();
+                __syncthreads();
 
-            // ---- k x k coefficients (identical in every workgroup) ----
-            double *ss = reinterpret_cast<double *>(ext);
-            for (int e = tid; e < a.Ws; e += kBT)
-                ss[e] = a.stot[e];
-            __syncthreads();
-            if (tid < KP) {
-                const int i = tid;
-                double inv = 0.0, s = 1.0;
-                if (i < a.k) {
-                    inv = 1.0 / sqrt(ss[TRI + i]);
-                    if (a.smooth) { // Alg. 3: exp(log rho + (log nu - log rho) sigmoid(z_i))
-                        const double z = a.coef->z[(int64_t)t & 1][i];
-                        s = exp(a.lrho + a.lspan / (1.0 + exp(-z)));
-                    } else {        // Alg. 2: max(v_i^T G_i, rho)
-                        s = ss[tri_idx(i, i)] * inv;
-                        if (!(s >= a.rho))
-                            s = a.rho;
+                // ---- k x k coefficients (identical in every workgroup) ----
+                double *ss = reinterpret_cast<double *>(ext);
+                // four loads of a thread in flight before its stores
+                for (int e0 = 0; e0 < a.Ws; e0 += 4 * kBT) {
+                    double r[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int e = e0 + tid + q * kBT;
+                        r[q] = e < a.Ws ? a.stot[e] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int e = e0 + tid + q * kBT;
+                        if (e < a.Ws)
+                            ss[e] = r[q];
                     }
                 }
-                dInv[i] = inv;
-                dS[i] = s;
-            }
-            __syncthreads();
-            if (LDA) {
-                // class sums S = L^T R (raw) and the centred normalised class-mean
-                // projections Mc_ci = (mu_c - mubar)^T v_i (FP64), cU = pi_c Mc_ci
-                for (int e = tid; e < kMaxCls * KP; e += kBT) {
-                    const int c = e / KP, i = e % KP;
-                    cSp[e] = (c < a.ncls && i < a.k) ? (float)gd[e] : 0.f;
-                }
+                __syncthreads();
                 if (tid < KP) {
                     const int i = tid;
-                    double mbar = 0.0, usum = 0.0;
-                    if (i < a.k)
-                        for (int c = 0; c < a.ncls; ++c)
-                            mbar += sprior[c] * ss[TRI + KP + c * KP + i] * dInv[i];
-                    for (int c = 0; c < kMaxCls; ++c) {
-                        double mc = 0.0;
-                        if (c < a.ncls && i < a.k)
-                            mc = ss[TRI + KP + c * KP + i] * dInv[i] - mbar;
-                        dMc[c * KP + i] = mc;
-                        const float u = (float)((c < a.ncls ? sprior[c] : 0.0) * mc);
-                        cU[c * KP + i] = u;
-                        usum += (double)u;
-                    }
-                    cUc[i] = (float)usum;
-                }
-            }
-            __syncthreads();
-            // (M_A)_ij: CCA b^-1 inv_i inv_j (P^T Q + Q^T P)_ij; LDA sum_c pi_c Mc_ci Mc_cj
-            auto MA = [&](int i, int j) -> double {
-                if (!LDA)
-                    return (gd[i * KP + j] + gd[j * KP + i]) * dInv[i] * dInv[j] * ib;
-                double s = 0.0;
-                for (int c = 0; c < a.ncls; ++c)
-                    s += sprior[c] * dMc[c * KP + i] * dMc[c * KP + j];
-                return s;
-            };
-            for (int e = tid; e < KP * KP; e += kBT) {
-                const int j = e / KP, i = e % KP;
-                double val = 0.0;
-                if (i < a.k && j < i)
-                    val = MA(i, j) / dS[j];
-                Tt[e] = (float)val;
-                Td[i * KP + j] = val;
-            }
-            __syncthreads();
-            Coef *cw = a.coef;
-            if (tid < KP) {
-                const int i = tid;
-                double mA = 0.0, mB = 0.0, c = 0.0;
-                if (i < a.k) {
-                    const double ii2 = dInv[i] * dInv[i];
-                    mA = MA(i, i);
-                    if (!LDA)
-                        mB = (gd[KP * KP + i] + gd[KP * KP + KP + i]) * ii2 * ib;
-                    else
-                        mB = gd[16 * KP + i] * ii2 * ib + a.eps_reg;
-                    for (int j = 0; j < i; ++j)
-                        c += Td[i * KP + j] * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
-                }
-                cMB[i] = (float)mB;
-                cMAc[i] = (float)(mA - c);
-                cInv[i] = (float)dInv[i];
-                if (wg == 0) {
+                    double inv = 0.0, s = 1.0;
                     if (i < a.k) {
-                        cw->ema_a[i] += a.gamma * (mA - cw->ema_a[i]);
-                        cw->ema_b[i] += a.gamma * (mB - cw->ema_b[i]);
-                        const double craw = ss[tri_idx(i, i)] * dInv[i];
-                        if (a.smooth) {
-                            // Alg. 3 z step at rate gamma, into the other buffer
-                            const double z = cw->z[(int64_t)t & 1][i];
-                            const double sg = 1.0 / (1.0 + exp(-z));
-                            const double zn = z + a.gamma * (craw - dS[i]) * dS[i] * a.lspan *
-                                                      sg * (1.0 - sg);
-                            cw->z[((int64_t)t + 1) & 1][i] = zn;
-                            if (!isfinite(zn))
-                                atomicOr(&cw->status, kStatusNonFinite);
-                        } else if (!(craw >= a.rho)) {
-                            atomicAdd(&cw->clip_count, 1);
+                        inv = 1.0 / sqrt(ss[TRI + i]);
+                        if (a.smooth) { // Alg. 3: exp(log rho + (log nu - log rho) sigmoid(z_i))
+                            const double z = a.coef->z[(int64_t)t & 1][i];
+                            s = exp(a.lrho + a.lspan / (1.0 + exp(-z)));
+                        } else {        // Alg. 2: max(v_i^T G_i, rho)
+                            s = ss[tri_idx(i, i)] * inv;
+                            if (!(s >= a.rho))
+                                s = a.rho;
                         }
-                        if (!isfinite(mA) || !isfinite(mB) || !isfinite(c) || !isfinite(dInv[i]) ||
-                            !(dInv[i] > 0.0) || !isfinite(craw))
-                            atomicOr(&cw->status, kStatusNonFinite);
                     }
-                    cw->mA[i] = mA;
-                    cw->mB[i] = mB;
-                    cw->c[i] = c;
-                    cw->s[i] = dS[i];
-                    if (i == 0) {
-                        cw->eta = eta_sched(a, t);
-                        cw->gamma = a.gamma;
+                    dInv[i] = inv;
+                    dS[i] = s;
+                }
+                __syncthreads();
+                if (LDA) {
+                    // class sums S = L^T R (raw) and the centred normalised class-mean
+                    // projections Mc_ci = (mu_c - mubar)^T v_i (FP64), cU = pi_c Mc_ci
+                    for (int e = tid; e < kMaxCls * KP; e += kBT) {
+                        const int c = e / KP, i = e % KP;
+                        cSp[e] = (c < a.ncls && i < a.k) ? (float)gd[e] : 0.f;
                     }
+                    if (tid < KP) {
+                        const int i = tid;
+                        double mbar = 0.0, usum = 0.0;
+                        if (i < a.k)
+                            for (int c = 0; c < a.ncls; ++c)
+                                mbar += sprior[c] * ss[TRI + KP + c * KP + i] * dInv[i];
+                        for (int c = 0; c < kMaxCls; ++c) {
+                            double mc = 0.0;
+                            if (c < a.ncls && i < a.k)
+                                mc = ss[TRI + KP + c * KP + i] * dInv[i] - mbar;
+                            dMc[c * KP + i] = mc;
+                            const float u = (float)((c < a.ncls ? sprior[c] : 0.0) * mc);
+                            cU[c * KP + i] = u;
+                            usum += (double)u;
+                        }
+                        cUc[i] = (float)usum;
+                    }
+                }
+                __syncthreads();
+                // (M_A)_ij: CCA b^-1 inv_i inv_j (P^T Q + Q^T P)_ij; LDA sum_c pi_c Mc_ci Mc_cj
+                auto MA = [&](int i, int j) -> double {
+                    if (!LDA)
+                        return (gd[i * KP + j] + gd[j * KP + i]) * dInv[i] * dInv[j] * ib;
+                    double s = 0.0;
+                    for (int c = 0; c < a.ncls; ++c)
+                        s += sprior[c] * dMc[c * KP + i] * dMc[c * KP + j];
+                    return s;
+                };
+                for (int e = tid; e < KP * KP; e += kBT) {
+                    const int j = e / KP, i = e % KP;
+                    double val = 0.0;
+                    if (i < a.k && j < i)
+                        val = MA(i, j) / dS[j];
+                    Tt[e] = (float)val;
+                    Td[i * KP + j] = val;
+                }
+                __syncthreads();
+                Coef *cw = a.coef;
+                if (tid < KP) {
+                    const int i = tid;
+                    double mA = 0.0, mB = 0.0, c = 0.0;
+                    if (i < a.k) {
+                        const double ii2 = dInv[i] * dInv[i];
+                        mA = MA(i, i);
+                        if (!LDA)
+                            mB = (gd[KP * KP + i] + gd[KP * KP + KP + i]) * ii2 * ib;
+                        else
+                            mB = gd[16 * KP + i] * ii2 * ib + a.eps_reg;
+                        for (int j = 0; j < i; ++j)
+                            c += Td[i * KP + j] * (ss[tri_idx(i, j)] * dInv[i]); // T_ij C_ij
+                    }
+                    cMB[i] = (float)mB;
+                    cMAc[i] = (float)(mA - c);
+                    cInv[i] = (float)dInv[i];
+                    if (wg == 0) {
+                        if (i < a.k) {
+                            cw->ema_a[i] += a.gamma * (mA - cw->ema_a[i]);
+                            cw->ema_b[i] += a.gamma * (mB - cw->ema_b[i]);
+                            const double craw = ss[tri_idx(i, i)] * dInv[i];
+                            if (a.smooth) {
+                                // Alg. 3 z step at rate gamma, into the other buffer
+                                const double z = cw->z[(int64_t)t & 1][i];
+                                const double sg = 1.0 / (1.0 + exp(-z));
+                                const double zn = z + a.gamma * (craw - dS[i]) * dS[i] * a.lspan *
+                                                          sg * (1.0 - sg);
+                                cw->z[((int64_t)t + 1) & 1][i] = zn;
+                                if (!isfinite(zn))
+                                    atomicOr(&cw->status, kStatusNonFinite);
+                            } else if (!(craw >= a.rho)) {
+                                atomicAdd(&cw->clip_count, 1);
+                            }
+                            if (!isfinite(mA) || !isfinite(mB) || !isfinite(c) || !isfinite(dInv[i]) ||
+                                !(dInv[i] > 0.0) || !isfinite(craw))
+                                atomicOr(&cw->status, kStatusNonFinite);
+                        }
+                        cw->mA[i] = mA;
+                        cw->mB[i] = mB;
+                        cw->c[i] = c;
+                        cw->s[i] = dS[i];
+                        if (i == 0) {
+                            cw->eta = eta_sched(a, t);
+                            cw->gamma = a.gamma;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            if constexpr (PART) { // the coefficient tile for k_wepi; no epilogue here
+                float *ct = a.ctile;
+                for (int e = tid; e < KP * KP; e += kBT)
+                    ct[e] = Tt[e];
+                if (tid < KP) {
+                    ct[KP * KP + tid] = cInv[tid];
+                    ct[KP * KP + KP + tid] = cMB[tid];
+                    ct[KP * KP + 2 * KP + tid] = cMAc[tid];
+                    ct[KP * KP + 3 * KP + tid] = cUc[tid];
+                }
+                if (LDA)
+                    for (int e = tid; e < NC * KP; e += kBT) {
+                        ct[KP * KP + 4 * KP + e] = cSp[e];
+                        ct[KP * KP + 4 * KP + NC * KP + e] = cU[e];
+                    }
+                return;
+            }
+
+            // ---- fused epilogue on 16 x 16 tiles (feature block fb, player block pb) ----
+            float *Gold = ext, *Vn = ext + kFT * GLD, *Gn = Vn + kFT * VLD;
+#pragma unroll
+            for (int q = 0; q < GPT; ++q) {
+                const int e = tid + q * kBT;
+                Gold[(e / KP) * GLD + e % KP] = gpre[q];
+            }
+            if (LDA) {
+                for (int e = tid; e < kMaxCls * kFT; e += kBT) {
+                    const int c = e / kFT, fl = e % kFT;
+                    Mt[e] = c < a.ncls ? a.M[(int64_t)c * a.dtot + frow + fl] : 0.f;
+                }
+                for (int e = tid; e < kFT; e += kBT)
+                    Mb[e] = a.Mbar[frow + e];
+            }
+            __syncthreads();
+            for (int tt = w; tt < 4 * NT; tt += kBW) {
+                const int fb = tt / NT, pb = tt % NT;
+                // parent penalty sum_j G_old[fl][j] T_ij, and (LDA) the class terms
+                // sum_c M[c][fl] S_ci and sum_c M[c][fl] U_ci: FP32 MFMA 16x16x4
+                f32x4 pen = {0.f, 0.f, 0.f, 0.f}, e2 = pen, e3 = pen;
+#pragma unroll 4
+                for (int j0 = 0; j0 < KP; j0 += 4)
+                    pen = __builtin_amdgcn_mfma_f32_16x16x4f32(Gold[(16 * fb + l16) * GLD + j0 + g],
+                                                              Tt[(j0 + g) * KP + 16 * pb + l16], pen, 0, 0, 0);
+                if (LDA) {
+#pragma unroll
+                    for (int c0 = 0; c0 < kMaxCls; c0 += 4) {
+                        const float mA_ = Mt[(c0 + g) * kFT + 16 * fb + l16];
+                        e2 = __builtin_amdgcn_mfma_f32_16x16x4f32(mA_, cSp[(c0 + g) * KP + 16 * pb + l16], e2, 0, 0, 0);
+                        e3 = __builtin_amdgcn_mfma_f32_16x16x4f32(mA_, cU[(c0 + g) * KP + 16 * pb + l16], e3, 0, 0, 0);
+                    }
+                }
+                const int i = 16 * pb + l16;
+                // the state of this tile's four rows, loaded together
+                float vold[4], mold[4], sold[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t si = (frow + 16 * fb + 4 * g + r) * KP + i;
+                    vold[r] = a.V[si];
+                    if (OPT != kOptSGD) {
+                        mold[r] = a.Am[si];
+                        sold[r] = a.As[si];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int fl = 16 * fb + 4 * g + r; // FP32 D row 4 (l/16) + r
+                    const int64_t si = (frow + fl) * KP + i;
+                    float vn = 0.f, gn = 0.f;
+                    if (fvh + fl < dv && i < a.k) {
+                        const float inv = cInv[i];
+                        const float vh = vold[r] * inv;
+                        const float *pr = red + fl * MWP;
+                        float av, bv;
+                        if (!LDA) {
+                            const float sf = IN == kInFP8 ? a.colscale[frow + fl] : 1.f;
+                            const float rawA = v == 0 ? pr[KP + i] : pr[i];
+                            const float rawB = v == 0 ? pr[i] : pr[KP + i];
+                            av = rawA * sf * inv * ibf;
+                            bv = rawB * sf * inv * ibf;
+                        } else {
+                            bv = (pr[i] - e2[r]) * inv * ibf + eps * vh;
+                            av = e3[r] - Mb[fl] * cUc[i];
+                        }
+                        const float grad = (av - pen[r]) * cMB[i] - bv * cMAc[i];
+                        if (OPT == kOptSGD) {
+                            vn = vh + eta * grad;
+                        } else {
+                            const float mm = b1 * mold[r] + (1.f - b1) * grad;
+                            const float sq = b2 * sold[r] + (1.f - b2) * grad * grad;
+                            a.Am[si] = mm;
+                            a.As[si] = sq;
+                            vn = vh + eta * (mm / c1) / (sqrtf(sq / c2) + aeps);
+                        }
+                        const float g0 = Gold[fl * GLD + i];
+                        gn = g0 + gam * (bv - g0);
+                        a.V[si] = vn;
+                        a.G[si] = gn;
+                    }
+                    Vn[fl * VLD + i] = vn;
+                    Gn[fl * VLD + i] = gn;
                 }
             }
             __syncthreads();
+            write_vop<KP, KIND, IN>(a, Vn, frow);
+            tile_stats<KP, KIND>(Vn, Gn, Mt, sacc);
+            tile_norms<KP, KIND>(Vn, nrm);
+            __syncthreads();
         }
-
-        // ---- fused epilogue on 16 x 16 tiles (feature block fb, player block pb) ----
-        float *Gold = ext, *Vn = ext + kFT * GLD, *Gn = Vn + kFT * VLD;
-#pragma unroll
-        for (int q = 0; q < GPT; ++q) {
-            const int e = tid + q * kBT;
-            Gold[(e / KP) * GLD + e % KP] = gpre[q];
-        }
-        if (LDA) {
-            for (int e = tid; e < kMaxCls * kFT; e += kBT) {
-                const int c = e / kFT, fl = e % kFT;
-                Mt[e] = c < a.ncls ? a.M[(int64_t)c * a.dtot + frow + fl] : 0.f;
-            }
-            for (int e = tid; e < kFT; e += kBT)
-                Mb[e] = a.Mbar[frow + e];
-        }
-        __syncthreads();
-        for (int tt = w; tt < 4 * NT; tt += kBW) {
-            const int fb = tt / NT, pb = tt % NT;
-            // parent penalty sum_j G_old[fl][j] T_ij, and (LDA) the class terms
-            // sum_c M[c][fl] S_ci and sum_c M[c][fl] U_ci: FP32 MFMA 16x16x4
-            f32x4 pen = {0.f, 0.f, 0.f, 0.f}, e2 = pen, e3 = pen;
-#pragma unroll 4
-            for (int j0 = 0; j0 < KP; j0 += 4)
-                pen = __builtin_amdgcn_mfma_f32_16x16x4f32(Gold[(16 * fb + l16) * GLD + j0 + g],
-                                                          Tt[(j0 + g) * KP + 16 * pb + l16], pen, 0, 0, 0);
-            if (LDA) {
-#pragma unroll
-                for (int c0 = 0; c0 < kMaxCls; c0 += 4) {
-                    const float mA_ = Mt[(c0 + g) * kFT + 16 * fb + l16];
-                    e2 = __builtin_amdgcn_mfma_f32_16x16x4f32(mA_, cSp[(c0 + g) * KP + 16 * pb + l16], e2, 0, 0, 0);
-                    e3 = __builtin_amdgcn_mfma_f32_16x16x4f32(mA_, cU[(c0 + g) * KP + 16 * pb + l16], e3, 0, 0, 0);
-                }
-            }
-            const int i = 16 * pb + l16;
-            // the state of this tile's four rows, loaded together
-            float vold[4], mold[4], sold[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t si = (frow + 16 * fb + 4 * g + r) * KP + i;
-                vold[r] = a.V[si];
-                if (OPT != kOptSGD) {
-                    mold[r] = a.Am[si];
-                    sold[r] = a.As[si];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int fl = 16 * fb + 4 * g + r; // FP32 D row 4 (l/16) + r
-                const int64_t si = (frow + fl) * KP + i;
-                float vn = 0.f, gn = 0.f;
-                if (fv0 + fl < dv && i < a.k) {
-                    const float inv = cInv[i];
-                    const float vh = vold[r] * inv;
-                    const float *pr = red + fl * MWP;
-                    float av, bv;
-                    if (!LDA) {
-                        const float sf = IN == kInFP8 ? a.colscale[frow + fl] : 1.f;
-                        const float rawA = v == 0 ? pr[KP + i] : pr[i];
-                        const float rawB = v == 0 ? pr[i] : pr[KP + i];
-                        av = rawA * sf * inv * ibf;
-                        bv = rawB * sf * inv * ibf;
-                    } else {
-                        bv = (pr[i] - e2[r]) * inv * ibf + eps * vh;
-                        av = e3[r] - Mb[fl] * cUc[i];
-                    }
-                    const float grad = (av - pen[r]) * cMB[i] - bv * cMAc[i];
-                    if (OPT == kOptSGD) {
-                        vn = vh + eta * grad;
-                    } else {
-                        const float mm = b1 * mold[r] + (1.f - b1) * grad;
-                        const float sq = b2 * sold[r] + (1.f - b2) * grad * grad;
-                        a.Am[si] = mm;
-                        a.As[si] = sq;
-                        vn = vh + eta * (mm / c1) / (sqrtf(sq / c2) + aeps);
-                    }
-                    const float g0 = Gold[fl * GLD + i];
-                    gn = g0 + gam * (bv - g0);
-                    a.V[si] = vn;
-                    a.G[si] = gn;
-                }
-                Vn[fl * VLD + i] = vn;
-                Gn[fl * VLD + i] = gn;
-            }
-        }
-        __syncthreads();
-        write_vop<KP, KIND, IN>(a, Vn, frow);
-        tile_stats<KP, KIND>(Vn, Gn, Mt, sacc);
-        tile_norms<KP, KIND>(Vn, nrm);
-        __syncthreads();
     }
+    write_stats<KP, KIND>(a, wg, sacc, nrm);
+}
+
+template <int KP, int IN, int KIND, int OPT>
+__global__ void __launch_bounds__(kBT) k_wbwd(WideArgs a)
+{
+    wbwd_body<KP, IN, KIND, OPT>(a);
+}
+
+template <int KP, int IN, int KIND>
+__global__ void __launch_bounds__(kBT) k_wprod(WideArgs a)
+{
+    wbwd_body<KP, IN, KIND, kOptSGD, 2 * kFT, true>(a);
+}
+
+// Size in floats of the coefficient tile: T (KP x KP), 1/||v||, m_B,
+// m_A - c, sum_c pi_c U (KP each), and (LDA) the class sums S and U.
+template <int KP, int KIND> constexpr int ctile_floats()
+{
+    return KP * KP + 4 * KP + (KIND == kKindLDA ? 2 * kMaxCls * KP : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Epilogue of the split backward: one workgroup per 64-feature tile of the
+// state (both views), from the products k_wprod left in memory and its
+// coefficient tile: update direction, retraction step (SGD or Adam),
+// auxiliary update, the V operand of the next iteration and this tile's
+// statistics partials (column = workgroup).  The same arithmetic as the
+// epilogue of k_wbwd.
+// ---------------------------------------------------------------------------
+template <int KP, int IN, int KIND, int OPT>
+__global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
+{
+    typedef Shape<KP, KIND> S;
+    constexpr int NT = S::NT, MWP = S::MWP, GLD = S::GLD, VLD = S::VLD, MWA = S::MWA;
+    constexpr bool LDA = S::LDA;
+    constexpr int NC = LDA ? kMaxCls : 1;
+    __shared__ float Gold[kFT * GLD], Vn[kFT * VLD], Gn[kFT * VLD];
+    __shared__ float Tt[KP * KP];
+    __shared__ float cInv[KP], cMB[KP], cMAc[KP], cUc[KP];
+    __shared__ float cSp[NC * KP], cU[NC * KP];
+    __shared__ float Mt[NC * kFT], Mb[LDA ? kFT : 1];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
+    const int l16 = lane & 15, g = lane >> 4;
+    const int wg = xcd_tile(blockIdx.x, gridDim.x);
+    const int nt0 = a.nsubv[0] * (a.ft / kFT); // 64-feature tiles of view 0
+    const int v = wg < nt0 ? 0 : 1;
+    const int64_t fvh = (int64_t)kFT * (v ? wg - nt0 : wg);
+    const int64_t dv = a.dv[v];
+    const int64_t frow = a.off[v] + fvh;
+    const double t = a.coef->t;
+    const double ib = 1.0 / (double)a.b;
+    const float eta = (float)eta_sched(a, t), gam = (float)a.gamma, ibf = (float)ib;
+    const float eps = (float)a.eps_reg;
+    const float b1 = (float)a.adam_b1, b2 = (float)a.adam_b2, aeps = (float)a.adam_eps;
+    const float c1 = (float)(1.0 - pow(a.adam_b1, t)), c2 = (float)(1.0 - pow(a.adam_b2, t));
+
+    // ---- everything the tile needs, in one round of loads: every load of a
+    // thread is issued before its first LDS store ----
+    constexpr int NTT = 4 * NT / kBW;      // epilogue tiles per wave
+    constexpr int PT = KP * KP / kBT;      // T
+    constexpr int PG = kFT * KP / kBT;     // old auxiliary tile
+    constexpr int PS = LDA ? NC * KP / kBT : 1; // class terms S, U
+    constexpr int PM = LDA ? NC * kFT / kBT : 1; // class means
+    constexpr int NPR = LDA ? 1 : 2;       // products per element: B_t V (LDA); X^T Q, X^T P
+    const float *ct = a.ctile;
+    float rT[PT], rG[PG], rS[PS], rU[PS], rM[PM], rMb = 0.f, rc[4] = {0.f, 0.f, 0.f, 0.f};
+    float vold_[NTT][4], prr[NTT][4][NPR];
+#pragma unroll
+    for (int q = 0; q < PT; ++q)
+        rT[q] = ct[tid + q * kBT];
+    if (tid < KP) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            rc[j] = ct[KP * KP + j * KP + tid]; // 1/||v||, m_B, m_A - c, sum_c pi_c U
+    }
+    if (LDA) {
+#pragma unroll
+        for (int q = 0; q < PS; ++q) {
+            rS[q] = ct[KP * KP + 4 * KP + tid + q * kBT];
+            rU[q] = ct[KP * KP + 4 * KP + NC * KP + tid + q * kBT];
+        }
+#pragma unroll
+        for (int q = 0; q < PM; ++q) {
+            const int e = tid + q * kBT, c = e / kFT, fl = e % kFT;
+            rM[q] = c < a.ncls ? a.M[(int64_t)c * a.dtot + frow + fl] : 0.f;
+        }
+        if (tid < kFT)
+            rMb = a.Mbar[frow + tid];
+    }
+#pragma unroll
+    for (int q = 0; q < PG; ++q)
+        rG[q] = a.G[frow * KP + tid + q * kBT];
+    // this lane's own elements of its epilogue tiles: old players and products
+    const float *pin = a.prod + frow * MWA;
+#pragma unroll
+    for (int h = 0; h < NTT; ++h) {
+        const int tt = w + kBW * h, fb = tt / NT, pb = tt % NT, i = 16 * pb + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int fl = 16 * fb + 4 * g + r;
+            vold_[h][r] = a.V[(frow + fl) * KP + i];
+            if (LDA) {
+                prr[h][r][0] = pin[fl * MWA + i];
+            } else { // view x: A_t from X^T Q (second half of the row), B_t from X^T P
+                prr[h][r][0] = pin[fl * MWA + KP + i];
+                prr[h][r][NPR - 1] = pin[fl * MWA + i];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PT; ++q)
+        Tt[tid + q * kBT] = rT[q];
+    if (tid < KP) {
+        cInv[tid] = rc[0];
+        cMB[tid] = rc[1];
+        cMAc[tid] = rc[2];
+        cUc[tid] = rc[3];
+    }
+    if (LDA) {
+#pragma unroll
+        for (int q = 0; q < PS; ++q) {
+            cSp[tid + q * kBT] = rS[q];
+            cU[tid + q * kBT] = rU[q];
+        }
+#pragma unroll
+        for (int q = 0; q < PM; ++q)
+            Mt[tid + q * kBT] = rM[q];
+        if (tid < kFT)
+            Mb[tid] = rMb;
+    }
+#pragma unroll
+    for (int q = 0; q < PG; ++q) {
+        const int e = tid + q * kBT;
+        Gold[(e / KP) * GLD + e % KP] = rG[q];
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int h = 0; h < NTT; ++h) {
+        const int tt = w + kBW * h, fb = tt / NT, pb = tt % NT;
+        f32x4 pen = {0.f, 0.f, 0.f, 0.f}, e2 = pen, e3 = pen;
+#pragma unroll 4
+        for (int j0 = 0; j0 < KP; j0 += 4)
+            pen = __builtin_amdgcn_mfma_f32_16x16x4f32(Gold[(16 * fb + l16) * GLD + j0 + g],
+                                                      Tt[(j0 + g) * KP + 16 * pb + l16], pen, 0, 0, 0);
+        if (LDA) {
+#pragma unroll
+            for (int c0 = 0; c0 < kMaxCls; c0 += 4) {
+                const float mA_ = Mt[(c0 + g) * kFT + 16 * fb + l16];
+                e2 = __builtin_amdgcn_mfma_f32_16x16x4f32(mA_, cSp[(c0 + g) * KP + 16 * pb + l16], e2, 0, 0, 0);
+                e3 = __builtin_amdgcn_mfma_f32_16x16x4f32(mA_, cU[(c0 + g) * KP + 16 * pb + l16], e3, 0, 0, 0);
+            }
+        }
+        const int i = 16 * pb + l16;
+        float vold[4], mold[4], sold[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t si = (frow + 16 * fb + 4 * g + r) * KP + i;
+            vold[r] = vold_[h][r];
+            if (OPT != kOptSGD) {
+                mold[r] = a.Am[si];
+                sold[r] = a.As[si];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int fl = 16 * fb + 4 * g + r; // FP32 D row 4 (l/16) + r
+            const int64_t si = (frow + fl) * KP + i;
+            float vn = 0.f, gn = 0.f;
+            if (fvh + fl < dv && i < a.k) {
+                const float inv = cInv[i];
+                const float vh = vold[r] * inv;
+                float av, bv;
+                if (!LDA) {
+                    const float sf = IN == kInFP8 ? a.colscale[frow + fl] : 1.f;
+                    // view x: A from X^T Q, B from X^T P; view y: the reverse
+                    const float rawA = v == 0 ? prr[h][r][0] : prr[h][r][NPR - 1];
+                    const float rawB = v == 0 ? prr[h][r][NPR - 1] : prr[h][r][0];
+                    av = rawA * sf * inv * ibf;
+                    bv = rawB * sf * inv * ibf;
+                } else {
+                    bv = (prr[h][r][0] - e2[r]) * inv * ibf + eps * vh;
+                    av = e3[r] - Mb[fl] * cUc[i];
+                }
+                const float grad = (av - pen[r]) * cMB[i] - bv * cMAc[i];
+                if (OPT == kOptSGD) {
+                    vn = vh + eta * grad;
+                } else {
+                    const float mm = b1 * mold[r] + (1.f - b1) * grad;
+                    const float sq = b2 * sold[r] + (1.f - b2) * grad * grad;
+                    a.Am[si] = mm;
+                    a.As[si] = sq;
+                    vn = vh + eta * (mm / c1) / (sqrtf(sq / c2) + aeps);
+                }
+                const float g0 = Gold[fl * GLD + i];
+                gn = g0 + gam * (bv - g0);
+                a.V[si] = vn;
+                a.G[si] = gn;
+            }
+            Vn[fl * VLD + i] = vn;
+            Gn[fl * VLD + i] = gn;
+        }
+    }
+    __syncthreads();
+    f64x4 sacc[StatTiles<KP, KIND>::H];
+#pragma unroll
+    for (int h = 0; h < StatTiles<KP, KIND>::H; ++h)
+        sacc[h] = f64x4{0, 0, 0, 0};
+    double nrm = 0.0;
+    write_vop<KP, KIND, IN>(a, Vn, frow);
+    tile_stats<KP, KIND>(Vn, Gn, Mt, sacc);
+    tile_norms<KP, KIND>(Vn, nrm);
     write_stats<KP, KIND>(a, wg, sacc, nrm);
 }
 
@@ -1205,8 +1526,9 @@ __global__ void __launch_bounds__(kBT) k_winit(WideArgs a)
     for (int h = 0; h < StatTiles<KP, KIND>::H; ++h)
         sacc[h] = f64x4{0, 0, 0, 0};
     double nrm = 0.0;
-    for (int sub = sub0; sub < sub1; ++sub) {
-        const int64_t frow = a.off[v] + (int64_t)sub * kFT;
+    const int nh = a.ft / kFT;
+    for (int sh = sub0 * nh; sh < sub1 * nh; ++sh) { // 64-feature halves of the subtiles
+        const int64_t frow = a.off[v] + (int64_t)sh * kFT;
         for (int e = tid; e < kFT * KP; e += kBT) {
             const float x = a.V[frow * KP + e];
             Vn[(e / KP) * VLD + e % KP] = x;

@@ -18,6 +18,7 @@ import pytest
 
 import oracle
 import synth
+from parity_bars import assert_players_close
 
 pytestmark = pytest.mark.gpu
 
@@ -89,7 +90,9 @@ def _run_cca(cfg, batches, V0, checkpoints, aux=None):
         s.step(Xd, Yd)
         oracle.gamma_step(pb, st, X, Y, _eta(cfg, t), cfg.gamma)
         if t in checkpoints:
-            res.append((t, s.vectors(), st.V.copy(), s.auxiliary(), st.G.copy(), s.eigvals(),
+            snap = oracle.State(V=st.V.copy(), G=st.G.copy(), t=st.t,
+                                s2=None if st.s2 is None else st.s2.copy())
+            res.append((t, s.vectors(), snap, s.auxiliary(), st.G.copy(), s.eigvals(),
                         st.eigvals()))
     s.close()
     return res
@@ -101,6 +104,10 @@ def _run_cca(cfg, batches, V0, checkpoints, aux=None):
     ("bf16", 64, 64, 1, 1, "sgd"),          # one player, one row
     ("fp8", 200, 136, 13, 100, "sgd"),
     ("fp8", 520, 264, 32, 130, "adam"),
+    # views wide enough for the split backward (128-feature products, then
+    # the epilogue per 64-feature tile); ragged last subtile of view x
+    ("bf16", 16392, 16384, 20, 64, "sgd"),
+    ("fp8", 16392, 16384, 20, 64, "adam"),
 ])
 def test_wide_cca_parity(fmt, dx, dy, k, b, opt):
     sg = _sg()
@@ -121,11 +128,11 @@ def test_wide_cca_parity(fmt, dx, dy, k, b, opt):
     batches = _cca_inputs(gen, N, b, fmt, scales)
     V0 = synth.initial_players(dx + dy, k, 4)
     res = _run_cca(cfg, batches, V0, {1, N}, aux)
-    for t, Vg, Vo, Gg, Go, lg, lo in res:
+    for t, Vg, so, Gg, Go, lg, lo in res:
         tol = TOLW_1 if t == 1 else TOLW_N
-        dv, dg = _maxdiff(Vg, Vo), _maxdiff(Gg, Go)
+        dv, dg = _maxdiff(Vg, so.V), _maxdiff(Gg, Go)
         print(f"  t={t}: max|dV|={dv:.2e} max|dG|={dg:.2e}", flush=True)
-        assert dv < tol, (t, dv)
+        assert_players_close(Vg, so, tol, adam, sum(_eta(cfg, i) for i in range(1, t + 1)))
         assert dg < tol, (t, dg)
         assert np.allclose(lg, lo, rtol=10 * tol, atol=10 * tol), (t, lg, lo)
         # unit players (Alg. 2 output)
@@ -150,6 +157,7 @@ TOLF_N = 3e-4
     (520, 6, 20, 130, "adam"),    # KP 32
     (136, 10, 64, 77, "sgd"),     # KP 64, k > classes (zero eigenvalues beyond c - 1)
     (4104, 5, 40, 200, "adam"),   # KP 64, several forward slices, ragged last subtile
+    (32776, 5, 40, 200, "adam"),  # BF16: the split backward, ragged last 128-feature subtile
 ])
 def test_wide_lda_parity(d, c, k, b, opt, fmt):
     sg = _sg()
@@ -186,23 +194,29 @@ def test_wide_lda_parity(d, c, k, b, opt, fmt):
             Vg, Gg = s.vectors(), s.auxiliary()
             dv, dg = _maxdiff(Vg, st.V), _maxdiff(Gg, st.G)
             print(f"  t={t}: max|dV|={dv:.2e} max|dG|={dg:.2e}", flush=True)
-            assert dv < tol, (t, dv)
+            assert_players_close(Vg, st, tol, adam, sum(_eta(cfg, i) for i in range(1, t + 1)))
             assert dg < tol * max(1.0, float(np.abs(st.G).max())), (t, dg)
             lg, lo = s.eigvals(), st.eigvals()
             assert np.allclose(lg, lo, rtol=10 * tol, atol=10 * tol), (t, lg, lo)
     s.close()
 
 
-def test_wide_determinism_resume_and_graph():
+@pytest.mark.parametrize("dx,dy", [(136, 72), (16392, 16384)])
+def test_wide_determinism_resume_and_graph(dx, dy):
     """Bitwise-identical reruns, checkpoint / resume in a fresh handle, and
-    hipGraph replay equal to eager steps (BF16 CCA with Adam)."""
+    hipGraph replay equal to eager steps (BF16 CCA with Adam; one backward
+    kernel, and the split backward at the wider views)."""
     torch = _torch()
     sg = _sg()
-    gen = synth.CCAPlanted(136, 72, np.linspace(0.9, 0.3, 4), sigma=0.5, seed=8)
-    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_BF16, 8, 136, 72, 96,
+    gen = synth.CCAPlanted(dx, dy, np.linspace(0.9, 0.3, 4), sigma=0.5, seed=8)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_BF16, 8, dx, dy, 96,
                          optimizer=sg.SGEP_ADAM, eta0=1e-3, gamma=0.3)
     batches = _cca_inputs(gen, 8, 96, "bf16")
-    V0 = synth.initial_players(208, 8, 1)
+    V0 = synth.initial_players(dx + dy, 8, 1)
+    probe = sg.Solver(cfg, V0)
+    nk = probe.kernels_per_step()
+    probe.close()
+    assert nk == (4 if dx > 10_000 else 3)
 
     def run(bs, solver=None):
         s = solver or sg.Solver(cfg, V0)
@@ -215,7 +229,7 @@ def test_wide_determinism_resume_and_graph():
     assert np.array_equal(a.auxiliary(), b.auxiliary())
     c = run(batches[:4])
     blob = c.get_state()
-    d = sg.Solver(cfg, synth.initial_players(208, 8, 7))
+    d = sg.Solver(cfg, synth.initial_players(dx + dy, 8, 7))
     d.set_state(blob)
     assert d.step_count() == 4
     run(batches[4:], solver=d)
