@@ -458,9 +458,11 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
     const bool adam = h->cfg.optimizer == SGEP_ADAM;
     // forward workgroups, then the statistics reductions
     const dim3 gf(a.n_rb * a.nview * a.n_split + wide_stat_blocks(a));
-    if constexpr (KP <= 32 && IN != kInF32) {
-        if (a.rbf == 128)
-            launch_k(k_wfwd<KP, IN, 128>, gf, blk, h->stream, ev[0], ev[1], a);
+    if constexpr (IN != kInF32) {
+        if (a.rbf == fwd4_rows<KP>()) // four waves (k_wfwd4)
+            launch_k(k_wfwd4<KP, IN>, gf, dim3(256), h->stream, ev[0], ev[1], a);
+        else if (KP <= 32 && a.rbf == 128)
+            launch_k(k_wfwd<KP, IN, (KP <= 32 ? 128 : 64)>, gf, blk, h->stream, ev[0], ev[1], a);
         else
             launch_k(k_wfwd<KP, IN, 64>, gf, blk, h->stream, ev[0], ev[1], a);
     } else {
@@ -627,25 +629,30 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.dtot = lda ? r64(c.dx) : r64(c.dx) + r64(c.dy);
     a.k = c.k;
     a.ncls = lda ? c.n_classes : 0;
-    a.ldr = (c.b_max + kRowPad - 1) / kRowPad * kRowPad;
+    // BF16 / FP8 minibatches of >= 256 rows: the forward with four waves of
+    // 256 rows (k_wfwd4); its row blocks pad the rows to multiples of 256
+    const bool fwd4 = !f32 && c.b_max >= 256;
+    const int64_t rowpad = fwd4 ? 256 : kRowPad;
+    a.ldr = (c.b_max + rowpad - 1) / rowpad * rowpad;
     // forward: aim at >= 512 workgroups of 64 rows at b_max (the same number of
     // rows in flight with 128-row blocks), each wave >= one 64-feature step;
     // 128-row blocks when they still give >= 256 workgroups
     const int64_t dvmax = a.dv[0] > a.dv[1] ? a.dv[0] : a.dv[1];
     const int64_t nf64 = (dvmax + 63) / 64;
     const int64_t ns_cap = (nf64 + kNW - 1) / kNW;
-    a.rbf = (KP <= 32 && !f32 && (a.ldr / 128) * a.nview * ns_cap >= 256) ? 128 : 64;
+    a.rbf = fwd4 ? (KP <= 32 ? 256 : 128) : ((KP <= 32 && !f32 && (a.ldr / 128) * a.nview * ns_cap >= 256) ? 128 : 64);
     const int64_t rbf = a.rbf;
+    const int64_t nwv = fwd4 ? 4 : kNW; // waves per forward workgroup
     const int64_t nrb = a.ldr / rbf;
-    const int64_t target = 512 * kRB / rbf;
+    const int64_t target = fwd4 ? 512 : 512 * kRB / rbf; // forward workgroups
     int64_t ns = (target + nrb * a.nview - 1) / (nrb * a.nview);
-    const int64_t ns_max = (nf64 + kNW - 1) / kNW;
+    const int64_t ns_max = (nf64 + nwv - 1) / nwv;
     if (ns > ns_max)
         ns = ns_max;
     if (ns < 1)
         ns = 1;
-    a.fw = 64 * ((nf64 + kNW * ns - 1) / (kNW * ns));
-    a.fs = kNW * a.fw;
+    a.fw = 64 * ((nf64 + nwv * ns - 1) / (nwv * ns));
+    a.fs = nwv * a.fw;
     a.n_split = (int32_t)((dvmax + a.fs - 1) / a.fs);
     // backward: subtiles of ft features, about 256 workgroups (64-feature
     // subtiles) or one 128-feature subtile per workgroup

