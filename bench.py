@@ -1000,6 +1000,9 @@ def main():
     ap.add_argument("--no-tta", action="store_true", help="skip the time-to-accuracy run")
     ap.add_argument("--no-twin", action="store_true",
                     help="skip the FP32 reference of a reduced-precision workload")
+    ap.add_argument("--tta-only", action="store_true",
+                    help="run only the time-to-accuracy leg of --workload (no throughput, twin "
+                         "or CPU baseline) and print its record with the error trajectory")
     ap.add_argument("--tta-steps", type=int, default=None,
                     help="step limit of each time-to-accuracy run (default per workload)")
     ap.add_argument("--batch-plan", default="",
@@ -1022,6 +1025,16 @@ def main():
         run_batch(args, BATCH_WORKLOADS[args.workload])
         return
     w = WORKLOADS[args.workload]
+    if args.tta_only:
+        tt = w["tta"]
+        mx = args.tta_steps if args.tta_steps is not None else tt["max_steps"]
+        log = (lambda m: print("bench: " + m, file=sys.stderr, flush=True))
+        res = time_to_accuracy(w, tt["targets"], mx, tt["every"], log=log)
+        print(json.dumps({"workload": args.workload, "dtype": w["dtype"],
+                          "config": {kk: w[kk] for kk in sorted(w)
+                                     if kk not in ("tta", "twin", "describe")},
+                          "time_to_accuracy": res}), flush=True)
+        return
     big = w["b"] * (w["dx"] + w["dy"]) > 1 << 24
     K = args.steps if args.steps is not None else (256 if big else 2048)
     W = args.warmup if args.warmup is not None else (8 if big else 64)

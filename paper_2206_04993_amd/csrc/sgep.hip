@@ -450,6 +450,12 @@ int wide_stat_blocks(const WideArgs &a)
     return (a.Ws + sgep::wide::kStatCols - 1) / sgep::wide::kStatCols;
 }
 
+// bytes of the statistics partials: groups of 16 statistics x lds columns
+static size_t wide_stat_part_bytes(const WideArgs &a)
+{
+    return (size_t)wide_stat_blocks(a) * sgep::wide::kStatCols * a.lds * sizeof(double);
+}
+
 template <int KP, int IN, int KIND>
 sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
 {
@@ -458,17 +464,29 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
     const bool adam = h->cfg.optimizer == SGEP_ADAM;
     // forward workgroups, then the statistics reductions
     const dim3 gf(a.n_rb * a.nview * a.n_split + wide_stat_blocks(a));
-    if constexpr (IN != kInF32) {
-        if (a.rbf == fwd4_rows<KP>()) // four waves (k_wfwd4)
-            launch_k(k_wfwd4<KP, IN>, gf, dim3(256), h->stream, ev[0], ev[1], a);
-        else if (KP <= 32 && a.rbf == 128)
-            launch_k(k_wfwd<KP, IN, (KP <= 32 ? 128 : 64)>, gf, blk, h->stream, ev[0], ev[1], a);
-        else
-            launch_k(k_wfwd<KP, IN, 64>, gf, blk, h->stream, ev[0], ev[1], a);
-    } else {
+    auto forward = [&]() {
+        if constexpr (IN != kInF32) {
+            if constexpr (KP == 64 && IN == kInBF16) {
+                if (a.rbf == kFwdVRows) { // V shared through LDS (k_wfwdv)
+                    launch_k(k_wfwdv<IN>, gf, dim3(512), h->stream, ev[0], ev[1], a);
+                    return;
+                }
+            }
+            if (a.rbf == fwd4_rows<KP>()) { // four waves (k_wfwd4)
+                launch_k(k_wfwd4<KP, IN>, gf, dim3(256), h->stream, ev[0], ev[1], a);
+                return;
+            }
+            if constexpr (KP <= 32) {
+                if (a.rbf == 128) {
+                    launch_k(k_wfwd<KP, IN, 128>, gf, blk, h->stream, ev[0], ev[1], a);
+                    return;
+                }
+            }
+        }
         launch_k(k_wfwd<KP, IN, 64>, gf, blk, h->stream, ev[0], ev[1], a);
-    }
-    launch_k(k_wmid<KP, IN, KIND>, dim3(a.nA), blk, h->stream, ev[2], ev[3], a);
+    };
+    forward();
+    launch_k(k_wmid<KP, IN, KIND>, dim3(a.nA), dim3(kMT), h->stream, ev[2], ev[3], a);
     const dim3 bblk(kBT);
     constexpr bool can128 = IN != kInF32; // 128-feature subtiles: BF16 / FP8 only
     if (can128 && a.ft == 2 * kFT) {
@@ -629,22 +647,30 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.dtot = lda ? r64(c.dx) : r64(c.dx) + r64(c.dy);
     a.k = c.k;
     a.ncls = lda ? c.n_classes : 0;
-    // BF16 / FP8 minibatches of >= 256 rows: the forward with four waves of
-    // 256 rows (k_wfwd4); its row blocks pad the rows to multiples of 256
-    const bool fwd4 = !f32 && c.b_max >= 256;
-    const int64_t rowpad = fwd4 ? 256 : kRowPad;
+    // forward kernels: KP = 64 BF16 minibatches of >= 1024 rows take
+    // k_wfwdv (512-row workgroups sharing the V operand through LDS, rows
+    // padded to 512); other BF16 / FP8 minibatches of >= 256 rows the
+    // four-wave k_wfwd4 (rows padded to 256); the rest k_wfwd
+    const bool fwdv = KP == 64 && !f32 && !fp8 && c.b_max >= 1024;
+    const bool fwd4 = !fwdv && !f32 && c.b_max >= 256;
+    const int64_t rowpad = fwdv ? kFwdVRows : (fwd4 ? 256 : kRowPad);
     a.ldr = (c.b_max + rowpad - 1) / rowpad * rowpad;
-    // forward: aim at >= 512 workgroups of 64 rows at b_max (the same number of
+    // k_wfwd: aim at >= 512 workgroups of 64 rows at b_max (the same number of
     // rows in flight with 128-row blocks), each wave >= one 64-feature step;
-    // 128-row blocks when they still give >= 256 workgroups
+    // 128-row blocks when they still give >= 256 workgroups.  k_wfwd4: 512
+    // workgroups; k_wfwdv: 256 (one per CU: each slice's partial costs 512
+    // rows x KP of memory traffic)
     const int64_t dvmax = a.dv[0] > a.dv[1] ? a.dv[0] : a.dv[1];
     const int64_t nf64 = (dvmax + 63) / 64;
     const int64_t ns_cap = (nf64 + kNW - 1) / kNW;
-    a.rbf = fwd4 ? (KP <= 32 ? 256 : 128) : ((KP <= 32 && !f32 && (a.ldr / 128) * a.nview * ns_cap >= 256) ? 128 : 64);
+    a.rbf = fwdv ? kFwdVRows
+                 : (fwd4 ? (KP <= 32 ? 256 : 128)
+                         : ((KP <= 32 && !f32 && (a.ldr / 128) * a.nview * ns_cap >= 256) ? 128 : 64));
     const int64_t rbf = a.rbf;
-    const int64_t nwv = fwd4 ? 4 : kNW; // waves per forward workgroup
+    // feature ranges per forward workgroup (k_wfwdv: one, shared by its waves)
+    const int64_t nwv = fwdv ? 1 : (fwd4 ? 4 : kNW);
     const int64_t nrb = a.ldr / rbf;
-    const int64_t target = fwd4 ? 512 : 512 * kRB / rbf; // forward workgroups
+    const int64_t target = fwdv ? 256 : (fwd4 ? 512 : 512 * kRB / rbf); // forward workgroups
     int64_t ns = (target + nrb * a.nview - 1) / (nrb * a.nview);
     const int64_t ns_max = (nf64 + nwv - 1) / nwv;
     if (ns > ns_max)
@@ -679,7 +705,7 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     const size_t st = (size_t)a.dtot * KP * sizeof(float);
     const size_t op = (size_t)KP * a.dtot * sizeof(uint16_t);
     const size_t wbytes = (size_t)MW * a.ldr * sizeof(uint16_t); // FP32 input: twice this
-    const size_t spb = (size_t)a.Ws * a.lds * sizeof(double);
+    const size_t spb = wide_stat_part_bytes(a);
     alloc(&h->V, st);
     alloc(&h->G, st);
     if (c.optimizer == SGEP_ADAM) {
@@ -843,7 +869,7 @@ sgep_status step_wide(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
     a.ldy = lda ? 0 : ldy;
     a.b = b;
     a.n_rb = (int32_t)((b + a.rbf - 1) / a.rbf);
-    a.nA = 4 * (int32_t)((b + sgep::wide::kRB - 1) / sgep::wide::kRB);
+    a.nA = (sgep::wide::kRB / sgep::wide::kMR) * (int32_t)((b + sgep::wide::kRB - 1) / sgep::wide::kRB);
     hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     if (events)
         for (int i = 0; i < 2 * wide_kernels(h); ++i)
@@ -879,7 +905,7 @@ StateLayout state_layout(const sgep_handle *h)
         L.add(h->Vh, op);
         L.add(h->Vl, op);
         L.add(h->Vf, 2 * op); // FP32 input: in place of Vh, Vl
-        L.add(h->stat_part, (size_t)h->wa.Ws * h->wa.lds * sizeof(double));
+        L.add(h->stat_part, wide_stat_part_bytes(h->wa));
     } else {
         const size_t st = (size_t)h->ldv * h->kp * h->esz;
         L.add(h->V, st);
@@ -1404,7 +1430,7 @@ sgep_status sgep_state_size(const sgep_handle *h, size_t *bytes)
         const size_t st = (size_t)h->wa.dtot * h->kp * sizeof(float);
         const size_t op = (size_t)h->kp * h->wa.dtot * sizeof(uint16_t);
         *bytes = sizeof(StateHeader) + sizeof(Coef) + st * (h->Am ? 4 : 2) + 2 * op +
-                 (size_t)h->wa.Ws * h->wa.lds * sizeof(double);
+                 wide_stat_part_bytes(h->wa);
         return SGEP_OK;
     }
     const size_t st = (size_t)h->ldv * h->kp * h->esz;

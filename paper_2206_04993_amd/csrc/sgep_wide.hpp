@@ -62,6 +62,8 @@ constexpr int kRowPad = 128;   // padding of the row dimension (256 with the fou
 // and the reduction buffer fit (KP <= 32) and the minibatch is large enough to
 // keep >= 256 workgroups busy (chosen at init)
 constexpr int kMaxCls = 16;    // LDA classes
+constexpr int kMR = 4;         // minibatch rows per middle-pass workgroup
+constexpr int kMT = 256;       // threads per middle-pass workgroup
 constexpr int kInBF16 = 0;
 constexpr int kInFP8 = 1;
 constexpr int kInF32 = 2;
@@ -86,7 +88,7 @@ struct WideArgs {
     // forward decomposition: block = (split, view, 64-row block), row blocks fastest
     int32_t n_rb, n_split;
     int32_t rbf;                // rows per forward workgroup: 64 or 128, or 256 (k_wfwd4)
-    int32_t nA;                 // k_wmid workgroups: 16 rows each, 4 per 64-row block
+    int32_t nA;                 // k_wmid workgroups: kMR rows each, over the 64-row blocks
     int64_t fs, fw;             // features per split and per wave (multiples of 64)
     int64_t ldr;                // padded rows (multiple of the forward row block) of the partials and of W
     // backward decomposition: workgroups [0, nwg0) cover view 0, the rest view 1;
@@ -108,7 +110,7 @@ struct WideArgs {
     const float *M;             // LDA: ncls x dtot class means
     const float *Mbar;          // LDA: dtot, prior-weighted mean of the class means
     const double *prior;        // LDA: ncls
-    double *spart;              // [Ws][lds], column = backward workgroup
+    double *spart;              // statistics partials, column = backward workgroup (sp_idx)
     double *stot;               // [Ws]
     int32_t lds, Ws;
     Coef *coef;
@@ -193,27 +195,55 @@ template <int KP, int KIND> struct Shape {
 };
 
 // ---------------------------------------------------------------------------
-// Statistics totals: kStatCols columns of the per-workgroup partials of the
-// latest backward pass (or of k_winit), summed over the workgroups in a fixed
-// order (each lane over a fixed strided subset, then a fixed butterfly).
+// Statistics partials: statistic e of workgroup column j sits in group e / 16,
+// a [lds][16] block, so the 16 consecutive statistics of one workgroup are
+// one 128-byte run (written together; read 4 columns x 16 per wave).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t sp_idx(const WideArgs &a, int e, int j)
+{
+    return ((int64_t)(e >> 4) * a.lds + j) * 16 + (e & 15);
+}
+
+// Statistics totals of group qb (kStatCols = 16 statistics): the partials of
+// the latest backward pass (or of k_winit) summed over the nstat columns in a
+// fixed order -- lane (e, q) of wave w over the columns j = 4 w + q (mod 4 NW),
+// ascending, then the four q by a butterfly, then the waves in order.
+// ---------------------------------------------------------------------------
+static_assert(kStatCols == 16, "one 16-statistic group per reduction workgroup");
 template <int NW = kNW>
 __device__ inline void reduce_stats(const WideArgs &a, int qb)
 {
+    __shared__ double part[NW][16];
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
-    for (int cc = w; cc < kStatCols; cc += NW) {
-        const int e = qb * kStatCols + cc;
-        if (e >= a.Ws)
-            break;
-        double s = 0.0;
-        for (int j = lane; j < a.nstat; j += 64)
-            s += a.spart[(int64_t)e * a.lds + j];
+    const int el = lane & 15;
+    const double *p = a.spart + (int64_t)qb * a.lds * 16 + el;
+    constexpr int JS = 4 * NW; // column stride of a lane
+    int j = 4 * w + (lane >> 4);
+    double s = 0.0;
+    for (; j + 3 * JS < a.nstat; j += 4 * JS) {
+        const double x0 = p[(int64_t)j * 16], x1 = p[(int64_t)(j + JS) * 16];
+        const double x2 = p[(int64_t)(j + 2 * JS) * 16], x3 = p[(int64_t)(j + 3 * JS) * 16];
+        s += x0;
+        s += x1;
+        s += x2;
+        s += x3;
+    }
+    for (; j < a.nstat; j += JS)
+        s += p[(int64_t)j * 16];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (lane < 16)
+        part[w][el] = s;
+    __syncthreads();
+    if (tid < 16) {
+        double t = part[0][tid];
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            s += __shfl_xor(s, off);
-        if (lane == 0)
-            a.stot[e] = s;
+        for (int ww = 1; ww < NW; ++ww)
+            t += part[ww][tid];
+        const int e = qb * 16 + tid;
+        if (e < a.Ws)
+            a.stot[e] = t;
     }
 }
 
@@ -563,24 +593,161 @@ __global__ void __launch_bounds__(256) k_wfwd4(WideArgs a)
 template <int KP> constexpr int fwd4_rows() { return KP <= 32 ? 256 : 128; }
 
 // ---------------------------------------------------------------------------
-// Middle pass, 16 rows per workgroup: sum the forward slices in a fixed order
+// Forward products for KP = 64 with the V operand shared through LDS (k_wfwdv,
+// BF16 minibatches): eight waves of 64 rows each (512 rows per workgroup) walk
+// the same feature slice in 64-feature chunks, so each row's 128-byte line is
+// read whole by one chunk (two 32-feature halves, issued together) instead of
+// half now and half after it may have left L2.  For every chunk each wave
+// fetches two of the sixteen V fragments (player tile w / 2, hi for even w,
+// lo for odd, both halves) into a double-buffered LDS ring, so one fragment
+// read from L2 serves 512 rows (k_wfwd4: 128); every wave then reads all
+// sixteen from LDS.  The minibatch loads run one chunk ahead.  Each wave owns
+// its rows, so the partials go straight from the accumulators to memory (no
+// cross-wave sum).  Within a half: lane layout, operands and MFMAs as k_wfwd.
+// ---------------------------------------------------------------------------
+constexpr int kFwdVRows = 512; // rows per k_wfwdv workgroup
+template <int IN>
+__global__ void __launch_bounds__(512) k_wfwdv(WideArgs a)
+{
+    static_assert(IN == kInBF16, "BF16 minibatches");
+    constexpr int KP = 64, NT = 4, TR = 4, NWV = 8;
+    __shared__ u32x4 vb[2][2][2 * NT][64]; // [buffer][half][fragment][lane]
+    const int nfwd = a.n_rb * a.nview * a.n_split;
+    if ((int)blockIdx.x >= nfwd) {
+        reduce_stats<NWV>(a, (int)blockIdx.x - nfwd);
+        return;
+    }
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
+    const int r16 = lane & 15, g = lane >> 4;
+    int blk = blockIdx.x; // XCD-aware order, as k_wfwd
+    if (nfwd % 8 == 0 && (a.nview * a.n_split) % 8 == 0)
+        blk = (blk % 8) * (nfwd / 8) + blk / 8;
+    const int rb = blk % a.n_rb;
+    blk /= a.n_rb;
+    const int v = blk % a.nview;
+    const int s = blk / a.nview;
+    const int64_t dv = a.dv[v];
+    const int64_t ld = v ? a.ldy : a.ldx;
+    const uint8_t *Xb = (const uint8_t *)(v ? a.Y : a.X);
+    const int64_t row0 = (int64_t)rb * kFwdVRows + 64 * w; // this wave's 64 rows
+    const int64_t fbeg = (int64_t)s * a.fs;                  // a multiple of 64
+    const int64_t fend = (fbeg + a.fs < dv) ? fbeg + a.fs : dv;
+    const int nst = fend > fbeg ? (int)((fend - fbeg + 63) / 64) : 0; // workgroup-uniform
+    const int64_t rlast = a.b - 1;
+    uint32_t rok = 0; // bit t: row valid
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+        if (row0 + 16 * t + r16 < a.b)
+            rok |= 1u << t;
+    // the V fragments this wave fetches: player tile w / 2, hi or lo
+    const uint16_t *Vsrc = ((w & 1) ? a.Vl : a.Vh) + a.off[v] +
+                           (int64_t)(16 * (w >> 1) + r16) * a.dtot + 8 * g;
+
+    f32x4 acc[TR][NT];
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+            acc[t][u] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // chunk st: features f0 + 32 h + 8 g .. + 7 of the lane's rows (clamped
+    // in-bounds: a row past the minibatch reads the last row, a feature unit
+    // past the view the last unit; zeroed where consumed) and the wave's two
+    // V fragments.  The V rows are padded to 64 features, so f0 + 64 stays
+    // inside the view's state rows.
+    auto load = [&](int st, u32x4(&xa)[2][TR], u32x4(&vg)[2]) {
+        const int64_t f0 = fbeg + 64 * (int64_t)(st < nst ? st : nst - 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t fx = f0 + 32 * h + 8 * g < dv ? f0 + 32 * h + 8 * g : dv - 8;
+#pragma unroll
+            for (int t = 0; t < TR; ++t) {
+                const int64_t row = (rok >> t) & 1u ? row0 + 16 * t + r16 : rlast;
+                xa[h][t] = *reinterpret_cast<const u32x4 *>(Xb + (row * ld + fx) * 2);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            vg[h] = *reinterpret_cast<const u32x4 *>(Vsrc + f0 + 32 * h);
+    };
+    auto step = [&](int st, const u32x4(&xa)[2][TR], const u32x4(&vg)[2]) {
+        // every wave reaches every barrier: nst is workgroup-uniform
+        u32x4(&buf)[2][2 * NT][64] = vb[st & 1];
+        buf[0][w][lane] = vg[0];
+        buf[1][w][lane] = vg[1];
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const bool fok = fbeg + 64 * (int64_t)st + 32 * h + 8 * g < dv;
+            u32x4 x[TR];
+#pragma unroll
+            for (int t = 0; t < TR; ++t)
+                x[t] = (fok && ((rok >> t) & 1u)) ? xa[h][t] : u32x4{0u, 0u, 0u, 0u};
+            // one player tile at a time: its hi / lo fragments from LDS
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+                const u32x4 vh = buf[h][2 * u][lane], vl = buf[h][2 * u + 1][lane];
+#pragma unroll
+                for (int t = 0; t < TR; ++t)
+                    acc[t][u] = mfma_bf16(x[t], vh, acc[t][u]);
+#pragma unroll
+                for (int t = 0; t < TR; ++t)
+                    acc[t][u] = mfma_bf16(x[t], vl, acc[t][u]);
+            }
+        }
+    };
+    // two register stages: chunk st + 1 is in flight while st is multiplied
+    // (one loop exit, so the loads stay in flight across the back edge)
+    u32x4 xa0[2][TR], xa1[2][TR], vg0[2], vg1[2];
+    if (nst > 0) {
+        load(0, xa0, vg0);
+        int st = 0;
+        for (; st + 2 <= nst; st += 2) {
+            load(st + 1, xa1, vg1);
+            __builtin_amdgcn_sched_barrier(0);
+            step(st, xa0, vg0);
+            load(st + 2, xa0, vg0);
+            __builtin_amdgcn_sched_barrier(0);
+            step(st + 1, xa1, vg1);
+        }
+        if (st < nst)
+            step(st, xa0, vg0);
+    }
+
+    // this wave's 64 x KP partial.  D layout: lane l, register q holds row
+    // 4 (l/16) + q, column l % 16 of each 16 x 16 tile
+    float *out = a.Ppart + (((int64_t)s * a.nview + v) * a.ldr + row0) * KP;
+#pragma unroll
+    for (int t = 0; t < TR; ++t)
+#pragma unroll
+        for (int u = 0; u < NT; ++u)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                out[(16 * t + 4 * g + q) * KP + 16 * u + r16] = acc[t][u][q];
+}
+
+// ---------------------------------------------------------------------------
+// Middle pass, kMR rows per workgroup: sum the forward slices in a fixed order
 // and write row m of W (BF16 hi/lo over the minibatch rows; FP32 input: FP32)
 // = column m of [P | Q] (CCA) or of R = P - (M V)[labels] followed by the
 // one-hot L (LDA, M V from the statistics totals of this iteration); block 0
-// advances t.
+// advances t.  One output element per thread; the slice loads of a thread
+// are issued eight at a time and added in slice order.
 // ---------------------------------------------------------------------------
 template <int KP, int IN, int KIND>
-__global__ void __launch_bounds__(kWT) k_wmid(WideArgs a)
+__global__ void __launch_bounds__(kMT) k_wmid(WideArgs a)
 {
     constexpr bool LDA = KIND == kKindLDA;
     constexpr int NV = LDA ? 1 : 2;
     constexpr int TRI = KP * (KP + 1) / 2;
-    __shared__ float tile[16 * NV * KP];
-    __shared__ int lab[16];
+    constexpr int NE = kMR * NV * KP; // output elements per workgroup
+    __shared__ float tile[NE];
+    __shared__ int lab[kMR];
     const int tid = threadIdx.x;
     const int q = blockIdx.x;
-    const int64_t r0 = (int64_t)q * 16;
-    if (LDA && tid < 16) {
+    const int64_t r0 = (int64_t)q * kMR;
+    if (LDA && tid < kMR) {
         const int64_t row = r0 + tid;
         int l = -1;
         if (row < a.b) {
@@ -593,39 +760,51 @@ __global__ void __launch_bounds__(kWT) k_wmid(WideArgs a)
         lab[tid] = l;
     }
     __syncthreads();
-    for (int e = tid; e < 16 * NV * KP; e += kWT) {
+    for (int e = tid; e < NE; e += kMT) {
         const int rl = e / (NV * KP), rem = e % (NV * KP);
         const int vv = rem / KP, c = rem % KP;
+        const float *pp = a.Ppart + ((int64_t)vv * a.ldr + r0 + rl) * KP + c;
+        const int64_t sstep = (int64_t)a.nview * a.ldr * KP; // between slices
         float s = 0.f;
-        for (int sp = 0; sp < a.n_split; ++sp)
-            s += a.Ppart[(((int64_t)sp * a.nview + vv) * a.ldr + r0 + rl) * KP + c];
+        int sp = 0;
+        for (; sp + 8 <= a.n_split; sp += 8) {
+            float p[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                p[j] = pp[(sp + j) * sstep];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                s += p[j];
+        }
+        for (; sp < a.n_split; ++sp)
+            s += pp[sp * sstep];
         if (LDA && lab[rl] >= 0)
             s = (float)((double)s - a.stot[TRI + KP + lab[rl] * KP + c]);
         tile[e] = s;
     }
     __syncthreads();
     if constexpr (IN == kInF32) {
-        for (int e = tid; e < NV * KP * 16; e += kWT) {
-            const int m = e / 16, rl = e % 16;
+        for (int e = tid; e < NE; e += kMT) {
+            const int m = e / kMR, rl = e % kMR;
             a.Wf[(int64_t)m * a.ldr + r0 + rl] = tile[rl * NV * KP + m];
         }
         if (LDA) {
-            for (int e = tid; e < 16 * 16; e += kWT) {
-                const int c = e / 16, rl = e % 16;
+            for (int e = tid; e < kMaxCls * kMR; e += kMT) {
+                const int c = e / kMR, rl = e % kMR;
                 a.Wf[(int64_t)(KP + c) * a.ldr + r0 + rl] = lab[rl] == c ? 1.f : 0.f;
             }
         }
     } else {
-        for (int e = tid; e < NV * KP * 16; e += kWT) {
-            const int m = e / 16, rl = e % 16;
+        for (int e = tid; e < NE; e += kMT) {
+            const int m = e / kMR, rl = e % kMR;
             uint32_t hi, lo;
             split_bf16(tile[rl * NV * KP + m], hi, lo);
             a.Wh[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)hi;
             a.Wl[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)lo;
         }
         if (LDA) {
-            for (int e = tid; e < 16 * 16; e += kWT) {
-                const int c = e / 16, rl = e % 16;
+            for (int e = tid; e < kMaxCls * kMR; e += kMT) {
+                const int c = e / kMR, rl = e % kMR;
                 a.Wh[(int64_t)(KP + c) * a.ldr + r0 + rl] =
                     lab[rl] == c ? (uint16_t)0x3F80 : (uint16_t)0;
             }
@@ -707,7 +886,7 @@ __device__ __forceinline__ void write_stats(const WideArgs &a, int wg,
             for (int r = 0; r < 4; ++r) {
                 const int i = 16 * u + g + 4 * r, j = 16 * u2 + l16; // FP64 D row (l/16) + 4 r
                 if (j <= i)
-                    a.spart[(int64_t)tri_idx(i, j) * a.lds + wg] = sacc[h][r];
+                    a.spart[sp_idx(a, tri_idx(i, j), wg)] = sacc[h][r];
             }
         } else {
             const int u2 = st - S::NT * (S::NT + 1) / 2;
@@ -715,12 +894,12 @@ __device__ __forceinline__ void write_stats(const WideArgs &a, int wg,
             for (int r = 0; r < 4; ++r) {
                 const int c = g + 4 * r, j = 16 * u2 + l16;
                 if (c < a.ncls)
-                    a.spart[(int64_t)(S::TRI + KP + c * KP + j) * a.lds + wg] = sacc[h][r];
+                    a.spart[sp_idx(a, S::TRI + KP + c * KP + j, wg)] = sacc[h][r];
             }
         }
     }
     if (tid < KP)
-        a.spart[(int64_t)(S::TRI + tid) * a.lds + wg] = nrm;
+        a.spart[sp_idx(a, S::TRI + tid, wg)] = nrm;
 }
 
 // Player-major BF16 hi/lo operand of s_f Vn for the 64 features of a tile

@@ -417,24 +417,29 @@ class LDAClasses:
                 torch.from_numpy(self.sigma).to(device=device, dtype=torch.float32))
 
     def sample_torch(self, n: int, t: int, device, dtype, tables=None, out=None):
-        """n fresh labelled rows drawn on `device` from a torch generator
-        seeded by (seed, t): uniform labels, x = mu_label + sigma * g in FP32
-        (same distribution as ``sample``, different values).  Returns
-        (x in `dtype`, int32 labels); `out` (n x d, `dtype`) receives x when
-        given."""
+        """n fresh labelled rows drawn on `device`, seeded by (seed, t): the
+        class counts are multinomial(n, uniform) (host generator), the rows
+        come grouped by class (a minibatch is an unordered sample, so this is
+        the distribution of n i.i.d. uniform labels), and each row is
+        mu_label + sigma * g with g from a torch generator, formed in FP32 and
+        rounded once to `dtype` (same distribution as ``sample``, different
+        values).  Returns (x in `dtype`, int32 labels on `device`); `out`
+        (n x d, `dtype`) receives x when given."""
         import torch
         g = torch.Generator(device=device)
         g.manual_seed((int(self.seed) * 1_000_003 + 7919 * int(t) + 5) & ((1 << 63) - 1))
         means, sig = tables if tables is not None else self.device_tables(device)
-        lab = torch.randint(0, self.c, (n,), generator=g, device=device, dtype=torch.int64)
-        x = torch.randn((n, self.d), generator=g, device=device, dtype=torch.float32)
-        x.mul_(sig).add_(means.index_select(0, lab))
-        if out is not None:
-            out.copy_(x)
-            x = out
-        else:
-            x = x.to(dtype)
-        return x, lab.to(torch.int32)
+        counts = np.random.default_rng([self.seed + 3, int(t)]).multinomial(
+            n, np.full(self.c, 1.0 / self.c))
+        noise = torch.randn((n, self.d), generator=g, device=device, dtype=torch.float32)
+        x = out if out is not None else torch.empty((n, self.d), device=device, dtype=dtype)
+        r0 = 0
+        for cls, m in enumerate(counts.tolist()):
+            if m:
+                torch.addcmul(means[cls:cls + 1], noise[r0:r0 + m], sig, out=x[r0:r0 + m])
+                r0 += m
+        lab = np.repeat(np.arange(self.c, dtype=np.int32), counts)
+        return x, torch.from_numpy(lab).to(device)
 
 
 @dataclass

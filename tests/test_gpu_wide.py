@@ -160,6 +160,10 @@ TOLF_N = 3e-4
     (4104, 5, 40, 200, "adam"),   # KP 64, several forward slices, ragged last subtile
     (32776, 5, 40, 300, "adam"),  # BF16: four-wave forward, split backward, ragged subtile
     (4104, 5, 40, 300, "sgd"),    # BF16: four-wave forward (128 rows per wave at KP 64)
+    # BF16: 512-row forward workgroups sharing V through LDS (b >= 1024), ragged
+    # last row block; with the split backward at the wider view
+    (4104, 5, 40, 1100, "sgd"),
+    (32776, 5, 40, 1030, "adam"),
 ])
 def test_wide_lda_parity(d, c, k, b, opt, fmt):
     sg = _sg()
