@@ -433,13 +433,14 @@ class LDAClasses:
             n, np.full(self.c, 1.0 / self.c))
         noise = torch.randn((n, self.d), generator=g, device=device, dtype=torch.float32)
         x = out if out is not None else torch.empty((n, self.d), device=device, dtype=dtype)
+        lab = torch.empty((n,), device=device, dtype=torch.int32)
         r0 = 0
         for cls, m in enumerate(counts.tolist()):
             if m:
                 torch.addcmul(means[cls:cls + 1], noise[r0:r0 + m], sig, out=x[r0:r0 + m])
+                lab[r0:r0 + m].fill_(cls)
                 r0 += m
-        lab = np.repeat(np.arange(self.c, dtype=np.int32), counts)
-        return x, torch.from_numpy(lab).to(device)
+        return x, lab
 
 
 @dataclass
