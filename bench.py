@@ -53,12 +53,12 @@ _C3 = dict(kind="cca", dx=8192, dy=8192, k=32, b=4096, ring=4, optimizer="adam",
 # and Adam's per-coordinate steps follow the noise); a slow auxiliary rate
 # gamma averages the noise of [Bv]
 _C5 = dict(kind="lda", dx=65536, dy=0, k=64, b=2048, ring=4, optimizer="sgd",
-           schedule="inv", eta0=4e-3, t0=250.0, gamma=0.03, rho=1e-6, eps_reg=1e-4,
+           schedule="inv", eta0=4e-3, t0=250.0, gamma=0.015, rho=1e-6, eps_reg=1e-4,
            n_classes=10, generator="lda_classes")
 # time to accuracy: graded on the top c - 1 = 9 players (rank of the
 # between-class A), within a bounded number of steps
-_C5_TTA = dict(targets=(1e-1, 5e-2, 2e-2, 1e-2, 5e-3, 1e-3), every=4000, max_steps=80_000,
-               chunk=50)
+_C5_TTA = dict(targets=(1e-1, 5e-2, 2e-2, 1e-2, 5e-3, 2e-3, 1e-3), every=8000,
+               max_steps=96_000, chunk=50)
 
 # (name) -> workload description
 WORKLOADS = {

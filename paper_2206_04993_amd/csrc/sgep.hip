@@ -274,11 +274,19 @@ template <typename T> bool spec_mode(int kp, int mb) { return mb == 1 && kp * (i
 // single pass with helper waves; 4 and 8 slices slower (the extra launch
 // and the partials' round trip outweigh the shorter main loop).  GENERAL
 // handles keep one pass, so that an instance of a batch matches its single
-// handle bit for bit.
+// handle bit for bit.  The split launches wait inside the kernel (k_fwds: the
+// y workgroup of a row tile on the x workgroup's stamped P words; the fused
+// k_bwdp: the last slice of a tile on the other slices and on workgroup 0's
+// coefficient words), so every workgroup of a launch must be resident at
+// once: the bounds below keep k_fwds within 2 * 128 + 1 workgroups (b_max <=
+// 2048) and k_bwdp within 2 * 128 + 8 (at most 128 feature tiles), while
+// the 256 CUs hold at least two workgroups of either kernel each.  Every
+// wait is bounded besides (a give-up sets the status word).
 constexpr int kSplit = 2;
 bool split_mode(const sgep_config &c, int mb, int n_tiles)
 {
-    return c.kind == SGEP_KIND_CCA && mb == 1 && n_tiles <= 128 && c.b_max >= 512;
+    return c.kind == SGEP_KIND_CCA && mb == 1 && n_tiles <= 128 && c.b_max >= 512 &&
+           c.b_max <= 2048;
 }
 
 template <typename T, int KP, int MB, int MODE, bool C>

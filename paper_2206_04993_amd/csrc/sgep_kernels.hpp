@@ -1,8 +1,11 @@
 // sgep_kernels.hpp -- CDNA4 (gfx950) kernels of the stochastic gamma-EigenGame
 // step (Alg. 2 of Gemp, Chen, McWilliams, ICLR 2023, with M = 1).
 //
-// One iteration is two launches and no cross-workgroup synchronisation inside
-// either of them (the kernel boundary is the only barrier):
+// One iteration is two launches in the basic form (below); the row-split form
+// of the CCA handles (k_fwds, k_bwdp) is described at those kernels: there a
+// workgroup may wait on stamped words published by workgroups of lower index
+// in the same launch (bounded polls; a give-up sets the status word).  The
+// basic form has no cross-workgroup wait inside a launch:
 //   k_fwd  P = X V and Q = Y V for a 16-row tile (tall-skinny products on
 //          MFMA, features split over the four waves), stored unnormalised,
 //          plus the tile's partial k x k Gram terms (column-major partials).
@@ -61,7 +64,7 @@ constexpr int kStatusSync = 4; // a workgroup gave up waiting for the coefficien
 // s_waitcnt operand: vector memory counter 0 (stores included), the
 // export and LDS / scalar counters at their maxima (not waited for)
 constexpr int kWaitVm0 = 0x0F70;
-constexpr int kSpinMax = 1 << 20; // polls of a bounded wait (each with a short sleep)
+constexpr int kSpinMax = 1 << 20; // polls a thread may spend on all its bounded waits of a launch (each with a short sleep)
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -631,15 +634,19 @@ template <> struct Stamped<float> {
         __hip_atomic_store(w, ((unsigned long long)st << 32) | __float_as_uint(v),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // false if the bounded wait gave up (value then zero)
-    static __device__ __forceinline__ bool get(const unsigned long long *w, unsigned st, float &v)
+    // false if the bounded wait gave up (value then zero).  budget: the polls
+    // the calling thread has left for all its waits of the launch; once it is
+    // spent every further wait looks once and gives up
+    static __device__ __forceinline__ bool get(const unsigned long long *w, unsigned st, float &v,
+                                               int &budget)
     {
         unsigned long long x;
-        for (int n = 0;; ++n) {
+        for (;;) {
             x = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((unsigned)(x >> 32) == st)
                 break;
-            if (n > kSpinMax) {
+            if (--budget < 0) {
+                budget = 0;
                 v = 0.0f;
                 return false;
             }
@@ -659,15 +666,17 @@ template <> struct Stamped<double> {
                            __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(w + 1, hs | (b >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    static __device__ __forceinline__ bool get(const unsigned long long *w, unsigned st, double &v)
+    static __device__ __forceinline__ bool get(const unsigned long long *w, unsigned st, double &v,
+                                               int &budget)
     {
         unsigned long long x[2];
         for (int h = 0; h < 2; ++h) {
-            for (int n = 0;; ++n) {
+            for (;;) {
                 x[h] = __hip_atomic_load(w + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if ((unsigned)(x[h] >> 32) == st)
                     break;
-                if (n > kSpinMax) {
+                if (--budget < 0) {
+                    budget = 0;
                     v = 0.0;
                     return false;
                 }
@@ -739,6 +748,7 @@ __global__ void __launch_bounds__(kNT) k_fwds(StepArgs a)
     // one contiguous quad-interleaved block
     SGEP_G T *out = (SGEP_G T *)(vy ? a.Q : a.P) + r0 * KP;
     unsigned long long *pw = (unsigned long long *)a.fpart + (int64_t)blk * TS * Stamped<T>::N;
+    int budget = kSpinMax; // polls left for all of this thread's waits
     for (int e = tid; e < TS; e += kNT) {
         const int rq = e / (4 * KP), c = (e / 4) % KP, r = 4 * rq + (e & 3);
         const int ti = r * KP + c;
@@ -748,7 +758,7 @@ __global__ void __launch_bounds__(kNT) k_fwds(StepArgs a)
         if (vy) {
             qt[r][c] = v;
             T p;
-            if (!Stamped<T>::get(pw + e * Stamped<T>::N, stamp, p))
+            if (!Stamped<T>::get(pw + e * Stamped<T>::N, stamp, p, budget))
                 bad = 1;
             pt[r][c] = p;
         } else {
@@ -1495,9 +1505,10 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
             return;
         }
         const unsigned long long *cw = (const unsigned long long *)a.xw + a.xw_coef;
+        int budget = kSpinMax; // polls left for all of this thread's waits
         for (int e = tid; e < NC; e += kNT) {
             T v;
-            if (!Stamped<T>::get(cw + e * NW, st, v))
+            if (!Stamped<T>::get(cw + e * NW, st, v, budget))
                 bad = 1;
             (&C.Tl[0])[e] = v;
         }
@@ -1508,8 +1519,8 @@ __device__ __forceinline__ void bwd_body(const StepArgs &a, int tile, int split 
                 T xa = avt[e], xb = bvt[e];
                 if (sp != split) {
                     const unsigned long long *ow = tw + (int64_t)sp * (2 * FT * KP) * NW;
-                    if (!Stamped<T>::get(ow + e * NW, st, xa) ||
-                        !Stamped<T>::get(ow + (FT * KP + e) * NW, st, xb))
+                    if (!Stamped<T>::get(ow + e * NW, st, xa, budget) ||
+                        !Stamped<T>::get(ow + (FT * KP + e) * NW, st, xb, budget))
                         bad = 1;
                 }
                 pa = sp == 0 ? xa : pa + xa;

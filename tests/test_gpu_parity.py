@@ -1,11 +1,13 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
 Both sides consume the same seeded minibatches (already rounded to the GPU's
-element type) and the same starting points.  Tolerances: FP64 runs agree to 1e-11 on unit players after 100
-iterations; FP32 runs agree to TOL32_1 after one iteration and TOL32_N after
-N iterations, which is the FP32 rounding of length-d and length-b dot
-products (unit round-off 6e-8 times sqrt-length growth, times the step-size
-amplification of the retraction) with a 10x margin."""
+element type) and the same starting points.  Tolerances, each about 10-20x
+the largest difference observed on MI355X: FP64 runs agree to 1e-12 on unit
+players over 100 iterations (observed <= 7e-16); FP32 runs to TOL32_1 after
+one iteration (observed <= 3.4e-8) and TOL32_N after up to 20 iterations
+(observed <= 1.0e-6, the one-row single-player case; others <= 1.1e-7).
+With Adam, elements whose gradient is at the rounding level may step either
+way (tests/parity_bars.py); every other element meets the same bars."""
 import ctypes
 
 import numpy as np
@@ -13,12 +15,20 @@ import pytest
 
 import oracle
 import synth
+from parity_bars import assert_players_close
 
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-11
-TOL32_1 = 2e-5
-TOL32_N = 3e-4
+TOL64 = 1e-12
+TOL32_1 = 5e-7
+TOL32_N = 1e-5
+TOL32_LONG_SGD = 1e-6  # 50 plain-ascent iterations at full size (observed 5e-8)
+# Adam: every element within TOL32_ADAM (observed 1.2e-5 at the full-size
+# medium CCA after one iteration; the renormalisation spreads the steps of
+# rounding-level-gradient elements, which may go either way, over their
+# column), those with a rounding-level gradient within 2 sum eta; the SGD
+# twin of that case meets TOL32_LONG_SGD
+TOL32_ADAM = 5e-5
 
 
 def _torch():
@@ -70,8 +80,10 @@ def run_both(cfg, batches, V0, checkpoints, labels=None):
                            sched["t_c"], sched["T"])
         oracle.gamma_step(pb, st, Xr, Yr, eta_t, cfg.gamma)
         if t in checkpoints:
+            snap = oracle.State(V=st.V.copy(), G=st.G.copy(), t=st.t,
+                                s2=None if st.s2 is None else st.s2.copy())
             out.append((t, solver.vectors(), st.V.copy(), solver.auxiliary(), st.G.copy(),
-                        solver.eigvals(), st.eigvals()))
+                        solver.eigvals(), st.eigvals(), snap))
     assert solver.step_count() == len(batches)
     solver.close()
     return out
@@ -79,6 +91,11 @@ def run_both(cfg, batches, V0, checkpoints, labels=None):
 
 def _maxdiff(a, b):
     return float(np.abs(a - b).max())
+
+
+def _eta_of(cfg, t):
+    h = _hyper_to_oracle(cfg)
+    return oracle.eta(h["schedule"], t, h["eta0"], h["eta_T"], h["t0"], h["t_c"], h["T"])
 
 
 def _cca_batches(gen, n, b):
@@ -97,7 +114,7 @@ def test_f64_tiny_cca_trajectory():
     batches = [pool.batch(t, 128) for t in range(1, 101)]
     V0 = synth.initial_players(16, 4, 0)
     res = run_both(cfg, batches, V0, {1, 10, 100})
-    for t, vg, vo, gg, go, lg, lo in res:
+    for t, vg, vo, gg, go, lg, lo, so in res:
         print(f"f64 t={t} dV={_maxdiff(vg, vo):.2e} dG={_maxdiff(gg, go):.2e} "
               f"dlam={_maxdiff(lg, lo):.2e}")
         assert _maxdiff(vg, vo) < TOL64
@@ -149,7 +166,7 @@ def test_f32_cca_parity(dx, dy, k, b):
     batches = _cca_batches(gen, 20, b)
     V0 = rng.standard_normal((dx + dy, k))
     res = run_both(cfg, batches, V0, {1, 20})
-    for t, vg, vo, gg, go, lg, lo in res:
+    for t, vg, vo, gg, go, lg, lo, so in res:
         dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
         print(f"f32 cca {dx},{dy},k={k},b={b} t={t} dV={dv:.2e} dG={dg:.2e}")
         tol = TOL32_1 if t == 1 else TOL32_N
@@ -166,12 +183,12 @@ def test_f32_cca_adam_parity():
     batches = _cca_batches(gen_small, 20, 512)
     V0 = synth.initial_players(176, 8, 4)
     res = run_both(cfg, batches, V0, {1, 20})
-    for t, vg, vo, gg, go, lg, lo in res:
+    for t, vg, vo, gg, go, lg, lo, so in res:
         dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
         print(f"f32 cca adam t={t} dV={dv:.2e} dG={dg:.2e}")
-        # Adam divides by sqrt(second moment): near-zero moments amplify rounding
-        tol = 5 * (TOL32_1 if t == 1 else TOL32_N)
-        assert dv < tol and dg < tol
+        assert_players_close(vg, so, TOL32_ADAM, adam=True,
+                             eta_sum=sum(_eta_of(cfg, i) for i in range(1, t + 1)))
+        assert dg < TOL32_ADAM
     del gen
 
 
@@ -185,7 +202,7 @@ def test_f32_general_parity(d, k, b):
     batches = [gen.batch(t, b) for t in range(1, 21)]
     V0 = synth.initial_players(d, k, 7)
     res = run_both(cfg, batches, V0, {1, 20})
-    for t, vg, vo, gg, go, lg, lo in res:
+    for t, vg, vo, gg, go, lg, lo, so in res:
         dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
         print(f"f32 general d={d} k={k} t={t} dV={dv:.2e} dG={dg:.2e}")
         tol = TOL32_1 if t == 1 else TOL32_N
@@ -200,7 +217,7 @@ def test_f64_general_kp32_parity():
                          eps_reg=1e-3)
     batches = [gen.batch(t, 100) for t in range(1, 31)]
     res = run_both(cfg, batches, synth.initial_players(80, 24, 2), {30})
-    for t, vg, vo, gg, go, lg, lo in res:
+    for t, vg, vo, gg, go, lg, lo, so in res:
         print(f"f64 general kp32 t={t} dV={_maxdiff(vg, vo):.2e}")
         assert _maxdiff(vg, vo) < TOL64
         assert _maxdiff(gg, go) < TOL64 * max(1.0, np.abs(go).max())
@@ -220,7 +237,7 @@ def test_f64_general_two_stage_coefficients():
     probe.close()
     batches = [gen.batch(t, n) for t, n in enumerate([1024, 1000, 17, 600] * 4, start=1)]
     res = run_both(cfg, batches, synth.initial_players(80, 24, 2), {1, 16})
-    for t, vg, vo, gg, go, lg, lo in res:
+    for t, vg, vo, gg, go, lg, lo, so in res:
         print(f"f64 general two-stage coefficients t={t} dV={_maxdiff(vg, vo):.2e}")
         assert _maxdiff(vg, vo) < TOL64
         assert _maxdiff(gg, go) < TOL64 * max(1.0, np.abs(go).max())
@@ -245,7 +262,7 @@ def test_cca_row_split_parity(dtype, k):
     sizes = [1024, 1000, 17, 600, 513, 1, 777, 1024]
     batches = [gen.batch(t, n) for t, n in enumerate(sizes, start=1)]
     res = run_both(cfg, batches, synth.initial_players(dx + dy, k, 3), {1, len(sizes)})
-    for t, vg, vo, gg, go, lg, lo in res:
+    for t, vg, vo, gg, go, lg, lo, so in res:
         dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
         print(f"{dtype} cca row split k={k} t={t} dV={dv:.2e} dG={dg:.2e}")
         tol = TOL64 if dtype == "f64" else (TOL32_1 if t == 1 else TOL32_N)
@@ -265,11 +282,28 @@ def test_f32_medium_cca_full_size():
                          t0=3000.0, gamma=0.3, rho=1e-6)
     batches = _cca_batches(gen, 5, 1024)
     res = run_both(cfg, batches, synth.initial_players(1024, 16, 0), {1, 5})
-    for t, vg, vo, gg, go, lg, lo in res:
+    for t, vg, vo, gg, go, lg, lo, so in res:
         dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
         print(f"f32 medium cca t={t} dV={dv:.2e} dG={dg:.2e} dlam={_maxdiff(lg, lo):.2e}")
-        tol = 5 * (TOL32_1 if t == 1 else TOL32_N)
-        assert dv < tol and dg < tol
+        assert_players_close(vg, so, TOL32_ADAM, adam=True,
+                             eta_sum=sum(_eta_of(cfg, i) for i in range(1, t + 1)))
+        assert dg < TOL32_ADAM
+
+
+def test_f32_medium_cca_full_size_sgd_50():
+    """The same full-size medium CCA with plain ascent over 50 iterations, at
+    the tighter bar TOL32_LONG_SGD on every element (no Adam amplification)."""
+    sg = _sg()
+    gen = synth.medium_cca(0)
+    cfg = sg.make_config(sg.SGEP_KIND_CCA, sg.SGEP_F32, 16, 512, 512, 1024,
+                         optimizer=sg.SGEP_SGD, schedule=sg.SGEP_SCHED_INV, eta0=0.05,
+                         t0=100.0, gamma=0.3, rho=1e-6)
+    batches = _cca_batches(gen, 50, 1024)
+    res = run_both(cfg, batches, synth.initial_players(1024, 16, 0), {1, 10, 50})
+    for t, vg, vo, gg, go, lg, lo, so in res:
+        dv, dg = _maxdiff(vg, vo), _maxdiff(gg, go) / max(1.0, np.abs(go).max())
+        print(f"f32 medium cca sgd t={t} dV={dv:.2e} dG={dg:.2e} dlam={_maxdiff(lg, lo):.2e}")
+        assert dv < TOL32_LONG_SGD and dg < TOL32_LONG_SGD
 
 
 # --------------------------------------------------------------------------- #
