@@ -46,7 +46,8 @@ PEAK_HBM_GBS = 8000.0
 
 _C3 = dict(kind="cca", dx=8192, dy=8192, k=32, b=4096, ring=4, optimizer="adam",
            schedule="inv", eta0=1e-3, t0=3000.0, gamma=0.3, rho=1e-6,
-           generator="cca_activation")
+           generator="cca_activation",
+           tta=dict(targets=(5e-3, 2e-3, 1e-3, 5e-4), every=500, max_steps=30_000, chunk=25))
 # the large LDA problem: plain ascent (Alg. 2) with the inverse-time
 # schedule, which reaches a given subspace error in fewer steps than Adam on
 # this problem (d / b = 32: the minibatch within-class covariance is noisy,

@@ -129,7 +129,10 @@ typedef struct sgep_config {
                         * iteration (the mean of the iteration's start), and the
                         * mean then moves toward the minibatch mean at rate gamma
                         * (starting at 0).  F64 / F32 CCA and GENERAL single
-                        * handles; SGEP_EUNSUPPORTED elsewhere */
+                        * handles, and BF16 / FP8-e4m3 CCA (there the products
+                        * are corrected by the rank-one terms, X itself enters
+                        * the arithmetic exactly); SGEP_EUNSUPPORTED elsewhere
+                        * (LDA, ICA, batches) */
     double nu;         /* Alg. 3: upper bound of lambda_max(B), nu > rho; unused
                         * (any value) with smooth = 0 */
 } sgep_config;

@@ -83,7 +83,8 @@ struct sgep_handle_s {
     Coef *coef = nullptr;
     void *cpre = nullptr; // coefficient block of the iteration (k_coef)
     int nsplit = 1;        // row slices of the backward products (1: one pass)
-    void *mu = nullptr;    // running means of the views (centring): 2 ldv elements
+    void *mu = nullptr;    // running means of the views (centring): 2 ldv elements (large-d: dtot FP32)
+    void *xsum = nullptr;  // large-d split backward with centring: minibatch column sums (dtot FP32)
     void *S1 = nullptr, *S2 = nullptr; // ICA: first backward pass products
     double *bb_part = nullptr;         // ICA: S1^T S1 tile partials
     double *gsum = nullptr; // column totals of the Gram partials (two-stage coefficients)
@@ -153,7 +154,7 @@ void free_all(sgep_handle *h)
                     h->stat_part, h->stat_tot, h->readout, h->coef, h->Vh, h->Vl, h->colscale,
                     h->Ppart, h->Wh, h->Wl, h->Mcls, h->Mbar, h->prior, h->cpre, h->bpart,
                     h->mu,   h->S1, h->S2,     h->bb_part, h->gsum, h->fpart,
-                    h->xw, h->cflag, h->Vf, h->Wf, h->prod, h->ctile};
+                    h->xw, h->cflag, h->Vf, h->Wf, h->prod, h->ctile, h->xsum};
     for (void *p : ptrs)
         if (p)
             (void)hipFree(p);
@@ -211,8 +212,8 @@ sgep_status check_cfg(const sgep_config *c)
         return SGEP_EINVAL;
     if ((c->smooth != 0 && c->smooth != 1) || (c->center != 0 && c->center != 1))
         return SGEP_EINVAL;
-    if (c->center && (narrow || lda || ica))
-        return SGEP_EUNSUPPORTED; // centring: F64 / F32 CCA and GENERAL
+    if (c->center && (lda || ica || (narrow && c->kind != SGEP_KIND_CCA)))
+        return SGEP_EUNSUPPORTED; // centring: F64 / F32 CCA and GENERAL, BF16 / FP8 CCA
     if (c->smooth && !(c->rho > 0.0 && c->nu > c->rho && std::isfinite(c->nu)))
         return SGEP_EINVAL;
     if (c->kind == SGEP_KIND_CCA && c->eps_reg != 0.0)
@@ -700,7 +701,9 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     // workgroup (64-feature tile) of the split backward
     a.nstat = ft == kFT ? a.nwg : (int32_t)(nsubt * (ft / kFT));
     a.lds = (a.nstat + 1) / 2 * 2;
-    a.Ws = (int32_t)(KP * (KP + 1) / 2 + KP + (lda ? a.ncls * KP : 0));
+    // statistics: v_i^T G_j (lower triangle), ||v_i||^2, then LDA the class
+    // means times v_i, CCA each view's running mean times v_i (centring)
+    a.Ws = (int32_t)(KP * (KP + 1) / 2 + KP + (lda ? a.ncls * KP : 2 * KP));
     const int64_t MW = lda ? KP + 16 : 2 * KP;
 
     bool ok = true;
@@ -739,7 +742,11 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
         const int64_t mwa = lda ? KP : 2 * KP; // rows of W in the products
         alloc(&h->prod, (size_t)a.dtot * mwa * sizeof(float));
         alloc(&h->ctile, (size_t)(KP * KP + 4 * KP + 2 * kMaxCls * KP) * sizeof(float));
+        if (c.center)
+            alloc(&h->xsum, (size_t)a.dtot * sizeof(float));
     }
+    if (c.center)
+        alloc(&h->mu, (size_t)a.dtot * sizeof(float));
     if (lda) {
         alloc(&h->Mcls, (size_t)a.ncls * a.dtot * sizeof(float));
         alloc(&h->Mbar, (size_t)a.dtot * sizeof(float));
@@ -786,6 +793,9 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.adam_b1 = c.adam_b1;
     a.adam_b2 = c.adam_b2;
     a.adam_eps = c.adam_eps;
+    a.center = c.center;
+    a.mu = (float *)h->mu;
+    a.xsum = (float *)h->xsum;
 
     // starting players: unit columns (FP64 norms), FP32, state rows of the views
     auto row_of = [&](int64_t f) { return f < c.dx ? f : a.off[1] + (f - c.dx); };
@@ -817,6 +827,8 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     if (h->Am)
         hok = hok && hipMemsetAsync(h->Am, 0, st, h->stream) == hipSuccess &&
               hipMemsetAsync(h->As, 0, st, h->stream) == hipSuccess;
+    if (h->mu) // the running means start at zero
+        hok = hok && hipMemsetAsync(h->mu, 0, (size_t)a.dtot * sizeof(float), h->stream) == hipSuccess;
     if (fp8) {
         hs.assign((size_t)a.dtot, 0.f);
         for (int64_t f = 0; f < d; ++f)
@@ -888,8 +900,8 @@ sgep_status step_wide(sgep_handle *h, const void *X, int64_t ldx, const void *Y,
 // device arrays of a checkpoint after the header and the coefficient block
 struct StateLayout {
     int n = 0;
-    void *ptr[8];
-    size_t bytes[8];
+    void *ptr[10];
+    size_t bytes[10];
     void add(void *p, size_t b)
     {
         if (p) {
@@ -914,6 +926,7 @@ StateLayout state_layout(const sgep_handle *h)
         L.add(h->Vl, op);
         L.add(h->Vf, 2 * op); // FP32 input: in place of Vh, Vl
         L.add(h->stat_part, wide_stat_part_bytes(h->wa));
+        L.add(h->mu, (size_t)h->wa.dtot * sizeof(float)); // centring: running means
     } else {
         const size_t st = (size_t)h->ldv * h->kp * h->esz;
         L.add(h->V, st);
@@ -1399,6 +1412,17 @@ sgep_status sgep_means(sgep_handle *h, double *out)
         return SGEP_EINVAL;
     if (h->poisoned)
         return SGEP_EPOISONED;
+    if (h->wide) { // FP32 at the state rows of the views
+        std::vector<float> mb((size_t)h->wa.dtot);
+        HIPCHK(hipMemcpyAsync(mb.data(), h->mu, mb.size() * sizeof(float), hipMemcpyDeviceToHost,
+                              h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int64_t f = 0; f < h->cfg.dx; ++f)
+            out[f] = (double)mb[(size_t)(h->wa.off[0] + f)];
+        for (int64_t f = 0; f < h->cfg.dy; ++f)
+            out[h->cfg.dx + f] = (double)mb[(size_t)(h->wa.off[1] + f)];
+        return SGEP_OK;
+    }
     const int64_t n = 2 * h->ldv;
     std::vector<unsigned char> buf((size_t)n * h->esz);
     HIPCHK(hipMemcpyAsync(buf.data(), h->mu, buf.size(), hipMemcpyDeviceToHost, h->stream));
@@ -1438,7 +1462,7 @@ sgep_status sgep_state_size(const sgep_handle *h, size_t *bytes)
         const size_t st = (size_t)h->wa.dtot * h->kp * sizeof(float);
         const size_t op = (size_t)h->kp * h->wa.dtot * sizeof(uint16_t);
         *bytes = sizeof(StateHeader) + sizeof(Coef) + st * (h->Am ? 4 : 2) + 2 * op +
-                 wide_stat_part_bytes(h->wa);
+                 wide_stat_part_bytes(h->wa) + (h->mu ? (size_t)h->wa.dtot * sizeof(float) : 0);
         return SGEP_OK;
     }
     const size_t st = (size_t)h->ldv * h->kp * h->esz;

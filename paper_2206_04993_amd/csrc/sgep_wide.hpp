@@ -118,6 +118,11 @@ struct WideArgs {
     double eta0, eta_T, t0, t_c, T, gamma, rho, eps_reg, adam_b1, adam_b2, adam_eps;
     int32_t smooth;          // Alg. 3 estimate of v_j^T B v_j instead of the clip
     double lrho, lspan;      // Alg. 3: log rho, log nu - log rho
+    // running-mean centring (CCA): mu, FP32 running means of the views at the
+    // state rows (s_f-scaled true values, zero on padding); xsum, the split
+    // backward's minibatch column sums (raw codes) from k_wprod to k_wepi
+    int32_t center;
+    float *mu, *xsum;
 };
 
 __device__ inline double eta_sched(const WideArgs &a, double t)
@@ -185,13 +190,16 @@ template <int KP, int KIND> struct Shape {
     static constexpr int SLOT = kFT * MWP;             // floats per reduction slot
     static constexpr int GLD = KP + 4;                 // LDS row of the old auxiliary tile
     static constexpr int VLD = KP + 1;                 // LDS row of the new V, G tiles
-    // Gram terms per wave (CCA: P^T Q, then sum P^2 and sum Q^2 per lane
-    // group; LDA: L^T R, then sum R^2 per lane group) and in total
-    static constexpr int GW = LDA ? 16 * KP + 4 * KP : KP * KP + 8 * KP;
-    static constexpr int GT = LDA ? 16 * KP + KP : KP * KP + 2 * KP;
+    // Gram terms per wave (CCA: P^T Q, then per lane group sum P^2, sum Q^2,
+    // sum P and sum Q -- the column sums of the centring; LDA: L^T R, then
+    // sum R^2 per lane group) and in total
+    static constexpr int GW = LDA ? 16 * KP + 4 * KP : KP * KP + 16 * KP;
+    static constexpr int GT = LDA ? 16 * KP + KP : KP * KP + 4 * KP;
     static constexpr int NG = LDA ? NT : NT * NT;      // Gram MFMA tiles per wave
-    // statistics tiles: lower 16x16 tiles of V^T G, then (LDA) M V tiles
-    static constexpr int NST = NT * (NT + 1) / 2 + (LDA ? NT : 0);
+    // statistics tiles: lower 16x16 tiles of V^T G, then the mean tiles: LDA
+    // the class means times V (16 rows), CCA the view's running mean times V
+    // (row 0; zero without centring)
+    static constexpr int NST = NT * (NT + 1) / 2 + NT;
 };
 
 // ---------------------------------------------------------------------------
@@ -780,6 +788,8 @@ __global__ void __launch_bounds__(kMT) k_wmid(WideArgs a)
             s += pp[sp * sstep];
         if (LDA && lab[rl] >= 0)
             s = (float)((double)s - a.stot[TRI + KP + lab[rl] * KP + c]);
+        if (!LDA && a.center && r0 + rl < a.b) // (X - 1 mu^T) V = X V - 1 (mu^T V)
+            s = (float)((double)s - a.stot[TRI + KP + vv * KP + c]);
         tile[e] = s;
     }
     __syncthreads();
@@ -827,7 +837,7 @@ template <int KP, int KIND> struct StatTiles {
 
 template <int KP, int KIND>
 __device__ __forceinline__ void tile_stats(const float *Vn, const float *Gn, const float *Mt,
-                                           f64x4 (&sacc)[StatTiles<KP, KIND>::H])
+                                           f64x4 (&sacc)[StatTiles<KP, KIND>::H], bool mv_on)
 {
     typedef Shape<KP, KIND> S;
     constexpr int VLD = S::VLD;
@@ -851,12 +861,16 @@ __device__ __forceinline__ void tile_stats(const float *Vn, const float *Gn, con
             mv = true;
             u = 0;
             u2 = st - S::NT * (S::NT + 1) / 2;
+            if (!mv_on)
+                continue; // wave-uniform: CCA without centring (its mean terms stay 0)
         }
         f64x4 acc = sacc[h];
 #pragma unroll 4
         for (int k4 = 0; k4 < kFT; k4 += 4) {
             const int fl = k4 + g;
-            const double av = mv ? (double)Mt[l16 * kFT + fl] : (double)Vn[fl * VLD + 16 * u + l16];
+            // mean tiles: LDA rows are the 16 class means; CCA has row 0 only
+            const double av = mv ? ((S::LDA || l16 == 0) ? (double)Mt[(S::LDA ? l16 : 0) * kFT + fl] : 0.0)
+                                 : (double)Vn[fl * VLD + 16 * u + l16];
             const double bv = mv ? (double)Vn[fl * VLD + 16 * u2 + l16] : (double)Gn[fl * VLD + 16 * u2 + l16];
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
@@ -866,7 +880,8 @@ __device__ __forceinline__ void tile_stats(const float *Vn, const float *Gn, con
 
 template <int KP, int KIND>
 __device__ __forceinline__ void write_stats(const WideArgs &a, int wg,
-                                            const f64x4 (&sacc)[StatTiles<KP, KIND>::H], double nrm)
+                                            const f64x4 (&sacc)[StatTiles<KP, KIND>::H], double nrm,
+                                            int v)
 {
     typedef Shape<KP, KIND> S;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -893,8 +908,13 @@ __device__ __forceinline__ void write_stats(const WideArgs &a, int wg,
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int c = g + 4 * r, j = 16 * u2 + l16;
-                if (c < a.ncls)
-                    a.spart[sp_idx(a, S::TRI + KP + c * KP + j, wg)] = sacc[h][r];
+                if (S::LDA) {
+                    if (c < a.ncls)
+                        a.spart[sp_idx(a, S::TRI + KP + c * KP + j, wg)] = sacc[h][r];
+                } else if (c == 0) { // CCA: mu_v^T v_j of this view, 0 for the other view
+                    a.spart[sp_idx(a, S::TRI + KP + v * KP + j, wg)] = sacc[h][r];
+                    a.spart[sp_idx(a, S::TRI + KP + (1 - v) * KP + j, wg)] = 0.0;
+                }
             }
         }
     }
@@ -1009,11 +1029,16 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
     __shared__ float cSp[NC * KP], cU[NC * KP];
     __shared__ double dMc[NC * KP];
     __shared__ float Mt[NC * kFT], Mb[LDA ? kFT : 1];
+    // centring (CCA): the tile's running means, the W column sums, the
+    // minibatch column sums of the subtile (per wave and lane group, then total)
+    __shared__ float muT[LDA ? 1 : kFT], cP[LDA ? 1 : KP], cQ[LDA ? 1 : KP];
+    __shared__ float xsp[LDA ? 1 : kBW * 4 * FT], xcs[LDA ? 1 : FT];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
     const int l16 = lane & 15, g = lane >> 4;
     const int wg = xcd_tile(blockIdx.x, gridDim.x);
+    const bool CEN = !LDA && a.center != 0; // workgroup-uniform
     int v, sub0, sub1;
     wg_range(a, wg, v, sub0, sub1);
     const int64_t dv = a.dv[v];
@@ -1053,10 +1078,14 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
 #pragma unroll
         for (int u = 0; u < NG; ++u)
             gacc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
-        float dP[NT], dQ[NT];
+        float dP[NT], dQ[NT], sP[NT], sQ[NT]; // sums of squares; column sums (centring)
 #pragma unroll
         for (int u = 0; u < NT; ++u)
-            dP[u] = dQ[u] = 0.f;
+            dP[u] = dQ[u] = sP[u] = sQ[u] = 0.f;
+        float xs[NCF]; // centring: this lane's column sums of the minibatch (raw codes)
+#pragma unroll
+        for (int c = 0; c < NCF; ++c)
+            xs[c] = 0.f;
 
         // Loads are unconditional, from clamped in-bounds addresses (a chunk past
         // the minibatch reads the last chunk, a row past it the last row, a
@@ -1198,6 +1227,13 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
                         }
                         col[j] = rvalid[j] ? x : 0u;
                     }
+                    if (CEN) {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) {
+                            xs[2 * p] += bf16_val(col[j] & 0xFFFFu);
+                            xs[2 * p + 1] += bf16_val(col[j] >> 16);
+                        }
+                    }
                     // B operands: the BF16 of rows 2q, 2q + 1 in dword q
                     u32x4 b0, b1;
 #pragma unroll
@@ -1247,6 +1283,10 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
                                                  bf16_val(B.wl[NT + u][q] & 0xFFFFu);
                                 const float q1 = bf16_val(B.wh[NT + u][q] >> 16) + bf16_val(B.wl[NT + u][q] >> 16);
                                 dQ[u] += q0 * q0 + q1 * q1;
+                                if (CEN) {
+                                    sP[u] += p0 + p1;
+                                    sQ[u] += q0 + q1;
+                                }
                             }
                         }
                 }
@@ -1268,6 +1308,21 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
             }
         }
 
+        if (CEN) { // the subtile's minibatch column sums: waves in order, then lane groups
+#pragma unroll
+            for (int c = 0; c < NCF; ++c)
+                xsp[(w * 4 + g) * FT + NCF * l16 + c] = xs[c];
+            __syncthreads();
+            for (int f = tid; f < FT; f += kBT) {
+                float t = 0.f;
+                for (int q = 0; q < kBW * 4; ++q)
+                    t += xsp[q * FT + f];
+                xcs[f] = t;
+                if (PART)
+                    a.xsum[a.off[v] + fv0 + f] = t;
+            }
+            __syncthreads();
+        }
         for (int hh = 0; hh < NH; ++hh) { // 64-feature halves
             // the old auxiliary tile of this subtile, into registers now (written
             // to LDS once the products and Gram terms no longer need the space)
@@ -1349,6 +1404,8 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
                     for (int u = 0; u < NT; ++u) {
                         gw[KP * KP + g * KP + 16 * u + l16] = dP[u];
                         gw[KP * KP + 4 * KP + g * KP + 16 * u + l16] = dQ[u];
+                        gw[KP * KP + 8 * KP + g * KP + 16 * u + l16] = sP[u];
+                        gw[KP * KP + 12 * KP + g * KP + 16 * u + l16] = sQ[u];
                     }
                 } else {
 #pragma unroll
@@ -1376,6 +1433,10 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
                     gd[e] = s;
                 }
                 __syncthreads();
+                if (!LDA && tid < KP) { // centring: column sums of P and Q over the rows
+                    cP[tid] = (float)gd[KP * KP + 2 * KP + tid];
+                    cQ[tid] = (float)gd[KP * KP + 3 * KP + tid];
+                }
 
                 // ---- k x k coefficients (identical in every workgroup) ----
                 double *ss = reinterpret_cast<double *>(ext);
@@ -1522,6 +1583,10 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
                         ct[KP * KP + 4 * KP + e] = cSp[e];
                         ct[KP * KP + 4 * KP + NC * KP + e] = cU[e];
                     }
+                else if (tid < KP) { // the column sums for the centring
+                    ct[KP * KP + 4 * KP + tid] = cP[tid];
+                    ct[KP * KP + 5 * KP + tid] = cQ[tid];
+                }
                 return;
             }
 
@@ -1540,6 +1605,8 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
                 for (int e = tid; e < kFT; e += kBT)
                     Mb[e] = a.Mbar[frow + e];
             }
+            if (CEN && tid < kFT)
+                muT[tid] = a.mu[frow + tid];
             __syncthreads();
             for (int tt = w; tt < 4 * NT; tt += kBW) {
                 const int fb = tt / NT, pb = tt % NT;
@@ -1584,8 +1651,13 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
                             const float sf = IN == kInFP8 ? a.colscale[frow + fl] : 1.f;
                             const float rawA = v == 0 ? pr[KP + i] : pr[i];
                             const float rawB = v == 0 ? pr[i] : pr[KP + i];
-                            av = rawA * sf * inv * ibf;
-                            bv = rawB * sf * inv * ibf;
+                            float rA = rawA * sf, rB = rawB * sf;
+                            if (CEN) { // (X - 1 mu^T)^T W = X^T W - mu (1^T W)
+                                rA -= muT[fl] * (v == 0 ? cQ[i] : cP[i]);
+                                rB -= muT[fl] * (v == 0 ? cP[i] : cQ[i]);
+                            }
+                            av = rA * inv * ibf;
+                            bv = rB * inv * ibf;
                         } else {
                             bv = (pr[i] - e2[r]) * inv * ibf + eps * vh;
                             av = e3[r] - Mb[fl] * cUc[i];
@@ -1609,14 +1681,23 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
                     Gn[fl * VLD + i] = gn;
                 }
             }
+            if (CEN && tid < kFT) { // mu += gamma (column mean - mu); Mt row 0 for the statistics
+                float mn = 0.f;
+                if (fvh + tid < dv) {
+                    const float sf = IN == kInFP8 ? a.colscale[frow + tid] : 1.f;
+                    mn = muT[tid] + gam * (xcs[kFT * hh + tid] * sf * ibf - muT[tid]);
+                }
+                a.mu[frow + tid] = mn;
+                Mt[tid] = mn;
+            }
             __syncthreads();
             write_vop<KP, KIND, IN>(a, Vn, frow);
-            tile_stats<KP, KIND>(Vn, Gn, Mt, sacc);
+            tile_stats<KP, KIND>(Vn, Gn, Mt, sacc, LDA || CEN);
             tile_norms<KP, KIND>(Vn, nrm);
             __syncthreads();
         }
     }
-    write_stats<KP, KIND>(a, wg, sacc, nrm);
+    write_stats<KP, KIND>(a, wg, sacc, nrm, v);
 }
 
 template <int KP, int IN, int KIND, int OPT>
@@ -1635,7 +1716,7 @@ __global__ void __launch_bounds__(kBT) k_wprod(WideArgs a)
 // m_A - c, sum_c pi_c U (KP each), and (LDA) the class sums S and U.
 template <int KP, int KIND> constexpr int ctile_floats()
 {
-    return KP * KP + 4 * KP + (KIND == kKindLDA ? 2 * kMaxCls * KP : 0);
+    return KP * KP + 4 * KP + (KIND == kKindLDA ? 2 * kMaxCls * KP : 2 * KP);
 }
 
 // ---------------------------------------------------------------------------
@@ -1658,6 +1739,7 @@ __global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
     __shared__ float cInv[KP], cMB[KP], cMAc[KP], cUc[KP];
     __shared__ float cSp[NC * KP], cU[NC * KP];
     __shared__ float Mt[NC * kFT], Mb[LDA ? kFT : 1];
+    __shared__ float muT[LDA ? 1 : kFT], xcs[LDA ? 1 : kFT], cP[LDA ? 1 : KP], cQ[LDA ? 1 : KP];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6); // wave index, scalar
@@ -1668,6 +1750,7 @@ __global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
     const int64_t fvh = (int64_t)kFT * (v ? wg - nt0 : wg);
     const int64_t dv = a.dv[v];
     const int64_t frow = a.off[v] + fvh;
+    const bool CEN = !LDA && a.center != 0; // centring (CCA): rank-one corrections
     const double t = a.coef->t;
     const double ib = 1.0 / (double)a.b;
     const float eta = (float)eta_sched(a, t), gam = (float)a.gamma, ibf = (float)ib;
@@ -1685,6 +1768,7 @@ __global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
     constexpr int NPR = LDA ? 1 : 2;       // products per element: B_t V (LDA); X^T Q, X^T P
     const float *ct = a.ctile;
     float rT[PT], rG[PG], rS[PS], rU[PS], rM[PM], rMb = 0.f, rc[4] = {0.f, 0.f, 0.f, 0.f};
+    float rmu = 0.f, rxs = 0.f, rcs = 0.f; // centring: mean, column sum, W column sum
     float vold_[NTT][4], prr[NTT][4][NPR];
 #pragma unroll
     for (int q = 0; q < PT; ++q)
@@ -1693,6 +1777,14 @@ __global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             rc[j] = ct[KP * KP + j * KP + tid]; // 1/||v||, m_B, m_A - c, sum_c pi_c U
+    }
+    if (CEN) {
+        if (tid < kFT) {
+            rmu = a.mu[frow + tid];
+            rxs = a.xsum[frow + tid];
+        }
+        if (tid < 2 * KP) // sum P (tid < KP), then sum Q
+            rcs = ct[KP * KP + 4 * KP + tid];
     }
     if (LDA) {
 #pragma unroll
@@ -1754,6 +1846,16 @@ __global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
         const int e = tid + q * kBT;
         Gold[(e / KP) * GLD + e % KP] = rG[q];
     }
+    if (CEN) {
+        if (tid < kFT) {
+            muT[tid] = rmu;
+            xcs[tid] = rxs;
+        }
+        if (tid < KP)
+            cP[tid] = rcs;
+        else if (tid < 2 * KP)
+            cQ[tid - KP] = rcs;
+    }
     __syncthreads();
 
 #pragma unroll
@@ -1797,8 +1899,13 @@ __global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
                     // view x: A from X^T Q, B from X^T P; view y: the reverse
                     const float rawA = v == 0 ? prr[h][r][0] : prr[h][r][NPR - 1];
                     const float rawB = v == 0 ? prr[h][r][NPR - 1] : prr[h][r][0];
-                    av = rawA * sf * inv * ibf;
-                    bv = rawB * sf * inv * ibf;
+                    float rA = rawA * sf, rB = rawB * sf;
+                    if (CEN) { // (X - 1 mu^T)^T W = X^T W - mu (1^T W)
+                        rA -= muT[fl] * (v == 0 ? cQ[i] : cP[i]);
+                        rB -= muT[fl] * (v == 0 ? cP[i] : cQ[i]);
+                    }
+                    av = rA * inv * ibf;
+                    bv = rB * inv * ibf;
                 } else {
                     bv = (prr[h][r][0] - e2[r]) * inv * ibf + eps * vh;
                     av = e3[r] - Mb[fl] * cUc[i];
@@ -1822,6 +1929,15 @@ __global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
             Gn[fl * VLD + i] = gn;
         }
     }
+    if (CEN && tid < kFT) { // mu += gamma (column mean - mu); Mt row 0 for the statistics
+        float mn = 0.f;
+        if (fvh + tid < dv) {
+            const float sf = IN == kInFP8 ? a.colscale[frow + tid] : 1.f;
+            mn = muT[tid] + gam * (xcs[tid] * sf * ibf - muT[tid]);
+        }
+        a.mu[frow + tid] = mn;
+        Mt[tid] = mn;
+    }
     __syncthreads();
     f64x4 sacc[StatTiles<KP, KIND>::H];
 #pragma unroll
@@ -1829,9 +1945,9 @@ __global__ void __launch_bounds__(kBT) k_wepi(WideArgs a)
         sacc[h] = f64x4{0, 0, 0, 0};
     double nrm = 0.0;
     write_vop<KP, KIND, IN>(a, Vn, frow);
-    tile_stats<KP, KIND>(Vn, Gn, Mt, sacc);
+    tile_stats<KP, KIND>(Vn, Gn, Mt, sacc, LDA || CEN);
     tile_norms<KP, KIND>(Vn, nrm);
-    write_stats<KP, KIND>(a, wg, sacc, nrm);
+    write_stats<KP, KIND>(a, wg, sacc, nrm, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -1845,6 +1961,7 @@ __global__ void __launch_bounds__(kBT) k_winit(WideArgs a)
     constexpr int VLD = Shape<KP, KIND>::VLD;
     __shared__ float Vn[kFT * VLD];
     __shared__ float Mt[(KIND == kKindLDA ? kMaxCls : 1) * kFT];
+    const bool CEN = KIND != kKindLDA && a.center != 0;
     const int tid = threadIdx.x;
     const int wg = blockIdx.x;
     int v, sub0, sub1;
@@ -1867,13 +1984,15 @@ __global__ void __launch_bounds__(kBT) k_winit(WideArgs a)
                 const int c = e / kFT, fl = e % kFT;
                 Mt[e] = c < a.ncls ? a.M[(int64_t)c * a.dtot + frow + fl] : 0.f;
             }
+        else if (CEN && tid < kFT) // the running means (zero at the start)
+            Mt[tid] = a.mu[frow + tid];
         __syncthreads();
         write_vop<KP, KIND, IN>(a, Vn, frow);
-        tile_stats<KP, KIND>(Vn, Vn, Mt, sacc);
+        tile_stats<KP, KIND>(Vn, Vn, Mt, sacc, KIND == kKindLDA || CEN);
         tile_norms<KP, KIND>(Vn, nrm);
         __syncthreads();
     }
-    write_stats<KP, KIND>(a, wg, sacc, nrm);
+    write_stats<KP, KIND>(a, wg, sacc, nrm, v);
 }
 
 // Read-out after k_wstats: out[i * d + f] (column-major FP64) =

@@ -104,7 +104,6 @@ def test_config_validation_is_synchronous():
         (mk(sg.SGEP_KIND_ICA, sg.SGEP_F32, 4, 16, 8, 16), sg.SGEP_ESHAPE),         # one stream
         (mk(sg.SGEP_KIND_ICA, sg.SGEP_F32, 4, 16, 0, 16, center=1), sg.SGEP_EUNSUPPORTED),
         (mk(sg.SGEP_KIND_ICA, sg.SGEP_F32, 4, 16, 0, 16, n_classes=3), sg.SGEP_EINVAL),
-        (mk(C, sg.SGEP_BF16, 4, 8, 8, 16, center=1), sg.SGEP_EUNSUPPORTED),  # centring: F64/F32
         (mk(L, sg.SGEP_BF16, 4, 8, 0, 16, n_classes=3, center=1), sg.SGEP_EUNSUPPORTED),
         (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=1, rho=0.0, nu=10.0), sg.SGEP_EINVAL),  # rho > 0
         (mk(C, sg.SGEP_F32, 4, 8, 8, 16, smooth=1, rho=1e-2, nu=1e-2), sg.SGEP_EINVAL),  # nu > rho

@@ -21,7 +21,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-11
+TOL64 = 1e-12
 TOL32_N = 3e-4
 
 

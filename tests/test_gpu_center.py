@@ -14,8 +14,8 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL64 = 1e-11
-TOL32_1, TOL32_N = 2e-5, 3e-4
+TOL64 = 1e-12
+TOL32_1, TOL32_N = 1e-6, 1e-5  # ~10x the observed maxima (6e-7 after 18 iterations)
 
 
 def _torch():
