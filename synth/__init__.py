@@ -341,21 +341,29 @@ class GeneralPlanted:
         y = rng.standard_normal((n, self.d)) @ self.Y_map.T
         return x.astype(dtype, copy=False), y.astype(dtype, copy=False)
 
-    def sample_torch(self, n: int, t: int, device, dtype):
+    def device_tables(self, device):
+        """The dense factors Qx, O and the vectors ax, lam as FP32 device
+        tensors (fast mixing; kept by the caller across calls of
+        sample_torch)."""
+        import torch
+        assert self._fx is not None, "device tables need mixing='fast'"
+        f32 = torch.float32
+        return (self._fx.dense_torch(device, f32), self._fo.dense_torch(device, f32),
+                torch.from_numpy(self.ax).to(device=device, dtype=f32),
+                torch.from_numpy(self.lam).to(device=device, dtype=f32))
+
+    def sample_torch(self, n: int, t: int, device, dtype, tables=None):
         """n fresh rows of x and y drawn on `device` (fast mixing only), from
         a torch generator seeded by (seed, t): x = Qx diag(sqrt(ax)) g and
         y = Qx diag(sqrt(ax + eps)) O diag(sqrt(lam)) g' with the dense
-        factors built in FP32 on the device.  Values differ from ``sample``,
-        which uses numpy's generator."""
+        factors built in FP32 on the device (``device_tables``).  Values
+        differ from ``sample``, which uses numpy's generator."""
         import torch
         assert self._fx is not None, "sample_torch needs mixing='fast'"
         g = torch.Generator(device=device)
         g.manual_seed((int(self.seed) * 1_000_003 + int(t)) & ((1 << 63) - 1))
         f32 = torch.float32
-        Q = self._fx.dense_torch(device, f32)
-        O = self._fo.dense_torch(device, f32)
-        ax = torch.from_numpy(self.ax).to(device=device, dtype=f32)
-        lam = torch.from_numpy(self.lam).to(device=device, dtype=f32)
+        Q, O, ax, lam = tables if tables is not None else self.device_tables(device)
         gx = torch.randn((n, self.d), generator=g, device=device, dtype=f32)
         gy = torch.randn((n, self.d), generator=g, device=device, dtype=f32)
         x = (gx * ax.sqrt()) @ Q.T
