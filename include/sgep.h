@@ -338,9 +338,9 @@ sgep_status sgep_batch_step(sgep_batch *bt, const void *const *X, const void *co
 
 /* Launches of one batched iteration: *n receives their number; kinds (cap
  * entries, nullable) receives 0 for a forward launch, -1 for a coefficient
- * launch (the k x k terms of each instance, once per iteration) and the
+ * launch (the k x k terms of each instance, once per iteration), the
  * backward feature-tile height in units of 16 features (1, 2 or 4) for a
- * backward launch. */
+ * backward launch, and -2 for the one launch of the persistent plan. */
 sgep_status sgep_batch_launches(const sgep_batch *bt, int32_t *n, int32_t *kinds, int32_t cap);
 
 /* sgep_batch_step with a start / end event pair per launch, in launch order
@@ -349,23 +349,32 @@ sgep_status sgep_batch_launches(const sgep_batch *bt, int32_t *n, int32_t *kinds
 sgep_status sgep_batch_step_profiled(sgep_batch *bt, const void *const *X, const void *const *Y,
                                      int64_t b, void *const *events, int32_t n_events);
 
-/* The launch plan: *groups, the number of instance groups run one after the
- * other (each a forward launch and its backward launches, so that a group's
- * minibatches are re-read from cache), and mb_bucket[3], the backward
- * feature-tile height (units of 16 features) for instances with d <= 256,
- * 256 < d <= 1024 and d > 1024. */
+/* The launch plan: *groups >= 1, the number of instance groups run one after
+ * the other (each a forward launch and its backward launches, so that a
+ * group's minibatches are re-read from cache), or *groups = -L <= -1, the
+ * persistent plan: one launch per iteration whose workgroups claim the
+ * items of per-XCC work queues (every instance's forward row tiles, its
+ * coefficient block and its backward tiles, in that order, the forward of
+ * the next L instances placed before an instance's coefficient item) and
+ * wait on per-instance counters (bounded waits; a give-up sets the status
+ * reported as SGEP_EDEVICE).  mb_bucket[3] is the backward feature-tile
+ * height (units of 16 features) for instances with d <= 256, 256 < d <= 1024
+ * and d > 1024. */
 sgep_status sgep_batch_plan(const sgep_batch *bt, int32_t *groups, int32_t *mb_bucket);
 
 /* Set the launch plan (mb_bucket entries 1 or the larger height this dtype
  * and k allow, as reported by sgep_batch_plan after sgep_batch_tune; groups
- * >= 1, clipped to n).  Only before the first iteration (SGEP_EINVAL
- * otherwise), because the norm partials of a running state are laid out by
- * tile.  Synchronises. */
+ * >= 1, clipped to n, or -64 <= groups <= -1 for the persistent plan).  Only
+ * before the first iteration (SGEP_EINVAL otherwise), because the norm
+ * partials of a running state are laid out by tile.  The persistent plan
+ * returns SGEP_EUNSUPPORTED unless every tile height is 1, k <= 32 (FP32) or
+ * k <= 16 (FP64) and the device reports its XCC count.  Synchronises. */
 sgep_status sgep_batch_set_plan(sgep_batch *bt, int32_t groups, const int32_t *mb_bucket);
 
 /* Autotune the launch plan on a caller's minibatch before the first
- * iteration: every candidate (groups 1, 2, 4, 8; per width bucket the tile
- * height 16 or the larger one) runs 1 + reps iterations from the initial
+ * iteration: every candidate (groups 1, 2, 4, 8 with, per width bucket, the
+ * tile height 16 or the larger one; the persistent plan with look-ahead 1, 2
+ * and 4 where it is supported) runs 1 + reps iterations from the initial
  * state on (X, Y, b) and is timed with HIP events; the fastest plan is kept
  * and the initial state restored, so the instances are as after
  * sgep_batch_init.  best_us (nullable) receives the chosen plan's time per

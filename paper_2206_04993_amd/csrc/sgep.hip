@@ -475,9 +475,9 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
     const dim3 gf(a.n_rb * a.nview * a.n_split + wide_stat_blocks(a));
     auto forward = [&]() {
         if constexpr (IN != kInF32) {
-            if constexpr (KP == 64 && IN == kInBF16) {
+            if constexpr ((KP == 32 || KP == 64) && IN == kInBF16) {
                 if (a.rbf == kFwdVRows) { // V shared through LDS (k_wfwdv)
-                    launch_k(k_wfwdv<IN>, gf, dim3(512), h->stream, ev[0], ev[1], a);
+                    launch_k(k_wfwdv<KP, IN>, gf, dim3(512), h->stream, ev[0], ev[1], a);
                     return;
                 }
             }
@@ -656,11 +656,11 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.dtot = lda ? r64(c.dx) : r64(c.dx) + r64(c.dy);
     a.k = c.k;
     a.ncls = lda ? c.n_classes : 0;
-    // forward kernels: KP = 64 BF16 minibatches of >= 1024 rows take
+    // forward kernels: KP = 32 or 64 BF16 minibatches of >= 1024 rows take
     // k_wfwdv (512-row workgroups sharing the V operand through LDS, rows
     // padded to 512); other BF16 / FP8 minibatches of >= 256 rows the
     // four-wave k_wfwd4 (rows padded to 256); the rest k_wfwd
-    const bool fwdv = KP == 64 && !f32 && !fp8 && c.b_max >= 1024;
+    const bool fwdv = (KP == 32 || KP == 64) && !f32 && !fp8 && c.b_max >= 1024;
     const bool fwd4 = !fwdv && !f32 && c.b_max >= 256;
     const int64_t rowpad = fwdv ? kFwdVRows : (fwd4 ? 256 : kRowPad);
     a.ldr = (c.b_max + rowpad - 1) / rowpad * rowpad;
@@ -1557,6 +1557,7 @@ sgep_status sgep_destroy(sgep_handle *h)
 namespace {
 
 constexpr int kBuckets = 3; // d <= 256, d <= 1024, larger
+constexpr int kMaxLag = 64;  // largest look-ahead of the persistent plan (instances)
 
 int bucket_of(int64_t d) { return d <= 256 ? 0 : (d <= 1024 ? 1 : 2); }
 
@@ -1581,6 +1582,15 @@ struct sgep_batch_s {
     std::vector<BatchLaunchRec> launches;
     StepArgs *d_args = nullptr;
     uint32_t *d_map = nullptr;
+    // persistent plan (groups < 0): one launch per iteration over per-XCC
+    // work queues with a look-ahead of `lag` instances
+    int lag = 0;
+    int n_xcc = 0;                       // XCCs of the device (0: unknown)
+    int pers_grid = 0;                   // workgroups of the persistent launch
+    unsigned long long *d_items = nullptr;
+    int32_t *d_meta = nullptr;
+    uint32_t *d_sync = nullptr;
+    sgep::batch::Queues queues;
 };
 
 namespace {
@@ -1592,13 +1602,115 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // backward feature-tile height mb_bucket[bucket(d)] per instance.  Within a
 // group every instance goes to one XCD, largest first, each to the XCD with
 // the least total width so far.  Synchronous (init and tuning only).
+// The persistent plan needs the XCC count (one queue per XCC), a player
+// block of at most 128 bytes per feature (FP32 k <= 32, FP64 k <= 16) and
+// 16-feature backward tiles for every instance.
+bool persistent_ok(const sgep_batch *bt, const int *mb_bucket)
+{
+    const sgep_handle *h0 = bt->inst[0];
+    if (bt->n_xcc < 1 || bt->n_xcc > sgep::batch::kMaxQueues || h0->kp * h0->esz > 128)
+        return false;
+    for (int c = 0; c < kBuckets; ++c)
+        if (mb_bucket[c] != 1)
+            return false;
+    for (int i = 0; i < bt->n; ++i)
+        if (bt->mb_min[i] != 1)
+            return false;
+    return true;
+}
+
+// The persistent plan: every instance to one XCC queue (largest first, each
+// to the XCC with the least total width so far); per queue the items
+//     F(i1) .. F(i_lag)  F(i_lag+1) C(i1) B(i1)  F(i_lag+2) C(i2) B(i2) ..
+// (sgep_batch.hpp, k_bpers).  Synchronous (init and tuning only).
+sgep_status apply_persistent(sgep_batch *bt, int lag)
+{
+    using namespace sgep::batch;
+    const int n = bt->n;
+    const int nq = bt->n_xcc;
+    if (nq < 1 || nq > kMaxQueues || lag < 1)
+        return SGEP_EUNSUPPORTED;
+    std::vector<int> ids(n);
+    for (int i = 0; i < n; ++i)
+        ids[i] = i;
+    std::stable_sort(ids.begin(), ids.end(), [&](int a, int b) { return bt->d[a] > bt->d[b]; });
+    std::vector<std::vector<int>> lists(nq);
+    std::vector<int64_t> load(nq, 0);
+    for (int i : ids) {
+        int x = 0;
+        for (int c = 1; c < nq; ++c)
+            if (load[c] < load[x])
+                x = c;
+        load[x] += bt->d[i];
+        lists[x].push_back(i);
+    }
+    const int64_t nf_max = ceil_div(bt->cfg.b_max, 16);
+    auto item = [](int kind, int inst, int64_t tile) {
+        return ((unsigned long long)kind << 48) | ((unsigned long long)inst << 32) |
+               (unsigned long long)tile;
+    };
+    std::vector<unsigned long long> items;
+    std::vector<int32_t> meta(2 * nq); // offsets, then lengths
+    Queues Q;
+    memset(&Q, 0, sizeof(Q));
+    for (int x = 0; x < nq; ++x) {
+        meta[x] = (int32_t)items.size();
+        const int m = (int)lists[x].size();
+        for (int j = 0; j < m + lag; ++j) {
+            if (j < m) { // forward: the norm-totals workgroup first, then the row tiles
+                const int i = lists[x][j];
+                items.push_back(item(kItemFwd, i, nf_max));
+                for (int64_t r = 0; r < nf_max; ++r)
+                    items.push_back(item(kItemFwd, i, r));
+            }
+            if (j - lag >= 0 && j - lag < m) {
+                const int i = lists[x][j - lag];
+                const sgep_handle *h = bt->inst[i];
+                items.push_back(item(kItemCoef, i, 0));
+                for (int t = 0; t < h->n_tiles; ++t)
+                    items.push_back(item(kItemBwd, i, t));
+            }
+        }
+        meta[nq + x] = (int32_t)items.size() - meta[x];
+    }
+    Q.nq = nq;
+    Q.nf_max = (int32_t)nf_max;
+    Q.n = n;
+    HIPCHK(hipStreamSynchronize(bt->stream));
+    if (bt->d_items)
+        HIPCHK(hipFree(bt->d_items));
+    bt->d_items = nullptr;
+    HIPCHK(hipMalloc((void **)&bt->d_items, items.size() * sizeof(unsigned long long)));
+    HIPCHK(hipMemcpy(bt->d_items, items.data(), items.size() * sizeof(unsigned long long),
+                     hipMemcpyHostToDevice));
+    if (!bt->d_meta)
+        HIPCHK(hipMalloc((void **)&bt->d_meta, 2 * kMaxQueues * sizeof(int32_t)));
+    HIPCHK(hipMemcpy(bt->d_meta, meta.data(), meta.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
+    const size_t nsync = (size_t)kSyncInst + 2 * (size_t)n;
+    if (!bt->d_sync)
+        HIPCHK(hipMalloc((void **)&bt->d_sync, nsync * sizeof(uint32_t)));
+    HIPCHK(hipMemset(bt->d_sync, 0, nsync * sizeof(uint32_t)));
+    HIPCHK(hipDeviceSynchronize());
+    Q.items = bt->d_items;
+    Q.meta = bt->d_meta;
+    Q.sync = bt->d_sync;
+    bt->queues = Q;
+    bt->launches.assign(1, BatchLaunchRec{-2, 0, 0});
+    bt->lag = lag;
+    bt->groups = -lag;
+    return SGEP_OK;
+}
+
 sgep_status apply_plan(sgep_batch *bt, int groups, const int *mb_bucket)
 {
     const int n = bt->n;
-    if (groups < 1)
-        groups = 1;
     if (groups > n)
         groups = n;
+    if (groups == 0)
+        groups = 1;
+    if (groups < 0 && !persistent_ok(bt, mb_bucket))
+        return SGEP_EUNSUPPORTED;
     std::vector<StepArgs> args(n);
     for (int i = 0; i < n; ++i) {
         sgep_handle *h = bt->inst[i];
@@ -1612,6 +1724,15 @@ sgep_status apply_plan(sgep_batch *bt, int groups, const int *mb_bucket)
         h->n_tiles = h->n_tx;
         const int64_t vec = 16 / (int64_t)h->esz;
         args[i] = make_args(h, bt->ld[i], bt->ld[i], bt->ld[i] % vec == 0);
+    }
+    if (groups < 0) {
+        HIPCHK(hipStreamSynchronize(bt->stream)); // the old table may still be in use
+        HIPCHK(hipMemcpy(bt->d_args, args.data(), n * sizeof(StepArgs), hipMemcpyHostToDevice));
+        const sgep_status rc = apply_persistent(bt, -groups);
+        if (rc == SGEP_OK)
+            for (int c = 0; c < kBuckets; ++c)
+                bt->mb_bucket[c] = mb_bucket[c];
+        return rc;
     }
     // contiguous groups of about equal total width
     int64_t total = 0;
@@ -1690,6 +1811,7 @@ sgep_status apply_plan(sgep_batch *bt, int groups, const int *mb_bucket)
     HIPCHK(hipMemcpy(bt->d_args, args.data(), n * sizeof(StepArgs), hipMemcpyHostToDevice));
     bt->launches = recs;
     bt->groups = (int)gstart.size() - 1;
+    bt->lag = 0;
     for (int c = 0; c < kBuckets; ++c)
         bt->mb_bucket[c] = mb_bucket[c];
     return SGEP_OK;
@@ -1712,7 +1834,24 @@ sgep_status batch_launch_t(sgep_batch *bt, const sgep::batch::Launch &base, void
         const dim3 blk(sgep::kNT);
         constexpr int MBW = mb_wide<T>(KP);
         constexpr int GEN = sgep::kKindGeneral;
-        if (r.mb == 0) {
+        if (r.mb == -2) { // persistent: every item of the iteration in one launch
+          if constexpr (KP * sizeof(T) <= 128) {
+            auto kern = adam ? k_bpers<T, KP, sgep::kOptAdam> : k_bpers<T, KP, sgep::kOptSGD>;
+            if (bt->pers_grid == 0) {
+                // as many workgroups as the CUs hold at once (the queues are
+                // drained by whichever run; more would only wait to start)
+                int occ = 0, cus = 0, dev = 0;
+                HIPCHK(hipGetDevice(&dev));
+                HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+                HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, sgep::kNT, 0));
+                bt->pers_grid = (occ < 1 ? 1 : occ) * (cus < 1 ? 1 : cus);
+            }
+            launch_k(kern, dim3((unsigned)bt->pers_grid), blk, bt->stream, e0, e1, L, bt->queues,
+                     L.args, L.X, L.Y);
+          } else {
+            return SGEP_EUNSUPPORTED; // not planned for larger player blocks
+          }
+        } else if (r.mb == 0) {
             launch_k(k_bfwd<T, KP, GEN>, dim3((unsigned)(8 * r.per_xcd * (nf + 1))), blk,
                      bt->stream, e0, e1, L, L.args, L.X, L.Y);
         } else if (r.mb < 0) {
@@ -1769,6 +1908,12 @@ void batch_free(sgep_batch *bt)
         (void)hipFree(bt->d_args);
     if (bt->d_map)
         (void)hipFree(bt->d_map);
+    if (bt->d_items)
+        (void)hipFree(bt->d_items);
+    if (bt->d_sync)
+        (void)hipFree(bt->d_sync);
+    if (bt->d_meta)
+        (void)hipFree(bt->d_meta);
     delete bt;
 }
 
@@ -1882,6 +2027,12 @@ sgep_status sgep_batch_init(sgep_batch **out, int32_t n, const int64_t *d, const
         batch_free(bt);
         return SGEP_ENOMEM;
     }
+    {
+        int dev = 0, nx = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess)
+            bt->n_xcc = nx;
+    }
     const int mb1[kBuckets] = {1, 1, 1};
     sgep_status rc = apply_plan(bt, 1, mb1);
     if (rc != SGEP_OK) {
@@ -1942,7 +2093,7 @@ sgep_status sgep_batch_plan(const sgep_batch *bt, int32_t *groups, int32_t *mb_b
 
 sgep_status sgep_batch_set_plan(sgep_batch *bt, int32_t groups, const int32_t *mb_bucket)
 {
-    if (!bt || !mb_bucket || groups < 1)
+    if (!bt || !mb_bucket || groups == 0 || groups < -kMaxLag)
         return SGEP_EINVAL;
     int mb[kBuckets];
     for (int c = 0; c < kBuckets; ++c) {
@@ -1985,10 +2136,17 @@ sgep_status sgep_batch_tune(sgep_batch *bt, const void *const *X, const void *co
         rc = SGEP_EDEVICE;
     double best = 1e300;
     int best_g = 1, best_mb[kBuckets] = {1, 1, 1};
-    const int gcand[4] = {1, 2, 4, 8};
-    for (int gi = 0; gi < 4 && rc == SGEP_OK; ++gi) {
-        if (gcand[gi] > bt->n)
-            break;
+    // grouped launches (1, 2, 4, 8 groups) and the persistent launch with a
+    // look-ahead of 1, 2 or 4 instances (when the XCC count is known)
+    const int gcand[7] = {1, 2, 4, 8, -1, -2, -4};
+    for (int gi = 0; gi < 7 && rc == SGEP_OK; ++gi) {
+        if (gcand[gi] > bt->n || (gcand[gi] < 0 && -gcand[gi] > bt->n))
+            continue;
+        if (gcand[gi] < 0) {
+            const int mb1[kBuckets] = {1, 1, 1};
+            if (!persistent_ok(bt, mb1))
+                continue;
+        }
         for (int mask = 0; mask < (1 << kBuckets) && rc == SGEP_OK; ++mask) {
             int mb[kBuckets];
             bool dup = false;
@@ -1998,8 +2156,8 @@ sgep_status sgep_batch_tune(sgep_batch *bt, const void *const *X, const void *co
                     dup = true; // same plan as with this bit clear
                 mb[c] = wide ? bt->mb_wide : 1;
             }
-            if (dup)
-                continue;
+            if (dup || (gcand[gi] < 0 && mask != 0))
+                continue; // the persistent form has 16-feature tiles only
             rc = apply_plan(bt, gcand[gi], mb);
             if (rc == SGEP_OK)
                 rc = batch_restore(bt, snap);

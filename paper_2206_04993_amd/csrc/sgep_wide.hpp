@@ -601,24 +601,28 @@ __global__ void __launch_bounds__(256) k_wfwd4(WideArgs a)
 template <int KP> constexpr int fwd4_rows() { return KP <= 32 ? 256 : 128; }
 
 // ---------------------------------------------------------------------------
-// Forward products for KP = 64 with the V operand shared through LDS (k_wfwdv,
-// BF16 minibatches): eight waves of 64 rows each (512 rows per workgroup) walk
-// the same feature slice in 64-feature chunks, so each row's 128-byte line is
-// read whole by one chunk (two 32-feature halves, issued together) instead of
-// half now and half after it may have left L2.  For every chunk each wave
-// fetches two of the sixteen V fragments (player tile w / 2, hi for even w,
-// lo for odd, both halves) into a double-buffered LDS ring, so one fragment
-// read from L2 serves 512 rows (k_wfwd4: 128); every wave then reads all
-// sixteen from LDS.  The minibatch loads run one chunk ahead.  Each wave owns
+// Forward products for KP = 32 and 64 with the V operand shared through LDS
+// (k_wfwdv, BF16 minibatches): eight waves of 64 rows each (512 rows per
+// workgroup) walk the same feature slice in 64-feature chunks, so each row's
+// 128-byte line is read whole by one chunk (two 32-feature halves, issued
+// together) instead of half now and half after it may have left L2.  For
+// every chunk the waves fetch the 4 KP / 16 V fragments (player tile x hi/lo
+// x 32-feature half) into a double-buffered LDS ring -- KP = 64: wave w
+// fragment w (player tile w / 2, hi for even w, lo for odd) of both halves;
+// KP = 32: fragment w % 4 of half w / 4 -- so one fragment read from L2
+// serves 512 rows (k_wfwd4: 128 or 256); every wave then reads them all from
+// LDS.  The minibatch loads run one chunk ahead.  Each wave owns
 // its rows, so the partials go straight from the accumulators to memory (no
 // cross-wave sum).  Within a half: lane layout, operands and MFMAs as k_wfwd.
 // ---------------------------------------------------------------------------
 constexpr int kFwdVRows = 512; // rows per k_wfwdv workgroup
-template <int IN>
+template <int KP, int IN>
 __global__ void __launch_bounds__(512) k_wfwdv(WideArgs a)
 {
     static_assert(IN == kInBF16, "BF16 minibatches");
-    constexpr int KP = 64, NT = 4, TR = 4, NWV = 8;
+    static_assert(KP == 32 || KP == 64, "two or four player tiles");
+    constexpr int NT = KP / 16, TR = 4, NWV = 8;
+    constexpr int NH = KP == 64 ? 2 : 1; // halves fetched per wave
     __shared__ u32x4 vb[2][2][2 * NT][64]; // [buffer][half][fragment][lane]
     const int nfwd = a.n_rb * a.nview * a.n_split;
     if ((int)blockIdx.x >= nfwd) {
@@ -648,9 +652,12 @@ __global__ void __launch_bounds__(512) k_wfwdv(WideArgs a)
     for (int t = 0; t < TR; ++t)
         if (row0 + 16 * t + r16 < a.b)
             rok |= 1u << t;
-    // the V fragments this wave fetches: player tile w / 2, hi or lo
-    const uint16_t *Vsrc = ((w & 1) ? a.Vl : a.Vh) + a.off[v] +
-                           (int64_t)(16 * (w >> 1) + r16) * a.dtot + 8 * g;
+    // the V fragments this wave fetches: fragment wf (player tile wf / 2, hi
+    // or lo) of both halves (KP = 64) or of half w / 4 (KP = 32)
+    const int wf = KP == 64 ? w : (w & 3);
+    const int h0 = KP == 64 ? 0 : (w >> 2);
+    const uint16_t *Vsrc = ((wf & 1) ? a.Vl : a.Vh) + a.off[v] +
+                           (int64_t)(16 * (wf >> 1) + r16) * a.dtot + 8 * g + 32 * h0;
 
     f32x4 acc[TR][NT];
 #pragma unroll
@@ -664,7 +671,7 @@ __global__ void __launch_bounds__(512) k_wfwdv(WideArgs a)
     // past the view the last unit; zeroed where consumed) and the wave's two
     // V fragments.  The V rows are padded to 64 features, so f0 + 64 stays
     // inside the view's state rows.
-    auto load = [&](int st, u32x4(&xa)[2][TR], u32x4(&vg)[2]) {
+    auto load = [&](int st, u32x4(&xa)[2][TR], u32x4(&vg)[NH]) {
         const int64_t f0 = fbeg + 64 * (int64_t)(st < nst ? st : nst - 1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -676,14 +683,15 @@ __global__ void __launch_bounds__(512) k_wfwdv(WideArgs a)
             }
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < NH; ++h)
             vg[h] = *reinterpret_cast<const u32x4 *>(Vsrc + f0 + 32 * h);
     };
-    auto step = [&](int st, const u32x4(&xa)[2][TR], const u32x4(&vg)[2]) {
+    auto step = [&](int st, const u32x4(&xa)[2][TR], const u32x4(&vg)[NH]) {
         // every wave reaches every barrier: nst is workgroup-uniform
         u32x4(&buf)[2][2 * NT][64] = vb[st & 1];
-        buf[0][w][lane] = vg[0];
-        buf[1][w][lane] = vg[1];
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+            buf[h0 + h][wf][lane] = vg[h];
         __syncthreads();
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -707,7 +715,7 @@ __global__ void __launch_bounds__(512) k_wfwdv(WideArgs a)
     };
     // two register stages: chunk st + 1 is in flight while st is multiplied
     // (one loop exit, so the loads stay in flight across the back edge)
-    u32x4 xa0[2][TR], xa1[2][TR], vg0[2], vg1[2];
+    u32x4 xa0[2][TR], xa1[2][TR], vg0[NH], vg1[NH];
     if (nst > 0) {
         load(0, xa0, vg0);
         int st = 0;

@@ -29,7 +29,7 @@ def _rows(path):
 
 
 # longer names first: "sgep::k_fwd" is a prefix of "sgep::k_fwd2"
-_KERNELS = ("k_bfwd", "k_bcoef", "k_bbwd", "k_wfwd", "k_wmid", "k_wbwd", "k_wprod", "k_wepi",
+_KERNELS = ("k_bpers", "k_bfwd", "k_bcoef", "k_bbwd", "k_wfwd", "k_wmid", "k_wbwd", "k_wprod", "k_wepi",
             "k_winit", "k_fwd2",
             "k_bwdp", "k_fwds", "k_fwd", "k_coefa", "k_coefb", "k_coef", "k_bwd")
 
@@ -97,7 +97,8 @@ def main(prof_dir: str, workload: str, cmd: str = "", copy_mib: int = 256):
              f"{copy_kib('write'):.0f} KiB by these counters",
              "kernel | dispatches | fetch_KiB(median) | write_KiB(median) | read_bytes | write_bytes"]
     for k in ("k_fwds", "k_fwd", "k_coef", "k_coefa", "k_coefb", "k_bwdp", "k_bwd1", "k_fwd2", "k_bwd",
-              "k_wfwd", "k_wmid", "k_wbwd", "k_wprod", "k_wepi", "k_bfwd", "k_bcoef", "k_bbwd"):
+              "k_wfwd", "k_wmid", "k_wbwd", "k_wprod", "k_wepi", "k_bfwd", "k_bcoef", "k_bbwd",
+              "k_bpers"):
         f = [v for _, v in vals.get((k, "fetch"), [])]
         w = [v for _, v in vals.get((k, "write"), [])]
         if not f:

@@ -117,6 +117,9 @@ def _run_cca(cfg, batches, V0, checkpoints, aux=None):
     ("bf16", 16392, 16384, 20, 300, "sgd"),  # with the four-wave forward (b >= 256)
     ("fp8", 16392, 16384, 20, 64, "adam"),
     ("fp8", 520, 264, 32, 300, "adam"),       # four-wave forward, KP 32, FP8 codes
+    # 512-row forward workgroups sharing V through LDS at KP 32 (b >= 1024), ragged rows
+    ("bf16", 520, 264, 32, 1100, "adam"),
+    ("bf16", 4104, 2056, 20, 1030, "sgd"),
 ])
 def test_wide_cca_parity(fmt, dx, dy, k, b, opt):
     sg = _sg()
@@ -406,6 +409,7 @@ class _Shifted:
 
 @pytest.mark.parametrize("fmt,dx,dy,k,b,opt", [
     ("bf16", 520, 264, 20, 300, "sgd"),      # one backward kernel, several subtiles
+    ("bf16", 520, 264, 20, 1100, "adam"),    # the LDS-shared forward at KP 32
     ("fp8", 200, 136, 13, 100, "adam"),      # column scales, ragged rows
     # split backward (k_wprod, k_wepi), offsets of scale 0.1: while the
     # running mean is still far from the offsets, the products carry the mean
