@@ -475,7 +475,7 @@ sgep_status wide_step_t(sgep_handle *h, const WideArgs &a, const hipEvent_t *ev)
     const dim3 gf(a.n_rb * a.nview * a.n_split + wide_stat_blocks(a));
     auto forward = [&]() {
         if constexpr (IN != kInF32) {
-            if constexpr ((KP == 32 || KP == 64) && IN == kInBF16) {
+            if constexpr (KP == 32 || KP == 64) {
                 if (a.rbf == kFwdVRows) { // V shared through LDS (k_wfwdv)
                     launch_k(k_wfwdv<KP, IN>, gf, dim3(512), h->stream, ev[0], ev[1], a);
                     return;
@@ -656,11 +656,11 @@ sgep_status init_wide(sgep_handle *h, const double *V0, const sgep_init_aux *aux
     a.dtot = lda ? r64(c.dx) : r64(c.dx) + r64(c.dy);
     a.k = c.k;
     a.ncls = lda ? c.n_classes : 0;
-    // forward kernels: KP = 32 or 64 BF16 minibatches of >= 1024 rows take
+    // forward kernels: KP = 32 or 64 BF16 / FP8 minibatches of >= 1024 rows take
     // k_wfwdv (512-row workgroups sharing the V operand through LDS, rows
     // padded to 512); other BF16 / FP8 minibatches of >= 256 rows the
     // four-wave k_wfwd4 (rows padded to 256); the rest k_wfwd
-    const bool fwdv = (KP == 32 || KP == 64) && !f32 && !fp8 && c.b_max >= 1024;
+    const bool fwdv = (KP == 32 || KP == 64) && !f32 && c.b_max >= 1024;
     const bool fwd4 = !fwdv && !f32 && c.b_max >= 256;
     const int64_t rowpad = fwdv ? kFwdVRows : (fwd4 ? 256 : kRowPad);
     a.ldr = (c.b_max + rowpad - 1) / rowpad * rowpad;

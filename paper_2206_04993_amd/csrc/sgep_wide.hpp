@@ -602,7 +602,8 @@ template <int KP> constexpr int fwd4_rows() { return KP <= 32 ? 256 : 128; }
 
 // ---------------------------------------------------------------------------
 // Forward products for KP = 32 and 64 with the V operand shared through LDS
-// (k_wfwdv, BF16 minibatches): eight waves of 64 rows each (512 rows per
+// (k_wfwdv, BF16 or FP8 minibatches; FP8 codes decode exactly to BF16, the
+// column scales folded into V): eight waves of 64 rows each (512 rows per
 // workgroup) walk the same feature slice in 64-feature chunks, so each row's
 // 128-byte line is read whole by one chunk (two 32-feature halves, issued
 // together) instead of half now and half after it may have left L2.  For
@@ -619,8 +620,9 @@ constexpr int kFwdVRows = 512; // rows per k_wfwdv workgroup
 template <int KP, int IN>
 __global__ void __launch_bounds__(512) k_wfwdv(WideArgs a)
 {
-    static_assert(IN == kInBF16, "BF16 minibatches");
+    static_assert(IN == kInBF16 || IN == kInFP8, "BF16 / FP8 codes");
     static_assert(KP == 32 || KP == 64, "two or four player tiles");
+    constexpr int ES = IN == kInBF16 ? 2 : 1;
     constexpr int NT = KP / 16, TR = 4, NWV = 8;
     constexpr int NH = KP == 64 ? 2 : 1; // halves fetched per wave
     __shared__ u32x4 vb[2][2][2 * NT][64]; // [buffer][half][fragment][lane]
@@ -679,7 +681,13 @@ __global__ void __launch_bounds__(512) k_wfwdv(WideArgs a)
 #pragma unroll
             for (int t = 0; t < TR; ++t) {
                 const int64_t row = (rok >> t) & 1u ? row0 + 16 * t + r16 : rlast;
-                xa[h][t] = *reinterpret_cast<const u32x4 *>(Xb + (row * ld + fx) * 2);
+                const uint8_t *p = Xb + (row * ld + fx) * ES;
+                if (IN == kInBF16) {
+                    xa[h][t] = *reinterpret_cast<const u32x4 *>(p);
+                } else { // eight codes, decoded where consumed
+                    const u32x2 q = *reinterpret_cast<const u32x2 *>(p);
+                    xa[h][t] = u32x4{q[0], q[1], 0u, 0u};
+                }
             }
         }
 #pragma unroll
@@ -698,8 +706,16 @@ __global__ void __launch_bounds__(512) k_wfwdv(WideArgs a)
             const bool fok = fbeg + 64 * (int64_t)st + 32 * h + 8 * g < dv;
             u32x4 x[TR];
 #pragma unroll
-            for (int t = 0; t < TR; ++t)
-                x[t] = (fok && ((rok >> t) & 1u)) ? xa[h][t] : u32x4{0u, 0u, 0u, 0u};
+            for (int t = 0; t < TR; ++t) {
+                u32x4 xt = xa[h][t];
+                if (IN == kInFP8) {
+                    uint32_t e0, e1, e2, e3;
+                    fp8x4_to_bf16(xa[h][t][0], e0, e1);
+                    fp8x4_to_bf16(xa[h][t][1], e2, e3);
+                    xt = u32x4{e0, e1, e2, e3};
+                }
+                x[t] = (fok && ((rok >> t) & 1u)) ? xt : u32x4{0u, 0u, 0u, 0u};
+            }
             // one player tile at a time: its hi / lo fragments from LDS
 #pragma unroll
             for (int u = 0; u < NT; ++u) {

@@ -120,6 +120,8 @@ def _run_cca(cfg, batches, V0, checkpoints, aux=None):
     # 512-row forward workgroups sharing V through LDS at KP 32 (b >= 1024), ragged rows
     ("bf16", 520, 264, 32, 1100, "adam"),
     ("bf16", 4104, 2056, 20, 1030, "sgd"),
+    ("fp8", 520, 264, 32, 1100, "sgd"),
+    ("fp8", 4104, 2056, 20, 1030, "adam"),
 ])
 def test_wide_cca_parity(fmt, dx, dy, k, b, opt):
     sg = _sg()
@@ -410,6 +412,7 @@ class _Shifted:
 @pytest.mark.parametrize("fmt,dx,dy,k,b,opt", [
     ("bf16", 520, 264, 20, 300, "sgd"),      # one backward kernel, several subtiles
     ("bf16", 520, 264, 20, 1100, "adam"),    # the LDS-shared forward at KP 32
+    ("fp8", 520, 264, 20, 1100, "sgd"),
     ("fp8", 200, 136, 13, 100, "adam"),      # column scales, ragged rows
     # split backward (k_wprod, k_wepi), offsets of scale 0.1: while the
     # running mean is still far from the offsets, the products carry the mean
