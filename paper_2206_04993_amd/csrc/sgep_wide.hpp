@@ -105,7 +105,7 @@ struct WideArgs {
     float *Vf;                  // FP32 input: KP x dtot, player-major copy of V
     const float *colscale;      // dtot (FP8 only): s_f, 0 on padding
     float *Ppart;               // [n_split][nview][ldr][KP]
-    uint16_t *Wh, *Wl;          // [rows of W][ldr]
+    uint16_t *Wh, *Wl;          // BF16 W: 1 KB tiles of 16 rows x 32 minibatch rows (w_idx)
     float *Wf;                  // FP32 input: [rows of W][ldr]
     const float *M;             // LDA: ncls x dtot class means
     const float *Mbar;          // LDA: dtot, prior-weighted mean of the class means
@@ -200,7 +200,20 @@ template <int KP, int KIND> struct Shape {
     // the class means times V (16 rows), CCA the view's running mean times V
     // (row 0; zero without centring)
     static constexpr int NST = NT * (NT + 1) / 2 + NT;
+    // 16-row tiles of the BF16 backward operand W (LDA: R, then the one-hot
+    // rows of the classes; CCA: P, then Q)
+    static constexpr int MWT = (LDA ? KP + kMaxCls : 2 * KP) / 16;
 };
+
+// Position of element (row m, minibatch row r) of the BF16 backward operand
+// W (Wh, Wl): 32-row chunks, within a chunk 16-row tiles of 16 x 32 elements
+// (1 KB), row-major inside the tile.  A wave's fragment load of one tile --
+// lane (m % 16, g) taking rows 8 g .. 8 g + 7 -- is then one contiguous 1 KB.
+template <int MWT>
+__device__ __forceinline__ int64_t w_idx(int m, int64_t r)
+{
+    return (((r >> 5) * MWT + (m >> 4)) * 16 + (m & 15)) * 32 + (r & 31);
+}
 
 // ---------------------------------------------------------------------------
 // Statistics partials: statistic e of workgroup column j sits in group e / 16,
@@ -829,18 +842,18 @@ __global__ void __launch_bounds__(kMT) k_wmid(WideArgs a)
             }
         }
     } else {
+        constexpr int MWT = Shape<KP, KIND>::MWT;
         for (int e = tid; e < NE; e += kMT) {
             const int m = e / kMR, rl = e % kMR;
             uint32_t hi, lo;
             split_bf16(tile[rl * NV * KP + m], hi, lo);
-            a.Wh[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)hi;
-            a.Wl[(int64_t)m * a.ldr + r0 + rl] = (uint16_t)lo;
+            a.Wh[w_idx<MWT>(m, r0 + rl)] = (uint16_t)hi;
+            a.Wl[w_idx<MWT>(m, r0 + rl)] = (uint16_t)lo;
         }
         if (LDA) {
             for (int e = tid; e < kMaxCls * kMR; e += kMT) {
                 const int c = e / kMR, rl = e % kMR;
-                a.Wh[(int64_t)(KP + c) * a.ldr + r0 + rl] =
-                    lab[rl] == c ? (uint16_t)0x3F80 : (uint16_t)0;
+                a.Wh[w_idx<MWT>(KP + c, r0 + rl)] = lab[rl] == c ? (uint16_t)0x3F80 : (uint16_t)0;
             }
         }
     }
@@ -1079,8 +1092,9 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
     const float c1 = (float)(1.0 - pow(a.adam_b1, t)), c2 = (float)(1.0 - pow(a.adam_b2, t));
     if (LDA && tid < NC)
         sprior[tid] = tid < a.ncls ? a.prior[tid] : 0.0; // read after the loop's barriers
-    const uint16_t *Wh = IN == kInF32 ? nullptr : a.Wh + (int64_t)l16 * a.ldr + 8 * g;
-    const uint16_t *Wl = IN == kInF32 ? nullptr : a.Wl + (int64_t)l16 * a.ldr + 8 * g;
+    // BF16 W in 1 KB tiles (w_idx): this lane's 16 bytes of a tile
+    const uint16_t *Wh = IN == kInF32 ? nullptr : a.Wh + l16 * 32 + 8 * g;
+    const uint16_t *Wl = IN == kInF32 ? nullptr : a.Wl + l16 * 32 + 8 * g;
     const float *Wf = IN == kInF32 ? a.Wf + (int64_t)l16 * a.ldr + 8 * g : nullptr;
 
     f64x4 sacc[StatTiles<KP, KIND>::H];
@@ -1202,7 +1216,8 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
             }
         } else {
             auto loadc = [&](int ch, BwdChunk<NU, XD> &B) {
-                const int64_t r0 = (int64_t)(ch < nch ? ch : nch - 1) * 32;
+                const int64_t cc = ch < nch ? ch : nch - 1;
+                const int64_t r0 = cc * 32;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int64_t row = r0 + 8 * g + j < a.b ? r0 + 8 * g + j : a.b - 1;
@@ -1219,12 +1234,12 @@ __device__ __forceinline__ void wbwd_body(WideArgs a)
                 }
 #pragma unroll
                 for (int u = 0; u < NU; ++u) {
-                    const int64_t wo = (int64_t)16 * u * a.ldr + r0;
+                    const int64_t wo = (cc * S::MWT + u) * 512;
                     B.wh[u] = *reinterpret_cast<const u32x4 *>(Wh + wo);
                     B.wl[u] = *reinterpret_cast<const u32x4 *>(Wl + wo);
                 }
                 if (LDA && first) // the one-hot rows only feed the Gram terms
-                    B.lh = *reinterpret_cast<const u32x4 *>(Wh + (int64_t)KP * a.ldr + r0);
+                    B.lh = *reinterpret_cast<const u32x4 *>(Wh + (cc * S::MWT + KP / 16) * 512);
             };
             auto compute = [&](int ch, const BwdChunk<NU, XD> &B) {
                 if (ch >= nch)
