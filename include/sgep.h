@@ -128,11 +128,11 @@ typedef struct sgep_config {
                         * minibatch view is centred by a running mean before the
                         * iteration (the mean of the iteration's start), and the
                         * mean then moves toward the minibatch mean at rate gamma
-                        * (starting at 0).  F64 / F32 CCA and GENERAL single
-                        * handles, and BF16 / FP8-e4m3 CCA (there the products
-                        * are corrected by the rank-one terms, X itself enters
-                        * the arithmetic exactly); SGEP_EUNSUPPORTED elsewhere
-                        * (LDA, ICA, batches) */
+                        * (starting at 0).  F64 / F32 CCA and GENERAL (single
+                        * handles and batches), and BF16 / FP8-e4m3 CCA (there
+                        * the products are corrected by the rank-one terms, X
+                        * itself enters the arithmetic exactly);
+                        * SGEP_EUNSUPPORTED elsewhere (LDA, ICA) */
     double nu;         /* Alg. 3: upper bound of lambda_max(B), nu > rho; unused
                         * (any value) with smooth = 0 */
 } sgep_config;
@@ -315,8 +315,7 @@ typedef struct sgep_batch_s sgep_batch;
  *   V0      : host, n pointers to d_i x k column-major starting points
  *   hip_stream : the stream of every instance
  * The initial launch plan is one group with 16-feature backward tiles.
- * Errors: as sgep_init; SGEP_EUNSUPPORTED for another kind or dtype, or with
- * centring. */
+ * Errors: as sgep_init; SGEP_EUNSUPPORTED for another kind or dtype. */
 sgep_status sgep_batch_init(sgep_batch **out, int32_t n, const int64_t *d, const int64_t *ld,
                             const sgep_config *common, const double *const *V0,
                             void *hip_stream);

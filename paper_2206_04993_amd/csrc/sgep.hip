@@ -1817,8 +1817,8 @@ sgep_status apply_plan(sgep_batch *bt, int groups, const int *mb_bucket)
     return SGEP_OK;
 }
 
-template <typename T, int KP>
-sgep_status batch_launch_t(sgep_batch *bt, const sgep::batch::Launch &base, void *const *events)
+template <typename T, int KP, bool CEN>
+sgep_status batch_launch_c(sgep_batch *bt, const sgep::batch::Launch &base, void *const *events)
 {
     using namespace sgep::batch;
     const bool adam = bt->cfg.optimizer == SGEP_ADAM;
@@ -1836,7 +1836,7 @@ sgep_status batch_launch_t(sgep_batch *bt, const sgep::batch::Launch &base, void
         constexpr int GEN = sgep::kKindGeneral;
         if (r.mb == -2) { // persistent: every item of the iteration in one launch
           if constexpr (KP * sizeof(T) <= 128) {
-            auto kern = adam ? k_bpers<T, KP, sgep::kOptAdam> : k_bpers<T, KP, sgep::kOptSGD>;
+            auto kern = adam ? k_bpers<T, KP, sgep::kOptAdam, CEN> : k_bpers<T, KP, sgep::kOptSGD, CEN>;
             if (bt->pers_grid == 0) {
                 // as many workgroups as the CUs hold at once (the queues are
                 // drained by whichever run; more would only wait to start)
@@ -1852,7 +1852,7 @@ sgep_status batch_launch_t(sgep_batch *bt, const sgep::batch::Launch &base, void
             return SGEP_EUNSUPPORTED; // not planned for larger player blocks
           }
         } else if (r.mb == 0) {
-            launch_k(k_bfwd<T, KP, GEN>, dim3((unsigned)(8 * r.per_xcd * (nf + 1))), blk,
+            launch_k(k_bfwd<T, KP, GEN, CEN>, dim3((unsigned)(8 * r.per_xcd * (nf + 1))), blk,
                      bt->stream, e0, e1, L, L.args, L.X, L.Y);
         } else if (r.mb < 0) {
             launch_k(k_bcoef<T, KP, GEN>, dim3((unsigned)(8 * r.per_xcd)), blk, bt->stream, e0, e1,
@@ -1860,21 +1860,29 @@ sgep_status batch_launch_t(sgep_batch *bt, const sgep::batch::Launch &base, void
         } else {
             const dim3 grid((unsigned)(8 * r.per_xcd));
             if (r.mb == 1 && !adam)
-                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptSGD>, grid, blk, bt->stream, e0, e1, L,
+                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptSGD, CEN>, grid, blk, bt->stream, e0, e1, L,
                          L.args, L.X, L.Y);
             else if (r.mb == 1)
-                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptAdam>, grid, blk, bt->stream, e0, e1, L,
+                launch_k(k_bbwd<T, KP, 1, GEN, sgep::kOptAdam, CEN>, grid, blk, bt->stream, e0, e1, L,
                          L.args, L.X, L.Y);
             else if (!adam)
-                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptSGD>, grid, blk, bt->stream, e0, e1, L,
+                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptSGD, CEN>, grid, blk, bt->stream, e0, e1, L,
                          L.args, L.X, L.Y);
             else
-                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptAdam>, grid, blk, bt->stream, e0, e1, L,
+                launch_k(k_bbwd<T, KP, MBW, GEN, sgep::kOptAdam, CEN>, grid, blk, bt->stream, e0, e1, L,
                          L.args, L.X, L.Y);
         }
     }
     HIPCHK(hipGetLastError());
     return SGEP_OK;
+}
+
+// the batch's centring flag as a compile-time choice of the kernels
+template <typename T, int KP>
+sgep_status batch_launch_t(sgep_batch *bt, const sgep::batch::Launch &base, void *const *events)
+{
+    return bt->cfg.center ? batch_launch_c<T, KP, true>(bt, base, events)
+                          : batch_launch_c<T, KP, false>(bt, base, events);
 }
 
 sgep_status batch_step_impl(sgep_batch *bt, const void *const *X, const void *const *Y, int64_t b,
@@ -1990,8 +1998,6 @@ sgep_status sgep_batch_init(sgep_batch **out, int32_t n, const int64_t *d, const
         return SGEP_EUNSUPPORTED;
     if (common->dtype != SGEP_F32 && common->dtype != SGEP_F64)
         return SGEP_EUNSUPPORTED;
-    if (common->center)
-        return SGEP_EUNSUPPORTED; // centring: single handles only
     for (int i = 0; i < n; ++i) {
         if (!V0[i])
             return SGEP_EINVAL;

@@ -63,7 +63,7 @@ __device__ __forceinline__ StepArgs instance_args(const Launch &L,
 // Forward launch: 8 * per_xcd * (n_fwd + 1) workgroups.  Slot s of XCD x
 // takes instance map[x * per_xcd + s / (n_fwd + 1)], row tile s % (n_fwd + 1)
 // (the last one of each instance reduces its norm / parent partials).
-template <typename T, int KP, int KIND>
+template <typename T, int KP, int KIND, bool CENTER = false>
 __global__ void __launch_bounds__(kNT) k_bfwd(Launch L, const StepArgs *__restrict__ args,
                                         const void *const *__restrict__ Xs,
                                         const void *const *__restrict__ Ys)
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(kNT) k_bfwd(Launch L, const StepArgs *__restri
     if (inst == kNoTile)
         return;
     const StepArgs a = instance_args(L, args, Xs, Ys, inst);
-    fwd_body<T, KP, KIND, true>(a, s - q * (nf + 1));
+    fwd_body<T, KP, KIND, true, CENTER>(a, s - q * (nf + 1));
 }
 
 // Coefficient launch: 8 * per_xcd workgroups over the forward map (one
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(kNT) k_bcoef(Launch L, const StepArgs *__restr
 
 // Backward launch: 8 * per_xcd workgroups; slot s of XCD x takes the feature
 // tile map[x * per_xcd + s] (kNoTile: nothing); coefficients from k_bcoef.
-template <typename T, int KP, int MB, int KIND, int OPT>
+template <typename T, int KP, int MB, int KIND, int OPT, bool CENTER = false>
 __global__ void __launch_bounds__(kNT) k_bbwd(Launch L, const StepArgs *__restrict__ args,
                                         const void *const *__restrict__ Xs,
                                         const void *const *__restrict__ Ys)
@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(kNT) k_bbwd(Launch L, const StepArgs *__restri
     if (e == kNoTile)
         return;
     const StepArgs a = instance_args(L, args, Xs, Ys, e >> 16);
-    bwd_body<T, KP, MB, KIND, OPT, kModePre, true>(a, (int)(e & 0xffffu));
+    bwd_body<T, KP, MB, KIND, OPT, kModePre, true, CENTER>(a, (int)(e & 0xffffu));
 }
 
 // ---------------------------------------------------------------------------
@@ -209,7 +209,7 @@ __device__ __forceinline__ void acquire(uint32_t *cnt, uint32_t target, int &bud
     __syncthreads();
 }
 
-template <typename T, int KP, int OPT>
+template <typename T, int KP, int OPT, bool CENTER = false>
 __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(2))) k_bpers(Launch L, Queues Q,
                                          const StepArgs *__restrict__ args,
                                          const void *const *__restrict__ Xs,
@@ -253,9 +253,9 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(2))) k
             const StepArgs a = instance_args(L, args, Xs, Ys, inst);
             // row tiles past this minibatch's rows do nothing but count
             if (tile == Q.nf_max)
-                fwd_body<T, KP, GEN, true>(a, a.n_fwd);
+                fwd_body<T, KP, GEN, true, CENTER>(a, a.n_fwd);
             else if (tile < a.n_fwd)
-                fwd_body<T, KP, GEN, true>(a, tile);
+                fwd_body<T, KP, GEN, true, CENTER>(a, tile);
             publish(cnt);
         } else if (kind == kItemCoef) {
             // every forward item of the instance done
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(kNT) __attribute__((amdgpu_waves_per_eu(2))) k
             // the instance's coefficient block written
             acquire(cnt + 1, 1u, budget, &args[inst].coef->status);
             const StepArgs a = instance_args(L, args, Xs, Ys, inst);
-            bwd_body<T, KP, 1, GEN, OPT, kModePre, true>(a, tile);
+            bwd_body<T, KP, 1, GEN, OPT, kModePre, true, CENTER>(a, tile);
         }
         __syncthreads(); // s_item is rewritten next
     }

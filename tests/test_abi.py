@@ -188,8 +188,6 @@ def test_batch_validation_is_synchronous():
                   V[:1]) == sg.SGEP_EUNSUPPORTED                                # GENERAL only
     assert status(1, [32], [32], mk(G, sg.SGEP_BF16, 4, 0, 0, 16),
                   V[:1]) == sg.SGEP_EUNSUPPORTED                                # F32 / F64 only
-    assert status(1, [32], [32], mk(G, sg.SGEP_F32, 4, 0, 0, 16, center=1),
-                  V[:1]) == sg.SGEP_EUNSUPPORTED                                # no centring
     assert lib.sgep_batch_init(None, 1, None, None, None, None, None) == sg.SGEP_EINVAL
     for fn in ("sgep_batch_sync", "sgep_batch_destroy"):
         assert getattr(lib, fn)(None) == sg.SGEP_EINVAL

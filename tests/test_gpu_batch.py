@@ -230,6 +230,74 @@ def test_batch_persistent_matches_single_handles(dtype, adam):
     eb.close()
 
 
+class _ShiftedGen:
+    """A generator whose views carry per-feature offsets of order 1 (so an
+    uncentred step differs at O(1))."""
+
+    def __init__(self, gen, d, seed):
+        rng = np.random.default_rng(seed)
+        self.gen, self.ox, self.oy = gen, rng.normal(0.0, 1.0, d), rng.normal(0.0, 1.0, d)
+
+    def batch(self, t, n):
+        X, Y = self.gen.batch(t, n)
+        return X + self.ox, Y + self.oy
+
+
+@pytest.mark.parametrize("dtype,groups", [("f64", 1), ("f64", -2), ("f32", 3), ("f32", -1)])
+def test_batch_centring_matches_single_handles_and_oracle(dtype, groups):
+    """Running-mean centring in the batch (grouped and persistent plans):
+    every instance bitwise equal to the same centred instance stepped alone,
+    and to the oracle's centring (Sec. 1 zero-mean assumption, the means
+    learnt at rate gamma) at the single-handle bars, the means included."""
+    torch = _torch()
+    sg = _sg()
+    f64 = dtype == "f64"
+    sdt = sg.SGEP_F64 if f64 else sg.SGEP_F32
+    ndt, tdt = (np.float64, torch.float64) if f64 else (np.float32, torch.float32)
+    k, b_max = 8, 128
+    sizes = [128, 100, 128, 37]
+    gens = [_ShiftedGen(synth.GeneralPlanted(d, k=min(k, d), seed=70 + i), d, 170 + i)
+            for i, d in enumerate(DIMS)]
+    V0s = [synth.initial_players(d, k, 30 + i) for i, d in enumerate(DIMS)]
+    cfg = sg.make_config(sg.SGEP_KIND_GENERAL, sdt, k, 0, 0, b_max, optimizer=sg.SGEP_SGD,
+                         schedule=sg.SGEP_SCHED_INV, eta0=0.05, t0=50.0, gamma=0.5, rho=1e-4,
+                         eps_reg=1e-3, center=1)
+    data = _Data(gens, DIMS, len(sizes), b_max, ndt, tdt)
+    bat = sg.BatchSolver(DIMS, cfg, V0s)
+    bat.set_plan(groups, [1, 1, 1])
+    ref = sg.BatchSolver(DIMS, cfg, V0s)
+    print(f"{dtype} centred batch plan={bat.plan()} launches={bat.launches()}", flush=True)
+    for t, b in enumerate(sizes):
+        bat.step(*data.ptrs[t], b)
+        xs, ys = data.dev[t]
+        for i, d in enumerate(DIMS):
+            sg.sgep_step(ref.instance(i), xs[i], d, ys[i], d, b)
+    bat.sync()
+    ref.sync()
+    host = [[(X[:b], Y[:b]) for X, Y in hs] for hs, b in zip(data.host, sizes)]
+    tol = TOL64 if f64 else TOL32_N
+    for i, d in enumerate(DIMS):
+        mb_ = sg.sgep_means(bat.instance(i), 2 * d)
+        assert np.array_equal(bat.vectors(i), ref.vectors(i)), (i, d)
+        assert np.array_equal(mb_, sg.sgep_means(ref.instance(i), 2 * d)), (i, d)
+        pb = oracle.Problem(oracle.KIND_GENERAL, cfg.k, d, d, eps_reg=cfg.eps_reg, rho=cfg.rho,
+                            optimizer=cfg.optimizer, center=True)
+        st = oracle.State.init(V0s[i], adam=False)
+        for t, hs in enumerate(host, start=1):
+            X, Y = hs[i]
+            oracle.gamma_step(pb, st, X, Y, oracle.eta(cfg.schedule, t, cfg.eta0, t0=cfg.t0),
+                              cfg.gamma)
+        dv = float(np.abs(bat.vectors(i) - st.V).max())
+        dg = float(np.abs(bat.auxiliary(i) - st.G).max()) / max(1.0, np.abs(st.G).max())
+        mo = np.concatenate([st.mu_x, st.mu_y])
+        dm = float(np.abs(mb_ - mo).max()) / max(1.0, float(np.abs(mo).max()))
+        print(f"  d={d} max|dV|={dv:.2e} rel|dG|={dg:.2e} rel|dmu|={dm:.2e}")
+        assert dv < tol and dg < tol, (i, d, dv, dg)
+        assert dm < (1e-12 if f64 else 1e-6), (i, d, dm)
+    bat.close()
+    ref.close()
+
+
 def test_batch_tune_keeps_initial_state_and_graph_replay_matches_eager():
     torch = _torch()
     sg = _sg()
