@@ -426,4 +426,16 @@ def test_batch_full_size_against_oracle():
         dg = float(np.abs(bat.auxiliary(i) - st.G).max()) / max(1.0, np.abs(st.G).max())
         print(f"  instance {i} d={dims[i]} max|dV|={dv:.2e} rel|dG|={dg:.2e}")
         assert dv < 5 * TOL32_N and dg < 5 * TOL32_N, (i, dv, dg)
+    # the persistent plan over the same steps: every instance bit for bit as
+    # under the tuned plan (16-feature tiles in both)
+    if all(m == 1 for m in bat.plan()[1]):
+        per = sg.BatchSolver(dims, cfg, V0s)
+        per.set_plan(-1, [1, 1, 1])
+        for xs, ys, px, py in steps:
+            per.step(px, py, b)
+        per.sync()
+        for i in range(len(dims)):
+            assert np.array_equal(per.vectors(i), bat.vectors(i)), i
+            assert np.array_equal(per.auxiliary(i), bat.auxiliary(i)), i
+        per.close()
     bat.close()
